@@ -1,0 +1,370 @@
+"""CPU oracle of the Laplace-evidence hot path -- TEST INFRASTRUCTURE ONLY.
+
+Python access (ctypes) to the plain FP64 C oracle in ``oracle.c``.  Only the
+tests, the smoke check and the benchmark's CPU-baseline leg use this package;
+the product library and its binding never import it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SRC_PATH = os.path.join(_HERE, "oracle.c")
+
+ST_ACTIVE, ST_CONVERGED, ST_STALLED, ST_MAXITER, ST_DEAD = 0, 1, 2, 3, 4
+OK, E_INVAL, E_NOTPD, E_NOMEM, E_NOMODE, E_CAPACITY, E_UNSUPPORTED = 0, -1, -2, -3, -5, -6, -7
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (plain -O2, OpenMP across starts)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, SRC_PATH, "-lm"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _Problem(C.Structure):
+    _fields_ = [("family", C.c_int32), ("norm", C.c_int32), ("d", C.c_int32), ("K", C.c_int32),
+                ("log_w", C.c_void_p), ("mu", C.c_void_p), ("prec", C.c_void_p),
+                ("nu", C.c_double), ("logl_offset", C.c_double)]
+
+
+class _Config(C.Structure):
+    _fields_ = [("n_rays", C.c_int32), ("n_points", C.c_int32), ("n_starts", C.c_int32),
+                ("m", C.c_int32), ("max_iter", C.c_int32), ("max_modes", C.c_int32),
+                ("grad_tol", C.c_double), ("dedup_tol", C.c_double),
+                ("dedup_tol_pre", C.c_double), ("seed", C.c_uint64), ("n_threads", C.c_int32)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("log_z", C.c_double), ("n_modes", C.c_int32), ("modes", C.c_void_p),
+                ("mode_log_z", C.c_void_p), ("mode_logl", C.c_void_p), ("log_det_h", C.c_void_p),
+                ("n_logl_evals", C.c_int64), ("n_grad_evals", C.c_int64),
+                ("n_hess_evals", C.c_int64), ("iterations", C.c_int32),
+                ("n_rejected_nonpd", C.c_int32), ("n_dead_starts", C.c_int32),
+                ("n_candidates", C.c_int32), ("n_reps_pre", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build(force=True)
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, f64, u64, u32 = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_uint64, C.c_uint32
+        L.or_pairwise_sum.restype = f64
+        L.or_pairwise_sum.argtypes = [vp, i64]
+        L.or_logsumexp.restype = f64
+        L.or_logsumexp.argtypes = [vp, i32]
+        L.or_cholesky.restype = i32
+        L.or_cholesky.argtypes = [i32, vp, vp]
+        L.or_logdet_from_chol.restype = f64
+        L.or_logdet_from_chol.argtypes = [i32, vp]
+        L.or_chol_solve.argtypes = [i32, vp, vp, vp]
+        L.or_validate_problem.restype = i32
+        L.or_validate_problem.argtypes = [vp]
+        L.or_prep.restype = i32
+        L.or_prep.argtypes = [vp, vp, vp]
+        L.or_logl.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.or_hvp.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.or_neg_hessian.argtypes = [vp, vp, vp, vp]
+        L.or_philox4x32_10.argtypes = [vp, vp, vp]
+        L.or_rng_word.restype = u32
+        L.or_rng_word.argtypes = [u64, u32, u32, u32, u32]
+        L.or_rng_uniform.restype = f64
+        L.or_rng_uniform.argtypes = [u64, u32, u32, u32, u32]
+        L.or_rays.argtypes = [i32, vp, vp, i32, u64, u32, vp, vp]
+        L.or_discover.restype = i32
+        L.or_discover.argtypes = [vp, vp, vp, vp, i32, i32, i32, u64, u32, vp, vp, vp, vp]
+        L.or_two_loop.argtypes = [i32, i32, vp, vp, vp, vp]
+        L.or_lbfgs.restype = i32
+        L.or_lbfgs.argtypes = [vp, vp, vp, i32, i32, f64, vp, vp, vp, vp]
+        L.or_newton.restype = i32
+        L.or_newton.argtypes = [vp, vp, vp, i32, vp]
+        L.or_dedup.restype = i32
+        L.or_dedup.argtypes = [i32, i32, vp, vp, vp, f64, vp, vp]
+        L.or_log_volume.restype = f64
+        L.or_log_volume.argtypes = [i32, vp, vp]
+        L.or_mode_log_z.restype = f64
+        L.or_mode_log_z.argtypes = [i32, f64, f64, f64]
+        L.or_evidence.restype = i32
+        L.or_evidence.argtypes = [vp, vp, vp, vp, vp]
+        L.or_reference_modes.restype = i32
+        L.or_reference_modes.argtypes = [vp, vp, vp, f64, i32, vp]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleProblem:
+    """Keeps the numpy arrays alive while the C struct points at them."""
+
+    def __init__(self, prob):
+        self.prob = prob
+        self.log_w = _f64(prob.log_w)
+        self.mu = _f64(prob.mu)
+        self.prec = _f64(prob.prec)
+        self.lo = _f64(prob.lo)
+        self.hi = _f64(prob.hi)
+        self.s = _Problem(prob.family, prob.norm, prob.d, prob.K, _p(self.log_w).value,
+                          _p(self.mu).value, _p(self.prec).value, float(prob.nu),
+                          float(prob.logl_offset))
+        self._beta = None
+
+    @property
+    def ptr(self):
+        return C.byref(self.s)
+
+    def beta(self) -> np.ndarray:
+        if self._beta is None:
+            b = np.zeros(self.prob.K)
+            st = lib().or_prep(self.ptr, _p(b), None)
+            if st != OK:
+                raise ValueError(f"oracle prep failed: {st}")
+            self._beta = b
+        return self._beta
+
+
+def pairwise_sum(x) -> float:
+    x = _f64(x)
+    return lib().or_pairwise_sum(_p(x), x.size)
+
+
+def logsumexp(x) -> float:
+    x = _f64(x)
+    return lib().or_logsumexp(_p(x), x.size)
+
+
+def cholesky(A):
+    A = _f64(A)
+    n = A.shape[0]
+    L = np.zeros_like(A)
+    st = lib().or_cholesky(n, _p(A), _p(L))
+    return st, L
+
+
+def logdet_spd(A) -> float:
+    st, L = cholesky(A)
+    if st:
+        raise ValueError("not positive definite")
+    return lib().or_logdet_from_chol(A.shape[0], _p(L))
+
+
+def chol_solve(L, b):
+    L = _f64(L)
+    b = _f64(b)
+    x = np.zeros_like(b)
+    lib().or_chol_solve(L.shape[0], _p(L), _p(b), _p(x))
+    return x
+
+
+def validate_problem(prob) -> int:
+    op = OracleProblem(prob)
+    return lib().or_validate_problem(op.ptr)
+
+
+def prep(prob):
+    op = OracleProblem(prob)
+    beta = np.zeros(prob.K)
+    ld = np.zeros(prob.K)
+    st = lib().or_prep(op.ptr, _p(beta), _p(ld))
+    return st, beta, ld
+
+
+def logl(prob, X, grad: bool = True, op: Optional[OracleProblem] = None):
+    op = op or OracleProblem(prob)
+    X = _f64(np.atleast_2d(X))
+    B = X.shape[0]
+    l = np.zeros(B)
+    g = np.zeros_like(X) if grad else None
+    lib().or_logl(op.ptr, _p(op.beta()), B, _p(X), _p(l), _p(g) if grad else None)
+    return (l, g) if grad else l
+
+
+def hvp(prob, X, V, op: Optional[OracleProblem] = None):
+    op = op or OracleProblem(prob)
+    X = _f64(np.atleast_2d(X))
+    V = _f64(np.atleast_2d(V))
+    HV = np.zeros_like(X)
+    lib().or_hvp(op.ptr, _p(op.beta()), X.shape[0], _p(X), _p(V), _p(HV))
+    return HV
+
+
+def neg_hessian(prob, x, op: Optional[OracleProblem] = None):
+    op = op or OracleProblem(prob)
+    x = _f64(x)
+    H = np.zeros((prob.d, prob.d))
+    lib().or_neg_hessian(op.ptr, _p(op.beta()), _p(x), _p(H))
+    return H
+
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().or_philox4x32_10(_p(c), _p(k), _p(o))
+    return o
+
+
+def rng_word(seed, problem, ray, stream, i) -> int:
+    return lib().or_rng_word(seed, problem, ray, stream, i)
+
+
+def rng_uniform(seed, problem, ray, stream, i) -> float:
+    return lib().or_rng_uniform(seed, problem, ray, stream, i)
+
+
+def rays(d, lo, hi, R, seed, problem=0):
+    lo = _f64(lo)
+    hi = _f64(hi)
+    P0 = np.zeros((R, d))
+    P1 = np.zeros((R, d))
+    lib().or_rays(d, _p(lo), _p(hi), R, seed, problem, _p(P0), _p(P1))
+    return P0, P1
+
+
+def discover(prob, R, n_pts, n_starts, seed, problem=0):
+    op = OracleProblem(prob)
+    bl = np.zeros(R)
+    bj = np.zeros(R, dtype=np.int32)
+    sr = np.zeros(n_starts, dtype=np.int32)
+    X0 = np.zeros((n_starts, prob.d))
+    st = lib().or_discover(op.ptr, _p(op.beta()), _p(op.lo), _p(op.hi), R, n_pts, n_starts, seed,
+                           problem, _p(bl), _p(bj), _p(sr), _p(X0))
+    if st != OK:
+        raise ValueError(f"discover failed {st}")
+    return dict(ray_best_l=bl, ray_best_j=bj, start_ray=sr, X0=X0)
+
+
+def two_loop(S, Y, g):
+    S = _f64(S)
+    Y = _f64(Y)
+    g = _f64(g)
+    cnt, d = S.shape
+    p = np.zeros(d)
+    lib().or_two_loop(d, cnt, _p(S), _p(Y), _p(g), _p(p))
+    return p
+
+
+def lbfgs(prob, x0, m=8, max_iter=None, grad_tol=1e-10, op=None):
+    op = op or OracleProblem(prob)
+    x = _f64(x0).copy()
+    l = C.c_double()
+    g = np.zeros(prob.d)
+    it = C.c_int32()
+    ev = C.c_int64()
+    mi = max_iter if max_iter is not None else 10 * prob.d + 200
+    st = lib().or_lbfgs(op.ptr, _p(op.beta()), _p(x), m, mi, grad_tol, C.byref(l), _p(g),
+                        C.byref(it), C.byref(ev))
+    return dict(status=st, x=x, logl=l.value, grad=g, iters=it.value, evals=ev.value)
+
+
+def newton(prob, x0, max_steps=20, op=None):
+    op = op or OracleProblem(prob)
+    x = _f64(x0).copy()
+    steps = C.c_int32()
+    st = lib().or_newton(op.ptr, _p(op.beta()), _p(x), max_steps, C.byref(steps))
+    return st, x, steps.value
+
+
+def dedup(X, l, tau, valid=None):
+    X = _f64(X)
+    l = _f64(l)
+    Cn, d = X.shape
+    rep_of = np.zeros(Cn, dtype=np.int32)
+    reps = np.zeros(max(Cn, 1), dtype=np.int32)
+    v = None if valid is None else np.ascontiguousarray(valid, dtype=np.uint8)
+    n = lib().or_dedup(Cn, d, _p(X), _p(l), _p(v) if v is not None else None, tau, _p(rep_of),
+                       _p(reps))
+    return rep_of, reps[:n].copy()
+
+
+def log_volume(lo, hi) -> float:
+    lo = _f64(lo)
+    hi = _f64(hi)
+    return lib().or_log_volume(lo.size, _p(lo), _p(hi))
+
+
+def mode_log_z(d, logl_v, log_det_h, log_vol) -> float:
+    return lib().or_mode_log_z(d, logl_v, log_det_h, log_vol)
+
+
+@dataclass
+class OracleResult:
+    status: int
+    log_z: float
+    n_modes: int
+    modes: np.ndarray
+    mode_log_z: np.ndarray
+    mode_logl: np.ndarray
+    log_det_h: np.ndarray
+    n_logl_evals: int
+    n_grad_evals: int
+    n_hess_evals: int
+    iterations: int
+    n_rejected_nonpd: int
+    n_dead_starts: int
+    n_candidates: int
+    n_reps_pre: int
+
+
+def _result(st, r, d, cap, modes, mlz, mll, ldh) -> OracleResult:
+    n = min(r.n_modes, cap) if st == OK else 0
+    return OracleResult(st, r.log_z, r.n_modes, modes[:n].copy(), mlz[:n].copy(), mll[:n].copy(),
+                        ldh[:n].copy(), r.n_logl_evals, r.n_grad_evals, r.n_hess_evals,
+                        r.iterations, r.n_rejected_nonpd, r.n_dead_starts, r.n_candidates,
+                        r.n_reps_pre)
+
+
+def evidence(prob, cfg, n_threads: int = 0, n_starts: Optional[int] = None) -> OracleResult:
+    """Run the whole path on the CPU.  ``n_starts`` overrides cfg.n_starts (fewer rays too)."""
+    op = OracleProblem(prob)
+    ns = cfg.n_starts if n_starts is None else n_starts
+    nr = cfg.n_rays if n_starts is None else max(ns, cfg.n_rays * ns // cfg.n_starts)
+    c = _Config(nr, cfg.n_points, ns, cfg.m, cfg.max_iter, cfg.max_modes, cfg.grad_tol,
+                cfg.dedup_tol, cfg.dedup_tol_pre, cfg.seed, n_threads)
+    cap = cfg.max_modes
+    d = prob.d
+    modes = np.zeros((cap, d))
+    mlz = np.zeros(cap)
+    mll = np.zeros(cap)
+    ldh = np.zeros(cap)
+    r = _Result()
+    r.modes, r.mode_log_z, r.mode_logl, r.log_det_h = (_p(modes).value, _p(mlz).value,
+                                                       _p(mll).value, _p(ldh).value)
+    st = lib().or_evidence(op.ptr, _p(op.lo), _p(op.hi), C.byref(c), C.byref(r))
+    return _result(st, r, d, cap, modes, mlz, mll, ldh)
+
+
+def reference_modes(prob, dedup_tol: float = 0.0, max_modes: int = 64) -> OracleResult:
+    """Expected mode set of a synthetic problem: Newton from each mu_k, filtered and deduplicated."""
+    op = OracleProblem(prob)
+    d = prob.d
+    modes = np.zeros((max_modes, d))
+    mlz = np.zeros(max_modes)
+    mll = np.zeros(max_modes)
+    ldh = np.zeros(max_modes)
+    r = _Result()
+    r.modes, r.mode_log_z, r.mode_logl, r.log_det_h = (_p(modes).value, _p(mlz).value,
+                                                       _p(mll).value, _p(ldh).value)
+    st = lib().or_reference_modes(op.ptr, _p(op.lo), _p(op.hi), dedup_tol, max_modes, C.byref(r))
+    return _result(st, r, d, max_modes, modes, mlz, mll, ldh)
