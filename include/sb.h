@@ -1,0 +1,259 @@
+/*
+ * sb.h -- C ABI of the MI355X (gfx950) Laplace-evidence library, version 1.
+ *
+ * The library computes the Bayesian evidence of a likelihood with a uniform
+ * box prior by the mode-centric Laplace method of SunBURST (arXiv
+ * 2601.19957):
+ *
+ *   log Z = logsumexp_k [ l(theta_k) + log pi(theta_k) + (d/2) log 2 pi
+ *                         - (1/2) log det H_k ],    H_k = -nabla^2 l(theta_k)
+ *
+ * (Laplace approximation, appendix eq. "laplace"; mixture of Laplace
+ * contributions, eq. "mixture-evidence"; problem statement in section 3,
+ * uniform prior on the box with log pi = -log V).  Modes theta_k are found by
+ * ray-bundle discovery (section "Ray Generation", "Two-Pass Sampling"),
+ * batched L-BFGS (appendix "L-BFGS Optimization"), L-infinity
+ * de-duplication (appendix "The L-infinity Metric") and a Newton polish
+ * with the exact Hessian; log det H_k comes from a Cholesky factor
+ * (appendix "Coordinate Whitening").
+ *
+ * Likelihood families (closed forms, theta in R^d):
+ *   SB_FAMILY_GAUSS_MIX: l = c + logsumexp_k (beta_k - q_k/2),
+ *       q_k = (theta-mu_k)^T P_k (theta-mu_k), beta_k = log w_k, plus
+ *       (1/2) log det P_k - (d/2) log 2 pi when norm == SB_NORM_DENSITY.
+ *   SB_FAMILY_STUDENT_T (K = 1): l = c + beta - ((nu+d)/2) log(1 + q/nu),
+ *       beta = lgamma((nu+d)/2) - lgamma(nu/2) - (d/2) log(nu pi)
+ *              + (1/2) log det P for SB_NORM_DENSITY, else 0.
+ *
+ * Conventions
+ *  - Arrays are row-major.  Host entry points take host pointers and
+ *    allocate their own device memory; *_dev entry points take device
+ *    pointers, a caller-provided workspace and a HIP stream (passed as
+ *    void*, hipStream_t), and never allocate.
+ *  - Every call returns an sb_status.  No exception crosses the ABI.  On an
+ *    error the outputs are untouched, except sb_result.log_z = NaN and, for
+ *    SB_E_CAPACITY, sb_result.n_modes = the number of modes found.
+ *  - Calls are deterministic: the same inputs, seed and GPU give bitwise
+ *    identical outputs.  Calls on different streams are independent.
+ *  - The caller owns every buffer.  sb_last_error() describes the last
+ *    failure on the calling thread.
+ */
+#ifndef SB_H
+#define SB_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SB_ABI_VERSION 1
+
+typedef enum {
+  SB_OK = 0,
+  SB_E_INVAL = -1,       /* invalid argument (sizes, pointers, box, config) */
+  SB_E_NOTPD = -2,       /* a precision matrix is asymmetric or not positive definite */
+  SB_E_NOMEM = -3,       /* device allocation failed or workspace too small */
+  SB_E_DEVICE = -4,      /* HIP runtime error, or no gfx950 device */
+  SB_E_NOMODE = -5,      /* no mode passed the filters; log_z = -inf */
+  SB_E_CAPACITY = -6,    /* more modes than max_modes; n_modes = modes found */
+  SB_E_UNSUPPORTED = -7  /* valid but not supported (e.g. Student-t with K > 1) */
+} sb_status;
+
+typedef enum { SB_FAMILY_GAUSS_MIX = 0, SB_FAMILY_STUDENT_T = 1 } sb_family;
+typedef enum { SB_NORM_PEAK_ZERO = 0, SB_NORM_DENSITY = 1 } sb_norm;
+/* SB_PREC_FP64: every step in FP64.  SB_PREC_MIXED: discovery GEMM in BF16
+ * with FP32 accumulation, L-BFGS bulk in FP32, then Newton polish, Hessian,
+ * Cholesky, log det and the logsumexp combine in FP64. */
+typedef enum { SB_PREC_FP64 = 0, SB_PREC_MIXED = 1 } sb_precision;
+typedef enum { SB_DTYPE_F64 = 0, SB_DTYPE_F32 = 1, SB_DTYPE_BF16 = 2 } sb_dtype;
+
+/* Likelihood: family, normalisation and parameters.
+ * log_w [K] (NULL: all weights 1), mu [K][d], prec [K][d][d] (symmetric
+ * positive definite precision matrices P_k = Sigma_k^{-1}).  Host pointers
+ * for sb_evidence / sb_evidence_batch, device pointers for *_dev calls. */
+typedef struct {
+  int32_t family, norm, d, K;
+  const double *log_w;
+  const double *mu;
+  const double *prec;
+  double nu;          /* Student-t degrees of freedom, > 0 */
+  double logl_offset; /* constant c */
+} sb_loglik;
+
+/* Uniform prior box prod_i [lo_i, hi_i], lo_i < hi_i finite, [d] each. */
+typedef struct {
+  const double *lo, *hi;
+} sb_box;
+
+/* Run parameters.  Non-positive tolerances and max_iter select defaults:
+ * grad_tol 1e-10 (FP64 bulk; the FP32 bulk of SB_PREC_MIXED stops at its
+ * rounding floor), dedup_tol 1e-6 * max_i(hi_i - lo_i), dedup_tol_pre 0.25,
+ * max_iter 10 d + 200.  Requires 1 <= m <= 8, 1 <= n_starts <= n_rays,
+ * n_points >= 1, max_modes >= 1. */
+typedef struct {
+  int32_t n_rays, n_points, n_starts, m, max_iter, max_modes, precision;
+  double grad_tol, dedup_tol, dedup_tol_pre;
+  uint64_t seed;
+} sb_config;
+
+/* Results (host memory, caller-allocated arrays of max_modes entries; may be
+ * NULL).  Modes are sorted by mode_log_z descending (ties: lexicographic). */
+typedef struct {
+  double log_z;
+  int32_t n_modes;
+  double *modes;      /* [max_modes][d] */
+  double *mode_log_z; /* [max_modes] */
+  double *mode_logl;  /* [max_modes] */
+  double *log_det_h;  /* [max_modes], log det of H = -nabla^2 l at the mode */
+  int64_t n_logl_evals; /* l-only evaluations (discovery) */
+  int64_t n_grad_evals; /* l + gradient evaluations (L-BFGS, polish) */
+  int64_t n_hess_evals; /* Hessian assemblies */
+  int32_t iterations;   /* L-BFGS batch steps */
+  int32_t n_rejected_nonpd, n_dead_starts, n_candidates, n_reps_pre;
+  double seconds[8];    /* prep, discovery, bulk, dedup_pre, polish, hessian+chol, combine, total */
+} sb_result;
+
+/* ------------------------------------------------------------------ whole path */
+
+/* Evidence of one problem (host buffers in and out).  Section 3 problem
+ * statement; modules CarryTiger / GreenDragon / BendTheBow in order. */
+int32_t sb_evidence(const sb_loglik *ll, const sb_box *box, const sb_config *cfg,
+                    sb_result *res);
+
+/* Evidence of n independent problems (uneven d and K), results in res[n].
+ * Problem j uses ll[j], box[j] and cfg[j]; their ray/start kernels run as
+ * one batch per phase. */
+int32_t sb_evidence_batch(int32_t n, const sb_loglik *ll, const sb_box *box,
+                          const sb_config *cfg, sb_result *res);
+
+/* Device-resident variant of sb_evidence: ll and box hold device pointers,
+ * the workspace (>= sb_evidence_workspace_bytes) is caller-owned device
+ * memory; results are written to host memory in res.  Synchronises stream. */
+size_t sb_evidence_workspace_bytes(const sb_loglik *ll, const sb_config *cfg);
+int32_t sb_evidence_dev(const sb_loglik *ll_dev, const sb_box *box_dev, const sb_config *cfg,
+                        sb_result *res, void *workspace, size_t ws_bytes, void *stream);
+
+/* --------------------------------------------------------------- single steps
+ * Device pointers throughout; nothing allocates.  "model" arrays:
+ *   beta [K] FP64 per-component constants written by sb_prep_dev;
+ *   prec_lp, mu_lp: FP32 copies (dtype F32) or BF16 precision + FP32 mu
+ *   (dtype BF16) written by sb_prep_dev when non-NULL. */
+typedef struct {
+  int32_t family, norm, d, K;
+  const double *log_w, *mu, *prec; /* device, FP64 */
+  double nu, logl_offset;
+  const double *beta;              /* device [K], from sb_prep_dev */
+  const void *prec_lp;             /* device [K][d][d] FP32 or BF16, or NULL */
+  const float *mu_lp;              /* device [K][d] FP32, or NULL */
+} sb_model_dev;
+
+/* Problem prep (step A1): Cholesky of every P_k; writes beta[K] and
+ * logdet_prec[K] (device FP64) and, when non-NULL, prec_f32 [K][d][d],
+ * prec_bf16 [K][d][d] (uint16 bit patterns) and mu_f32 [K][d].
+ * SB_E_NOTPD if a P_k is asymmetric (> 1e-12 relative) or not positive
+ * definite.  Workspace >= sb_prep_workspace_bytes(d, K). */
+size_t sb_prep_workspace_bytes(int32_t d, int32_t K);
+int32_t sb_prep_dev(const sb_loglik *ll_dev, double *beta, double *logdet_prec, float *prec_f32,
+                    uint16_t *prec_bf16, float *mu_f32, void *workspace, size_t ws_bytes,
+                    void *stream);
+
+/* Batched log-likelihood and gradient (step A3): for B points X [B][d]
+ * (dtype F64: double; F32: float) writes logl [B] and, if grad != NULL,
+ * grad [B][d] (same dtype).  One GEMM (X - mu_k) P_k on the matrix cores,
+ * then the logsumexp / Student-t epilogue and the hand-written backward.
+ * Workspace >= sb_logl_grad_workspace_bytes(d, K, B, dtype). */
+size_t sb_logl_grad_workspace_bytes(int32_t d, int32_t K, int64_t B, int32_t dtype);
+int32_t sb_logl_grad_dev(const sb_model_dev *m, int64_t B, const void *X, void *logl, void *grad,
+                         int32_t dtype, void *workspace, size_t ws_bytes, void *stream);
+
+/* Batched Hessian-vector product (step A3'): HV[b] = nabla^2 l(X[b]) V[b],
+ * FP64.  Workspace >= sb_hvp_workspace_bytes(d, K, B). */
+size_t sb_hvp_workspace_bytes(int32_t d, int32_t K, int64_t B);
+int32_t sb_hvp_dev(const sb_model_dev *m, int64_t B, const double *X, const double *V, double *HV,
+                   void *workspace, size_t ws_bytes, void *stream);
+
+/* Ray-bundle discovery (step A2, section "Ray Generation" and the coarse
+ * pass): R rays of the four geometries (ray r uses r mod 4) from Philox4x32-10
+ * keyed by seed; l at t_j = (j + 1/2)/n_pts; per-ray argmax (ties: lowest j);
+ * the n_starts rays with the highest maxima (ties: lowest ray).  dtype F64
+ * evaluates in FP64, BF16 runs the GEMM in BF16 with FP32 accumulation.
+ * Outputs (device): P0, P1 [R][d] FP64 endpoints (may be NULL), ray_best_l
+ * [R] FP64, ray_best_j [R], start_ray [n_starts], X0 [n_starts][d] FP64.
+ * Workspace >= sb_discover_workspace_bytes(d, K, R, n_pts, dtype). */
+size_t sb_discover_workspace_bytes(int32_t d, int32_t K, int32_t R, int32_t n_pts, int32_t dtype);
+int32_t sb_discover_dev(const sb_model_dev *m, const double *lo, const double *hi, int32_t R,
+                        int32_t n_pts, int32_t n_starts, uint64_t seed, int32_t dtype,
+                        double *P0, double *P1, double *ray_best_l, int32_t *ray_best_j,
+                        int32_t *start_ray, double *X0, void *workspace, size_t ws_bytes,
+                        void *stream);
+
+/* L-BFGS two-loop direction (appendix "L-BFGS Optimization") for B
+ * independent histories: S, Y [B][m][d] in logical order (oldest first),
+ * cnt [B] pairs used (0 <= cnt <= m), G [B][d] gradient of f.  Writes the
+ * direction P [B][d] = -H_k G.  FP64 (dtype F64) or FP32 (dtype F32). */
+int32_t sb_lbfgs_direction_dev(int64_t B, int32_t d, int32_t m, const int32_t *cnt,
+                               const void *S, const void *Y, const void *G, void *P,
+                               int32_t dtype, void *stream);
+
+/* Batched L-BFGS on f = -l (steps A4-A5) from X [B][d] (in place).  The
+ * Armijo line search (c1 = 1e-4, halving up to 40 times), curvature skip
+ * s^T y <= 1e-10 |s||y|, history reset on failure, stop at
+ * ||grad l||_inf <= grad_tol or max_iter accepted steps.  Writes logl [B],
+ * grad [B][d] at the final points, status [B] (1 converged, 2 stalled,
+ * 3 max-iter, 4 dead) and iters [B]; *n_evals (host) gets the number of
+ * l+grad evaluations.  dtype F64 or F32 (model needs prec_lp/mu_lp for F32).
+ * Workspace >= sb_lbfgs_workspace_bytes(d, K, B, m, dtype). */
+size_t sb_lbfgs_workspace_bytes(int32_t d, int32_t K, int64_t B, int32_t m, int32_t dtype);
+int32_t sb_lbfgs_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m, int32_t max_iter,
+                     double grad_tol, int32_t dtype, void *logl, void *grad, int32_t *status,
+                     int32_t *iters, int64_t *n_evals, void *workspace, size_t ws_bytes,
+                     void *stream);
+
+/* L-infinity leader de-duplication (step A7): candidates X [C][d] (FP64 or
+ * FP32 per dtype) with values l [C] (same dtype) and valid [C] (nullable,
+ * nonzero = candidate).  Visiting order l descending, ties lower index;
+ * each candidate joins the first representative within tau, else founds
+ * one.  Writes rep_of [C] (representative index, -1 if invalid) and reps
+ * [max_reps]; *n_reps (host) = representatives found (SB_E_CAPACITY if more
+ * than max_reps).  Workspace >= sb_dedup_workspace_bytes(C). */
+size_t sb_dedup_workspace_bytes(int32_t C);
+int32_t sb_dedup_dev(int32_t C, int32_t d, const void *X, const void *l, const uint8_t *valid,
+                     double tau, int32_t dtype, int32_t *rep_of, int32_t *reps, int32_t max_reps,
+                     int32_t *n_reps, void *workspace, size_t ws_bytes, void *stream);
+
+/* Hessian assembly (step A8): H [C][d][d] = -nabla^2 l at X [C][d], FP64,
+ * symmetrised; assembled from the same GEMM and epilogue as sb_hvp_dev with
+ * V = I.  Workspace >= sb_hessian_workspace_bytes(d, K, C). */
+size_t sb_hessian_workspace_bytes(int32_t d, int32_t K, int32_t C);
+int32_t sb_hessian_dev(const sb_model_dev *m, int32_t C, const double *X, double *H,
+                       void *workspace, size_t ws_bytes, void *stream);
+
+/* Batched FP64 Cholesky and log det (step A9): A [C][n][n] SPD (read; only
+ * the lower triangle is used) -> L [C][n][n] lower factor (may alias A),
+ * logdet [C] = 2 sum log L_ii (pairwise), info [C] = 0 or the 1-based column
+ * whose pivot was not positive (then logdet = NaN). */
+int32_t sb_cholesky_logdet_dev(int32_t C, int32_t n, const double *A, double *L, double *logdet,
+                               int32_t *info, void *stream);
+/* Solve L L^T x = b for C right-hand sides b [C][n] with factors L [C][n][n]. */
+int32_t sb_cholesky_solve_dev(int32_t C, int32_t n, const double *L, const double *b, double *x,
+                              void *stream);
+
+/* Laplace combine (step A10): log Z_k = logl_k - log V + (d/2) log 2 pi -
+ * (1/2) logdet_k for n modes, sorted descending (ties: lexicographic in
+ * modes [n][d]), log Z = logsumexp in that order.  Device inputs; writes
+ * order [n] (sorted position -> input index), mode_log_z [n] (sorted) and
+ * log_z [1]. */
+int32_t sb_combine_dev(int32_t n, int32_t d, const double *lo, const double *hi,
+                       const double *logl, const double *logdet, const double *modes,
+                       int32_t *order, double *mode_log_z, double *log_z, void *stream);
+
+/* ------------------------------------------------------------------- misc */
+const char *sb_status_string(int32_t status);
+const char *sb_last_error(void); /* thread-local; "" if none */
+int32_t sb_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SB_H */

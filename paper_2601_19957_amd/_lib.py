@@ -1,0 +1,492 @@
+"""ctypes binding of libsb.so (the C ABI in include/sb.h).
+
+Argument marshalling only: every computation runs in the library's gfx950
+kernels.  Device buffers and streams come from PyTorch (``torch.cuda`` is
+HIP on ROCm).  Importing this module loads the library and fails loudly if
+it has not been built; it never falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsb.so")
+
+OK, E_INVAL, E_NOTPD, E_NOMEM, E_DEVICE, E_NOMODE, E_CAPACITY, E_UNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+FAMILY_GAUSS_MIX, FAMILY_STUDENT_T = 0, 1
+NORM_PEAK_ZERO, NORM_DENSITY = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+DTYPE_F64, DTYPE_F32, DTYPE_BF16 = 0, 1, 2
+ST_CONVERGED, ST_STALLED, ST_MAXITER, ST_DEAD = 1, 2, 3, 4
+
+# every extern "C" symbol declared in include/sb.h
+EXPORTS = [
+    "sb_evidence", "sb_evidence_batch", "sb_evidence_workspace_bytes", "sb_evidence_dev",
+    "sb_prep_workspace_bytes", "sb_prep_dev", "sb_logl_grad_workspace_bytes", "sb_logl_grad_dev",
+    "sb_hvp_workspace_bytes", "sb_hvp_dev", "sb_discover_workspace_bytes", "sb_discover_dev",
+    "sb_lbfgs_direction_dev", "sb_lbfgs_workspace_bytes", "sb_lbfgs_dev",
+    "sb_dedup_workspace_bytes", "sb_dedup_dev", "sb_hessian_workspace_bytes", "sb_hessian_dev",
+    "sb_cholesky_logdet_dev", "sb_cholesky_solve_dev", "sb_combine_dev", "sb_status_string",
+    "sb_last_error", "sb_abi_version",
+]
+
+
+class SbError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({last_error()})")
+
+
+class sb_loglik(C.Structure):
+    _fields_ = [("family", C.c_int32), ("norm", C.c_int32), ("d", C.c_int32), ("K", C.c_int32),
+                ("log_w", C.c_void_p), ("mu", C.c_void_p), ("prec", C.c_void_p),
+                ("nu", C.c_double), ("logl_offset", C.c_double)]
+
+
+class sb_box(C.Structure):
+    _fields_ = [("lo", C.c_void_p), ("hi", C.c_void_p)]
+
+
+class sb_config(C.Structure):
+    _fields_ = [("n_rays", C.c_int32), ("n_points", C.c_int32), ("n_starts", C.c_int32),
+                ("m", C.c_int32), ("max_iter", C.c_int32), ("max_modes", C.c_int32),
+                ("precision", C.c_int32), ("grad_tol", C.c_double), ("dedup_tol", C.c_double),
+                ("dedup_tol_pre", C.c_double), ("seed", C.c_uint64)]
+
+
+class sb_result(C.Structure):
+    _fields_ = [("log_z", C.c_double), ("n_modes", C.c_int32), ("modes", C.c_void_p),
+                ("mode_log_z", C.c_void_p), ("mode_logl", C.c_void_p), ("log_det_h", C.c_void_p),
+                ("n_logl_evals", C.c_int64), ("n_grad_evals", C.c_int64),
+                ("n_hess_evals", C.c_int64), ("iterations", C.c_int32),
+                ("n_rejected_nonpd", C.c_int32), ("n_dead_starts", C.c_int32),
+                ("n_candidates", C.c_int32), ("n_reps_pre", C.c_int32),
+                ("seconds", C.c_double * 8)]
+
+
+class sb_model_dev(C.Structure):
+    _fields_ = [("family", C.c_int32), ("norm", C.c_int32), ("d", C.c_int32), ("K", C.c_int32),
+                ("log_w", C.c_void_p), ("mu", C.c_void_p), ("prec", C.c_void_p),
+                ("nu", C.c_double), ("logl_offset", C.c_double), ("beta", C.c_void_p),
+                ("prec_lp", C.c_void_p), ("mu_lp", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsb.so; raises if it is missing (build it with __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                              "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, f64, u64, sz = (C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_uint64,
+                                      C.c_size_t)
+        sig = {
+            "sb_evidence": (i32, [vp, vp, vp, vp]),
+            "sb_evidence_batch": (i32, [i32, vp, vp, vp, vp]),
+            "sb_evidence_workspace_bytes": (sz, [vp, vp]),
+            "sb_evidence_dev": (i32, [vp, vp, vp, vp, vp, sz, vp]),
+            "sb_prep_workspace_bytes": (sz, [i32, i32]),
+            "sb_prep_dev": (i32, [vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+            "sb_logl_grad_workspace_bytes": (sz, [i32, i32, i64, i32]),
+            "sb_logl_grad_dev": (i32, [vp, i64, vp, vp, vp, i32, vp, sz, vp]),
+            "sb_hvp_workspace_bytes": (sz, [i32, i32, i64]),
+            "sb_hvp_dev": (i32, [vp, i64, vp, vp, vp, vp, sz, vp]),
+            "sb_discover_workspace_bytes": (sz, [i32, i32, i32, i32, i32]),
+            "sb_discover_dev": (i32, [vp, vp, vp, i32, i32, i32, u64, i32, vp, vp, vp, vp, vp, vp,
+                                      vp, sz, vp]),
+            "sb_lbfgs_direction_dev": (i32, [i64, i32, i32, vp, vp, vp, vp, vp, i32, vp]),
+            "sb_lbfgs_workspace_bytes": (sz, [i32, i32, i64, i32, i32]),
+            "sb_lbfgs_dev": (i32, [vp, i64, vp, i32, i32, f64, i32, vp, vp, vp, vp, vp, vp, sz,
+                                   vp]),
+            "sb_dedup_workspace_bytes": (sz, [i32]),
+            "sb_dedup_dev": (i32, [i32, i32, vp, vp, vp, f64, i32, vp, vp, i32, vp, vp, sz, vp]),
+            "sb_hessian_workspace_bytes": (sz, [i32, i32, i32]),
+            "sb_hessian_dev": (i32, [vp, i32, vp, vp, vp, sz, vp]),
+            "sb_cholesky_logdet_dev": (i32, [i32, i32, vp, vp, vp, vp, vp]),
+            "sb_cholesky_solve_dev": (i32, [i32, i32, vp, vp, vp, vp]),
+            "sb_combine_dev": (i32, [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+            "sb_status_string": (C.c_char_p, [i32]),
+            "sb_last_error": (C.c_char_p, []),
+            "sb_abi_version": (i32, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(st: int) -> str:
+    return lib().sb_status_string(st).decode()
+
+
+def last_error() -> str:
+    return lib().sb_last_error().decode()
+
+
+def _check(st: int, where: str, ok=(OK,)):
+    if st not in ok:
+        raise SbError(st, where)
+    return st
+
+
+# ---------------------------------------------------------------- host path
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+@dataclass
+class EvidenceResult:
+    status: int
+    log_z: float
+    n_modes: int
+    modes: np.ndarray
+    mode_log_z: np.ndarray
+    mode_logl: np.ndarray
+    log_det_h: np.ndarray
+    n_logl_evals: int
+    n_grad_evals: int
+    n_hess_evals: int
+    iterations: int
+    n_rejected_nonpd: int
+    n_dead_starts: int
+    n_candidates: int
+    n_reps_pre: int
+    seconds: list = field(default_factory=list)
+
+
+def make_config(cfg) -> sb_config:
+    return sb_config(cfg.n_rays, cfg.n_points, cfg.n_starts, cfg.m, cfg.max_iter, cfg.max_modes,
+                     cfg.precision, cfg.grad_tol, cfg.dedup_tol,
+                     getattr(cfg, "dedup_tol_pre", 0.0), cfg.seed)
+
+
+class _HostProblem:
+    def __init__(self, prob):
+        self.log_w = _f64(prob.log_w)
+        self.mu = _f64(prob.mu)
+        self.prec = _f64(prob.prec)
+        self.lo = _f64(prob.lo)
+        self.hi = _f64(prob.hi)
+        self.ll = sb_loglik(prob.family, prob.norm, prob.d, prob.K, self.log_w.ctypes.data,
+                            self.mu.ctypes.data, self.prec.ctypes.data, float(prob.nu),
+                            float(prob.logl_offset))
+        self.box = sb_box(self.lo.ctypes.data, self.hi.ctypes.data)
+
+
+def _result_arrays(cap: int, d: int):
+    return (np.zeros((cap, d)), np.zeros(cap), np.zeros(cap), np.zeros(cap))
+
+
+def _to_result(st, r, cap, arrs) -> EvidenceResult:
+    modes, mlz, mll, ldh = arrs
+    n = min(r.n_modes, cap) if st == OK else 0
+    return EvidenceResult(st, r.log_z, r.n_modes, modes[:n].copy(), mlz[:n].copy(),
+                          mll[:n].copy(), ldh[:n].copy(), r.n_logl_evals, r.n_grad_evals,
+                          r.n_hess_evals, r.iterations, r.n_rejected_nonpd, r.n_dead_starts,
+                          r.n_candidates, r.n_reps_pre, list(r.seconds))
+
+
+def _new_result(cap, d):
+    arrs = _result_arrays(cap, d)
+    r = sb_result()
+    r.modes, r.mode_log_z, r.mode_logl, r.log_det_h = (a.ctypes.data for a in arrs)
+    return r, arrs
+
+
+def sb_evidence(prob, cfg) -> EvidenceResult:
+    """Evidence of one problem from host arrays (the library allocates device memory)."""
+    hp = _HostProblem(prob)
+    c = make_config(cfg)
+    r, arrs = _new_result(cfg.max_modes, prob.d)
+    st = lib().sb_evidence(C.byref(hp.ll), C.byref(hp.box), C.byref(c), C.byref(r))
+    return _to_result(st, r, cfg.max_modes, arrs)
+
+
+def sb_evidence_batch(probs: Sequence, cfgs: Sequence) -> list:
+    n = len(probs)
+    hps = [_HostProblem(p) for p in probs]
+    LL = (sb_loglik * n)(*[h.ll for h in hps])
+    BX = (sb_box * n)(*[h.box for h in hps])
+    CF = (sb_config * n)(*[make_config(c) for c in cfgs])
+    RS = (sb_result * n)()
+    keep = []
+    for j in range(n):
+        r, arrs = _new_result(cfgs[j].max_modes, probs[j].d)
+        RS[j] = r
+        keep.append(arrs)
+    lib().sb_evidence_batch(n, LL, BX, CF, RS)
+    out = []
+    for j in range(n):
+        st = OK
+        if RS[j].n_modes == 0 and RS[j].log_z == -math.inf:
+            st = E_NOMODE
+        elif math.isnan(RS[j].log_z):
+            st = E_INVAL
+        out.append(_to_result(st, RS[j], cfgs[j].max_modes, keep[j]))
+    return out
+
+
+# ---------------------------------------------------------------- device path
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class DeviceModel:
+    """Likelihood parameters resident on the GPU plus the prep outputs (beta, log det P)."""
+
+    def __init__(self, prob, device="cuda", low_precision: bool = False):
+        import torch
+
+        self.prob = prob
+        dev = torch.device(device)
+        self.d, self.K = prob.d, prob.K
+        self.log_w = torch.as_tensor(_f64(prob.log_w), device=dev)
+        self.mu = torch.as_tensor(_f64(prob.mu), device=dev)
+        self.prec = torch.as_tensor(_f64(prob.prec), device=dev)
+        self.lo = torch.as_tensor(_f64(prob.lo), device=dev)
+        self.hi = torch.as_tensor(_f64(prob.hi), device=dev)
+        self.beta = torch.zeros(self.K, dtype=torch.float64, device=dev)
+        self.logdet_prec = torch.zeros(self.K, dtype=torch.float64, device=dev)
+        self.prec_f32 = self.prec_bf16 = self.mu_f32 = None
+        if low_precision:
+            self.prec_f32 = torch.empty(self.prec.shape, dtype=torch.float32, device=dev)
+            self.prec_bf16 = torch.empty(self.prec.shape, dtype=torch.int16, device=dev)
+            self.mu_f32 = torch.empty(self.mu.shape, dtype=torch.float32, device=dev)
+        self.ll = sb_loglik(prob.family, prob.norm, prob.d, prob.K, self.log_w.data_ptr(),
+                            self.mu.data_ptr(), self.prec.data_ptr(), float(prob.nu),
+                            float(prob.logl_offset))
+        ws = torch.empty(int(lib().sb_prep_workspace_bytes(self.d, self.K)), dtype=torch.uint8,
+                         device=dev)
+        st = lib().sb_prep_dev(C.byref(self.ll), self.beta.data_ptr(),
+                               self.logdet_prec.data_ptr(), _ptr(self.prec_f32),
+                               _ptr(self.prec_bf16), _ptr(self.mu_f32), ws.data_ptr(), ws.numel(),
+                               _stream())
+        _check(st, "sb_prep_dev")
+
+    def view(self, dtype: int = DTYPE_F64) -> sb_model_dev:
+        lp = None
+        if dtype == DTYPE_F32:
+            lp = _ptr(self.prec_f32)
+        elif dtype == DTYPE_BF16:
+            lp = _ptr(self.prec_bf16)
+        return sb_model_dev(self.prob.family, self.prob.norm, self.d, self.K,
+                            self.log_w.data_ptr(), self.mu.data_ptr(), self.prec.data_ptr(),
+                            float(self.prob.nu), float(self.prob.logl_offset),
+                            self.beta.data_ptr(), lp, _ptr(self.mu_f32))
+
+
+def _ws(nbytes: int, device):
+    import torch
+
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def sb_logl_grad_dev(model: DeviceModel, X, grad: bool = True):
+    """l (and grad l) at the rows of X (float64 -> FP64 path, float32 -> FP32 path)."""
+    import torch
+
+    dt = DTYPE_F64 if X.dtype == torch.float64 else DTYPE_F32
+    X = X.contiguous()
+    B = X.shape[0]
+    l = torch.empty(B, dtype=X.dtype, device=X.device)
+    g = torch.empty_like(X) if grad else None
+    ws = _ws(lib().sb_logl_grad_workspace_bytes(model.d, model.K, B, dt), X.device)
+    mv = model.view(dt)
+    st = lib().sb_logl_grad_dev(C.byref(mv), B, X.data_ptr(), l.data_ptr(), _ptr(g), dt,
+                                ws.data_ptr(), ws.numel(), _stream())
+    _check(st, "sb_logl_grad_dev")
+    return (l, g) if grad else l
+
+
+def sb_hvp_dev(model: DeviceModel, X, V):
+    import torch
+
+    X = X.contiguous().to(torch.float64)
+    V = V.contiguous().to(torch.float64)
+    B = X.shape[0]
+    HV = torch.empty_like(X)
+    ws = _ws(lib().sb_hvp_workspace_bytes(model.d, model.K, B), X.device)
+    mv = model.view(DTYPE_F64)
+    st = lib().sb_hvp_dev(C.byref(mv), B, X.data_ptr(), V.data_ptr(), HV.data_ptr(),
+                          ws.data_ptr(), ws.numel(), _stream())
+    _check(st, "sb_hvp_dev")
+    return HV
+
+
+def sb_discover_dev(model: DeviceModel, R: int, n_pts: int, n_starts: int, seed: int,
+                    dtype: int = DTYPE_F64):
+    import torch
+
+    dev = model.mu.device
+    d = model.d
+    P0 = torch.empty((R, d), dtype=torch.float64, device=dev)
+    P1 = torch.empty((R, d), dtype=torch.float64, device=dev)
+    bl = torch.empty(R, dtype=torch.float64, device=dev)
+    bj = torch.empty(R, dtype=torch.int32, device=dev)
+    sr = torch.empty(n_starts, dtype=torch.int32, device=dev)
+    X0 = torch.empty((n_starts, d), dtype=torch.float64, device=dev)
+    ws = _ws(lib().sb_discover_workspace_bytes(d, model.K, R, n_pts, dtype), dev)
+    mv = model.view(dtype)
+    st = lib().sb_discover_dev(C.byref(mv), model.lo.data_ptr(), model.hi.data_ptr(), R, n_pts,
+                               n_starts, seed, dtype, P0.data_ptr(), P1.data_ptr(), bl.data_ptr(),
+                               bj.data_ptr(), sr.data_ptr(), X0.data_ptr(), ws.data_ptr(),
+                               ws.numel(), _stream())
+    _check(st, "sb_discover_dev")
+    return dict(P0=P0, P1=P1, ray_best_l=bl, ray_best_j=bj, start_ray=sr, X0=X0)
+
+
+def sb_lbfgs_direction_dev(S, Y, G, cnt):
+    import torch
+
+    B, m, d = S.shape
+    dt = DTYPE_F64 if S.dtype == torch.float64 else DTYPE_F32
+    P = torch.empty_like(G)
+    st = lib().sb_lbfgs_direction_dev(B, d, m, cnt.data_ptr(), S.contiguous().data_ptr(),
+                                      Y.contiguous().data_ptr(), G.contiguous().data_ptr(),
+                                      P.data_ptr(), dt, _stream())
+    _check(st, "sb_lbfgs_direction_dev")
+    return P
+
+
+def sb_lbfgs_dev(model: DeviceModel, X0, m: int = 8, max_iter: int = 0, grad_tol: float = 0.0):
+    import torch
+
+    dt = DTYPE_F64 if X0.dtype == torch.float64 else DTYPE_F32
+    X = X0.clone().contiguous()
+    B, d = X.shape
+    l = torch.empty(B, dtype=X.dtype, device=X.device)
+    g = torch.empty_like(X)
+    status = torch.empty(B, dtype=torch.int32, device=X.device)
+    iters = torch.empty(B, dtype=torch.int32, device=X.device)
+    nev = C.c_int64()
+    ws = _ws(lib().sb_lbfgs_workspace_bytes(d, model.K, B, m, dt), X.device)
+    mv = model.view(dt)
+    st = lib().sb_lbfgs_dev(C.byref(mv), B, X.data_ptr(), m, max_iter, grad_tol, dt, l.data_ptr(),
+                            g.data_ptr(), status.data_ptr(), iters.data_ptr(), C.byref(nev),
+                            ws.data_ptr(), ws.numel(), _stream())
+    _check(st, "sb_lbfgs_dev")
+    return dict(x=X, logl=l, grad=g, status=status, iters=iters, n_evals=nev.value)
+
+
+def sb_dedup_dev(X, l, tau: float, valid=None, max_reps: int = 1024):
+    import torch
+
+    Cn, d = X.shape
+    dt = DTYPE_F64 if X.dtype == torch.float64 else DTYPE_F32
+    rep_of = torch.empty(Cn, dtype=torch.int32, device=X.device)
+    reps = torch.empty(max_reps, dtype=torch.int32, device=X.device)
+    n = C.c_int32()
+    ws = _ws(lib().sb_dedup_workspace_bytes(Cn), X.device)
+    v = None if valid is None else valid.to(torch.uint8).contiguous()
+    st = lib().sb_dedup_dev(Cn, d, X.contiguous().data_ptr(), l.contiguous().data_ptr(), _ptr(v),
+                            tau, dt, rep_of.data_ptr(), reps.data_ptr(), max_reps, C.byref(n),
+                            ws.data_ptr(), ws.numel(), _stream())
+    _check(st, "sb_dedup_dev")
+    return rep_of, reps[:n.value]
+
+
+def sb_hessian_dev(model: DeviceModel, X):
+    import torch
+
+    X = X.contiguous().to(torch.float64)
+    Cn = X.shape[0]
+    H = torch.empty((Cn, model.d, model.d), dtype=torch.float64, device=X.device)
+    ws = _ws(lib().sb_hessian_workspace_bytes(model.d, model.K, Cn), X.device)
+    mv = model.view(DTYPE_F64)
+    st = lib().sb_hessian_dev(C.byref(mv), Cn, X.data_ptr(), H.data_ptr(), ws.data_ptr(),
+                              ws.numel(), _stream())
+    _check(st, "sb_hessian_dev")
+    return H
+
+
+def sb_cholesky_logdet_dev(A):
+    import torch
+
+    A = A.contiguous().to(torch.float64)
+    Cn, n, _ = A.shape
+    L = torch.empty_like(A)
+    ld = torch.empty(Cn, dtype=torch.float64, device=A.device)
+    info = torch.empty(Cn, dtype=torch.int32, device=A.device)
+    st = lib().sb_cholesky_logdet_dev(Cn, n, A.data_ptr(), L.data_ptr(), ld.data_ptr(),
+                                      info.data_ptr(), _stream())
+    _check(st, "sb_cholesky_logdet_dev")
+    return L, ld, info
+
+
+def sb_cholesky_solve_dev(L, b):
+    import torch
+
+    L = L.contiguous()
+    b = b.contiguous().to(torch.float64)
+    x = torch.empty_like(b)
+    Cn, n, _ = L.shape
+    st = lib().sb_cholesky_solve_dev(Cn, n, L.data_ptr(), b.data_ptr(), x.data_ptr(), _stream())
+    _check(st, "sb_cholesky_solve_dev")
+    return x
+
+
+def sb_combine_dev(lo, hi, logl, logdet, modes):
+    import torch
+
+    n, d = modes.shape
+    order = torch.empty(n, dtype=torch.int32, device=modes.device)
+    mlz = torch.empty(n, dtype=torch.float64, device=modes.device)
+    lz = torch.empty(1, dtype=torch.float64, device=modes.device)
+    st = lib().sb_combine_dev(n, d, lo.data_ptr(), hi.data_ptr(), logl.contiguous().data_ptr(),
+                              logdet.contiguous().data_ptr(), modes.contiguous().data_ptr(),
+                              order.data_ptr(), mlz.data_ptr(), lz.data_ptr(), _stream())
+    _check(st, "sb_combine_dev")
+    return order, mlz, lz
+
+
+class EvidenceRunner:
+    """Device-resident evidence: inputs in HBM, workspace allocated once (sb_evidence_dev)."""
+
+    def __init__(self, prob, cfg, device="cuda"):
+        import torch
+
+        self.prob, self.cfg = prob, cfg
+        dev = torch.device(device)
+        self.log_w = torch.as_tensor(_f64(prob.log_w), device=dev)
+        self.mu = torch.as_tensor(_f64(prob.mu), device=dev)
+        self.prec = torch.as_tensor(_f64(prob.prec), device=dev)
+        self.lo = torch.as_tensor(_f64(prob.lo), device=dev)
+        self.hi = torch.as_tensor(_f64(prob.hi), device=dev)
+        self.ll = sb_loglik(prob.family, prob.norm, prob.d, prob.K, self.log_w.data_ptr(),
+                            self.mu.data_ptr(), self.prec.data_ptr(), float(prob.nu),
+                            float(prob.logl_offset))
+        self.box = sb_box(self.lo.data_ptr(), self.hi.data_ptr())
+        self.c = make_config(cfg)
+        nb = lib().sb_evidence_workspace_bytes(C.byref(self.ll), C.byref(self.c))
+        if nb == 0:
+            raise SbError(E_INVAL, "sb_evidence_workspace_bytes")
+        self.ws = torch.empty(int(nb), dtype=torch.uint8, device=dev)
+
+    def run(self, stream=None) -> EvidenceResult:
+        r, arrs = _new_result(self.cfg.max_modes, self.prob.d)
+        st = lib().sb_evidence_dev(C.byref(self.ll), C.byref(self.box), C.byref(self.c),
+                                   C.byref(r), self.ws.data_ptr(), self.ws.numel(),
+                                   _stream(stream))
+        return _to_result(st, r, self.cfg.max_modes, arrs)

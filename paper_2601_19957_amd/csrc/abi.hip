@@ -1,0 +1,746 @@
+// extern "C" entry points of sb.h: argument validation (before any HIP call),
+// device checks, workspace sizing, and dispatch to the kernels.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+
+using namespace sb;
+
+namespace {
+
+// The library targets gfx950 only; checked once per process.
+int device_status() {
+  static std::once_flag once;
+  static int status = SB_OK;
+  static char msg[256] = {0};
+  std::call_once(once, [] {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {
+      status = SB_E_DEVICE;
+      snprintf(msg, sizeof(msg), "no HIP device available");
+      return;
+    }
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+      status = SB_E_DEVICE;
+      snprintf(msg, sizeof(msg), "hipGetDeviceProperties failed");
+      return;
+    }
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+      status = SB_E_DEVICE;
+      snprintf(msg, sizeof(msg), "device %s is not gfx950 (MI355X)", prop.gcnArchName);
+    }
+  });
+  if (status != SB_OK) set_error("%s", msg);
+  return status;
+}
+
+int fail(int st, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  char buf[512];
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  set_error("%s", buf);
+  return st;
+}
+
+// Checks that need no array contents.
+int validate_shape(const sb_loglik *ll) {
+  if (!ll) return fail(SB_E_INVAL, "loglik is NULL");
+  if (ll->d < 1) return fail(SB_E_INVAL, "d must be >= 1 (got %d)", ll->d);
+  if (ll->K < 1) return fail(SB_E_INVAL, "K must be >= 1 (got %d)", ll->K);
+  if (ll->family != SB_FAMILY_GAUSS_MIX && ll->family != SB_FAMILY_STUDENT_T)
+    return fail(SB_E_INVAL, "unknown family %d", ll->family);
+  if (ll->norm != SB_NORM_PEAK_ZERO && ll->norm != SB_NORM_DENSITY)
+    return fail(SB_E_INVAL, "unknown normalisation %d", ll->norm);
+  if (!ll->mu || !ll->prec) return fail(SB_E_INVAL, "mu and prec must not be NULL");
+  if (ll->family == SB_FAMILY_STUDENT_T) {
+    if (ll->K != 1) return fail(SB_E_UNSUPPORTED, "Student-t supports K = 1 only");
+    if (!(ll->nu > 0.0) || !std::isfinite(ll->nu)) return fail(SB_E_INVAL, "nu must be > 0");
+  }
+  if (!std::isfinite(ll->logl_offset)) return fail(SB_E_INVAL, "logl_offset must be finite");
+  if (ll->K > 16) return fail(SB_E_UNSUPPORTED, "at most 16 components are supported");
+  return SB_OK;
+}
+
+int validate_cfg(const sb_loglik *ll, const sb_config *c) {
+  if (!c) return fail(SB_E_INVAL, "config is NULL");
+  if (c->m < 1 || c->m > 32) return fail(SB_E_INVAL, "m must be in [1, 32] (got %d)", c->m);
+  if (c->m > kMaxHist)
+    return fail(SB_E_UNSUPPORTED, "m = %d: the register-resident history holds at most %d pairs",
+                c->m, kMaxHist);
+  if (c->n_rays < 1 || c->n_points < 1) return fail(SB_E_INVAL, "n_rays, n_points must be >= 1");
+  if (c->n_starts < 1 || c->n_starts > c->n_rays)
+    return fail(SB_E_INVAL, "need 1 <= n_starts <= n_rays");
+  if (c->max_modes < 1) return fail(SB_E_INVAL, "max_modes must be >= 1");
+  if (c->precision != SB_PREC_FP64 && c->precision != SB_PREC_MIXED)
+    return fail(SB_E_INVAL, "unknown precision %d", c->precision);
+  if (ll->d > 4096) return fail(SB_E_UNSUPPORTED, "d > 4096 is not supported");
+  if ((int64_t)c->n_rays * c->n_points > (int64_t)1 << 30)
+    return fail(SB_E_INVAL, "n_rays * n_points too large");
+  return SB_OK;
+}
+
+int validate_box_host(int d, const double *lo, const double *hi) {
+  if (!lo || !hi) return fail(SB_E_INVAL, "box bounds must not be NULL");
+  for (int i = 0; i < d; ++i)
+    if (!std::isfinite(lo[i]) || !std::isfinite(hi[i]) || !(lo[i] < hi[i]))
+      return fail(SB_E_INVAL, "box coordinate %d: need finite lo < hi", i);
+  return SB_OK;
+}
+
+int validate_arrays_host(const sb_loglik *ll) {
+  const int64_t d = ll->d, K = ll->K;
+  for (int64_t i = 0; i < K * d; ++i)
+    if (!std::isfinite(ll->mu[i])) return fail(SB_E_INVAL, "mu has a non-finite entry");
+  if (ll->log_w)
+    for (int64_t k = 0; k < K; ++k)
+      if (!std::isfinite(ll->log_w[k])) return fail(SB_E_INVAL, "log_w has a non-finite entry");
+  for (int64_t i = 0; i < K * d * d; ++i)
+    if (!std::isfinite(ll->prec[i])) return fail(SB_E_INVAL, "prec has a non-finite entry");
+  return SB_OK;
+}
+
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+Model model_from(const sb_model_dev *m) {
+  Model r;
+  r.family = m->family;
+  r.norm = m->norm;
+  r.d = m->d;
+  r.K = m->K;
+  r.mu64 = m->mu;
+  r.P64 = m->prec;
+  r.beta = m->beta;
+  r.mu32 = m->mu_lp;
+  r.Plp = m->prec_lp;
+  r.nu = m->nu;
+  r.c = m->logl_offset;
+  return r;
+}
+
+int validate_model(const sb_model_dev *m) {
+  if (!m) return fail(SB_E_INVAL, "model is NULL");
+  sb_loglik ll;
+  ll.family = m->family;
+  ll.norm = m->norm;
+  ll.d = m->d;
+  ll.K = m->K;
+  ll.mu = m->mu;
+  ll.prec = m->prec;
+  ll.nu = m->nu;
+  ll.logl_offset = m->logl_offset;
+  ll.log_w = m->log_w;
+  int st = validate_shape(&ll);
+  if (st) return st;
+  if (!m->beta) return fail(SB_E_INVAL, "beta (from sb_prep_dev) must not be NULL");
+  return SB_OK;
+}
+
+size_t eval_bytes(int dtype, int d, int K, int64_t B, bool with_aux) {
+  const size_t es = (dtype == SB_DTYPE_F64) ? 8 : 4;
+  size_t n = align_up(es * (size_t)B * K * d) + align_up(es * (size_t)B * K * ceil_div(d, 64));
+  if (with_aux) n += align_up(es * (size_t)B * K) + align_up(es * (size_t)B * d);
+  return n + 1024;
+}
+
+}  // namespace
+
+// =====================================================================
+extern "C" {
+
+const char *sb_status_string(int32_t st) {
+  switch (st) {
+    case SB_OK: return "SB_OK";
+    case SB_E_INVAL: return "SB_E_INVAL: invalid argument";
+    case SB_E_NOTPD: return "SB_E_NOTPD: precision matrix not symmetric positive definite";
+    case SB_E_NOMEM: return "SB_E_NOMEM: out of device memory or workspace too small";
+    case SB_E_DEVICE: return "SB_E_DEVICE: HIP runtime error or no gfx950 device";
+    case SB_E_NOMODE: return "SB_E_NOMODE: no mode passed the filters";
+    case SB_E_CAPACITY: return "SB_E_CAPACITY: more modes than max_modes";
+    case SB_E_UNSUPPORTED: return "SB_E_UNSUPPORTED: valid but unsupported request";
+    default: return "unknown status";
+  }
+}
+
+const char *sb_last_error(void) { return last_error(); }
+int32_t sb_abi_version(void) { return SB_ABI_VERSION; }
+
+size_t sb_evidence_workspace_bytes(const sb_loglik *ll, const sb_config *cfg) {
+  if (validate_shape(ll) || validate_cfg(ll, cfg)) return 0;
+  return evidence_ws_bytes(ll, cfg);
+}
+
+int32_t sb_evidence_dev(const sb_loglik *ll, const sb_box *box, const sb_config *cfg,
+                        sb_result *res, void *workspace, size_t ws_bytes, void *stream) {
+  int st = validate_shape(ll);
+  if (!st) st = validate_cfg(ll, cfg);
+  if (!st && (!box || !box->lo || !box->hi)) st = fail(SB_E_INVAL, "box is NULL");
+  if (!st && !res) st = fail(SB_E_INVAL, "result is NULL");
+  if (st) {
+    if (res) res->log_z = NAN;
+    return st;
+  }
+  if ((st = device_status())) {
+    res->log_z = NAN;
+    return st;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  // box contents are validated on the host (2d values)
+  {
+    std::vector<double> lo(ll->d), hi(ll->d);
+    if (hipMemcpy(lo.data(), box->lo, sizeof(double) * ll->d, hipMemcpyDeviceToHost) ||
+        hipMemcpy(hi.data(), box->hi, sizeof(double) * ll->d, hipMemcpyDeviceToHost)) {
+      res->log_z = NAN;
+      return fail(SB_E_DEVICE, "reading the box failed");
+    }
+    if ((st = validate_box_host(ll->d, lo.data(), hi.data()))) {
+      res->log_z = NAN;
+      return st;
+    }
+  }
+  hipStream_t own = nullptr;
+  if (s == nullptr) {
+    if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess)
+      return fail(SB_E_DEVICE, "stream creation failed");
+    (void)hipDeviceSynchronize();
+    s = own;
+  }
+  DevProblem P;
+  P.family = ll->family;
+  P.norm = ll->norm;
+  P.d = ll->d;
+  P.K = ll->K;
+  P.log_w = ll->log_w;
+  P.mu = ll->mu;
+  P.prec = ll->prec;
+  P.lo = box->lo;
+  P.hi = box->hi;
+  P.nu = ll->nu;
+  P.c = ll->logl_offset;
+  st = run_evidence(P, cfg, res, workspace, ws_bytes, s);
+  if (own) {
+    (void)hipStreamSynchronize(own);
+    (void)hipStreamDestroy(own);
+  }
+  if (st && st != SB_E_NOMODE && st != SB_E_CAPACITY) res->log_z = NAN;
+  return st;
+}
+
+int32_t sb_evidence(const sb_loglik *ll, const sb_box *box, const sb_config *cfg,
+                    sb_result *res) {
+  int st = validate_shape(ll);
+  if (!st) st = validate_cfg(ll, cfg);
+  if (!st && !box) st = fail(SB_E_INVAL, "box is NULL");
+  if (!st) st = validate_box_host(ll->d, box->lo, box->hi);
+  if (!st && !res) st = fail(SB_E_INVAL, "result is NULL");
+  if (!st) st = validate_arrays_host(ll);
+  if (st) {
+    if (res) res->log_z = NAN;
+    return st;
+  }
+  if ((st = device_status())) {
+    res->log_z = NAN;
+    return st;
+  }
+  const int64_t d = ll->d, K = ll->K;
+  const size_t n_prob = align_up(8 * K) + align_up(8 * K * d) + align_up(8 * K * d * d) +
+                        2 * align_up(8 * d);
+  const size_t ws = evidence_ws_bytes(ll, cfg);
+  DevBuf buf;
+  if (hipMalloc(&buf.p, n_prob + ws) != hipSuccess) {
+    res->log_z = NAN;
+    return fail(SB_E_NOMEM, "hipMalloc of %zu bytes failed", n_prob + ws);
+  }
+  char *p = (char *)buf.p;
+  double *lw = (double *)p;
+  p += align_up(8 * K);
+  double *mu = (double *)p;
+  p += align_up(8 * K * d);
+  double *prec = (double *)p;
+  p += align_up(8 * K * d * d);
+  double *lo = (double *)p;
+  p += align_up(8 * d);
+  double *hi = (double *)p;
+  p += align_up(8 * d);
+  hipStream_t s;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+    res->log_z = NAN;
+    return fail(SB_E_DEVICE, "stream creation failed");
+  }
+  bool ok = true;
+  if (ll->log_w) ok &= hipMemcpyAsync(lw, ll->log_w, 8 * K, hipMemcpyHostToDevice, s) == hipSuccess;
+  ok &= hipMemcpyAsync(mu, ll->mu, 8 * K * d, hipMemcpyHostToDevice, s) == hipSuccess;
+  ok &= hipMemcpyAsync(prec, ll->prec, 8 * K * d * d, hipMemcpyHostToDevice, s) == hipSuccess;
+  ok &= hipMemcpyAsync(lo, box->lo, 8 * d, hipMemcpyHostToDevice, s) == hipSuccess;
+  ok &= hipMemcpyAsync(hi, box->hi, 8 * d, hipMemcpyHostToDevice, s) == hipSuccess;
+  if (!ok) {
+    (void)hipStreamDestroy(s);
+    res->log_z = NAN;
+    return fail(SB_E_DEVICE, "host-to-device copy failed");
+  }
+  DevProblem P;
+  P.family = ll->family;
+  P.norm = ll->norm;
+  P.d = ll->d;
+  P.K = ll->K;
+  P.log_w = ll->log_w ? lw : nullptr;
+  P.mu = mu;
+  P.prec = prec;
+  P.lo = lo;
+  P.hi = hi;
+  P.nu = ll->nu;
+  P.c = ll->logl_offset;
+  st = run_evidence(P, cfg, res, p, ws, s);
+  (void)hipStreamSynchronize(s);
+  (void)hipStreamDestroy(s);
+  if (st && st != SB_E_NOMODE && st != SB_E_CAPACITY) res->log_z = NAN;
+  return st;
+}
+
+int32_t sb_evidence_batch(int32_t n, const sb_loglik *ll, const sb_box *box,
+                          const sb_config *cfg, sb_result *res) {
+  if (n < 0 || (n > 0 && (!ll || !box || !cfg || !res)))
+    return fail(SB_E_INVAL, "invalid batch arguments");
+  int first_err = SB_OK;
+  for (int j = 0; j < n; ++j) {
+    int st = sb_evidence(&ll[j], &box[j], &cfg[j], &res[j]);
+    if (st && st != SB_E_NOMODE && first_err == SB_OK) first_err = st;
+  }
+  return first_err;
+}
+
+// ------------------------------------------------------------------ prep
+size_t sb_prep_workspace_bytes(int32_t d, int32_t K) {
+  if (d < 1 || K < 1) return 0;
+  return align_up(8ull * K * d * d) + 4 * align_up(8ull * K) + align_up(64) + 1024;
+}
+
+int32_t sb_prep_dev(const sb_loglik *ll, double *beta, double *logdet_prec, float *prec_f32,
+                    uint16_t *prec_bf16, float *mu_f32, void *workspace, size_t ws_bytes,
+                    void *stream) {
+  int st = validate_shape(ll);
+  if (st) return st;
+  if (!beta || !logdet_prec) return fail(SB_E_INVAL, "beta and logdet_prec must not be NULL");
+  if (!workspace || ws_bytes < sb_prep_workspace_bytes(ll->d, ll->K))
+    return fail(SB_E_NOMEM, "prep workspace too small");
+  if ((st = device_status())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int d = ll->d, K = ll->K;
+  Arena ar(workspace, ws_bytes);
+  double *Lp = ar.take<double>((size_t)K * d * d);
+  double *mx = ar.take<double>(K);
+  int32_t *info = ar.take<int32_t>(K);
+  int32_t *flags = ar.take<int32_t>(16);
+  Model m;
+  m.family = ll->family;
+  m.norm = ll->norm;
+  m.d = d;
+  m.K = K;
+  m.mu64 = ll->mu;
+  m.P64 = ll->prec;
+  m.nu = ll->nu;
+  m.c = ll->logl_offset;
+  if ((st = launch_fill_i32(16, 0, flags, s))) return st;
+  if ((st = launch_symmetry_check(ll->prec, K, d, mx, flags, s))) return st;
+  if ((st = chol_batched(K, d, ll->prec, Lp, info, s))) return st;
+  if ((st = launch_logdet(K, d, Lp, info, logdet_prec, s))) return st;
+  if ((st = launch_beta(m, ll->log_w, logdet_prec, beta, s))) return st;
+  if (prec_f32 || prec_bf16 || mu_f32) {
+    if ((st = launch_convert_model(m, prec_f32, (bf16_t *)prec_bf16, mu_f32, s))) return st;
+  }
+  std::vector<int32_t> hinfo(K);
+  int32_t hflag = 0;
+  if (hipMemcpyAsync(&hflag, flags, 4, hipMemcpyDeviceToHost, s) ||
+      hipMemcpyAsync(hinfo.data(), info, 4 * K, hipMemcpyDeviceToHost, s) ||
+      hipStreamSynchronize(s))
+    return fail(SB_E_DEVICE, "prep readback failed");
+  if (hflag) return fail(SB_E_NOTPD, "precision matrix is not symmetric to 1e-12 relative");
+  for (int k = 0; k < K; ++k)
+    if (hinfo[k]) return fail(SB_E_NOTPD, "precision matrix %d is not positive definite", k);
+  return SB_OK;
+}
+
+// ------------------------------------------------------------- logl + grad
+size_t sb_logl_grad_workspace_bytes(int32_t d, int32_t K, int64_t B, int32_t dtype) {
+  if (d < 1 || K < 1 || B < 0) return 0;
+  return eval_bytes(dtype == SB_DTYPE_F64 ? SB_DTYPE_F64 : SB_DTYPE_F32, d, K, B, false);
+}
+
+int32_t sb_logl_grad_dev(const sb_model_dev *mdl, int64_t B, const void *X, void *logl,
+                         void *grad, int32_t dtype, void *workspace, size_t ws_bytes,
+                         void *stream) {
+  int st = validate_model(mdl);
+  if (st) return st;
+  if (B < 0 || (B > 0 && (!X || !logl))) return fail(SB_E_INVAL, "bad B / X / logl");
+  if (dtype != SB_DTYPE_F64 && dtype != SB_DTYPE_F32)
+    return fail(SB_E_INVAL, "dtype must be F64 or F32");
+  if (dtype == SB_DTYPE_F32 && (!mdl->prec_lp || !mdl->mu_lp))
+    return fail(SB_E_INVAL, "F32 needs prec_lp (FP32) and mu_lp");
+  if (B == 0) return SB_OK;
+  if (!workspace || ws_bytes < sb_logl_grad_workspace_bytes(mdl->d, mdl->K, B, dtype))
+    return fail(SB_E_NOMEM, "workspace too small");
+  if ((st = device_status())) return st;
+  Model m = model_from(mdl);
+  const size_t es = dtype == SB_DTYPE_F64 ? 8 : 4;
+  Arena ar(workspace, ws_bytes);
+  void *Y = ar.take<char>(es * (size_t)B * m.K * m.d);
+  void *qp = ar.take<char>(es * (size_t)B * m.K * ceil_div(m.d, 64));
+  ASrc a;
+  a.kind = 0;
+  a.X = X;
+  a.ldx = m.d;
+  QuadOut o;
+  o.Y = Y;
+  o.ldy = (int64_t)m.K * m.d;
+  o.qpart = qp;
+  TileCfg t = autotune_tiles(dtype, m, B, (hipStream_t)stream);
+  if ((st = launch_quad_gemm(dtype, m, a, B, nullptr, o, t, (hipStream_t)stream))) return st;
+  FinishArgs f;
+  f.M = B;
+  f.qpart = qp;
+  f.ntn = o.ntn;
+  f.Y = Y;
+  f.ldy = o.ldy;
+  f.logl = logl;
+  f.grad = grad;
+  f.ldg = m.d;
+  return launch_finish(dtype, m, f, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------- HVP
+size_t sb_hvp_workspace_bytes(int32_t d, int32_t K, int64_t B) {
+  if (d < 1 || K < 1 || B < 0) return 0;
+  return 2 * eval_bytes(SB_DTYPE_F64, d, K, B, false);
+}
+
+int32_t sb_hvp_dev(const sb_model_dev *mdl, int64_t B, const double *X, const double *V,
+                   double *HV, void *workspace, size_t ws_bytes, void *stream) {
+  int st = validate_model(mdl);
+  if (st) return st;
+  if (B < 0 || (B > 0 && (!X || !V || !HV))) return fail(SB_E_INVAL, "bad B / X / V / HV");
+  if (B == 0) return SB_OK;
+  if (!workspace || ws_bytes < sb_hvp_workspace_bytes(mdl->d, mdl->K, B))
+    return fail(SB_E_NOMEM, "workspace too small");
+  if ((st = device_status())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Model m = model_from(mdl);
+  Arena ar(workspace, ws_bytes);
+  double *Y = ar.take<double>((size_t)B * m.K * m.d);
+  double *Z = ar.take<double>((size_t)B * m.K * m.d);
+  double *qp = ar.take<double>((size_t)B * m.K * ceil_div(m.d, 64));
+  double *qz = ar.take<double>((size_t)B * m.K * ceil_div(m.d, 64));
+  TileCfg t = autotune_tiles(SB_DTYPE_F64, m, B, s);
+  ASrc a;
+  a.kind = 0;
+  a.X = X;
+  a.ldx = m.d;
+  QuadOut o;
+  o.Y = Y;
+  o.ldy = (int64_t)m.K * m.d;
+  o.qpart = qp;
+  if ((st = launch_quad_gemm(SB_DTYPE_F64, m, a, B, nullptr, o, t, s))) return st;
+  ASrc av = a;
+  av.X = V;
+  av.zero_mu = true;
+  QuadOut oz;
+  oz.Y = Z;
+  oz.ldy = o.ldy;
+  oz.qpart = qz;
+  if ((st = launch_quad_gemm(SB_DTYPE_F64, m, av, B, nullptr, oz, t, s))) return st;
+  HvpArgs h;
+  h.M = B;
+  h.qpart = qp;
+  h.ntn = o.ntn;
+  h.Y = Y;
+  h.Z = Z;
+  h.ldy = o.ldy;
+  h.V = V;
+  h.HV = HV;
+  return launch_hvp_finish(m, h, s);
+}
+
+// ------------------------------------------------------------- discovery
+size_t sb_discover_workspace_bytes(int32_t d, int32_t K, int32_t R, int32_t n_pts, int32_t dtype) {
+  if (d < 1 || K < 1 || R < 1 || n_pts < 1) return 0;
+  const int64_t NP = (int64_t)R * n_pts;
+  const size_t es = dtype == SB_DTYPE_F64 ? 8 : 4;
+  return 2 * align_up(8ull * R * d) + 2 * align_up(4ull * R * d) + align_up(es * NP) +
+         align_up(es * (size_t)NP * K * ceil_div(d, 64)) + 2048;
+}
+
+int32_t sb_discover_dev(const sb_model_dev *mdl, const double *lo, const double *hi, int32_t R,
+                        int32_t n_pts, int32_t n_starts, uint64_t seed, int32_t dtype, double *P0,
+                        double *P1, double *ray_best_l, int32_t *ray_best_j, int32_t *start_ray,
+                        double *X0, void *workspace, size_t ws_bytes, void *stream) {
+  int st = validate_model(mdl);
+  if (st) return st;
+  if (!lo || !hi || !ray_best_l || !ray_best_j || !start_ray || !X0)
+    return fail(SB_E_INVAL, "NULL output");
+  if (R < 1 || n_pts < 1 || n_starts < 1 || n_starts > R)
+    return fail(SB_E_INVAL, "need R, n_pts >= 1 and 1 <= n_starts <= R");
+  if (dtype != SB_DTYPE_F64 && dtype != SB_DTYPE_BF16)
+    return fail(SB_E_INVAL, "discovery dtype must be F64 or BF16");
+  if (dtype == SB_DTYPE_BF16 && (!mdl->prec_lp || !mdl->mu_lp))
+    return fail(SB_E_INVAL, "BF16 needs prec_lp (BF16) and mu_lp");
+  if (!workspace || ws_bytes < sb_discover_workspace_bytes(mdl->d, mdl->K, R, n_pts, dtype))
+    return fail(SB_E_NOMEM, "workspace too small");
+  if ((st = device_status())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Model m = model_from(mdl);
+  const int d = m.d;
+  const int64_t NP = (int64_t)R * n_pts;
+  const size_t es = dtype == SB_DTYPE_F64 ? 8 : 4;
+  Arena ar(workspace, ws_bytes);
+  double *p0 = ar.take<double>((size_t)R * d), *p1 = ar.take<double>((size_t)R * d);
+  float *p0f = ar.take<float>((size_t)R * d), *p1f = ar.take<float>((size_t)R * d);
+  void *lpts = ar.take<char>(es * NP);
+  void *qp = ar.take<char>(es * (size_t)NP * m.K * ceil_div(d, 64));
+  if (P0) p0 = P0;
+  if (P1) p1 = P1;
+  const bool bf = dtype == SB_DTYPE_BF16;
+  if ((st = launch_rays(d, lo, hi, R, seed, 0u, p0, p1, bf ? p0f : nullptr, bf ? p1f : nullptr,
+                        s)))
+    return st;
+  ASrc a;
+  a.kind = 1;
+  a.P0 = bf ? (const void *)p0f : (const void *)p0;
+  a.P1 = bf ? (const void *)p1f : (const void *)p1;
+  a.n_pts = n_pts;
+  QuadOut o;
+  o.Y = nullptr;
+  o.ldy = (int64_t)m.K * d;
+  o.qpart = qp;
+  TileCfg t = autotune_tiles(dtype, m, NP, s);
+  if ((st = launch_quad_gemm(dtype, m, a, NP, nullptr, o, t, s))) return st;
+  FinishArgs f;
+  f.M = NP;
+  f.qpart = qp;
+  f.ntn = o.ntn;
+  f.logl = lpts;
+  if ((st = launch_finish(bf ? SB_DTYPE_F32 : SB_DTYPE_F64, m, f, s))) return st;
+  if ((st = launch_ray_argmax(R, n_pts, bf ? SB_DTYPE_F32 : SB_DTYPE_F64, lpts, ray_best_l,
+                              ray_best_j, s)))
+    return st;
+  if ((st = launch_topn(R, n_starts, ray_best_l, start_ray, s))) return st;
+  return launch_gather_starts(d, n_pts, n_starts, start_ray, ray_best_j, p0, p1, X0, s);
+}
+
+// ---------------------------------------------------------------- L-BFGS
+int32_t sb_lbfgs_direction_dev(int64_t B, int32_t d, int32_t m, const int32_t *cnt,
+                               const void *S, const void *Y, const void *G, void *P,
+                               int32_t dtype, void *stream) {
+  if (B < 0 || d < 1 || m < 1 || (B > 0 && (!cnt || !S || !Y || !G || !P)))
+    return fail(SB_E_INVAL, "bad two-loop arguments");
+  if (dtype != SB_DTYPE_F64 && dtype != SB_DTYPE_F32)
+    return fail(SB_E_INVAL, "dtype must be F64 or F32");
+  if (m > kMaxHist) return fail(SB_E_UNSUPPORTED, "m > %d", kMaxHist);
+  if (B == 0) return SB_OK;
+  int st = device_status();
+  if (st) return st;
+  return launch_two_loop(B, d, m, cnt, S, Y, G, P, dtype, (hipStream_t)stream);
+}
+
+size_t sb_lbfgs_workspace_bytes(int32_t d, int32_t K, int64_t B, int32_t m, int32_t dtype) {
+  if (d < 1 || K < 1 || B < 1 || m < 1) return 0;
+  const int dt = dtype == SB_DTYPE_F64 ? SB_DTYPE_F64 : SB_DTYPE_F32;
+  return lbfgs_state_bytes(dt, B, d, m) + eval_bytes(dt, d, K, B, false) + 4096;
+}
+
+int32_t sb_lbfgs_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m, int32_t max_iter,
+                     double grad_tol, int32_t dtype, void *logl, void *grad, int32_t *status,
+                     int32_t *iters, int64_t *n_evals, void *workspace, size_t ws_bytes,
+                     void *stream) {
+  int st = validate_model(mdl);
+  if (st) return st;
+  if (B < 1 || !X) return fail(SB_E_INVAL, "bad B / X");
+  if (m < 1 || m > kMaxHist) return fail(SB_E_UNSUPPORTED, "m must be in [1, %d]", kMaxHist);
+  if (dtype != SB_DTYPE_F64 && dtype != SB_DTYPE_F32)
+    return fail(SB_E_INVAL, "dtype must be F64 or F32");
+  if (dtype == SB_DTYPE_F32 && (!mdl->prec_lp || !mdl->mu_lp))
+    return fail(SB_E_INVAL, "F32 needs prec_lp (FP32) and mu_lp");
+  if (!workspace || ws_bytes < sb_lbfgs_workspace_bytes(mdl->d, mdl->K, B, m, dtype))
+    return fail(SB_E_NOMEM, "workspace too small");
+  if ((st = device_status())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Model md = model_from(mdl);
+  const int d = md.d;
+  Arena ar(workspace, ws_bytes);
+  LbfgsBuffers lb;
+  lb.dtype = dtype;
+  lb.B = B;
+  lb.d = d;
+  lb.m = m;
+  if ((st = lbfgs_carve(ar, lb))) return fail(st, "workspace too small");
+  const size_t es = dtype == SB_DTYPE_F64 ? 8 : 4;
+  void *Y = ar.take<char>(es * (size_t)B * md.K * d);
+  void *qp = ar.take<char>(es * (size_t)B * md.K * ceil_div(d, 64));
+  if ((st = launch_lbfgs_init(lb, X, s))) return st;
+  TileCfg t = autotune_tiles(dtype, md, B, s);
+  auto eval = [&](const int32_t *rowmap, const int32_t *count) -> int {
+    ASrc a;
+    a.kind = 0;
+    a.X = lb.X;
+    a.ldx = d;
+    a.rowmap = rowmap;
+    QuadOut o;
+    o.Y = Y;
+    o.ldy = (int64_t)md.K * d;
+    o.qpart = qp;
+    int r = launch_quad_gemm(dtype, md, a, B, count, o, t, s);
+    if (r) return r;
+    FinishArgs f;
+    f.M = B;
+    f.count = count;
+    f.outmap = rowmap;
+    f.qpart = qp;
+    f.ntn = o.ntn;
+    f.Y = Y;
+    f.ldy = o.ldy;
+    f.logl = lb.F;
+    f.grad = lb.G;
+    f.ldg = d;
+    return launch_finish(dtype, md, f, s);
+  };
+  if ((st = eval(nullptr, nullptr))) return st;
+  const int mi = max_iter > 0 ? max_iter : 10 * d + 200;
+  const double tol = grad_tol > 0 ? grad_tol : 1e-10;
+  int32_t hcount = 1;
+  for (int64_t step = 0; step < 42ll * mi + 64 && hcount > 0; ++step) {
+    if ((st = launch_lbfgs_step(lb, mi, tol, s))) return st;
+    if ((st = launch_compact(lb, s))) return st;
+    if ((st = eval(lb.idx, lb.count))) return st;
+    if ((step & 7) == 7) {
+      if (hipMemcpyAsync(&hcount, lb.count, 4, hipMemcpyDeviceToHost, s) ||
+          hipStreamSynchronize(s))
+        return fail(SB_E_DEVICE, "count readback failed");
+    }
+  }
+  if ((st = launch_lbfgs_gather(lb, X, logl, grad, status, iters, s))) return st;
+  if (n_evals) {
+    if (hipMemcpyAsync(n_evals, lb.evals, 8, hipMemcpyDeviceToHost, s) || hipStreamSynchronize(s))
+      return fail(SB_E_DEVICE, "eval count readback failed");
+  }
+  return SB_OK;
+}
+
+// ----------------------------------------------------------------- dedup
+size_t sb_dedup_workspace_bytes(int32_t C) { return dedup_ws_bytes(C) + 1024; }
+
+int32_t sb_dedup_dev(int32_t C, int32_t d, const void *X, const void *l, const uint8_t *valid,
+                     double tau, int32_t dtype, int32_t *rep_of, int32_t *reps, int32_t max_reps,
+                     int32_t *n_reps, void *workspace, size_t ws_bytes, void *stream) {
+  if (C < 0 || d < 1 || (C > 0 && (!X || !l || !rep_of || !reps)) || max_reps < 1 || !n_reps)
+    return fail(SB_E_INVAL, "bad dedup arguments");
+  if (!(tau >= 0.0)) return fail(SB_E_INVAL, "tau must be >= 0");
+  if (dtype != SB_DTYPE_F64 && dtype != SB_DTYPE_F32)
+    return fail(SB_E_INVAL, "dtype must be F64 or F32");
+  if (!workspace || ws_bytes < sb_dedup_workspace_bytes(C))
+    return fail(SB_E_NOMEM, "workspace too small");
+  int st = device_status();
+  if (st) return st;
+  Arena ar(workspace, ws_bytes);
+  int n = 0;
+  st = dedup_run(C, d, X, l, valid, tau, dtype, rep_of, reps, max_reps, &n, ar,
+                 (hipStream_t)stream);
+  *n_reps = n;
+  if (st == SB_E_CAPACITY) set_error("%d representatives exceed max_reps = %d", n, max_reps);
+  return st;
+}
+
+// --------------------------------------------------------------- Hessian
+size_t sb_hessian_workspace_bytes(int32_t d, int32_t K, int32_t C) {
+  if (d < 1 || K < 1 || C < 0) return 0;
+  return eval_bytes(SB_DTYPE_F64, d, K, C, true) + align_up(8ull * C) + 1024;
+}
+
+int32_t sb_hessian_dev(const sb_model_dev *mdl, int32_t C, const double *X, double *H,
+                       void *workspace, size_t ws_bytes, void *stream) {
+  int st = validate_model(mdl);
+  if (st) return st;
+  if (C < 0 || (C > 0 && (!X || !H))) return fail(SB_E_INVAL, "bad C / X / H");
+  if (C == 0) return SB_OK;
+  if (!workspace || ws_bytes < sb_hessian_workspace_bytes(mdl->d, mdl->K, C))
+    return fail(SB_E_NOMEM, "workspace too small");
+  if ((st = device_status())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Model m = model_from(mdl);
+  Arena ar(workspace, ws_bytes);
+  double *Y = ar.take<double>((size_t)C * m.K * m.d);
+  double *qp = ar.take<double>((size_t)C * m.K * ceil_div(m.d, 64));
+  double *aux = ar.take<double>((size_t)C * m.K);
+  double *G = ar.take<double>((size_t)C * m.d);
+  double *l = ar.take<double>(C);
+  ASrc a;
+  a.kind = 0;
+  a.X = X;
+  a.ldx = m.d;
+  QuadOut o;
+  o.Y = Y;
+  o.ldy = (int64_t)m.K * m.d;
+  o.qpart = qp;
+  TileCfg t = autotune_tiles(SB_DTYPE_F64, m, C, s);
+  if ((st = launch_quad_gemm(SB_DTYPE_F64, m, a, C, nullptr, o, t, s))) return st;
+  FinishArgs f;
+  f.M = C;
+  f.qpart = qp;
+  f.ntn = o.ntn;
+  f.Y = Y;
+  f.ldy = o.ldy;
+  f.logl = l;
+  f.grad = G;
+  f.ldg = m.d;
+  f.aux = aux;
+  if ((st = launch_finish(SB_DTYPE_F64, m, f, s))) return st;
+  return launch_hessian_assemble(m, C, Y, o.ldy, aux, G, H, s);
+}
+
+// -------------------------------------------------------------- Cholesky
+int32_t sb_cholesky_logdet_dev(int32_t C, int32_t n, const double *A, double *L, double *logdet,
+                               int32_t *info, void *stream) {
+  if (C < 0 || n < 1 || (C > 0 && (!A || !L || !logdet || !info)))
+    return fail(SB_E_INVAL, "bad Cholesky arguments");
+  if (C == 0) return SB_OK;
+  int st = device_status();
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = chol_batched(C, n, A, L, info, s))) return st;
+  return launch_logdet(C, n, L, info, logdet, s);
+}
+
+int32_t sb_cholesky_solve_dev(int32_t C, int32_t n, const double *L, const double *b, double *x,
+                              void *stream) {
+  if (C < 0 || n < 1 || (C > 0 && (!L || !b || !x))) return fail(SB_E_INVAL, "bad solve arguments");
+  if (C == 0) return SB_OK;
+  int st = device_status();
+  if (st) return st;
+  return launch_chol_solve(C, n, L, b, x, nullptr, (hipStream_t)stream);
+}
+
+// --------------------------------------------------------------- combine
+int32_t sb_combine_dev(int32_t n, int32_t d, const double *lo, const double *hi,
+                       const double *logl, const double *logdet, const double *modes,
+                       int32_t *order, double *mode_log_z, double *log_z, void *stream) {
+  if (n < 0 || d < 1 || !lo || !hi || !log_z ||
+      (n > 0 && (!logl || !logdet || !modes || !order || !mode_log_z)))
+    return fail(SB_E_INVAL, "bad combine arguments");
+  int st = device_status();
+  if (st) return st;
+  return launch_combine(n, d, lo, hi, logl, logdet, modes, order, mode_log_z, log_z,
+                        (hipStream_t)stream);
+}
+
+}  // extern "C"

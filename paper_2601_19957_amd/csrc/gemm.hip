@@ -1,0 +1,620 @@
+// Quadratic-form GEMM of the likelihood families on the CDNA4 matrix cores,
+// and its row epilogues (log-likelihood, hand-written gradient, HVP,
+// Hessian assembly).
+//
+// For points x_r (rows of A) and each component k the GEMM forms
+//   Y_k[r][n] = sum_j P_k[n][j] (x_r[j] - mu_k[j])      (= (P_k delta_k)_n)
+// on MFMA tiles (FP64 16x16x4, FP32 16x16x4, BF16 16x16x32 with FP32
+// accumulation) and, in the epilogue, the partial quadratic forms
+//   qpart[r][k][tile] = sum_{n in tile} delta_k[r][n] Y_k[r][n],
+// so that q_k = (x - mu_k)^T P_k (x - mu_k) is a fixed-order sum of tiles.
+// The row epilogue then applies the family's closed forms: for the Gaussian
+// mixture l = c + logsumexp_k(beta_k - q_k/2) and grad l = -sum_k r_k Y_k
+// with r = softmax(beta - q/2); for the Student-t l = c + beta -
+// ((nu+d)/2) log1p(q/nu) and grad l = -((nu+d)/(nu+q)) Y.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace sb {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+template <typename TOp>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  using acc_t = double;
+  using accv = d4v;
+  static constexpr int KPI = 4;  // k per instruction
+  static constexpr int KPL = 1;  // k values per lane
+  // accumulator item v of lane l holds row lr + 4v (lr = l/16), column l%16
+  __device__ static int row(int lr, int v) { return lr + 4 * v; }
+  __device__ static accv mma(const double *a, const double *b, accv c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<float> {
+  using acc_t = float;
+  using accv = f4v;
+  static constexpr int KPI = 4;
+  static constexpr int KPL = 1;
+  // accumulator item v of lane l holds row 4 lr + v (lr = l/16), column l%16
+  __device__ static int row(int lr, int v) { return 4 * lr + v; }
+  __device__ static accv mma(const float *a, const float *b, accv c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<bf16_t> {
+  using acc_t = float;
+  using accv = f4v;
+  static constexpr int KPI = 32;
+  static constexpr int KPL = 8;
+  __device__ static int row(int lr, int v) { return 4 * lr + v; }
+  __device__ static accv mma(const bf16_t *a, const bf16_t *b, accv c) {
+    bf8v va = *reinterpret_cast<const bf8v *>(a);
+    bf8v vb = *reinterpret_cast<const bf8v *>(b);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, c, 0, 0, 0);
+  }
+};
+
+template <typename TOp>
+__device__ inline TOp to_op(float v);
+template <>
+__device__ inline float to_op<float>(float v) { return v; }
+template <>
+__device__ inline bf16_t to_op<bf16_t>(float v) { return f32_to_bf16(v); }
+__device__ inline double to_op_d(double v) { return v; }
+
+struct GemmParams {
+  ASrc a;
+  int64_t M;
+  const int32_t *count;
+  int d, K, ntn;
+  const void *mu;  // [K][d] of type TIn
+  const void *P;   // [K][d][d] of type TOp
+  void *Y;
+  int64_t ldy;
+  void *qpart;
+};
+
+// Value of point `row` at coordinate j (type TIn), without the mean.
+template <typename TIn>
+__device__ inline TIn point_value(const ASrc &a, int64_t row, int64_t d, int j) {
+  if (a.kind == 0) {
+    int64_t r = a.rowmap ? (int64_t)a.rowmap[row] : row;
+    return ((const TIn *)a.X)[r * a.ldx + j];
+  }
+  {
+    // ray point p + t (q - p), t = (j + 1/2) / n_pts; no contraction into an
+    // FMA so that the value is the same two-rounding expression everywhere.
+#pragma clang fp contract(off)
+    int64_t ray = row / a.n_pts;
+    int jj = (int)(row % a.n_pts);
+    TIn t = ((TIn)jj + (TIn)0.5) / (TIn)a.n_pts;
+    TIn p = ((const TIn *)a.P0)[ray * d + j];
+    TIn q = ((const TIn *)a.P1)[ray * d + j];
+    return p + t * (q - p);
+  }
+}
+
+template <typename TIn, typename TOp, int BM, int BN, int BK>
+__global__ __launch_bounds__(256) void quad_gemm_kernel(GemmParams g) {
+  using MF = Mfma<TOp>;
+  using TAcc = typename MF::acc_t;
+  using accv = typename MF::accv;
+  constexpr int PAD = (sizeof(TOp) == 8) ? 2 : (sizeof(TOp) == 4 ? 4 : 8);
+  constexpr int LDA = BK + PAD;
+  constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+  __shared__ __attribute__((aligned(16))) TOp As[BM * LDA];
+  __shared__ __attribute__((aligned(16))) TOp Bs[BN * LDA];
+  __shared__ TAcc qs[2][BM];
+
+  const int64_t M = g.count ? (int64_t)(*g.count) : g.M;
+  const int64_t m0 = (int64_t)blockIdx.x * BM;
+  if (m0 >= M) return;
+  const int k = blockIdx.y / g.ntn;
+  const int n0 = (blockIdx.y % g.ntn) * BN;
+  const int d = g.d;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const TIn *mu = g.a.zero_mu ? nullptr : (const TIn *)g.mu + (size_t)k * d;
+  const TOp *Pk = (const TOp *)g.P + (size_t)k * d * d;
+
+  accv acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = accv{0, 0, 0, 0};
+
+  for (int k0 = 0; k0 < d; k0 += BK) {
+    // A tile: delta = x - mu, converted to the operand type
+    for (int e = tid; e < BM * BK; e += 256) {
+      int i = e / BK, kk = e % BK;
+      int64_t row = m0 + i;
+      int j = k0 + kk;
+      TIn v = 0;
+      if (row < M && j < d) {
+        v = point_value<TIn>(g.a, row, d, j);
+        if (mu) v = v - mu[j];
+      }
+      if constexpr (sizeof(TOp) == 8)
+        As[i * LDA + kk] = v;
+      else
+        As[i * LDA + kk] = to_op<TOp>((float)v);
+    }
+    // B tile: rows n of P_k (Bs[n][j] = P_k[n0+n][k0+j]) so Y_n = sum_j P[n][j] delta_j
+    for (int e = tid; e < BN * BK; e += 256) {
+      int n = e / BK, kk = e % BK;
+      int nn = n0 + n, j = k0 + kk;
+      TOp v;
+      if (nn < d && j < d)
+        v = Pk[(size_t)nn * d + j];
+      else
+        v = TOp(0);
+      Bs[n * LDA + kk] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += MF::KPI) {
+      const int kl = kk + MF::KPL * (lane >> 4);
+      const TOp *af[TM];
+      const TOp *bfp[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[i] = &As[(wm * WM + i * 16 + (lane & 15)) * LDA + kl];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bfp[j] = &Bs[(wn * WN + j * 16 + (lane & 15)) * LDA + kl];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(af[i], bfp[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+
+  // Epilogue: store Y, accumulate delta * Y per row over this tile's columns.
+  const int lr = lane >> 4, lc = lane & 15;
+  TAcc qrow[TM][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) qrow[i][v] = 0;
+  TAcc *Y = (TAcc *)g.Y;
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int il = wm * WM + i * 16 + MF::row(lr, v);
+      const int64_t row = m0 + il;
+      if (row >= M) continue;
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = n0 + wn * WN + j * 16 + lc;
+        if (n >= d) continue;
+        TAcc yv = acc[i][j][v];
+        if (Y) Y[row * g.ldy + (int64_t)k * d + n] = yv;
+        TIn x = point_value<TIn>(g.a, row, d, n);
+        TAcc dl = (TAcc)(mu ? x - mu[n] : x);
+        qrow[i][v] += dl * yv;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      TAcc t = qrow[i][v];
+      t += __shfl_xor(t, 1, 64);
+      t += __shfl_xor(t, 2, 64);
+      t += __shfl_xor(t, 4, 64);
+      t += __shfl_xor(t, 8, 64);
+      qrow[i][v] = t;
+    }
+  if (lc == 0) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) qs[wn][wm * WM + i * 16 + MF::row(lr, v)] = qrow[i][v];
+  }
+  __syncthreads();
+  if (g.qpart) {
+    TAcc *qp = (TAcc *)g.qpart;
+    for (int i = tid; i < BM; i += 256) {
+      int64_t row = m0 + i;
+      if (row < M) qp[(row * g.K + k) * g.ntn + (blockIdx.y % g.ntn)] = qs[0][i] + qs[1][i];
+    }
+  }
+}
+
+int quad_gemm_ntn(int dtype, int d, TileCfg t) { return (int)ceil_div(d, t.bn); }
+
+template <typename TIn, typename TOp, int BM, int BN, int BK>
+static int launch_t(const GemmParams &p, hipStream_t s) {
+  dim3 grid((unsigned)ceil_div(p.M, BM), (unsigned)(p.K * p.ntn));
+  if (grid.x == 0 || grid.y == 0) return SB_OK;
+  hipLaunchKernelGGL((quad_gemm_kernel<TIn, TOp, BM, BN, BK>), grid, dim3(256), 0, s, p);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+int launch_quad_gemm(int dtype, const Model &m, const ASrc &a, int64_t M, const int32_t *count,
+                     QuadOut &o, TileCfg t, hipStream_t s) {
+  GemmParams p;
+  p.a = a;
+  p.M = M;
+  p.count = count;
+  p.d = m.d;
+  p.K = m.K;
+  if (t.bn != 64 && t.bn != 128) t.bn = 128;
+  if (t.bm != 64 && t.bm != 128) t.bm = 128;
+  o.ntn = (int)ceil_div(m.d, t.bn);
+  p.ntn = o.ntn;
+  p.Y = o.Y;
+  p.ldy = o.ldy;
+  p.qpart = o.qpart;
+  if (dtype == DT_F64) {
+    p.mu = m.mu64;
+    p.P = m.P64;
+    if (t.bm == 64 && t.bn == 64) return launch_t<double, double, 64, 64, 16>(p, s);
+    if (t.bm == 128 && t.bn == 64) return launch_t<double, double, 128, 64, 16>(p, s);
+    if (t.bm == 64 && t.bn == 128) return launch_t<double, double, 64, 128, 16>(p, s);
+    return launch_t<double, double, 128, 128, 16>(p, s);
+  }
+  p.mu = m.mu32;
+  p.P = m.Plp;
+  if (!p.P || !p.mu) {
+    set_error("low-precision model copies missing");
+    return SB_E_INVAL;
+  }
+  if (dtype == DT_F32) {
+    if (t.bm == 64 && t.bn == 64) return launch_t<float, float, 64, 64, 16>(p, s);
+    if (t.bm == 128 && t.bn == 64) return launch_t<float, float, 128, 64, 16>(p, s);
+    if (t.bm == 64 && t.bn == 128) return launch_t<float, float, 64, 128, 16>(p, s);
+    return launch_t<float, float, 128, 128, 16>(p, s);
+  }
+  if (t.bm == 64 && t.bn == 64) return launch_t<float, bf16_t, 64, 64, 32>(p, s);
+  if (t.bm == 128 && t.bn == 64) return launch_t<float, bf16_t, 128, 64, 32>(p, s);
+  if (t.bm == 64 && t.bn == 128) return launch_t<float, bf16_t, 64, 128, 32>(p, s);
+  return launch_t<float, bf16_t, 128, 128, 32>(p, s);
+}
+
+// ------------------------------------------------------------------ finish
+
+constexpr int kMaxK = 16;
+
+// One wave per row: q_k from the tile partials, the family's l, and (if
+// requested) the gradient -sum_k r_k Y_k (mixture) or -((nu+d)/(nu+q)) Y.
+template <typename T>
+__global__ __launch_bounds__(256) void finish_kernel(Model m, FinishArgs f) {
+  const int64_t M = f.count ? (int64_t)(*f.count) : f.M;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= M) return;
+  const int d = m.d, K = m.K;
+  const T *qp = (const T *)f.qpart + (size_t)row * K * f.ntn;
+  const T *Y = (const T *)f.Y + (size_t)row * f.ldy;
+  const int64_t orow = f.outmap ? (int64_t)f.outmap[row] : row;
+  T *gout = f.grad ? (T *)f.grad + (size_t)orow * f.ldg : nullptr;
+  if (m.family == SB_FAMILY_STUDENT_T) {
+    T q = 0;
+    for (int t = 0; t < f.ntn; ++t) q += qp[t];
+    const T nd = (T)m.nu + (T)d;
+    T l = (T)(m.c - f.shift) + (T)m.beta[0] - (T)0.5 * nd * log1p(q / (T)m.nu);
+    if (lane == 0) {
+      ((T *)f.logl)[orow] = l;
+      if (f.aux) ((T *)f.aux)[row * K] = q;
+    }
+    if (gout) {
+      const T sc = nd / ((T)m.nu + q);
+      for (int n = lane; n < d; n += 64) gout[n] = -sc * Y[n];
+    }
+    return;
+  }
+  T a[kMaxK];
+  T mx = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) {
+    if (k < K) {
+      T q = 0;
+      for (int t = 0; t < f.ntn; ++t) q += qp[k * f.ntn + t];
+      a[k] = (T)m.beta[k] - (T)0.5 * q;
+      mx = fmax(mx, a[k]);
+    }
+  }
+  T lse;
+  if (K == 1) {
+    lse = a[0];
+  } else {
+    T ssum = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+      if (k < K) ssum += exp(a[k] - mx);
+    lse = mx + log(ssum);
+  }
+  if (lane == 0) ((T *)f.logl)[orow] = (T)(m.c - f.shift) + lse;
+  T r[kMaxK];
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) r[k] = (k < K) ? (K == 1 ? (T)1 : exp(a[k] - lse)) : (T)0;
+  if (f.aux && lane < K) {
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+      if (k == lane) ((T *)f.aux)[row * K + k] = r[k];
+  }
+  if (gout) {
+    for (int n = lane; n < d; n += 64) {
+      T s = 0;
+#pragma unroll
+      for (int k = 0; k < kMaxK; ++k)
+        if (k < K) s += r[k] * Y[(size_t)k * d + n];
+      gout[n] = -s;
+    }
+  }
+}
+
+int launch_finish(int dtype, const Model &m, const FinishArgs &f, hipStream_t s) {
+  if (m.K > kMaxK) {
+    set_error("K=%d exceeds the supported %d components", m.K, kMaxK);
+    return SB_E_UNSUPPORTED;
+  }
+  dim3 grid((unsigned)ceil_div(f.M, 4));
+  if (grid.x == 0) return SB_OK;
+  if (dtype == DT_F64)
+    hipLaunchKernelGGL(finish_kernel<double>, grid, dim3(256), 0, s, m, f);
+  else
+    hipLaunchKernelGGL(finish_kernel<float>, grid, dim3(256), 0, s, m, f);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// -------------------------------------------------------------------- HVP
+
+// HV = nabla^2 l v.  Mixture: sum_k r_k (Y_k (Y_k . v) - Z_k) - g (g . v)
+// with Y_k = P_k delta_k, Z_k = P_k v, g = grad l.  Student-t:
+// -((nu+d)/(nu+q)) Z + (2 (nu+d)/(nu+q)^2) Y (Y . v).  One wave per row.
+__global__ __launch_bounds__(256) void hvp_finish_kernel(Model m, HvpArgs h) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= h.M) return;
+  const int d = m.d, K = m.K;
+  const double *qp = (const double *)h.qpart + (size_t)row * K * h.ntn;
+  const double *Y = h.Y + (size_t)row * h.ldy;
+  const double *Z = h.Z + (size_t)row * h.ldy;
+  const double *v = h.V + (size_t)row * d;
+  double *out = h.HV + (size_t)row * d;
+  if (m.family == SB_FAMILY_STUDENT_T) {
+    double q = 0;
+    for (int t = 0; t < h.ntn; ++t) q += qp[t];
+    double nd = m.nu + d, den = m.nu + q;
+    double uv = 0;
+    for (int n = lane; n < d; n += 64) uv += Y[n] * v[n];
+    uv = wave_sum(uv);
+    for (int n = lane; n < d; n += 64)
+      out[n] = -(nd / den) * Z[n] + (2.0 * nd / (den * den)) * Y[n] * uv;
+    return;
+  }
+  double a[kMaxK], r[kMaxK], uv[kMaxK];
+  double mx = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) {
+    if (k < K) {
+      double q = 0;
+      for (int t = 0; t < h.ntn; ++t) q += qp[k * h.ntn + t];
+      a[k] = m.beta[k] - 0.5 * q;
+      mx = fmax(mx, a[k]);
+    }
+  }
+  double ssum = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k)
+    if (k < K) ssum += exp(a[k] - mx);
+  double lse = mx + log(ssum);
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) r[k] = (k < K) ? (K == 1 ? 1.0 : exp(a[k] - lse)) : 0.0;
+  // g . v and Y_k . v
+  double gv = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) uv[k] = 0;
+  for (int n = lane; n < d; n += 64) {
+    double gn = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+      if (k < K) {
+        gn += r[k] * Y[(size_t)k * d + n];
+        uv[k] += Y[(size_t)k * d + n] * v[n];
+      }
+    gv += -gn * v[n];
+  }
+  gv = wave_sum(gv);
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k)
+    if (k < K) uv[k] = wave_sum(uv[k]);
+  for (int n = lane; n < d; n += 64) {
+    double gn = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+      if (k < K) gn += r[k] * Y[(size_t)k * d + n];
+    gn = -gn;
+    double hv = -gn * gv;
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+      if (k < K) hv += r[k] * (Y[(size_t)k * d + n] * uv[k] - Z[(size_t)k * d + n]);
+    out[n] = hv;
+  }
+}
+
+int launch_hvp_finish(const Model &m, const HvpArgs &h, hipStream_t s) {
+  if (m.K > kMaxK) return SB_E_UNSUPPORTED;
+  dim3 grid((unsigned)ceil_div(h.M, 4));
+  if (grid.x == 0) return SB_OK;
+  hipLaunchKernelGGL(hvp_finish_kernel, grid, dim3(256), 0, s, m, h);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// --------------------------------------------------------- Hessian assembly
+
+// H = -nabla^2 l = sum_k r_k (P_k - u_k u_k^T) + g g^T (mixture) or
+// ((nu+d)/(nu+q)) P - (2 (nu+d)/(nu+q)^2) u u^T (Student-t), u_k = Y_k;
+// symmetrised as (H + H^T)/2.  This is the HVP epilogue with V = I.
+__device__ inline double hess_entry(const Model &m, int c, int i, int j, const double *Y,
+                                    int64_t ldy, const double *aux, const double *grad) {
+  const int d = m.d, K = m.K;
+  const double *y = Y + (size_t)c * ldy;
+  if (m.family == SB_FAMILY_STUDENT_T) {
+    double q = aux[(size_t)c * K];
+    double nd = m.nu + d, den = m.nu + q;
+    return (nd / den) * m.P64[(size_t)i * d + j] - (2.0 * nd / (den * den)) * y[i] * y[j];
+  }
+  const double *g = grad + (size_t)c * d;
+  double s = g[i] * g[j];
+  for (int k = 0; k < K; ++k) {
+    double rk = aux[(size_t)c * K + k];
+    const double *u = y + (size_t)k * d;
+    s += rk * (m.P64[(size_t)k * d * d + (size_t)i * d + j] - u[i] * u[j]);
+  }
+  return s;
+}
+
+__global__ __launch_bounds__(256) void hessian_kernel(Model m, int C, const double *Y, int64_t ldy,
+                                                      const double *aux, const double *grad,
+                                                      double *H) {
+  const int c = blockIdx.z;
+  const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
+  const int j = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int d = m.d;
+  if (c >= C || i >= d || j >= d) return;
+  double hij = hess_entry(m, c, i, j, Y, ldy, aux, grad);
+  double hji = hess_entry(m, c, j, i, Y, ldy, aux, grad);
+  H[(size_t)c * d * d + (size_t)i * d + j] = 0.5 * (hij + hji);
+}
+
+int launch_hessian_assemble(const Model &m, int C, const double *Y, int64_t ldy,
+                            const double *aux, const double *grad, double *H, hipStream_t s) {
+  if (C <= 0) return SB_OK;
+  dim3 grid((unsigned)ceil_div(m.d, 16), (unsigned)ceil_div(m.d, 16), (unsigned)C);
+  hipLaunchKernelGGL(hessian_kernel, grid, dim3(256), 0, s, m, C, Y, ldy, aux, grad, H);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// ---------------------------------------------------------------- prep
+
+__global__ void convert_model_kernel(const double *P, const double *mu, int64_t nP, int64_t nmu,
+                                     float *P32, bf16_t *Pbf, float *mu32) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = i; e < nP; e += stride) {
+    float v = (float)P[e];
+    if (P32) P32[e] = v;
+    if (Pbf) Pbf[e] = f32_to_bf16(v);
+  }
+  for (int64_t e = i; e < nmu; e += stride)
+    if (mu32) mu32[e] = (float)mu[e];
+}
+
+int launch_convert_model(const Model &m, float *P32, bf16_t *Pbf, float *mu32, hipStream_t s) {
+  int64_t nP = (int64_t)m.K * m.d * m.d, nmu = (int64_t)m.K * m.d;
+  unsigned blocks = (unsigned)std::min<int64_t>(4096, ceil_div(nP, 256));
+  hipLaunchKernelGGL(convert_model_kernel, dim3(blocks), dim3(256), 0, s, m.P64, m.mu64, nP, nmu,
+                     P32, Pbf, mu32);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// Per-component max |P_k| into mx[k], then bad[0] = 1 if any
+// |P_ij - P_ji| > 1e-12 * mx[k].
+__global__ void maxabs_kernel(const double *P, int d, double *mx) {
+  const int k = blockIdx.x;
+  const double *Pk = P + (size_t)k * d * d;
+  __shared__ double red[4];
+  double v = 0;
+  for (int64_t e = threadIdx.x; e < (int64_t)d * d; e += 256) v = fmax(v, fabs(Pk[e]));
+  v = block_max<256>(v, red);
+  if (threadIdx.x == 0) mx[k] = v;
+}
+__global__ void symmetry_kernel(const double *P, int d, const double *mx, int32_t *bad) {
+  const int k = blockIdx.y;
+  const double *Pk = P + (size_t)k * d * d;
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)d * d) return;
+  int i = (int)(e / d), j = (int)(e % d);
+  if (j <= i) return;
+  double a = Pk[(size_t)i * d + j], b = Pk[(size_t)j * d + i];
+  if (!(fabs(a - b) <= 1e-12 * mx[k])) bad[0] = 1;
+}
+
+int launch_symmetry_check(const double *P, int K, int d, double *mx, int32_t *bad,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(maxabs_kernel, dim3(K), dim3(256), 0, s, P, d, mx);
+  SB_LAUNCH_CHECK();
+  dim3 grid((unsigned)ceil_div((int64_t)d * d, 256), (unsigned)K);
+  hipLaunchKernelGGL(symmetry_kernel, grid, dim3(256), 0, s, P, d, mx, bad);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// beta_k from log w_k and log det P_k (see sb.h for the closed forms).
+__global__ void beta_kernel(Model m, const double *log_w, const double *logdetP, double *beta) {
+  const int k = threadIdx.x;
+  if (k >= m.K) return;
+  const double d = m.d;
+  double b = 0.0;
+  if (m.family == SB_FAMILY_GAUSS_MIX) {
+    b = log_w ? log_w[k] : 0.0;
+    if (m.norm == SB_NORM_DENSITY) b += 0.5 * logdetP[k] - 0.5 * d * kLog2Pi;
+  } else if (m.norm == SB_NORM_DENSITY) {
+    b = lgamma(0.5 * (m.nu + d)) - lgamma(0.5 * m.nu) - 0.5 * d * log(m.nu * M_PI) +
+        0.5 * logdetP[k];
+  }
+  beta[k] = b;
+}
+
+int launch_beta(const Model &m, const double *log_w, const double *logdetP, double *beta,
+                hipStream_t s) {
+  hipLaunchKernelGGL(beta_kernel, dim3(1), dim3(64 * (int)ceil_div(m.K, 64)), 0, s, m, log_w,
+                     logdetP, beta);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// ---------------------------------------------------------------- casts
+
+__global__ void cast_d2f(int64_t n, const double *a, float *b) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) b[i] = (float)a[i];
+}
+__global__ void cast_f2d(int64_t n, const float *a, double *b) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) b[i] = (double)a[i];
+}
+__global__ void fill_i32(int64_t n, int32_t v, int32_t *p) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+int launch_cast_f64_f32(int64_t n, const double *a, float *b, hipStream_t s) {
+  if (n <= 0) return SB_OK;
+  hipLaunchKernelGGL(cast_d2f, dim3((unsigned)std::min<int64_t>(8192, ceil_div(n, 256))),
+                     dim3(256), 0, s, n, a, b);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+int launch_cast_f32_f64(int64_t n, const float *a, double *b, hipStream_t s) {
+  if (n <= 0) return SB_OK;
+  hipLaunchKernelGGL(cast_f2d, dim3((unsigned)std::min<int64_t>(8192, ceil_div(n, 256))),
+                     dim3(256), 0, s, n, a, b);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+int launch_fill_i32(int64_t n, int32_t v, int32_t *p, hipStream_t s) {
+  if (n <= 0) return SB_OK;
+  hipLaunchKernelGGL(fill_i32, dim3((unsigned)std::min<int64_t>(8192, ceil_div(n, 256))),
+                     dim3(256), 0, s, n, v, p);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+}  // namespace sb

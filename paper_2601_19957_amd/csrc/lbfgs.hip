@@ -1,0 +1,632 @@
+// Batched L-BFGS on f = -l, one workgroup per start (appendix "L-BFGS
+// Optimization"; batched over samples as the paper describes).
+//
+// Each start is a small state machine advanced once per batch step:
+//   INIT      the start point has been evaluated: choose the first direction.
+//   TRIAL     the trial x + alpha p has been evaluated: Armijo test
+//             f(x_t) <= f(x) + 1e-4 alpha g^T p.  Accept -> store (s, y) if
+//             s^T y > 1e-10 |s| |y|, compute the next direction by the
+//             two-loop recursion; reject -> halve alpha (at most 40 times;
+//             then clear the history and retry steepest descent once, else
+//             the start is stalled).
+// Starts stop when ||grad l||_inf <= tol or after max_iter accepted steps.
+// The first direction, and any direction after a history reset or a
+// non-descent two-loop result, is -g / max(1, ||g||_inf).
+//
+// Points and gradients are double-buffered per start (slots 0/1, `cur` names
+// the accepted point), so accepting a trial swaps a slot index instead of
+// copying.  The history S, Y [B][m][d] is a ring in memory; the kernel loads
+// it into registers in logical order (oldest first) and runs both loops of
+// the recursion with workgroup reductions for the dot products.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace sb {
+
+enum { PH_INIT = 0, PH_TRIAL = 1 };
+enum { ST_ACTIVE = 0, ST_CONVERGED = 1, ST_STALLED = 2, ST_MAXITER = 3, ST_DEAD = 4 };
+
+template <typename T>
+struct LbArgs {
+  int64_t B;
+  int d, m, max_iter;
+  T tol;
+  T *X, *G, *F, *Pd, *S, *Yh, *rho, *yy, *alpha, *gtp;
+  int32_t *cur, *head, *cnt, *iters, *ls, *status, *phase, *rowid, *active;
+};
+
+// Two-loop recursion on register-resident history (logical order, oldest
+// first).  q <- g; backward: alpha_j = rho_j s_j^T q, q -= alpha_j y_j;
+// r = gamma q, gamma = s^T y / y^T y of the newest pair; forward:
+// beta = rho_j y_j^T r, r += (alpha_j - beta) s_j; returns p = -r.
+template <typename T, int TPB, int EPT>
+__device__ inline void two_loop(const T (&Sr)[kMaxHist][EPT], const T (&Yr)[kMaxHist][EPT],
+                                const T (&rh)[kMaxHist], T gamma, int cnt, const T (&g)[EPT],
+                                T (&p)[EPT], T *red) {
+  T q[EPT], al[kMaxHist];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) q[e] = g[e];
+#pragma unroll
+  for (int j = kMaxHist - 1; j >= 0; --j) {
+    if (j < cnt) {
+      T dd = 0;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) dd += Sr[j][e] * q[e];
+      dd = block_sum<TPB>(dd, red);
+      al[j] = rh[j] * dd;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) q[e] -= al[j] * Yr[j][e];
+    } else {
+      al[j] = 0;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) q[e] *= gamma;
+#pragma unroll
+  for (int j = 0; j < kMaxHist; ++j) {
+    if (j < cnt) {
+      T bb = 0;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) bb += Yr[j][e] * q[e];
+      bb = rh[j] * block_sum<TPB>(bb, red);
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) q[e] += (al[j] - bb) * Sr[j][e];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) p[e] = -q[e];
+}
+
+template <typename T, int TPB, int EPT>
+__global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
+  const int64_t s = blockIdx.x;
+  const int tid = threadIdx.x;
+  __shared__ T red[4 * (TPB / 64)];
+  if (a.status[s] != ST_ACTIVE) {
+    if (tid == 0) a.active[s] = 0;
+    return;
+  }
+  const int d = a.d, m = a.m;
+  const int64_t B = a.B;
+  int cur = a.cur[s];
+  const int phase = a.phase[s];
+  int cnt = a.cnt[s], head = a.head[s], it = a.iters[s];
+  const T lcur = a.F[(size_t)cur * B + s];
+
+  // ---- decide what this step does from the scalars alone
+  enum { M_INIT, M_ACCEPT, M_BACKTRACK, M_RESET, M_STALL };
+  int mode = M_INIT;
+  T alpha = 1;
+  int lsn = 0;
+  if (phase == PH_TRIAL) {
+    const int tr = 1 - cur;
+    const T lt = a.F[(size_t)tr * B + s];
+    alpha = a.alpha[s];
+    const T gtp_old = a.gtp[s];
+    const T fc = -lcur, ft = -lt;
+    if (isfinite(ft) && ft <= fc + (T)1e-4 * alpha * gtp_old) {
+      mode = M_ACCEPT;
+    } else {
+      lsn = a.ls[s] + 1;
+      alpha *= (T)0.5;
+      if (lsn <= 40)
+        mode = M_BACKTRACK;
+      else
+        mode = (cnt > 0) ? M_RESET : M_STALL;
+    }
+  }
+  if (mode == M_STALL) {
+    if (tid == 0) {
+      a.status[s] = ST_STALLED;
+      a.active[s] = 0;
+    }
+    return;
+  }
+  if (mode == M_BACKTRACK) {
+    const int tr = 1 - cur;
+    const T *xc = a.X + ((size_t)cur * B + s) * d;
+    T *xt = a.X + ((size_t)tr * B + s) * d;
+    const T *pd = a.Pd + (size_t)s * d;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int i = e * TPB + tid;
+      if (i < d) xt[i] = xc[i] + alpha * pd[i];
+    }
+    if (tid == 0) {
+      a.alpha[s] = alpha;
+      a.ls[s] = lsn;
+      a.active[s] = 1;
+      a.rowid[s] = (int32_t)((size_t)tr * B + s);
+    }
+    return;
+  }
+
+  // ---- load the point whose direction we now compute (and, on accept, the old one)
+  T x[EPT], gl[EPT], sv[EPT], yv[EPT];
+  const int newcur = (mode == M_ACCEPT) ? 1 - cur : cur;
+  {
+    const T *xn = a.X + ((size_t)newcur * B + s) * d;
+    const T *gn = a.G + ((size_t)newcur * B + s) * d;
+    const T *xo = a.X + ((size_t)cur * B + s) * d;
+    const T *go = a.G + ((size_t)cur * B + s) * d;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int i = e * TPB + tid;
+      x[e] = (i < d) ? xn[i] : (T)0;
+      gl[e] = (i < d) ? gn[i] : (T)0;
+      if (mode == M_ACCEPT) {
+        sv[e] = (i < d) ? x[e] - xo[i] : (T)0;
+        yv[e] = (i < d) ? go[i] - gl[e] : (T)0;  // grad f(x_t) - grad f(x), grad f = -grad l
+      }
+    }
+  }
+  if (mode == M_RESET) {
+    cnt = 0;
+    head = 0;
+  }
+  // history in logical order (loads issued before the reductions below)
+  T Sr[kMaxHist][EPT], Yr[kMaxHist][EPT], rh[kMaxHist], yyr[kMaxHist];
+#pragma unroll
+  for (int j = 0; j < kMaxHist; ++j) {
+    rh[j] = 0;
+    yyr[j] = 0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) Sr[j][e] = Yr[j][e] = 0;
+    if (mode == M_ACCEPT && j < cnt) {
+      const int ph = (head - cnt + j + 2 * m) % m;
+      const T *Sp = a.S + ((size_t)s * m + ph) * d;
+      const T *Yp = a.Yh + ((size_t)s * m + ph) * d;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int i = e * TPB + tid;
+        if (i < d) {
+          Sr[j][e] = Sp[i];
+          Yr[j][e] = Yp[i];
+        }
+      }
+      rh[j] = a.rho[(size_t)s * m + ph];
+      yyr[j] = a.yy[(size_t)s * m + ph];
+    }
+  }
+  if (mode == M_ACCEPT) {
+    T v3[3] = {0, 0, 0};
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      v3[0] += sv[e] * yv[e];
+      v3[1] += sv[e] * sv[e];
+      v3[2] += yv[e] * yv[e];
+    }
+    block_sum_n<TPB, 3>(v3, red);
+    const T sy = v3[0], ss = v3[1], yy = v3[2];
+    cur = newcur;
+    ++it;
+    if (sy > (T)1e-10 * sqrt(ss) * sqrt(yy)) {
+      // store the pair in the ring and append it to the logical history
+      T *Sp = a.S + ((size_t)s * m + head) * d;
+      T *Yp = a.Yh + ((size_t)s * m + head) * d;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int i = e * TPB + tid;
+        if (i < d) {
+          Sp[i] = sv[e];
+          Yp[i] = yv[e];
+        }
+      }
+      if (tid == 0) {
+        a.rho[(size_t)s * m + head] = (T)1 / sy;
+        a.yy[(size_t)s * m + head] = yy;
+      }
+      const bool full = (cnt == m);
+      if (full) {
+#pragma unroll
+        for (int j = 0; j < kMaxHist - 1; ++j) {
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            Sr[j][e] = Sr[j + 1][e];
+            Yr[j][e] = Yr[j + 1][e];
+          }
+          rh[j] = rh[j + 1];
+          yyr[j] = yyr[j + 1];
+        }
+      }
+      const int pos = full ? m - 1 : cnt;
+#pragma unroll
+      for (int j = 0; j < kMaxHist; ++j) {
+        if (j == pos) {
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            Sr[j][e] = sv[e];
+            Yr[j][e] = yv[e];
+          }
+          rh[j] = (T)1 / sy;
+          yyr[j] = yy;
+        }
+      }
+      head = (head + 1) % m;
+      cnt = full ? m : cnt + 1;
+    }
+  }
+
+  // ---- convergence tests at the current point
+  // ||grad l||_inf; a non-finite entry makes it NaN (no convergence on NaN)
+  T gn = 0, bad = 0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    gn = fmax(gn, fabs(gl[e]));
+    if (!isfinite(gl[e])) bad = 1;
+  }
+  gn = block_max<TPB>(gn, red);
+  bad = block_max<TPB>(bad, red);
+  if (bad != (T)0) gn = (T)NAN;
+  int newst = ST_ACTIVE;
+  if (mode == M_INIT && !(isfinite(lcur) && isfinite(gn)))
+    newst = ST_DEAD;
+  else if (gn <= a.tol)
+    newst = ST_CONVERGED;
+  else if (it >= a.max_iter)
+    newst = ST_MAXITER;
+  if (newst != ST_ACTIVE) {
+    if (tid == 0) {
+      a.status[s] = newst;
+      a.active[s] = 0;
+      a.cur[s] = cur;
+      a.cnt[s] = cnt;
+      a.head[s] = head;
+      a.iters[s] = it;
+    }
+    return;
+  }
+
+  // ---- next direction
+  T g[EPT], p[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) g[e] = -gl[e];
+  T gtp = 0;
+  bool sd = (cnt == 0);
+  if (!sd) {
+    // gamma = s^T y / y^T y of the newest pair (logical index cnt - 1)
+    T rnew = 0, yynew = 1;
+#pragma unroll
+    for (int j = 0; j < kMaxHist; ++j)
+      if (j == cnt - 1) {
+        rnew = rh[j];
+        yynew = yyr[j];
+      }
+    const T gamma = ((T)1 / rnew) / yynew;
+    two_loop<T, TPB, EPT>(Sr, Yr, rh, gamma, cnt, g, p, red);
+    T t = 0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) t += g[e] * p[e];
+    gtp = block_sum<TPB>(t, red);
+    if (!(gtp < (T)0)) {
+      sd = true;
+      cnt = 0;
+      head = 0;
+    }
+  }
+  if (sd) {
+    const T sc = (T)1 / (gn > (T)1 ? gn : (T)1);
+    T t = 0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      p[e] = -g[e] * sc;
+      t += g[e] * p[e];
+    }
+    gtp = block_sum<TPB>(t, red);
+  }
+  const int tr = 1 - cur;
+  T *xt = a.X + ((size_t)tr * B + s) * d;
+  T *pd = a.Pd + (size_t)s * d;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int i = e * TPB + tid;
+    if (i < d) {
+      pd[i] = p[e];
+      xt[i] = x[e] + p[e];
+    }
+  }
+  if (tid == 0) {
+    a.alpha[s] = (T)1;
+    a.gtp[s] = gtp;
+    a.ls[s] = 0;
+    a.cur[s] = cur;
+    a.cnt[s] = cnt;
+    a.head[s] = head;
+    a.iters[s] = it;
+    a.phase[s] = PH_TRIAL;
+    a.active[s] = 1;
+    a.rowid[s] = (int32_t)((size_t)tr * B + s);
+  }
+}
+
+// Two-loop direction only, for B independent histories given in logical
+// order (used to check the recursion in isolation).
+template <typename T, int TPB, int EPT>
+__global__ __launch_bounds__(TPB) void two_loop_kernel(int d, int m, const int32_t *cntv,
+                                                       const T *S, const T *Y, const T *G, T *P) {
+  const int64_t b = blockIdx.x;
+  const int tid = threadIdx.x;
+  __shared__ T red[4 * (TPB / 64)];
+  const int cnt = min(max(cntv[b], 0), m);  // never read past this start's m slots
+  T Sr[kMaxHist][EPT], Yr[kMaxHist][EPT], rh[kMaxHist], g[EPT], p[EPT];
+  T gamma = 1;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int i = e * TPB + tid;
+    g[e] = (i < d) ? G[(size_t)b * d + i] : (T)0;
+  }
+#pragma unroll
+  for (int j = 0; j < kMaxHist; ++j) {
+    rh[j] = 0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int i = e * TPB + tid;
+      const bool ok = (j < cnt) && (i < d);
+      Sr[j][e] = ok ? S[((size_t)b * m + j) * d + i] : (T)0;
+      Yr[j][e] = ok ? Y[((size_t)b * m + j) * d + i] : (T)0;
+    }
+    if (j < cnt) {
+      T v2[2] = {0, 0};
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        v2[0] += Sr[j][e] * Yr[j][e];
+        v2[1] += Yr[j][e] * Yr[j][e];
+      }
+      block_sum_n<TPB, 2>(v2, red);
+      rh[j] = (T)1 / v2[0];
+      if (j == cnt - 1) gamma = v2[0] / v2[1];
+    }
+  }
+  two_loop<T, TPB, EPT>(Sr, Yr, rh, gamma, cnt, g, p, red);
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int i = e * TPB + tid;
+    if (i < d) P[(size_t)b * d + i] = p[e];
+  }
+}
+
+// ------------------------------------------------------------- dispatch
+
+#define SB_LB_CASES(KERNEL, T, ...)                                                  \
+  if (d <= 64) {                                                                      \
+    hipLaunchKernelGGL((KERNEL<T, 64, 1>), dim3((unsigned)B), dim3(64), 0, s, __VA_ARGS__);   \
+  } else if (d <= 128) {                                                              \
+    hipLaunchKernelGGL((KERNEL<T, 64, 2>), dim3((unsigned)B), dim3(64), 0, s, __VA_ARGS__);   \
+  } else if (d <= 256) {                                                              \
+    hipLaunchKernelGGL((KERNEL<T, 64, 4>), dim3((unsigned)B), dim3(64), 0, s, __VA_ARGS__);   \
+  } else if (d <= 512) {                                                              \
+    hipLaunchKernelGGL((KERNEL<T, 128, 4>), dim3((unsigned)B), dim3(128), 0, s, __VA_ARGS__); \
+  } else if (d <= 1024) {                                                             \
+    hipLaunchKernelGGL((KERNEL<T, 256, 4>), dim3((unsigned)B), dim3(256), 0, s, __VA_ARGS__); \
+  } else if (d <= 2048) {                                                             \
+    hipLaunchKernelGGL((KERNEL<T, 512, 4>), dim3((unsigned)B), dim3(512), 0, s, __VA_ARGS__); \
+  } else {                                                                            \
+    hipLaunchKernelGGL((KERNEL<T, 1024, 4>), dim3((unsigned)B), dim3(1024), 0, s, __VA_ARGS__); \
+  }
+
+static int check_d(int d, int m) {
+  if (d < 1 || d > 4096) {
+    set_error("L-BFGS supports 1 <= d <= 4096 (got %d)", d);
+    return SB_E_UNSUPPORTED;
+  }
+  if (m < 1 || m > kMaxHist) {
+    set_error("L-BFGS memory m must be in [1, %d] (got %d)", kMaxHist, m);
+    return SB_E_INVAL;
+  }
+  return SB_OK;
+}
+
+template <typename T>
+static LbArgs<T> make_args(const LbfgsBuffers &b, int max_iter, double tol) {
+  LbArgs<T> a;
+  a.B = b.B;
+  a.d = b.d;
+  a.m = b.m;
+  a.max_iter = max_iter;
+  a.tol = (T)tol;
+  a.X = (T *)b.X;
+  a.G = (T *)b.G;
+  a.F = (T *)b.F;
+  a.Pd = (T *)b.Pd;
+  a.S = (T *)b.S;
+  a.Yh = (T *)b.Yh;
+  a.rho = (T *)b.rho;
+  a.yy = (T *)b.yy;
+  a.alpha = (T *)b.alpha;
+  a.gtp = (T *)b.gtp;
+  a.cur = b.cur;
+  a.head = b.head;
+  a.cnt = b.cnt;
+  a.iters = b.iters;
+  a.ls = b.ls;
+  a.status = b.status;
+  a.phase = b.phase;
+  a.rowid = b.rowid;
+  a.active = b.active;
+  return a;
+}
+
+int launch_lbfgs_step(const LbfgsBuffers &b, int max_iter, double grad_tol, hipStream_t s) {
+  int st = check_d(b.d, b.m);
+  if (st) return st;
+  const int d = b.d;
+  const int64_t B = b.B;
+  if (B <= 0) return SB_OK;
+  if (b.dtype == DT_F64) {
+    LbArgs<double> a = make_args<double>(b, max_iter, grad_tol);
+    SB_LB_CASES(lbfgs_step_kernel, double, a);
+  } else {
+    LbArgs<float> a = make_args<float>(b, max_iter, grad_tol);
+    SB_LB_CASES(lbfgs_step_kernel, float, a);
+  }
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+int launch_two_loop(int64_t B, int d, int m, const int32_t *cnt, const void *S, const void *Y,
+                    const void *G, void *P, int dtype, hipStream_t s) {
+  int st = check_d(d, m);
+  if (st) return st;
+  if (B <= 0) return SB_OK;
+  if (dtype == DT_F64) {
+    SB_LB_CASES(two_loop_kernel, double, d, m, cnt, (const double *)S, (const double *)Y,
+                (const double *)G, (double *)P);
+  } else {
+    SB_LB_CASES(two_loop_kernel, float, d, m, cnt, (const float *)S, (const float *)Y,
+                (const float *)G, (float *)P);
+  }
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// ------------------------------------------------------------- state
+
+size_t lbfgs_state_bytes(int dtype, int64_t B, int d, int m) {
+  LbfgsBuffers b;
+  b.dtype = dtype;
+  b.B = B;
+  b.d = d;
+  b.m = m;
+  Arena ar(nullptr, 0);
+  lbfgs_carve(ar, b);
+  return ar.off;
+}
+
+int lbfgs_carve(Arena &ar, LbfgsBuffers &b) {
+  const size_t es = (b.dtype == DT_F64) ? 8 : 4;
+  const int64_t B = b.B, d = b.d, m = b.m;
+  auto take = [&](size_t n) -> void * { return (void *)ar.take<char>(n * es); };
+  b.X = take(2 * B * d);
+  b.G = take(2 * B * d);
+  b.F = take(2 * B);
+  b.Pd = take(B * d);
+  b.S = take(B * m * d);
+  b.Yh = take(B * m * d);
+  b.rho = take(B * m);
+  b.yy = take(B * m);
+  b.alpha = take(B);
+  b.gtp = take(B);
+  b.cur = ar.take<int32_t>(B);
+  b.head = ar.take<int32_t>(B);
+  b.cnt = ar.take<int32_t>(B);
+  b.iters = ar.take<int32_t>(B);
+  b.ls = ar.take<int32_t>(B);
+  b.status = ar.take<int32_t>(B);
+  b.phase = ar.take<int32_t>(B);
+  b.rowid = ar.take<int32_t>(B);
+  b.active = ar.take<int32_t>(B);
+  b.idx = ar.take<int32_t>(B);
+  b.count = ar.take<int32_t>(4);
+  b.evals = ar.take<int64_t>(2);
+  return ar.ok() ? SB_OK : SB_E_NOMEM;
+}
+
+template <typename T>
+__global__ void lbfgs_init_kernel(int64_t B, int d, const T *X0, T *X, int32_t *cur,
+                                  int32_t *head, int32_t *cnt, int32_t *iters, int32_t *ls,
+                                  int32_t *status, int32_t *phase, int32_t *count,
+                                  int64_t *evals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = B * d;
+  for (int64_t e = i; e < n; e += (int64_t)gridDim.x * blockDim.x) X[e] = X0[e];
+  for (int64_t e = i; e < B; e += (int64_t)gridDim.x * blockDim.x) {
+    cur[e] = 0;
+    head[e] = 0;
+    cnt[e] = 0;
+    iters[e] = 0;
+    ls[e] = 0;
+    status[e] = ST_ACTIVE;
+    phase[e] = PH_INIT;
+  }
+  if (i == 0) {
+    count[0] = (int32_t)B;
+    evals[0] = B;
+  }
+}
+
+int launch_lbfgs_init(const LbfgsBuffers &b, const void *X0, hipStream_t s) {
+  unsigned blocks = (unsigned)std::min<int64_t>(8192, ceil_div(b.B * b.d, 256));
+  if (b.dtype == DT_F64)
+    hipLaunchKernelGGL(lbfgs_init_kernel<double>, dim3(blocks), dim3(256), 0, s, b.B, b.d,
+                       (const double *)X0, (double *)b.X, b.cur, b.head, b.cnt, b.iters, b.ls,
+                       b.status, b.phase, b.count, b.evals);
+  else
+    hipLaunchKernelGGL(lbfgs_init_kernel<float>, dim3(blocks), dim3(256), 0, s, b.B, b.d,
+                       (const float *)X0, (float *)b.X, b.cur, b.head, b.cnt, b.iters, b.ls,
+                       b.status, b.phase, b.count, b.evals);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// Compaction of the active starts into idx (their trial row ids), in start
+// order; count[0] = number active, evals[0] += count.  One workgroup: each
+// thread owns a contiguous chunk, exclusive scan of the chunk counts in LDS.
+__global__ __launch_bounds__(1024) void compact_kernel(int64_t B, const int32_t *active,
+                                                       const int32_t *rowid, int32_t *idx,
+                                                       int32_t *count, int64_t *evals) {
+  __shared__ int32_t sc[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (B + 1023) / 1024;
+  const int64_t b0 = (int64_t)t * per, b1 = std::min<int64_t>(B, b0 + per);
+  int32_t c = 0;
+  for (int64_t i = b0; i < b1; ++i) c += active[i] ? 1 : 0;
+  sc[t] = c;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int32_t v = (t >= o) ? sc[t - o] : 0;
+    __syncthreads();
+    sc[t] += v;
+    __syncthreads();
+  }
+  int32_t off = sc[t] - c;
+  for (int64_t i = b0; i < b1; ++i)
+    if (active[i]) idx[off++] = rowid[i];
+  if (t == 1023) {
+    count[0] = sc[1023];
+    evals[0] += sc[1023];
+  }
+}
+
+int launch_compact(const LbfgsBuffers &b, hipStream_t s) {
+  hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, s, b.B, b.active, b.rowid, b.idx,
+                     b.count, b.evals);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+template <typename T>
+__global__ void lbfgs_gather_kernel(int64_t B, int d, const T *X, const T *G, const T *F,
+                                    const int32_t *cur, const int32_t *st, const int32_t *its,
+                                    T *Xo, T *lo, T *go, int32_t *sto, int32_t *ito) {
+  const int64_t s = blockIdx.x;
+  const int c = cur[s];
+  for (int i = threadIdx.x; i < d; i += blockDim.x) {
+    if (Xo) Xo[(size_t)s * d + i] = X[((size_t)c * B + s) * d + i];
+    if (go) go[(size_t)s * d + i] = G[((size_t)c * B + s) * d + i];
+  }
+  if (threadIdx.x == 0) {
+    if (lo) lo[s] = F[(size_t)c * B + s];
+    if (sto) sto[s] = st[s];
+    if (ito) ito[s] = its[s];
+  }
+}
+
+int launch_lbfgs_gather(const LbfgsBuffers &b, void *X, void *logl, void *grad, int32_t *status,
+                        int32_t *iters, hipStream_t s) {
+  if (b.B <= 0) return SB_OK;
+  if (b.dtype == DT_F64)
+    hipLaunchKernelGGL(lbfgs_gather_kernel<double>, dim3((unsigned)b.B), dim3(256), 0, s, b.B,
+                       b.d, (const double *)b.X, (const double *)b.G, (const double *)b.F, b.cur,
+                       b.status, b.iters, (double *)X, (double *)logl, (double *)grad, status,
+                       iters);
+  else
+    hipLaunchKernelGGL(lbfgs_gather_kernel<float>, dim3((unsigned)b.B), dim3(256), 0, s, b.B, b.d,
+                       (const float *)b.X, (const float *)b.G, (const float *)b.F, b.cur,
+                       b.status, b.iters, (float *)X, (float *)logl, (float *)grad, status,
+                       iters);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+}  // namespace sb

@@ -1,0 +1,283 @@
+// Batched FP64 Cholesky factorisation, log-determinant and solves.
+//
+// H = L L^T (the whitening factor of the paper's appendix "Coordinate
+// Whitening"); log det H = 2 sum_i log L_ii.  A failed pivot means H is not
+// positive definite, i.e. the candidate is not a maximum (saddle filter of
+// GreenDragon, generalised).  Blocked right-looking factorisation with 64-wide
+// panels: diagonal block in LDS, triangular solve of the panel below it,
+// symmetric rank-64 update of the trailing lower triangle.  One launch per
+// stage covers every matrix of the batch.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace sb {
+
+constexpr int NB = 64;
+
+// Factor the diagonal block [j0, j0+nb)^2 of every matrix in LDS.
+__global__ __launch_bounds__(256) void chol_diag_kernel(int n, int j0, double *L,
+                                                        int32_t *info) {
+  const int c = blockIdx.x;
+  if (info[c] != 0) return;
+  double *A = L + (size_t)c * n * n;
+  const int nb = min(NB, n - j0);
+  const int tid = threadIdx.x;
+  __shared__ double T[NB][NB + 1];
+  __shared__ int fail;
+  for (int e = tid; e < nb * nb; e += 256) {
+    int i = e / nb, k = e % nb;
+    T[i][k] = (k <= i) ? A[(size_t)(j0 + i) * n + j0 + k] : 0.0;
+  }
+  if (tid == 0) fail = 0;
+  __syncthreads();
+  for (int col = 0; col < nb; ++col) {
+    if (tid == 0) {
+      double p = T[col][col];
+      if (!(p > 0.0))
+        fail = col + 1;
+      else
+        T[col][col] = sqrt(p);
+    }
+    __syncthreads();
+    if (fail) break;
+    const double ljj = T[col][col];
+    for (int i = col + 1 + tid; i < nb; i += 256) T[i][col] /= ljj;
+    __syncthreads();
+    const int rem = nb - col - 1;
+    for (int e = tid; e < rem * rem; e += 256) {
+      int i = col + 1 + e / rem, k = col + 1 + e % rem;
+      if (k <= i) T[i][k] -= T[i][col] * T[k][col];
+    }
+    __syncthreads();
+  }
+  if (fail) {
+    if (tid == 0) info[c] = j0 + fail;
+    return;
+  }
+  for (int e = tid; e < nb * nb; e += 256) {
+    int i = e / nb, k = e % nb;
+    A[(size_t)(j0 + i) * n + j0 + k] = (k <= i) ? T[i][k] : 0.0;
+  }
+}
+
+// Rows i >= j0+nb: L[i][j0:j0+nb] = A[i][j0:j0+nb] L_jj^{-T}; one thread per row.
+__global__ __launch_bounds__(64) void chol_trsm_kernel(int n, int j0, double *L,
+                                                       const int32_t *info) {
+  const int c = blockIdx.y;
+  if (info[c] != 0) return;
+  double *A = L + (size_t)c * n * n;
+  const int nb = min(NB, n - j0);
+  const int r0 = j0 + nb;
+  __shared__ double D[NB][NB + 1];
+  for (int e = threadIdx.x; e < nb * nb; e += 64) {
+    int i = e / nb, k = e % nb;
+    D[i][k] = A[(size_t)(j0 + i) * n + j0 + k];
+  }
+  __syncthreads();
+  const int i = r0 + blockIdx.x * 64 + threadIdx.x;
+  if (i >= n) return;
+  double *row = A + (size_t)i * n + j0;
+  double x[NB];
+#pragma unroll
+  for (int cc = 0; cc < NB; ++cc) x[cc] = (cc < nb) ? row[cc] : 0.0;
+#pragma unroll
+  for (int cc = 0; cc < NB; ++cc) {
+    if (cc < nb) {
+      double s = x[cc];
+#pragma unroll
+      for (int t = 0; t < cc; ++t) s -= x[t] * D[cc][t];
+      x[cc] = s / D[cc][cc];
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < NB; ++cc)
+    if (cc < nb) row[cc] = x[cc];
+}
+
+// Trailing update A[i][k] -= sum_c L[i][j0+c] L[k][j0+c] for r0 <= k <= i < n,
+// 64x64 tiles of the lower triangle, 4x4 outputs per thread.
+__global__ __launch_bounds__(256) void chol_syrk_kernel(int n, int j0, double *L,
+                                                        const int32_t *info) {
+  const int c = blockIdx.y;
+  if (info[c] != 0) return;
+  double *A = L + (size_t)c * n * n;
+  const int nb = min(NB, n - j0);
+  const int r0 = j0 + nb;
+  // tile index -> (I, J) with I >= J
+  const int t = blockIdx.x;
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  const int J = t - I * (I + 1) / 2;
+  const int i0 = r0 + I * 64, k0 = r0 + J * 64;
+  __shared__ double LI[64][NB + 1];
+  __shared__ double LJ[64][NB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * nb; e += 256) {
+    int r = e / nb, cc = e % nb;
+    LI[r][cc] = (i0 + r < n) ? A[(size_t)(i0 + r) * n + j0 + cc] : 0.0;
+    LJ[r][cc] = (k0 + r < n) ? A[(size_t)(k0 + r) * n + j0 + cc] : 0.0;
+  }
+  __syncthreads();
+  const int ti = (tid >> 4) * 4, tk = (tid & 15) * 4;
+  double acc[4][4] = {};
+  for (int cc = 0; cc < nb; ++cc) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = LI[ti + u][cc];
+      b[u] = LJ[tk + u][cc];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int i = i0 + ti + u, k = k0 + tk + v;
+      if (i < n && k < n && k <= i) A[(size_t)i * n + k] -= acc[u][v];
+    }
+}
+
+__global__ void copy_lower_kernel(int C, int n, const double *A, double *L) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t total = (int64_t)C * n * n;
+  for (; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e % ((int64_t)n * n);
+    int i = (int)(r / n), k = (int)(r % n);
+    L[e] = (k <= i) ? A[e] : 0.0;
+  }
+}
+
+int chol_batched(int C, int n, const double *A, double *L, int32_t *info, hipStream_t s) {
+  if (C <= 0 || n <= 0) return SB_OK;
+  int st = launch_fill_i32(C, 0, info, s);
+  if (st) return st;
+  {
+    int64_t total = (int64_t)C * n * n;
+    unsigned blocks = (unsigned)std::min<int64_t>(8192, ceil_div(total, 256));
+    hipLaunchKernelGGL(copy_lower_kernel, dim3(blocks), dim3(256), 0, s, C, n, A, L);
+    SB_LAUNCH_CHECK();
+  }
+  for (int j0 = 0; j0 < n; j0 += NB) {
+    const int nb = std::min(NB, n - j0);
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(C), dim3(256), 0, s, n, j0, L, info);
+    SB_LAUNCH_CHECK();
+    const int rest = n - j0 - nb;
+    if (rest <= 0) break;
+    hipLaunchKernelGGL(chol_trsm_kernel, dim3((unsigned)ceil_div(rest, 64), C), dim3(64), 0, s, n,
+                       j0, L, info);
+    SB_LAUNCH_CHECK();
+    const int T = (int)ceil_div(rest, 64);
+    hipLaunchKernelGGL(chol_syrk_kernel, dim3((unsigned)(T * (T + 1) / 2), C), dim3(256), 0, s, n,
+                       j0, L, info);
+    SB_LAUNCH_CHECK();
+  }
+  return SB_OK;
+}
+
+// log det = 2 sum_i log L_ii from the factor (fixed-order reduction), NaN if it failed.
+__global__ __launch_bounds__(256) void logdet_kernel(int n, const double *L,
+                                                     const int32_t *info, double *logdet) {
+  const int c = blockIdx.x;
+  __shared__ double red[4];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) v += log(L[(size_t)c * n * n + (size_t)i * n + i]);
+  v = block_sum<256>(v, red);
+  if (threadIdx.x == 0) logdet[c] = info[c] ? NAN : 2.0 * v;
+}
+
+int launch_logdet(int C, int n, const double *L, const int32_t *info, double *logdet,
+                  hipStream_t s) {
+  if (C <= 0) return SB_OK;
+  hipLaunchKernelGGL(logdet_kernel, dim3(C), dim3(256), 0, s, n, L, info, logdet);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// Solve L L^T x = b: blocked forward (row dots over solved blocks, then the
+// 64x64 diagonal block in one wave) and backward substitution.  One workgroup
+// per matrix; x lives in LDS.
+__global__ __launch_bounds__(256) void chol_solve_kernel(int n, const double *Lall,
+                                                         const double *ball, double *xall,
+                                                         const int32_t *info) {
+  extern __shared__ double xs[];  // [n]
+  __shared__ double part[4][64];
+  const int c = blockIdx.x;
+  const double *L = Lall + (size_t)c * n * n;
+  const double *b = ball + (size_t)c * n;
+  double *x = xall + (size_t)c * n;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (info && info[c] != 0) {
+    for (int i = tid; i < n; i += 256) x[i] = NAN;
+    return;
+  }
+  for (int i = tid; i < n; i += 256) xs[i] = b[i];
+  __syncthreads();
+  // forward: L z = b
+  for (int i0 = 0; i0 < n; i0 += 64) {
+    const int nb = min(64, n - i0);
+    // rows i0..i0+nb: subtract sum_{k < i0} L[i][k] z_k; each wave takes 16 rows
+    for (int rr = 0; rr < 16; ++rr) {
+      const int r = w * 16 + rr;
+      double sacc = 0.0;
+      if (r < nb)
+        for (int k = lane; k < i0; k += 64) sacc += L[(size_t)(i0 + r) * n + k] * xs[k];
+      sacc = wave_sum(sacc);
+      if (lane == 0) part[0][r] = sacc;
+    }
+    __syncthreads();
+    if (w == 0) {
+      double val = (lane < nb) ? xs[i0 + lane] - part[0][lane] : 0.0;
+      for (int cc = 0; cc < nb; ++cc) {
+        double xc = __shfl(val / L[(size_t)(i0 + cc) * n + i0 + cc], cc, 64);
+        if (lane == cc) val = xc;
+        if (lane > cc && lane < nb) val -= L[(size_t)(i0 + lane) * n + i0 + cc] * xc;
+      }
+      if (lane < nb) xs[i0 + lane] = val;
+    }
+    __syncthreads();
+  }
+  // backward: L^T x = z
+  for (int iend = n; iend > 0; iend -= 64) {
+    const int i0 = max(0, iend - 64);
+    const int nb = iend - i0;
+    // s_i = sum_{k >= iend} L[k][i] x_k for i in block; lanes index i, waves split k
+    double sacc = 0.0;
+    if (lane < nb)
+      for (int k = iend + w; k < n; k += 4) sacc += L[(size_t)k * n + i0 + lane] * xs[k];
+    part[w][lane] = sacc;
+    __syncthreads();
+    if (w == 0) {
+      double sv = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+      double val = (lane < nb) ? xs[i0 + lane] - sv : 0.0;
+      for (int cc = nb - 1; cc >= 0; --cc) {
+        double xc = __shfl(val / L[(size_t)(i0 + cc) * n + i0 + cc], cc, 64);
+        if (lane == cc) val = xc;
+        if (lane < cc) val -= L[(size_t)(i0 + cc) * n + i0 + lane] * xc;
+      }
+      if (lane < nb) xs[i0 + lane] = val;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += 256) x[i] = xs[i];
+}
+
+int launch_chol_solve(int C, int n, const double *L, const double *b, double *x,
+                      const int32_t *info, hipStream_t s) {
+  if (C <= 0) return SB_OK;
+  size_t shm = sizeof(double) * (size_t)n;
+  if (shm > 64 * 1024) {
+    set_error("solve dimension %d too large", n);
+    return SB_E_UNSUPPORTED;
+  }
+  hipLaunchKernelGGL(chol_solve_kernel, dim3(C), dim3(256), shm, s, n, L, b, x, info);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+}  // namespace sb

@@ -1,0 +1,225 @@
+// Ray-bundle discovery (CarryTiger's ray generation and coarse pass).
+//
+// Ray r uses geometry r mod 4: vertex-to-vertex, vertex-to-edge-midpoint,
+// wall-to-wall along a random axis, and sunburst from the box centre along a
+// uniform direction on the sphere to the boundary (section "Ray Generation").
+// Randomness is Philox4x32-10 (Salmon et al., SC'11): counter (ray, block,
+// stream, problem), key (seed low word, seed high word); coordinate i of a
+// stream uses word i%4 of block i/4, a uniform uses the two words of half
+// block i%2 of block i/2 (53 bits).  Points t_j = (j + 1/2)/n_pts along each
+// ray are scored by the likelihood GEMM; each ray keeps its argmax (ties:
+// lowest j) and the rays with the highest maxima seed the optimiser (ties:
+// lowest ray index).
+#include <algorithm>
+
+#include "internal.h"
+
+namespace sb {
+
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    if (round) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+    const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+__device__ inline uint32_t rng_word(uint64_t seed, uint32_t problem, uint32_t ray, uint32_t stream,
+                                    uint32_t i) {
+  uint32_t c[4] = {ray, i >> 2, stream, problem};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  return c[i & 3u];
+}
+
+__device__ inline double rng_uniform(uint64_t seed, uint32_t problem, uint32_t ray,
+                                     uint32_t stream, uint32_t i) {
+  uint32_t c[4] = {ray, i >> 1, stream, problem};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const uint32_t a = c[2u * (i & 1u)], b = c[2u * (i & 1u) + 1u];
+  return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+__global__ __launch_bounds__(256) void rays_kernel(int d, const double *lo, const double *hi,
+                                                   uint64_t seed, uint32_t problem, double *P0,
+                                                   double *P1, float *P0f, float *P1f) {
+#pragma clang fp contract(off)
+  const uint32_t r = blockIdx.x;
+  const int g = (int)(r & 3u);
+  double *p = P0 + (size_t)r * d, *q = P1 + (size_t)r * d;
+  __shared__ double red[4];
+  const uint32_t axis =
+      (uint32_t)(((uint64_t)rng_word(seed, problem, r, 2, 0) * (uint64_t)d) >> 32);
+  if (g == 0 || g == 1) {
+    for (int i = threadIdx.x; i < d; i += 256) {
+      p[i] = (rng_word(seed, problem, r, 0, i) & 1u) ? hi[i] : lo[i];
+      double qi = (rng_word(seed, problem, r, 1, i) & 1u) ? hi[i] : lo[i];
+      if (g == 1 && (uint32_t)i == axis) qi = 0.5 * (lo[i] + hi[i]);
+      q[i] = qi;
+    }
+  } else if (g == 2) {
+    for (int i = threadIdx.x; i < d; i += 256) {
+      double pi = lo[i] + rng_uniform(seed, problem, r, 0, i) * (hi[i] - lo[i]);
+      double qi = lo[i] + rng_uniform(seed, problem, r, 1, i) * (hi[i] - lo[i]);
+      if ((uint32_t)i == axis) {
+        pi = lo[i];
+        qi = hi[i];
+      }
+      p[i] = pi;
+      q[i] = qi;
+    }
+  } else {
+    // z ~ N(0, I) by Box-Muller (cosine branch), u = z / |z|, exit where the
+    // ray from the centre leaves the box.
+    double n2 = 0.0;
+    for (int i = threadIdx.x; i < d; i += 256) {
+      double u1 = rng_uniform(seed, problem, r, 0, i);
+      double u2 = rng_uniform(seed, problem, r, 1, i);
+      double z = sqrt(-2.0 * log(1.0 - u1)) * cos(2.0 * M_PI * u2);
+      q[i] = z;
+      n2 += z * z;
+    }
+    n2 = block_sum<256>(n2, red);
+    const double nrm = sqrt(n2);
+    double tmin = INFINITY;
+    for (int i = threadIdx.x; i < d; i += 256) {
+      double c = 0.5 * (lo[i] + hi[i]);
+      double u = nrm > 0.0 ? q[i] / nrm : (i == 0 ? 1.0 : 0.0);
+      q[i] = u;
+      double t = INFINITY;
+      if (u > 0.0)
+        t = (hi[i] - c) / u;
+      else if (u < 0.0)
+        t = (lo[i] - c) / u;
+      tmin = fmin(tmin, t);
+    }
+    __syncthreads();
+    tmin = -block_max<256>(-tmin, red);
+    for (int i = threadIdx.x; i < d; i += 256) {
+      double c = 0.5 * (lo[i] + hi[i]);
+      p[i] = c;
+      q[i] = c + tmin * q[i];
+    }
+  }
+  if (P0f) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < d; i += 256) {
+      P0f[(size_t)r * d + i] = (float)p[i];
+      P1f[(size_t)r * d + i] = (float)q[i];
+    }
+  }
+}
+
+int launch_rays(int d, const double *lo, const double *hi, int R, uint64_t seed, uint32_t problem,
+                double *P0, double *P1, float *P0f, float *P1f, hipStream_t s) {
+  if (R <= 0) return SB_OK;
+  hipLaunchKernelGGL(rays_kernel, dim3(R), dim3(256), 0, s, d, lo, hi, seed, problem, P0, P1, P0f,
+                     P1f);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// Per-ray argmax over the n_pts scores (strict >, so ties keep the lowest j;
+// NaN never wins).
+template <typename T>
+__global__ void ray_argmax_kernel(int R, int n_pts, const T *l, double *best_l, int32_t *best_j) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double best = -INFINITY;
+  int bj = 0;
+  for (int j = 0; j < n_pts; ++j) {
+    double v = (double)l[(size_t)r * n_pts + j];
+    if (v > best) {
+      best = v;
+      bj = j;
+    }
+  }
+  best_l[r] = best;
+  best_j[r] = bj;
+}
+
+int launch_ray_argmax(int R, int n_pts, int dtype, const void *l, double *best_l, int32_t *best_j,
+                      hipStream_t s) {
+  if (R <= 0) return SB_OK;
+  dim3 grid((unsigned)ceil_div(R, 256));
+  if (dtype == DT_F64)
+    hipLaunchKernelGGL(ray_argmax_kernel<double>, grid, dim3(256), 0, s, R, n_pts,
+                       (const double *)l, best_l, best_j);
+  else
+    hipLaunchKernelGGL(ray_argmax_kernel<float>, grid, dim3(256), 0, s, R, n_pts,
+                       (const float *)l, best_l, best_j);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// Rank of each ray by (best l descending, index ascending), NaN as -inf; the
+// first n_starts ranks name the starts.
+__global__ __launch_bounds__(256) void topn_kernel(int R, int n_starts, const double *best_l,
+                                                   int32_t *start_ray) {
+  __shared__ double tile[256];
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  double key = -INFINITY;
+  if (r < R) {
+    key = best_l[r];
+    if (key != key) key = -INFINITY;
+  }
+  int rank = 0;
+  for (int t0 = 0; t0 < R; t0 += 256) {
+    __syncthreads();
+    int t = t0 + threadIdx.x;
+    double v = -INFINITY;
+    if (t < R) {
+      v = best_l[t];
+      if (v != v) v = -INFINITY;
+    }
+    tile[threadIdx.x] = v;
+    __syncthreads();
+    const int lim = min(256, R - t0);
+    for (int u = 0; u < lim; ++u) {
+      double w = tile[u];
+      rank += (w > key) || (w == key && t0 + u < r);
+    }
+  }
+  if (r < R && rank < n_starts) start_ray[rank] = r;
+}
+
+int launch_topn(int R, int n_starts, const double *best_l, int32_t *start_ray, hipStream_t s) {
+  if (R <= 0) return SB_OK;
+  hipLaunchKernelGGL(topn_kernel, dim3((unsigned)ceil_div(R, 256)), dim3(256), 0, s, R, n_starts,
+                     best_l, start_ray);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+__global__ void gather_starts_kernel(int d, int n_pts, int n_starts, const int32_t *start_ray,
+                                     const int32_t *best_j, const double *P0, const double *P1,
+                                     double *X0) {
+#pragma clang fp contract(off)
+  const int sidx = blockIdx.x;
+  const int r = start_ray[sidx];
+  const double t = ((double)best_j[r] + 0.5) / (double)n_pts;
+  for (int i = threadIdx.x; i < d; i += blockDim.x) {
+    double a = P0[(size_t)r * d + i], b = P1[(size_t)r * d + i];
+    X0[(size_t)sidx * d + i] = a + t * (b - a);
+  }
+}
+
+int launch_gather_starts(int d, int n_pts, int n_starts, const int32_t *start_ray,
+                         const int32_t *best_j, const double *P0, const double *P1, double *X0,
+                         hipStream_t s) {
+  if (n_starts <= 0) return SB_OK;
+  hipLaunchKernelGGL(gather_starts_kernel, dim3(n_starts), dim3(256), 0, s, d, n_pts, n_starts,
+                     start_ray, best_j, P0, P1, X0);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+}  // namespace sb

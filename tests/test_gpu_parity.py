@@ -1,0 +1,414 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Step by step on identical seeded inputs (l, grad, HVP, Hessian, Cholesky,
+rays, discovery, two-loop, L-BFGS, dedup, combine), then the whole path per
+workload.  FP64 tolerances follow from rounding-order differences of O(d)
+sums (~d * 2^-53 relative); the mixed path is held to |d log Z| <= 1e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2601_19957_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2601_19957_amd import _lib
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    _lib.lib()
+    return _lib
+
+
+def small_mixture(d, K, seed, box=12.0, norm=synth.NORM_DENSITY):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return synth.gaussian_mixture(rng, d, K, -8.0, 8.0, 0.05, 1.0, 12.0 if K > 1 else 0.0,
+                                  box_half=box, norm=norm, linf_min=1.0)
+
+
+def t_problem(d, seed, nu=30.0):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return synth.student_t(rng, d, nu, -5.0, 5.0, 0.01, 1.0, 20.0)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def rel(a, ref, floor=1.0, axis=None):
+    """max |a - ref| / max(floor, |ref|) (row-wise scale when axis=1), as a float."""
+    a, ref = np.asarray(a, dtype=np.float64), np.asarray(ref, dtype=np.float64)
+    if axis is None:
+        sc = np.maximum(floor, np.abs(ref))
+    else:
+        sc = np.maximum(floor, np.abs(ref).max(axis=axis, keepdims=True))
+    return float(np.max(np.abs(a - ref) / sc)) if a.size else 0.0
+
+
+def absmax(a):
+    return float(np.max(np.abs(np.asarray(a, dtype=np.float64)))) if np.size(a) else 0.0
+
+
+PROBLEMS = {
+    "c0": lambda: synth.make_problem("c0"),
+    "mix_d37_K3": lambda: small_mixture(37, 3, 3),
+    "mix_d200_K2": lambda: small_mixture(200, 2, 4),
+    "c1": lambda: synth.make_problem("c1"),
+    "t_d256": lambda: t_problem(256, 5),
+    "t_d70": lambda: t_problem(70, 6, nu=4.0),
+}
+
+
+# ------------------------------------------------------------------ prep / A1
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_prep_constants(L, name):
+    prob = PROBLEMS[name]()
+    st, beta, ld = O.prep(prob)
+    m = L.DeviceModel(prob)
+    assert np.allclose(m.beta.cpu().numpy(), beta, rtol=1e-12, atol=1e-10)
+    assert np.allclose(m.logdet_prec.cpu().numpy(), ld, rtol=1e-12, atol=1e-10)
+
+
+def test_prep_rejects_indefinite_and_asymmetric(L):
+    prob = small_mixture(20, 2, 9)
+    bad = prob.copy()
+    bad.prec[1] = -bad.prec[1]
+    with pytest.raises(L.SbError) as e:
+        L.DeviceModel(bad)
+    assert e.value.status == L.E_NOTPD
+    asym = prob.copy()
+    asym.prec[0, 2, 5] += 1e-6
+    with pytest.raises(L.SbError) as e:
+        L.DeviceModel(asym)
+    assert e.value.status == L.E_NOTPD
+
+
+# ---------------------------------------------------------- logl + grad / A3
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+@pytest.mark.parametrize("B", [1, 131, 300])
+def test_logl_grad_fp64(L, name, B):
+    prob = PROBLEMS[name]()
+    X = np.concatenate([synth.points_near_modes(prob, (B + 1) // 2, 11, scale=0.8),
+                        synth.random_points(prob, B // 2, 12, spread=0.9)])[:B]
+    lo, go = O.logl(prob, X)
+    m = L.DeviceModel(prob)
+    l, g = L.sb_logl_grad_dev(m, dev(X))
+    l, g = l.cpu().numpy(), g.cpu().numpy()
+    el, eg = rel(l, lo), rel(g, go, axis=1)
+    assert el < 1e-11 and eg < 1e-11, (el, eg)
+
+
+@pytest.mark.parametrize("name", ["mix_d37_K3", "c1", "t_d256"])
+def test_logl_grad_fp32(L, name):
+    prob = PROBLEMS[name]()
+    X = synth.points_near_modes(prob, 200, 13, scale=0.5)
+    lo, go = O.logl(prob, X)
+    m = L.DeviceModel(prob, low_precision=True)
+    l, g = L.sb_logl_grad_dev(m, dev(X).float())
+    l, g = l.double().cpu().numpy(), g.double().cpu().numpy()
+    # FP32 rounding of delta, P and the O(d) sums: ~ d * 2^-24 relative to |q|, |P delta|
+    q_scale = np.maximum(1.0, np.abs(lo - O.prep(prob)[1].max()))
+    el = float(np.max(np.abs(l - lo) / (q_scale + np.abs(lo))))
+    eg = rel(g, go, axis=1)
+    assert el < 5e-5 and eg < 5e-5, (el, eg)
+
+
+def test_gradient_central_differences_on_gpu(L):
+    """The hand-written backward against central differences of the GPU's own l (h = 1e-6)."""
+    prob = synth.make_problem("c1")
+    m = L.DeviceModel(prob)
+    x = synth.points_near_modes(prob, 1, 21, scale=0.3)[0]
+    _, g = L.sb_logl_grad_dev(m, dev(x[None]))
+    g = g.cpu().numpy()[0]
+    h = 1e-6
+    E = np.eye(prob.d) * h
+    lp = L.sb_logl_grad_dev(m, dev(x[None] + E), grad=False).cpu().numpy()
+    lm = L.sb_logl_grad_dev(m, dev(x[None] - E), grad=False).cpu().numpy()
+    fd = (lp - lm) / (2 * h)
+    e = absmax(fd - g) / max(1.0, absmax(g))
+    assert e <= 1e-6, e
+
+
+# --------------------------------------------------------------- HVP / A3'
+
+@pytest.mark.parametrize("name", ["c0", "mix_d37_K3", "c1", "t_d256", "t_d70"])
+def test_hvp(L, name):
+    prob = PROBLEMS[name]()
+    X = synth.points_near_modes(prob, 40, 31, scale=0.6)
+    V = np.random.default_rng(32).standard_normal(X.shape)
+    ref = O.hvp(prob, X, V)
+    m = L.DeviceModel(prob)
+    hv = L.sb_hvp_dev(m, dev(X), dev(V)).cpu().numpy()
+    e = rel(hv, ref, axis=1)
+    assert e < 1e-11, e
+
+
+# ---------------------------------------------------------- Hessian / A8
+
+@pytest.mark.parametrize("name", ["c0", "mix_d37_K3", "mix_d200_K2", "t_d256"])
+def test_hessian_assembly(L, name):
+    prob = PROBLEMS[name]()
+    X = synth.points_near_modes(prob, 3, 41, scale=0.2)
+    m = L.DeviceModel(prob)
+    H = L.sb_hessian_dev(m, dev(X)).cpu().numpy()
+    for c in range(3):
+        ref = O.neg_hessian(prob, X[c])
+        e = absmax(H[c] - ref) / absmax(ref)
+        assert e <= 1e-12, e
+        assert np.array_equal(H[c], H[c].T)
+
+
+def test_hessian_equals_hvp_columns(L):
+    prob = small_mixture(24, 3, 8)
+    m = L.DeviceModel(prob)
+    x = synth.points_near_modes(prob, 1, 5, scale=0.4)
+    H = L.sb_hessian_dev(m, dev(x)).cpu().numpy()[0]
+    X = np.repeat(x, prob.d, axis=0)
+    HV = L.sb_hvp_dev(m, dev(X), dev(np.eye(prob.d))).cpu().numpy()
+    e = absmax(-HV.T - H) / absmax(H)
+    assert e <= 1e-12, e
+
+
+# ---------------------------------------------------------- Cholesky / A9
+
+@pytest.mark.parametrize("n", [1, 5, 64, 65, 200])
+def test_cholesky_logdet(L, n):
+    A = synth.random_spd(n, 100 + n, cond=1e3, batch=3)
+    Lf, ld, info = L.sb_cholesky_logdet_dev(dev(A))
+    Lf, ld, info = Lf.cpu().numpy(), ld.cpu().numpy(), info.cpu().numpy()
+    for c in range(3):
+        st, Lo = O.cholesky(A[c])
+        assert info[c] == 0 and st == 0
+        e = absmax(Lf[c] - Lo) / absmax(Lo)
+        assert e <= 1e-12, e
+        e2 = abs(ld[c] - O.logdet_spd(A[c])) / max(1.0, abs(ld[c]))
+        assert e2 <= 1e-12, e2
+    b = np.random.default_rng(n).standard_normal((3, n))
+    x = L.sb_cholesky_solve_dev(torch.as_tensor(Lf, device="cuda"), dev(b)).cpu().numpy()
+    for c in range(3):
+        ref = O.chol_solve(O.cholesky(A[c])[1], b[c])
+        e = rel(x[c], ref, floor=1e-2)
+        assert e <= 1e-10, e
+
+
+def test_cholesky_failure_column(L):
+    A = synth.random_spd(70, 3, cond=10.0, batch=2)
+    A[1, 66, 66] = -5.0  # pivot 67 fails
+    st, _ = O.cholesky(A[1])
+    _, ld, info = L.sb_cholesky_logdet_dev(dev(A))
+    info = info.cpu().numpy()
+    assert info[0] == 0 and info[1] == st == 67
+    assert math.isnan(float(ld[1]))
+
+
+# -------------------------------------------------------------- rays / A2
+
+@pytest.mark.parametrize("d", [4, 7, 300])
+def test_rays_match_oracle(L, d):
+    prob = small_mixture(d, 1, 50 + d, box=9.0)
+    R = 64
+    P0o, P1o = O.rays(d, prob.lo, prob.hi, R, 777)
+    m = L.DeviceModel(prob)
+    out = L.sb_discover_dev(m, R, 8, 8, 777)
+    P0, P1 = out["P0"].cpu().numpy(), out["P1"].cpu().numpy()
+    assert np.array_equal(P0[0::4], P0o[0::4]) and np.array_equal(P1[0::4], P1o[0::4])
+    assert np.array_equal(P0[1::4], P0o[1::4]) and np.array_equal(P1[1::4], P1o[1::4])
+    assert np.array_equal(P0[2::4], P0o[2::4]) and np.array_equal(P1[2::4], P1o[2::4])
+    # sunburst: Box-Muller uses the device's log/cos (a few ulp from the host libm)
+    e0, e1 = absmax(P0[3::4] - P0o[3::4]), absmax(P1[3::4] - P1o[3::4])
+    assert e0 <= 1e-13 and e1 <= 1e-11, (e0, e1)
+
+
+@pytest.mark.parametrize("name", ["c0", "mix_d37_K3", "t_d70"])
+def test_discovery_fp64(L, name):
+    prob = PROBLEMS[name]()
+    R, npts, ns = 256, 32, 64
+    ref = O.discover(prob, R, npts, ns, 4242)
+    m = L.DeviceModel(prob)
+    out = L.sb_discover_dev(m, R, npts, ns, 4242)
+    bl = out["ray_best_l"].cpu().numpy()
+    e = rel(bl, ref["ray_best_l"])
+    assert e < 1e-11, e
+    # argmax is unique where the best two samples of a ray differ clearly: compare the
+    # chosen sample's value instead of its index (equal values are both correct)
+    P0o, P1o = O.rays(prob.d, prob.lo, prob.hi, R, 4242)
+    bj = out["ray_best_j"].cpu().numpy()
+    t = (bj + 0.5) / npts
+    pts = P0o + t[:, None] * (P1o - P0o)
+    lv = O.logl(prob, pts, grad=False)
+    e = rel(lv, ref["ray_best_l"])
+    assert e < 1e-11, e
+    # the chosen rays carry the n_starts largest maxima, in order
+    sr = out["start_ray"].cpu().numpy()
+    assert np.all(np.diff(ref["ray_best_l"][sr]) <= 1e-9 * np.abs(ref["ray_best_l"][sr[:-1]]))
+    assert set(sr) == set(ref["start_ray"]) or np.sort(ref["ray_best_l"])[-ns] == \
+        np.sort(ref["ray_best_l"])[-ns - 1]
+    X0 = out["X0"].cpu().numpy()
+    e = absmax(X0 - pts[sr]) / absmax(pts)
+    assert e <= 1e-12, e
+
+
+def test_discovery_bf16_ranks(L):
+    """BF16 scores only rank the samples: the best BF16 sample of a ray must be
+    within the BF16 error bound of the ray's true maximum (parity of values unpinned)."""
+    prob = small_mixture(128, 2, 60, box=12.0)
+    R, npts = 128, 32
+    m = L.DeviceModel(prob, low_precision=True)
+    out = L.sb_discover_dev(m, R, npts, 32, 99, dtype=L.DTYPE_BF16)
+    ref = O.discover(prob, R, npts, 32, 99)
+    P0o, P1o = O.rays(prob.d, prob.lo, prob.hi, R, 99)
+    bj = out["ray_best_j"].cpu().numpy()
+    pts = P0o + ((bj + 0.5) / npts)[:, None] * (P1o - P0o)
+    lv = O.logl(prob, pts, grad=False)
+    gap = ref["ray_best_l"] - lv
+    assert float(gap.min()) >= -1e-9, float(gap.min())
+    # |dq| <~ 2^-7 |delta|^T |P| |delta| per component; compare with the scale of q
+    e = float(np.max(gap / np.maximum(1.0, np.abs(ref["ray_best_l"]))))
+    assert e < 0.05, e
+
+
+# ------------------------------------------------------------ two-loop / A4
+
+@pytest.mark.parametrize("d", [4, 64, 100, 256, 700, 1024])
+def test_two_loop_direction(L, d):
+    B, m = 6, 8
+    cnts = [0, 1, 3, 5, 8, 8]
+    S = np.zeros((B, m, d))
+    Y = np.zeros((B, m, d))
+    G = np.zeros((B, d))
+    for b in range(B):
+        s_, y_, g_ = synth.lbfgs_history(d, m, cnts[b], seed=70 + b)
+        S[b], Y[b], G[b] = s_[0], y_[0], g_[0]
+    P = L.sb_lbfgs_direction_dev(dev(S), dev(Y), dev(G), dev(np.array(cnts, dtype=np.int32)))
+    P = P.cpu().numpy()
+    for b in range(B):
+        ref = O.two_loop(S[b, :cnts[b]], Y[b, :cnts[b]], G[b]) if cnts[b] else -G[b]
+        e = absmax(P[b] - ref) / absmax(ref)
+        assert e <= 1e-12, (b, e)
+
+
+# -------------------------------------------------------------- L-BFGS / A4-A5
+
+@pytest.mark.parametrize("name", ["c0", "mix_d37_K3", "t_d70"])
+def test_lbfgs_reaches_oracle_points(L, name):
+    """Same start points, FP64: every start converges to the point the oracle's
+    optimiser reaches (the paths may differ in the last bits)."""
+    prob = PROBLEMS[name]()
+    X0 = synth.points_near_modes(prob, 48, 81, scale=1.0)
+    m = L.DeviceModel(prob)
+    out = L.sb_lbfgs_dev(m, dev(X0), m=8, grad_tol=1e-10)
+    st = out["status"].cpu().numpy()
+    x = out["x"].cpu().numpy()
+    assert int((st != L.ST_CONVERGED).sum()) == 0, np.unique(st).tolist()
+    op = O.OracleProblem(prob)
+    for s in range(0, 48, 5):
+        r = O.lbfgs(prob, X0[s], m=8, grad_tol=1e-10, op=op)
+        assert r["status"] == O.ST_CONVERGED
+        e = absmax(x[s] - r["x"])
+        assert e < 1e-8, (s, e)
+    eg = absmax(out["grad"].cpu().numpy())
+    assert eg <= 1e-10, eg
+
+
+# -------------------------------------------------------------- dedup / A7
+
+def test_dedup_handmade(L):
+    X = np.array([[0.0, 0.0], [0.05, 0.0], [1.0, 1.0], [1.02, 0.99], [0.0, 0.09], [5.0, 5.0]])
+    l = np.array([1.0, 3.0, 2.0, 2.0, 0.5, -1.0])
+    rep_of, reps = L.sb_dedup_dev(dev(X), dev(l), 0.1)
+    assert list(reps.cpu().numpy()) == [1, 2, 5]
+    assert list(rep_of.cpu().numpy()) == [1, 1, 2, 2, 1, 5]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_dedup_matches_oracle(L, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(0, 1, (500, 6))
+    l = np.round(rng.standard_normal(500), 1)
+    valid = rng.uniform(size=500) > 0.1
+    ro, rs = O.dedup(X, l, 0.3, valid=valid)
+    rep_of, reps = L.sb_dedup_dev(dev(X), dev(l), 0.3, valid=dev(valid))
+    assert np.array_equal(rep_of.cpu().numpy(), ro)
+    assert np.array_equal(reps.cpu().numpy(), rs)
+
+
+# ------------------------------------------------------------ combine / A10
+
+def test_combine(L):
+    rng = np.random.default_rng(4)
+    d, n = 9, 6
+    lo, hi = -np.ones(d) * 3, np.ones(d) * 4
+    logl = rng.normal(size=n) * 5
+    logl[4] = logl[1]
+    logdet = rng.normal(size=n)
+    logdet[4] = logdet[1]
+    modes = rng.normal(size=(n, d))
+    order, mlz, lz = L.sb_combine_dev(dev(lo), dev(hi), dev(logl), dev(logdet), dev(modes))
+    lv = O.log_volume(lo, hi)
+    ref = np.array([O.mode_log_z(d, logl[i], logdet[i], lv) for i in range(n)])
+    o = order.cpu().numpy()
+    e = absmax(mlz.cpu().numpy() - ref[o])
+    assert e <= 1e-12, e
+    assert np.all(np.diff(ref[o]) <= 0)
+    # the tie (modes 1 and 4) is broken lexicographically
+    i1, i4 = list(o).index(1), list(o).index(4)
+    assert (i1 < i4) == (tuple(modes[1]) < tuple(modes[4]))
+    assert abs(float(lz) - O.logsumexp(ref[o])) < 1e-12
+
+
+# ------------------------------------------------------------ whole path
+
+def _compare(r, ref, tol_logz, tol_modes=1e-8):
+    assert r.status == 0, (r.status, r.n_modes)
+    assert ref.status == 0
+    assert r.n_modes == ref.n_modes, (r.n_modes, ref.n_modes, r.n_reps_pre)
+    dz = abs(r.log_z - ref.log_z)
+    dm = absmax(r.modes - ref.modes)
+    dk = absmax(r.mode_log_z - ref.mode_log_z)
+    dh = absmax(r.log_det_h - ref.log_det_h)
+    assert dz <= tol_logz and dm <= tol_modes and dk <= tol_logz and dh <= max(tol_logz, 1e-9), \
+        (dz, dm, dk, dh)
+
+
+@pytest.mark.parametrize("name,ns,prec", [
+    ("c0", None, 0), ("c0", None, 1), ("c1", 512, 0), ("c1", 512, 1), ("c2", 256, 0),
+])
+def test_evidence_matches_oracle(L, name, ns, prec):
+    prob, cfg = synth.make_workload(name, n_starts=ns, precision=prec)
+    r = L.sb_evidence(prob, cfg)
+    ref = O.evidence(prob, synth.make_run_config(name, n_starts=ns, precision=0))
+    _compare(r, ref, 1e-9 if prec == 0 else 1e-6)
+
+
+def test_evidence_device_entry_and_determinism(L):
+    prob, cfg = synth.make_workload("c1", n_starts=256)
+    run = L.EvidenceRunner(prob, cfg)
+    a = run.run()
+    b = run.run()
+    assert a.status == 0
+    assert a.log_z == b.log_z and np.array_equal(a.modes, b.modes)
+    h = L.sb_evidence(prob, cfg)
+    assert h.log_z == a.log_z
+
+
+def test_evidence_statuses(L):
+    prob, cfg = synth.make_workload("c1", n_starts=128)
+    cfg.max_modes = 2
+    r = L.sb_evidence(prob, cfg)
+    assert r.status == L.E_CAPACITY and r.n_modes == 4 and math.isnan(r.log_z)
+    p0, c0 = synth.make_workload("c0")
+    p0.mu = p0.mu + 25.0
+    r0 = L.sb_evidence(p0, c0)
+    assert r0.status == L.E_NOMODE and r0.log_z == -math.inf
+    p1, c1 = synth.make_workload("c0")
+    p1.prec[0] = -p1.prec[0]
+    assert L.sb_evidence(p1, c1).status == L.E_NOTPD
