@@ -1,0 +1,253 @@
+#!/usr/bin/env python
+"""Benchmark of the Laplace-evidence hot path on one MI355X.
+
+Metric: logL+grad evaluations per second and time-to-log Z at d = 1024, for
+the mixed-precision path (BF16 discovery GEMM, FP32 L-BFGS bulk, FP64 polish,
+Hessian, Cholesky and combine) against the plain FP64 path.
+
+One step = one full evidence computation (discovery, batched L-BFGS, dedup,
+Newton polish, Hessian, Cholesky, log det, combine) for each posterior of the
+d = 1024 workload: (a) a dense-covariance Gaussian and (b) a K = 8 Gaussian
+mixture, 16384 rays x 32 points and 16384 starts each.  Inputs are resident
+in HBM when the timed region starts (sb_evidence_dev); the value is the
+number of logL+grad evaluations performed per second of wall time.
+
+Also reported: the roofline of the dominant kernel (the FP32 quadratic-form
+GEMM of the L-BFGS bulk at the mixture's shape, HIP events on its stream)
+and the CPU oracle timed on the host on a bounded sample of the workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0, "hbm": 8000.0}
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload(names, n_starts=None):
+    from paper_2601_19957_amd import synth
+
+    out = {}
+    for nm in names:
+        prob, cfg = synth.make_workload(nm, n_starts=n_starts)
+        out[nm] = (prob, cfg)
+    return out
+
+
+def closed_form_logz(prob) -> float:
+    """Laplace log Z of the synthetic problem from its generator data (box truncation aside)."""
+    d = prob.d
+    logv = float(sum(math.log(h - l) for l, h in zip(prob.lo, prob.hi)))
+    if prob.norm == 0 and prob.K == 1:  # peak-zero Gaussian
+        return 0.5 * d * math.log(2 * math.pi) + 0.5 * float(prob.sum_log_lambda[0]) - logv
+    return -logv  # normalised mixture: total mass 1
+
+
+def time_quadform(L, prob, B, reps=20):
+    """Average duration of the FP32 A3 GEMM at the bulk shape, HIP events on its stream."""
+    import torch
+    from paper_2601_19957_amd import synth
+
+    m = L.DeviceModel(prob, low_precision=True)
+    X = torch.as_tensor(synth.points_near_modes(prob, B, 5, scale=0.3), device="cuda").float()
+    qf = L.QuadForm(m, X)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        qf(stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        qf(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    avg_s = e0.elapsed_time(e1) * 1e-3 / reps
+    d, K = prob.d, prob.K
+    flops = 2.0 * B * K * d * d + 2.0 * B * K * d  # Y = delta P^T, q = delta . Y
+    return avg_s, flops
+
+
+def cpu_baseline(prob, cfg, budget_s=20.0):
+    """The oracle, as it stands, on a bounded sample: a few starts of the same workload."""
+    import oracle
+
+    threads = os.cpu_count() or 1
+    ns = max(1, min(threads, 32))
+    t0 = time.perf_counter()
+    r = oracle.evidence(prob, cfg, n_threads=threads, n_starts=ns)
+    dt = time.perf_counter() - t0
+    if dt < 0.25 * budget_s and ns < 4 * threads:  # too short a sample: take more starts
+        ns = min(int(ns * min(8.0, budget_s / max(dt, 1e-3))), 8 * threads)
+        t0 = time.perf_counter()
+        r = oracle.evidence(prob, cfg, n_threads=threads, n_starts=ns)
+        dt = time.perf_counter() - t0
+    return dict(value=r.n_grad_evals / dt, unit="logL+grad evals/s", cores=threads, kind="oracle",
+                sample=f"{prob.name}: whole path with {ns} starts "
+                       f"({ns} rays x {cfg.n_points} points), {r.n_grad_evals} logL+grad evals "
+                       f"in {dt:.2f} s, log Z {r.log_z:.6f}",
+                seconds=dt, log_z=r.log_z)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--workload", default="c4a,c4b")
+    ap.add_argument("--starts", type=int, default=None, help="override the start count")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only the roofline kernel timing (for profiling that kernel)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for {max(args.gpus, world)}): the evidence "
+              "path here runs on a single MI355X; see DESIGN.md for how it would shard.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import numpy as np
+    from paper_2601_19957_amd import _lib as L
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    L.lib()
+    names = [n.strip() for n in args.workload.split(",") if n.strip()]
+    log(f"generating {names}")
+    wl = workload(names, args.starts)
+    big = names[-1]
+    prob_big, cfg_big = wl[big]
+
+    # ---- roofline kernel: FP32 quadratic-form GEMM at the bulk shape of the largest posterior
+    log("timing the A3 GEMM (FP32) at the bulk shape")
+    kt_s, kflops = time_quadform(L, prob_big, cfg_big.n_starts)
+    roofline = dict(bound="mfma", achieved=kflops / kt_s / 1e12, peak=PEAK["fp32"],
+                    unit="TFLOP/s", frac=(kflops / kt_s / 1e12) / PEAK["fp32"], traffic=None,
+                    kernel="quad_gemm_kernel<float,float> (A3 logL+grad contraction)",
+                    shape=f"B={cfg_big.n_starts} d={prob_big.d} K={prob_big.K}",
+                    avg_launch_us=kt_s * 1e6)
+    if args.kernel_only:
+        print(json.dumps(dict(kernel_only=True, roofline=roofline)), flush=True)
+        return 0
+
+    # ---- whole path, inputs resident in HBM
+    runners = {n: L.EvidenceRunner(p, c) for n, (p, c) in wl.items()}
+    ref = {n: closed_form_logz(p) for n, (p, _) in wl.items()}
+    for w in range(args.warmup):
+        for n, r in runners.items():
+            res = r.run()
+            log(f"warmup {w} {n}: status {res.status} log Z {res.log_z:.9f} "
+                f"(closed form {ref[n]:.9f}) modes {res.n_modes} iters {res.iterations} "
+                f"evals {res.n_grad_evals} t {res.seconds[7]*1e3:.1f} ms "
+                f"phases {[round(s*1e3, 2) for s in res.seconds[:7]]}")
+    torch.cuda.synchronize()
+    per = {n: [] for n in names}
+    last = {}
+    evals = 0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        for n, r in runners.items():
+            ts = time.perf_counter()
+            res = r.run()
+            per[n].append(time.perf_counter() - ts)
+            evals += res.n_grad_evals
+            last[n] = res
+            if res.status != 0:
+                log(f"step {k} {n}: status {res.status} {L.last_error()}")
+        log(f"step {k} done")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+
+    # ---- plain FP64 path, same pipeline and starts
+    t64 = {}
+    res64 = {}
+    if not args.no_fp64:
+        from paper_2601_19957_amd import synth
+
+        for n, (p, c) in wl.items():
+            c64 = synth.RunConfig(**{**vars(c), "precision": synth.PREC_FP64})
+            r64 = L.EvidenceRunner(p, c64)
+            r64.run()  # warm (code objects, tile cache)
+            ts = []
+            for _ in range(args.fp64_steps):
+                t1 = time.perf_counter()
+                res64[n] = r64.run()
+                ts.append(time.perf_counter() - t1)
+            t64[n] = float(np.median(ts))
+            log(f"fp64 {n}: {t64[n]*1e3:.1f} ms log Z {res64[n].log_z:.9f} "
+                f"iters {res64[n].iterations} evals {res64[n].n_grad_evals}")
+            del r64
+            torch.cuda.empty_cache()
+
+    # ---- parity against the oracle's reference mode set (Newton from each mean)
+    import oracle
+
+    dlogz, dmodes, refz = {}, {}, {}
+    for n, (p, _) in wl.items():
+        refm = oracle.reference_modes(p)
+        refz[n] = refm.log_z
+        dlogz[n] = abs(last[n].log_z - refm.log_z) if n in last else None
+        if n in last and last[n].n_modes == refm.n_modes:
+            dmodes[n] = float(np.max(np.abs(last[n].modes - refm.modes)))
+        log(f"{n}: |dlogZ| vs oracle {dlogz[n]:.3e} (closed form gap "
+            f"{abs(refm.log_z - ref[n]):.3e}), modes {last[n].n_modes}/{refm.n_modes}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("CPU baseline (oracle) on a bounded sample")
+        cb = cpu_baseline(prob_big, cfg_big)
+        cpu = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+
+    ms_per_step = total / max(1, args.steps) * 1e3
+    out = {
+        "metric": "logL+grad evals/s and time-to-log Z at d=1024 vs plain FP64 (|dlogZ|<=1e-6)",
+        "value": evals / total,
+        "unit": "logL+grad evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16/f32/f64 (mixed)",
+        "data": "synthetic",
+        "config": {
+            "workload": " + ".join(f"{n}: d={wl[n][0].d} K={wl[n][0].K} "
+                                   f"{'Gaussian' if wl[n][0].K == 1 else 'mixture'} "
+                                   f"{wl[n][1].n_rays}x{wl[n][1].n_points} rays, "
+                                   f"{wl[n][1].n_starts} starts" for n in names),
+            "precision": "mixed",
+        },
+        "time_to_logz_ms": {n: float(np.median(per[n])) * 1e3 for n in names},
+        "time_to_logz_fp64_ms": {n: t64[n] * 1e3 for n in t64},
+        "speedup_vs_fp64": {n: t64[n] / float(np.median(per[n])) for n in t64},
+        "dlogz_vs_oracle": dlogz,
+        "dlogz_fp64_vs_oracle": {n: abs(res64[n].log_z - refz[n]) for n in res64},
+        "max_mode_dist_vs_oracle": dmodes,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -167,6 +167,14 @@ size_t sb_logl_grad_workspace_bytes(int32_t d, int32_t K, int64_t B, int32_t dty
 int32_t sb_logl_grad_dev(const sb_model_dev *m, int64_t B, const void *X, void *logl, void *grad,
                          int32_t dtype, void *workspace, size_t ws_bytes, void *stream);
 
+/* The contraction of step A3 alone, as used inside sb_logl_grad_dev and the
+ * optimiser: Y [B][K*d] with Y[b][k*d + n] = sum_j P_k[n][j] (X[b][j] -
+ * mu_k[j]) and per-tile partial quadratic forms qpart [B][K][*n_tiles]
+ * (q_k = sum over tiles).  dtype F64 or F32 (Y, qpart in that type).  qpart
+ * must hold B*K*ceil(d/64) values.  For measurement and testing. */
+int32_t sb_quadform_dev(const sb_model_dev *m, int64_t B, const void *X, int32_t dtype, void *Y,
+                        void *qpart, int32_t *n_tiles, void *stream);
+
 /* Batched Hessian-vector product (step A3'): HV[b] = nabla^2 l(X[b]) V[b],
  * FP64.  Workspace >= sb_hvp_workspace_bytes(d, K, B). */
 size_t sb_hvp_workspace_bytes(int32_t d, int32_t K, int64_t B);

@@ -30,7 +30,7 @@ ST_CONVERGED, ST_STALLED, ST_MAXITER, ST_DEAD = 1, 2, 3, 4
 EXPORTS = [
     "sb_evidence", "sb_evidence_batch", "sb_evidence_workspace_bytes", "sb_evidence_dev",
     "sb_prep_workspace_bytes", "sb_prep_dev", "sb_logl_grad_workspace_bytes", "sb_logl_grad_dev",
-    "sb_hvp_workspace_bytes", "sb_hvp_dev", "sb_discover_workspace_bytes", "sb_discover_dev",
+    "sb_quadform_dev", "sb_hvp_workspace_bytes", "sb_hvp_dev", "sb_discover_workspace_bytes", "sb_discover_dev",
     "sb_lbfgs_direction_dev", "sb_lbfgs_workspace_bytes", "sb_lbfgs_dev",
     "sb_dedup_workspace_bytes", "sb_dedup_dev", "sb_hessian_workspace_bytes", "sb_hessian_dev",
     "sb_cholesky_logdet_dev", "sb_cholesky_solve_dev", "sb_combine_dev", "sb_status_string",
@@ -100,6 +100,7 @@ def lib():
             "sb_prep_dev": (i32, [vp, vp, vp, vp, vp, vp, vp, sz, vp]),
             "sb_logl_grad_workspace_bytes": (sz, [i32, i32, i64, i32]),
             "sb_logl_grad_dev": (i32, [vp, i64, vp, vp, vp, i32, vp, sz, vp]),
+            "sb_quadform_dev": (i32, [vp, i64, vp, i32, vp, vp, vp, vp]),
             "sb_hvp_workspace_bytes": (sz, [i32, i32, i64]),
             "sb_hvp_dev": (i32, [vp, i64, vp, vp, vp, vp, sz, vp]),
             "sb_discover_workspace_bytes": (sz, [i32, i32, i32, i32, i32]),
@@ -318,6 +319,29 @@ def sb_logl_grad_dev(model: DeviceModel, X, grad: bool = True):
                                 ws.data_ptr(), ws.numel(), _stream())
     _check(st, "sb_logl_grad_dev")
     return (l, g) if grad else l
+
+
+class QuadForm:
+    """Repeated launches of the A3 contraction alone (sb_quadform_dev) on fixed buffers."""
+
+    def __init__(self, model: DeviceModel, X):
+        import torch
+
+        self.model = model
+        self.dt = DTYPE_F64 if X.dtype == torch.float64 else DTYPE_F32
+        self.X = X.contiguous()
+        B = X.shape[0]
+        self.Y = torch.empty((B, model.K * model.d), dtype=X.dtype, device=X.device)
+        self.qpart = torch.empty((B, model.K, (model.d + 63) // 64), dtype=X.dtype,
+                                 device=X.device)
+        self.mv = model.view(self.dt)
+        self.n_tiles = C.c_int32()
+
+    def __call__(self, stream=None):
+        st = lib().sb_quadform_dev(C.byref(self.mv), self.X.shape[0], self.X.data_ptr(), self.dt,
+                                   self.Y.data_ptr(), self.qpart.data_ptr(),
+                                   C.byref(self.n_tiles), _stream(stream))
+        _check(st, "sb_quadform_dev")
 
 
 def sb_hvp_dev(model: DeviceModel, X, V):

@@ -421,6 +421,31 @@ int32_t sb_logl_grad_dev(const sb_model_dev *mdl, int64_t B, const void *X, void
   return launch_finish(dtype, m, f, (hipStream_t)stream);
 }
 
+int32_t sb_quadform_dev(const sb_model_dev *mdl, int64_t B, const void *X, int32_t dtype, void *Y,
+                        void *qpart, int32_t *n_tiles, void *stream) {
+  int st = validate_model(mdl);
+  if (st) return st;
+  if (B < 0 || (B > 0 && (!X || !Y || !qpart))) return fail(SB_E_INVAL, "bad B / X / Y / qpart");
+  if (dtype != SB_DTYPE_F64 && dtype != SB_DTYPE_F32)
+    return fail(SB_E_INVAL, "dtype must be F64 or F32");
+  if (dtype == SB_DTYPE_F32 && (!mdl->prec_lp || !mdl->mu_lp))
+    return fail(SB_E_INVAL, "F32 needs prec_lp (FP32) and mu_lp");
+  if ((st = device_status())) return st;
+  Model m = model_from(mdl);
+  ASrc a;
+  a.kind = 0;
+  a.X = X;
+  a.ldx = m.d;
+  QuadOut o;
+  o.Y = Y;
+  o.ldy = (int64_t)m.K * m.d;
+  o.qpart = qpart;
+  TileCfg t = autotune_tiles(dtype, m, B, (hipStream_t)stream);
+  st = launch_quad_gemm(dtype, m, a, B, nullptr, o, t, (hipStream_t)stream);
+  if (n_tiles) *n_tiles = o.ntn;
+  return st;
+}
+
 // ------------------------------------------------------------------- HVP
 size_t sb_hvp_workspace_bytes(int32_t d, int32_t K, int64_t B) {
   if (d < 1 || K < 1 || B < 0) return 0;
@@ -611,6 +636,7 @@ int32_t sb_lbfgs_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m, int
     f.Y = Y;
     f.ldy = o.ldy;
     f.logl = lb.F;
+    f.logl_f64 = true;
     f.grad = lb.G;
     f.ldg = d;
     return launch_finish(dtype, md, f, s);
@@ -629,7 +655,7 @@ int32_t sb_lbfgs_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m, int
         return fail(SB_E_DEVICE, "count readback failed");
     }
   }
-  if ((st = launch_lbfgs_gather(lb, X, logl, grad, status, iters, s))) return st;
+  if ((st = launch_lbfgs_gather(lb, X, logl, false, grad, status, iters, s))) return st;
   if (n_evals) {
     if (hipMemcpyAsync(n_evals, lb.evals, 8, hipMemcpyDeviceToHost, s) || hipStreamSynchronize(s))
       return fail(SB_E_DEVICE, "eval count readback failed");
@@ -654,7 +680,7 @@ int32_t sb_dedup_dev(int32_t C, int32_t d, const void *X, const void *l, const u
   if (st) return st;
   Arena ar(workspace, ws_bytes);
   int n = 0;
-  st = dedup_run(C, d, X, l, valid, tau, dtype, rep_of, reps, max_reps, &n, ar,
+  st = dedup_run(C, d, X, dtype, l, dtype, valid, tau, rep_of, reps, max_reps, &n, ar,
                  (hipStream_t)stream);
   *n_reps = n;
   if (st == SB_E_CAPACITY) set_error("%d representatives exceed max_reps = %d", n, max_reps);

@@ -28,8 +28,8 @@ __device__ inline bool key_before(double la, int ia, double lb, int ib) {
   return (la > lb) || (la == lb && ia < ib);
 }
 
-template <typename T>
-__global__ __launch_bounds__(1024) void leader_kernel(int C, const T *l, const uint8_t *valid,
+template <typename TL>
+__global__ __launch_bounds__(1024) void leader_kernel(int C, const TL *l, const uint8_t *valid,
                                                       const int32_t *rep_of, int32_t *state,
                                                       int32_t *reps, int max_reps) {
   // state[0] = current leader (-1 none), state[1] = number of reps, state[2] = done flag
@@ -92,9 +92,9 @@ __global__ __launch_bounds__(256) void assign_kernel(int C, int d, const T *X, c
 
 size_t dedup_ws_bytes(int C) { return align_up(sizeof(int32_t) * 8) + 256; }
 
-int dedup_run(int C, int d, const void *X, const void *l, const uint8_t *valid, double tau,
-              int dtype, int32_t *rep_of, int32_t *reps, int max_reps, int *n_reps, Arena &ar,
-              hipStream_t s) {
+int dedup_run(int C, int d, const void *X, int x_dtype, const void *l, int l_dtype,
+              const uint8_t *valid, double tau, int32_t *rep_of, int32_t *reps, int max_reps,
+              int *n_reps, Arena &ar, hipStream_t s) {
   *n_reps = 0;
   if (C <= 0) return SB_OK;
   int32_t *state = ar.take<int32_t>(8);
@@ -107,17 +107,18 @@ int dedup_run(int C, int d, const void *X, const void *l, const uint8_t *valid, 
   const int chunk = 8;
   for (int round = 0; round <= C; round += chunk) {
     for (int k = 0; k < chunk; ++k) {
-      if (dtype == DT_F64) {
+      if (l_dtype == DT_F64)
         hipLaunchKernelGGL(leader_kernel<double>, dim3(1), dim3(1024), 0, s, C,
                            (const double *)l, valid, rep_of, state, reps, max_reps);
-        hipLaunchKernelGGL(assign_kernel<double>, dim3((unsigned)ceil_div(C, 4)), dim3(256), 0,
-                           s, C, d, (const double *)X, valid, rep_of, state, tau);
-      } else {
+      else
         hipLaunchKernelGGL(leader_kernel<float>, dim3(1), dim3(1024), 0, s, C, (const float *)l,
                            valid, rep_of, state, reps, max_reps);
+      if (x_dtype == DT_F64)
+        hipLaunchKernelGGL(assign_kernel<double>, dim3((unsigned)ceil_div(C, 4)), dim3(256), 0,
+                           s, C, d, (const double *)X, valid, rep_of, state, tau);
+      else
         hipLaunchKernelGGL(assign_kernel<float>, dim3((unsigned)ceil_div(C, 4)), dim3(256), 0, s,
                            C, d, (const float *)X, valid, rep_of, state, tau);
-      }
       SB_LAUNCH_CHECK();
     }
     SB_HIP(hipMemcpyAsync(host_state, state, sizeof(host_state), hipMemcpyDeviceToHost, s));

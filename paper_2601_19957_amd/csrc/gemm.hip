@@ -288,6 +288,10 @@ constexpr int kMaxK = 16;
 
 // One wave per row: q_k from the tile partials, the family's l, and (if
 // requested) the gradient -sum_k r_k Y_k (mixture) or -((nu+d)/(nu+q)) Y.
+// The scalar part (q_k sums, beta_k - q_k/2, logsumexp, responsibilities)
+// runs in FP64 for every operand type: l carries constants of size
+// ~(d/2) log 2 pi and (1/2) log det P, and the line search compares l values
+// whose difference is far below the FP32 spacing at that magnitude.
 template <typename T>
 __global__ __launch_bounds__(256) void finish_kernel(Model m, FinishArgs f) {
   const int64_t M = f.count ? (int64_t)(*f.count) : f.M;
@@ -300,45 +304,53 @@ __global__ __launch_bounds__(256) void finish_kernel(Model m, FinishArgs f) {
   const int64_t orow = f.outmap ? (int64_t)f.outmap[row] : row;
   T *gout = f.grad ? (T *)f.grad + (size_t)orow * f.ldg : nullptr;
   if (m.family == SB_FAMILY_STUDENT_T) {
-    T q = 0;
-    for (int t = 0; t < f.ntn; ++t) q += qp[t];
-    const T nd = (T)m.nu + (T)d;
-    T l = (T)(m.c - f.shift) + (T)m.beta[0] - (T)0.5 * nd * log1p(q / (T)m.nu);
+    double q = 0;
+    for (int t = 0; t < f.ntn; ++t) q += (double)qp[t];
+    const double nd = m.nu + (double)d;
+    const double l = m.c + m.beta[0] - 0.5 * nd * log1p(q / m.nu);
     if (lane == 0) {
-      ((T *)f.logl)[orow] = l;
-      if (f.aux) ((T *)f.aux)[row * K] = q;
+      if (f.logl_f64)
+        ((double *)f.logl)[orow] = l;
+      else
+        ((T *)f.logl)[orow] = (T)l;
+      if (f.aux) ((T *)f.aux)[row * K] = (T)q;
     }
     if (gout) {
-      const T sc = nd / ((T)m.nu + q);
+      const T sc = (T)(nd / (m.nu + q));
       for (int n = lane; n < d; n += 64) gout[n] = -sc * Y[n];
     }
     return;
   }
-  T a[kMaxK];
-  T mx = -INFINITY;
+  double a[kMaxK];
+  double mx = -INFINITY;
 #pragma unroll
   for (int k = 0; k < kMaxK; ++k) {
     if (k < K) {
-      T q = 0;
-      for (int t = 0; t < f.ntn; ++t) q += qp[k * f.ntn + t];
-      a[k] = (T)m.beta[k] - (T)0.5 * q;
+      double q = 0;
+      for (int t = 0; t < f.ntn; ++t) q += (double)qp[k * f.ntn + t];
+      a[k] = m.beta[k] - 0.5 * q;
       mx = fmax(mx, a[k]);
     }
   }
-  T lse;
+  double lse;
   if (K == 1) {
     lse = a[0];
   } else {
-    T ssum = 0;
+    double ssum = 0;
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k)
       if (k < K) ssum += exp(a[k] - mx);
     lse = mx + log(ssum);
   }
-  if (lane == 0) ((T *)f.logl)[orow] = (T)(m.c - f.shift) + lse;
+  if (lane == 0) {
+    if (f.logl_f64)
+      ((double *)f.logl)[orow] = m.c + lse;
+    else
+      ((T *)f.logl)[orow] = (T)(m.c + lse);
+  }
   T r[kMaxK];
 #pragma unroll
-  for (int k = 0; k < kMaxK; ++k) r[k] = (k < K) ? (K == 1 ? (T)1 : exp(a[k] - lse)) : (T)0;
+  for (int k = 0; k < kMaxK; ++k) r[k] = (k < K) ? (K == 1 ? (T)1 : (T)exp(a[k] - lse)) : (T)0;
   if (f.aux && lane < K) {
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k)

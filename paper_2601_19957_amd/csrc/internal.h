@@ -59,7 +59,7 @@ struct FinishArgs {
   void *grad = nullptr;             // [*][ldg] acc type (nullable)
   int64_t ldg = 0;
   void *aux = nullptr;              // [M][K]: responsibilities (mixture) / q (Student-t)
-  double shift = 0.0;               // subtracted from l (FP32 bulk keeps values small)
+  bool logl_f64 = false;            // l output is FP64 whatever the operand type
 };
 int launch_finish(int dtype, const Model &m, const FinishArgs &f, hipStream_t s);
 
@@ -111,7 +111,7 @@ struct LbfgsBuffers {
   int dtype = DT_F64;
   int64_t B = 0;
   int d = 0, m = 8;
-  void *X = nullptr, *G = nullptr, *F = nullptr;  // [2][B][d], [2][B][d], [2][B]
+  void *X = nullptr, *G = nullptr, *F = nullptr;  // [2][B][d], [2][B][d], [2][B] (F: FP64)
   void *Pd = nullptr;                             // [B][d]
   void *S = nullptr, *Yh = nullptr;               // [B][m][d]
   void *rho = nullptr, *yy = nullptr;             // [B][m]
@@ -126,15 +126,15 @@ int lbfgs_carve(Arena &ar, LbfgsBuffers &b);
 int launch_lbfgs_init(const LbfgsBuffers &b, const void *X0, hipStream_t s);
 int launch_lbfgs_step(const LbfgsBuffers &b, int max_iter, double grad_tol, hipStream_t s);
 int launch_compact(const LbfgsBuffers &b, hipStream_t s);
-int launch_lbfgs_gather(const LbfgsBuffers &b, void *X, void *logl, void *grad, int32_t *status,
-                        int32_t *iters, hipStream_t s);
+int launch_lbfgs_gather(const LbfgsBuffers &b, void *X, void *logl, bool logl_f64, void *grad,
+                        int32_t *status, int32_t *iters, hipStream_t s);
 int launch_two_loop(int64_t B, int d, int m, const int32_t *cnt, const void *S, const void *Y,
                     const void *G, void *P, int dtype, hipStream_t s);
 
 // Dedup (leader clustering).
-int dedup_run(int C, int d, const void *X, const void *l, const uint8_t *valid, double tau,
-              int dtype, int32_t *rep_of, int32_t *reps, int max_reps, int *n_reps, Arena &ar,
-              hipStream_t s);
+int dedup_run(int C, int d, const void *X, int x_dtype, const void *l, int l_dtype,
+              const uint8_t *valid, double tau, int32_t *rep_of, int32_t *reps, int max_reps,
+              int *n_reps, Arena &ar, hipStream_t s);
 size_t dedup_ws_bytes(int C);
 
 // Combine.

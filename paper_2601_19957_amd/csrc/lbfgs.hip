@@ -32,7 +32,8 @@ struct LbArgs {
   int64_t B;
   int d, m, max_iter;
   T tol;
-  T *X, *G, *F, *Pd, *S, *Yh, *rho, *yy, *alpha, *gtp;
+  T *X, *G, *Pd, *S, *Yh, *rho, *yy, *alpha, *gtp;
+  double *F;  // l at both slots, FP64 for every operand type
   int32_t *cur, *head, *cnt, *iters, *ls, *status, *phase, *rowid, *active;
 };
 
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
   int cur = a.cur[s];
   const int phase = a.phase[s];
   int cnt = a.cnt[s], head = a.head[s], it = a.iters[s];
-  const T lcur = a.F[(size_t)cur * B + s];
+  const double lcur = a.F[(size_t)cur * B + s];
 
   // ---- decide what this step does from the scalars alone
   enum { M_INIT, M_ACCEPT, M_BACKTRACK, M_RESET, M_STALL };
@@ -101,11 +102,11 @@ __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
   int lsn = 0;
   if (phase == PH_TRIAL) {
     const int tr = 1 - cur;
-    const T lt = a.F[(size_t)tr * B + s];
+    const double lt = a.F[(size_t)tr * B + s];
     alpha = a.alpha[s];
-    const T gtp_old = a.gtp[s];
-    const T fc = -lcur, ft = -lt;
-    if (isfinite(ft) && ft <= fc + (T)1e-4 * alpha * gtp_old) {
+    const double gtp_old = (double)a.gtp[s];
+    const double fc = -lcur, ft = -lt;
+    if (isfinite(ft) && ft <= fc + 1e-4 * (double)alpha * gtp_old) {
       mode = M_ACCEPT;
     } else {
       lsn = a.ls[s] + 1;
@@ -427,7 +428,7 @@ static LbArgs<T> make_args(const LbfgsBuffers &b, int max_iter, double tol) {
   a.tol = (T)tol;
   a.X = (T *)b.X;
   a.G = (T *)b.G;
-  a.F = (T *)b.F;
+  a.F = (double *)b.F;
   a.Pd = (T *)b.Pd;
   a.S = (T *)b.S;
   a.Yh = (T *)b.Yh;
@@ -499,7 +500,7 @@ int lbfgs_carve(Arena &ar, LbfgsBuffers &b) {
   auto take = [&](size_t n) -> void * { return (void *)ar.take<char>(n * es); };
   b.X = take(2 * B * d);
   b.G = take(2 * B * d);
-  b.F = take(2 * B);
+  b.F = (void *)ar.take<double>(2 * B);
   b.Pd = take(B * d);
   b.S = take(B * m * d);
   b.Yh = take(B * m * d);
@@ -596,9 +597,10 @@ int launch_compact(const LbfgsBuffers &b, hipStream_t s) {
 }
 
 template <typename T>
-__global__ void lbfgs_gather_kernel(int64_t B, int d, const T *X, const T *G, const T *F,
+__global__ void lbfgs_gather_kernel(int64_t B, int d, const T *X, const T *G, const double *F,
                                     const int32_t *cur, const int32_t *st, const int32_t *its,
-                                    T *Xo, T *lo, T *go, int32_t *sto, int32_t *ito) {
+                                    T *Xo, void *lo, bool lo_f64, T *go, int32_t *sto,
+                                    int32_t *ito) {
   const int64_t s = blockIdx.x;
   const int c = cur[s];
   for (int i = threadIdx.x; i < d; i += blockDim.x) {
@@ -606,24 +608,29 @@ __global__ void lbfgs_gather_kernel(int64_t B, int d, const T *X, const T *G, co
     if (go) go[(size_t)s * d + i] = G[((size_t)c * B + s) * d + i];
   }
   if (threadIdx.x == 0) {
-    if (lo) lo[s] = F[(size_t)c * B + s];
+    if (lo) {
+      if (lo_f64)
+        ((double *)lo)[s] = F[(size_t)c * B + s];
+      else
+        ((T *)lo)[s] = (T)F[(size_t)c * B + s];
+    }
     if (sto) sto[s] = st[s];
     if (ito) ito[s] = its[s];
   }
 }
 
-int launch_lbfgs_gather(const LbfgsBuffers &b, void *X, void *logl, void *grad, int32_t *status,
-                        int32_t *iters, hipStream_t s) {
+int launch_lbfgs_gather(const LbfgsBuffers &b, void *X, void *logl, bool logl_f64, void *grad,
+                        int32_t *status, int32_t *iters, hipStream_t s) {
   if (b.B <= 0) return SB_OK;
   if (b.dtype == DT_F64)
     hipLaunchKernelGGL(lbfgs_gather_kernel<double>, dim3((unsigned)b.B), dim3(256), 0, s, b.B,
                        b.d, (const double *)b.X, (const double *)b.G, (const double *)b.F, b.cur,
-                       b.status, b.iters, (double *)X, (double *)logl, (double *)grad, status,
+                       b.status, b.iters, (double *)X, logl, logl_f64, (double *)grad, status,
                        iters);
   else
     hipLaunchKernelGGL(lbfgs_gather_kernel<float>, dim3((unsigned)b.B), dim3(256), 0, s, b.B, b.d,
-                       (const float *)b.X, (const float *)b.G, (const float *)b.F, b.cur,
-                       b.status, b.iters, (float *)X, (float *)logl, (float *)grad, status,
+                       (const float *)b.X, (const float *)b.G, (const double *)b.F, b.cur,
+                       b.status, b.iters, (float *)X, logl, logl_f64, (float *)grad, status,
                        iters);
   SB_LAUNCH_CHECK();
   return SB_OK;

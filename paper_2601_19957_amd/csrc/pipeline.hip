@@ -179,7 +179,7 @@ struct Evaluator {
   }
   // rows: X rows (via rowmap if given), count: device count or null (M rows)
   int run(const ASrc &a, int64_t M, const int32_t *count, void *logl, void *grad, int64_t ldg,
-          const int32_t *outmap, void *aux, double shift, hipStream_t s, bool want_y = true) {
+          const int32_t *outmap, void *aux, bool logl_f64, hipStream_t s, bool want_y = true) {
     QuadOut o;
     o.Y = want_y ? Y : nullptr;
     o.ldy = ldy;
@@ -199,7 +199,7 @@ struct Evaluator {
     f.grad = grad;
     f.ldg = ldg;
     f.aux = aux;
-    f.shift = shift;
+    f.logl_f64 = logl_f64;
     return launch_finish(dtype, m, f, s);
   }
 };
@@ -333,7 +333,7 @@ static int carve_layout(Arena &ar, Layout &L, const sb_loglik *ll, const RunCfg 
   if (L.bulk.carve(ar)) return SB_E_NOMEM;
   L.X0b = mixed ? (void *)ar.take<float>((size_t)B * d) : (void *)L.X0;
   L.Xend = ar.take<char>(bes * (size_t)B * d);
-  L.lend = ar.take<char>(bes * (size_t)B);
+  L.lend = ar.take<double>((size_t)B);
   L.status = ar.take<int32_t>(B);
   L.counts = ar.take<int32_t>(8);
   L.valid = ar.take<uint8_t>(B);
@@ -391,7 +391,7 @@ size_t evidence_ws_bytes(const sb_loglik *ll, const sb_config *cfg) {
 // ------------------------------------------------------------ the path
 
 // Bulk L-BFGS over all starts in dtype of lb; X0 in that dtype.
-static int run_bulk(Layout &L, const RunCfg &rc, double tol, double shift, hipStream_t s,
+static int run_bulk(Layout &L, const RunCfg &rc, double tol, hipStream_t s,
                     int64_t *evals_out, int *steps_out) {
   LbfgsBuffers &lb = L.lb;
   Evaluator &ev = L.bulk;
@@ -403,7 +403,7 @@ static int run_bulk(Layout &L, const RunCfg &rc, double tol, double shift, hipSt
   a0.kind = 0;
   a0.X = lb.X;
   a0.ldx = d;
-  st = ev.run(a0, lb.B, nullptr, lb.F, lb.G, d, nullptr, nullptr, shift, s);
+  st = ev.run(a0, lb.B, nullptr, lb.F, lb.G, d, nullptr, nullptr, true, s);
   if (st) return st;
   ASrc at;
   at.kind = 0;
@@ -415,7 +415,7 @@ static int run_bulk(Layout &L, const RunCfg &rc, double tol, double shift, hipSt
     if (r) return r;
     r = launch_compact(lb, s);
     if (r) return r;
-    return ev.run(at, lb.B, lb.count, lb.F, lb.G, d, lb.idx, nullptr, shift, s);
+    return ev.run(at, lb.B, lb.count, lb.F, lb.G, d, lb.idx, nullptr, true, s);
   };
   int32_t *hcount = nullptr;
   SB_HIP(hipHostMalloc((void **)&hcount, sizeof(int32_t) * 4, hipHostMallocDefault));
@@ -481,7 +481,7 @@ static int run_bulk(Layout &L, const RunCfg &rc, double tol, double shift, hipSt
   *evals_out = ev_h;
   *steps_out = steps;
   if (rc_st) return rc_st;
-  return launch_lbfgs_gather(lb, L.Xend, L.lend, nullptr, L.status, nullptr, s);
+  return launch_lbfgs_gather(lb, L.Xend, L.lend, true, nullptr, L.status, nullptr, s);
 }
 
 // FP64 Newton polish + final Hessian/Cholesky/filters for reps [c0, c0+n).
@@ -500,7 +500,7 @@ static int polish_chunk(Layout &L, const Model &m64, const DevProblem &P, int n,
   if ((st = launch_fill_i32(n, 0, L.rejected, s))) return st;
   int32_t nact_h = 0;
   for (int it = 0; it < 20; ++it) {
-    if ((st = ev.run(a, n, nullptr, L.lp, L.Gp, d, nullptr, L.auxp, 0.0, s))) return st;
+    if ((st = ev.run(a, n, nullptr, L.lp, L.Gp, d, nullptr, L.auxp, true, s))) return st;
     *grad_evals += n;
     if ((st = launch_hessian_assemble(m64, n, (const double *)ev.Y, ev.ldy, L.auxp, L.Gp, L.H, s)))
       return st;
@@ -516,7 +516,7 @@ static int polish_chunk(Layout &L, const Model &m64, const DevProblem &P, int n,
     if (nact_h == 0) break;
   }
   // final point: l, grad, Hessian, Cholesky, log det, filters
-  if ((st = ev.run(a, n, nullptr, L.lp, L.Gp, d, nullptr, L.auxp, 0.0, s))) return st;
+  if ((st = ev.run(a, n, nullptr, L.lp, L.Gp, d, nullptr, L.auxp, true, s))) return st;
   *grad_evals += n;
   if ((st = launch_hessian_assemble(m64, n, (const double *)ev.Y, ev.ldy, L.auxp, L.Gp, L.H, s)))
     return st;
@@ -617,7 +617,7 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
       a.n_pts = rc.n_pts;
       const int64_t NP = (int64_t)rc.R * rc.n_pts;
       L.disc.tile = default_tiles(ddt, d, NP);
-      if ((st = L.disc.run(a, NP, nullptr, L.lpts, nullptr, 0, nullptr, nullptr, 0.0, s, false)))
+      if ((st = L.disc.run(a, NP, nullptr, L.lpts, nullptr, 0, nullptr, nullptr, false, s, false)))
         return st;
     }
     if ((st = launch_ray_argmax(rc.R, rc.n_pts, ddt, L.lpts, L.best_l, L.best_j, s))) return st;
@@ -629,7 +629,6 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     // ---------------- A3-A5 bulk L-BFGS
     Model mb = m64;
     double tol = rc.grad_tol > 0 ? rc.grad_tol : 1e-10;
-    double shift = 0.0;
     if (mixed) {
       mb.mu32 = L.mu32;
       mb.Plp = L.P32;
@@ -642,10 +641,6 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
         maxabs_theta = std::max(maxabs_theta, std::max(std::fabs(hlo[i]), std::fabs(hhi[i])));
       tol = 32.0 * 5.9604644775390625e-08 * pmax * (1.0 + maxabs_theta);
       if (rc.grad_tol > 0) tol = std::max(tol, rc.grad_tol);
-      // keep FP32 values near the modes small: subtract the largest beta
-      std::vector<double> hb(K);
-      SB_HIP(hipMemcpy(hb.data(), L.beta, sizeof(double) * K, hipMemcpyDeviceToHost));
-      shift = P.c + *std::max_element(hb.begin(), hb.end());
       if ((st = launch_cast_f64_f32((int64_t)rc.n_starts * d, L.X0, (float *)L.X0b, s)))
         return st;
     }
@@ -654,21 +649,17 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     L.bulk.tile = default_tiles(L.bulk.dtype, d, rc.n_starts);
     int64_t bulk_evals = 0;
     int steps = 0;
-    if ((st = run_bulk(L, rc, tol, shift, s, &bulk_evals, &steps))) return st;
+    if ((st = run_bulk(L, rc, tol, s, &bulk_evals, &steps))) return st;
     tm.mark(s);  // 3
     // ---------------- A7 pre-dedup
     const int64_t B = rc.n_starts;
     if ((st = launch_fill_i32(8, 0, L.counts, s))) return st;
-    if (mixed)
-      hipLaunchKernelGGL(candidate_flags_kernel<float>, dim3((unsigned)ceil_div(B, 256)),
-                         dim3(256), 0, s, B, L.status, (const float *)L.lend, L.valid, L.counts);
-    else
-      hipLaunchKernelGGL(candidate_flags_kernel<double>, dim3((unsigned)ceil_div(B, 256)),
-                         dim3(256), 0, s, B, L.status, (const double *)L.lend, L.valid, L.counts);
+    hipLaunchKernelGGL(candidate_flags_kernel<double>, dim3((unsigned)ceil_div(B, 256)),
+                       dim3(256), 0, s, B, L.status, (const double *)L.lend, L.valid, L.counts);
     SB_LAUNCH_CHECK();
     int nrep = 0;
-    st = dedup_run((int)B, d, L.Xend, L.lend, L.valid, rc.dedup_tol_pre, L.lb.dtype, L.rep_of,
-                   L.reps, rc.cap_pre, &nrep, L.dedup_ar, s);
+    st = dedup_run((int)B, d, L.Xend, L.lb.dtype, L.lend, DT_F64, L.valid, rc.dedup_tol_pre,
+                   L.rep_of, L.reps, rc.cap_pre, &nrep, L.dedup_ar, s);
     if (st == SB_E_CAPACITY) {
       set_error("%d representatives after the pre-polish dedup exceed the polish capacity %d",
                 nrep, rc.cap_pre);
@@ -709,8 +700,8 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     }
     Arena ar2(L.dedup_ar.base, L.dedup_ar.cap);
     int nm = 0;
-    st = dedup_run(nrep, d, L.XA, L.lA, L.okA, tau, DT_F64, L.rep2_of, L.rep2, rc.cap_pre, &nm,
-                   ar2, s);
+    st = dedup_run(nrep, d, L.XA, DT_F64, L.lA, DT_F64, L.okA, tau, L.rep2_of, L.rep2,
+                   rc.cap_pre, &nm, ar2, s);
     if (st && st != SB_E_CAPACITY) return st;
     // ---------------- A10 combine
     int32_t hcounts[8];
