@@ -233,10 +233,258 @@ __global__ __launch_bounds__(256) void quad_gemm_kernel(GemmParams g) {
 int quad_gemm_ntn(int dtype, int d, TileCfg t) { return (int)ceil_div(d, t.bn); }
 
 template <typename TIn, typename TOp, int BM, int BN, int BK>
-static int launch_t(const GemmParams &p, hipStream_t s) {
+static int launch_scalar(const GemmParams &p, hipStream_t s) {
   dim3 grid((unsigned)ceil_div(p.M, BM), (unsigned)(p.K * p.ntn));
   if (grid.x == 0 || grid.y == 0) return SB_OK;
   hipLaunchKernelGGL((quad_gemm_kernel<TIn, TOp, BM, BN, BK>), grid, dim3(256), 0, s, p);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// ------------------------------------------------------- vectorised GEMM
+//
+// Same tile, fragment and epilogue layout as quad_gemm_kernel, for d a
+// multiple of the 16-byte vector widths: every thread owns fixed A rows and
+// B rows for the whole K loop (row pointers and the row map resolved once),
+// loads 16-byte vectors, and prefetches k-tile t+1 into registers while the
+// MFMAs of tile t run from LDS.
+
+template <typename T>
+struct V16;
+template <>
+struct V16<double> {
+  typedef double v __attribute__((ext_vector_type(2)));
+  static constexpr int N = 2;
+};
+template <>
+struct V16<float> {
+  typedef float v __attribute__((ext_vector_type(4)));
+  static constexpr int N = 4;
+};
+template <>
+struct V16<bf16_t> {
+  typedef uint16_t v __attribute__((ext_vector_type(8)));
+  static constexpr int N = 8;
+};
+
+template <typename TIn, typename TOp, int BM, int BN, int BK, int KIND>
+__global__ __launch_bounds__(256) void quad_gemm_vec_kernel(GemmParams g) {
+  using MF = Mfma<TOp>;
+  using TAcc = typename MF::acc_t;
+  using accv = typename MF::accv;
+  using VI = typename V16<TIn>::v;
+  using VO = typename V16<TOp>::v;
+  constexpr int NI = V16<TIn>::N, NO = V16<TOp>::N;
+  constexpr int PAD = (sizeof(TOp) == 8) ? 2 : (sizeof(TOp) == 4 ? 4 : 8);
+  constexpr int LDA = BK + PAD;
+  constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+  constexpr int VRA = BK / NI, VRB = BK / NO;
+  constexpr int NA = BM * VRA / 256, NB = BN * VRB / 256;
+  static_assert(NA >= 1 && NB >= 1 && (BM * VRA) % 256 == 0 && (BN * VRB) % 256 == 0, "tile");
+  static_assert(256 % VRA == 0 && 256 % VRB == 0, "tile");
+  __shared__ __attribute__((aligned(16))) TOp As[BM * LDA];
+  __shared__ __attribute__((aligned(16))) TOp Bs[BN * LDA];
+  __shared__ TAcc qs[2][BM];
+
+  const int64_t M = g.count ? (int64_t)(*g.count) : g.M;
+  const int64_t m0 = (int64_t)blockIdx.x * BM;
+  if (m0 >= M) return;
+  const int k = blockIdx.y / g.ntn;
+  const int n0 = (blockIdx.y % g.ntn) * BN;
+  const int d = g.d;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const TIn *mu = g.a.zero_mu ? nullptr : (const TIn *)g.mu + (size_t)k * d;
+  const TOp *Pk = (const TOp *)g.P + (size_t)k * d * d;
+
+  // fixed rows of this thread
+  const int ca = tid % VRA, cb = tid % VRB;
+  const TIn *arow[NA];
+  const TIn *qrow_p[NA];
+  TIn tpar[NA];
+  bool aok[NA];
+#pragma unroll
+  for (int r = 0; r < NA; ++r) {
+    const int i = (tid + 256 * r) / VRA;
+    const int64_t row = m0 + i;
+    aok[r] = row < M;
+    arow[r] = nullptr;
+    qrow_p[r] = nullptr;
+    tpar[r] = 0;
+    if (aok[r]) {
+      if constexpr (KIND == 0) {
+        const int64_t src = g.a.rowmap ? (int64_t)g.a.rowmap[row] : row;
+        arow[r] = (const TIn *)g.a.X + src * g.a.ldx;
+      } else {
+        const int64_t ray = row / g.a.n_pts;
+        const int jj = (int)(row % g.a.n_pts);
+        tpar[r] = ((TIn)jj + (TIn)0.5) / (TIn)g.a.n_pts;
+        arow[r] = (const TIn *)g.a.P0 + ray * d;
+        qrow_p[r] = (const TIn *)g.a.P1 + ray * d;
+      }
+    }
+  }
+  const TOp *brow[NB];
+  bool bok[NB];
+#pragma unroll
+  for (int r = 0; r < NB; ++r) {
+    const int n = (tid + 256 * r) / VRB;
+    bok[r] = (n0 + n) < d;
+    brow[r] = Pk + (size_t)(n0 + n) * d;
+  }
+
+  VI ra[NA], rq[NA], rmu;
+  VO rb[NB];
+  auto zero_i = []() {
+    VI z;
+#pragma unroll
+    for (int e = 0; e < NI; ++e) z[e] = (TIn)0;
+    return z;
+  };
+  auto zero_o = []() {
+    VO z;
+#pragma unroll
+    for (int e = 0; e < NO; ++e) z[e] = 0;
+    return z;
+  };
+  auto load = [&](int k0) {
+    const int ka = k0 + ca * NI;
+    const bool kin = ka < d;
+#pragma unroll
+    for (int r = 0; r < NA; ++r) {
+      const bool ok = aok[r] && kin;
+      ra[r] = ok ? *(const VI *)(arow[r] + ka) : zero_i();
+      if constexpr (KIND == 1) rq[r] = ok ? *(const VI *)(qrow_p[r] + ka) : zero_i();
+    }
+    rmu = (mu && kin) ? *(const VI *)(mu + ka) : zero_i();
+    const int kb = k0 + cb * NO;
+    const bool kbin = kb < d;
+#pragma unroll
+    for (int r = 0; r < NB; ++r) rb[r] = (bok[r] && kbin) ? *(const VO *)(brow[r] + kb) : zero_o();
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int r = 0; r < NA; ++r) {
+      const int i = (tid + 256 * r) / VRA;
+      TOp *dst = &As[i * LDA + ca * NI];
+#pragma unroll
+      for (int e = 0; e < NI; ++e) {
+        TIn x;
+        if constexpr (KIND == 0) {
+          x = ra[r][e];
+        } else {
+#pragma clang fp contract(off)
+          x = ra[r][e] + tpar[r] * (rq[r][e] - ra[r][e]);
+        }
+        const TIn v = aok[r] ? x - rmu[e] : (TIn)0;
+        if constexpr (sizeof(TOp) == 8)
+          dst[e] = v;
+        else
+          dst[e] = to_op<TOp>((float)v);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      const int n = (tid + 256 * r) / VRB;
+      *(VO *)&Bs[n * LDA + cb * NO] = rb[r];
+    }
+  };
+
+  accv acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = accv{0, 0, 0, 0};
+
+  load(0);
+  for (int k0 = 0; k0 < d; k0 += BK) {
+    store();
+    __syncthreads();
+    if (k0 + BK < d) load(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += MF::KPI) {
+      const int kl = kk + MF::KPL * (lane >> 4);
+      const TOp *af[TM];
+      const TOp *bfp[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[i] = &As[(wm * WM + i * 16 + (lane & 15)) * LDA + kl];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bfp[j] = &Bs[(wn * WN + j * 16 + (lane & 15)) * LDA + kl];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(af[i], bfp[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+
+  // Epilogue (as in quad_gemm_kernel): store Y, partial q per row for this tile.
+  const int lr = lane >> 4, lc = lane & 15;
+  TAcc qrow[TM][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) qrow[i][v] = 0;
+  TAcc *Y = (TAcc *)g.Y;
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int il = wm * WM + i * 16 + MF::row(lr, v);
+      const int64_t row = m0 + il;
+      if (row >= M) continue;
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = n0 + wn * WN + j * 16 + lc;
+        if (n >= d) continue;
+        TAcc yv = acc[i][j][v];
+        if (Y) Y[row * g.ldy + (int64_t)k * d + n] = yv;
+        TIn x = point_value<TIn>(g.a, row, d, n);
+        TAcc dl = (TAcc)(mu ? x - mu[n] : x);
+        qrow[i][v] += dl * yv;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      TAcc t = qrow[i][v];
+      t += __shfl_xor(t, 1, 64);
+      t += __shfl_xor(t, 2, 64);
+      t += __shfl_xor(t, 4, 64);
+      t += __shfl_xor(t, 8, 64);
+      qrow[i][v] = t;
+    }
+  if (lc == 0) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) qs[wn][wm * WM + i * 16 + MF::row(lr, v)] = qrow[i][v];
+  }
+  __syncthreads();
+  if (g.qpart) {
+    TAcc *qp = (TAcc *)g.qpart;
+    for (int i = tid; i < BM; i += 256) {
+      int64_t row = m0 + i;
+      if (row < M) qp[(row * g.K + k) * g.ntn + (blockIdx.y % g.ntn)] = qs[0][i] + qs[1][i];
+    }
+  }
+}
+
+template <typename TIn, typename TOp, int BM, int BN, int BK>
+static int launch_t(const GemmParams &p, hipStream_t s) {
+  dim3 grid((unsigned)ceil_div(p.M, BM), (unsigned)(p.K * p.ntn));
+  if (grid.x == 0 || grid.y == 0) return SB_OK;
+  // vector path: 16-byte aligned rows of X (or ray endpoints), mu and P
+  const bool vec = (p.d % V16<TIn>::N == 0) && (p.d % V16<TOp>::N == 0) &&
+                   (p.a.kind == 1 || p.a.ldx % V16<TIn>::N == 0);
+  if (vec && p.a.kind == 0)
+    hipLaunchKernelGGL((quad_gemm_vec_kernel<TIn, TOp, BM, BN, BK, 0>), grid, dim3(256), 0, s, p);
+  else if (vec)
+    hipLaunchKernelGGL((quad_gemm_vec_kernel<TIn, TOp, BM, BN, BK, 1>), grid, dim3(256), 0, s, p);
+  else
+    return launch_scalar<TIn, TOp, BM, BN, BK>(p, s);
   SB_LAUNCH_CHECK();
   return SB_OK;
 }
