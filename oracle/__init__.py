@@ -42,7 +42,8 @@ class _Config(C.Structure):
     _fields_ = [("n_rays", C.c_int32), ("n_points", C.c_int32), ("n_starts", C.c_int32),
                 ("m", C.c_int32), ("max_iter", C.c_int32), ("max_modes", C.c_int32),
                 ("grad_tol", C.c_double), ("dedup_tol", C.c_double),
-                ("dedup_tol_pre", C.c_double), ("seed", C.c_uint64), ("n_threads", C.c_int32)]
+                ("dedup_tol_pre", C.c_double), ("seed", C.c_uint64), ("n_threads", C.c_int32),
+                ("problem", C.c_uint32)]
 
 
 class _Result(C.Structure):
@@ -335,13 +336,15 @@ def _result(st, r, d, cap, modes, mlz, mll, ldh) -> OracleResult:
                         r.n_reps_pre)
 
 
-def evidence(prob, cfg, n_threads: int = 0, n_starts: Optional[int] = None) -> OracleResult:
-    """Run the whole path on the CPU.  ``n_starts`` overrides cfg.n_starts (fewer rays too)."""
+def evidence(prob, cfg, n_threads: int = 0, n_starts: Optional[int] = None,
+             problem: int = 0) -> OracleResult:
+    """Run the whole path on the CPU.  ``n_starts`` overrides cfg.n_starts (fewer rays too);
+    ``problem`` is the problem's index within a batch (Philox counter word 3)."""
     op = OracleProblem(prob)
     ns = cfg.n_starts if n_starts is None else n_starts
     nr = cfg.n_rays if n_starts is None else max(ns, cfg.n_rays * ns // cfg.n_starts)
     c = _Config(nr, cfg.n_points, ns, cfg.m, cfg.max_iter, cfg.max_modes, cfg.grad_tol,
-                cfg.dedup_tol, cfg.dedup_tol_pre, cfg.seed, n_threads)
+                cfg.dedup_tol, cfg.dedup_tol_pre, cfg.seed, n_threads, problem)
     cap = cfg.max_modes
     d = prob.d
     modes = np.zeros((cap, d))

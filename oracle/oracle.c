@@ -849,7 +849,8 @@ int32_t or_evidence(const or_problem *p, const double *lo, const double *hi, con
   res->n_logl_evals = (int64_t)R * cfg->n_points;
   res->n_grad_evals = 0;
   res->n_hess_evals = 0;
-  st = or_discover(p, beta, lo, hi, R, cfg->n_points, ns, cfg->seed, 0u, rbl, rbj, sray, X);
+  st = or_discover(p, beta, lo, hi, R, cfg->n_points, ns, cfg->seed, cfg->problem, rbl, rbj, sray,
+                   X);
   if (st == OR_OK) {
     const int32_t max_iter = cfg->max_iter > 0 ? cfg->max_iter : 10 * d + 200;
     const double tol = cfg->grad_tol > 0 ? cfg->grad_tol : 1e-10;

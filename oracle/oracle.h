@@ -50,6 +50,7 @@ typedef struct {
   double dedup_tol_pre; /* pre-polish dedup radius (<=0: 0.25) */
   uint64_t seed;
   int32_t n_threads;    /* OpenMP threads for per-start work (<=0: all) */
+  uint32_t problem;     /* problem index within a batch: Philox counter word 3 */
 } or_config;
 
 typedef struct {

@@ -218,7 +218,14 @@ def sb_evidence(prob, cfg) -> EvidenceResult:
 
 
 def sb_evidence_batch(probs: Sequence, cfgs: Sequence) -> list:
+    """Evidence of independent problems in one batched run (host arrays).
+
+    Returns one result per problem; a problem without modes has status
+    E_NOMODE, one over its capacity E_CAPACITY (log Z NaN).  Errors that stop
+    the whole batch (invalid input, device failure) raise SbError."""
     n = len(probs)
+    if n != len(cfgs):
+        raise ValueError("one config per problem")
     hps = [_HostProblem(p) for p in probs]
     LL = (sb_loglik * n)(*[h.ll for h in hps])
     BX = (sb_box * n)(*[h.box for h in hps])
@@ -229,14 +236,16 @@ def sb_evidence_batch(probs: Sequence, cfgs: Sequence) -> list:
         r, arrs = _new_result(cfgs[j].max_modes, probs[j].d)
         RS[j] = r
         keep.append(arrs)
-    lib().sb_evidence_batch(n, LL, BX, CF, RS)
+    st_all = lib().sb_evidence_batch(n, LL, BX, CF, RS)
+    if st_all not in (OK, E_NOMODE, E_CAPACITY):
+        raise SbError(st_all, "sb_evidence_batch")
     out = []
     for j in range(n):
         st = OK
-        if RS[j].n_modes == 0 and RS[j].log_z == -math.inf:
+        if RS[j].log_z == -math.inf:
             st = E_NOMODE
         elif math.isnan(RS[j].log_z):
-            st = E_INVAL
+            st = E_CAPACITY
         out.append(_to_result(st, RS[j], cfgs[j].max_modes, keep[j]))
     return out
 

@@ -315,12 +315,30 @@ int32_t sb_evidence_batch(int32_t n, const sb_loglik *ll, const sb_box *box,
                           const sb_config *cfg, sb_result *res) {
   if (n < 0 || (n > 0 && (!ll || !box || !cfg || !res)))
     return fail(SB_E_INVAL, "invalid batch arguments");
-  int first_err = SB_OK;
+  if (n == 0) return SB_OK;
+  for (int j = 0; j < n; ++j) res[j].log_z = NAN;
   for (int j = 0; j < n; ++j) {
-    int st = sb_evidence(&ll[j], &box[j], &cfg[j], &res[j]);
-    if (st && st != SB_E_NOMODE && first_err == SB_OK) first_err = st;
+    int st = validate_shape(&ll[j]);
+    if (!st) st = validate_cfg(&ll[j], &cfg[j]);
+    if (!st) st = validate_box_host(ll[j].d, box[j].lo, box[j].hi);
+    if (!st) st = validate_arrays_host(&ll[j]);
+    if (!st && (cfg[j].precision != cfg[0].precision || cfg[j].m != cfg[0].m))
+      st = fail(SB_E_INVAL, "every problem of a batch needs the same precision and m");
+    if (st) {
+      char msg[512];
+      snprintf(msg, sizeof(msg), "problem %d: %s", j, sb::last_error());
+      return fail(st, "%s", msg);
+    }
   }
-  return first_err;
+  int st = device_status();
+  if (st) return st;
+  hipStream_t s;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+    return fail(SB_E_DEVICE, "stream creation failed");
+  st = sb::run_evidence_batch(n, ll, box, cfg, res, s);
+  (void)hipStreamSynchronize(s);
+  (void)hipStreamDestroy(s);
+  return st;
 }
 
 // ------------------------------------------------------------------ prep

@@ -80,6 +80,7 @@ struct GemmParams {
   void *Y;
   int64_t ldy;
   void *qpart;
+  GroupView gv;  // grouped mode only
 };
 
 // Value of point `row` at coordinate j (type TIn), without the mean.
@@ -267,7 +268,7 @@ struct V16<bf16_t> {
   static constexpr int N = 8;
 };
 
-template <typename TIn, typename TOp, int BM, int BN, int BK, int KIND>
+template <typename TIn, typename TOp, int BM, int BN, int BK, int KIND, bool GROUP>
 __global__ __launch_bounds__(256) void quad_gemm_vec_kernel(GemmParams g) {
   using MF = Mfma<TOp>;
   using TAcc = typename MF::acc_t;
@@ -286,16 +287,81 @@ __global__ __launch_bounds__(256) void quad_gemm_vec_kernel(GemmParams g) {
   __shared__ __attribute__((aligned(16))) TOp Bs[BN * LDA];
   __shared__ TAcc qs[2][BM];
 
-  const int64_t M = g.count ? (int64_t)(*g.count) : g.M;
-  const int64_t m0 = (int64_t)blockIdx.x * BM;
-  if (m0 >= M) return;
-  const int k = blockIdx.y / g.ntn;
-  const int n0 = (blockIdx.y % g.ntn) * BN;
-  const int d = g.d;
+  // ---- tile context: rows [m0, M) (global row indices), component k, columns n0..
+  int64_t M, m0;
+  int k, nt, ntn, d, n_pts;
+  const TIn *mu;
+  const TOp *Pk;
+  const TIn *X0 = (const TIn *)g.a.X;      // kind 0 rows / kind 1 ray start points
+  const TIn *X1 = (const TIn *)g.a.P1;     // kind 1 ray end points
+  int64_t pt_first = 0, roff = 0;          // kind 1: first point row, endpoint base
+  int64_t ybase = 0, qbase = 0;            // grouped: packed Y / q-partial bases
+  int64_t ystr = 0, qstr = 0;              // grouped: Y / q-partial row strides
+  if constexpr (!GROUP) {
+    M = g.count ? (int64_t)(*g.count) : g.M;
+    m0 = (int64_t)blockIdx.x * BM;
+    if (m0 >= M) return;
+    ntn = g.ntn;
+    k = blockIdx.y / ntn;
+    nt = blockIdx.y % ntn;
+    d = g.d;
+    n_pts = g.a.n_pts;
+    mu = g.a.zero_mu ? nullptr : (const TIn *)g.mu + (size_t)k * d;
+    Pk = (const TOp *)g.P + (size_t)k * d * d;
+    if constexpr (KIND == 1) X0 = (const TIn *)g.a.P0;
+  } else {
+    const GroupView &gv = g.gv;
+    const int sgi = gv.tile_seg[blockIdx.x];
+    const GSeg sg = gv.segs[sgi];
+    const BatchProb pr = gv.probs[sg.prob];
+    const int64_t rows = gv.counts ? (int64_t)gv.counts[sgi] : (int64_t)sg.rows;
+    m0 = sg.row0 + (int64_t)gv.tile_idx[blockIdx.x] * BM;
+    M = sg.row0 + rows;
+    if (m0 >= M) return;
+    d = pr.dp;
+    ntn = (d + BN - 1) / BN;
+    if ((int)blockIdx.y >= pr.K * ntn) return;
+    k = blockIdx.y / ntn;
+    nt = blockIdx.y % ntn;
+    n_pts = pr.n_pts;
+    mu = g.a.zero_mu ? nullptr : (const TIn *)gv.mu + pr.mu_off + (size_t)k * d;
+    Pk = (const TOp *)gv.P + pr.P_off + (size_t)k * d * d;
+    // packed Y / q-partial rows of this segment
+    ystr = (int64_t)pr.K * d;
+    qstr = (int64_t)pr.K * ntn;
+    ybase = sg.yoff - sg.row0 * ystr;
+    qbase = sg.qoff - sg.row0 * qstr;
+    if constexpr (KIND == 1) {
+      X0 = (const TIn *)g.a.P0;
+      pt_first = sg.row0;
+      roff = pr.roff0;
+    }
+  }
+  const int n0 = nt * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const TIn *mu = g.a.zero_mu ? nullptr : (const TIn *)g.mu + (size_t)k * d;
-  const TOp *Pk = (const TOp *)g.P + (size_t)k * d * d;
+
+  // Row pointers of global row `row`: its X row (kind 0) or its ray's two
+  // endpoints and parameter t (kind 1).
+  auto row_src = [&](int64_t row, const TIn *&a, const TIn *&b, TIn &t) {
+    if constexpr (KIND == 0) {
+      int64_t off;
+      if constexpr (GROUP)
+        off = g.gv.rowoff[row];
+      else
+        off = (g.a.rowmap ? (int64_t)g.a.rowmap[row] : row) * g.a.ldx;
+      a = X0 + off;
+      b = nullptr;
+      t = 0;
+    } else {
+      const int64_t i = row - pt_first;
+      const int64_t ray = i / n_pts;
+      const int jj = (int)(i % n_pts);
+      t = ((TIn)jj + (TIn)0.5) / (TIn)n_pts;
+      a = X0 + roff + ray * d;
+      b = X1 + roff + ray * d;
+    }
+  };
 
   // fixed rows of this thread
   const int ca = tid % VRA, cb = tid % VRB;
@@ -311,18 +377,7 @@ __global__ __launch_bounds__(256) void quad_gemm_vec_kernel(GemmParams g) {
     arow[r] = nullptr;
     qrow_p[r] = nullptr;
     tpar[r] = 0;
-    if (aok[r]) {
-      if constexpr (KIND == 0) {
-        const int64_t src = g.a.rowmap ? (int64_t)g.a.rowmap[row] : row;
-        arow[r] = (const TIn *)g.a.X + src * g.a.ldx;
-      } else {
-        const int64_t ray = row / g.a.n_pts;
-        const int jj = (int)(row % g.a.n_pts);
-        tpar[r] = ((TIn)jj + (TIn)0.5) / (TIn)g.a.n_pts;
-        arow[r] = (const TIn *)g.a.P0 + ray * d;
-        qrow_p[r] = (const TIn *)g.a.P1 + ray * d;
-      }
-    }
+    if (aok[r]) row_src(row, arow[r], qrow_p[r], tpar[r]);
   }
   const TOp *brow[NB];
   bool bok[NB];
@@ -418,7 +473,7 @@ __global__ __launch_bounds__(256) void quad_gemm_vec_kernel(GemmParams g) {
     __syncthreads();
   }
 
-  // Epilogue (as in quad_gemm_kernel): store Y, partial q per row for this tile.
+  // Epilogue: store Y, partial q per row for this tile's columns.
   const int lr = lane >> 4, lc = lane & 15;
   TAcc qrow[TM][4];
 #pragma unroll
@@ -426,6 +481,7 @@ __global__ __launch_bounds__(256) void quad_gemm_vec_kernel(GemmParams g) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) qrow[i][v] = 0;
   TAcc *Y = (TAcc *)g.Y;
+  const int64_t ystride = GROUP ? ystr : g.ldy;
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
 #pragma unroll
@@ -433,13 +489,22 @@ __global__ __launch_bounds__(256) void quad_gemm_vec_kernel(GemmParams g) {
       const int il = wm * WM + i * 16 + MF::row(lr, v);
       const int64_t row = m0 + il;
       if (row >= M) continue;
+      const TIn *pa, *pb;
+      TIn tt;
+      row_src(row, pa, pb, tt);
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int n = n0 + wn * WN + j * 16 + lc;
         if (n >= d) continue;
         TAcc yv = acc[i][j][v];
-        if (Y) Y[row * g.ldy + (int64_t)k * d + n] = yv;
-        TIn x = point_value<TIn>(g.a, row, d, n);
+        if (Y) Y[ybase + row * ystride + (int64_t)k * d + n] = yv;
+        TIn x;
+        if constexpr (KIND == 0) {
+          x = pa[n];
+        } else {
+#pragma clang fp contract(off)
+          x = pa[n] + tt * (pb[n] - pa[n]);
+        }
         TAcc dl = (TAcc)(mu ? x - mu[n] : x);
         qrow[i][v] += dl * yv;
       }
@@ -466,8 +531,12 @@ __global__ __launch_bounds__(256) void quad_gemm_vec_kernel(GemmParams g) {
   if (g.qpart) {
     TAcc *qp = (TAcc *)g.qpart;
     for (int i = tid; i < BM; i += 256) {
-      int64_t row = m0 + i;
-      if (row < M) qp[(row * g.K + k) * g.ntn + (blockIdx.y % g.ntn)] = qs[0][i] + qs[1][i];
+      const int64_t row = m0 + i;
+      if (row >= M) continue;
+      if constexpr (GROUP)
+        qp[qbase + row * qstr + (int64_t)k * ntn + nt] = qs[0][i] + qs[1][i];
+      else
+        qp[(row * g.K + k) * g.ntn + nt] = qs[0][i] + qs[1][i];
     }
   }
 }
@@ -480,9 +549,9 @@ static int launch_t(const GemmParams &p, hipStream_t s) {
   const bool vec = (p.d % V16<TIn>::N == 0) && (p.d % V16<TOp>::N == 0) &&
                    (p.a.kind == 1 || p.a.ldx % V16<TIn>::N == 0);
   if (vec && p.a.kind == 0)
-    hipLaunchKernelGGL((quad_gemm_vec_kernel<TIn, TOp, BM, BN, BK, 0>), grid, dim3(256), 0, s, p);
+    hipLaunchKernelGGL((quad_gemm_vec_kernel<TIn, TOp, BM, BN, BK, 0, false>), grid, dim3(256), 0, s, p);
   else if (vec)
-    hipLaunchKernelGGL((quad_gemm_vec_kernel<TIn, TOp, BM, BN, BK, 1>), grid, dim3(256), 0, s, p);
+    hipLaunchKernelGGL((quad_gemm_vec_kernel<TIn, TOp, BM, BN, BK, 1, false>), grid, dim3(256), 0, s, p);
   else
     return launch_scalar<TIn, TOp, BM, BN, BK>(p, s);
   SB_LAUNCH_CHECK();
@@ -873,6 +942,298 @@ int launch_fill_i32(int64_t n, int32_t v, int32_t *p, hipStream_t s) {
   if (n <= 0) return SB_OK;
   hipLaunchKernelGGL(fill_i32, dim3((unsigned)std::min<int64_t>(8192, ceil_div(n, 256))),
                      dim3(256), 0, s, n, v, p);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+}  // namespace sb
+
+// ====================================================================
+// Batched (grouped) variants: many problems of uneven dimension, each
+// M-tile belonging to one problem; see BatchProb.
+namespace sb {
+
+int launch_quad_gemm_group(int dtype, const BatchDev &b, const GroupView &gv_in, const void *A0,
+                           const void *A1, int64_t n_tiles, void *Y, void *qpart, TileCfg t,
+                           hipStream_t s) {
+  if (n_tiles <= 0) return SB_OK;
+  GemmParams p{};
+  p.a.kind = gv_in.kind;
+  p.a.X = A0;
+  p.a.P0 = A0;
+  p.a.P1 = A1;
+  p.Y = Y;
+  p.qpart = qpart;
+  p.gv = gv_in;
+  const int bn = (t.bn == 64) ? 64 : 128;
+  const int bm = (t.bm == 64) ? 64 : 128;
+  dim3 grid((unsigned)n_tiles, (unsigned)(b.K_max * ceil_div(b.dp_max, bn)));
+  if (dtype == DT_F64) {
+    p.gv.mu = b.mu64;
+    p.gv.P = b.P64;
+  } else if (dtype == DT_F32) {
+    p.gv.mu = b.mu32;
+    p.gv.P = b.P32;
+  } else {
+    p.gv.mu = b.mu32;
+    p.gv.P = b.Pbf;
+  }
+#define SB_GG(TI, TO, BMv, BNv, BKv)                                                             \
+  do {                                                                                           \
+    if (p.a.kind == 0)                                                                           \
+      hipLaunchKernelGGL((quad_gemm_vec_kernel<TI, TO, BMv, BNv, BKv, 0, true>), grid, dim3(256), \
+                         0, s, p);                                                               \
+    else                                                                                         \
+      hipLaunchKernelGGL((quad_gemm_vec_kernel<TI, TO, BMv, BNv, BKv, 1, true>), grid, dim3(256), \
+                         0, s, p);                                                               \
+  } while (0)
+  if (dtype == DT_F64) {
+    if (bm == 64 && bn == 64) SB_GG(double, double, 64, 64, 16);
+    else if (bm == 128 && bn == 64) SB_GG(double, double, 128, 64, 16);
+    else if (bm == 64) SB_GG(double, double, 64, 128, 16);
+    else SB_GG(double, double, 128, 128, 16);
+  } else if (dtype == DT_F32) {
+    if (bm == 64 && bn == 64) SB_GG(float, float, 64, 64, 16);
+    else if (bm == 128 && bn == 64) SB_GG(float, float, 128, 64, 16);
+    else if (bm == 64) SB_GG(float, float, 64, 128, 16);
+    else SB_GG(float, float, 128, 128, 16);
+  } else {
+    if (bm == 64 && bn == 64) SB_GG(float, bf16_t, 64, 64, 32);
+    else if (bm == 128 && bn == 64) SB_GG(float, bf16_t, 128, 64, 32);
+    else if (bm == 64) SB_GG(float, bf16_t, 64, 128, 32);
+    else SB_GG(float, bf16_t, 128, 128, 32);
+  }
+#undef SB_GG
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// Segment of global row r: the last segment whose row0 <= r.
+__device__ inline int find_seg(const GSeg *segs, int n, int64_t r) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].row0 <= r)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Row epilogue for a batch (one wave per row), same arithmetic as
+// finish_kernel.  l -> F[fidx[r]] / F[r] (FP64) or lout[r] (type T);
+// gradient -> grad + goff[r] (or r * ldg); aux -> aux + r * auxs.
+template <typename T>
+__global__ __launch_bounds__(256) void finish_group_kernel(BatchDev b, FinishGroupArgs f) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= f.nrows) return;
+  const int sgi = find_seg(f.segs, f.nseg, row);
+  const GSeg sg = f.segs[sgi];
+  const int64_t rows = f.counts ? (int64_t)f.counts[sgi] : (int64_t)sg.rows;
+  if (row - sg.row0 >= rows) return;
+  const BatchProb pr = b.probs[sg.prob];
+  const int d = pr.dp, K = pr.K;
+  const int ntn = (d + f.bn - 1) / f.bn;
+  const int64_t rl = row - sg.row0;
+  const T *qp = (const T *)f.qpart + sg.qoff + rl * (int64_t)K * ntn;
+  const T *Y = f.Y ? (const T *)f.Y + sg.yoff + rl * (int64_t)K * d : nullptr;
+  const double *beta = b.beta + pr.beta_off;
+  T *gout = nullptr;
+  if (f.grad) gout = (T *)f.grad + (f.goff ? f.goff[row] : row * (int64_t)f.ldg);
+  auto put_l = [&](double l) {
+    if (lane != 0) return;
+    if (f.F)
+      f.F[f.fidx ? (int64_t)f.fidx[row] : row] = l;
+    else
+      ((T *)f.lout)[row] = (T)l;
+  };
+  if (pr.family == SB_FAMILY_STUDENT_T) {
+    double q = 0;
+    for (int t = 0; t < ntn; ++t) q += (double)qp[t];
+    const double nd = pr.nu + (double)pr.d;
+    put_l(pr.c + beta[0] - 0.5 * nd * log1p(q / pr.nu));
+    if (f.aux && lane == 0) ((T *)f.aux)[row * f.auxs] = (T)q;
+    if (gout) {
+      const T sc = (T)(nd / (pr.nu + q));
+      for (int n = lane; n < d; n += 64) gout[n] = -sc * Y[n];
+    }
+    return;
+  }
+  double a[kMaxK];
+  double mx = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) {
+    if (k < K) {
+      double q = 0;
+      for (int t = 0; t < ntn; ++t) q += (double)qp[k * ntn + t];
+      a[k] = beta[k] - 0.5 * q;
+      mx = fmax(mx, a[k]);
+    }
+  }
+  double lse;
+  if (K == 1) {
+    lse = a[0];
+  } else {
+    double ssum = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+      if (k < K) ssum += exp(a[k] - mx);
+    lse = mx + log(ssum);
+  }
+  put_l(pr.c + lse);
+  T r[kMaxK];
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) r[k] = (k < K) ? (K == 1 ? (T)1 : (T)exp(a[k] - lse)) : (T)0;
+  if (f.aux && lane < K) {
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+      if (k == lane) ((T *)f.aux)[row * f.auxs + k] = r[k];
+  }
+  if (gout) {
+    for (int n = lane; n < d; n += 64) {
+      T s = 0;
+#pragma unroll
+      for (int k = 0; k < kMaxK; ++k)
+        if (k < K) s += r[k] * Y[(size_t)k * d + n];
+      gout[n] = -s;
+    }
+  }
+}
+
+int launch_finish_group(int dtype, const BatchDev &b, const FinishGroupArgs &f, hipStream_t s) {
+  if (b.K_max > kMaxK) {
+    set_error("K=%d exceeds the supported %d components", b.K_max, kMaxK);
+    return SB_E_UNSUPPORTED;
+  }
+  if (f.nrows <= 0 || f.nseg <= 0) return SB_OK;
+  dim3 grid((unsigned)ceil_div(f.nrows, 4));
+  if (dtype == DT_F64)
+    hipLaunchKernelGGL(finish_group_kernel<double>, grid, dim3(256), 0, s, b, f);
+  else
+    hipLaunchKernelGGL(finish_group_kernel<float>, grid, dim3(256), 0, s, b, f);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// Hessian H = -nabla^2 l of row c (its segment's problem), true dimension
+// d_p, leading dimension d_p, at H + hoff[c]; Y rows packed by segment,
+// aux rows of stride auxs, gradient rows of stride gs.  Symmetrised.
+__global__ __launch_bounds__(256) void hessian_group_kernel(BatchDev b, const GSeg *segs,
+                                                             int nseg, int C, const double *Y,
+                                                             const double *aux, int64_t auxs,
+                                                             const double *grad, int64_t gs,
+                                                             const int64_t *hoff, double *H) {
+  const int c = blockIdx.z;
+  if (c >= C) return;
+  const GSeg sg = segs[find_seg(segs, nseg, c)];
+  const BatchProb pr = b.probs[sg.prob];
+  const int d = pr.d, dp = pr.dp;
+  const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
+  const int j = blockIdx.x * 16 + (threadIdx.x & 15);
+  if (i >= d || j >= d) return;
+  const double *y = Y + sg.yoff + (int64_t)(c - sg.row0) * pr.K * dp;
+  const double *P = b.P64 + pr.P_off;
+  auto entry = [&](int a, int bb) -> double {
+    if (pr.family == SB_FAMILY_STUDENT_T) {
+      const double q = aux[(size_t)c * auxs];
+      const double nd = pr.nu + pr.d, den = pr.nu + q;
+      return (nd / den) * P[(size_t)a * dp + bb] - (2.0 * nd / (den * den)) * y[a] * y[bb];
+    }
+    const double *g = grad + (size_t)c * gs;
+    double s = g[a] * g[bb];
+    for (int k = 0; k < pr.K; ++k) {
+      const double rk = aux[(size_t)c * auxs + k];
+      const double *u = y + (size_t)k * dp;
+      s += rk * (P[(size_t)k * dp * dp + (size_t)a * dp + bb] - u[a] * u[bb]);
+    }
+    return s;
+  };
+  H[hoff[c] + (size_t)i * d + j] = 0.5 * (entry(i, j) + entry(j, i));
+}
+
+int launch_hessian_group(const BatchDev &b, const GSeg *segs, int nseg, int C, const double *Y,
+                         const double *aux, int64_t auxs, const double *grad, int64_t gs,
+                         const int64_t *hoff, double *H, int d_max, hipStream_t s) {
+  if (C <= 0) return SB_OK;
+  dim3 grid((unsigned)ceil_div(d_max, 16), (unsigned)ceil_div(d_max, 16), (unsigned)C);
+  hipLaunchKernelGGL(hessian_group_kernel, grid, dim3(256), 0, s, b, segs, nseg, C, Y, aux, auxs,
+                     grad, gs, hoff, H);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// beta_k of every problem (one thread per component).
+__global__ void beta_group_kernel(BatchDev b, const double *log_w, const double *logdetP,
+                                  double *beta) {
+  const int p = blockIdx.x;
+  const BatchProb pr = b.probs[p];
+  const int k = threadIdx.x;
+  if (k >= pr.K) return;
+  const double d = pr.d;
+  const int64_t o = pr.beta_off + k;
+  double v = 0.0;
+  if (pr.family == SB_FAMILY_GAUSS_MIX) {
+    v = log_w ? log_w[o] : 0.0;
+    if (pr.norm == SB_NORM_DENSITY) v += 0.5 * logdetP[o] - 0.5 * d * kLog2Pi;
+  } else if (pr.norm == SB_NORM_DENSITY) {
+    v = lgamma(0.5 * (pr.nu + d)) - lgamma(0.5 * pr.nu) - 0.5 * d * log(pr.nu * M_PI) +
+        0.5 * logdetP[o];
+  }
+  beta[o] = v;
+}
+
+int launch_beta_group(const BatchDev &b, const double *log_w, const double *logdetP,
+                      double *beta, hipStream_t s) {
+  hipLaunchKernelGGL(beta_group_kernel, dim3(b.n), dim3(64 * (int)ceil_div(b.K_max, 64)), 0, s,
+                     b, log_w, logdetP, beta);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// Per component: max |P| (for the FP32 tolerance) and the symmetry flag, in
+// the padded layout (padding is zero and symmetric).  grid (chunks, components).
+__global__ __launch_bounds__(256) void maxabs_sym_group_kernel(BatchDev b, const int32_t *comp_prob,
+                                                               const int32_t *comp_k, double *mx,
+                                                               int32_t *bad) {
+  const int c = blockIdx.y;
+  const BatchProb pr = b.probs[comp_prob[c]];
+  const int dp = pr.dp;
+  const double *P = b.P64 + pr.P_off + (size_t)comp_k[c] * dp * dp;
+  __shared__ double red[4];
+  const int64_t n = (int64_t)dp * dp;
+  double m = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    m = fmax(m, fabs(P[e]));
+  m = block_max<256>(m, red);
+  if (threadIdx.x == 0) mx[(size_t)c * gridDim.x + blockIdx.x] = m;
+}
+__global__ __launch_bounds__(256) void sym_group_kernel(BatchDev b, const int32_t *comp_prob,
+                                                        const int32_t *comp_k, const double *mx,
+                                                        int chunks, int32_t *bad) {
+  const int c = blockIdx.y;
+  const BatchProb pr = b.probs[comp_prob[c]];
+  const int dp = pr.dp;
+  const double *P = b.P64 + pr.P_off + (size_t)comp_k[c] * dp * dp;
+  double m = 0.0;
+  for (int t = 0; t < chunks; ++t) m = fmax(m, mx[(size_t)c * chunks + t]);
+  const int64_t n = (int64_t)dp * dp;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    const int i = (int)(e / dp), j = (int)(e % dp);
+    if (j <= i) continue;
+    if (!(fabs(P[e] - P[(size_t)j * dp + i]) <= 1e-12 * m)) bad[0] = 1;
+  }
+}
+
+int launch_check_group(const BatchDev &b, int ncomp, const int32_t *comp_prob,
+                       const int32_t *comp_k, double *mx, int chunks, int32_t *bad,
+                       hipStream_t s) {
+  if (ncomp <= 0) return SB_OK;
+  hipLaunchKernelGGL(maxabs_sym_group_kernel, dim3(chunks, ncomp), dim3(256), 0, s, b, comp_prob,
+                     comp_k, mx, bad);
+  hipLaunchKernelGGL(sym_group_kernel, dim3(chunks, ncomp), dim3(256), 0, s, b, comp_prob, comp_k,
+                     mx, chunks, bad);
   SB_LAUNCH_CHECK();
   return SB_OK;
 }

@@ -17,6 +17,58 @@ struct Model {
   double nu = 0.0, c = 0.0;       // Student-t dof, additive constant
 };
 
+// ------------------------------------------------------------------ batches
+// A batch of n independent problems laid out side by side in packed arrays.
+// Problem p's vectors have length dp = d rounded up to a multiple of 8; the
+// padding of every vector, mean and precision row is exactly zero and stays
+// zero through the GEMM (zero P rows/columns) and the optimiser (zero
+// gradient there).  A single problem is a batch of one.
+struct BatchProb {
+  int d = 0, dp = 0, K = 0, family = 0, norm = 0, n_pts = 0;
+  double nu = 0.0, c = 0.0;
+  int64_t P_off = 0;     // packed P: component k of p at P_off + k*dp*dp
+  int64_t mu_off = 0;    // packed mu: P's component k at mu_off + k*dp
+  int64_t beta_off = 0;  // packed beta / log det P: beta_off + k
+  int64_t box_off = 0;   // packed lo/hi: box_off + i, i < dp (padding unused)
+  int64_t s0 = 0, B = 0, voff0 = 0;           // starts: global index, count, vector offset
+  int64_t r0 = 0, R = 0, roff0 = 0, pt0 = 0;  // rays: global index, count, endpoint offset, first point row
+  uint64_t seed = 0;                          // Philox key of this problem's rays
+  int32_t index = 0;                          // problem number (Philox counter word 3)
+};
+
+// Device tables of a batch (all device pointers).
+struct BatchDev {
+  int n = 0;                          // problems
+  const BatchProb *probs = nullptr;   // [n]
+  int64_t Btot = 0, Ltot = 0;         // starts, sum of B_p * dp_p
+  int64_t Rtot = 0, RLtot = 0, NPtot = 0;  // rays, sum R_p * dp_p, sum R_p * n_pts_p
+  int dp_max = 0, K_max = 0;
+  const double *P64 = nullptr, *mu64 = nullptr, *beta = nullptr, *lo = nullptr, *hi = nullptr;
+  const float *P32 = nullptr, *mu32 = nullptr;
+  const bf16_t *Pbf = nullptr;
+};
+
+// A row segment of a grouped GEMM: rows [row0, row0 + rows) all belong to
+// problem `prob`; their Y rows (K*dp each) start at element yoff and their
+// q-partial rows (K*ntn each, ntn = ceil(dp / bn)) at element qoff.
+struct GSeg {
+  int32_t prob = 0, rows = 0;
+  int64_t row0 = 0, yoff = 0, qoff = 0;
+};
+
+// Grouped GEMM view: each M-tile belongs to one segment (static table).
+struct GroupView {
+  const BatchProb *probs = nullptr;
+  const GSeg *segs = nullptr;
+  int nseg = 0;
+  const int32_t *tile_seg = nullptr;   // [grid.x] segment of the M-tile
+  const int32_t *tile_idx = nullptr;   // [grid.x] tile index within the segment
+  const int32_t *counts = nullptr;     // [nseg] active rows per segment (nullable: segs[].rows)
+  int kind = 0;                        // 0: rows of X (rowoff), 1: ray points of the problem
+  const int64_t *rowoff = nullptr;     // kind 0: global row -> element offset of its X row
+  const void *mu = nullptr, *P = nullptr;  // packed mu / P in the GEMM's input / operand types
+};
+
 // Source of the A operand (the points) of the quadratic-form GEMM.
 struct ASrc {
   int kind = 0;                   // 0: rows of X; 1: ray points p + t (q - p)
@@ -120,11 +172,75 @@ struct LbfgsBuffers {
   int32_t *status = nullptr, *phase = nullptr, *rowid = nullptr, *active = nullptr;
   int32_t *idx = nullptr, *count = nullptr;       // compacted rows, [B] and [1]
   int64_t *evals = nullptr;                       // [1]
+  // batches: per-start vector offset/length, total vector length, trial row
+  // offsets (per start) and their compacted copy (per compacted row)
+  const int64_t *voff = nullptr;
+  const int32_t *vdim = nullptr;
+  int64_t Ltot = 0;
+  int64_t *rowoff = nullptr, *croff = nullptr;
+  // batches: problem of each start, per-problem gradient tolerance and
+  // iteration cap (nullable: the launch's scalars), per-problem evaluations
+  const int32_t *sprob = nullptr;
+  const double *ptol = nullptr;
+  const int32_t *pmaxit = nullptr;
+  int64_t *pevals = nullptr;
 };
+
+// Per-problem compaction of a batch's active starts: rows of problem p land
+// at s0_p + i (i < counts[p]) in idx (F index) and croff (row offsets).
+int launch_compact_group(const BatchDev &b, const LbfgsBuffers &lb, int32_t *counts,
+                         hipStream_t s);
+int launch_lbfgs_init_group(const LbfgsBuffers &b, const void *X0, hipStream_t s);
+int launch_lbfgs_gather_group(const LbfgsBuffers &b, void *X, double *logl, int32_t *status,
+                              hipStream_t s);
+
+// Grouped GEMM and its epilogue over a batch.
+struct FinishGroupArgs {
+  const GSeg *segs = nullptr;        // row segments (as given to the GEMM)
+  int nseg = 0;
+  int64_t nrows = 0;                 // rows spanned by the segments
+  const int32_t *counts = nullptr;   // per-segment active rows (nullable: all)
+  const void *qpart = nullptr;
+  int bn = 128;                      // GEMM column tile (n-tiles per component = ceil(dp/bn))
+  const void *Y = nullptr;
+  double *F = nullptr;               // l (FP64): F[fidx[row]] (with fidx) or F[row]
+  const int32_t *fidx = nullptr;
+  void *lout = nullptr;              // l in the operand type at lout[row] when F is null
+  void *grad = nullptr;              // gradient rows at goff[row] (or row * ldg)
+  const int64_t *goff = nullptr;
+  int64_t ldg = 0;
+  void *aux = nullptr;               // responsibilities / q, row stride auxs
+  int64_t auxs = 0;
+};
+int launch_quad_gemm_group(int dtype, const BatchDev &b, const GroupView &gv, const void *A0,
+                           const void *A1, int64_t n_tiles, void *Y, void *qpart, TileCfg t,
+                           hipStream_t s);
+// q-partial columns per row of a problem of padded dimension dp (tile bn).
+inline int group_ntn(int dp, int bn) { return (dp + bn - 1) / bn; }
+int launch_finish_group(int dtype, const BatchDev &b, const FinishGroupArgs &f, hipStream_t s);
+int launch_hessian_group(const BatchDev &b, const GSeg *segs, int nseg, int C, const double *Y,
+                         const double *aux, int64_t auxs, const double *grad, int64_t gs,
+                         const int64_t *hoff, double *H, int d_max, hipStream_t s);
+int launch_beta_group(const BatchDev &b, const double *log_w, const double *logdetP,
+                      double *beta, hipStream_t s);
+int launch_check_group(const BatchDev &b, int ncomp, const int32_t *comp_prob,
+                       const int32_t *comp_k, double *mx, int chunks, int32_t *bad,
+                       hipStream_t s);
+int chol_batched_u(int C, const int32_t *nv, const int64_t *off, int n_max, double *L,
+                   int32_t *info, hipStream_t s);
+int launch_logdet_u(int C, const int32_t *nv, const int64_t *off, const double *L,
+                    const int32_t *info, double *logdet, hipStream_t s);
+int launch_chol_solve_u(int C, const int32_t *nv, const int64_t *off, int n_max, const double *L,
+                        const double *b, double *x, int64_t vs, const int32_t *info,
+                        hipStream_t s);
 size_t lbfgs_state_bytes(int dtype, int64_t B, int d, int m);
 int lbfgs_carve(Arena &ar, LbfgsBuffers &b);
 int launch_lbfgs_init(const LbfgsBuffers &b, const void *X0, hipStream_t s);
 int launch_lbfgs_step(const LbfgsBuffers &b, int max_iter, double grad_tol, hipStream_t s);
+// Steps of starts [s_begin, s_begin + count) only, dispatched for vectors of
+// length at most d_class (batches sorted by dimension launch once per class).
+int launch_lbfgs_step_range(const LbfgsBuffers &b, int64_t s_begin, int64_t count, int d_class,
+                            double grad_tol, int max_iter, hipStream_t s);
 int launch_compact(const LbfgsBuffers &b, hipStream_t s);
 int launch_lbfgs_gather(const LbfgsBuffers &b, void *X, void *logl, bool logl_f64, void *grad,
                         int32_t *status, int32_t *iters, hipStream_t s);
@@ -142,6 +258,10 @@ int launch_combine(int n, int d, const double *lo, const double *hi, const doubl
                    const double *logdet, const double *modes, int32_t *order, double *mode_log_z,
                    double *log_z, hipStream_t s);
 
+// Whole path over a batch of n problems (host inputs; one stream).
+int run_evidence_batch(int n, const sb_loglik *ll, const sb_box *box, const sb_config *cfg,
+                       sb_result *res, hipStream_t s);
+
 // Whole path (device inputs), and its workspace size.
 struct DevProblem {
   int family, norm, d, K;
@@ -155,4 +275,25 @@ size_t evidence_ws_bytes(const sb_loglik *ll, const sb_config *cfg);
 // Autotuner: tile choice for the quadratic-form GEMM (cached per shape class).
 TileCfg autotune_tiles(int dtype, const Model &m, int64_t M, hipStream_t s);
 
+}  // namespace sb
+
+namespace sb {
+// Batched discovery, dedup and combine (see rays.hip, dedup.hip).
+int launch_rays_group(const BatchDev &b, double *P0, double *P1, float *P0f, float *P1f,
+                      hipStream_t s);
+int launch_ray_argmax_group(const BatchDev &b, int dtype, const void *l, double *best_l,
+                            int32_t *best_j, hipStream_t s);
+int launch_topn_group(const BatchDev &b, const double *best_l, int32_t *start_ray, hipStream_t s);
+int launch_gather_starts_group(const BatchDev &b, const int32_t *start_ray, const int32_t *best_j,
+                               const double *P0, const double *P1, void *X0, int dtype,
+                               hipStream_t s);
+int dedup_group_run(int n, int64_t Ctot, const int64_t *cfirst, const int64_t *ccount,
+                    const BatchProb *probs, const void *X, int x_dtype, const int64_t *xoff,
+                    const double *l, const uint8_t *valid, const double *ptau, int32_t *rep_of,
+                    const int64_t *rbase, const int32_t *rcap, int32_t *reps, int32_t *state,
+                    int64_t max_rounds, hipStream_t s);
+int launch_combine_group(const BatchDev &b, const int32_t *state, const int64_t *rbase,
+                         const int32_t *rcap, const int32_t *reps, const double *l,
+                         const double *logdet, const double *X, const int64_t *xoff,
+                         int32_t *order, double *mlz, double *log_z, hipStream_t s);
 }  // namespace sb

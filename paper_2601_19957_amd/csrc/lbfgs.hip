@@ -35,6 +35,18 @@ struct LbArgs {
   T *X, *G, *Pd, *S, *Yh, *rho, *yy, *alpha, *gtp;
   double *F;  // l at both slots, FP64 for every operand type
   int32_t *cur, *head, *cnt, *iters, *ls, *status, *phase, *rowid, *active;
+  // per-start vector offset and length (nullable: s * d and d), and the
+  // element offset of each start's trial row (nullable)
+  const int64_t *voff;
+  const int32_t *vdim;
+  int64_t *rowoff;
+  int64_t Ltot;
+  // batches: problem of each start, per-problem tolerance and iteration cap
+  // (nullable: tol / max_iter), and the first start of this launch
+  const int32_t *sprob;
+  const double *ptol;
+  const int32_t *pmaxit;
+  int64_t s_base;
 };
 
 // Two-loop recursion on register-resident history (logical order, oldest
@@ -81,15 +93,25 @@ __device__ inline void two_loop(const T (&Sr)[kMaxHist][EPT], const T (&Yr)[kMax
 
 template <typename T, int TPB, int EPT>
 __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
-  const int64_t s = blockIdx.x;
+  const int64_t s = a.s_base + blockIdx.x;
   const int tid = threadIdx.x;
   __shared__ T red[4 * (TPB / 64)];
   if (a.status[s] != ST_ACTIVE) {
     if (tid == 0) a.active[s] = 0;
     return;
   }
-  const int d = a.d, m = a.m;
+  const int m = a.m;
+  const int d = a.vdim ? a.vdim[s] : a.d;
+  const int64_t vo = a.voff ? a.voff[s] : (int64_t)s * a.d;
+  const int64_t Lt = a.Ltot;
   const int64_t B = a.B;
+  T tol = a.tol;
+  int max_iter = a.max_iter;
+  if (a.sprob) {
+    const int p = a.sprob[s];
+    tol = (T)a.ptol[p];
+    max_iter = a.pmaxit[p];
+  }
   int cur = a.cur[s];
   const int phase = a.phase[s];
   int cnt = a.cnt[s], head = a.head[s], it = a.iters[s];
@@ -126,9 +148,9 @@ __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
   }
   if (mode == M_BACKTRACK) {
     const int tr = 1 - cur;
-    const T *xc = a.X + ((size_t)cur * B + s) * d;
-    T *xt = a.X + ((size_t)tr * B + s) * d;
-    const T *pd = a.Pd + (size_t)s * d;
+    const T *xc = a.X + (size_t)cur * Lt + vo;
+    T *xt = a.X + (size_t)tr * Lt + vo;
+    const T *pd = a.Pd + vo;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int i = e * TPB + tid;
@@ -139,6 +161,7 @@ __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
       a.ls[s] = lsn;
       a.active[s] = 1;
       a.rowid[s] = (int32_t)((size_t)tr * B + s);
+      if (a.rowoff) a.rowoff[s] = (int64_t)tr * Lt + vo;
     }
     return;
   }
@@ -147,10 +170,10 @@ __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
   T x[EPT], gl[EPT], sv[EPT], yv[EPT];
   const int newcur = (mode == M_ACCEPT) ? 1 - cur : cur;
   {
-    const T *xn = a.X + ((size_t)newcur * B + s) * d;
-    const T *gn = a.G + ((size_t)newcur * B + s) * d;
-    const T *xo = a.X + ((size_t)cur * B + s) * d;
-    const T *go = a.G + ((size_t)cur * B + s) * d;
+    const T *xn = a.X + (size_t)newcur * Lt + vo;
+    const T *gn = a.G + (size_t)newcur * Lt + vo;
+    const T *xo = a.X + (size_t)cur * Lt + vo;
+    const T *go = a.G + (size_t)cur * Lt + vo;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int i = e * TPB + tid;
@@ -176,8 +199,8 @@ __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
     for (int e = 0; e < EPT; ++e) Sr[j][e] = Yr[j][e] = 0;
     if (mode == M_ACCEPT && j < cnt) {
       const int ph = (head - cnt + j + 2 * m) % m;
-      const T *Sp = a.S + ((size_t)s * m + ph) * d;
-      const T *Yp = a.Yh + ((size_t)s * m + ph) * d;
+      const T *Sp = a.S + (size_t)m * vo + (size_t)ph * d;
+      const T *Yp = a.Yh + (size_t)m * vo + (size_t)ph * d;
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         const int i = e * TPB + tid;
@@ -204,8 +227,8 @@ __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
     ++it;
     if (sy > (T)1e-10 * sqrt(ss) * sqrt(yy)) {
       // store the pair in the ring and append it to the logical history
-      T *Sp = a.S + ((size_t)s * m + head) * d;
-      T *Yp = a.Yh + ((size_t)s * m + head) * d;
+      T *Sp = a.S + (size_t)m * vo + (size_t)head * d;
+      T *Yp = a.Yh + (size_t)m * vo + (size_t)head * d;
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         const int i = e * TPB + tid;
@@ -263,9 +286,9 @@ __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
   int newst = ST_ACTIVE;
   if (mode == M_INIT && !(isfinite(lcur) && isfinite(gn)))
     newst = ST_DEAD;
-  else if (gn <= a.tol)
+  else if (gn <= tol)
     newst = ST_CONVERGED;
-  else if (it >= a.max_iter)
+  else if (it >= max_iter)
     newst = ST_MAXITER;
   if (newst != ST_ACTIVE) {
     if (tid == 0) {
@@ -317,8 +340,8 @@ __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
     gtp = block_sum<TPB>(t, red);
   }
   const int tr = 1 - cur;
-  T *xt = a.X + ((size_t)tr * B + s) * d;
-  T *pd = a.Pd + (size_t)s * d;
+  T *xt = a.X + (size_t)tr * Lt + vo;
+  T *pd = a.Pd + vo;
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int i = e * TPB + tid;
@@ -338,6 +361,7 @@ __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
     a.phase[s] = PH_TRIAL;
     a.active[s] = 1;
     a.rowid[s] = (int32_t)((size_t)tr * B + s);
+    if (a.rowoff) a.rowoff[s] = (int64_t)tr * Lt + vo;
   }
 }
 
@@ -445,6 +469,14 @@ static LbArgs<T> make_args(const LbfgsBuffers &b, int max_iter, double tol) {
   a.phase = b.phase;
   a.rowid = b.rowid;
   a.active = b.active;
+  a.voff = b.voff;
+  a.vdim = b.vdim;
+  a.rowoff = b.rowoff;
+  a.Ltot = b.voff ? b.Ltot : b.B * (int64_t)b.d;
+  a.sprob = b.sprob;
+  a.ptol = b.ptol;
+  a.pmaxit = b.pmaxit;
+  a.s_base = 0;
   return a;
 }
 
@@ -459,6 +491,31 @@ int launch_lbfgs_step(const LbfgsBuffers &b, int max_iter, double grad_tol, hipS
     SB_LB_CASES(lbfgs_step_kernel, double, a);
   } else {
     LbArgs<float> a = make_args<float>(b, max_iter, grad_tol);
+    SB_LB_CASES(lbfgs_step_kernel, float, a);
+  }
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+int launch_lbfgs_step_range(const LbfgsBuffers &b, int64_t s_begin, int64_t count, int d_class,
+                            double grad_tol, int max_iter, hipStream_t s) {
+  int st = check_d(d_class, b.m);
+  if (st) return st;
+  if (count <= 0) return SB_OK;
+  if (s_begin < 0 || s_begin + count > b.B) {
+    set_error("start range [%lld, %lld) outside [0, %lld)", (long long)s_begin,
+              (long long)(s_begin + count), (long long)b.B);
+    return SB_E_INVAL;
+  }
+  const int d = d_class;
+  const int64_t B = count;
+  if (b.dtype == DT_F64) {
+    LbArgs<double> a = make_args<double>(b, max_iter, grad_tol);
+    a.s_base = s_begin;
+    SB_LB_CASES(lbfgs_step_kernel, double, a);
+  } else {
+    LbArgs<float> a = make_args<float>(b, max_iter, grad_tol);
+    a.s_base = s_begin;
     SB_LB_CASES(lbfgs_step_kernel, float, a);
   }
   SB_LAUNCH_CHECK();
@@ -632,6 +689,119 @@ int launch_lbfgs_gather(const LbfgsBuffers &b, void *X, void *logl, bool logl_f6
                        (const float *)b.X, (const float *)b.G, (const double *)b.F, b.cur,
                        b.status, b.iters, (float *)X, logl, logl_f64, (float *)grad, status,
                        iters);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+}  // namespace sb
+
+// ====================================================================
+// Batches: per-problem compaction, layout-preserving init and gather.
+namespace sb {
+
+// One workgroup per problem: active starts of [s0, s0 + B) in start order.
+__global__ __launch_bounds__(1024) void compact_group_kernel(const BatchProb *probs,
+                                                             const int32_t *active,
+                                                             const int32_t *rowid,
+                                                             const int64_t *rowoff, int32_t *idx,
+                                                             int64_t *croff, int32_t *counts,
+                                                             int64_t *evals) {
+  __shared__ int32_t sc[1024];
+  const BatchProb pr = probs[blockIdx.x];
+  const int t = threadIdx.x;
+  const int64_t B = pr.B, s0 = pr.s0;
+  const int64_t per = (B + 1023) / 1024;
+  const int64_t b0 = s0 + (int64_t)t * per, b1 = std::min<int64_t>(s0 + B, b0 + per);
+  int32_t c = 0;
+  for (int64_t i = b0; i < b1; ++i) c += active[i] ? 1 : 0;
+  sc[t] = c;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int32_t v = (t >= o) ? sc[t - o] : 0;
+    __syncthreads();
+    sc[t] += v;
+    __syncthreads();
+  }
+  int64_t pos = s0 + sc[t] - c;
+  for (int64_t i = b0; i < b1; ++i)
+    if (active[i]) {
+      idx[pos] = rowid[i];
+      croff[pos] = rowoff[i];
+      ++pos;
+    }
+  if (t == 1023) {
+    counts[blockIdx.x] = sc[1023];
+    evals[blockIdx.x] += sc[1023];  // one workgroup per problem: no race
+  }
+}
+
+int launch_compact_group(const BatchDev &b, const LbfgsBuffers &lb, int32_t *counts,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(compact_group_kernel, dim3(b.n), dim3(1024), 0, s, b.probs, lb.active,
+                     lb.rowid, lb.rowoff, lb.idx, lb.croff, counts, lb.pevals);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+template <typename T>
+__global__ void lbfgs_init_group_kernel(int64_t B, int64_t L, const T *X0, T *X, int32_t *cur,
+                                        int32_t *head, int32_t *cnt, int32_t *iters, int32_t *ls,
+                                        int32_t *status, int32_t *phase, int64_t *evals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = i; e < L; e += stride) X[e] = X0[e];
+  for (int64_t e = i; e < B; e += stride) {
+    cur[e] = 0;
+    head[e] = 0;
+    cnt[e] = 0;
+    iters[e] = 0;
+    ls[e] = 0;
+    status[e] = ST_ACTIVE;
+    phase[e] = PH_INIT;
+  }
+  if (i == 0 && evals) evals[0] = B;
+}
+
+int launch_lbfgs_init_group(const LbfgsBuffers &b, const void *X0, hipStream_t s) {
+  unsigned blocks = (unsigned)std::min<int64_t>(8192, ceil_div(std::max(b.Ltot, b.B), 256));
+  if (b.dtype == DT_F64)
+    hipLaunchKernelGGL(lbfgs_init_group_kernel<double>, dim3(blocks), dim3(256), 0, s, b.B,
+                       b.Ltot, (const double *)X0, (double *)b.X, b.cur, b.head, b.cnt, b.iters,
+                       b.ls, b.status, b.phase, b.evals);
+  else
+    hipLaunchKernelGGL(lbfgs_init_group_kernel<float>, dim3(blocks), dim3(256), 0, s, b.B,
+                       b.Ltot, (const float *)X0, (float *)b.X, b.cur, b.head, b.cnt, b.iters,
+                       b.ls, b.status, b.phase, b.evals);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+template <typename T>
+__global__ void lbfgs_gather_group_kernel(int64_t B, int64_t L, const int64_t *voff,
+                                          const int32_t *vdim, const T *X, const double *F,
+                                          const int32_t *cur, const int32_t *st, T *Xo,
+                                          double *lo, int32_t *sto) {
+  const int64_t s = blockIdx.x;
+  const int c = cur[s];
+  const int64_t vo = voff[s];
+  for (int i = threadIdx.x; i < vdim[s]; i += blockDim.x) Xo[vo + i] = X[(size_t)c * L + vo + i];
+  if (threadIdx.x == 0) {
+    lo[s] = F[(size_t)c * B + s];
+    sto[s] = st[s];
+  }
+}
+
+int launch_lbfgs_gather_group(const LbfgsBuffers &b, void *X, double *logl, int32_t *status,
+                              hipStream_t s) {
+  if (b.B <= 0) return SB_OK;
+  if (b.dtype == DT_F64)
+    hipLaunchKernelGGL(lbfgs_gather_group_kernel<double>, dim3((unsigned)b.B), dim3(256), 0, s,
+                       b.B, b.Ltot, b.voff, b.vdim, (const double *)b.X, (const double *)b.F,
+                       b.cur, b.status, (double *)X, logl, status);
+  else
+    hipLaunchKernelGGL(lbfgs_gather_group_kernel<float>, dim3((unsigned)b.B), dim3(256), 0, s,
+                       b.B, b.Ltot, b.voff, b.vdim, (const float *)b.X, (const double *)b.F,
+                       b.cur, b.status, (float *)X, logl, status);
   SB_LAUNCH_CHECK();
   return SB_OK;
 }

@@ -281,3 +281,281 @@ int launch_chol_solve(int C, int n, const double *L, const double *b, double *x,
 }
 
 }  // namespace sb
+
+// ====================================================================
+// Uneven batches: matrix c has size n[c] and starts at off[c] (row-major,
+// leading dimension n[c]); vectors of matrix c start at voff[c].  The panel
+// loop runs to max n; a matrix whose size is reached skips the stage.
+namespace sb {
+
+__global__ __launch_bounds__(256) void chol_diag_u_kernel(int j0, const int32_t *nv,
+                                                          const int64_t *off, double *L,
+                                                          int32_t *info) {
+  const int c = blockIdx.x;
+  const int n = nv[c];
+  if (j0 >= n || info[c] != 0) return;
+  double *A = L + off[c];
+  const int nb = min(NB, n - j0);
+  const int tid = threadIdx.x;
+  __shared__ double T[NB][NB + 1];
+  __shared__ int fail;
+  for (int e = tid; e < nb * nb; e += 256) {
+    int i = e / nb, k = e % nb;
+    T[i][k] = (k <= i) ? A[(size_t)(j0 + i) * n + j0 + k] : 0.0;
+  }
+  if (tid == 0) fail = 0;
+  __syncthreads();
+  for (int col = 0; col < nb; ++col) {
+    if (tid == 0) {
+      double p = T[col][col];
+      if (!(p > 0.0))
+        fail = col + 1;
+      else
+        T[col][col] = sqrt(p);
+    }
+    __syncthreads();
+    if (fail) break;
+    const double ljj = T[col][col];
+    for (int i = col + 1 + tid; i < nb; i += 256) T[i][col] /= ljj;
+    __syncthreads();
+    const int rem = nb - col - 1;
+    for (int e = tid; e < rem * rem; e += 256) {
+      int i = col + 1 + e / rem, k = col + 1 + e % rem;
+      if (k <= i) T[i][k] -= T[i][col] * T[k][col];
+    }
+    __syncthreads();
+  }
+  if (fail) {
+    if (tid == 0) info[c] = j0 + fail;
+    return;
+  }
+  for (int e = tid; e < nb * nb; e += 256) {
+    int i = e / nb, k = e % nb;
+    A[(size_t)(j0 + i) * n + j0 + k] = (k <= i) ? T[i][k] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(64) void chol_trsm_u_kernel(int j0, const int32_t *nv,
+                                                         const int64_t *off, double *L,
+                                                         const int32_t *info) {
+  const int c = blockIdx.y;
+  const int n = nv[c];
+  if (j0 >= n || info[c] != 0) return;
+  double *A = L + off[c];
+  const int nb = min(NB, n - j0);
+  const int r0 = j0 + nb;
+  if (r0 + (int)blockIdx.x * 64 >= n) return;
+  __shared__ double D[NB][NB + 1];
+  for (int e = threadIdx.x; e < nb * nb; e += 64) {
+    int i = e / nb, k = e % nb;
+    D[i][k] = A[(size_t)(j0 + i) * n + j0 + k];
+  }
+  __syncthreads();
+  const int i = r0 + blockIdx.x * 64 + threadIdx.x;
+  if (i >= n) return;
+  double *row = A + (size_t)i * n + j0;
+  double x[NB];
+#pragma unroll
+  for (int cc = 0; cc < NB; ++cc) x[cc] = (cc < nb) ? row[cc] : 0.0;
+#pragma unroll
+  for (int cc = 0; cc < NB; ++cc) {
+    if (cc < nb) {
+      double s = x[cc];
+#pragma unroll
+      for (int t = 0; t < cc; ++t) s -= x[t] * D[cc][t];
+      x[cc] = s / D[cc][cc];
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < NB; ++cc)
+    if (cc < nb) row[cc] = x[cc];
+}
+
+__global__ __launch_bounds__(256) void chol_syrk_u_kernel(int j0, const int32_t *nv,
+                                                          const int64_t *off, double *L,
+                                                          const int32_t *info) {
+  const int c = blockIdx.y;
+  const int n = nv[c];
+  if (j0 >= n || info[c] != 0) return;
+  double *A = L + off[c];
+  const int nb = min(NB, n - j0);
+  const int r0 = j0 + nb;
+  const int rest = n - r0;
+  if (rest <= 0) return;
+  const int Tn = (rest + 63) / 64;
+  const int t = blockIdx.x;
+  if (t >= Tn * (Tn + 1) / 2) return;
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  const int J = t - I * (I + 1) / 2;
+  const int i0 = r0 + I * 64, k0 = r0 + J * 64;
+  __shared__ double LI[64][NB + 1];
+  __shared__ double LJ[64][NB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * nb; e += 256) {
+    int r = e / nb, cc = e % nb;
+    LI[r][cc] = (i0 + r < n) ? A[(size_t)(i0 + r) * n + j0 + cc] : 0.0;
+    LJ[r][cc] = (k0 + r < n) ? A[(size_t)(k0 + r) * n + j0 + cc] : 0.0;
+  }
+  __syncthreads();
+  const int ti = (tid >> 4) * 4, tk = (tid & 15) * 4;
+  double acc[4][4] = {};
+  for (int cc = 0; cc < nb; ++cc) {
+    double a[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = LI[ti + u][cc];
+      bv[u] = LJ[tk + u][cc];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * bv[v];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int i = i0 + ti + u, k = k0 + tk + v;
+      if (i < n && k < n && k <= i) A[(size_t)i * n + k] -= acc[u][v];
+    }
+}
+
+__global__ void zero_upper_u_kernel(int C, const int32_t *nv, const int64_t *off, double *L) {
+  const int c = blockIdx.y;
+  if (c >= C) return;
+  const int n = nv[c];
+  const int64_t tot = (int64_t)n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), k = (int)(e % n);
+    if (k > i) L[off[c] + e] = 0.0;
+  }
+}
+
+// In-place factorisation of C matrices of sizes nv[c] at offsets off[c].
+int chol_batched_u(int C, const int32_t *nv, const int64_t *off, int n_max, double *L,
+                   int32_t *info, hipStream_t s) {
+  if (C <= 0 || n_max <= 0) return SB_OK;
+  int st = launch_fill_i32(C, 0, info, s);
+  if (st) return st;
+  hipLaunchKernelGGL(zero_upper_u_kernel, dim3((unsigned)std::min<int64_t>(64, ceil_div((int64_t)n_max * n_max, 256)), C),
+                     dim3(256), 0, s, C, nv, off, L);
+  SB_LAUNCH_CHECK();
+  for (int j0 = 0; j0 < n_max; j0 += NB) {
+    hipLaunchKernelGGL(chol_diag_u_kernel, dim3(C), dim3(256), 0, s, j0, nv, off, L, info);
+    const int rest = n_max - j0 - std::min(NB, n_max - j0);
+    if (rest <= 0) {
+      SB_LAUNCH_CHECK();
+      break;
+    }
+    hipLaunchKernelGGL(chol_trsm_u_kernel, dim3((unsigned)ceil_div(rest, 64), C), dim3(64), 0, s,
+                       j0, nv, off, L, info);
+    const int T = (int)ceil_div(rest, 64);
+    hipLaunchKernelGGL(chol_syrk_u_kernel, dim3((unsigned)(T * (T + 1) / 2), C), dim3(256), 0, s,
+                       j0, nv, off, L, info);
+    SB_LAUNCH_CHECK();
+  }
+  return SB_OK;
+}
+
+__global__ __launch_bounds__(256) void logdet_u_kernel(const int32_t *nv, const int64_t *off,
+                                                       const double *L, const int32_t *info,
+                                                       double *logdet) {
+  const int c = blockIdx.x;
+  const int n = nv[c];
+  __shared__ double red[4];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) v += log(L[off[c] + (size_t)i * n + i]);
+  v = block_sum<256>(v, red);
+  if (threadIdx.x == 0) logdet[c] = info[c] ? NAN : 2.0 * v;
+}
+
+int launch_logdet_u(int C, const int32_t *nv, const int64_t *off, const double *L,
+                    const int32_t *info, double *logdet, hipStream_t s) {
+  if (C <= 0) return SB_OK;
+  hipLaunchKernelGGL(logdet_u_kernel, dim3(C), dim3(256), 0, s, nv, off, L, info, logdet);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// Solve L L^T x = b for matrix c (size nv[c]); b and x rows start at c * vs.
+__global__ __launch_bounds__(256) void chol_solve_u_kernel(const int32_t *nv, const int64_t *off,
+                                                           const double *Lall, const double *ball,
+                                                           double *xall, int64_t vs,
+                                                           const int32_t *info) {
+  extern __shared__ double xs[];
+  __shared__ double part[4][64];
+  const int c = blockIdx.x;
+  const int n = nv[c];
+  const double *L = Lall + off[c];
+  const double *b = ball + (size_t)c * vs;
+  double *x = xall + (size_t)c * vs;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (info && info[c] != 0) {
+    for (int i = tid; i < n; i += 256) x[i] = NAN;
+    return;
+  }
+  for (int i = tid; i < n; i += 256) xs[i] = b[i];
+  __syncthreads();
+  for (int i0 = 0; i0 < n; i0 += 64) {
+    const int nb = min(64, n - i0);
+    for (int rr = 0; rr < 16; ++rr) {
+      const int r = w * 16 + rr;
+      double sacc = 0.0;
+      if (r < nb)
+        for (int k = lane; k < i0; k += 64) sacc += L[(size_t)(i0 + r) * n + k] * xs[k];
+      sacc = wave_sum(sacc);
+      if (lane == 0) part[0][r] = sacc;
+    }
+    __syncthreads();
+    if (w == 0) {
+      double val = (lane < nb) ? xs[i0 + lane] - part[0][lane] : 0.0;
+      for (int cc = 0; cc < nb; ++cc) {
+        double xc = __shfl(val / L[(size_t)(i0 + cc) * n + i0 + cc], cc, 64);
+        if (lane == cc) val = xc;
+        if (lane > cc && lane < nb) val -= L[(size_t)(i0 + lane) * n + i0 + cc] * xc;
+      }
+      if (lane < nb) xs[i0 + lane] = val;
+    }
+    __syncthreads();
+  }
+  for (int iend = n; iend > 0; iend -= 64) {
+    const int i0 = max(0, iend - 64);
+    const int nb = iend - i0;
+    double sacc = 0.0;
+    if (lane < nb)
+      for (int k = iend + w; k < n; k += 4) sacc += L[(size_t)k * n + i0 + lane] * xs[k];
+    part[w][lane] = sacc;
+    __syncthreads();
+    if (w == 0) {
+      double sv = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+      double val = (lane < nb) ? xs[i0 + lane] - sv : 0.0;
+      for (int cc = nb - 1; cc >= 0; --cc) {
+        double xc = __shfl(val / L[(size_t)(i0 + cc) * n + i0 + cc], cc, 64);
+        if (lane == cc) val = xc;
+        if (lane < cc) val -= L[(size_t)(i0 + cc) * n + i0 + lane] * xc;
+      }
+      if (lane < nb) xs[i0 + lane] = val;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += 256) x[i] = xs[i];
+}
+
+int launch_chol_solve_u(int C, const int32_t *nv, const int64_t *off, int n_max, const double *L,
+                        const double *b, double *x, int64_t vs, const int32_t *info,
+                        hipStream_t s) {
+  if (C <= 0) return SB_OK;
+  const size_t shm = sizeof(double) * (size_t)n_max;
+  if (shm > 64 * 1024) {
+    set_error("solve dimension %d too large", n_max);
+    return SB_E_UNSUPPORTED;
+  }
+  hipLaunchKernelGGL(chol_solve_u_kernel, dim3(C), dim3(256), shm, s, nv, off, L, b, x, vs, info);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+}  // namespace sb

@@ -106,3 +106,20 @@ def test_workspace_sizes_scale():
     big = _lib.lib().sb_evidence_workspace_bytes(C.byref(ll), C.byref(_lib.make_config(cfg)))
     assert 0 < small < big
     assert _lib.lib().sb_logl_grad_workspace_bytes(64, 4, 1000, 0) > 8 * 1000 * 256
+
+
+def test_batch_validation_before_device():
+    """Mismatched precisions in one batch are rejected before any device work."""
+    import numpy as np
+    from paper_2601_19957_amd import _lib, synth
+
+    p = synth.make_problem("c0")
+    c0 = synth.make_run_config("c0", precision=0)
+    c1 = synth.make_run_config("c0", precision=1)
+    try:
+        _lib.sb_evidence_batch([p, p], [c0, c1])
+    except _lib.SbError as e:
+        assert e.status == _lib.E_INVAL and "problem 1" in str(e)
+    else:
+        raise AssertionError("expected SbError")
+    assert np.isfinite(p.lo).all()
