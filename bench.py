@@ -119,6 +119,40 @@ def cpu_baseline(prob, cfg, budget_s=20.0):
                 seconds=dt, log_z=r.log_z)
 
 
+def uneven_batch(L, serial=False):
+    """The 512-problem uneven workload (d log-uniform in 8..512, K in 1..4,
+    1024 starts each, FP64) as one sb_evidence_batch call: one warm-up call,
+    then one timed call; log Z checked against the closed form -log V."""
+    import numpy as np
+    from paper_2601_19957_amd import synth
+
+    probs, cfg = synth.make_workload("c3")
+    cfgs = [synth.make_run_config("c3", seed=cfg.seed + j) for j in range(len(probs))]
+    log(f"uneven batch: {len(probs)} problems, sum d = {sum(p.d for p in probs)}")
+    L.sb_evidence_batch(probs, cfgs)
+    t0 = time.perf_counter()
+    res = L.sb_evidence_batch(probs, cfgs)
+    dt = time.perf_counter() - t0
+    ok = sum(1 for p, r in zip(probs, res) if r.status == 0 and r.n_modes == p.K)
+    gap = max(abs(r.log_z + float(np.sum(np.log(p.hi - p.lo)))) for p, r in zip(probs, res)
+              if r.status == 0 and r.n_modes == p.K) if ok else None
+    evals = sum(r.n_grad_evals for r in res)
+    out = dict(problems=len(probs), starts=sum(c.n_starts for c in cfgs), seconds=dt,
+               problems_per_s=len(probs) / dt, logl_grad_evals_per_s=evals / dt,
+               all_modes_found=f"{ok}/{len(probs)}", max_dlogz_vs_closed_form=gap,
+               phases_ms=[round(x * 1e3, 2) for x in res[0].seconds[:7]], dtype="f64")
+    log(f"uneven batch: {dt*1e3:.1f} ms, {ok}/{len(probs)} complete, gap {gap}")
+    if serial:
+        t0 = time.perf_counter()
+        for p, c in zip(probs, cfgs):
+            L.sb_evidence(p, c)
+        ds = time.perf_counter() - t0
+        out["serial_seconds"] = ds
+        out["speedup_vs_serial"] = ds / dt
+        log(f"one call per problem: {ds*1e3:.1f} ms")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +163,10 @@ def main() -> int:
     ap.add_argument("--starts", type=int, default=None, help="override the start count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the uneven-batch leg (512 problems, d in 8..512)")
+    ap.add_argument("--batch-serial", action="store_true",
+                    help="also time the uneven batch as one call per problem")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the roofline kernel timing (for profiling that kernel)")
     args = ap.parse_args()
@@ -241,6 +279,10 @@ def main() -> int:
         log(f"{n}: |dlogZ| vs oracle {dlogz[n]:.3e} (closed form gap "
             f"{abs(refm.log_z - ref[n]):.3e}), modes {last[n].n_modes}/{refm.n_modes}")
 
+    batch = None
+    if not args.no_batch:
+        batch = uneven_batch(L, serial=args.batch_serial)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle) on a bounded sample")
@@ -274,6 +316,7 @@ def main() -> int:
         "dlogz_vs_oracle": dlogz,
         "dlogz_fp64_vs_oracle": {n: abs(res64[n].log_z - refz[n]) for n in res64},
         "max_mode_dist_vs_oracle": dmodes,
+        "uneven_batch": batch,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -1,13 +1,14 @@
 // Tile-shape autotuner for the quadratic-form GEMM.
 //
-// Candidates (BM x BN in {64, 128}^2) are timed with HIP events on the
-// caller's own inputs the first time a shape class (dtype, d, K, M rounded to
-// a power of two) is seen; the fastest is cached for the process.  Timing
-// runs write only the GEMM's own scratch outputs, which the real launch
-// overwrites.  SB_TILE=BMxBN forces a shape; SB_AUTOTUNE=0 uses the
-// heuristic choice without timing.
-#include <cstdlib>
+// The first time a shape class (dtype, d, K, M rounded up to a power of two)
+// is seen, each candidate tile (BM x BN in {64, 128}^2) is timed with HIP
+// events on device buffers of that shape (up to 8192 rows, seeded values in
+// [-1, 1)), and the fastest is cached for the process.  Timing needs its own
+// allocations and a synchronisation, so a stream under graph capture gets
+// the heuristic choice (not cached).  SB_TILE=BMxBN forces a shape;
+// SB_AUTOTUNE=0 uses the heuristic without timing.
 #include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -18,21 +19,126 @@ namespace sb {
 
 namespace {
 std::mutex g_mu;
-std::map<std::tuple<int, int, int, int>, TileCfg> g_cache;
+std::map<std::tuple<int, int, int, int, int>, TileCfg> g_cache;
 
 int bucket(int64_t M) {
   int b = 0;
   while ((1ll << b) < M) ++b;
   return b;
 }
-}  // namespace
 
-static TileCfg heuristic(int dtype, int d, int64_t M) {
+// Seeded values in [-1, 1) (a 32-bit integer hash of the index).
+template <typename T>
+__global__ void tune_fill_kernel(int64_t n, T *p, uint32_t salt) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t h = (uint32_t)i * 0x9E3779B1u ^ salt;
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    const float v = (float)(h >> 8) * (1.0f / 8388608.0f) - 1.0f;
+    if constexpr (sizeof(T) == 2)
+      p[i] = f32_to_bf16(v);
+    else
+      p[i] = (T)v;
+  }
+}
+
+template <typename T>
+void fill(int64_t n, void *p, uint32_t salt, hipStream_t s) {
+  const unsigned blocks = (unsigned)std::min<int64_t>(4096, ceil_div(n, 256));
+  if (n > 0) hipLaunchKernelGGL(tune_fill_kernel<T>, dim3(blocks), dim3(256), 0, s, n, (T *)p, salt);
+}
+
+TileCfg heuristic(int d, int64_t M) {
   TileCfg t;
   t.bn = (d <= 64) ? 64 : 128;
   t.bm = (M <= 4096 || d <= 64) ? 64 : 128;
   return t;
 }
+
+// Times the four candidates on buffers of shape (Mt, d, K); returns false on
+// any runtime error (the caller then uses the heuristic).
+bool time_candidates(int dtype, int d, int K, int64_t M, hipStream_t s, TileCfg *best) {
+  const int64_t Mt = std::max<int64_t>(1, std::min<int64_t>(M, 8192));
+  const size_t in_es = (dtype == DT_F64) ? 8 : 4;
+  const size_t op_es = (dtype == DT_F64) ? 8 : (dtype == DT_F32 ? 4 : 2);
+  const size_t acc_es = (dtype == DT_F64) ? 8 : 4;
+  const size_t nX = (size_t)Mt * d, nmu = (size_t)K * d, nP = (size_t)K * d * d;
+  const size_t nY = (size_t)Mt * K * d, nq = (size_t)Mt * K * ceil_div(d, 64);
+  const size_t bytes = align_up(in_es * nX) + align_up(in_es * nmu) + align_up(op_es * nP) +
+                       align_up(acc_es * nY) + align_up(acc_es * nq);
+  void *buf = nullptr;
+  if (hipMalloc(&buf, bytes) != hipSuccess) return false;
+  char *p = (char *)buf;
+  void *X = p;
+  p += align_up(in_es * nX);
+  void *mu = p;
+  p += align_up(in_es * nmu);
+  void *P = p;
+  p += align_up(op_es * nP);
+  void *Y = p;
+  p += align_up(acc_es * nY);
+  void *q = p;
+  if (dtype == DT_F64) {
+    fill<double>(nX, X, 1u, s);
+    fill<double>(nmu, mu, 2u, s);
+    fill<double>(nP, P, 3u, s);
+  } else {
+    fill<float>(nX, X, 1u, s);
+    fill<float>(nmu, mu, 2u, s);
+    if (dtype == DT_F32)
+      fill<float>(nP, P, 3u, s);
+    else
+      fill<bf16_t>(nP, P, 3u, s);
+  }
+  Model m;
+  m.d = d;
+  m.K = K;
+  if (dtype == DT_F64) {
+    m.mu64 = (const double *)mu;
+    m.P64 = (const double *)P;
+  } else {
+    m.mu32 = (const float *)mu;
+    m.Plp = P;
+  }
+  ASrc a;
+  a.kind = 0;
+  a.X = X;
+  a.ldx = d;
+  hipEvent_t e0, e1;
+  bool ok = hipEventCreate(&e0) == hipSuccess;
+  ok = ok && hipEventCreate(&e1) == hipSuccess;
+  float best_ms = 0.f;
+  const int cands[4][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}};
+  for (int c = 0; c < 4 && ok; ++c) {
+    TileCfg t;
+    t.bm = cands[c][0];
+    t.bn = cands[c][1];
+    QuadOut o;
+    o.Y = Y;
+    o.ldy = (int64_t)K * d;
+    o.qpart = q;
+    ok = launch_quad_gemm(dtype, m, a, Mt, nullptr, o, t, s) == SB_OK;  // warm-up
+    ok = ok && hipEventRecord(e0, s) == hipSuccess;
+    for (int r = 0; r < 3 && ok; ++r) ok = launch_quad_gemm(dtype, m, a, Mt, nullptr, o, t, s) == SB_OK;
+    ok = ok && hipEventRecord(e1, s) == hipSuccess;
+    ok = ok && hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.f;
+    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    if (ok && (c == 0 || ms < best_ms)) {
+      best_ms = ms;
+      *best = t;
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(buf);
+  (void)hipGetLastError();
+  return ok;
+}
+}  // namespace
 
 TileCfg autotune_tiles(int dtype, const Model &m, int64_t M, hipStream_t s) {
   const char *force = getenv("SB_TILE");
@@ -45,12 +151,19 @@ TileCfg autotune_tiles(int dtype, const Model &m, int64_t M, hipStream_t s) {
       return t;
     }
   }
-  (void)s;
+  const char *at = getenv("SB_AUTOTUNE");
+  const bool timed = !(at && at[0] == '0');
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) cs = hipStreamCaptureStatusNone;
+  if (!timed || cs != hipStreamCaptureStatusNone) return heuristic(m.d, M);
   std::lock_guard<std::mutex> lk(g_mu);
-  auto key = std::make_tuple(dtype, m.d, m.K, bucket(M));
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  auto key = std::make_tuple(dev, dtype, m.d, m.K, bucket(M));
   auto it = g_cache.find(key);
   if (it != g_cache.end()) return it->second;
-  TileCfg t = heuristic(dtype, m.d, M);
+  TileCfg t = heuristic(m.d, M);
+  if (!time_candidates(dtype, m.d, m.K, M, s, &t)) t = heuristic(m.d, M);
   g_cache[key] = t;
   return t;
 }

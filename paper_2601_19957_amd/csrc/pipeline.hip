@@ -204,13 +204,6 @@ struct Evaluator {
   }
 };
 
-static TileCfg default_tiles(int dtype, int d, int64_t M) {
-  TileCfg t;
-  t.bn = (d <= 64) ? 64 : 128;
-  t.bm = (M <= 4096 || d <= 64) ? 64 : 128;
-  return t;
-}
-
 // ------------------------------------------------------------ config
 
 struct RunCfg {
@@ -491,6 +484,7 @@ static int polish_chunk(Layout &L, const Model &m64, const DevProblem &P, int n,
   Evaluator &ev = L.pol;
   ev.m = m64;
   ev.dtype = DT_F64;
+  ev.tile = autotune_tiles(DT_F64, m64, n, s);
   ASrc a;
   a.kind = 0;
   a.X = L.Xp;
@@ -616,7 +610,7 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
       a.P1 = mixed ? (const void *)L.P1f : (const void *)L.P1;
       a.n_pts = rc.n_pts;
       const int64_t NP = (int64_t)rc.R * rc.n_pts;
-      L.disc.tile = default_tiles(ddt, d, NP);
+      L.disc.tile = autotune_tiles(ddt, md, NP, s);
       if ((st = L.disc.run(a, NP, nullptr, L.lpts, nullptr, 0, nullptr, nullptr, false, s, false)))
         return st;
     }
@@ -646,7 +640,7 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     }
     L.bulk.m = mb;
     L.bulk.dtype = mixed ? DT_F32 : DT_F64;
-    L.bulk.tile = default_tiles(L.bulk.dtype, d, rc.n_starts);
+    L.bulk.tile = autotune_tiles(L.bulk.dtype, mb, rc.n_starts, s);
     int64_t bulk_evals = 0;
     int steps = 0;
     if ((st = run_bulk(L, rc, tol, s, &bulk_evals, &steps))) return st;
