@@ -165,6 +165,8 @@ def main() -> int:
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the uneven-batch leg (512 problems, d in 8..512)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the uneven-batch leg (for profiling it)")
     ap.add_argument("--batch-serial", action="store_true",
                     help="also time the uneven batch as one call per problem")
     ap.add_argument("--kernel-only", action="store_true",
@@ -186,6 +188,10 @@ def main() -> int:
         print("no GPU visible", file=sys.stderr)
         return 1
     L.lib()
+    if args.batch_only:
+        print(json.dumps(dict(batch_only=True, uneven_batch=uneven_batch(L, args.batch_serial))),
+              flush=True)
+        return 0
     names = [n.strip() for n in args.workload.split(",") if n.strip()]
     log(f"generating {names}")
     wl = workload(names, args.starts)

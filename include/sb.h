@@ -66,7 +66,16 @@ typedef enum { SB_NORM_PEAK_ZERO = 0, SB_NORM_DENSITY = 1 } sb_norm;
  * with FP32 accumulation, L-BFGS bulk in FP32, then Newton polish, Hessian,
  * Cholesky, log det and the logsumexp combine in FP64. */
 typedef enum { SB_PREC_FP64 = 0, SB_PREC_MIXED = 1 } sb_precision;
-typedef enum { SB_DTYPE_F64 = 0, SB_DTYPE_F32 = 1, SB_DTYPE_BF16 = 2 } sb_dtype;
+/* SB_DTYPE_F32_SPLIT: FP32 data whose contraction runs on the BF16 matrix
+ * cores as three products of split operands (v = hi + lo, hi = bf16(v),
+ * lo = bf16(v - hi); hi*hi + hi*lo + lo*hi with FP32 accumulation, about
+ * 2^-16 relative per product); needs d a multiple of 8. */
+typedef enum {
+  SB_DTYPE_F64 = 0,
+  SB_DTYPE_F32 = 1,
+  SB_DTYPE_BF16 = 2,
+  SB_DTYPE_F32_SPLIT = 3
+} sb_dtype;
 
 /* Likelihood: family, normalisation and parameters.
  * log_w [K] (NULL: all weights 1), mu [K][d], prec [K][d][d] (symmetric
@@ -144,7 +153,8 @@ typedef struct {
   const double *log_w, *mu, *prec; /* device, FP64 */
   double nu, logl_offset;
   const double *beta;              /* device [K], from sb_prep_dev */
-  const void *prec_lp;             /* device [K][d][d] FP32 or BF16, or NULL */
+  const void *prec_lp;             /* device [K][d][d] FP32 or BF16, or [2][K][d][d]
+                                      BF16 hi then lo (dtype F32_SPLIT), or NULL */
   const float *mu_lp;              /* device [K][d] FP32, or NULL */
 } sb_model_dev;
 
@@ -159,7 +169,7 @@ int32_t sb_prep_dev(const sb_loglik *ll_dev, double *beta, double *logdet_prec, 
                     void *stream);
 
 /* Batched log-likelihood and gradient (step A3): for B points X [B][d]
- * (dtype F64: double; F32: float) writes logl [B] and, if grad != NULL,
+ * (dtype F64: double; F32 or F32_SPLIT: float) writes logl [B] and, if grad != NULL,
  * grad [B][d] (same dtype).  One GEMM (X - mu_k) P_k on the matrix cores,
  * then the logsumexp / Student-t epilogue and the hand-written backward.
  * Workspace >= sb_logl_grad_workspace_bytes(d, K, B, dtype). */
@@ -170,10 +180,17 @@ int32_t sb_logl_grad_dev(const sb_model_dev *m, int64_t B, const void *X, void *
 /* The contraction of step A3 alone, as used inside sb_logl_grad_dev and the
  * optimiser: Y [B][K*d] with Y[b][k*d + n] = sum_j P_k[n][j] (X[b][j] -
  * mu_k[j]) and per-tile partial quadratic forms qpart [B][K][*n_tiles]
- * (q_k = sum over tiles).  dtype F64 or F32 (Y, qpart in that type).  qpart
+ * (q_k = sum over tiles).  dtype F64, F32 or F32_SPLIT (Y, qpart FP64 or
+ * FP32; *n_tiles gets the tiles' count, which depends on dtype).  qpart
  * must hold B*K*ceil(d/64) values.  For measurement and testing. */
 int32_t sb_quadform_dev(const sb_model_dev *m, int64_t B, const void *X, int32_t dtype, void *Y,
                         void *qpart, int32_t *n_tiles, void *stream);
+
+/* Split copy for the F32_SPLIT contraction: hi[i] = bf16(fp32(x[i])) and,
+ * when lo != NULL, lo[i] = bf16(x[i] - hi[i]) (round to nearest even; uint16
+ * bit patterns), for n device values.  A model's prec_lp for dtype
+ * F32_SPLIT is hi of all K d x d precisions followed by lo. */
+int32_t sb_split_bf16_dev(int64_t n, const double *x, uint16_t *hi, uint16_t *lo, void *stream);
 
 /* Batched Hessian-vector product (step A3'): HV[b] = nabla^2 l(X[b]) V[b],
  * FP64.  Workspace >= sb_hvp_workspace_bytes(d, K, B). */

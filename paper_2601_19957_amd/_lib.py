@@ -23,14 +23,14 @@ OK, E_INVAL, E_NOTPD, E_NOMEM, E_DEVICE, E_NOMODE, E_CAPACITY, E_UNSUPPORTED = (
 FAMILY_GAUSS_MIX, FAMILY_STUDENT_T = 0, 1
 NORM_PEAK_ZERO, NORM_DENSITY = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
-DTYPE_F64, DTYPE_F32, DTYPE_BF16 = 0, 1, 2
+DTYPE_F64, DTYPE_F32, DTYPE_BF16, DTYPE_F32_SPLIT = 0, 1, 2, 3
 ST_CONVERGED, ST_STALLED, ST_MAXITER, ST_DEAD = 1, 2, 3, 4
 
 # every extern "C" symbol declared in include/sb.h
 EXPORTS = [
     "sb_evidence", "sb_evidence_batch", "sb_evidence_workspace_bytes", "sb_evidence_dev",
     "sb_prep_workspace_bytes", "sb_prep_dev", "sb_logl_grad_workspace_bytes", "sb_logl_grad_dev",
-    "sb_quadform_dev", "sb_hvp_workspace_bytes", "sb_hvp_dev", "sb_discover_workspace_bytes", "sb_discover_dev",
+    "sb_quadform_dev", "sb_split_bf16_dev", "sb_hvp_workspace_bytes", "sb_hvp_dev", "sb_discover_workspace_bytes", "sb_discover_dev",
     "sb_lbfgs_direction_dev", "sb_lbfgs_workspace_bytes", "sb_lbfgs_dev",
     "sb_dedup_workspace_bytes", "sb_dedup_dev", "sb_hessian_workspace_bytes", "sb_hessian_dev",
     "sb_cholesky_logdet_dev", "sb_cholesky_solve_dev", "sb_combine_dev", "sb_status_string",
@@ -101,6 +101,7 @@ def lib():
             "sb_logl_grad_workspace_bytes": (sz, [i32, i32, i64, i32]),
             "sb_logl_grad_dev": (i32, [vp, i64, vp, vp, vp, i32, vp, sz, vp]),
             "sb_quadform_dev": (i32, [vp, i64, vp, i32, vp, vp, vp, vp]),
+            "sb_split_bf16_dev": (i32, [i64, vp, vp, vp, vp]),
             "sb_hvp_workspace_bytes": (sz, [i32, i32, i64]),
             "sb_hvp_dev": (i32, [vp, i64, vp, vp, vp, vp, sz, vp]),
             "sb_discover_workspace_bytes": (sz, [i32, i32, i32, i32, i32]),
@@ -267,6 +268,8 @@ class DeviceModel:
     """Likelihood parameters resident on the GPU plus the prep outputs (beta, log det P)."""
 
     def __init__(self, prob, device="cuda", low_precision: bool = False):
+        """low_precision also builds the FP32 / BF16 copies and the split
+        [2][K][d][d] BF16 hi/lo copy (dtype F32_SPLIT) of the precisions."""
         import torch
 
         self.prob = prob
@@ -279,11 +282,13 @@ class DeviceModel:
         self.hi = torch.as_tensor(_f64(prob.hi), device=dev)
         self.beta = torch.zeros(self.K, dtype=torch.float64, device=dev)
         self.logdet_prec = torch.zeros(self.K, dtype=torch.float64, device=dev)
-        self.prec_f32 = self.prec_bf16 = self.mu_f32 = None
+        self.prec_f32 = self.prec_bf16 = self.mu_f32 = self.prec_split = None
         if low_precision:
             self.prec_f32 = torch.empty(self.prec.shape, dtype=torch.float32, device=dev)
             self.prec_bf16 = torch.empty(self.prec.shape, dtype=torch.int16, device=dev)
             self.mu_f32 = torch.empty(self.mu.shape, dtype=torch.float32, device=dev)
+            self.prec_split = torch.empty((2,) + tuple(self.prec.shape), dtype=torch.int16,
+                                          device=dev)
         self.ll = sb_loglik(prob.family, prob.norm, prob.d, prob.K, self.log_w.data_ptr(),
                             self.mu.data_ptr(), self.prec.data_ptr(), float(prob.nu),
                             float(prob.logl_offset))
@@ -294,6 +299,11 @@ class DeviceModel:
                                _ptr(self.prec_bf16), _ptr(self.mu_f32), ws.data_ptr(), ws.numel(),
                                _stream())
         _check(st, "sb_prep_dev")
+        if low_precision:
+            n = self.prec.numel()
+            st = lib().sb_split_bf16_dev(n, self.prec.data_ptr(), self.prec_split[0].data_ptr(),
+                                         self.prec_split[1].data_ptr(), _stream())
+            _check(st, "sb_split_bf16_dev")
 
     def view(self, dtype: int = DTYPE_F64) -> sb_model_dev:
         lp = None
@@ -301,6 +311,8 @@ class DeviceModel:
             lp = _ptr(self.prec_f32)
         elif dtype == DTYPE_BF16:
             lp = _ptr(self.prec_bf16)
+        elif dtype == DTYPE_F32_SPLIT:
+            lp = _ptr(self.prec_split)
         return sb_model_dev(self.prob.family, self.prob.norm, self.d, self.K,
                             self.log_w.data_ptr(), self.mu.data_ptr(), self.prec.data_ptr(),
                             float(self.prob.nu), float(self.prob.logl_offset),
@@ -313,11 +325,12 @@ def _ws(nbytes: int, device):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
-def sb_logl_grad_dev(model: DeviceModel, X, grad: bool = True):
-    """l (and grad l) at the rows of X (float64 -> FP64 path, float32 -> FP32 path)."""
+def sb_logl_grad_dev(model: DeviceModel, X, grad: bool = True, dtype=None):
+    """l (and grad l) at the rows of X (float64 -> FP64 path, float32 -> FP32 path, or
+    DTYPE_F32_SPLIT for float32 data through the split BF16 contraction)."""
     import torch
 
-    dt = DTYPE_F64 if X.dtype == torch.float64 else DTYPE_F32
+    dt = dtype if dtype is not None else (DTYPE_F64 if X.dtype == torch.float64 else DTYPE_F32)
     X = X.contiguous()
     B = X.shape[0]
     l = torch.empty(B, dtype=X.dtype, device=X.device)
@@ -333,11 +346,12 @@ def sb_logl_grad_dev(model: DeviceModel, X, grad: bool = True):
 class QuadForm:
     """Repeated launches of the A3 contraction alone (sb_quadform_dev) on fixed buffers."""
 
-    def __init__(self, model: DeviceModel, X):
+    def __init__(self, model: DeviceModel, X, dtype=None):
         import torch
 
         self.model = model
-        self.dt = DTYPE_F64 if X.dtype == torch.float64 else DTYPE_F32
+        self.dt = dtype if dtype is not None else (
+            DTYPE_F64 if X.dtype == torch.float64 else DTYPE_F32)
         self.X = X.contiguous()
         B = X.shape[0]
         self.Y = torch.empty((B, model.K * model.d), dtype=X.dtype, device=X.device)

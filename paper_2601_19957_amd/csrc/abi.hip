@@ -132,6 +132,27 @@ Model model_from(const sb_model_dev *m) {
   return r;
 }
 
+// Model for a GEMM dtype: F32_SPLIT reads prec_lp as [2][K][d][d] BF16.
+Model model_for(const sb_model_dev *m, int dtype) {
+  Model r = model_from(m);
+  if (dtype == SB_DTYPE_F32_SPLIT) {
+    r.Phi = (const bf16_t *)m->prec_lp;
+    r.Plo = r.Phi + (size_t)m->K * m->d * m->d;
+    r.Plp = nullptr;
+  }
+  return r;
+}
+
+int check_gemm_dtype(const sb_model_dev *m, int dtype) {
+  if (dtype != SB_DTYPE_F64 && dtype != SB_DTYPE_F32 && dtype != SB_DTYPE_F32_SPLIT)
+    return fail(SB_E_INVAL, "dtype must be F64, F32 or F32_SPLIT");
+  if (dtype != SB_DTYPE_F64 && (!m->prec_lp || !m->mu_lp))
+    return fail(SB_E_INVAL, "dtype F32 / F32_SPLIT needs prec_lp and mu_lp");
+  if (dtype == SB_DTYPE_F32_SPLIT && m->d % 8 != 0)
+    return fail(SB_E_UNSUPPORTED, "F32_SPLIT needs d a multiple of 8 (got %d)", m->d);
+  return SB_OK;
+}
+
 int validate_model(const sb_model_dev *m) {
   if (!m) return fail(SB_E_INVAL, "model is NULL");
   sb_loglik ll;
@@ -404,15 +425,12 @@ int32_t sb_logl_grad_dev(const sb_model_dev *mdl, int64_t B, const void *X, void
   int st = validate_model(mdl);
   if (st) return st;
   if (B < 0 || (B > 0 && (!X || !logl))) return fail(SB_E_INVAL, "bad B / X / logl");
-  if (dtype != SB_DTYPE_F64 && dtype != SB_DTYPE_F32)
-    return fail(SB_E_INVAL, "dtype must be F64 or F32");
-  if (dtype == SB_DTYPE_F32 && (!mdl->prec_lp || !mdl->mu_lp))
-    return fail(SB_E_INVAL, "F32 needs prec_lp (FP32) and mu_lp");
+  if ((st = check_gemm_dtype(mdl, dtype))) return st;
   if (B == 0) return SB_OK;
   if (!workspace || ws_bytes < sb_logl_grad_workspace_bytes(mdl->d, mdl->K, B, dtype))
     return fail(SB_E_NOMEM, "workspace too small");
   if ((st = device_status())) return st;
-  Model m = model_from(mdl);
+  Model m = model_for(mdl, dtype);
   const size_t es = dtype == SB_DTYPE_F64 ? 8 : 4;
   Arena ar(workspace, ws_bytes);
   void *Y = ar.take<char>(es * (size_t)B * m.K * m.d);
@@ -425,7 +443,8 @@ int32_t sb_logl_grad_dev(const sb_model_dev *mdl, int64_t B, const void *X, void
   o.Y = Y;
   o.ldy = (int64_t)m.K * m.d;
   o.qpart = qp;
-  TileCfg t = autotune_tiles(dtype, m, B, (hipStream_t)stream);
+  TileCfg t;
+  if (dtype != SB_DTYPE_F32_SPLIT) t = autotune_tiles(dtype, m, B, (hipStream_t)stream);
   if ((st = launch_quad_gemm(dtype, m, a, B, nullptr, o, t, (hipStream_t)stream))) return st;
   FinishArgs f;
   f.M = B;
@@ -444,12 +463,9 @@ int32_t sb_quadform_dev(const sb_model_dev *mdl, int64_t B, const void *X, int32
   int st = validate_model(mdl);
   if (st) return st;
   if (B < 0 || (B > 0 && (!X || !Y || !qpart))) return fail(SB_E_INVAL, "bad B / X / Y / qpart");
-  if (dtype != SB_DTYPE_F64 && dtype != SB_DTYPE_F32)
-    return fail(SB_E_INVAL, "dtype must be F64 or F32");
-  if (dtype == SB_DTYPE_F32 && (!mdl->prec_lp || !mdl->mu_lp))
-    return fail(SB_E_INVAL, "F32 needs prec_lp (FP32) and mu_lp");
+  if ((st = check_gemm_dtype(mdl, dtype))) return st;
   if ((st = device_status())) return st;
-  Model m = model_from(mdl);
+  Model m = model_for(mdl, dtype);
   ASrc a;
   a.kind = 0;
   a.X = X;
@@ -458,10 +474,19 @@ int32_t sb_quadform_dev(const sb_model_dev *mdl, int64_t B, const void *X, int32
   o.Y = Y;
   o.ldy = (int64_t)m.K * m.d;
   o.qpart = qpart;
-  TileCfg t = autotune_tiles(dtype, m, B, (hipStream_t)stream);
+  TileCfg t;
+  if (dtype != SB_DTYPE_F32_SPLIT) t = autotune_tiles(dtype, m, B, (hipStream_t)stream);
   st = launch_quad_gemm(dtype, m, a, B, nullptr, o, t, (hipStream_t)stream);
   if (n_tiles) *n_tiles = o.ntn;
   return st;
+}
+
+int32_t sb_split_bf16_dev(int64_t n, const double *x, uint16_t *hi, uint16_t *lo, void *stream) {
+  if (n < 0 || (n > 0 && (!x || !hi))) return fail(SB_E_INVAL, "bad n / x / hi");
+  if (n == 0) return SB_OK;
+  int st = device_status();
+  if (st) return st;
+  return launch_split_bf16(n, x, hi, lo, (hipStream_t)stream);
 }
 
 // ------------------------------------------------------------------- HVP

@@ -1,7 +1,8 @@
 // Tile-shape autotuner for the quadratic-form GEMM.
 //
 // The first time a shape class (dtype, d, K, M rounded up to a power of two)
-// is seen, each candidate tile (BM x BN in {64, 128}^2) is timed with HIP
+// is seen, each candidate tile (BM x BN in {64, 128}^2; for the BF16 and
+// split contractions BM x k-tile in {128 x 32, 128 x 64, 256 x 32}) is timed with HIP
 // events on device buffers of that shape (up to 8192 rows, seeded values in
 // [-1, 1)), and the fastest is cached for the process.  Timing needs its own
 // allocations and a synchronisation, so a stream under graph capture gets
@@ -51,7 +52,7 @@ void fill(int64_t n, void *p, uint32_t salt, hipStream_t s) {
 }
 
 TileCfg heuristic(int d, int64_t M) {
-  TileCfg t;
+  TileCfg t;  // (for the BF16 kernels: 128 rows, 128 -> a 32-wide k-tile)
   t.bn = (d <= 64) ? 64 : 128;
   t.bm = (M <= 4096 || d <= 64) ? 64 : 128;
   return t;
@@ -61,8 +62,10 @@ TileCfg heuristic(int d, int64_t M) {
 // any runtime error (the caller then uses the heuristic).
 bool time_candidates(int dtype, int d, int K, int64_t M, hipStream_t s, TileCfg *best) {
   const int64_t Mt = std::max<int64_t>(1, std::min<int64_t>(M, 8192));
+  const bool bf = (dtype == DT_BF16 || dtype == DT_F32S) && quad_gemm_bf16_ok(d);
   const size_t in_es = (dtype == DT_F64) ? 8 : 4;
-  const size_t op_es = (dtype == DT_F64) ? 8 : (dtype == DT_F32 ? 4 : 2);
+  // the BF16 kernels read hi and lo copies (2 x bf16 per entry)
+  const size_t op_es = (dtype == DT_F64) ? 8 : (dtype == DT_F32 ? 4 : (bf ? 4 : 2));
   const size_t acc_es = (dtype == DT_F64) ? 8 : 4;
   const size_t nX = (size_t)Mt * d, nmu = (size_t)K * d, nP = (size_t)K * d * d;
   const size_t nY = (size_t)Mt * K * d, nq = (size_t)Mt * K * ceil_div(d, 64);
@@ -90,7 +93,7 @@ bool time_candidates(int dtype, int d, int K, int64_t M, hipStream_t s, TileCfg 
     if (dtype == DT_F32)
       fill<float>(nP, P, 3u, s);
     else
-      fill<bf16_t>(nP, P, 3u, s);
+      fill<bf16_t>(bf ? 2 * nP : nP, P, 3u, s);
   }
   Model m;
   m.d = d;
@@ -101,6 +104,10 @@ bool time_candidates(int dtype, int d, int K, int64_t M, hipStream_t s, TileCfg 
   } else {
     m.mu32 = (const float *)mu;
     m.Plp = P;
+    if (bf) {
+      m.Phi = (const bf16_t *)P;
+      m.Plo = (const bf16_t *)P + nP;
+    }
   }
   ASrc a;
   a.kind = 0;
@@ -110,11 +117,14 @@ bool time_candidates(int dtype, int d, int K, int64_t M, hipStream_t s, TileCfg 
   bool ok = hipEventCreate(&e0) == hipSuccess;
   ok = ok && hipEventCreate(&e1) == hipSuccess;
   float best_ms = 0.f;
+  // GEMM tiles (BM, BN); for the BF16 kernels (BM, k-tile)
   const int cands[4][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}};
-  for (int c = 0; c < 4 && ok; ++c) {
+  const int cands_bf[3][2] = {{128, 32}, {128, 64}, {256, 32}};
+  const int nc = bf ? 3 : 4;
+  for (int c = 0; c < nc && ok; ++c) {
     TileCfg t;
-    t.bm = cands[c][0];
-    t.bn = cands[c][1];
+    t.bm = bf ? cands_bf[c][0] : cands[c][0];
+    t.bn = bf ? cands_bf[c][1] : cands[c][1];
     QuadOut o;
     o.Y = Y;
     o.ldy = (int64_t)K * d;

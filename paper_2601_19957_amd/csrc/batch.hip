@@ -724,6 +724,7 @@ int run_evidence_batch(int n, const sb_loglik *ll, const sb_box *box, const sb_c
       f.segs = D.sbulk.segs;
       f.nseg = D.sbulk.nseg;
       f.nrows = Btot;
+      f.rowseg = D.sprob;  // bulk segments are the problems, rows the starts
       f.counts = counts;
       f.qpart = D.qbulk;
       f.bn = tbulk.bn;

@@ -560,6 +560,16 @@ static int launch_t(const GemmParams &p, hipStream_t s) {
 
 int launch_quad_gemm(int dtype, const Model &m, const ASrc &a, int64_t M, const int32_t *count,
                      QuadOut &o, TileCfg t, hipStream_t s) {
+  // BF16 matrix-core kernel: split FP32 always when d allows (else plain
+  // FP32), BF16 when d allows and the BF16 copy is given.
+  if (dtype == DT_F32S && quad_gemm_bf16_ok(m.d))
+    return launch_quad_gemm_bf16(3, m, a, M, count, o, s, t);
+  if (dtype == DT_F32S) dtype = DT_F32;
+  if (dtype == DT_BF16 && quad_gemm_bf16_ok(m.d)) {
+    Model mb = m;
+    if (!mb.Phi) mb.Phi = (const bf16_t *)m.Plp;
+    return launch_quad_gemm_bf16(1, mb, a, M, count, o, s, t);
+  }
   GemmParams p;
   p.a = a;
   p.M = M;
@@ -1029,7 +1039,7 @@ __global__ __launch_bounds__(256) void finish_group_kernel(BatchDev b, FinishGro
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= f.nrows) return;
-  const int sgi = find_seg(f.segs, f.nseg, row);
+  const int sgi = f.rowseg ? f.rowseg[row] : find_seg(f.segs, f.nseg, row);
   const GSeg sg = f.segs[sgi];
   const int64_t rows = f.counts ? (int64_t)f.counts[sgi] : (int64_t)sg.rows;
   if (row - sg.row0 >= rows) return;

@@ -1,0 +1,371 @@
+// BF16 matrix-core contraction of step A3 for d a multiple of 8:
+//   Y_k = (X - mu_k) P_k^T,  q_k = sum_n (X - mu_k)_n Y_kn   (FP32 accumulation)
+// NPROD = 1: BF16 operands (the mixed-precision discovery GEMM).
+// NPROD = 3: FP32 data as split operands v = hi + lo, hi = bf16(v),
+//   lo = bf16(v - hi); the product is hi*hi + hi*lo + lo*hi (lo*lo, ~2^-16
+//   relative, is dropped), so one FP32-accurate-to-~2^-16 contraction costs
+//   three BF16 MFMAs instead of eight FP32 ones.
+// Tile: 128 x 128 outputs per workgroup (four waves of 64 x 64, each a 4 x 4
+// grid of 16x16x32 MFMAs), k-tiles staged through LDS, the next k-tile
+// prefetched into registers while the current one is multiplied.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace sb {
+
+namespace {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+
+struct Bf16Params {
+  ASrc a;                   // points: rows of X (kind 0) or ray points (kind 1), FP32
+  int64_t M;
+  const int32_t *count;     // device row count (nullable -> M)
+  int d, K, ntn;
+  const float *mu;          // [K][d]
+  const bf16_t *Phi, *Plo;  // [K][d][d]
+  float *Y;                 // [M][ldy] (nullable)
+  int64_t ldy;
+  float *qpart;             // [M][K][ntn]
+};
+
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+
+// Two FP32 values to packed BF16, round to nearest even (one v_cvt_pk_bf16_f32).
+__device__ inline uint32_t pack2(float a, float b) {
+  const bf2v h = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, h);
+}
+// The FP32 values of a packed pair (low half, high half).
+__device__ inline float lo_half(uint32_t u) { return __builtin_bit_cast(float, u << 16); }
+__device__ inline float hi_half(uint32_t u) { return __builtin_bit_cast(float, u & 0xffff0000u); }
+
+template <int NPROD, int KIND, int BM, int BK>
+__global__ __launch_bounds__(256, BM == 128 ? 2 : 1) void quad_gemm_bf16_kernel(Bf16Params g) {
+  constexpr int BN = 128, LDK = BK + 8;
+  constexpr int WM = BM / 2, TM = WM / 16;  // wave tile WM x 64: TM x 4 MFMA blocks
+  constexpr int VA = BK / 4;          // float4 per A row per k-tile
+  constexpr int NA = BM * VA / 256;   // float4 loads per thread
+  constexpr int VB = BK / 8;          // 8-bf16 vectors per B row per k-tile
+  constexpr int NB = BN * VB / 256;   // per thread and operand half
+  constexpr bool SPLIT = NPROD == 3;
+  static_assert(NA >= 1 && NB >= 1 && 256 % VA == 0 && 256 % VB == 0, "tile");
+  __shared__ __attribute__((aligned(16))) bf16_t Ah[BM * LDK];
+  __shared__ __attribute__((aligned(16))) bf16_t Al[SPLIT ? BM * LDK : 8];
+  __shared__ __attribute__((aligned(16))) bf16_t Bh[BN * LDK];
+  __shared__ __attribute__((aligned(16))) bf16_t Bl[SPLIT ? BN * LDK : 8];
+  __shared__ float qs[2][BM];
+
+  // XCD-aware tile order.  Workgroup w runs on XCD w % 8; each XCD owns a
+  // fixed set of column blocks (component k, n-tile) and walks the M-tiles
+  // in order, so the workgroups sharing an M-tile's rows of A run together
+  // on one L2 and the XCD's column blocks of P stay resident in it.
+  const int ncol = g.K * g.ntn;
+  const int64_t w = blockIdx.x;
+  int col;
+  int64_t mt;
+  if (ncol % 8 == 0) {
+    const int per = ncol / 8;
+    const int64_t li = w / 8;
+    col = (int)(w % 8) + 8 * (int)(li % per);
+    mt = li / per;
+  } else {
+    col = (int)(w % ncol);
+    mt = w / ncol;
+  }
+  const int64_t M = g.count ? (int64_t)(*g.count) : g.M;
+  const int64_t m0 = mt * BM;
+  if (m0 >= M) return;
+  const int d = g.d;
+  const int k = col / g.ntn, nt = col % g.ntn;
+  const int n0 = nt * BN;
+  const float *mu = g.a.zero_mu ? nullptr : g.mu + (size_t)k * d;
+  const bf16_t *Ph = g.Phi + (size_t)k * d * d;
+  const bf16_t *Pl = SPLIT ? g.Plo + (size_t)k * d * d : nullptr;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // rows of this thread: X row, or the ray's endpoints and its parameter t
+  auto row_src = [&](int64_t row, const float *&pa, const float *&pb, float &t) {
+    if constexpr (KIND == 0) {
+      const int64_t r = g.a.rowmap ? (int64_t)g.a.rowmap[row] : row;
+      pa = (const float *)g.a.X + r * g.a.ldx;
+      pb = nullptr;
+      t = 0.f;
+    } else {
+      const int64_t ray = row / g.a.n_pts;
+      const int jj = (int)(row % g.a.n_pts);
+      t = ((float)jj + 0.5f) / (float)g.a.n_pts;
+      pa = (const float *)g.a.P0 + ray * d;
+      pb = (const float *)g.a.P1 + ray * d;
+    }
+  };
+  const int ca = tid % VA, cb = tid % VB;
+  const float *arow[NA], *brow_p[NA];
+  float tpar[NA];
+  bool aok[NA];
+#pragma unroll
+  for (int r = 0; r < NA; ++r) {
+    const int64_t row = m0 + (tid + 256 * r) / VA;
+    aok[r] = row < M;
+    arow[r] = nullptr;
+    brow_p[r] = nullptr;
+    tpar[r] = 0.f;
+    if (aok[r]) row_src(row, arow[r], brow_p[r], tpar[r]);
+  }
+  const bf16_t *bh[NB], *bl[NB];
+  bool bok[NB];
+#pragma unroll
+  for (int r = 0; r < NB; ++r) {
+    const int n = n0 + (tid + 256 * r) / VB;
+    bok[r] = n < d;
+    bh[r] = Ph + (size_t)n * d;
+    bl[r] = SPLIT ? Pl + (size_t)n * d : nullptr;
+  }
+
+  f4v ra[NA], rq[NA], rmu;
+  u4v rbh[NB], rbl[NB];
+  auto load = [&](int k0) {
+    const int ka = k0 + ca * 4;
+    const bool kin = ka < d;
+#pragma unroll
+    for (int r = 0; r < NA; ++r) {
+      const bool ok = aok[r] && kin;
+      ra[r] = ok ? *(const f4v *)(arow[r] + ka) : f4v{0.f, 0.f, 0.f, 0.f};
+      if constexpr (KIND == 1) rq[r] = ok ? *(const f4v *)(brow_p[r] + ka) : f4v{0.f, 0.f, 0.f, 0.f};
+    }
+    rmu = (mu && kin) ? *(const f4v *)(mu + ka) : f4v{0.f, 0.f, 0.f, 0.f};
+    const int kb = k0 + cb * 8;
+    const bool kbin = kb < d;
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      const bool ok = bok[r] && kbin;
+      rbh[r] = ok ? *(const u4v *)(bh[r] + kb) : u4v{0u, 0u, 0u, 0u};
+      if constexpr (SPLIT) rbl[r] = ok ? *(const u4v *)(bl[r] + kb) : u4v{0u, 0u, 0u, 0u};
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int r = 0; r < NA; ++r) {
+      const int i = (tid + 256 * r) / VA;
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float x;
+        if constexpr (KIND == 0) {
+          x = ra[r][e];
+        } else {
+#pragma clang fp contract(off)
+          x = ra[r][e] + tpar[r] * (rq[r][e] - ra[r][e]);
+        }
+        v[e] = aok[r] ? x - rmu[e] : 0.f;
+      }
+      const uint32_t h01 = pack2(v[0], v[1]), h23 = pack2(v[2], v[3]);
+      *(u2v *)&Ah[i * LDK + ca * 4] = u2v{h01, h23};
+      if constexpr (SPLIT) {
+        // v - hi is exact in FP32 (hi holds v's leading bits); lo rounds it
+        const uint32_t l01 = pack2(v[0] - lo_half(h01), v[1] - hi_half(h01));
+        const uint32_t l23 = pack2(v[2] - lo_half(h23), v[3] - hi_half(h23));
+        *(u2v *)&Al[i * LDK + ca * 4] = u2v{l01, l23};
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      const int n = (tid + 256 * r) / VB;
+      *(u4v *)&Bh[n * LDK + cb * 8] = rbh[r];
+      if constexpr (SPLIT) *(u4v *)&Bl[n * LDK + cb * 8] = rbl[r];
+    }
+  };
+
+  f4v acc[TM][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+
+  const int fr = lane & 15, fk = 8 * (lane >> 4);
+  load(0);
+  for (int k0 = 0; k0 < d; k0 += BK) {
+    store();
+    __syncthreads();
+    if (k0 + BK < d) load(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 32) {
+      bf8v ah[TM], al[TM], bhv[4], blv[4];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int o = (wm * WM + i * 16 + fr) * LDK + kk + fk;
+        ah[i] = *(const bf8v *)&Ah[o];
+        if constexpr (SPLIT) al[i] = *(const bf8v *)&Al[o];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int o = (wn * 64 + j * 16 + fr) * LDK + kk + fk;
+        bhv[j] = *(const bf8v *)&Bh[o];
+        if constexpr (SPLIT) blv[j] = *(const bf8v *)&Bl[o];
+      }
+      // product-major order: 16 independent MFMAs separate two updates of
+      // one accumulator (small cross terms first)
+      if constexpr (SPLIT) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bhv[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], blv[j], acc[i][j], 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bhv[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // Epilogue: Y, and per-row partial q over this tile's columns.  Item v of
+  // lane l holds row 4 (l / 16) + v, column l % 16 of its 16 x 16 block.
+  const int lr = lane >> 4, lc = lane & 15;
+  float qrow[TM][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) qrow[i][v] = 0.f;
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = m0 + wm * WM + i * 16 + 4 * lr + v;
+      if (row >= M) continue;
+      const float *pa, *pb;
+      float tt;
+      row_src(row, pa, pb, tt);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = n0 + wn * 64 + j * 16 + lc;
+        if (n >= d) continue;
+        const float yv = acc[i][j][v];
+        if (g.Y) g.Y[row * g.ldy + (int64_t)k * d + n] = yv;
+        float x;
+        if constexpr (KIND == 0) {
+          x = pa[n];
+        } else {
+#pragma clang fp contract(off)
+          x = pa[n] + tt * (pb[n] - pa[n]);
+        }
+        qrow[i][v] += (mu ? x - mu[n] : x) * yv;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float t = qrow[i][v];
+      t += __shfl_xor(t, 1, 64);
+      t += __shfl_xor(t, 2, 64);
+      t += __shfl_xor(t, 4, 64);
+      t += __shfl_xor(t, 8, 64);
+      qrow[i][v] = t;
+    }
+  if (lc == 0) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) qs[wn][wm * WM + i * 16 + 4 * lr + v] = qrow[i][v];
+  }
+  __syncthreads();
+  if (g.qpart) {
+    for (int i = tid; i < BM; i += 256) {
+      const int64_t row = m0 + i;
+      if (row < M) g.qpart[(row * g.K + k) * g.ntn + nt] = qs[0][i] + qs[1][i];
+    }
+  }
+}
+
+// hi = bf16(fp32(x)), lo = bf16(fp32(x - hi)) for n values.
+__global__ void split_bf16_kernel(int64_t n, const double *x, bf16_t *hi, bf16_t *lo) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const bf16_t h = f32_to_bf16((float)x[i]);
+    hi[i] = h;
+    if (lo) lo[i] = f32_to_bf16((float)(x[i] - (double)bf16_to_f32(h)));
+  }
+}
+
+}  // namespace
+
+bool quad_gemm_bf16_ok(int d) { return d >= 8 && d % 8 == 0; }
+
+int launch_quad_gemm_bf16(int nprod, const Model &m, const ASrc &a, int64_t M,
+                          const int32_t *count, QuadOut &o, hipStream_t s, TileCfg t) {
+  if (!quad_gemm_bf16_ok(m.d)) {
+    set_error("BF16 contraction needs d a multiple of 8 (got %d)", m.d);
+    return SB_E_UNSUPPORTED;
+  }
+  if (!m.mu32 || !m.Phi || (nprod == 3 && !m.Plo)) {
+    set_error("BF16 model copies missing");
+    return SB_E_INVAL;
+  }
+  // tile variants: t.bm in {128, 256} rows, t.bn reused as the k-tile in {32, 64}
+  const int BM = (t.bm == 256) ? 256 : 128;
+  const int BK = (t.bn == 64 && a.kind == 0) ? 64 : 32;  // ray points: 32 (register budget)
+  Bf16Params p;
+  p.a = a;
+  p.M = M;
+  p.count = count;
+  p.d = m.d;
+  p.K = m.K;
+  p.ntn = (int)ceil_div(m.d, 128);
+  p.mu = m.mu32;
+  p.Phi = m.Phi;
+  p.Plo = m.Plo;
+  p.Y = (float *)o.Y;
+  p.ldy = o.ldy;
+  p.qpart = (float *)o.qpart;
+  o.ntn = p.ntn;
+  const int64_t ntile = ceil_div(M, BM) * (int64_t)(m.K * p.ntn);
+  if (ntile == 0) return SB_OK;
+  if (ntile > 0x7fffffffll) {
+    set_error("contraction too large for one launch (%lld tiles)", (long long)ntile);
+    return SB_E_UNSUPPORTED;
+  }
+  dim3 grid((unsigned)ntile);
+#define SB_BF(NP, KD, BMv, BKv) \
+  hipLaunchKernelGGL((quad_gemm_bf16_kernel<NP, KD, BMv, BKv>), grid, dim3(256), 0, s, p)
+  if (a.kind == 1) {
+    if (nprod == 3 && BM == 128) SB_BF(3, 1, 128, 32);
+    else if (nprod == 3) SB_BF(3, 1, 256, 32);
+    else if (BM == 128) SB_BF(1, 1, 128, 32);
+    else SB_BF(1, 1, 256, 32);
+  } else if (nprod == 3) {
+    if (BM == 128 && BK == 32) SB_BF(3, 0, 128, 32);
+    else if (BM == 128) SB_BF(3, 0, 128, 64);
+    else SB_BF(3, 0, 256, 32);
+  } else {
+    if (BM == 128 && BK == 32) SB_BF(1, 0, 128, 32);
+    else if (BM == 128) SB_BF(1, 0, 128, 64);
+    else SB_BF(1, 0, 256, 32);
+  }
+#undef SB_BF
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+int launch_split_bf16(int64_t n, const double *x, bf16_t *hi, bf16_t *lo, hipStream_t s) {
+  if (n <= 0) return SB_OK;
+  hipLaunchKernelGGL(split_bf16_kernel, dim3((unsigned)std::min<int64_t>(8192, ceil_div(n, 256))),
+                     dim3(256), 0, s, n, x, hi, lo);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+}  // namespace sb

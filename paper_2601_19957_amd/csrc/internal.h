@@ -4,7 +4,12 @@
 
 namespace sb {
 
-enum Dtype { DT_F64 = SB_DTYPE_F64, DT_F32 = SB_DTYPE_F32, DT_BF16 = SB_DTYPE_BF16 };
+enum Dtype {
+  DT_F64 = SB_DTYPE_F64,
+  DT_F32 = SB_DTYPE_F32,
+  DT_BF16 = SB_DTYPE_BF16,
+  DT_F32S = SB_DTYPE_F32_SPLIT  // FP32 data, contraction as three BF16 products
+};
 
 // Device-side view of a likelihood (all pointers are device pointers).
 struct Model {
@@ -14,6 +19,8 @@ struct Model {
   const double *beta = nullptr;   // [K]
   const float *mu32 = nullptr;    // [K][d] (FP32 / BF16 paths)
   const void *Plp = nullptr;      // [K][d][d] FP32 or BF16 copy
+  const bf16_t *Phi = nullptr;    // [K][d][d] bf16(P) (BF16 and split contractions)
+  const bf16_t *Plo = nullptr;    // [K][d][d] bf16(P - hi) (split contraction)
   double nu = 0.0, c = 0.0;       // Student-t dof, additive constant
 };
 
@@ -95,6 +102,14 @@ struct TileCfg {
 };
 
 int quad_gemm_ntn(int dtype, int d, TileCfg t);
+// BF16 matrix-core contraction (d a multiple of 8): nprod 1 = BF16 operands,
+// 3 = split FP32 operands (hi*hi + hi*lo + lo*hi); Y and qpart in FP32.
+bool quad_gemm_bf16_ok(int d);
+// t selects the variant: t.bm rows per tile (128 / 256), t.bn the k-tile (32 / 64).
+int launch_quad_gemm_bf16(int nprod, const Model &m, const ASrc &a, int64_t M,
+                          const int32_t *count, QuadOut &o, hipStream_t s, TileCfg t);
+// hi = bf16(fp32(x)), lo = bf16(x - hi) (lo nullable) for n values.
+int launch_split_bf16(int64_t n, const double *x, bf16_t *hi, bf16_t *lo, hipStream_t s);
 int launch_quad_gemm(int dtype, const Model &m, const ASrc &a, int64_t M, const int32_t *count,
                      QuadOut &o, TileCfg t, hipStream_t s);
 
@@ -199,6 +214,7 @@ struct FinishGroupArgs {
   const GSeg *segs = nullptr;        // row segments (as given to the GEMM)
   int nseg = 0;
   int64_t nrows = 0;                 // rows spanned by the segments
+  const int32_t *rowseg = nullptr;   // row -> segment (nullable: binary search on row0)
   const int32_t *counts = nullptr;   // per-segment active rows (nullable: all)
   const void *qpart = nullptr;
   int bn = 128;                      // GEMM column tile (n-tiles per component = ceil(dp/bn))

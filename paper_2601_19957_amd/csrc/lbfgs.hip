@@ -46,7 +46,7 @@ struct LbArgs {
   const int32_t *sprob;
   const double *ptol;
   const int32_t *pmaxit;
-  int64_t s_base;
+  int64_t s_base, s_count;  // starts [s_base, s_base + s_count) of this launch
 };
 
 // Two-loop recursion on register-resident history (logical order, oldest
@@ -91,11 +91,10 @@ __device__ inline void two_loop(const T (&Sr)[kMaxHist][EPT], const T (&Yr)[kMax
   for (int e = 0; e < EPT; ++e) p[e] = -q[e];
 }
 
+// One step of start s (the whole workgroup; every branch is uniform in s).
 template <typename T, int TPB, int EPT>
-__global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
-  const int64_t s = a.s_base + blockIdx.x;
+__device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t s, T *red) {
   const int tid = threadIdx.x;
-  __shared__ T red[4 * (TPB / 64)];
   if (a.status[s] != ST_ACTIVE) {
     if (tid == 0) a.active[s] = 0;
     return;
@@ -365,6 +364,14 @@ __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
   }
 }
 
+// Starts [s_base, s_base + s_count), strided by the grid.
+template <typename T, int TPB, int EPT>
+__global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
+  __shared__ T red[4 * (TPB / 64)];
+  for (int64_t i = blockIdx.x; i < a.s_count; i += gridDim.x)
+    lbfgs_step_one<T, TPB, EPT>(a, a.s_base + i, red);
+}
+
 // Two-loop direction only, for B independent histories given in logical
 // order (used to check the recursion in isolation).
 template <typename T, int TPB, int EPT>
@@ -477,14 +484,23 @@ static LbArgs<T> make_args(const LbfgsBuffers &b, int max_iter, double tol) {
   a.ptol = b.ptol;
   a.pmaxit = b.pmaxit;
   a.s_base = 0;
+  a.s_count = b.B;
   return a;
+}
+
+// One workgroup per start of the launch: the dispatcher hands freed slots
+// to the next start, which balances starts of uneven cost (a fixed grid
+// striding over starts measured slower: its last round runs part-empty).
+static int64_t step_grid(int d, int64_t count) {
+  (void)d;
+  return count;
 }
 
 int launch_lbfgs_step(const LbfgsBuffers &b, int max_iter, double grad_tol, hipStream_t s) {
   int st = check_d(b.d, b.m);
   if (st) return st;
   const int d = b.d;
-  const int64_t B = b.B;
+  const int64_t B = step_grid(d, b.B);
   if (B <= 0) return SB_OK;
   if (b.dtype == DT_F64) {
     LbArgs<double> a = make_args<double>(b, max_iter, grad_tol);
@@ -508,14 +524,16 @@ int launch_lbfgs_step_range(const LbfgsBuffers &b, int64_t s_begin, int64_t coun
     return SB_E_INVAL;
   }
   const int d = d_class;
-  const int64_t B = count;
+  const int64_t B = step_grid(d, count);
   if (b.dtype == DT_F64) {
     LbArgs<double> a = make_args<double>(b, max_iter, grad_tol);
     a.s_base = s_begin;
+    a.s_count = count;
     SB_LB_CASES(lbfgs_step_kernel, double, a);
   } else {
     LbArgs<float> a = make_args<float>(b, max_iter, grad_tol);
     a.s_base = s_begin;
+    a.s_count = count;
     SB_LB_CASES(lbfgs_step_kernel, float, a);
   }
   SB_LAUNCH_CHECK();

@@ -159,7 +159,8 @@ struct Timer {
 // One evaluation of l (+grad, +aux) at B rows of X through GEMM + finish.
 struct Evaluator {
   Model m;
-  int dtype = DT_F64;
+  int dtype = DT_F64;      // data / epilogue type
+  int gemm_dtype = -1;     // contraction type (-1: dtype)
   int64_t cap = 0;  // rows
   void *Y = nullptr, *qpart = nullptr;
   int64_t ldy = 0;
@@ -184,7 +185,7 @@ struct Evaluator {
     o.Y = want_y ? Y : nullptr;
     o.ldy = ldy;
     o.qpart = qpart;
-    int st = launch_quad_gemm(dtype, m, a, M, count, o, tile, s);
+    int st = launch_quad_gemm(gemm_dtype >= 0 ? gemm_dtype : dtype, m, a, M, count, o, tile, s);
     if (st) return st;
     ntn = o.ntn;
     FinishArgs f;
@@ -245,7 +246,7 @@ struct Layout {
   double *Lprep = nullptr, *logdetP = nullptr, *beta = nullptr, *mx = nullptr;
   int32_t *info = nullptr, *flags = nullptr;
   float *P32 = nullptr, *mu32 = nullptr;
-  bf16_t *Pbf = nullptr;
+  bf16_t *Pbf = nullptr, *Plo = nullptr;
   // discovery
   double *P0 = nullptr, *P1 = nullptr, *best_l = nullptr, *X0 = nullptr;
   float *P0f = nullptr, *P1f = nullptr;
@@ -291,6 +292,7 @@ static int carve_layout(Arena &ar, Layout &L, const sb_loglik *ll, const RunCfg 
   if (mixed) {
     L.P32 = ar.take<float>((size_t)K * d * d);
     L.Pbf = ar.take<bf16_t>((size_t)K * d * d);
+    L.Plo = ar.take<bf16_t>((size_t)K * d * d);
     L.mu32 = ar.take<float>((size_t)K * d);
   }
   L.P0 = ar.take<double>((size_t)R * d);
@@ -563,6 +565,7 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
   if ((st = launch_beta(m64, P.log_w, L.logdetP, L.beta, s))) return st;
   if (mixed) {
     if ((st = launch_convert_model(m64, L.P32, L.Pbf, L.mu32, s))) return st;
+    if ((st = launch_split_bf16((int64_t)K * d * d, P.prec, L.Pbf, L.Plo, s))) return st;
   }
   {
     int32_t hflag[1];
@@ -601,6 +604,7 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     if (mixed) {
       md.mu32 = L.mu32;
       md.Plp = L.Pbf;
+      md.Phi = L.Pbf;
     }
     L.disc.m = md;
     {
@@ -626,6 +630,8 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     if (mixed) {
       mb.mu32 = L.mu32;
       mb.Plp = L.P32;
+      mb.Phi = L.Pbf;
+      mb.Plo = L.Plo;
       double maxabs_theta = 0.0;
       std::vector<double> hlo(d), hhi(d);
       SB_HIP(hipMemcpyAsync(hlo.data(), P.lo, sizeof(double) * d, hipMemcpyDeviceToHost, s));
@@ -640,7 +646,12 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     }
     L.bulk.m = mb;
     L.bulk.dtype = mixed ? DT_F32 : DT_F64;
-    L.bulk.tile = autotune_tiles(L.bulk.dtype, mb, rc.n_starts, s);
+    // mixed bulk: the contraction on the BF16 matrix cores with split operands
+    // (SB_BULK_GEMM=f32 keeps the FP32 matrix-core kernel)
+    const char *bg = getenv("SB_BULK_GEMM");
+    const bool split = mixed && quad_gemm_bf16_ok(d) && !(bg && bg[0] == 'f');
+    L.bulk.gemm_dtype = split ? DT_F32S : -1;
+    if (!split) L.bulk.tile = autotune_tiles(L.bulk.dtype, mb, rc.n_starts, s);
     int64_t bulk_evals = 0;
     int steps = 0;
     if ((st = run_bulk(L, rc, tol, s, &bulk_evals, &steps))) return st;

@@ -1,0 +1,104 @@
+"""The split-BF16 contraction (dtype F32_SPLIT) and its operand copies.
+
+FP32 data v is carried as hi = bf16(v) plus lo = bf16(v - hi); each product
+is formed as hi*hi + hi*lo + lo*hi with FP32 accumulation.  Per product the
+dropped lo*lo and the two representation remainders are each below about
+2^-16 of |x y|, so every output obeys |Y - Y_exact| <= 2^-14 sum_j |P_nj
+delta_j| (this also absorbs the FP32 rounding of delta and of the d-term
+sums).  A missing cross term would exceed that bound by ~2^6.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2601_19957_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2601_19957_amd import _lib
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    _lib.lib()
+    return _lib
+
+
+def gaussian(d, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = synth.gaussian_mixture(rng, d, 1, -8.0, 8.0, 1e-3, 1.0, 0.0, box_half=30.0,
+                               norm=synth.NORM_PEAK_ZERO)
+    p.mu = p.mu.astype(np.float32).astype(np.float64)  # the GPU's FP32 mean, exactly
+    return p
+
+
+@pytest.mark.parametrize("d,B", [(8, 5), (64, 300), (200, 129), (1024, 260)])
+def test_split_contraction_within_bound(L, d, B):
+    prob = gaussian(d, 900 + d)
+    X = synth.random_points(prob, B, 901, spread=0.7).astype(np.float32).astype(np.float64)
+    m = L.DeviceModel(prob, low_precision=True)
+    _, g = L.sb_logl_grad_dev(m, torch.as_tensor(X, device="cuda").float(),
+                              dtype=L.DTYPE_F32_SPLIT)
+    g = g.double().cpu().numpy()
+    _, g_ref = O.logl(prob, X)  # K = 1: grad l = -P (x - mu), exactly the contraction
+    delta = X - prob.mu[0]
+    bound = 2.0 ** -14 * (np.abs(delta) @ np.abs(prob.prec[0]).T) + 1e-30
+    ratio = float(np.max(np.abs(g - g_ref) / bound))
+    assert ratio <= 1.0, ratio
+
+
+def test_split_quadform_matches_fp32_kernel(L):
+    """Same FP32 data through the FP32 and the split contraction: Y agree to the split bound."""
+    prob = synth.make_problem("c1")
+    X = torch.as_tensor(synth.points_near_modes(prob, 300, 5, scale=1.0), device="cuda").float()
+    m = L.DeviceModel(prob, low_precision=True)
+    q32 = L.QuadForm(m, X)
+    qs = L.QuadForm(m, X, dtype=L.DTYPE_F32_SPLIT)
+    q32()
+    qs()
+    torch.cuda.synchronize()
+    y32, ys = q32.Y.double().cpu().numpy(), qs.Y.double().cpu().numpy()
+    delta = X.double().cpu().numpy()[:, None, :] - prob.mu[None, :, :]
+    bound = 2.0 ** -13 * np.einsum("bkj,knj->bkn", np.abs(delta), np.abs(prob.prec))
+    err = np.abs(ys - y32).reshape(bound.shape)
+    assert float(np.max(err / (bound + 1e-30))) <= 1.0
+
+
+def test_split_copy_bits(L):
+    """hi / lo bit patterns against torch's round-to-nearest-even BF16 conversion."""
+    rng = np.random.Generator(np.random.PCG64(77))
+    x = np.concatenate([rng.standard_normal(5000) * 10.0 ** rng.uniform(-6, 6, 5000),
+                        [0.0, -0.0, 1.0, 3.0e38, -1e-30, 65504.0]])
+    xd = torch.as_tensor(x, device="cuda")
+    hi = torch.empty(x.size, dtype=torch.int16, device="cuda")
+    lo = torch.empty(x.size, dtype=torch.int16, device="cuda")
+    L._check(L.lib().sb_split_bf16_dev(x.size, xd.data_ptr(), hi.data_ptr(), lo.data_ptr(), 0),
+             "sb_split_bf16_dev")
+    torch.cuda.synchronize()
+    t = torch.as_tensor(x.astype(np.float32))
+    hi_ref = t.to(torch.bfloat16)
+    lo_ref = torch.as_tensor((x - hi_ref.double().numpy()).astype(np.float32)).to(torch.bfloat16)
+    assert torch.equal(hi.cpu(), hi_ref.view(torch.int16))
+    assert torch.equal(lo.cpu(), lo_ref.view(torch.int16))
+
+
+@pytest.mark.parametrize("name", ["c1", "t_d256"])
+def test_split_logl_grad(L, name):
+    if name == "c1":
+        prob = synth.make_problem("c1")
+    else:
+        rng = np.random.Generator(np.random.PCG64(5))
+        prob = synth.student_t(rng, 256, 30.0, -5.0, 5.0, 0.01, 1.0, 20.0)
+    X = synth.points_near_modes(prob, 200, 13, scale=0.5)
+    lo, go = O.logl(prob, X)
+    m = L.DeviceModel(prob, low_precision=True)
+    l, g = L.sb_logl_grad_dev(m, torch.as_tensor(X, device="cuda").float(),
+                              dtype=L.DTYPE_F32_SPLIT)
+    l, g = l.double().cpu().numpy(), g.double().cpu().numpy()
+    q_scale = np.maximum(1.0, np.abs(lo - O.prep(prob)[1].max()))
+    el = float(np.max(np.abs(l - lo) / (q_scale + np.abs(lo))))
+    eg = float(np.max(np.abs(g - go) / np.maximum(1.0, np.abs(go).max(axis=1, keepdims=True))))
+    assert el < 5e-4 and eg < 5e-4, (el, eg)
