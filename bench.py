@@ -55,14 +55,15 @@ def closed_form_logz(prob) -> float:
     return -logv  # normalised mixture: total mass 1
 
 
-def time_quadform(L, prob, B, reps=20):
-    """Average duration of the FP32 A3 GEMM at the bulk shape, HIP events on its stream."""
+def time_quadform(L, prob, B, reps=20, dtype=None):
+    """Average duration of the A3 contraction at the bulk shape (the split-BF16 kernel the
+    mixed bulk runs, or another dtype), HIP events on its stream."""
     import torch
     from paper_2601_19957_amd import synth
 
     m = L.DeviceModel(prob, low_precision=True)
     X = torch.as_tensor(synth.points_near_modes(prob, B, 5, scale=0.3), device="cuda").float()
-    qf = L.QuadForm(m, X)
+    qf = L.QuadForm(m, X, dtype=L.DTYPE_F32_SPLIT if dtype is None else dtype)
     stream = torch.cuda.current_stream()
     for _ in range(3):
         qf(stream)
@@ -79,8 +80,8 @@ def time_quadform(L, prob, B, reps=20):
     return avg_s, flops
 
 
-def recorded_traffic(summary="profiles/quad_gemm_f32_B16384_d1024_K8.md",
-                     source="paper_2601_19957_amd/csrc/gemm.hip"):
+def recorded_traffic(summary="profiles/quad_gemm_split_B16384_d1024_K8.md",
+                     source="paper_2601_19957_amd/csrc/gemm_bf16.hip"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
     kernel source changed since the counters were taken."""
     import hashlib
@@ -198,16 +199,22 @@ def main() -> int:
     big = names[-1]
     prob_big, cfg_big = wl[big]
 
-    # ---- roofline kernel: FP32 quadratic-form GEMM at the bulk shape of the largest posterior
-    log("timing the A3 GEMM (FP32) at the bulk shape")
+    # ---- roofline kernel: the bulk contraction (split BF16) at the largest posterior's shape
+    log("timing the A3 contraction (split BF16) at the bulk shape")
     kt_s, kflops = time_quadform(L, prob_big, cfg_big.n_starts)
+    kt32_s, _ = time_quadform(L, prob_big, cfg_big.n_starts, reps=5, dtype=L.DTYPE_F32)
     traffic = recorded_traffic() if (prob_big.d, prob_big.K, cfg_big.n_starts) == (1024, 8, 16384) \
         else None
-    roofline = dict(bound="mfma", achieved=kflops / kt_s / 1e12, peak=PEAK["fp32"],
-                    unit="TFLOP/s", frac=(kflops / kt_s / 1e12) / PEAK["fp32"], traffic=traffic,
-                    kernel="quad_gemm_kernel<float,float> (A3 logL+grad contraction)",
+    achieved = kflops / kt_s / 1e12
+    roofline = dict(bound="mfma", achieved=achieved, peak=PEAK["bf16"], unit="TFLOP/s",
+                    frac=achieved / PEAK["bf16"], traffic=traffic,
+                    kernel="quad_gemm_bf16_kernel<3,0,...> (A3 contraction, FP32 data as "
+                           "split BF16: 3 MFMA products per multiply-add)",
                     shape=f"B={cfg_big.n_starts} d={prob_big.d} K={prob_big.K}",
-                    avg_launch_us=kt_s * 1e6)
+                    avg_launch_us=kt_s * 1e6,
+                    executed_mfma_frac=3.0 * achieved / PEAK["bf16"],
+                    fp32_equivalent_frac=achieved / PEAK["fp32"],
+                    fp32_kernel_us=kt32_s * 1e6)
     if args.kernel_only:
         # a plain copy of known size, to calibrate HBM byte counters of the same run;
         # a 1 GiB fill in between evicts the source from the 256 MB last-level cache

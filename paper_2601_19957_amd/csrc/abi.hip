@@ -664,6 +664,7 @@ int32_t sb_lbfgs_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m, int
     a.X = lb.X;
     a.ldx = d;
     a.rowmap = rowmap;
+    a.rows = 2 * B;  // both slots
     QuadOut o;
     o.Y = Y;
     o.ldy = (int64_t)md.K * d;

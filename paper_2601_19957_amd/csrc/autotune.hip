@@ -2,11 +2,12 @@
 //
 // The first time a shape class (dtype, d, K, M rounded up to a power of two)
 // is seen, each candidate tile (BM x BN in {64, 128}^2; for the BF16 and
-// split contractions BM x k-tile in {128 x 32, 128 x 64, 256 x 32}) is timed with HIP
+// split contractions BM x BN x k-tile in {128x128x32, 128x128x64, 256x128x32,
+// 128x256x32}) is timed with HIP
 // events on device buffers of that shape (up to 8192 rows, seeded values in
 // [-1, 1)), and the fastest is cached for the process.  Timing needs its own
 // allocations and a synchronisation, so a stream under graph capture gets
-// the heuristic choice (not cached).  SB_TILE=BMxBN forces a shape;
+// the heuristic choice (not cached).  SB_TILE=BMxBN[xBK] forces a shape;
 // SB_AUTOTUNE=0 uses the heuristic without timing.
 #include <cstdio>
 #include <cstdlib>
@@ -117,14 +118,15 @@ bool time_candidates(int dtype, int d, int K, int64_t M, hipStream_t s, TileCfg 
   bool ok = hipEventCreate(&e0) == hipSuccess;
   ok = ok && hipEventCreate(&e1) == hipSuccess;
   float best_ms = 0.f;
-  // GEMM tiles (BM, BN); for the BF16 kernels (BM, k-tile)
+  // GEMM tiles (BM, BN); for the BF16 kernels (BM, BN, k-tile)
   const int cands[4][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}};
-  const int cands_bf[3][2] = {{128, 32}, {128, 64}, {256, 32}};
-  const int nc = bf ? 3 : 4;
+  const int cands_bf[4][3] = {{128, 128, 32}, {128, 128, 64}, {256, 128, 32}, {128, 256, 32}};
+  const int nc = 4;
   for (int c = 0; c < nc && ok; ++c) {
     TileCfg t;
     t.bm = bf ? cands_bf[c][0] : cands[c][0];
     t.bn = bf ? cands_bf[c][1] : cands[c][1];
+    t.bk = bf ? cands_bf[c][2] : 32;
     QuadOut o;
     o.Y = Y;
     o.ldy = (int64_t)K * d;
@@ -153,11 +155,12 @@ bool time_candidates(int dtype, int d, int K, int64_t M, hipStream_t s, TileCfg 
 TileCfg autotune_tiles(int dtype, const Model &m, int64_t M, hipStream_t s) {
   const char *force = getenv("SB_TILE");
   if (force) {
-    int bm = 0, bn = 0;
-    if (sscanf(force, "%dx%d", &bm, &bn) == 2) {
+    int bm = 0, bn = 0, bk = 32;
+    if (sscanf(force, "%dx%dx%d", &bm, &bn, &bk) >= 2) {
       TileCfg t;
       t.bm = bm;
       t.bn = bn;
+      t.bk = bk;
       return t;
     }
   }

@@ -684,11 +684,13 @@ __global__ __launch_bounds__(256) void finish_kernel(Model m, FinishArgs f) {
       if (k == lane) ((T *)f.aux)[row * K + k] = r[k];
   }
   if (gout) {
+    // components whose responsibility rounds to zero in T add nothing: their
+    // Y rows are not read (separated mixtures touch one row of K)
     for (int n = lane; n < d; n += 64) {
       T s = 0;
 #pragma unroll
       for (int k = 0; k < kMaxK; ++k)
-        if (k < K) s += r[k] * Y[(size_t)k * d + n];
+        if (k < K && r[k] != (T)0) s += r[k] * Y[(size_t)k * d + n];
       gout[n] = -s;
     }
   }
@@ -866,14 +868,24 @@ int launch_convert_model(const Model &m, float *P32, bf16_t *Pbf, float *mu32, h
 
 // Per-component max |P_k| into mx[k], then bad[0] = 1 if any
 // |P_ij - P_ji| > 1e-12 * mx[k].
-__global__ void maxabs_kernel(const double *P, int d, double *mx) {
-  const int k = blockIdx.x;
+// max |P_k| over (chunks x K) workgroups: each reduces a strided share and
+// folds it in with an integer atomic max on the bit pattern (non-negative
+// doubles order like their bits; a NaN entry yields a NaN-pattern maximum).
+__global__ void zero_f64_kernel(int n, double *x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+__global__ __launch_bounds__(256) void maxabs_kernel(const double *P, int d, double *mx) {
+  const int k = blockIdx.y;
   const double *Pk = P + (size_t)k * d * d;
   __shared__ double red[4];
   double v = 0;
-  for (int64_t e = threadIdx.x; e < (int64_t)d * d; e += 256) v = fmax(v, fabs(Pk[e]));
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < (int64_t)d * d;
+       e += (int64_t)gridDim.x * 256)
+    v = fmax(v, fabs(Pk[e]));
   v = block_max<256>(v, red);
-  if (threadIdx.x == 0) mx[k] = v;
+  if (threadIdx.x == 0)
+    atomicMax((unsigned long long *)&mx[k], (unsigned long long)__double_as_longlong(v));
 }
 __global__ void symmetry_kernel(const double *P, int d, const double *mx, int32_t *bad) {
   const int k = blockIdx.y;
@@ -888,7 +900,9 @@ __global__ void symmetry_kernel(const double *P, int d, const double *mx, int32_
 
 int launch_symmetry_check(const double *P, int K, int d, double *mx, int32_t *bad,
                           hipStream_t s) {
-  hipLaunchKernelGGL(maxabs_kernel, dim3(K), dim3(256), 0, s, P, d, mx);
+  hipLaunchKernelGGL(zero_f64_kernel, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, s, K, mx);
+  const unsigned chunks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, ceil_div((int64_t)d * d, 4096)));
+  hipLaunchKernelGGL(maxabs_kernel, dim3(chunks, K), dim3(256), 0, s, P, d, mx);
   SB_LAUNCH_CHECK();
   dim3 grid((unsigned)ceil_div((int64_t)d * d, 256), (unsigned)K);
   hipLaunchKernelGGL(symmetry_kernel, grid, dim3(256), 0, s, P, d, mx, bad);
@@ -1102,11 +1116,13 @@ __global__ __launch_bounds__(256) void finish_group_kernel(BatchDev b, FinishGro
       if (k == lane) ((T *)f.aux)[row * f.auxs + k] = r[k];
   }
   if (gout) {
+    // components whose responsibility rounds to zero in T add nothing: their
+    // Y rows are not read (separated mixtures touch one row of K)
     for (int n = lane; n < d; n += 64) {
       T s = 0;
 #pragma unroll
       for (int k = 0; k < kMaxK; ++k)
-        if (k < K) s += r[k] * Y[(size_t)k * d + n];
+        if (k < K && r[k] != (T)0) s += r[k] * Y[(size_t)k * d + n];
       gout[n] = -s;
     }
   }

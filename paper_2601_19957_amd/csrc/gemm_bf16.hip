@@ -44,20 +44,29 @@ __device__ inline uint32_t pack2(float a, float b) {
 __device__ inline float lo_half(uint32_t u) { return __builtin_bit_cast(float, u << 16); }
 __device__ inline float hi_half(uint32_t u) { return __builtin_bit_cast(float, u & 0xffff0000u); }
 
-template <int NPROD, int KIND, int BM, int BK>
-__global__ __launch_bounds__(256, BM == 128 ? 2 : 1) void quad_gemm_bf16_kernel(Bf16Params g) {
-  constexpr int BN = 128, LDK = BK + 8;
-  constexpr int WM = BM / 2, TM = WM / 16;  // wave tile WM x 64: TM x 4 MFMA blocks
+template <int NPROD, int KIND, int BM, int BN, int BK>
+__global__ __launch_bounds__(256, (BM == 128 && BN == 128) ? 2 : 1) void quad_gemm_bf16_kernel(
+    Bf16Params g) {
+  // LDS rows of BK bf16 without padding; the 16-byte chunk c of row r sits
+  // at chunk c ^ swz(r), swz(r) = (r / R) mod C (C chunks per row, R rows per
+  // 32 banks): the row-wise tile stores and the 8-row fragment reads both
+  // touch 32 distinct banks per cycle.
+  constexpr int C = BK / 8, R = 64 / BK;
+  auto lds = [](int row, int kel) {  // element index of (row, k) in an LDS tile
+    return row * BK + ((((kel >> 3) ^ ((row / R) % C))) << 3) + (kel & 7);
+  };
+  constexpr int WM = BM / 2, TM = WM / 16;  // wave tile WM x WN: TM x TN MFMA blocks
+  constexpr int WN = BN / 2, TN = WN / 16;
   constexpr int VA = BK / 4;          // float4 per A row per k-tile
   constexpr int NA = BM * VA / 256;   // float4 loads per thread
   constexpr int VB = BK / 8;          // 8-bf16 vectors per B row per k-tile
   constexpr int NB = BN * VB / 256;   // per thread and operand half
   constexpr bool SPLIT = NPROD == 3;
   static_assert(NA >= 1 && NB >= 1 && 256 % VA == 0 && 256 % VB == 0, "tile");
-  __shared__ __attribute__((aligned(16))) bf16_t Ah[BM * LDK];
-  __shared__ __attribute__((aligned(16))) bf16_t Al[SPLIT ? BM * LDK : 8];
-  __shared__ __attribute__((aligned(16))) bf16_t Bh[BN * LDK];
-  __shared__ __attribute__((aligned(16))) bf16_t Bl[SPLIT ? BN * LDK : 8];
+  __shared__ __attribute__((aligned(16))) bf16_t Ah[BM * BK];
+  __shared__ __attribute__((aligned(16))) bf16_t Al[SPLIT ? BM * BK : 8];
+  __shared__ __attribute__((aligned(16))) bf16_t Bh[BN * BK];
+  __shared__ __attribute__((aligned(16))) bf16_t Bl[SPLIT ? BN * BK : 8];
   __shared__ float qs[2][BM];
 
   // XCD-aware tile order.  Workgroup w runs on XCD w % 8; each XCD owns a
@@ -83,69 +92,71 @@ __global__ __launch_bounds__(256, BM == 128 ? 2 : 1) void quad_gemm_bf16_kernel(
   const int d = g.d;
   const int k = col / g.ntn, nt = col % g.ntn;
   const int n0 = nt * BN;
-  const float *mu = g.a.zero_mu ? nullptr : g.mu + (size_t)k * d;
-  const bf16_t *Ph = g.Phi + (size_t)k * d * d;
-  const bf16_t *Pl = SPLIT ? g.Plo + (size_t)k * d * d : nullptr;
+  const float *mu = g.mu + (size_t)k * d;
+  const char *Phb = (const char *)(g.Phi + (size_t)k * d * d);
+  const char *Plb = SPLIT ? (const char *)(g.Plo + (size_t)k * d * d) : nullptr;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  // rows of this thread: X row, or the ray's endpoints and its parameter t
-  auto row_src = [&](int64_t row, const float *&pa, const float *&pb, float &t) {
+  // Element offset of point row `row`'s data (kind 0: its X row; kind 1: its
+  // ray's endpoint rows) and the ray parameter t.  The host guarantees the
+  // operand arrays are below 4 GiB, so byte offsets fit in 32 bits.
+  auto row_off = [&](int64_t row, uint32_t &off, float &t) {
     if constexpr (KIND == 0) {
       const int64_t r = g.a.rowmap ? (int64_t)g.a.rowmap[row] : row;
-      pa = (const float *)g.a.X + r * g.a.ldx;
-      pb = nullptr;
+      off = (uint32_t)(r * g.a.ldx);
       t = 0.f;
     } else {
       const int64_t ray = row / g.a.n_pts;
       const int jj = (int)(row % g.a.n_pts);
       t = ((float)jj + 0.5f) / (float)g.a.n_pts;
-      pa = (const float *)g.a.P0 + ray * d;
-      pb = (const float *)g.a.P1 + ray * d;
+      off = (uint32_t)(ray * d);
     }
   };
+  const char *Xa = (const char *)(KIND == 0 ? g.a.X : g.a.P0);
+  const char *Xb = (const char *)g.a.P1;
   const int ca = tid % VA, cb = tid % VB;
-  const float *arow[NA], *brow_p[NA];
+  uint32_t aoff[NA];  // byte offsets of this thread's A rows (rows >= M read row m0)
   float tpar[NA];
   bool aok[NA];
 #pragma unroll
   for (int r = 0; r < NA; ++r) {
     const int64_t row = m0 + (tid + 256 * r) / VA;
     aok[r] = row < M;
-    arow[r] = nullptr;
-    brow_p[r] = nullptr;
-    tpar[r] = 0.f;
-    if (aok[r]) row_src(row, arow[r], brow_p[r], tpar[r]);
+    uint32_t off;
+    row_off(aok[r] ? row : m0, off, tpar[r]);
+    aoff[r] = 4u * (off + (uint32_t)(ca * 4));
   }
-  const bf16_t *bh[NB], *bl[NB];
+  uint32_t boff[NB];  // byte offsets of this thread's B rows (rows >= d read row 0)
   bool bok[NB];
 #pragma unroll
   for (int r = 0; r < NB; ++r) {
     const int n = n0 + (tid + 256 * r) / VB;
     bok[r] = n < d;
-    bh[r] = Ph + (size_t)n * d;
-    bl[r] = SPLIT ? Pl + (size_t)n * d : nullptr;
+    boff[r] = 2u * ((uint32_t)(bok[r] ? n : 0) * (uint32_t)d + (uint32_t)(cb * 8));
   }
+  const uint32_t muoff = 4u * (uint32_t)(ca * 4);
 
   f4v ra[NA], rq[NA], rmu;
   u4v rbh[NB], rbl[NB];
+  // k-tile loads; a full tile (k0 + BK <= d, uniform) needs no column test
   auto load = [&](int k0) {
-    const int ka = k0 + ca * 4;
-    const bool kin = ka < d;
+    const bool full = k0 + BK <= d;
+    const bool kin = full || (k0 + ca * 4 < d);
+    const uint32_t ka = 4u * (uint32_t)k0;
 #pragma unroll
     for (int r = 0; r < NA; ++r) {
-      const bool ok = aok[r] && kin;
-      ra[r] = ok ? *(const f4v *)(arow[r] + ka) : f4v{0.f, 0.f, 0.f, 0.f};
-      if constexpr (KIND == 1) rq[r] = ok ? *(const f4v *)(brow_p[r] + ka) : f4v{0.f, 0.f, 0.f, 0.f};
+      ra[r] = kin ? *(const f4v *)(Xa + (aoff[r] + ka)) : f4v{0.f, 0.f, 0.f, 0.f};
+      if constexpr (KIND == 1)
+        rq[r] = kin ? *(const f4v *)(Xb + (aoff[r] + ka)) : f4v{0.f, 0.f, 0.f, 0.f};
     }
-    rmu = (mu && kin) ? *(const f4v *)(mu + ka) : f4v{0.f, 0.f, 0.f, 0.f};
-    const int kb = k0 + cb * 8;
-    const bool kbin = kb < d;
+    rmu = kin ? *(const f4v *)((const char *)mu + (muoff + ka)) : f4v{0.f, 0.f, 0.f, 0.f};
+    const bool kbin = full || (k0 + cb * 8 < d);
+    const uint32_t kb = 2u * (uint32_t)k0;
 #pragma unroll
     for (int r = 0; r < NB; ++r) {
-      const bool ok = bok[r] && kbin;
-      rbh[r] = ok ? *(const u4v *)(bh[r] + kb) : u4v{0u, 0u, 0u, 0u};
-      if constexpr (SPLIT) rbl[r] = ok ? *(const u4v *)(bl[r] + kb) : u4v{0u, 0u, 0u, 0u};
+      rbh[r] = kbin ? *(const u4v *)(Phb + (boff[r] + kb)) : u4v{0u, 0u, 0u, 0u};
+      if constexpr (SPLIT) rbl[r] = kbin ? *(const u4v *)(Plb + (boff[r] + kb)) : u4v{0u, 0u, 0u, 0u};
     }
   };
   auto store = [&]() {
@@ -165,27 +176,29 @@ __global__ __launch_bounds__(256, BM == 128 ? 2 : 1) void quad_gemm_bf16_kernel(
         v[e] = aok[r] ? x - rmu[e] : 0.f;
       }
       const uint32_t h01 = pack2(v[0], v[1]), h23 = pack2(v[2], v[3]);
-      *(u2v *)&Ah[i * LDK + ca * 4] = u2v{h01, h23};
+      const int ai = lds(i, ca * 4);
+      *(u2v *)&Ah[ai] = u2v{h01, h23};
       if constexpr (SPLIT) {
         // v - hi is exact in FP32 (hi holds v's leading bits); lo rounds it
         const uint32_t l01 = pack2(v[0] - lo_half(h01), v[1] - hi_half(h01));
         const uint32_t l23 = pack2(v[2] - lo_half(h23), v[3] - hi_half(h23));
-        *(u2v *)&Al[i * LDK + ca * 4] = u2v{l01, l23};
+        *(u2v *)&Al[ai] = u2v{l01, l23};
       }
     }
 #pragma unroll
     for (int r = 0; r < NB; ++r) {
       const int n = (tid + 256 * r) / VB;
-      *(u4v *)&Bh[n * LDK + cb * 8] = rbh[r];
-      if constexpr (SPLIT) *(u4v *)&Bl[n * LDK + cb * 8] = rbl[r];
+      const int bi = lds(n, cb * 8);
+      *(u4v *)&Bh[bi] = bok[r] ? rbh[r] : u4v{0u, 0u, 0u, 0u};
+      if constexpr (SPLIT) *(u4v *)&Bl[bi] = bok[r] ? rbl[r] : u4v{0u, 0u, 0u, 0u};
     }
   };
 
-  f4v acc[TM][4];
+  f4v acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < TN; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
 
   const int fr = lane & 15, fk = 8 * (lane >> 4);
   load(0);
@@ -195,37 +208,37 @@ __global__ __launch_bounds__(256, BM == 128 ? 2 : 1) void quad_gemm_bf16_kernel(
     if (k0 + BK < d) load(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 32) {
-      bf8v ah[TM], al[TM], bhv[4], blv[4];
+      bf8v ah[TM], al[TM], bhv[TN], blv[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        const int o = (wm * WM + i * 16 + fr) * LDK + kk + fk;
+        const int o = lds(wm * WM + i * 16 + fr, kk + fk);
         ah[i] = *(const bf8v *)&Ah[o];
         if constexpr (SPLIT) al[i] = *(const bf8v *)&Al[o];
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int o = (wn * 64 + j * 16 + fr) * LDK + kk + fk;
+      for (int j = 0; j < TN; ++j) {
+        const int o = lds(wn * WN + j * 16 + fr, kk + fk);
         bhv[j] = *(const bf8v *)&Bh[o];
         if constexpr (SPLIT) blv[j] = *(const bf8v *)&Bl[o];
       }
-      // product-major order: 16 independent MFMAs separate two updates of
-      // one accumulator (small cross terms first)
+      // product-major order: TM x TN independent MFMAs separate two updates
+      // of one accumulator (small cross terms first)
       if constexpr (SPLIT) {
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < TN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bhv[j], acc[i][j], 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < TN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], blv[j], acc[i][j], 0, 0, 0);
       }
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bhv[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
@@ -245,12 +258,14 @@ __global__ __launch_bounds__(256, BM == 128 ? 2 : 1) void quad_gemm_bf16_kernel(
     for (int v = 0; v < 4; ++v) {
       const int64_t row = m0 + wm * WM + i * 16 + 4 * lr + v;
       if (row >= M) continue;
-      const float *pa, *pb;
+      uint32_t off;
       float tt;
-      row_src(row, pa, pb, tt);
+      row_off(row, off, tt);
+      const float *pa = (const float *)Xa + off;
+      const float *pb = (const float *)Xb + off;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int n = n0 + wn * 64 + j * 16 + lc;
+      for (int j = 0; j < TN; ++j) {
+        const int n = n0 + wn * WN + j * 16 + lc;
         if (n >= d) continue;
         const float yv = acc[i][j][v];
         if (g.Y) g.Y[row * g.ldy + (int64_t)k * d + n] = yv;
@@ -261,7 +276,7 @@ __global__ __launch_bounds__(256, BM == 128 ? 2 : 1) void quad_gemm_bf16_kernel(
 #pragma clang fp contract(off)
           x = pa[n] + tt * (pb[n] - pa[n]);
         }
-        qrow[i][v] += (mu ? x - mu[n] : x) * yv;
+        qrow[i][v] += (x - mu[n]) * yv;
       }
     }
   }
@@ -311,20 +326,29 @@ int launch_quad_gemm_bf16(int nprod, const Model &m, const ASrc &a, int64_t M,
     set_error("BF16 contraction needs d a multiple of 8 (got %d)", m.d);
     return SB_E_UNSUPPORTED;
   }
-  if (!m.mu32 || !m.Phi || (nprod == 3 && !m.Plo)) {
+  if (!m.mu32 || !m.Phi || (nprod == 3 && !m.Plo) || a.zero_mu) {
     set_error("BF16 model copies missing");
     return SB_E_INVAL;
   }
-  // tile variants: t.bm in {128, 256} rows, t.bn reused as the k-tile in {32, 64}
-  const int BM = (t.bm == 256) ? 256 : 128;
-  const int BK = (t.bn == 64 && a.kind == 0) ? 64 : 32;  // ray points: 32 (register budget)
+  // operand arrays addressed with 32-bit byte offsets
+  const int64_t a_rows = a.kind == 0 ? std::max<int64_t>(a.rows, M) : ceil_div(M, a.n_pts);
+  const int64_t a_ld = a.kind == 0 ? a.ldx : m.d;
+  if (4 * a_rows * a_ld >= ((int64_t)1 << 32) || 2 * (int64_t)m.d * m.d >= ((int64_t)1 << 32)) {
+    set_error("BF16 contraction operands above 4 GiB");
+    return SB_E_UNSUPPORTED;
+  }
+  // variants (BM, BN, BK); ray points take the 32-wide k-tile (register budget)
+  int BM = (t.bm == 256) ? 256 : 128;
+  int BN = (t.bn == 256 && BM == 128) ? 256 : 128;  // 256 x 256 does not fit the registers
+  int BK = (t.bk == 64 && a.kind == 0 && BN == 128 && BM == 128) ? 64 : 32;
+  if (a.kind == 1) BM = 128;
   Bf16Params p;
   p.a = a;
   p.M = M;
   p.count = count;
   p.d = m.d;
   p.K = m.K;
-  p.ntn = (int)ceil_div(m.d, 128);
+  p.ntn = (int)ceil_div(m.d, BN);
   p.mu = m.mu32;
   p.Phi = m.Phi;
   p.Plo = m.Plo;
@@ -339,21 +363,23 @@ int launch_quad_gemm_bf16(int nprod, const Model &m, const ASrc &a, int64_t M,
     return SB_E_UNSUPPORTED;
   }
   dim3 grid((unsigned)ntile);
-#define SB_BF(NP, KD, BMv, BKv) \
-  hipLaunchKernelGGL((quad_gemm_bf16_kernel<NP, KD, BMv, BKv>), grid, dim3(256), 0, s, p)
+#define SB_BF(NP, KD, BMv, BNv, BKv) \
+  hipLaunchKernelGGL((quad_gemm_bf16_kernel<NP, KD, BMv, BNv, BKv>), grid, dim3(256), 0, s, p)
   if (a.kind == 1) {
-    if (nprod == 3 && BM == 128) SB_BF(3, 1, 128, 32);
-    else if (nprod == 3) SB_BF(3, 1, 256, 32);
-    else if (BM == 128) SB_BF(1, 1, 128, 32);
-    else SB_BF(1, 1, 256, 32);
+    if (nprod == 3 && BN == 128) SB_BF(3, 1, 128, 128, 32);
+    else if (nprod == 3) SB_BF(3, 1, 128, 256, 32);
+    else if (BN == 128) SB_BF(1, 1, 128, 128, 32);
+    else SB_BF(1, 1, 128, 256, 32);
   } else if (nprod == 3) {
-    if (BM == 128 && BK == 32) SB_BF(3, 0, 128, 32);
-    else if (BM == 128) SB_BF(3, 0, 128, 64);
-    else SB_BF(3, 0, 256, 32);
+    if (BM == 128 && BN == 128 && BK == 32) SB_BF(3, 0, 128, 128, 32);
+    else if (BM == 128 && BN == 128) SB_BF(3, 0, 128, 128, 64);
+    else if (BM == 256 && BN == 128) SB_BF(3, 0, 256, 128, 32);
+    else SB_BF(3, 0, 128, 256, 32);
   } else {
-    if (BM == 128 && BK == 32) SB_BF(1, 0, 128, 32);
-    else if (BM == 128) SB_BF(1, 0, 128, 64);
-    else SB_BF(1, 0, 256, 32);
+    if (BM == 128 && BN == 128 && BK == 32) SB_BF(1, 0, 128, 128, 32);
+    else if (BM == 128 && BN == 128) SB_BF(1, 0, 128, 128, 64);
+    else if (BM == 256 && BN == 128) SB_BF(1, 0, 256, 128, 32);
+    else SB_BF(1, 0, 128, 256, 32);
   }
 #undef SB_BF
   SB_LAUNCH_CHECK();

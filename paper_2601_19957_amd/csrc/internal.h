@@ -82,6 +82,7 @@ struct ASrc {
   const void *X = nullptr;        // kind 0: [rows][ldx], double (F64) or float (F32/BF16)
   int64_t ldx = 0;
   const int32_t *rowmap = nullptr;// kind 0: GEMM row r reads X row rowmap[r] (nullable)
+  int64_t rows = 0;               // kind 0: rows of X (0: the GEMM's row count)
   const void *P0 = nullptr, *P1 = nullptr;  // kind 1: [R][d] endpoints, same type as X
   int n_pts = 1;
   bool zero_mu = false;           // A = X instead of X - mu_k
@@ -99,6 +100,7 @@ struct QuadOut {
 // Tile shape used for a GEMM call; chosen by the autotuner.
 struct TileCfg {
   int bm = 128, bn = 128;
+  int bk = 32;  // k-tile of the BF16 matrix-core kernels
 };
 
 int quad_gemm_ntn(int dtype, int d, TileCfg t);

@@ -364,12 +364,11 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
   }
 }
 
-// Starts [s_base, s_base + s_count), strided by the grid.
+// Start s_base + blockIdx.x (one workgroup per start of the launch's range).
 template <typename T, int TPB, int EPT>
 __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
   __shared__ T red[4 * (TPB / 64)];
-  for (int64_t i = blockIdx.x; i < a.s_count; i += gridDim.x)
-    lbfgs_step_one<T, TPB, EPT>(a, a.s_base + i, red);
+  if ((int64_t)blockIdx.x < a.s_count) lbfgs_step_one<T, TPB, EPT>(a, a.s_base + blockIdx.x, red);
 }
 
 // Two-loop direction only, for B independent histories given in logical
@@ -491,16 +490,13 @@ static LbArgs<T> make_args(const LbfgsBuffers &b, int max_iter, double tol) {
 // One workgroup per start of the launch: the dispatcher hands freed slots
 // to the next start, which balances starts of uneven cost (a fixed grid
 // striding over starts measured slower: its last round runs part-empty).
-static int64_t step_grid(int d, int64_t count) {
-  (void)d;
-  return count;
-}
+static int64_t step_grid(int64_t count) { return count; }
 
 int launch_lbfgs_step(const LbfgsBuffers &b, int max_iter, double grad_tol, hipStream_t s) {
   int st = check_d(b.d, b.m);
   if (st) return st;
   const int d = b.d;
-  const int64_t B = step_grid(d, b.B);
+  const int64_t B = step_grid(b.B);
   if (B <= 0) return SB_OK;
   if (b.dtype == DT_F64) {
     LbArgs<double> a = make_args<double>(b, max_iter, grad_tol);
@@ -524,7 +520,7 @@ int launch_lbfgs_step_range(const LbfgsBuffers &b, int64_t s_begin, int64_t coun
     return SB_E_INVAL;
   }
   const int d = d_class;
-  const int64_t B = step_grid(d, count);
+  const int64_t B = step_grid(count);
   if (b.dtype == DT_F64) {
     LbArgs<double> a = make_args<double>(b, max_iter, grad_tol);
     a.s_base = s_begin;

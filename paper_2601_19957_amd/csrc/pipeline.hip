@@ -405,6 +405,7 @@ static int run_bulk(Layout &L, const RunCfg &rc, double tol, hipStream_t s,
   at.X = lb.X;
   at.ldx = d;
   at.rowmap = lb.idx;
+  at.rows = 2 * lb.B;  // both slots
   auto one_step = [&]() -> int {
     int r = launch_lbfgs_step(lb, rc.max_iter, tol, s);
     if (r) return r;
