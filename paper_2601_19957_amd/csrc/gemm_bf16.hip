@@ -45,7 +45,7 @@ __device__ inline float lo_half(uint32_t u) { return __builtin_bit_cast(float, u
 __device__ inline float hi_half(uint32_t u) { return __builtin_bit_cast(float, u & 0xffff0000u); }
 
 template <int NPROD, int KIND, int BM, int BN, int BK>
-__global__ __launch_bounds__(256, (BM == 128 && BN == 128) ? 2 : 1) void quad_gemm_bf16_kernel(
+__global__ __launch_bounds__(256, (BM == 128 && BN == 128) ? ((BK == 32 && !(KIND == 1 && NPROD == 3)) ? 3 : 2) : 1) void quad_gemm_bf16_kernel(
     Bf16Params g) {
   // LDS rows of BK bf16 without padding; the 16-byte chunk c of row r sits
   // at chunk c ^ swz(r), swz(r) = (r / R) mod C (C chunks per row, R rows per
@@ -208,38 +208,33 @@ __global__ __launch_bounds__(256, (BM == 128 && BN == 128) ? 2 : 1) void quad_ge
     if (k0 + BK < d) load(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 32) {
-      bf8v ah[TM], al[TM], bhv[TN], blv[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        const int o = lds(wm * WM + i * 16 + fr, kk + fk);
-        ah[i] = *(const bf8v *)&Ah[o];
-        if constexpr (SPLIT) al[i] = *(const bf8v *)&Al[o];
-      }
+      // B fragments of this k-step, then one A row block at a time: only
+      // two A fragments are live, and TN independent MFMAs separate two
+      // updates of one accumulator (small cross terms first)
+      bf8v bhv[TN], blv[TN];
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int o = lds(wn * WN + j * 16 + fr, kk + fk);
         bhv[j] = *(const bf8v *)&Bh[o];
         if constexpr (SPLIT) blv[j] = *(const bf8v *)&Bl[o];
       }
-      // product-major order: TM x TN independent MFMAs separate two updates
-      // of one accumulator (small cross terms first)
-      if constexpr (SPLIT) {
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bhv[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
+      for (int i = 0; i < TM; ++i) {
+        const int o = lds(wm * WM + i * 16 + fr, kk + fk);
+        const bf8v ah = *(const bf8v *)&Ah[o];
+        if constexpr (SPLIT) {
+          const bf8v al = *(const bf8v *)&Al[o];
 #pragma unroll
           for (int j = 0; j < TN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], blv[j], acc[i][j], 0, 0, 0);
-      }
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bhv[j], acc[i][j], 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, blv[j], acc[i][j], 0, 0, 0);
+        }
 #pragma unroll
         for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bhv[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bhv[j], acc[i][j], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
