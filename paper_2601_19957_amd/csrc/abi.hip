@@ -443,8 +443,8 @@ int32_t sb_logl_grad_dev(const sb_model_dev *mdl, int64_t B, const void *X, void
   o.Y = Y;
   o.ldy = (int64_t)m.K * m.d;
   o.qpart = qp;
-  TileCfg t;
-  if (dtype != SB_DTYPE_F32_SPLIT) t = autotune_tiles(dtype, m, B, (hipStream_t)stream);
+  const TuneProbe pr{a, o};
+  TileCfg t = autotune_tiles(dtype, m, B, (hipStream_t)stream, &pr);
   if ((st = launch_quad_gemm(dtype, m, a, B, nullptr, o, t, (hipStream_t)stream))) return st;
   FinishArgs f;
   f.M = B;
@@ -474,8 +474,8 @@ int32_t sb_quadform_dev(const sb_model_dev *mdl, int64_t B, const void *X, int32
   o.Y = Y;
   o.ldy = (int64_t)m.K * m.d;
   o.qpart = qpart;
-  TileCfg t;
-  if (dtype != SB_DTYPE_F32_SPLIT) t = autotune_tiles(dtype, m, B, (hipStream_t)stream);
+  const TuneProbe pr{a, o};
+  TileCfg t = autotune_tiles(dtype, m, B, (hipStream_t)stream, &pr);
   st = launch_quad_gemm(dtype, m, a, B, nullptr, o, t, (hipStream_t)stream);
   if (n_tiles) *n_tiles = o.ntn;
   return st;
@@ -511,7 +511,6 @@ int32_t sb_hvp_dev(const sb_model_dev *mdl, int64_t B, const double *X, const do
   double *Z = ar.take<double>((size_t)B * m.K * m.d);
   double *qp = ar.take<double>((size_t)B * m.K * ceil_div(m.d, 64));
   double *qz = ar.take<double>((size_t)B * m.K * ceil_div(m.d, 64));
-  TileCfg t = autotune_tiles(SB_DTYPE_F64, m, B, s);
   ASrc a;
   a.kind = 0;
   a.X = X;
@@ -520,6 +519,8 @@ int32_t sb_hvp_dev(const sb_model_dev *mdl, int64_t B, const double *X, const do
   o.Y = Y;
   o.ldy = (int64_t)m.K * m.d;
   o.qpart = qp;
+  const TuneProbe pr{a, o};
+  TileCfg t = autotune_tiles(SB_DTYPE_F64, m, B, s, &pr);
   if ((st = launch_quad_gemm(SB_DTYPE_F64, m, a, B, nullptr, o, t, s))) return st;
   ASrc av = a;
   av.X = V;
@@ -592,7 +593,8 @@ int32_t sb_discover_dev(const sb_model_dev *mdl, const double *lo, const double 
   o.Y = nullptr;
   o.ldy = (int64_t)m.K * d;
   o.qpart = qp;
-  TileCfg t = autotune_tiles(dtype, m, NP, s);
+  const TuneProbe pr{a, o};
+  TileCfg t = autotune_tiles(dtype, m, NP, s, &pr);
   if ((st = launch_quad_gemm(dtype, m, a, NP, nullptr, o, t, s))) return st;
   FinishArgs f;
   f.M = NP;
@@ -657,7 +659,14 @@ int32_t sb_lbfgs_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m, int
   void *Y = ar.take<char>(es * (size_t)B * md.K * d);
   void *qp = ar.take<char>(es * (size_t)B * md.K * ceil_div(d, 64));
   if ((st = launch_lbfgs_init(lb, X, s))) return st;
-  TileCfg t = autotune_tiles(dtype, md, B, s);
+  TuneProbe pr;
+  pr.a.kind = 0;
+  pr.a.X = lb.X;  // slot 0 holds the start points now
+  pr.a.ldx = d;
+  pr.o.Y = Y;
+  pr.o.ldy = (int64_t)md.K * d;
+  pr.o.qpart = qp;
+  TileCfg t = autotune_tiles(dtype, md, B, s, &pr);
   auto eval = [&](const int32_t *rowmap, const int32_t *count) -> int {
     ASrc a;
     a.kind = 0;
@@ -762,7 +771,8 @@ int32_t sb_hessian_dev(const sb_model_dev *mdl, int32_t C, const double *X, doub
   o.Y = Y;
   o.ldy = (int64_t)m.K * m.d;
   o.qpart = qp;
-  TileCfg t = autotune_tiles(SB_DTYPE_F64, m, C, s);
+  const TuneProbe pr{a, o};
+  TileCfg t = autotune_tiles(SB_DTYPE_F64, m, C, s, &pr);
   if ((st = launch_quad_gemm(SB_DTYPE_F64, m, a, C, nullptr, o, t, s))) return st;
   FinishArgs f;
   f.M = C;

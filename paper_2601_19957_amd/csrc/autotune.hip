@@ -3,12 +3,15 @@
 // The first time a shape class (dtype, d, K, M rounded up to a power of two)
 // is seen, each candidate tile (BM x BN in {64, 128}^2; for the BF16 and
 // split contractions BM x BN x k-tile in {128x128x32, 128x128x64, 256x128x32,
-// 128x256x32}) is timed with HIP
-// events on device buffers of that shape (up to 8192 rows, seeded values in
-// [-1, 1)), and the fastest is cached for the process.  Timing needs its own
-// allocations and a synchronisation, so a stream under graph capture gets
-// the heuristic choice (not cached).  SB_TILE=BMxBN[xBK] forces a shape;
+// 128x256x32}) is timed with HIP events, one warm-up and three timed launches,
+// and the fastest is cached for the process.  The launches run on the
+// caller's probe (its operands and scratch outputs, which the real launch
+// overwrites) or, for host-level callers, on private seeded buffers of the
+// shape (up to 8192 rows, values in [-1, 1)).  Timing synchronises the
+// stream, so a stream under graph capture gets the heuristic choice (not
+// cached).  SB_TILE=BMxBN[xBK] forces a shape;
 // SB_AUTOTUNE=0 uses the heuristic without timing.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -59,8 +62,43 @@ TileCfg heuristic(int d, int64_t M) {
   return t;
 }
 
-// Times the four candidates on buffers of shape (Mt, d, K); returns false on
-// any runtime error (the caller then uses the heuristic).
+// Times the candidates of one launch; returns false on any runtime error (the
+// caller then uses the heuristic).
+bool time_launches(int dtype, const Model &m, const ASrc &a, QuadOut o, int64_t M, hipStream_t s,
+                   TileCfg *best) {
+  const bool bf = (dtype == DT_BF16 || dtype == DT_F32S) && quad_gemm_bf16_ok(m.d);
+  hipEvent_t e0, e1;
+  bool ok = hipEventCreate(&e0) == hipSuccess;
+  ok = ok && hipEventCreate(&e1) == hipSuccess;
+  float best_ms = 0.f;
+  // GEMM tiles (BM, BN); for the BF16 kernels (BM, BN, k-tile)
+  const int cands[4][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}};
+  const int cands_bf[4][3] = {{128, 128, 32}, {128, 128, 64}, {256, 128, 32}, {128, 256, 32}};
+  for (int c = 0; c < 4 && ok; ++c) {
+    TileCfg t;
+    t.bm = bf ? cands_bf[c][0] : cands[c][0];
+    t.bn = bf ? cands_bf[c][1] : cands[c][1];
+    t.bk = bf ? cands_bf[c][2] : 32;
+    ok = launch_quad_gemm(dtype, m, a, M, nullptr, o, t, s) == SB_OK;  // warm-up
+    ok = ok && hipEventRecord(e0, s) == hipSuccess;
+    for (int r = 0; r < 3 && ok; ++r) ok = launch_quad_gemm(dtype, m, a, M, nullptr, o, t, s) == SB_OK;
+    ok = ok && hipEventRecord(e1, s) == hipSuccess;
+    ok = ok && hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.f;
+    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    if (ok && (c == 0 || ms < best_ms)) {
+      best_ms = ms;
+      *best = t;
+    }
+  }
+  if (ok) ok = hipStreamSynchronize(s) == hipSuccess;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipGetLastError();
+  return ok;
+}
+
+// Times the candidates on private buffers of shape (min(M, 8192), d, K).
 bool time_candidates(int dtype, int d, int K, int64_t M, hipStream_t s, TileCfg *best) {
   const int64_t Mt = std::max<int64_t>(1, std::min<int64_t>(M, 8192));
   const bool bf = (dtype == DT_BF16 || dtype == DT_F32S) && quad_gemm_bf16_ok(d);
@@ -114,45 +152,20 @@ bool time_candidates(int dtype, int d, int K, int64_t M, hipStream_t s, TileCfg 
   a.kind = 0;
   a.X = X;
   a.ldx = d;
-  hipEvent_t e0, e1;
-  bool ok = hipEventCreate(&e0) == hipSuccess;
-  ok = ok && hipEventCreate(&e1) == hipSuccess;
-  float best_ms = 0.f;
-  // GEMM tiles (BM, BN); for the BF16 kernels (BM, BN, k-tile)
-  const int cands[4][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}};
-  const int cands_bf[4][3] = {{128, 128, 32}, {128, 128, 64}, {256, 128, 32}, {128, 256, 32}};
-  const int nc = 4;
-  for (int c = 0; c < nc && ok; ++c) {
-    TileCfg t;
-    t.bm = bf ? cands_bf[c][0] : cands[c][0];
-    t.bn = bf ? cands_bf[c][1] : cands[c][1];
-    t.bk = bf ? cands_bf[c][2] : 32;
-    QuadOut o;
-    o.Y = Y;
-    o.ldy = (int64_t)K * d;
-    o.qpart = q;
-    ok = launch_quad_gemm(dtype, m, a, Mt, nullptr, o, t, s) == SB_OK;  // warm-up
-    ok = ok && hipEventRecord(e0, s) == hipSuccess;
-    for (int r = 0; r < 3 && ok; ++r) ok = launch_quad_gemm(dtype, m, a, Mt, nullptr, o, t, s) == SB_OK;
-    ok = ok && hipEventRecord(e1, s) == hipSuccess;
-    ok = ok && hipEventSynchronize(e1) == hipSuccess;
-    float ms = 0.f;
-    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-    if (ok && (c == 0 || ms < best_ms)) {
-      best_ms = ms;
-      *best = t;
-    }
-  }
+  QuadOut o;
+  o.Y = Y;
+  o.ldy = (int64_t)K * d;
+  o.qpart = q;
+  const bool ok = time_launches(dtype, m, a, o, Mt, s, best);
   (void)hipStreamSynchronize(s);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   (void)hipFree(buf);
   (void)hipGetLastError();
   return ok;
 }
 }  // namespace
 
-TileCfg autotune_tiles(int dtype, const Model &m, int64_t M, hipStream_t s) {
+TileCfg autotune_tiles(int dtype, const Model &m, int64_t M, hipStream_t s, const TuneProbe *probe,
+                       bool may_alloc) {
   const char *force = getenv("SB_TILE");
   if (force) {
     int bm = 0, bn = 0, bk = 32;
@@ -168,7 +181,7 @@ TileCfg autotune_tiles(int dtype, const Model &m, int64_t M, hipStream_t s) {
   const bool timed = !(at && at[0] == '0');
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess) cs = hipStreamCaptureStatusNone;
-  if (!timed || cs != hipStreamCaptureStatusNone) return heuristic(m.d, M);
+  if (!timed || cs != hipStreamCaptureStatusNone || M <= 0) return heuristic(m.d, M);
   std::lock_guard<std::mutex> lk(g_mu);
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -176,7 +189,14 @@ TileCfg autotune_tiles(int dtype, const Model &m, int64_t M, hipStream_t s) {
   auto it = g_cache.find(key);
   if (it != g_cache.end()) return it->second;
   TileCfg t = heuristic(m.d, M);
-  if (!time_candidates(dtype, m.d, m.K, M, s, &t)) t = heuristic(m.d, M);
+  bool ok = false;
+  if (probe)  // a prefix of the caller's launch is enough to rank the tiles
+    ok = time_launches(dtype, m, probe->a, probe->o, std::min<int64_t>(M, 65536), s, &t);
+  else if (may_alloc)
+    ok = time_candidates(dtype, m.d, m.K, M, s, &t);
+  else
+    return t;  // no buffers to time on: heuristic, not cached
+  if (!ok) t = heuristic(m.d, M);
   g_cache[key] = t;
   return t;
 }

@@ -277,12 +277,13 @@ int download(std::vector<T> &dst, const T *src, size_t n, hipStream_t s) {
 }
 
 // Tile shape of a grouped GEMM phase: the autotuner's choice for the batch's
-// largest padded dimension and the phase's row count.
+// largest padded dimension and the phase's row count (timed on private
+// buffers: this is a host-level entry point, which allocates anyway).
 TileCfg batch_tiles(int dtype, int dp_max, int K_max, int64_t rows, hipStream_t s) {
   Model m;
   m.d = dp_max;
   m.K = K_max;
-  return autotune_tiles(dtype, m, rows, s);
+  return autotune_tiles(dtype, m, rows, s, nullptr, true);
 }
 
 }  // namespace

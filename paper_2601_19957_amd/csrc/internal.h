@@ -291,7 +291,17 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
 size_t evidence_ws_bytes(const sb_loglik *ll, const sb_config *cfg);
 
 // Autotuner: tile choice for the quadratic-form GEMM (cached per shape class).
-TileCfg autotune_tiles(int dtype, const Model &m, int64_t M, hipStream_t s);
+// Candidates are timed on the caller's own operands and scratch outputs
+// (`probe`: the launch about to be made, whose outputs the real launch then
+// overwrites), so device entry points allocate nothing.  Without a probe the
+// shape is timed on private buffers only when `may_alloc` (host-level
+// entry points), else the heuristic choice is returned uncached.
+struct TuneProbe {
+  ASrc a;
+  QuadOut o;
+};
+TileCfg autotune_tiles(int dtype, const Model &m, int64_t M, hipStream_t s,
+                       const TuneProbe *probe = nullptr, bool may_alloc = false);
 
 }  // namespace sb
 

@@ -487,11 +487,18 @@ static int polish_chunk(Layout &L, const Model &m64, const DevProblem &P, int n,
   Evaluator &ev = L.pol;
   ev.m = m64;
   ev.dtype = DT_F64;
-  ev.tile = autotune_tiles(DT_F64, m64, n, s);
   ASrc a;
   a.kind = 0;
   a.X = L.Xp;
   a.ldx = d;
+  {
+    TuneProbe pr;
+    pr.a = a;
+    pr.o.Y = ev.Y;
+    pr.o.ldy = (int64_t)K * d;
+    pr.o.qpart = ev.qpart;
+    ev.tile = autotune_tiles(DT_F64, m64, n, s, &pr);
+  }
   int st;
   if ((st = launch_fill_i32(n, 0, L.done, s))) return st;
   if ((st = launch_fill_i32(n, 0, L.rejected, s))) return st;
@@ -615,7 +622,12 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
       a.P1 = mixed ? (const void *)L.P1f : (const void *)L.P1;
       a.n_pts = rc.n_pts;
       const int64_t NP = (int64_t)rc.R * rc.n_pts;
-      L.disc.tile = autotune_tiles(ddt, md, NP, s);
+      TuneProbe pr;
+      pr.a = a;
+      pr.o.Y = nullptr;
+      pr.o.ldy = L.disc.ldy;
+      pr.o.qpart = L.disc.qpart;
+      L.disc.tile = autotune_tiles(ddt, md, NP, s, &pr);
       if ((st = L.disc.run(a, NP, nullptr, L.lpts, nullptr, 0, nullptr, nullptr, false, s, false)))
         return st;
     }
@@ -652,7 +664,16 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     const char *bg = getenv("SB_BULK_GEMM");
     const bool split = mixed && quad_gemm_bf16_ok(d) && !(bg && bg[0] == 'f');
     L.bulk.gemm_dtype = split ? DT_F32S : -1;
-    if (!split) L.bulk.tile = autotune_tiles(L.bulk.dtype, mb, rc.n_starts, s);
+    {
+      TuneProbe pr;  // timed on the start points and the bulk's own scratch
+      pr.a.kind = 0;
+      pr.a.X = L.X0b;
+      pr.a.ldx = d;
+      pr.o.Y = L.bulk.Y;
+      pr.o.ldy = L.bulk.ldy;
+      pr.o.qpart = L.bulk.qpart;
+      L.bulk.tile = autotune_tiles(split ? DT_F32S : L.bulk.dtype, mb, rc.n_starts, s, &pr);
+    }
     int64_t bulk_evals = 0;
     int steps = 0;
     if ((st = run_bulk(L, rc, tol, s, &bulk_evals, &steps))) return st;
