@@ -47,7 +47,42 @@ struct LbArgs {
   const double *ptol;
   const int32_t *pmaxit;
   int64_t s_base, s_count;  // starts [s_base, s_base + s_count) of this launch
+  int32_t *count_reset;     // compaction count, zeroed by this launch (nullable)
 };
+
+// A thread's chunk [i0, i0 + EPT) of a length-d vector (i0 = tid * EPT):
+// one vector access when `vec` (d and the base offset multiples of EPT, so
+// the chunk is aligned) and the chunk is whole, else element by element.
+template <typename T, int EPT>
+__device__ inline void vload(const T *p, int i0, int d, bool vec, T (&v)[EPT]) {
+  if constexpr (EPT > 1) {
+    typedef T vt __attribute__((ext_vector_type(EPT)));
+    if (vec && i0 + EPT <= d) {
+      const vt w = *(const vt *)(p + i0);
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) v[e] = w[e];
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) v[e] = (i0 + e < d) ? p[i0 + e] : (T)0;
+}
+template <typename T, int EPT>
+__device__ inline void vstore(T *p, int i0, int d, bool vec, const T (&v)[EPT]) {
+  if constexpr (EPT > 1) {
+    typedef T vt __attribute__((ext_vector_type(EPT)));
+    if (vec && i0 + EPT <= d) {
+      vt w;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) w[e] = v[e];
+      *(vt *)(p + i0) = w;
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e)
+    if (i0 + e < d) p[i0 + e] = v[e];
+}
 
 // Two-loop recursion on register-resident history (logical order, oldest
 // first).  q <- g; backward: alpha_j = rho_j s_j^T q, q -= alpha_j y_j;
@@ -104,6 +139,8 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
   const int64_t vo = a.voff ? a.voff[s] : (int64_t)s * a.d;
   const int64_t Lt = a.Ltot;
   const int64_t B = a.B;
+  const int i0 = tid * EPT;  // this thread's chunk of every vector
+  const bool vec = (d % EPT == 0) && (vo % EPT == 0) && (Lt % EPT == 0);
   T tol = a.tol;
   int max_iter = a.max_iter;
   if (a.sprob) {
@@ -150,11 +187,12 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
     const T *xc = a.X + (size_t)cur * Lt + vo;
     T *xt = a.X + (size_t)tr * Lt + vo;
     const T *pd = a.Pd + vo;
+    T c[EPT], q[EPT];
+    vload<T, EPT>(xc, i0, d, vec, c);
+    vload<T, EPT>(pd, i0, d, vec, q);
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int i = e * TPB + tid;
-      if (i < d) xt[i] = xc[i] + alpha * pd[i];
-    }
+    for (int e = 0; e < EPT; ++e) c[e] = c[e] + alpha * q[e];
+    vstore<T, EPT>(xt, i0, d, vec, c);
     if (tid == 0) {
       a.alpha[s] = alpha;
       a.ls[s] = lsn;
@@ -173,14 +211,16 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
     const T *gn = a.G + (size_t)newcur * Lt + vo;
     const T *xo = a.X + (size_t)cur * Lt + vo;
     const T *go = a.G + (size_t)cur * Lt + vo;
+    vload<T, EPT>(xn, i0, d, vec, x);
+    vload<T, EPT>(gn, i0, d, vec, gl);
+    if (mode == M_ACCEPT) {
+      T xov[EPT], gov[EPT];
+      vload<T, EPT>(xo, i0, d, vec, xov);
+      vload<T, EPT>(go, i0, d, vec, gov);
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int i = e * TPB + tid;
-      x[e] = (i < d) ? xn[i] : (T)0;
-      gl[e] = (i < d) ? gn[i] : (T)0;
-      if (mode == M_ACCEPT) {
-        sv[e] = (i < d) ? x[e] - xo[i] : (T)0;
-        yv[e] = (i < d) ? go[i] - gl[e] : (T)0;  // grad f(x_t) - grad f(x), grad f = -grad l
+      for (int e = 0; e < EPT; ++e) {
+        sv[e] = x[e] - xov[e];
+        yv[e] = gov[e] - gl[e];  // grad f(x_t) - grad f(x), grad f = -grad l
       }
     }
   }
@@ -200,14 +240,8 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
       const int ph = (head - cnt + j + 2 * m) % m;
       const T *Sp = a.S + (size_t)m * vo + (size_t)ph * d;
       const T *Yp = a.Yh + (size_t)m * vo + (size_t)ph * d;
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int i = e * TPB + tid;
-        if (i < d) {
-          Sr[j][e] = Sp[i];
-          Yr[j][e] = Yp[i];
-        }
-      }
+      vload<T, EPT>(Sp, i0, d, vec, Sr[j]);
+      vload<T, EPT>(Yp, i0, d, vec, Yr[j]);
       rh[j] = a.rho[(size_t)s * m + ph];
       yyr[j] = a.yy[(size_t)s * m + ph];
     }
@@ -228,14 +262,8 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
       // store the pair in the ring and append it to the logical history
       T *Sp = a.S + (size_t)m * vo + (size_t)head * d;
       T *Yp = a.Yh + (size_t)m * vo + (size_t)head * d;
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int i = e * TPB + tid;
-        if (i < d) {
-          Sp[i] = sv[e];
-          Yp[i] = yv[e];
-        }
-      }
+      vstore<T, EPT>(Sp, i0, d, vec, sv);
+      vstore<T, EPT>(Yp, i0, d, vec, yv);
       if (tid == 0) {
         a.rho[(size_t)s * m + head] = (T)1 / sy;
         a.yy[(size_t)s * m + head] = yy;
@@ -341,14 +369,11 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
   const int tr = 1 - cur;
   T *xt = a.X + (size_t)tr * Lt + vo;
   T *pd = a.Pd + vo;
+  T xtv[EPT];
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int i = e * TPB + tid;
-    if (i < d) {
-      pd[i] = p[e];
-      xt[i] = x[e] + p[e];
-    }
-  }
+  for (int e = 0; e < EPT; ++e) xtv[e] = x[e] + p[e];
+  vstore<T, EPT>(pd, i0, d, vec, p);
+  vstore<T, EPT>(xt, i0, d, vec, xtv);
   if (tid == 0) {
     a.alpha[s] = (T)1;
     a.gtp[s] = gtp;
@@ -368,6 +393,9 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
 template <typename T, int TPB, int EPT>
 __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
   __shared__ T red[4 * (TPB / 64)];
+  // the compaction that follows counts from zero; every reader of the
+  // previous count ran before this launch
+  if (a.count_reset && blockIdx.x == 0 && threadIdx.x == 0) *a.count_reset = 0;
   if ((int64_t)blockIdx.x < a.s_count) lbfgs_step_one<T, TPB, EPT>(a, a.s_base + blockIdx.x, red);
 }
 
@@ -382,20 +410,18 @@ __global__ __launch_bounds__(TPB) void two_loop_kernel(int d, int m, const int32
   const int cnt = min(max(cntv[b], 0), m);  // never read past this start's m slots
   T Sr[kMaxHist][EPT], Yr[kMaxHist][EPT], rh[kMaxHist], g[EPT], p[EPT];
   T gamma = 1;
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int i = e * TPB + tid;
-    g[e] = (i < d) ? G[(size_t)b * d + i] : (T)0;
-  }
+  const int i0 = tid * EPT;
+  const bool vec = (d % EPT == 0);
+  vload<T, EPT>(G + (size_t)b * d, i0, d, vec, g);
 #pragma unroll
   for (int j = 0; j < kMaxHist; ++j) {
     rh[j] = 0;
+    if (j < cnt) {
+      vload<T, EPT>(S + ((size_t)b * m + j) * d, i0, d, vec, Sr[j]);
+      vload<T, EPT>(Y + ((size_t)b * m + j) * d, i0, d, vec, Yr[j]);
+    } else {
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int i = e * TPB + tid;
-      const bool ok = (j < cnt) && (i < d);
-      Sr[j][e] = ok ? S[((size_t)b * m + j) * d + i] : (T)0;
-      Yr[j][e] = ok ? Y[((size_t)b * m + j) * d + i] : (T)0;
+      for (int e = 0; e < EPT; ++e) Sr[j][e] = Yr[j][e] = (T)0;
     }
     if (j < cnt) {
       T v2[2] = {0, 0};
@@ -410,11 +436,7 @@ __global__ __launch_bounds__(TPB) void two_loop_kernel(int d, int m, const int32
     }
   }
   two_loop<T, TPB, EPT>(Sr, Yr, rh, gamma, cnt, g, p, red);
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int i = e * TPB + tid;
-    if (i < d) P[(size_t)b * d + i] = p[e];
-  }
+  vstore<T, EPT>(P + (size_t)b * d, i0, d, vec, p);
 }
 
 // ------------------------------------------------------------- dispatch
@@ -484,6 +506,7 @@ static LbArgs<T> make_args(const LbfgsBuffers &b, int max_iter, double tol) {
   a.pmaxit = b.pmaxit;
   a.s_base = 0;
   a.s_count = b.B;
+  a.count_reset = nullptr;
   return a;
 }
 
@@ -500,9 +523,11 @@ int launch_lbfgs_step(const LbfgsBuffers &b, int max_iter, double grad_tol, hipS
   if (B <= 0) return SB_OK;
   if (b.dtype == DT_F64) {
     LbArgs<double> a = make_args<double>(b, max_iter, grad_tol);
+    a.count_reset = b.count;
     SB_LB_CASES(lbfgs_step_kernel, double, a);
   } else {
     LbArgs<float> a = make_args<float>(b, max_iter, grad_tol);
+    a.count_reset = b.count;
     SB_LB_CASES(lbfgs_step_kernel, float, a);
   }
   SB_LAUNCH_CHECK();
@@ -634,35 +659,32 @@ int launch_lbfgs_init(const LbfgsBuffers &b, const void *X0, hipStream_t s) {
 // Compaction of the active starts into idx (their trial row ids), in start
 // order; count[0] = number active, evals[0] += count.  One workgroup: each
 // thread owns a contiguous chunk, exclusive scan of the chunk counts in LDS.
-__global__ __launch_bounds__(1024) void compact_kernel(int64_t B, const int32_t *active,
-                                                       const int32_t *rowid, int32_t *idx,
-                                                       int32_t *count, int64_t *evals) {
-  __shared__ int32_t sc[1024];
-  const int t = threadIdx.x;
-  const int64_t per = (B + 1023) / 1024;
-  const int64_t b0 = (int64_t)t * per, b1 = std::min<int64_t>(B, b0 + per);
-  int32_t c = 0;
-  for (int64_t i = b0; i < b1; ++i) c += active[i] ? 1 : 0;
-  sc[t] = c;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    int32_t v = (t >= o) ? sc[t - o] : 0;
-    __syncthreads();
-    sc[t] += v;
-    __syncthreads();
+// Active starts' trial rows into idx[0, count).  Each wave ballots its
+// starts and reserves its slice with one atomic: the order of the list
+// depends on wave timing, the rows' results do not (every row of the
+// contraction and of the epilogue is computed on its own).
+__global__ __launch_bounds__(256) void compact_kernel(int64_t B, const int32_t *active,
+                                                      const int32_t *rowid, int32_t *idx,
+                                                      int32_t *count, int64_t *evals) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool on = s < B && active[s] != 0;
+  const unsigned long long mask = __ballot(on);
+  const int lane = threadIdx.x & 63;
+  const int n = __popcll(mask);
+  int base = 0;
+  if (lane == 0 && n > 0) {
+    base = atomicAdd(count, n);
+    atomicAdd((unsigned long long *)evals, (unsigned long long)n);
   }
-  int32_t off = sc[t] - c;
-  for (int64_t i = b0; i < b1; ++i)
-    if (active[i]) idx[off++] = rowid[i];
-  if (t == 1023) {
-    count[0] = sc[1023];
-    evals[0] += sc[1023];
-  }
+  base = __shfl(base, 0, 64);
+  if (on) idx[base + __popcll(mask & ((1ull << lane) - 1ull))] = rowid[s];
 }
 
+// The step launch that precedes each compaction zeroes count.
 int launch_compact(const LbfgsBuffers &b, hipStream_t s) {
-  hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, s, b.B, b.active, b.rowid, b.idx,
-                     b.count, b.evals);
+  if (b.B > 0)
+    hipLaunchKernelGGL(compact_kernel, dim3((unsigned)ceil_div(b.B, 256)), dim3(256), 0, s, b.B,
+                       b.active, b.rowid, b.idx, b.count, b.evals);
   SB_LAUNCH_CHECK();
   return SB_OK;
 }

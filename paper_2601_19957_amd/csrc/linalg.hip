@@ -207,6 +207,7 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(int n, const double *La
                                                          const int32_t *info) {
   extern __shared__ double xs[];  // [n]
   __shared__ double part[4][64];
+  __shared__ double Tb[64][65];   // current diagonal block
   const int c = blockIdx.x;
   const double *L = Lall + (size_t)c * n * n;
   const double *b = ball + (size_t)c * n;
@@ -226,17 +227,20 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(int n, const double *La
       const int r = w * 16 + rr;
       double sacc = 0.0;
       if (r < nb)
+#pragma unroll 8
         for (int k = lane; k < i0; k += 64) sacc += L[(size_t)(i0 + r) * n + k] * xs[k];
       sacc = wave_sum(sacc);
       if (lane == 0) part[0][r] = sacc;
     }
+    for (int r = w; r < nb; r += 4)  // diagonal block into LDS, row by row
+      if (lane < nb) Tb[r][lane] = L[(size_t)(i0 + r) * n + i0 + lane];
     __syncthreads();
     if (w == 0) {
       double val = (lane < nb) ? xs[i0 + lane] - part[0][lane] : 0.0;
       for (int cc = 0; cc < nb; ++cc) {
-        double xc = __shfl(val / L[(size_t)(i0 + cc) * n + i0 + cc], cc, 64);
+        double xc = __shfl(val / Tb[cc][cc], cc, 64);
         if (lane == cc) val = xc;
-        if (lane > cc && lane < nb) val -= L[(size_t)(i0 + lane) * n + i0 + cc] * xc;
+        if (lane > cc && lane < nb) val -= Tb[lane][cc] * xc;
       }
       if (lane < nb) xs[i0 + lane] = val;
     }
@@ -249,16 +253,19 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(int n, const double *La
     // s_i = sum_{k >= iend} L[k][i] x_k for i in block; lanes index i, waves split k
     double sacc = 0.0;
     if (lane < nb)
+#pragma unroll 8
       for (int k = iend + w; k < n; k += 4) sacc += L[(size_t)k * n + i0 + lane] * xs[k];
     part[w][lane] = sacc;
+    for (int r = w; r < nb; r += 4)
+      if (lane < nb) Tb[r][lane] = L[(size_t)(i0 + r) * n + i0 + lane];
     __syncthreads();
     if (w == 0) {
       double sv = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
       double val = (lane < nb) ? xs[i0 + lane] - sv : 0.0;
       for (int cc = nb - 1; cc >= 0; --cc) {
-        double xc = __shfl(val / L[(size_t)(i0 + cc) * n + i0 + cc], cc, 64);
+        double xc = __shfl(val / Tb[cc][cc], cc, 64);
         if (lane == cc) val = xc;
-        if (lane < cc) val -= L[(size_t)(i0 + cc) * n + i0 + lane] * xc;
+        if (lane < cc) val -= Tb[cc][lane] * xc;
       }
       if (lane < nb) xs[i0 + lane] = val;
     }
@@ -487,6 +494,7 @@ __global__ __launch_bounds__(256) void chol_solve_u_kernel(const int32_t *nv, co
                                                            const int32_t *info) {
   extern __shared__ double xs[];
   __shared__ double part[4][64];
+  __shared__ double Tb[64][65];
   const int c = blockIdx.x;
   const int n = nv[c];
   const double *L = Lall + off[c];
@@ -505,17 +513,20 @@ __global__ __launch_bounds__(256) void chol_solve_u_kernel(const int32_t *nv, co
       const int r = w * 16 + rr;
       double sacc = 0.0;
       if (r < nb)
+#pragma unroll 8
         for (int k = lane; k < i0; k += 64) sacc += L[(size_t)(i0 + r) * n + k] * xs[k];
       sacc = wave_sum(sacc);
       if (lane == 0) part[0][r] = sacc;
     }
+    for (int r = w; r < nb; r += 4)  // diagonal block into LDS, row by row
+      if (lane < nb) Tb[r][lane] = L[(size_t)(i0 + r) * n + i0 + lane];
     __syncthreads();
     if (w == 0) {
       double val = (lane < nb) ? xs[i0 + lane] - part[0][lane] : 0.0;
       for (int cc = 0; cc < nb; ++cc) {
-        double xc = __shfl(val / L[(size_t)(i0 + cc) * n + i0 + cc], cc, 64);
+        double xc = __shfl(val / Tb[cc][cc], cc, 64);
         if (lane == cc) val = xc;
-        if (lane > cc && lane < nb) val -= L[(size_t)(i0 + lane) * n + i0 + cc] * xc;
+        if (lane > cc && lane < nb) val -= Tb[lane][cc] * xc;
       }
       if (lane < nb) xs[i0 + lane] = val;
     }
@@ -526,16 +537,19 @@ __global__ __launch_bounds__(256) void chol_solve_u_kernel(const int32_t *nv, co
     const int nb = iend - i0;
     double sacc = 0.0;
     if (lane < nb)
+#pragma unroll 8
       for (int k = iend + w; k < n; k += 4) sacc += L[(size_t)k * n + i0 + lane] * xs[k];
     part[w][lane] = sacc;
+    for (int r = w; r < nb; r += 4)
+      if (lane < nb) Tb[r][lane] = L[(size_t)(i0 + r) * n + i0 + lane];
     __syncthreads();
     if (w == 0) {
       double sv = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
       double val = (lane < nb) ? xs[i0 + lane] - sv : 0.0;
       for (int cc = nb - 1; cc >= 0; --cc) {
-        double xc = __shfl(val / L[(size_t)(i0 + cc) * n + i0 + cc], cc, 64);
+        double xc = __shfl(val / Tb[cc][cc], cc, 64);
         if (lane == cc) val = xc;
-        if (lane < cc) val -= L[(size_t)(i0 + cc) * n + i0 + lane] * xc;
+        if (lane < cc) val -= Tb[cc][lane] * xc;
       }
       if (lane < nb) xs[i0 + lane] = val;
     }
