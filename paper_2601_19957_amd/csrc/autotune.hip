@@ -3,7 +3,7 @@
 // The first time a shape class (dtype, d, K, M rounded up to a power of two)
 // is seen, each candidate tile (BM x BN in {64, 128}^2; for the BF16 and
 // split contractions BM x BN x k-tile in {128x128x32, 128x128x64, 256x128x32,
-// 128x256x32}) is timed with HIP events, one warm-up and three timed launches,
+// 128x256x32, 256x256x32 on eight waves}) is timed with HIP events, one warm-up and three timed launches,
 // and the fastest is cached for the process.  The launches run on the
 // caller's probe (its operands and scratch outputs, which the real launch
 // overwrites) or, for host-level callers, on private seeded buffers of the
@@ -73,8 +73,10 @@ bool time_launches(int dtype, const Model &m, const ASrc &a, QuadOut o, int64_t 
   float best_ms = 0.f;
   // GEMM tiles (BM, BN); for the BF16 kernels (BM, BN, k-tile)
   const int cands[4][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}};
-  const int cands_bf[4][3] = {{128, 128, 32}, {128, 128, 64}, {256, 128, 32}, {128, 256, 32}};
-  for (int c = 0; c < 4 && ok; ++c) {
+  const int cands_bf[5][3] = {{128, 128, 32}, {128, 128, 64}, {256, 128, 32}, {128, 256, 32},
+                              {256, 256, 32}};
+  const int nc = bf ? 5 : 4;
+  for (int c = 0; c < nc && ok; ++c) {
     TileCfg t;
     t.bm = bf ? cands_bf[c][0] : cands[c][0];
     t.bn = bf ? cands_bf[c][1] : cands[c][1];

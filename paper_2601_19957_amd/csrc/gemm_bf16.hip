@@ -44,9 +44,20 @@ __device__ inline uint32_t pack2(float a, float b) {
 __device__ inline float lo_half(uint32_t u) { return __builtin_bit_cast(float, u << 16); }
 __device__ inline float hi_half(uint32_t u) { return __builtin_bit_cast(float, u & 0xffff0000u); }
 
-template <int NPROD, int KIND, int BM, int BN, int BK>
-__global__ __launch_bounds__(256, (BM == 128 && BN == 128) ? ((BK == 32 && !(KIND == 1 && NPROD == 3)) ? 3 : 2) : 1) void quad_gemm_bf16_kernel(
-    Bf16Params g) {
+// Launch bounds: workgroup size and the minimum waves per SIMD the register
+// allocation must leave room for.
+template <int BM, int BN, int BK, int KIND, int NPROD, int NT>
+struct Bf16Occ {
+  static constexpr int value =
+      NT == 512 ? 2 : ((BM == 128 && BN == 128) ? ((BK == 32 && !(KIND == 1 && NPROD == 3)) ? 3 : 2) : 1);
+};
+
+// NT = 64 * WGM * WGN threads: a WGM x WGN grid of waves, each owning a
+// (BM / WGM) x (BN / WGN) block of the tile.
+template <int NPROD, int KIND, int BM, int BN, int BK, int WGM = 2, int WGN = 2>
+__global__ __launch_bounds__(64 * WGM * WGN, (Bf16Occ<BM, BN, BK, KIND, NPROD, 64 * WGM * WGN>::value))
+void quad_gemm_bf16_kernel(Bf16Params g) {
+  constexpr int NT = 64 * WGM * WGN;
   // LDS rows of BK bf16 without padding; the 16-byte chunk c of row r sits
   // at chunk c ^ swz(r), swz(r) = (r / R) mod C (C chunks per row, R rows per
   // 32 banks): the row-wise tile stores and the 8-row fragment reads both
@@ -55,19 +66,19 @@ __global__ __launch_bounds__(256, (BM == 128 && BN == 128) ? ((BK == 32 && !(KIN
   auto lds = [](int row, int kel) {  // element index of (row, k) in an LDS tile
     return row * BK + ((((kel >> 3) ^ ((row / R) % C))) << 3) + (kel & 7);
   };
-  constexpr int WM = BM / 2, TM = WM / 16;  // wave tile WM x WN: TM x TN MFMA blocks
-  constexpr int WN = BN / 2, TN = WN / 16;
+  constexpr int WM = BM / WGM, TM = WM / 16;  // wave tile WM x WN: TM x TN MFMA blocks
+  constexpr int WN = BN / WGN, TN = WN / 16;
   constexpr int VA = BK / 4;          // float4 per A row per k-tile
-  constexpr int NA = BM * VA / 256;   // float4 loads per thread
+  constexpr int NA = BM * VA / NT;    // float4 loads per thread
   constexpr int VB = BK / 8;          // 8-bf16 vectors per B row per k-tile
-  constexpr int NB = BN * VB / 256;   // per thread and operand half
+  constexpr int NB = BN * VB / NT;    // per thread and operand half
   constexpr bool SPLIT = NPROD == 3;
-  static_assert(NA >= 1 && NB >= 1 && 256 % VA == 0 && 256 % VB == 0, "tile");
+  static_assert(NA >= 1 && NB >= 1 && NT % VA == 0 && NT % VB == 0, "tile");
   __shared__ __attribute__((aligned(16))) bf16_t Ah[BM * BK];
   __shared__ __attribute__((aligned(16))) bf16_t Al[SPLIT ? BM * BK : 8];
   __shared__ __attribute__((aligned(16))) bf16_t Bh[BN * BK];
   __shared__ __attribute__((aligned(16))) bf16_t Bl[SPLIT ? BN * BK : 8];
-  __shared__ float qs[2][BM];
+  __shared__ float qs[WGN][BM];
 
   // XCD-aware tile order.  Workgroup w runs on XCD w % 8; each XCD owns a
   // fixed set of column blocks (component k, n-tile) and walks the M-tiles
@@ -96,7 +107,7 @@ __global__ __launch_bounds__(256, (BM == 128 && BN == 128) ? ((BK == 32 && !(KIN
   const char *Phb = (const char *)(g.Phi + (size_t)k * d * d);
   const char *Plb = SPLIT ? (const char *)(g.Plo + (size_t)k * d * d) : nullptr;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WGN, wn = wave % WGN;
 
   // Element offset of point row `row`'s data (kind 0: its X row; kind 1: its
   // ray's endpoint rows) and the ray parameter t.  The host guarantees the
@@ -121,7 +132,7 @@ __global__ __launch_bounds__(256, (BM == 128 && BN == 128) ? ((BK == 32 && !(KIN
   bool aok[NA];
 #pragma unroll
   for (int r = 0; r < NA; ++r) {
-    const int64_t row = m0 + (tid + 256 * r) / VA;
+    const int64_t row = m0 + (tid + NT * r) / VA;
     aok[r] = row < M;
     uint32_t off;
     row_off(aok[r] ? row : m0, off, tpar[r]);
@@ -131,7 +142,7 @@ __global__ __launch_bounds__(256, (BM == 128 && BN == 128) ? ((BK == 32 && !(KIN
   bool bok[NB];
 #pragma unroll
   for (int r = 0; r < NB; ++r) {
-    const int n = n0 + (tid + 256 * r) / VB;
+    const int n = n0 + (tid + NT * r) / VB;
     bok[r] = n < d;
     boff[r] = 2u * ((uint32_t)(bok[r] ? n : 0) * (uint32_t)d + (uint32_t)(cb * 8));
   }
@@ -162,7 +173,7 @@ __global__ __launch_bounds__(256, (BM == 128 && BN == 128) ? ((BK == 32 && !(KIN
   auto store = [&]() {
 #pragma unroll
     for (int r = 0; r < NA; ++r) {
-      const int i = (tid + 256 * r) / VA;
+      const int i = (tid + NT * r) / VA;
       float v[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -187,7 +198,7 @@ __global__ __launch_bounds__(256, (BM == 128 && BN == 128) ? ((BK == 32 && !(KIN
     }
 #pragma unroll
     for (int r = 0; r < NB; ++r) {
-      const int n = (tid + 256 * r) / VB;
+      const int n = (tid + NT * r) / VB;
       const int bi = lds(n, cb * 8);
       *(u4v *)&Bh[bi] = bok[r] ? rbh[r] : u4v{0u, 0u, 0u, 0u};
       if constexpr (SPLIT) *(u4v *)&Bl[bi] = bok[r] ? rbl[r] : u4v{0u, 0u, 0u, 0u};
@@ -294,9 +305,14 @@ __global__ __launch_bounds__(256, (BM == 128 && BN == 128) ? ((BK == 32 && !(KIN
   }
   __syncthreads();
   if (g.qpart) {
-    for (int i = tid; i < BM; i += 256) {
+    for (int i = tid; i < BM; i += NT) {
       const int64_t row = m0 + i;
-      if (row < M) g.qpart[(row * g.K + k) * g.ntn + nt] = qs[0][i] + qs[1][i];
+      if (row < M) {
+        float q = qs[0][i];
+#pragma unroll
+        for (int w2 = 1; w2 < WGN; ++w2) q += qs[w2][i];
+        g.qpart[(row * g.K + k) * g.ntn + nt] = q;
+      }
     }
   }
 }
@@ -334,9 +350,9 @@ int launch_quad_gemm_bf16(int nprod, const Model &m, const ASrc &a, int64_t M,
   }
   // variants (BM, BN, BK); ray points take the 32-wide k-tile (register budget)
   int BM = (t.bm == 256) ? 256 : 128;
-  int BN = (t.bn == 256 && BM == 128) ? 256 : 128;  // 256 x 256 does not fit the registers
+  int BN = (t.bn == 256) ? 256 : 128;  // 256 x 256 runs on 8 waves (2 x 4)
   int BK = (t.bk == 64 && a.kind == 0 && BN == 128 && BM == 128) ? 64 : 32;
-  if (a.kind == 1) BM = 128;
+  if (a.kind == 1 && BN == 128) BM = 128;
   Bf16Params p;
   p.a = a;
   p.M = M;
@@ -360,11 +376,19 @@ int launch_quad_gemm_bf16(int nprod, const Model &m, const ASrc &a, int64_t M,
   dim3 grid((unsigned)ntile);
 #define SB_BF(NP, KD, BMv, BNv, BKv) \
   hipLaunchKernelGGL((quad_gemm_bf16_kernel<NP, KD, BMv, BNv, BKv>), grid, dim3(256), 0, s, p)
-  if (a.kind == 1) {
+#define SB_BF8(NP, KD) \
+  hipLaunchKernelGGL((quad_gemm_bf16_kernel<NP, KD, 256, 256, 32, 2, 4>), grid, dim3(512), 0, s, p)
+  if (a.kind == 1 && BM == 256 && BN == 256) {
+    if (nprod == 3) SB_BF8(3, 1);
+    else SB_BF8(1, 1);
+  } else if (a.kind == 1) {
     if (nprod == 3 && BN == 128) SB_BF(3, 1, 128, 128, 32);
     else if (nprod == 3) SB_BF(3, 1, 128, 256, 32);
     else if (BN == 128) SB_BF(1, 1, 128, 128, 32);
     else SB_BF(1, 1, 128, 256, 32);
+  } else if (BM == 256 && BN == 256) {
+    if (nprod == 3) SB_BF8(3, 0);
+    else SB_BF8(1, 0);
   } else if (nprod == 3) {
     if (BM == 128 && BN == 128 && BK == 32) SB_BF(3, 0, 128, 128, 32);
     else if (BM == 128 && BN == 128) SB_BF(3, 0, 128, 128, 64);
@@ -376,6 +400,7 @@ int launch_quad_gemm_bf16(int nprod, const Model &m, const ASrc &a, int64_t M,
     else if (BM == 256 && BN == 128) SB_BF(1, 0, 256, 128, 32);
     else SB_BF(1, 0, 128, 256, 32);
   }
+#undef SB_BF8
 #undef SB_BF
   SB_LAUNCH_CHECK();
   return SB_OK;

@@ -102,3 +102,55 @@ def test_split_logl_grad(L, name):
     el = float(np.max(np.abs(l - lo) / (q_scale + np.abs(lo))))
     eg = float(np.max(np.abs(g - go) / np.maximum(1.0, np.abs(go).max(axis=1, keepdims=True))))
     assert el < 5e-4 and eg < 5e-4, (el, eg)
+
+
+TILES = ["128x128x32", "128x128x64", "256x128x32", "128x256x32", "256x256x32"]
+
+
+@pytest.fixture
+def forced_tile(request):
+    import os
+
+    old = os.environ.get("SB_TILE")
+    os.environ["SB_TILE"] = request.param
+    yield request.param
+    if old is None:
+        os.environ.pop("SB_TILE", None)
+    else:
+        os.environ["SB_TILE"] = old
+
+
+@pytest.mark.parametrize("forced_tile", TILES, indirect=True)
+@pytest.mark.parametrize("d,B", [(200, 300), (1024, 129)])
+def test_split_every_tile_variant(L, forced_tile, d, B):
+    """Each tile variant the autotuner may pick, on ragged row and column tails."""
+    prob = gaussian(d, 950 + d)
+    X = synth.random_points(prob, B, 951, spread=0.7).astype(np.float32).astype(np.float64)
+    m = L.DeviceModel(prob, low_precision=True)
+    _, g = L.sb_logl_grad_dev(m, torch.as_tensor(X, device="cuda").float(),
+                              dtype=L.DTYPE_F32_SPLIT)
+    g = g.double().cpu().numpy()
+    _, g_ref = O.logl(prob, X)
+    delta = X - prob.mu[0]
+    bound = 2.0 ** -14 * (np.abs(delta) @ np.abs(prob.prec[0]).T) + 1e-30
+    assert float(np.max(np.abs(g - g_ref) / bound)) <= 1.0
+
+
+@pytest.mark.parametrize("forced_tile", ["128x128x32", "128x256x32", "256x256x32"], indirect=True)
+def test_bf16_discovery_every_tile_variant(L, forced_tile):
+    """BF16 ray-point contraction per tile variant: the best BF16 sample of each ray lies
+    within the BF16 error bound of the ray's FP64 maximum."""
+    rng = np.random.Generator(np.random.PCG64(61))
+    prob = synth.gaussian_mixture(rng, 96, 2, -8.0, 8.0, 0.05, 1.0, 12.0, box_half=12.0,
+                                  norm=synth.NORM_DENSITY, linf_min=1.0)
+    R, npts = 96, 32
+    m = L.DeviceModel(prob, low_precision=True)
+    out = L.sb_discover_dev(m, R, npts, 32, 7, dtype=L.DTYPE_BF16)
+    ref = O.discover(prob, R, npts, 32, 7)
+    P0o, P1o = O.rays(prob.d, prob.lo, prob.hi, R, 7)
+    bj = out["ray_best_j"].cpu().numpy()
+    pts = P0o + ((bj + 0.5) / npts)[:, None] * (P1o - P0o)
+    lv = O.logl(prob, pts, grad=False)
+    gap = ref["ray_best_l"] - lv
+    assert float(gap.min()) >= -1e-9
+    assert float(np.max(gap / np.maximum(1.0, np.abs(ref["ray_best_l"])))) < 0.05
