@@ -49,7 +49,8 @@ __device__ inline float hi_half(uint32_t u) { return __builtin_bit_cast(float, u
 template <int BM, int BN, int BK, int KIND, int NPROD, int NT>
 struct Bf16Occ {
   static constexpr int value =
-      NT == 512 ? 2 : ((BM == 128 && BN == 128) ? ((BK == 32 && !(KIND == 1 && NPROD == 3)) ? 3 : 2) : 1);
+      NT == 512 ? 2
+                : ((BM == 128 && BN == 128) ? ((BK == 32 && !(KIND == 1 && NPROD == 3)) ? 3 : 2) : 1);
 };
 
 // NT = 64 * WGM * WGN threads: a WGM x WGN grid of waves, each owning a
@@ -150,24 +151,38 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
 
   f4v ra[NA], rq[NA], rmu;
   u4v rbh[NB], rbl[NB];
-  // k-tile loads; a full tile (k0 + BK <= d, uniform) needs no column test
+  // k-tile loads.  Rows past M (A) or d (B) read a clamped valid row: they
+  // feed only outputs that are never written.  A whole k-tile (the uniform
+  // case k0 + BK <= d) loads unconditionally; the tail zeroes k >= d.
   auto load = [&](int k0) {
-    const bool full = k0 + BK <= d;
-    const bool kin = full || (k0 + ca * 4 < d);
-    const uint32_t ka = 4u * (uint32_t)k0;
+    const uint32_t ka = 4u * (uint32_t)k0, kb = 2u * (uint32_t)k0;
+    if (k0 + BK <= d) {
 #pragma unroll
-    for (int r = 0; r < NA; ++r) {
-      ra[r] = kin ? *(const f4v *)(Xa + (aoff[r] + ka)) : f4v{0.f, 0.f, 0.f, 0.f};
-      if constexpr (KIND == 1)
-        rq[r] = kin ? *(const f4v *)(Xb + (aoff[r] + ka)) : f4v{0.f, 0.f, 0.f, 0.f};
-    }
-    rmu = kin ? *(const f4v *)((const char *)mu + (muoff + ka)) : f4v{0.f, 0.f, 0.f, 0.f};
-    const bool kbin = full || (k0 + cb * 8 < d);
-    const uint32_t kb = 2u * (uint32_t)k0;
+      for (int r = 0; r < NA; ++r) {
+        ra[r] = *(const f4v *)(Xa + (aoff[r] + ka));
+        if constexpr (KIND == 1) rq[r] = *(const f4v *)(Xb + (aoff[r] + ka));
+      }
+      rmu = *(const f4v *)((const char *)mu + (muoff + ka));
 #pragma unroll
-    for (int r = 0; r < NB; ++r) {
-      rbh[r] = kbin ? *(const u4v *)(Phb + (boff[r] + kb)) : u4v{0u, 0u, 0u, 0u};
-      if constexpr (SPLIT) rbl[r] = kbin ? *(const u4v *)(Plb + (boff[r] + kb)) : u4v{0u, 0u, 0u, 0u};
+      for (int r = 0; r < NB; ++r) {
+        rbh[r] = *(const u4v *)(Phb + (boff[r] + kb));
+        if constexpr (SPLIT) rbl[r] = *(const u4v *)(Plb + (boff[r] + kb));
+      }
+    } else {
+      const bool kin = k0 + ca * 4 < d;
+#pragma unroll
+      for (int r = 0; r < NA; ++r) {
+        ra[r] = kin ? *(const f4v *)(Xa + (aoff[r] + ka)) : f4v{0.f, 0.f, 0.f, 0.f};
+        if constexpr (KIND == 1)
+          rq[r] = kin ? *(const f4v *)(Xb + (aoff[r] + ka)) : f4v{0.f, 0.f, 0.f, 0.f};
+      }
+      rmu = kin ? *(const f4v *)((const char *)mu + (muoff + ka)) : f4v{0.f, 0.f, 0.f, 0.f};
+      const bool kbin = k0 + cb * 8 < d;
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        rbh[r] = kbin ? *(const u4v *)(Phb + (boff[r] + kb)) : u4v{0u, 0u, 0u, 0u};
+        if constexpr (SPLIT) rbl[r] = kbin ? *(const u4v *)(Plb + (boff[r] + kb)) : u4v{0u, 0u, 0u, 0u};
+      }
     }
   };
   auto store = [&]() {
@@ -184,7 +199,7 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
 #pragma clang fp contract(off)
           x = ra[r][e] + tpar[r] * (rq[r][e] - ra[r][e]);
         }
-        v[e] = aok[r] ? x - rmu[e] : 0.f;
+        v[e] = x - rmu[e];  // k >= d: both zero
       }
       const uint32_t h01 = pack2(v[0], v[1]), h23 = pack2(v[2], v[3]);
       const int ai = lds(i, ca * 4);
@@ -200,8 +215,8 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
     for (int r = 0; r < NB; ++r) {
       const int n = (tid + NT * r) / VB;
       const int bi = lds(n, cb * 8);
-      *(u4v *)&Bh[bi] = bok[r] ? rbh[r] : u4v{0u, 0u, 0u, 0u};
-      if constexpr (SPLIT) *(u4v *)&Bl[bi] = bok[r] ? rbl[r] : u4v{0u, 0u, 0u, 0u};
+      *(u4v *)&Bh[bi] = rbh[r];
+      if constexpr (SPLIT) *(u4v *)&Bl[bi] = rbl[r];
     }
   };
 
@@ -229,12 +244,24 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
         bhv[j] = *(const bf8v *)&Bh[o];
         if constexpr (SPLIT) blv[j] = *(const bf8v *)&Bl[o];
       }
+      // A fragments of row block i + 1 are read while block i multiplies
+      bf8v ahb[2], alb[2];
+      {
+        const int o = lds(wm * WM + fr, kk + fk);
+        ahb[0] = *(const bf8v *)&Ah[o];
+        if constexpr (SPLIT) alb[0] = *(const bf8v *)&Al[o];
+      }
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        const int o = lds(wm * WM + i * 16 + fr, kk + fk);
-        const bf8v ah = *(const bf8v *)&Ah[o];
+        const int cbuf = i & 1;
+        if (i + 1 < TM) {
+          const int o = lds(wm * WM + (i + 1) * 16 + fr, kk + fk);
+          ahb[cbuf ^ 1] = *(const bf8v *)&Ah[o];
+          if constexpr (SPLIT) alb[cbuf ^ 1] = *(const bf8v *)&Al[o];
+        }
+        const bf8v ah = ahb[cbuf];
         if constexpr (SPLIT) {
-          const bf8v al = *(const bf8v *)&Al[o];
+          const bf8v al = alb[cbuf];
 #pragma unroll
           for (int j = 0; j < TN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bhv[j], acc[i][j], 0, 0, 0);
