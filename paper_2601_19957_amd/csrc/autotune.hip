@@ -3,13 +3,14 @@
 // The first time a shape class (dtype, d, K, M rounded up to a power of two)
 // is seen, each candidate tile (BM x BN in {64, 128}^2; for the BF16 and
 // split contractions BM x BN x k-tile in {128x128x32, 128x128x64, 256x128x32,
-// 128x256x32, 256x256x32 on eight waves}) is timed with HIP events, one warm-up and three timed launches,
+// 128x256x32, 256x256x32 on eight waves}, the square 32-wide ones also with
+// two ping-pong LDS stages) is timed with HIP events, one warm-up and three timed launches,
 // and the fastest is cached for the process.  The launches run on the
 // caller's probe (its operands and scratch outputs, which the real launch
 // overwrites) or, for host-level callers, on private seeded buffers of the
 // shape (up to 8192 rows, values in [-1, 1)).  Timing synchronises the
 // stream, so a stream under graph capture gets the heuristic choice (not
-// cached).  SB_TILE=BMxBN[xBK] forces a shape;
+// cached).  SB_TILE=BMxBN[xBK[xSTAGES]] forces a shape;
 // SB_AUTOTUNE=0 uses the heuristic without timing.
 #include <algorithm>
 #include <cstdio>
@@ -73,14 +74,16 @@ bool time_launches(int dtype, const Model &m, const ASrc &a, QuadOut o, int64_t 
   float best_ms = 0.f;
   // GEMM tiles (BM, BN); for the BF16 kernels (BM, BN, k-tile)
   const int cands[4][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}};
-  const int cands_bf[5][3] = {{128, 128, 32}, {128, 128, 64}, {256, 128, 32}, {128, 256, 32},
-                              {256, 256, 32}};
-  const int nc = bf ? 5 : 4;
+  const int cands_bf[7][4] = {{128, 128, 32, 1}, {128, 128, 64, 1}, {256, 128, 32, 1},
+                              {128, 256, 32, 1}, {256, 256, 32, 1}, {128, 128, 32, 2},
+                              {256, 256, 32, 2}};
+  const int nc = bf ? 7 : 4;
   for (int c = 0; c < nc && ok; ++c) {
     TileCfg t;
     t.bm = bf ? cands_bf[c][0] : cands[c][0];
     t.bn = bf ? cands_bf[c][1] : cands[c][1];
     t.bk = bf ? cands_bf[c][2] : 32;
+    t.stages = bf ? cands_bf[c][3] : 1;
     ok = launch_quad_gemm(dtype, m, a, M, nullptr, o, t, s) == SB_OK;  // warm-up
     ok = ok && hipEventRecord(e0, s) == hipSuccess;
     for (int r = 0; r < 3 && ok; ++r) ok = launch_quad_gemm(dtype, m, a, M, nullptr, o, t, s) == SB_OK;
@@ -170,12 +173,13 @@ TileCfg autotune_tiles(int dtype, const Model &m, int64_t M, hipStream_t s, cons
                        bool may_alloc) {
   const char *force = getenv("SB_TILE");
   if (force) {
-    int bm = 0, bn = 0, bk = 32;
-    if (sscanf(force, "%dx%dx%d", &bm, &bn, &bk) >= 2) {
+    int bm = 0, bn = 0, bk = 32, st = 1;
+    if (sscanf(force, "%dx%dx%dx%d", &bm, &bn, &bk, &st) >= 2) {
       TileCfg t;
       t.bm = bm;
       t.bn = bn;
       t.bk = bk;
+      t.stages = st;
       return t;
     }
   }

@@ -44,19 +44,31 @@ __device__ inline uint32_t pack2(float a, float b) {
 __device__ inline float lo_half(uint32_t u) { return __builtin_bit_cast(float, u << 16); }
 __device__ inline float hi_half(uint32_t u) { return __builtin_bit_cast(float, u & 0xffff0000u); }
 
+// Rows per epilogue pass: the largest WM / 2^i (at least 16) within `fit`.
+constexpr int stage_rows(int wm, int fit) {
+  int r = wm;
+  while (r > 16 && r > fit) r /= 2;
+  return r;
+}
+
 // Launch bounds: workgroup size and the minimum waves per SIMD the register
 // allocation must leave room for.
-template <int BM, int BN, int BK, int KIND, int NPROD, int NT>
+template <int BM, int BN, int BK, int KIND, int NPROD, int NT, int NS>
 struct Bf16Occ {
   static constexpr int value =
-      NT == 512 ? 2
-                : ((BM == 128 && BN == 128) ? ((BK == 32 && !(KIND == 1 && NPROD == 3)) ? 3 : 2) : 1);
+      (NT == 512 || NS == 2)
+          ? 2
+          : ((BM == 128 && BN == 128) ? ((BK == 32 && !(KIND == 1 && NPROD == 3)) ? 3 : 2) : 1);
 };
 
 // NT = 64 * WGM * WGN threads: a WGM x WGN grid of waves, each owning a
-// (BM / WGM) x (BN / WGN) block of the tile.
-template <int NPROD, int KIND, int BM, int BN, int BK, int WGM = 2, int WGN = 2>
-__global__ __launch_bounds__(64 * WGM * WGN, (Bf16Occ<BM, BN, BK, KIND, NPROD, 64 * WGM * WGN>::value))
+// (BM / WGM) x (BN / WGN) block of the tile.  NS LDS stages: with one, a
+// k-tile is stored, multiplied and released between two barriers; with two
+// (ping-pong), the split and store of k-tile t + 1 run beside the MFMAs of
+// k-tile t, one barrier per k-tile.
+template <int NPROD, int KIND, int BM, int BN, int BK, int WGM = 2, int WGN = 2, int NS = 1>
+__global__ __launch_bounds__(64 * WGM * WGN,
+                             (Bf16Occ<BM, BN, BK, KIND, NPROD, 64 * WGM * WGN, NS>::value))
 void quad_gemm_bf16_kernel(Bf16Params g) {
   constexpr int NT = 64 * WGM * WGN;
   // LDS rows of BK bf16 without padding; the 16-byte chunk c of row r sits
@@ -75,10 +87,21 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
   constexpr int NB = BN * VB / NT;    // per thread and operand half
   constexpr bool SPLIT = NPROD == 3;
   static_assert(NA >= 1 && NB >= 1 && NT % VA == 0 && NT % VB == 0, "tile");
-  __shared__ __attribute__((aligned(16))) bf16_t Ah[BM * BK];
-  __shared__ __attribute__((aligned(16))) bf16_t Al[SPLIT ? BM * BK : 8];
-  __shared__ __attribute__((aligned(16))) bf16_t Bh[BN * BK];
-  __shared__ __attribute__((aligned(16))) bf16_t Bl[SPLIT ? BN * BK : 8];
+  static_assert(NS == 1 || NS == 2, "stages");
+  // One LDS arena: the k-tile stages during the main loop, then the
+  // epilogue's per-wave staging of the accumulators (SR rows of WN + 4
+  // floats per wave and pass).
+  constexpr int NH = SPLIT ? 2 : 1;  // operand halves
+  constexpr int MAIN_B = NS * NH * (BM + BN) * BK * 2;
+  constexpr int NWV = WGM * WGN, SLD = WN + 4;
+  constexpr int SR = stage_rows(WM, MAIN_B / (NWV * SLD * 4));
+  constexpr int ARENA_B = MAIN_B > NWV * SR * SLD * 4 ? MAIN_B : NWV * SR * SLD * 4;
+  static_assert(WM % SR == 0, "epilogue passes");
+  __shared__ __attribute__((aligned(16))) char arena[ARENA_B];
+  bf16_t *const Ah = (bf16_t *)arena;
+  bf16_t *const Al = Ah + NS * BM * BK;
+  bf16_t *const Bh = Ah + NH * NS * BM * BK;
+  bf16_t *const Bl = Bh + NS * BN * BK;
   __shared__ float qs[WGN][BM];
 
   // XCD-aware tile order.  Workgroup w runs on XCD w % 8; each XCD owns a
@@ -185,7 +208,8 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
       }
     }
   };
-  auto store = [&]() {
+  auto store = [&](int st) {  // into LDS stage st
+    const int sa = st * BM * BK, sbo = st * BN * BK;
 #pragma unroll
     for (int r = 0; r < NA; ++r) {
       const int i = (tid + NT * r) / VA;
@@ -202,7 +226,7 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
         v[e] = x - rmu[e];  // k >= d: both zero
       }
       const uint32_t h01 = pack2(v[0], v[1]), h23 = pack2(v[2], v[3]);
-      const int ai = lds(i, ca * 4);
+      const int ai = sa + lds(i, ca * 4);
       *(u2v *)&Ah[ai] = u2v{h01, h23};
       if constexpr (SPLIT) {
         // v - hi is exact in FP32 (hi holds v's leading bits); lo rounds it
@@ -214,7 +238,7 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
 #pragma unroll
     for (int r = 0; r < NB; ++r) {
       const int n = (tid + NT * r) / VB;
-      const int bi = lds(n, cb * 8);
+      const int bi = sbo + lds(n, cb * 8);
       *(u4v *)&Bh[bi] = rbh[r];
       if constexpr (SPLIT) *(u4v *)&Bl[bi] = rbl[r];
     }
@@ -227,11 +251,9 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
     for (int j = 0; j < TN; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
 
   const int fr = lane & 15, fk = 8 * (lane >> 4);
-  load(0);
-  for (int k0 = 0; k0 < d; k0 += BK) {
-    store();
-    __syncthreads();
-    if (k0 + BK < d) load(k0 + BK);
+  // MFMAs of the k-tile in LDS stage st
+  auto mma = [&](int st) {
+    const int sa = st * BM * BK, sbo = st * BN * BK;
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 32) {
       // B fragments of this k-step, then one A row block at a time: only
@@ -240,14 +262,14 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
       bf8v bhv[TN], blv[TN];
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        const int o = lds(wn * WN + j * 16 + fr, kk + fk);
+        const int o = sbo + lds(wn * WN + j * 16 + fr, kk + fk);
         bhv[j] = *(const bf8v *)&Bh[o];
         if constexpr (SPLIT) blv[j] = *(const bf8v *)&Bl[o];
       }
       // A fragments of row block i + 1 are read while block i multiplies
       bf8v ahb[2], alb[2];
       {
-        const int o = lds(wm * WM + fr, kk + fk);
+        const int o = sa + lds(wm * WM + fr, kk + fk);
         ahb[0] = *(const bf8v *)&Ah[o];
         if constexpr (SPLIT) alb[0] = *(const bf8v *)&Al[o];
       }
@@ -255,7 +277,7 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
       for (int i = 0; i < TM; ++i) {
         const int cbuf = i & 1;
         if (i + 1 < TM) {
-          const int o = lds(wm * WM + (i + 1) * 16 + fr, kk + fk);
+          const int o = sa + lds(wm * WM + (i + 1) * 16 + fr, kk + fk);
           ahb[cbuf ^ 1] = *(const bf8v *)&Ah[o];
           if constexpr (SPLIT) alb[cbuf ^ 1] = *(const bf8v *)&Al[o];
         }
@@ -274,61 +296,87 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bhv[j], acc[i][j], 0, 0, 0);
       }
     }
+  };
+  load(0);
+  if constexpr (NS == 1) {
+    for (int k0 = 0; k0 < d; k0 += BK) {
+      store(0);
+      __syncthreads();
+      if (k0 + BK < d) load(k0 + BK);
+      mma(0);
+      __syncthreads();
+    }
+  } else {
+    // k-tile t sits in stage t & 1; the registers loaded during k-tile t
+    // are split and stored into the other stage after t's MFMAs are issued
+    store(0);
     __syncthreads();
+    const int nk = (d + BK - 1) / BK;
+    int st = 0;
+    for (int t = 0; t + 1 < nk; ++t) {
+      load((t + 1) * BK);
+      mma(st);
+      store(st ^ 1);
+      __syncthreads();
+      st ^= 1;
+    }
+    mma(st);
   }
 
-  // Epilogue: Y, and per-row partial q over this tile's columns.  Item v of
-  // lane l holds row 4 (l / 16) + v, column l % 16 of its 16 x 16 block.
+  // Epilogue.  Item v of lane l holds row 4 (l / 16) + v, column l % 16 of
+  // its 16 x 16 block; each wave stages SR rows of its tile at a time in
+  // LDS and writes them back as 16-byte row chunks (Y), with the partial
+  // q over its columns from the same chunks of X and mu.
+  if constexpr (NS == 2) __syncthreads();  // (one stage is still being read)
+  float *const stg = (float *)arena + wave * SR * SLD;
   const int lr = lane >> 4, lc = lane & 15;
-  float qrow[TM][4];
+  constexpr int CPR = WN / 4, RPI = 64 / CPR;  // float4 chunks per row, rows per instruction
+  static_assert(CPR <= 64 && 64 % CPR == 0 && SR % RPI == 0, "epilogue layout");
+  const int er = lane / CPR, ec = lane % CPR;
+  const int c0 = n0 + wn * WN + 4 * ec;  // this lane's first column
+  const bool cin = c0 < d;               // d % 8 == 0: the whole chunk is in or out
+  const f4v muv = cin ? *(const f4v *)(mu + c0) : f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int p0 = 0; p0 < WM; p0 += SR) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) qrow[i][v] = 0.f;
+    for (int i = p0 / 16; i < (p0 + SR) / 16; ++i)
 #pragma unroll
-  for (int i = 0; i < TM; ++i) {
+      for (int j = 0; j < TN; ++j)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t row = m0 + wm * WM + i * 16 + 4 * lr + v;
-      if (row >= M) continue;
-      uint32_t off;
-      float tt;
-      row_off(row, off, tt);
-      const float *pa = (const float *)Xa + off;
-      const float *pb = (const float *)Xb + off;
+        for (int v = 0; v < 4; ++v) stg[(i * 16 - p0 + 4 * lr + v) * SLD + j * 16 + lc] = acc[i][j][v];
+    // the wave reads back what its other lanes wrote
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int n = n0 + wn * WN + j * 16 + lc;
-        if (n >= d) continue;
-        const float yv = acc[i][j][v];
-        if (g.Y) g.Y[row * g.ldy + (int64_t)k * d + n] = yv;
-        float x;
-        if constexpr (KIND == 0) {
-          x = pa[n];
-        } else {
+    for (int rr = 0; rr < SR; rr += RPI) {
+      const int lrow = wm * WM + p0 + rr + er;  // row within the tile
+      const int64_t row = m0 + lrow;
+      const f4v y = *(const f4v *)&stg[(rr + er) * SLD + 4 * ec];
+      float q = 0.f;
+      if (row < M && cin) {
+        if (g.Y) *(f4v *)&g.Y[row * g.ldy + (int64_t)k * d + c0] = y;
+        uint32_t off;
+        float tt;
+        row_off(row, off, tt);
+        f4v x = *(const f4v *)((const float *)Xa + off + c0);
+        if constexpr (KIND == 1) {
 #pragma clang fp contract(off)
-          x = pa[n] + tt * (pb[n] - pa[n]);
+          const f4v xb = *(const f4v *)((const float *)Xb + off + c0);
+          for (int e = 0; e < 4; ++e) x[e] = x[e] + tt * (xb[e] - x[e]);
         }
-        qrow[i][v] += (x - mu[n]) * yv;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) q += (x[e] - muv[e]) * y[e];
       }
+#pragma unroll
+      for (int o = 1; o < CPR; o <<= 1) q += __shfl_xor(q, o, 64);
+      if (ec == 0) qs[wn][lrow] = q;
     }
-  }
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      float t = qrow[i][v];
-      t += __shfl_xor(t, 1, 64);
-      t += __shfl_xor(t, 2, 64);
-      t += __shfl_xor(t, 4, 64);
-      t += __shfl_xor(t, 8, 64);
-      qrow[i][v] = t;
-    }
-  if (lc == 0) {
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) qs[wn][wm * WM + i * 16 + 4 * lr + v] = qrow[i][v];
+    // the next pass overwrites the staging rows
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   __syncthreads();
   if (g.qpart) {
@@ -375,6 +423,14 @@ int launch_quad_gemm_bf16(int nprod, const Model &m, const ASrc &a, int64_t M,
     set_error("BF16 contraction operands above 4 GiB");
     return SB_E_UNSUPPORTED;
   }
+  // 16-byte vector access to the point rows, mu and Y
+  const bool al16 = ((uintptr_t)(a.kind == 0 ? a.X : a.P0) % 16 == 0) &&
+                    (a.kind == 0 || (uintptr_t)a.P1 % 16 == 0) && (uintptr_t)m.mu32 % 16 == 0 &&
+                    (uintptr_t)o.Y % 16 == 0 && (a.kind == 1 || a.ldx % 4 == 0) && o.ldy % 4 == 0;
+  if (!al16) {
+    set_error("BF16 contraction needs 16-byte aligned X, mu and Y and row strides a multiple of 4");
+    return SB_E_INVAL;
+  }
   // variants (BM, BN, BK); ray points take the 32-wide k-tile (register budget)
   int BM = (t.bm == 256) ? 256 : 128;
   int BN = (t.bn == 256) ? 256 : 128;  // 256 x 256 runs on 8 waves (2 x 4)
@@ -405,7 +461,17 @@ int launch_quad_gemm_bf16(int nprod, const Model &m, const ASrc &a, int64_t M,
   hipLaunchKernelGGL((quad_gemm_bf16_kernel<NP, KD, BMv, BNv, BKv>), grid, dim3(256), 0, s, p)
 #define SB_BF8(NP, KD) \
   hipLaunchKernelGGL((quad_gemm_bf16_kernel<NP, KD, 256, 256, 32, 2, 4>), grid, dim3(512), 0, s, p)
-  if (a.kind == 1 && BM == 256 && BN == 256) {
+#define SB_BFP(NP, BMv, BNv, WGNv) \
+  hipLaunchKernelGGL((quad_gemm_bf16_kernel<NP, 0, BMv, BNv, 32, 2, WGNv, 2>), grid, \
+                     dim3(128 * WGNv), 0, s, p)
+  const bool pp = t.stages == 2 && a.kind == 0 && BK == 32 && BM == BN;
+  if (pp && BM == 256) {
+    if (nprod == 3) SB_BFP(3, 256, 256, 4);
+    else SB_BFP(1, 256, 256, 4);
+  } else if (pp) {
+    if (nprod == 3) SB_BFP(3, 128, 128, 2);
+    else SB_BFP(1, 128, 128, 2);
+  } else if (a.kind == 1 && BM == 256 && BN == 256) {
     if (nprod == 3) SB_BF8(3, 1);
     else SB_BF8(1, 1);
   } else if (a.kind == 1) {
@@ -427,6 +493,7 @@ int launch_quad_gemm_bf16(int nprod, const Model &m, const ASrc &a, int64_t M,
     else if (BM == 256 && BN == 128) SB_BF(1, 0, 256, 128, 32);
     else SB_BF(1, 0, 128, 256, 32);
   }
+#undef SB_BFP
 #undef SB_BF8
 #undef SB_BF
   SB_LAUNCH_CHECK();

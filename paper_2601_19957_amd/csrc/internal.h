@@ -100,7 +100,8 @@ struct QuadOut {
 // Tile shape used for a GEMM call; chosen by the autotuner.
 struct TileCfg {
   int bm = 128, bn = 128;
-  int bk = 32;  // k-tile of the BF16 matrix-core kernels
+  int bk = 32;      // k-tile of the BF16 matrix-core kernels
+  int stages = 1;  // BF16 kernels: LDS stages (2 = ping-pong, square tiles, k-tile 32)
 };
 
 int quad_gemm_ntn(int dtype, int d, TileCfg t);

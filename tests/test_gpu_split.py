@@ -104,7 +104,8 @@ def test_split_logl_grad(L, name):
     assert el < 5e-4 and eg < 5e-4, (el, eg)
 
 
-TILES = ["128x128x32", "128x128x64", "256x128x32", "128x256x32", "256x256x32"]
+TILES = ["128x128x32", "128x128x64", "256x128x32", "128x256x32", "256x256x32",
+         "128x128x32x2", "256x256x32x2"]
 
 
 @pytest.fixture
