@@ -94,7 +94,12 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
   constexpr int NH = SPLIT ? 2 : 1;  // operand halves
   constexpr int MAIN_B = NS * NH * (BM + BN) * BK * 2;
   constexpr int NWV = WGM * WGN, SLD = WN + 4;
-  constexpr int SR = stage_rows(WM, MAIN_B / (NWV * SLD * 4));
+  // LDS a workgroup may take without lowering its occupancy (known for the
+  // square tiles, whose register use meets the launch bound); the staging
+  // may grow the arena up to it
+  constexpr int WGCU = (Bf16Occ<BM, BN, BK, KIND, NPROD, NT, NS>::value * 4) / NWV;
+  constexpr int CAP = BM == BN ? (160 * 1024) / (WGCU > 0 ? WGCU : 1) - WGN * BM * 4 - 1024 : 0;
+  constexpr int SR = stage_rows(WM, (MAIN_B > CAP ? MAIN_B : CAP) / (NWV * SLD * 4));
   constexpr int ARENA_B = MAIN_B > NWV * SR * SLD * 4 ? MAIN_B : NWV * SR * SLD * 4;
   static_assert(WM % SR == 0, "epilogue passes");
   __shared__ __attribute__((aligned(16))) char arena[ARENA_B];
@@ -326,16 +331,19 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
   // Epilogue.  Item v of lane l holds row 4 (l / 16) + v, column l % 16 of
   // its 16 x 16 block; each wave stages SR rows of its tile at a time in
   // LDS and writes them back as 16-byte row chunks (Y), with the partial
-  // q over its columns from the same chunks of X and mu.
-  if constexpr (NS == 2) __syncthreads();  // (one stage is still being read)
-  float *const stg = (float *)arena + wave * SR * SLD;
+  // q over its columns from the same chunks of X and mu.  Passes are as
+  // large as the LDS the occupancy leaves allows, so the X loads of a pass
+  // are issued together.
   const int lr = lane >> 4, lc = lane & 15;
   constexpr int CPR = WN / 4, RPI = 64 / CPR;  // float4 chunks per row, rows per instruction
+  constexpr int NU = SR / RPI;                 // rows per lane and pass
   static_assert(CPR <= 64 && 64 % CPR == 0 && SR % RPI == 0, "epilogue layout");
   const int er = lane / CPR, ec = lane % CPR;
   const int c0 = n0 + wn * WN + 4 * ec;  // this lane's first column
   const bool cin = c0 < d;               // d % 8 == 0: the whole chunk is in or out
   const f4v muv = cin ? *(const f4v *)(mu + c0) : f4v{0.f, 0.f, 0.f, 0.f};
+  if constexpr (NS == 2) __syncthreads();  // (one stage is still being read)
+  float *const stg = (float *)arena + wave * SR * SLD;
 #pragma unroll
   for (int p0 = 0; p0 < WM; p0 += SR) {
 #pragma unroll
@@ -350,10 +358,10 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-    for (int rr = 0; rr < SR; rr += RPI) {
-      const int lrow = wm * WM + p0 + rr + er;  // row within the tile
+    for (int u = 0; u < NU; ++u) {
+      const int lrow = wm * WM + p0 + u * RPI + er;  // row within the tile
       const int64_t row = m0 + lrow;
-      const f4v y = *(const f4v *)&stg[(rr + er) * SLD + 4 * ec];
+      const f4v y = *(const f4v *)&stg[(u * RPI + er) * SLD + 4 * ec];
       float q = 0.f;
       if (row < M && cin) {
         if (g.Y) *(f4v *)&g.Y[row * g.ldy + (int64_t)k * d + c0] = y;
@@ -363,8 +371,8 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
         f4v x = *(const f4v *)((const float *)Xa + off + c0);
         if constexpr (KIND == 1) {
 #pragma clang fp contract(off)
-          const f4v xb = *(const f4v *)((const float *)Xb + off + c0);
-          for (int e = 0; e < 4; ++e) x[e] = x[e] + tt * (xb[e] - x[e]);
+          const f4v xq = *(const f4v *)((const float *)Xb + off + c0);
+          for (int e = 0; e < 4; ++e) x[e] = x[e] + tt * (xq[e] - x[e]);
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) q += (x[e] - muv[e]) * y[e];
