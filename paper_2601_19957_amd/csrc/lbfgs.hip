@@ -84,6 +84,46 @@ __device__ inline void vstore(T *p, int i0, int d, bool vec, const T (&v)[EPT]) 
     if (i0 + e < d) p[i0 + e] = v[e];
 }
 
+// Workgroup reductions over a two-slot LDS ring, one barrier each (the
+// summation order of block_sum: butterfly within each wave, then the wave
+// totals in order, so results are the same).  Reduction k writes slot
+// k & 1; a thread reaches the write of reduction k + 2 only after every
+// thread has passed the barrier of reduction k + 1, that is, after every
+// read of reduction k.  All threads make the same sequence of calls.
+template <int TPB, typename T>
+struct BlockRed {
+  static constexpr int NW = TPB / 64, NMAX = 4;
+  T *buf;  // LDS, 2 * NMAX * NW elements
+  int slot;
+  template <int N, bool MAX>
+  __device__ void reduce(T (&v)[N]) {
+    static_assert(N <= NMAX, "values per reduction");
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = MAX ? wave_max(v[j]) : wave_sum(v[j]);
+    if constexpr (NW > 1) {
+      T *r = buf + slot * (NMAX * NW);
+      slot ^= 1;
+      const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+      if (l == 0)
+#pragma unroll
+        for (int j = 0; j < N; ++j) r[j * NW + w] = v[j];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        T t = r[j * NW];
+#pragma unroll
+        for (int i = 1; i < NW; ++i) t = MAX ? fmax(t, r[j * NW + i]) : t + r[j * NW + i];
+        v[j] = t;
+      }
+    }
+  }
+  __device__ T sum(T x) {
+    T v[1] = {x};
+    reduce<1, false>(v);
+    return v[0];
+  }
+};
+
 // Two-loop recursion on register-resident history (logical order, oldest
 // first).  q <- g; backward: alpha_j = rho_j s_j^T q, q -= alpha_j y_j;
 // r = gamma q, gamma = s^T y / y^T y of the newest pair; forward:
@@ -91,7 +131,7 @@ __device__ inline void vstore(T *p, int i0, int d, bool vec, const T (&v)[EPT]) 
 template <typename T, int TPB, int EPT>
 __device__ inline void two_loop(const T (&Sr)[kMaxHist][EPT], const T (&Yr)[kMaxHist][EPT],
                                 const T (&rh)[kMaxHist], T gamma, int cnt, const T (&g)[EPT],
-                                T (&p)[EPT], T *red) {
+                                T (&p)[EPT], BlockRed<TPB, T> &red) {
   T q[EPT], al[kMaxHist];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) q[e] = g[e];
@@ -101,7 +141,7 @@ __device__ inline void two_loop(const T (&Sr)[kMaxHist][EPT], const T (&Yr)[kMax
       T dd = 0;
 #pragma unroll
       for (int e = 0; e < EPT; ++e) dd += Sr[j][e] * q[e];
-      dd = block_sum<TPB>(dd, red);
+      dd = red.sum(dd);
       al[j] = rh[j] * dd;
 #pragma unroll
       for (int e = 0; e < EPT; ++e) q[e] -= al[j] * Yr[j][e];
@@ -117,7 +157,7 @@ __device__ inline void two_loop(const T (&Sr)[kMaxHist][EPT], const T (&Yr)[kMax
       T bb = 0;
 #pragma unroll
       for (int e = 0; e < EPT; ++e) bb += Yr[j][e] * q[e];
-      bb = rh[j] * block_sum<TPB>(bb, red);
+      bb = rh[j] * red.sum(bb);
 #pragma unroll
       for (int e = 0; e < EPT; ++e) q[e] += (al[j] - bb) * Sr[j][e];
     }
@@ -128,7 +168,8 @@ __device__ inline void two_loop(const T (&Sr)[kMaxHist][EPT], const T (&Yr)[kMax
 
 // One step of start s (the whole workgroup; every branch is uniform in s).
 template <typename T, int TPB, int EPT>
-__device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t s, T *red) {
+__device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t s,
+                                               BlockRed<TPB, T> &red) {
   const int tid = threadIdx.x;
   if (a.status[s] != ST_ACTIVE) {
     if (tid == 0) a.active[s] = 0;
@@ -254,7 +295,7 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
       v3[1] += sv[e] * sv[e];
       v3[2] += yv[e] * yv[e];
     }
-    block_sum_n<TPB, 3>(v3, red);
+    red.template reduce<3, false>(v3);
     const T sy = v3[0], ss = v3[1], yy = v3[2];
     cur = newcur;
     ++it;
@@ -307,9 +348,12 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
     gn = fmax(gn, fabs(gl[e]));
     if (!isfinite(gl[e])) bad = 1;
   }
-  gn = block_max<TPB>(gn, red);
-  bad = block_max<TPB>(bad, red);
-  if (bad != (T)0) gn = (T)NAN;
+  {
+    T v2[2] = {gn, bad};
+    red.template reduce<2, true>(v2);
+    gn = v2[0];
+    if (v2[1] != (T)0) gn = (T)NAN;
+  }
   int newst = ST_ACTIVE;
   if (mode == M_INIT && !(isfinite(lcur) && isfinite(gn)))
     newst = ST_DEAD;
@@ -349,7 +393,7 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
     T t = 0;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) t += g[e] * p[e];
-    gtp = block_sum<TPB>(t, red);
+    gtp = red.sum(t);
     if (!(gtp < (T)0)) {
       sd = true;
       cnt = 0;
@@ -364,7 +408,7 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
       p[e] = -g[e] * sc;
       t += g[e] * p[e];
     }
-    gtp = block_sum<TPB>(t, red);
+    gtp = red.sum(t);
   }
   const int tr = 1 - cur;
   T *xt = a.X + (size_t)tr * Lt + vo;
@@ -392,7 +436,8 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
 // Start s_base + blockIdx.x (one workgroup per start of the launch's range).
 template <typename T, int TPB, int EPT>
 __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
-  __shared__ T red[4 * (TPB / 64)];
+  __shared__ T rbuf[2 * BlockRed<TPB, T>::NMAX * (TPB / 64)];
+  BlockRed<TPB, T> red{rbuf, 0};
   // the compaction that follows counts from zero; every reader of the
   // previous count ran before this launch
   if (a.count_reset && blockIdx.x == 0 && threadIdx.x == 0) *a.count_reset = 0;
@@ -406,7 +451,8 @@ __global__ __launch_bounds__(TPB) void two_loop_kernel(int d, int m, const int32
                                                        const T *S, const T *Y, const T *G, T *P) {
   const int64_t b = blockIdx.x;
   const int tid = threadIdx.x;
-  __shared__ T red[4 * (TPB / 64)];
+  __shared__ T rbuf[2 * BlockRed<TPB, T>::NMAX * (TPB / 64)];
+  BlockRed<TPB, T> red{rbuf, 0};
   const int cnt = min(max(cntv[b], 0), m);  // never read past this start's m slots
   T Sr[kMaxHist][EPT], Yr[kMaxHist][EPT], rh[kMaxHist], g[EPT], p[EPT];
   T gamma = 1;
@@ -430,7 +476,7 @@ __global__ __launch_bounds__(TPB) void two_loop_kernel(int d, int m, const int32
         v2[0] += Sr[j][e] * Yr[j][e];
         v2[1] += Yr[j][e] * Yr[j][e];
       }
-      block_sum_n<TPB, 2>(v2, red);
+      red.template reduce<2, false>(v2);
       rh[j] = (T)1 / v2[0];
       if (j == cnt - 1) gamma = v2[0] / v2[1];
     }

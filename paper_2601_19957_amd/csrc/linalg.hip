@@ -4,9 +4,9 @@
 // Whitening"); log det H = 2 sum_i log L_ii.  A failed pivot means H is not
 // positive definite, i.e. the candidate is not a maximum (saddle filter of
 // GreenDragon, generalised).  Blocked right-looking factorisation with 64-wide
-// panels: diagonal block in LDS, triangular solve of the panel below it,
-// symmetric rank-64 update of the trailing lower triangle.  One launch per
-// stage covers every matrix of the batch.
+// panels: diagonal block in registers, triangular solve of the panel below
+// it, symmetric rank-64 update of the trailing lower triangle.  One launch
+// per stage covers every matrix of the batch.
 #include <algorithm>
 
 #include "internal.h"
@@ -15,84 +15,177 @@ namespace sb {
 
 constexpr int NB = 64;
 
-// Factor the diagonal block [j0, j0+nb)^2 of every matrix in LDS.
+// The 64 x 64 blocks below are held as a 16 x 16 grid of 4 x 4 register
+// tiles, thread t owning tile (t / 16, t % 16), and processed four columns
+// (one tile column) at a time.  Every element receives the subtractions of
+// the columns before it one at a time in column order and is scaled by the
+// reciprocal of its pivot last (one division per pivot instead of one per
+// element: the serial pivot chain is the kernels' critical path).
+
+// Factor the diagonal block [j0, j0+nb)^2 of every matrix.  Step s: the
+// owner of diagonal tile s factors it (left-looking within the tile), the
+// tiles below it solve against it, and the trailing tiles take the rank-4
+// update.  Rows and columns past nb are padded with the identity.
 __global__ __launch_bounds__(256) void chol_diag_kernel(int n, int j0, double *L,
                                                         int32_t *info) {
   const int c = blockIdx.x;
   if (info[c] != 0) return;
   double *A = L + (size_t)c * n * n;
   const int nb = min(NB, n - j0);
-  const int tid = threadIdx.x;
-  __shared__ double T[NB][NB + 1];
+  const int tid = threadIdx.x, ti = tid >> 4, tk = tid & 15;
+  const bool low = ti >= tk;
+  __shared__ double Dg[2][4][4];   // factor of the step's diagonal tile
+  __shared__ double Dr[2][4];      // reciprocals of its diagonal
+  __shared__ double Pn[2][NB][4];  // the step's solved tile column
   __shared__ int fail;
-  for (int e = tid; e < nb * nb; e += 256) {
-    int i = e / nb, k = e % nb;
-    T[i][k] = (k <= i) ? A[(size_t)(j0 + i) * n + j0 + k] : 0.0;
-  }
+  double a[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 4 * ti + u, k = 4 * tk + v;
+      a[u][v] = (i < nb && k < nb) ? (k <= i ? A[(size_t)(j0 + i) * n + j0 + k] : 0.0)
+                                   : (i == k ? 1.0 : 0.0);
+    }
   if (tid == 0) fail = 0;
   __syncthreads();
-  for (int col = 0; col < nb; ++col) {
-    if (tid == 0) {
-      double p = T[col][col];
-      if (!(p > 0.0))
-        fail = col + 1;
-      else
-        T[col][col] = sqrt(p);
+  for (int s = 0; s < NB / 4; ++s) {
+    const int b = s & 1;
+    if (ti == s && tk == s) {
+      int f = 0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double p = a[v][v];
+#pragma unroll
+        for (int w = 0; w < v; ++w) p -= a[v][w] * a[v][w];
+        if (!(p > 0.0) && f == 0) f = 4 * s + v + 1;
+        const double d = sqrt(p), r = 1.0 / d;
+        a[v][v] = d;
+        Dr[b][v] = r;
+#pragma unroll
+        for (int u = v + 1; u < 4; ++u) {
+          double t = a[u][v];
+#pragma unroll
+          for (int w = 0; w < v; ++w) t -= a[u][w] * a[v][w];
+          a[u][v] = t * r;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Dg[b][u][v] = (v <= u) ? a[u][v] : 0.0;
+      if (f) fail = f;
     }
     __syncthreads();
     if (fail) break;
-    const double ljj = T[col][col];
-    for (int i = col + 1 + tid; i < nb; i += 256) T[i][col] /= ljj;
-    __syncthreads();
-    const int rem = nb - col - 1;
-    for (int e = tid; e < rem * rem; e += 256) {
-      int i = col + 1 + e / rem, k = col + 1 + e % rem;
-      if (k <= i) T[i][k] -= T[i][col] * T[k][col];
+    if (tk == s && ti > s) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double t = a[u][v];
+#pragma unroll
+          for (int w = 0; w < v; ++w) t -= a[u][w] * Dg[b][v][w];
+          a[u][v] = t * Dr[b][v];
+          Pn[b][4 * ti + u][v] = a[u][v];
+        }
     }
     __syncthreads();
+    // Pn[b] and Dg[b] are next written at step s + 2, after every thread
+    // has passed the first barrier of step s + 1
+    if (low && tk > s) {
+      double pi[4][4], pk[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          pi[u][w] = Pn[b][4 * ti + u][w];
+          pk[u][w] = Pn[b][4 * tk + u][w];
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int w = 0; w < 4; ++w) a[u][v] -= pi[u][w] * pk[v][w];
+    }
   }
   if (fail) {
     if (tid == 0) info[c] = j0 + fail;
     return;
   }
-  for (int e = tid; e < nb * nb; e += 256) {
-    int i = e / nb, k = e % nb;
-    A[(size_t)(j0 + i) * n + j0 + k] = (k <= i) ? T[i][k] : 0.0;
-  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 4 * ti + u, k = 4 * tk + v;
+      if (i < nb && k < nb) A[(size_t)(j0 + i) * n + j0 + k] = (k <= i) ? a[u][v] : 0.0;
+    }
 }
 
-// Rows i >= j0+nb: L[i][j0:j0+nb] = A[i][j0:j0+nb] L_jj^{-T}; one thread per row.
-__global__ __launch_bounds__(64) void chol_trsm_kernel(int n, int j0, double *L,
-                                                       const int32_t *info) {
+// Rows i >= j0+nb: L[i][j0:j0+nb] = A[i][j0:j0+nb] L_jj^{-T}, 64 rows per
+// workgroup.  Step s: the threads of tile column s finish their tiles by
+// substitution against diagonal tile s, then the tiles to the right
+// subtract their products with L_jj's tile row.
+__global__ __launch_bounds__(256) void chol_trsm_kernel(int n, int j0, double *L,
+                                                        const int32_t *info) {
   const int c = blockIdx.y;
   if (info[c] != 0) return;
   double *A = L + (size_t)c * n * n;
   const int nb = min(NB, n - j0);
-  const int r0 = j0 + nb;
-  __shared__ double D[NB][NB + 1];
-  for (int e = threadIdx.x; e < nb * nb; e += 64) {
-    int i = e / nb, k = e % nb;
-    D[i][k] = A[(size_t)(j0 + i) * n + j0 + k];
+  const int rb = j0 + nb + blockIdx.x * 64;
+  const int tid = threadIdx.x, ti = tid >> 4, tk = tid & 15;
+  __shared__ double D[NB][NB + 1];  // L_jj, identity-padded past nb
+  __shared__ double Rd[NB];         // reciprocals of its diagonal
+  __shared__ double Xc[2][64][4];   // the step's solved tile column
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e / NB, k = e % NB;
+    D[i][k] = (i < nb && k < nb) ? (k <= i ? A[(size_t)(j0 + i) * n + j0 + k] : 0.0)
+                                 : (i == k ? 1.0 : 0.0);
   }
+  if (tid < NB) Rd[tid] = tid < nb ? 1.0 / A[(size_t)(j0 + tid) * n + j0 + tid] : 1.0;
+  double a[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = rb + 4 * ti + u, k = 4 * tk + v;
+      a[u][v] = (i < n && k < nb) ? A[(size_t)i * n + j0 + k] : 0.0;
+    }
   __syncthreads();
-  const int i = r0 + blockIdx.x * 64 + threadIdx.x;
-  if (i >= n) return;
-  double *row = A + (size_t)i * n + j0;
-  double x[NB];
+  for (int s = 0; s < NB / 4; ++s) {
+    const int b = s & 1;
+    if (tk == s) {
 #pragma unroll
-  for (int cc = 0; cc < NB; ++cc) x[cc] = (cc < nb) ? row[cc] : 0.0;
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-  for (int cc = 0; cc < NB; ++cc) {
-    if (cc < nb) {
-      double s = x[cc];
+        for (int v = 0; v < 4; ++v) {
+          double t = a[u][v];
 #pragma unroll
-      for (int t = 0; t < cc; ++t) s -= x[t] * D[cc][t];
-      x[cc] = s / D[cc][cc];
+          for (int w = 0; w < v; ++w) t -= a[u][w] * D[4 * s + v][4 * s + w];
+          a[u][v] = t * Rd[4 * s + v];
+          Xc[b][4 * ti + u][v] = a[u][v];
+        }
+    }
+    __syncthreads();
+    // Xc[b] is next written at step s + 2, after this step's readers have
+    // passed the barrier of step s + 1
+    if (tk > s) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int w = 0; w < 4; ++w) a[u][v] -= Xc[b][4 * ti + u][w] * D[4 * tk + v][4 * s + w];
     }
   }
 #pragma unroll
-  for (int cc = 0; cc < NB; ++cc)
-    if (cc < nb) row[cc] = x[cc];
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = rb + 4 * ti + u, k = 4 * tk + v;
+      if (i < n && k < nb) A[(size_t)i * n + j0 + k] = a[u][v];
+    }
 }
 
 // Trailing update A[i][k] -= sum_c L[i][j0+c] L[k][j0+c] for r0 <= k <= i < n,
@@ -169,7 +262,7 @@ int chol_batched(int C, int n, const double *A, double *L, int32_t *info, hipStr
     SB_LAUNCH_CHECK();
     const int rest = n - j0 - nb;
     if (rest <= 0) break;
-    hipLaunchKernelGGL(chol_trsm_kernel, dim3((unsigned)ceil_div(rest, 64), C), dim3(64), 0, s, n,
+    hipLaunchKernelGGL(chol_trsm_kernel, dim3((unsigned)ceil_div(rest, 64), C), dim3(256), 0, s, n,
                        j0, L, info);
     SB_LAUNCH_CHECK();
     const int T = (int)ceil_div(rest, 64);
@@ -200,13 +293,23 @@ int launch_logdet(int C, int n, const double *L, const int32_t *info, double *lo
 }
 
 // Solve L L^T x = b: blocked forward (row dots over solved blocks, then the
-// 64x64 diagonal block in one wave) and backward substitution.  One workgroup
-// per matrix; x lives in LDS.
-__global__ __launch_bounds__(256) void chol_solve_kernel(int n, const double *Lall,
-                                                         const double *ball, double *xall,
-                                                         const int32_t *info) {
+// 64x64 diagonal block in one wave) and backward substitution.  One
+// workgroup of 16 waves per matrix, x in LDS; the dots against the solved
+// part are split over all waves with several independent loads per lane in
+// flight (the solve is bound by the latency of reading L).
+constexpr int SV_T = 1024, SV_W = SV_T / 64;
+// Lane l's value to every lane (l uniform): two scalar reads, no LDS trip.
+__device__ inline double lane_bcast(double v, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__global__ __launch_bounds__(SV_T) void chol_solve_kernel(int n, const double *Lall,
+                                                          const double *ball, double *xall,
+                                                          const int32_t *info) {
   extern __shared__ double xs[];  // [n]
-  __shared__ double part[4][64];
+  __shared__ double part[SV_W][64];
   __shared__ double Tb[64][65];   // current diagonal block
   const int c = blockIdx.x;
   const double *L = Lall + (size_t)c * n * n;
@@ -214,31 +317,40 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(int n, const double *La
   double *x = xall + (size_t)c * n;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (info && info[c] != 0) {
-    for (int i = tid; i < n; i += 256) x[i] = NAN;
+    for (int i = tid; i < n; i += SV_T) x[i] = NAN;
     return;
   }
-  for (int i = tid; i < n; i += 256) xs[i] = b[i];
+  for (int i = tid; i < n; i += SV_T) xs[i] = b[i];
   __syncthreads();
   // forward: L z = b
   for (int i0 = 0; i0 < n; i0 += 64) {
     const int nb = min(64, n - i0);
-    // rows i0..i0+nb: subtract sum_{k < i0} L[i][k] z_k; each wave takes 16 rows
-    for (int rr = 0; rr < 16; ++rr) {
-      const int r = w * 16 + rr;
-      double sacc = 0.0;
-      if (r < nb)
-#pragma unroll 8
-        for (int k = lane; k < i0; k += 64) sacc += L[(size_t)(i0 + r) * n + k] * xs[k];
-      sacc = wave_sum(sacc);
-      if (lane == 0) part[0][r] = sacc;
-    }
-    for (int r = w; r < nb; r += 4)  // diagonal block into LDS, row by row
+    for (int r = w; r < nb; r += SV_W)  // diagonal block into LDS, row by row
       if (lane < nb) Tb[r][lane] = L[(size_t)(i0 + r) * n + i0 + lane];
+    // rows i0 + w + 16 q (q < 4) less sum_{k < i0} L[i][k] z_k; lanes split k
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k = lane; k < i0; k += 64) {
+      const double zk = xs[k];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = w + SV_W * q;
+        if (r < nb) acc[q] += L[(size_t)(i0 + r) * n + k] * zk;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double t = wave_sum(acc[q]);
+      if (lane == 0) part[0][w + SV_W * q] = t;
+    }
     __syncthreads();
     if (w == 0) {
+      // lane cc holds the reciprocal of pivot cc; one division per lane
+      const double rp = (lane < nb) ? 1.0 / Tb[lane][lane] : 1.0;
       double val = (lane < nb) ? xs[i0 + lane] - part[0][lane] : 0.0;
-      for (int cc = 0; cc < nb; ++cc) {
-        double xc = __shfl(val / Tb[cc][cc], cc, 64);
+#pragma unroll 8
+      for (int cc = 0; cc < nb; ++cc) {  // (unrolled: the Tb reads leave the chain)
+        const double xc = lane_bcast(val * rp, cc);
         if (lane == cc) val = xc;
         if (lane > cc && lane < nb) val -= Tb[lane][cc] * xc;
       }
@@ -250,20 +362,24 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(int n, const double *La
   for (int iend = n; iend > 0; iend -= 64) {
     const int i0 = max(0, iend - 64);
     const int nb = iend - i0;
+    for (int r = w; r < nb; r += SV_W)
+      if (lane < nb) Tb[r][lane] = L[(size_t)(i0 + r) * n + i0 + lane];
     // s_i = sum_{k >= iend} L[k][i] x_k for i in block; lanes index i, waves split k
     double sacc = 0.0;
     if (lane < nb)
-#pragma unroll 8
-      for (int k = iend + w; k < n; k += 4) sacc += L[(size_t)k * n + i0 + lane] * xs[k];
+#pragma unroll 4
+      for (int k = iend + w; k < n; k += SV_W) sacc += L[(size_t)k * n + i0 + lane] * xs[k];
     part[w][lane] = sacc;
-    for (int r = w; r < nb; r += 4)
-      if (lane < nb) Tb[r][lane] = L[(size_t)(i0 + r) * n + i0 + lane];
     __syncthreads();
     if (w == 0) {
-      double sv = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+      double sv = part[0][lane];
+#pragma unroll
+      for (int u = 1; u < SV_W; ++u) sv += part[u][lane];
       double val = (lane < nb) ? xs[i0 + lane] - sv : 0.0;
+      const double rp = (lane < nb) ? 1.0 / Tb[lane][lane] : 1.0;
+#pragma unroll 8
       for (int cc = nb - 1; cc >= 0; --cc) {
-        double xc = __shfl(val / Tb[cc][cc], cc, 64);
+        const double xc = lane_bcast(val * rp, cc);
         if (lane == cc) val = xc;
         if (lane < cc) val -= Tb[cc][lane] * xc;
       }
@@ -271,7 +387,7 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(int n, const double *La
     }
     __syncthreads();
   }
-  for (int i = tid; i < n; i += 256) x[i] = xs[i];
+  for (int i = tid; i < n; i += SV_T) x[i] = xs[i];
 }
 
 int launch_chol_solve(int C, int n, const double *L, const double *b, double *x,
@@ -282,7 +398,7 @@ int launch_chol_solve(int C, int n, const double *L, const double *b, double *x,
     set_error("solve dimension %d too large", n);
     return SB_E_UNSUPPORTED;
   }
-  hipLaunchKernelGGL(chol_solve_kernel, dim3(C), dim3(256), shm, s, n, L, b, x, info);
+  hipLaunchKernelGGL(chol_solve_kernel, dim3(C), dim3(SV_T), shm, s, n, L, b, x, info);
   SB_LAUNCH_CHECK();
   return SB_OK;
 }

@@ -180,7 +180,7 @@ def test_hessian_equals_hvp_columns(L):
 
 # ---------------------------------------------------------- Cholesky / A9
 
-@pytest.mark.parametrize("n", [1, 5, 64, 65, 200])
+@pytest.mark.parametrize("n", [1, 5, 64, 65, 200, 1024])
 def test_cholesky_logdet(L, n):
     A = synth.random_spd(n, 100 + n, cond=1e3, batch=3)
     Lf, ld, info = L.sb_cholesky_logdet_dev(dev(A))
