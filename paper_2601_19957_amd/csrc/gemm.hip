@@ -644,7 +644,18 @@ __global__ __launch_bounds__(256) void finish_kernel(Model m, FinishArgs f) {
     }
     if (gout) {
       const T sc = (T)(nd / (m.nu + q));
-      for (int n = lane; n < d; n += 64) gout[n] = -sc * Y[n];
+      constexpr int V = 16 / sizeof(T);
+      typedef T vt __attribute__((ext_vector_type(V)));
+      if (d % V == 0 && ((uintptr_t)Y % 16) == 0 && ((uintptr_t)gout % 16) == 0) {
+        for (int n = lane * V; n < d; n += 64 * V) {
+          vt y = *(const vt *)&Y[n];
+#pragma unroll
+          for (int e = 0; e < V; ++e) y[e] = -sc * y[e];
+          *(vt *)&gout[n] = y;
+        }
+      } else {
+        for (int n = lane; n < d; n += 64) gout[n] = -sc * Y[n];
+      }
     }
     return;
   }
@@ -685,13 +696,35 @@ __global__ __launch_bounds__(256) void finish_kernel(Model m, FinishArgs f) {
   }
   if (gout) {
     // components whose responsibility rounds to zero in T add nothing: their
-    // Y rows are not read (separated mixtures touch one row of K)
-    for (int n = lane; n < d; n += 64) {
-      T s = 0;
+    // Y rows are not read (separated mixtures touch one row of K).  16-byte
+    // accesses where the rows allow them (same sums, element by element).
+    constexpr int V = 16 / sizeof(T);
+    typedef T vt __attribute__((ext_vector_type(V)));
+    const bool vec = d % V == 0 && ((uintptr_t)Y % 16) == 0 && ((uintptr_t)gout % 16) == 0;
+    if (vec) {
+      for (int n = lane * V; n < d; n += 64 * V) {
+        vt s;
 #pragma unroll
-      for (int k = 0; k < kMaxK; ++k)
-        if (k < K && r[k] != (T)0) s += r[k] * Y[(size_t)k * d + n];
-      gout[n] = -s;
+        for (int e = 0; e < V; ++e) s[e] = 0;
+#pragma unroll
+        for (int k = 0; k < kMaxK; ++k)
+          if (k < K && r[k] != (T)0) {
+            const vt y = *(const vt *)&Y[(size_t)k * d + n];
+#pragma unroll
+            for (int e = 0; e < V; ++e) s[e] += r[k] * y[e];
+          }
+#pragma unroll
+        for (int e = 0; e < V; ++e) s[e] = -s[e];
+        *(vt *)&gout[n] = s;
+      }
+    } else {
+      for (int n = lane; n < d; n += 64) {
+        T s = 0;
+#pragma unroll
+        for (int k = 0; k < kMaxK; ++k)
+          if (k < K && r[k] != (T)0) s += r[k] * Y[(size_t)k * d + n];
+        gout[n] = -s;
+      }
     }
   }
 }
@@ -1117,13 +1150,35 @@ __global__ __launch_bounds__(256) void finish_group_kernel(BatchDev b, FinishGro
   }
   if (gout) {
     // components whose responsibility rounds to zero in T add nothing: their
-    // Y rows are not read (separated mixtures touch one row of K)
-    for (int n = lane; n < d; n += 64) {
-      T s = 0;
+    // Y rows are not read (separated mixtures touch one row of K).  16-byte
+    // accesses where the rows allow them (same sums, element by element).
+    constexpr int V = 16 / sizeof(T);
+    typedef T vt __attribute__((ext_vector_type(V)));
+    const bool vec = d % V == 0 && ((uintptr_t)Y % 16) == 0 && ((uintptr_t)gout % 16) == 0;
+    if (vec) {
+      for (int n = lane * V; n < d; n += 64 * V) {
+        vt s;
 #pragma unroll
-      for (int k = 0; k < kMaxK; ++k)
-        if (k < K && r[k] != (T)0) s += r[k] * Y[(size_t)k * d + n];
-      gout[n] = -s;
+        for (int e = 0; e < V; ++e) s[e] = 0;
+#pragma unroll
+        for (int k = 0; k < kMaxK; ++k)
+          if (k < K && r[k] != (T)0) {
+            const vt y = *(const vt *)&Y[(size_t)k * d + n];
+#pragma unroll
+            for (int e = 0; e < V; ++e) s[e] += r[k] * y[e];
+          }
+#pragma unroll
+        for (int e = 0; e < V; ++e) s[e] = -s[e];
+        *(vt *)&gout[n] = s;
+      }
+    } else {
+      for (int n = lane; n < d; n += 64) {
+        T s = 0;
+#pragma unroll
+        for (int k = 0; k < kMaxK; ++k)
+          if (k < K && r[k] != (T)0) s += r[k] * Y[(size_t)k * d + n];
+        gout[n] = -s;
+      }
     }
   }
 }

@@ -171,15 +171,26 @@ template <typename T, int TPB, int EPT>
 __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t s,
                                                BlockRed<TPB, T> &red) {
   const int tid = threadIdx.x;
-  if (a.status[s] != ST_ACTIVE) {
+  const int64_t B = a.B;
+  // every per-start scalar is read before the first decision, so the reads
+  // share one memory round trip (all are in bounds for any start)
+  const int status = a.status[s];
+  int cur = a.cur[s];
+  const int phase = a.phase[s];
+  int cnt = a.cnt[s], head = a.head[s], it = a.iters[s];
+  const double f0 = a.F[s], f1 = a.F[(size_t)B + s];
+  const T alpha_s = a.alpha[s], gtp_s = a.gtp[s];
+  const int ls_s = a.ls[s];
+  const int dv = a.vdim ? a.vdim[s] : a.d;
+  const int64_t vov = a.voff ? a.voff[s] : (int64_t)s * a.d;
+  if (status != ST_ACTIVE) {
     if (tid == 0) a.active[s] = 0;
     return;
   }
   const int m = a.m;
-  const int d = a.vdim ? a.vdim[s] : a.d;
-  const int64_t vo = a.voff ? a.voff[s] : (int64_t)s * a.d;
+  const int d = dv;
+  const int64_t vo = vov;
   const int64_t Lt = a.Ltot;
-  const int64_t B = a.B;
   const int i0 = tid * EPT;  // this thread's chunk of every vector
   const bool vec = (d % EPT == 0) && (vo % EPT == 0) && (Lt % EPT == 0);
   T tol = a.tol;
@@ -189,10 +200,7 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
     tol = (T)a.ptol[p];
     max_iter = a.pmaxit[p];
   }
-  int cur = a.cur[s];
-  const int phase = a.phase[s];
-  int cnt = a.cnt[s], head = a.head[s], it = a.iters[s];
-  const double lcur = a.F[(size_t)cur * B + s];
+  const double lcur = cur ? f1 : f0;
 
   // ---- decide what this step does from the scalars alone
   enum { M_INIT, M_ACCEPT, M_BACKTRACK, M_RESET, M_STALL };
@@ -200,15 +208,14 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
   T alpha = 1;
   int lsn = 0;
   if (phase == PH_TRIAL) {
-    const int tr = 1 - cur;
-    const double lt = a.F[(size_t)tr * B + s];
-    alpha = a.alpha[s];
-    const double gtp_old = (double)a.gtp[s];
+    const double lt = cur ? f0 : f1;
+    alpha = alpha_s;
+    const double gtp_old = (double)gtp_s;
     const double fc = -lcur, ft = -lt;
     if (isfinite(ft) && ft <= fc + 1e-4 * (double)alpha * gtp_old) {
       mode = M_ACCEPT;
     } else {
-      lsn = a.ls[s] + 1;
+      lsn = ls_s + 1;
       alpha *= (T)0.5;
       if (lsn <= 40)
         mode = M_BACKTRACK;
