@@ -99,6 +99,54 @@ def recorded_traffic(summary="profiles/quad_gemm_split_B16384_d1024_K8.md",
     return float(m_t.group(1))
 
 
+def recorded_lbfgs(summary="profiles/lbfgs_step_B16384_d1024_m8.md",
+                   source="paper_2601_19957_amd/csrc/lbfgs.hip"):
+    """HBM roofline of the L-BFGS step at full batch (16384 starts, d = 1024, m = 8) from the
+    committed rocprofv3 trace and counter summary, or None when the kernel source changed."""
+    import hashlib
+    import re
+
+    try:
+        txt = open(os.path.join(ROOT, summary)).read()
+        sha = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m_h = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
+    if not m_h or m_h.group(1) != sha:
+        return None
+    val = {}
+    for key in ("lbfgs_full_batch_avg_us", "lbfgs_traffic_bytes_per_launch",
+                "lbfgs_algorithmic_bytes_per_launch", "copy_tbps"):
+        m_v = re.search(key + r":\s*([0-9.eE+]+)", txt)
+        if not m_v:
+            return None
+        val[key] = float(m_v.group(1))
+    achieved = val["lbfgs_traffic_bytes_per_launch"] / val["lbfgs_full_batch_avg_us"] / 1e3
+    return dict(bound="hbm", achieved=achieved, peak=PEAK["hbm"], unit="GB/s",
+                frac=achieved / PEAK["hbm"], traffic=val["lbfgs_traffic_bytes_per_launch"],
+                algorithmic_bytes=val["lbfgs_algorithmic_bytes_per_launch"],
+                avg_launch_us=val["lbfgs_full_batch_avg_us"],
+                copy_GBps=val["copy_tbps"] * 1e3, source=summary)
+
+
+def calibration_copy() -> int:
+    """A plain device copy of known size (1 GiB read + 1 GiB written) that calibrates the HBM
+    byte counters of a profiled run; a 1 GiB fill in between evicts the source from the 256 MB
+    last-level cache.  Returns the bytes moved each way."""
+    import torch
+
+    n_copy = 256 << 20  # floats
+    src = torch.ones(n_copy, dtype=torch.float32, device="cuda")
+    flush = torch.full((n_copy,), 2.0, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del flush, src, dst
+    torch.cuda.empty_cache()
+    return 4 * n_copy
+
+
 def cpu_baseline(prob, cfg, budget_s=20.0):
     """The oracle, as it stands, on a bounded sample: a few starts of the same workload."""
     import oracle
@@ -172,6 +220,8 @@ def main() -> int:
                     help="also time the uneven batch as one call per problem")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the roofline kernel timing (for profiling that kernel)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with the 1 GiB device copy that calibrates HBM byte counters")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -216,18 +266,8 @@ def main() -> int:
                     fp32_equivalent_frac=achieved / PEAK["fp32"],
                     fp32_kernel_us=kt32_s * 1e6)
     if args.kernel_only:
-        # a plain copy of known size, to calibrate HBM byte counters of the same run;
-        # a 1 GiB fill in between evicts the source from the 256 MB last-level cache
-        n_copy = 256 << 20  # floats: 1 GiB read + 1 GiB written
-        src = torch.ones(n_copy, dtype=torch.float32, device="cuda")
-        flush = torch.full((n_copy,), 2.0, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del flush
         print(json.dumps(dict(kernel_only=True, roofline=roofline,
-                              copy_calibration_bytes=4 * n_copy)), flush=True)
+                              copy_calibration_bytes=calibration_copy())), flush=True)
         return 0
 
     # ---- whole path, inputs resident in HBM
@@ -331,8 +371,11 @@ def main() -> int:
         "max_mode_dist_vs_oracle": dmodes,
         "uneven_batch": batch,
         "roofline": roofline,
+        "lbfgs_step_roofline": recorded_lbfgs(),
         "cpu_baseline": cpu,
     }
+    if args.calibrate_copy:
+        calibration_copy()
     print(json.dumps(out), flush=True)
     return 0
 
