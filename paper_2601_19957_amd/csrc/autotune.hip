@@ -85,8 +85,10 @@ bool time_launches(int dtype, const Model &m, const ASrc &a, QuadOut o, int64_t 
     t.bn = bf ? cands_bf[c][1] : cands[c][1];
     t.bk = bf ? cands_bf[c][2] : 32;
     t.stages = bf ? cands_bf[c][3] : 1;
-    // ray points run only the 32-wide single-stage k-tiles and no 256 x 128
-    if (bf && a.kind == 1 && (t.bk != 32 || t.stages != 1 || (t.bm == 256 && t.bn == 128)))
+    // ray points run only the 32-wide k-tiles, no 256 x 128, and two stages only for
+    // the BF16 operand
+    if (bf && a.kind == 1 &&
+        (t.bk != 32 || (t.stages != 1 && dtype != DT_BF16) || (t.bm == 256 && t.bn == 128)))
       continue;
     ok = launch_quad_gemm(dtype, m, a, M, nullptr, o, t, s) == SB_OK;  // warm-up
     ok = ok && hipEventRecord(e0, s) == hipSuccess;

@@ -156,12 +156,18 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
   const char *Xa = (const char *)(KIND == 0 ? g.a.X : g.a.P0);
   const char *Xb = (const char *)g.a.P1;
   const int ca = tid % VA, cb = tid % VB;
+  // This thread's A rows within the tile: rows of X are spread over the
+  // workgroup (one row per VA threads and load); ray points take NA
+  // consecutive rows, so when NA divides the points per ray they lie on one
+  // ray and share one load of each endpoint chunk.
+  auto arow = [&](int r) { return KIND == 1 ? (tid / VA) * NA + r : (tid + NT * r) / VA; };
+  const bool one_ray = KIND == 1 && g.a.n_pts % NA == 0;
   uint32_t aoff[NA];  // byte offsets of this thread's A rows (rows >= M read row m0)
   float tpar[NA];
   bool aok[NA];
 #pragma unroll
   for (int r = 0; r < NA; ++r) {
-    const int64_t row = m0 + (tid + NT * r) / VA;
+    const int64_t row = m0 + arow(r);
     aok[r] = row < M;
     uint32_t off;
     row_off(aok[r] ? row : m0, off, tpar[r]);
@@ -185,10 +191,19 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
   auto load = [&](int k0) {
     const uint32_t ka = 4u * (uint32_t)k0, kb = 2u * (uint32_t)k0;
     if (k0 + BK <= d) {
+      if (one_ray) {
+        const f4v p0 = *(const f4v *)(Xa + (aoff[0] + ka)), p1 = *(const f4v *)(Xb + (aoff[0] + ka));
 #pragma unroll
-      for (int r = 0; r < NA; ++r) {
-        ra[r] = *(const f4v *)(Xa + (aoff[r] + ka));
-        if constexpr (KIND == 1) rq[r] = *(const f4v *)(Xb + (aoff[r] + ka));
+        for (int r = 0; r < NA; ++r) {
+          ra[r] = p0;
+          rq[r] = p1;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < NA; ++r) {
+          ra[r] = *(const f4v *)(Xa + (aoff[r] + ka));
+          if constexpr (KIND == 1) rq[r] = *(const f4v *)(Xb + (aoff[r] + ka));
+        }
       }
       rmu = *(const f4v *)((const char *)mu + (muoff + ka));
 #pragma unroll
@@ -217,7 +232,7 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
     const int sa = st * BM * BK, sbo = st * BN * BK;
 #pragma unroll
     for (int r = 0; r < NA; ++r) {
-      const int i = (tid + NT * r) / VA;
+      const int i = arow(r);
       float v[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -472,8 +487,15 @@ int launch_quad_gemm_bf16(int nprod, const Model &m, const ASrc &a, int64_t M,
 #define SB_BFP(NP, BMv, BNv, WGNv) \
   hipLaunchKernelGGL((quad_gemm_bf16_kernel<NP, 0, BMv, BNv, 32, 2, WGNv, 2>), grid, \
                      dim3(128 * WGNv), 0, s, p)
-  const bool pp = t.stages == 2 && a.kind == 0 && BK == 32 && BM == BN;
-  if (pp && BM == 256) {
+#define SB_BFP1(BMv, BNv, WGNv) \
+  hipLaunchKernelGGL((quad_gemm_bf16_kernel<1, 1, BMv, BNv, 32, 2, WGNv, 2>), grid, \
+                     dim3(128 * WGNv), 0, s, p)
+  // two LDS stages: square 32-wide tiles; for ray points the BF16 operand only
+  const bool pp = t.stages == 2 && BK == 32 && BM == BN && (a.kind == 0 || nprod == 1);
+  if (pp && a.kind == 1) {
+    if (BM == 256) SB_BFP1(256, 256, 4);
+    else SB_BFP1(128, 128, 2);
+  } else if (pp && BM == 256) {
     if (nprod == 3) SB_BFP(3, 256, 256, 4);
     else SB_BFP(1, 256, 256, 4);
   } else if (pp) {
@@ -501,6 +523,7 @@ int launch_quad_gemm_bf16(int nprod, const Model &m, const ASrc &a, int64_t M,
     else if (BM == 256 && BN == 128) SB_BF(1, 0, 256, 128, 32);
     else SB_BF(1, 0, 128, 256, 32);
   }
+#undef SB_BFP1
 #undef SB_BFP
 #undef SB_BF8
 #undef SB_BF

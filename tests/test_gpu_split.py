@@ -137,14 +137,16 @@ def test_split_every_tile_variant(L, forced_tile, d, B):
     assert float(np.max(np.abs(g - g_ref) / bound)) <= 1.0
 
 
-@pytest.mark.parametrize("forced_tile", ["128x128x32", "128x256x32", "256x256x32"], indirect=True)
-def test_bf16_discovery_every_tile_variant(L, forced_tile):
+@pytest.mark.parametrize("forced_tile", ["128x128x32", "128x256x32", "256x256x32", "128x128x32x2",
+                                         "256x256x32x2"], indirect=True)
+@pytest.mark.parametrize("npts", [32, 6])  # 6: a thread's rows straddle rays
+def test_bf16_discovery_every_tile_variant(L, forced_tile, npts):
     """BF16 ray-point contraction per tile variant: the best BF16 sample of each ray lies
     within the BF16 error bound of the ray's FP64 maximum."""
     rng = np.random.Generator(np.random.PCG64(61))
     prob = synth.gaussian_mixture(rng, 96, 2, -8.0, 8.0, 0.05, 1.0, 12.0, box_half=12.0,
                                   norm=synth.NORM_DENSITY, linf_min=1.0)
-    R, npts = 96, 32
+    R = 96
     m = L.DeviceModel(prob, low_precision=True)
     out = L.sb_discover_dev(m, R, npts, 32, 7, dtype=L.DTYPE_BF16)
     ref = O.discover(prob, R, npts, 32, 7)
