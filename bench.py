@@ -99,6 +99,59 @@ def recorded_traffic(summary="profiles/quad_gemm_split_B16384_d1024_K8.md",
     return float(m_t.group(1))
 
 
+def a3_variants(L):
+    """logL+grad (A3: contraction, epilogue and hand-written backward) per config and precision
+    at the config's start count, HIP events on its stream: evals/s and the fraction of the
+    peak of the arithmetic the contraction runs on (algorithmic flops 2 B K d^2 + 4 B K d)."""
+    import torch
+    from paper_2601_19957_amd import synth
+
+    out = []
+    cases = [("c1", [L.DTYPE_F64]), ("c2", [L.DTYPE_F64]),
+             ("c4a", [L.DTYPE_F64, L.DTYPE_F32, L.DTYPE_F32_SPLIT]),
+             ("c4b", [L.DTYPE_F64, L.DTYPE_F32, L.DTYPE_F32_SPLIT])]
+    names = {L.DTYPE_F64: ("f64", "fp64"), L.DTYPE_F32: ("f32", "fp32"),
+             L.DTYPE_F32_SPLIT: ("f32 as split bf16", "bf16")}
+    for name, dts in cases:
+        prob, cfg = synth.make_workload(name)
+        B = cfg.n_starts
+        m = L.DeviceModel(prob, low_precision=True)
+        X64 = torch.as_tensor(synth.points_near_modes(prob, B, 11, scale=0.5), device="cuda")
+        flops = 2.0 * B * prob.K * prob.d ** 2 + 4.0 * B * prob.K * prob.d
+        for dt in dts:
+            X = X64 if dt == L.DTYPE_F64 else X64.float()
+            reps = 5 if prob.d * prob.K >= 4096 and dt == L.DTYPE_F64 else 10
+            L.sb_logl_grad_dev(m, X, dtype=dt)  # warm (code objects, tile cache)
+            st = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(st)
+            for _ in range(reps):
+                L.sb_logl_grad_dev(m, X, dtype=dt)
+            e1.record(st)
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) / reps / 1e3
+            lab, pk = names[dt]
+            out.append(dict(config=name, d=prob.d, K=prob.K, batch=B, dtype=lab,
+                            ms=sec * 1e3, evals_per_s=B / sec, tflops=flops / sec / 1e12,
+                            peak_tflops=PEAK[pk], frac=flops / sec / 1e12 / PEAK[pk]))
+            log(f"A3 {name} {lab}: {sec*1e3:.3f} ms, {B/sec:.3e} evals/s, "
+                f"{flops/sec/1e12:.1f} TFLOP/s")
+        del m, X64
+        torch.cuda.empty_cache()
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def recorded_lbfgs(summary="profiles/lbfgs_step_B16384_d1024_m8.md",
                    source="paper_2601_19957_amd/csrc/lbfgs.hip"):
     """HBM roofline of the L-BFGS step at full batch (16384 starts, d = 1024, m = 8) from the
@@ -161,11 +214,17 @@ def cpu_baseline(prob, cfg, budget_s=20.0):
         t0 = time.perf_counter()
         r = oracle.evidence(prob, cfg, n_threads=threads, n_starts=ns)
         dt = time.perf_counter() - t0
+    # single-threaded, a smaller sample of the same workload
+    ns1 = max(1, min(4, ns))
+    t1 = time.perf_counter()
+    r1 = oracle.evidence(prob, cfg, n_threads=1, n_starts=ns1)
+    dt1 = time.perf_counter() - t1
     return dict(value=r.n_grad_evals / dt, unit="logL+grad evals/s", cores=threads, kind="oracle",
                 sample=f"{prob.name}: whole path with {ns} starts "
                        f"({ns} rays x {cfg.n_points} points), {r.n_grad_evals} logL+grad evals "
                        f"in {dt:.2f} s, log Z {r.log_z:.6f}",
-                seconds=dt, log_z=r.log_z)
+                seconds=dt, log_z=r.log_z, cpu_model=cpu_model(),
+                single_thread=dict(value=r1.n_grad_evals / dt1, starts=ns1, seconds=dt1))
 
 
 def uneven_batch(L, serial=False):
@@ -216,6 +275,10 @@ def main() -> int:
                     help="skip the uneven-batch leg (512 problems, d in 8..512)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the uneven-batch leg (for profiling it)")
+    ap.add_argument("--no-host", action="store_true",
+                    help="skip the host-entry (sb_evidence) time-to-log Z")
+    ap.add_argument("--no-a3", action="store_true",
+                    help="skip the per-config logL+grad (A3) precision variants")
     ap.add_argument("--batch-serial", action="store_true",
                     help="also time the uneven batch as one call per problem")
     ap.add_argument("--kernel-only", action="store_true",
@@ -273,9 +336,13 @@ def main() -> int:
     # ---- whole path, inputs resident in HBM
     runners = {n: L.EvidenceRunner(p, c) for n, (p, c) in wl.items()}
     ref = {n: closed_form_logz(p) for n, (p, _) in wl.items()}
+    cold = {}
     for w in range(args.warmup):
         for n, r in runners.items():
+            tc = time.perf_counter()
             res = r.run()
+            if w == 0:
+                cold[n] = time.perf_counter() - tc
             log(f"warmup {w} {n}: status {res.status} log Z {res.log_z:.9f} "
                 f"(closed form {ref[n]:.9f}) modes {res.n_modes} iters {res.iterations} "
                 f"evals {res.n_grad_evals} t {res.seconds[7]*1e3:.1f} ms "
@@ -332,15 +399,33 @@ def main() -> int:
         log(f"{n}: |dlogZ| vs oracle {dlogz[n]:.3e} (closed form gap "
             f"{abs(refm.log_z - ref[n]):.3e}), modes {last[n].n_modes}/{refm.n_modes}")
 
+    # ---- time-to-log Z through the host entry point (upload of the problem and allocation
+    # of the device workspace included)
+    host = {}
+    if not args.no_host:
+        for n, (p, c) in wl.items():
+            ts = []
+            for _ in range(2):
+                t1 = time.perf_counter()
+                rh = L.sb_evidence(p, c)
+                ts.append(time.perf_counter() - t1)
+            host[n] = float(np.median(ts)) * 1e3
+            log(f"host entry {n}: {host[n]:.1f} ms, log Z {rh.log_z:.9f}")
+
     batch = None
     if not args.no_batch:
         batch = uneven_batch(L, serial=args.batch_serial)
+
+    a3 = None
+    if not args.no_a3:
+        a3 = a3_variants(L)
 
     cpu = None
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle) on a bounded sample")
         cb = cpu_baseline(prob_big, cfg_big)
-        cpu = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        cpu = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample", "cpu_model",
+                                  "single_thread")}
 
     ms_per_step = total / max(1, args.steps) * 1e3
     out = {
@@ -364,12 +449,20 @@ def main() -> int:
             "precision": "mixed",
         },
         "time_to_logz_ms": {n: float(np.median(per[n])) * 1e3 for n in names},
+        "time_to_logz_range_ms": {n: [min(per[n]) * 1e3, max(per[n]) * 1e3] for n in names},
+        "time_to_logz_cold_ms": {n: cold[n] * 1e3 for n in cold},
+        "time_to_logz_host_entry_ms": host or None,
+        "phases_ms": {n: dict(zip(("prep", "discovery", "bulk", "dedup_pre",
+                                   "polish_hessian_chol", "dedup_combine"),
+                                  [round(last[n].seconds[i] * 1e3, 2) for i in (0, 1, 2, 3, 4, 6)]))
+                      for n in last},
         "time_to_logz_fp64_ms": {n: t64[n] * 1e3 for n in t64},
         "speedup_vs_fp64": {n: t64[n] / float(np.median(per[n])) for n in t64},
         "dlogz_vs_oracle": dlogz,
         "dlogz_fp64_vs_oracle": {n: abs(res64[n].log_z - refz[n]) for n in res64},
         "max_mode_dist_vs_oracle": dmodes,
         "uneven_batch": batch,
+        "a3_variants": a3,
         "roofline": roofline,
         "lbfgs_step_roofline": recorded_lbfgs(),
         "cpu_baseline": cpu,
