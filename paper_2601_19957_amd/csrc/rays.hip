@@ -161,40 +161,44 @@ int launch_ray_argmax(int R, int n_pts, int dtype, const void *l, double *best_l
 }
 
 // Rank of each ray by (best l descending, index ascending), NaN as -inf; the
-// first n_starts ranks name the starts.
-__global__ __launch_bounds__(256) void topn_kernel(int R, int n_starts, const double *best_l,
-                                                   int32_t *start_ray) {
-  __shared__ double tile[256];
-  const int r = blockIdx.x * 256 + threadIdx.x;
+// first n_starts ranks name the starts.  A workgroup ranks 64 rays: lane l of
+// every wave holds ray 64 b + l, and wave w counts the rays of the w-th
+// sixteenth of the array that precede it (the compared key is the same for
+// the whole wave, a broadcast read); the 16 partial counts are added in LDS.
+constexpr int TOPN_PARTS = 16;
+__global__ __launch_bounds__(64 * TOPN_PARTS) void topn_kernel(int R, int n_starts,
+                                                               const double *best_l,
+                                                               int32_t *start_ray) {
+  __shared__ int part[TOPN_PARTS][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = blockIdx.x * 64 + lane;
   double key = -INFINITY;
   if (r < R) {
     key = best_l[r];
     if (key != key) key = -INFINITY;
   }
-  int rank = 0;
-  for (int t0 = 0; t0 < R; t0 += 256) {
-    __syncthreads();
-    int t = t0 + threadIdx.x;
-    double v = -INFINITY;
-    if (t < R) {
-      v = best_l[t];
-      if (v != v) v = -INFINITY;
-    }
-    tile[threadIdx.x] = v;
-    __syncthreads();
-    const int lim = min(256, R - t0);
-    for (int u = 0; u < lim; ++u) {
-      double w = tile[u];
-      rank += (w > key) || (w == key && t0 + u < r);
-    }
+  const int seg = (R + TOPN_PARTS - 1) / TOPN_PARTS;
+  const int t0 = w * seg, t1 = min(R, t0 + seg);
+  int cnt = 0;
+  for (int t = t0; t < t1; ++t) {
+    double v = best_l[t];
+    if (v != v) v = -INFINITY;
+    cnt += (v > key) || (v == key && t < r);
   }
-  if (r < R && rank < n_starts) start_ray[rank] = r;
+  part[w][lane] = cnt;
+  __syncthreads();
+  if (w == 0 && r < R) {
+    int rank = 0;
+#pragma unroll
+    for (int q = 0; q < TOPN_PARTS; ++q) rank += part[q][lane];
+    if (rank < n_starts) start_ray[rank] = r;
+  }
 }
 
 int launch_topn(int R, int n_starts, const double *best_l, int32_t *start_ray, hipStream_t s) {
   if (R <= 0) return SB_OK;
-  hipLaunchKernelGGL(topn_kernel, dim3((unsigned)ceil_div(R, 256)), dim3(256), 0, s, R, n_starts,
-                     best_l, start_ray);
+  hipLaunchKernelGGL(topn_kernel, dim3((unsigned)ceil_div(R, 64)), dim3(64 * TOPN_PARTS), 0, s, R,
+                     n_starts, best_l, start_ray);
   SB_LAUNCH_CHECK();
   return SB_OK;
 }

@@ -257,6 +257,23 @@ def test_discovery_fp64(L, name):
     assert e <= 1e-12, e
 
 
+def test_discovery_top_n_ties(L):
+    """A likelihood flat to FP64 precision (P = 1e-300 I): every ray's maximum is the same
+    value, so the top-n rule (l descending, ties to the lower ray index) keeps rays 0..n-1.
+    R is not a multiple of the ranking blocks."""
+    d, R, npts, ns = 4, 333, 8, 100
+    prob = synth.Problem(family=synth.FAMILY_GAUSS_MIX, norm=synth.NORM_DENSITY, d=d, K=1,
+                         log_w=np.zeros(1), mu=np.zeros((1, d)),
+                         prec=(1e-300 * np.eye(d))[None], nu=0.0, logl_offset=0.0,
+                         lo=-np.ones(d), hi=np.ones(d), sum_log_lambda=np.array([d * 690.8]))
+    ref = O.discover(prob, R, npts, ns, 5)
+    assert np.all(ref["ray_best_l"] == ref["ray_best_l"][0])
+    m = L.DeviceModel(prob)
+    out = L.sb_discover_dev(m, R, npts, ns, 5)
+    sr = out["start_ray"].cpu().numpy()
+    assert np.array_equal(sr, np.arange(ns)) and np.array_equal(ref["start_ray"], np.arange(ns))
+
+
 def test_discovery_bf16_ranks(L):
     """BF16 scores only rank the samples: the best BF16 sample of a ray must be
     within the BF16 error bound of the ray's true maximum (parity of values unpinned)."""
