@@ -25,7 +25,7 @@ namespace sb {
 
 namespace {
 std::mutex g_mu;
-std::map<std::tuple<int, int, int, int, int>, TileCfg> g_cache;
+std::map<std::tuple<int, int, int, int, int, int>, TileCfg> g_cache;
 
 int bucket(int64_t M) {
   int b = 0;
@@ -198,7 +198,9 @@ TileCfg autotune_tiles(int dtype, const Model &m, int64_t M, hipStream_t s, cons
   std::lock_guard<std::mutex> lk(g_mu);
   int dev = 0;
   (void)hipGetDevice(&dev);
-  auto key = std::make_tuple(dev, dtype, m.d, m.K, bucket(M));
+  // (the operand kind and the sum-of-squares mode select kernels of their own)
+  const int variant = probe ? probe->a.kind + 2 * (probe->o.sumsq ? 1 : 0) : 0;
+  auto key = std::make_tuple(dev, dtype, m.d, m.K, bucket(M), variant);
   auto it = g_cache.find(key);
   if (it != g_cache.end()) return it->second;
   TileCfg t = heuristic(m.d, M);

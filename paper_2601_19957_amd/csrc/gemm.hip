@@ -613,6 +613,38 @@ int launch_quad_gemm(int dtype, const Model &m, const ASrc &a, int64_t M, const 
 
 constexpr int kMaxK = 16;
 
+// Mixture row: q_k from its tile partials, a_k = beta_k - q_k/2, lse =
+// logsumexp_k a_k and the responsibilities r_k = exp(a_k - lse) in T (FP64
+// arithmetic).  Shared by the epilogue and the active-component lists, so
+// both see the same zero responsibilities.
+template <typename T>
+__device__ inline void mixture_resp(const Model &m, const T *qp, int ntn, double &lse,
+                                    T (&r)[kMaxK]) {
+  const int K = m.K;
+  double a[kMaxK];
+  double mx = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) {
+    if (k < K) {
+      double q = 0;
+      for (int t = 0; t < ntn; ++t) q += (double)qp[k * ntn + t];
+      a[k] = m.beta[k] - 0.5 * q;
+      mx = fmax(mx, a[k]);
+    }
+  }
+  if (K == 1) {
+    lse = a[0];
+  } else {
+    double ssum = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+      if (k < K) ssum += exp(a[k] - mx);
+    lse = mx + log(ssum);
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) r[k] = (k < K) ? (K == 1 ? (T)1 : (T)exp(a[k] - lse)) : (T)0;
+}
+
 // One wave per row: q_k from the tile partials, the family's l, and (if
 // requested) the gradient -sum_k r_k Y_k (mixture) or -((nu+d)/(nu+q)) Y.
 // The scalar part (q_k sums, beta_k - q_k/2, logsumexp, responsibilities)
@@ -659,36 +691,15 @@ __global__ __launch_bounds__(256) void finish_kernel(Model m, FinishArgs f) {
     }
     return;
   }
-  double a[kMaxK];
-  double mx = -INFINITY;
-#pragma unroll
-  for (int k = 0; k < kMaxK; ++k) {
-    if (k < K) {
-      double q = 0;
-      for (int t = 0; t < f.ntn; ++t) q += (double)qp[k * f.ntn + t];
-      a[k] = m.beta[k] - 0.5 * q;
-      mx = fmax(mx, a[k]);
-    }
-  }
   double lse;
-  if (K == 1) {
-    lse = a[0];
-  } else {
-    double ssum = 0;
-#pragma unroll
-    for (int k = 0; k < kMaxK; ++k)
-      if (k < K) ssum += exp(a[k] - mx);
-    lse = mx + log(ssum);
-  }
+  T r[kMaxK];
+  mixture_resp<T>(m, qp, f.ntn, lse, r);
   if (lane == 0) {
     if (f.logl_f64)
       ((double *)f.logl)[orow] = m.c + lse;
     else
       ((T *)f.logl)[orow] = (T)(m.c + lse);
   }
-  T r[kMaxK];
-#pragma unroll
-  for (int k = 0; k < kMaxK; ++k) r[k] = (k < K) ? (K == 1 ? (T)1 : (T)exp(a[k] - lse)) : (T)0;
   if (f.aux && lane < K) {
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k)
@@ -727,6 +738,46 @@ __global__ __launch_bounds__(256) void finish_kernel(Model m, FinishArgs f) {
       }
     }
   }
+}
+
+// Per component k, the rows whose responsibility r_k is not zero: row r
+// (GEMM row) is appended to rows[k] and its operand row (rowmap[r], or r) to
+// xrows[k]; cnt[k] (zeroed by the caller) counts them.  Order within a list
+// is arbitrary; every row's outputs are independent of it.
+__global__ void active_lists_kernel(Model m, int64_t M, const int32_t *count, const float *qpart,
+                                    int ntn, const int32_t *rowmap, int32_t *cnt, int32_t *rows,
+                                    int32_t *xrows, int64_t cap) {
+  const int64_t Mr = count ? (int64_t)(*count) : M;
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= Mr) return;
+  double lse;
+  float r[kMaxK];
+  mixture_resp<float>(m, qpart + (size_t)row * m.K * ntn, ntn, lse, r);
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k)
+    if (k < m.K && r[k] != 0.f) {
+      const int pos = atomicAdd(&cnt[k], 1);
+      rows[(int64_t)k * cap + pos] = (int32_t)row;
+      xrows[(int64_t)k * cap + pos] = rowmap ? rowmap[row] : (int32_t)row;
+    }
+}
+
+int launch_active_lists(const Model &m, int64_t M, const int32_t *count, const float *qpart,
+                        int ntn, const int32_t *rowmap, int32_t *cnt, int32_t *rows,
+                        int32_t *xrows, int64_t cap, hipStream_t s) {
+  if (m.K > kMaxK) {
+    set_error("K=%d exceeds the supported %d components", m.K, kMaxK);
+    return SB_E_UNSUPPORTED;
+  }
+  if (M > cap || M > 0x7fffffffll) {
+    set_error("active lists: %lld rows over the capacity %lld", (long long)M, (long long)cap);
+    return SB_E_INVAL;
+  }
+  if (M <= 0) return SB_OK;
+  hipLaunchKernelGGL(active_lists_kernel, dim3((unsigned)ceil_div(M, 256)), dim3(256), 0, s, m, M,
+                     count, qpart, ntn, rowmap, cnt, rows, xrows, cap);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
 }
 
 int launch_finish(int dtype, const Model &m, const FinishArgs &f, hipStream_t s) {

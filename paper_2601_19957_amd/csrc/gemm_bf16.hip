@@ -30,7 +30,17 @@ struct Bf16Params {
   const bf16_t *Phi, *Plo;  // [K][d][d]
   float *Y;                 // [M][ldy] (nullable)
   int64_t ldy;
-  float *qpart;             // [M][K][ntn]
+  float *qpart;             // [M][K][ntn] (nullable)
+  // Sum-of-squares mode: B holds U_k = L_k^T (upper triangular, P_k = L_k L_k^T),
+  // the k-loop starts at the column tile's first column (U's rows below it
+  // are zero there) and qpart gets sum_n Z_n^2 of Z = (X - mu_k) U_k^T; no Y.
+  int sumsq;
+  const int32_t *ymap;      // Y row of GEMM row r: ymap[r] (nullable: r)
+  int64_t ycol;             // column offset of the Y block
+  // Grouped by component (nullable): component k multiplies gcnt[k] rows,
+  // listed at a.rowmap + k * gcap (X rows) and ymap + k * gcap (Y rows)
+  const int32_t *gcnt;
+  int64_t gcap;
 };
 
 typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
@@ -115,18 +125,46 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
   // on one L2 and the XCD's column blocks of P stay resident in it.
   const int ncol = g.K * g.ntn;
   const int64_t w = blockIdx.x;
-  int col;
-  int64_t mt;
-  if (ncol % 8 == 0) {
-    const int per = ncol / 8;
-    const int64_t li = w / 8;
-    col = (int)(w % 8) + 8 * (int)(li % per);
-    mt = li / per;
+  int col = 0;
+  int64_t mt = 0, M;
+  const int32_t *rmap = g.a.rowmap, *ymp = g.ymap;
+  if (g.gcnt) {
+    // row tiles of the components one after another (ceil(gcnt[k] / BM) each)
+    const int64_t tt = w / g.ntn;
+    int kk = -1;
+    int64_t acc = 0;
+    for (int q = 0; q < g.K; ++q) {
+      const int64_t nq = ((int64_t)g.gcnt[q] + BM - 1) / BM;
+      if (kk < 0 && tt < acc + nq) {
+        kk = q;
+        mt = tt - acc;
+      }
+      acc += nq;
+    }
+    if (kk < 0) return;
+    col = kk * g.ntn + (int)(w % g.ntn);
+    M = g.gcnt[kk];
+    rmap += (int64_t)kk * g.gcap;
+    ymp += (int64_t)kk * g.gcap;
   } else {
-    col = (int)(w % ncol);
-    mt = w / ncol;
+    if (ncol % 8 == 0) {
+      const int per = ncol / 8;
+      const int64_t li = w / 8;
+      col = (int)(w % 8) + 8 * (int)(li % per);
+      mt = li / per;
+      if (g.sumsq) {
+        // the triangle makes column tile nt cost (d - nt BN): rotate each
+        // component's tiles by its first column's slot so every XCD gets a
+        // mix of long and short tiles (a bijection within each component)
+        const int kc = col / g.ntn;
+        col = kc * g.ntn + (col % g.ntn + (kc * g.ntn) / 8) % g.ntn;
+      }
+    } else {
+      col = (int)(w % ncol);
+      mt = w / ncol;
+    }
+    M = g.count ? (int64_t)(*g.count) : g.M;
   }
-  const int64_t M = g.count ? (int64_t)(*g.count) : g.M;
   const int64_t m0 = mt * BM;
   if (m0 >= M) return;
   const int d = g.d;
@@ -143,7 +181,7 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
   // operand arrays are below 4 GiB, so byte offsets fit in 32 bits.
   auto row_off = [&](int64_t row, uint32_t &off, float &t) {
     if constexpr (KIND == 0) {
-      const int64_t r = g.a.rowmap ? (int64_t)g.a.rowmap[row] : row;
+      const int64_t r = rmap ? (int64_t)rmap[row] : row;
       off = (uint32_t)(r * g.a.ldx);
       t = 0.f;
     } else {
@@ -317,9 +355,10 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
       }
     }
   };
-  load(0);
+  const int kbeg = g.sumsq ? (n0 / BK) * BK : 0;
+  load(kbeg);
   if constexpr (NS == 1) {
-    for (int k0 = 0; k0 < d; k0 += BK) {
+    for (int k0 = kbeg; k0 < d; k0 += BK) {
       store(0);
       __syncthreads();
       if (k0 + BK < d) load(k0 + BK);
@@ -333,7 +372,7 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
     __syncthreads();
     const int nk = (d + BK - 1) / BK;
     int st = 0;
-    for (int t = 0; t + 1 < nk; ++t) {
+    for (int t = kbeg / BK; t + 1 < nk; ++t) {
       load((t + 1) * BK);
       mma(st);
       store(st ^ 1);
@@ -343,13 +382,39 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
     mma(st);
   }
 
+  const int lr = lane >> 4, lc = lane & 15;
+  if (g.sumsq) {
+    // q partial = sum of the squares over this tile's columns below d: item
+    // v of lane l holds row 4 (l / 16) + v, column l % 16 of its 16 x 16 block
+    float qrow[TM][4];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float t = 0.f;
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          if (n0 + wn * WN + j * 16 + lc < d) t += acc[i][j][v] * acc[i][j][v];
+        t += __shfl_xor(t, 1, 64);
+        t += __shfl_xor(t, 2, 64);
+        t += __shfl_xor(t, 4, 64);
+        t += __shfl_xor(t, 8, 64);
+        qrow[i][v] = t;
+      }
+    if (lc == 0) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) qs[wn][wm * WM + i * 16 + 4 * lr + v] = qrow[i][v];
+    }
+  } else {
   // Epilogue.  Item v of lane l holds row 4 (l / 16) + v, column l % 16 of
   // its 16 x 16 block; each wave stages SR rows of its tile at a time in
   // LDS and writes them back as 16-byte row chunks (Y), with the partial
   // q over its columns from the same chunks of X and mu.  Passes are as
   // large as the LDS the occupancy leaves allows, so the X loads of a pass
-  // are issued together.
-  const int lr = lane >> 4, lc = lane & 15;
+  // are issued together.  Without qpart only Y is written.
+  const bool wq = g.qpart != nullptr;
   constexpr int CPR = WN / 4, RPI = 64 / CPR;  // float4 chunks per row, rows per instruction
   constexpr int NU = SR / RPI;                 // rows per lane and pass
   static_assert(CPR <= 64 && 64 % CPR == 0 && SR % RPI == 0, "epilogue layout");
@@ -379,7 +444,12 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
       const f4v y = *(const f4v *)&stg[(u * RPI + er) * SLD + 4 * ec];
       float q = 0.f;
       if (row < M && cin) {
-        if (g.Y) *(f4v *)&g.Y[row * g.ldy + (int64_t)k * d + c0] = y;
+        if (g.Y) {
+          const int64_t yrow = ymp ? (int64_t)ymp[row] : row;
+          *(f4v *)&g.Y[yrow * g.ldy + g.ycol + (int64_t)k * d + c0] = y;
+        }
+      }
+      if (wq && row < M && cin) {
         uint32_t off;
         float tt;
         row_off(row, off, tt);
@@ -400,6 +470,7 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
   }
   __syncthreads();
   if (g.qpart) {
@@ -425,7 +496,31 @@ __global__ void split_bf16_kernel(int64_t n, const double *x, bf16_t *hi, bf16_t
   }
 }
 
+// hi/lo split of U_k = L_k^T for K lower-triangular factors L [K][d][d]
+// (row-major): U[k][n][j] = L[k][j][n] for j >= n, else 0.
+__global__ void split_upper_kernel(int K, int d, const double *L, bf16_t *hi, bf16_t *lo) {
+  const int64_t n_all = (int64_t)K * d * d;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_all;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = i / ((int64_t)d * d);
+    const int r = (int)((i / d) % d), c = (int)(i % d);  // U row r, column c
+    const double v = c >= r ? L[(k * d + c) * d + r] : 0.0;
+    const bf16_t h = f32_to_bf16((float)v);
+    hi[i] = h;
+    lo[i] = f32_to_bf16((float)(v - (double)bf16_to_f32(h)));
+  }
+}
+
 }  // namespace
+
+int launch_split_upper(int K, int d, const double *L, bf16_t *hi, bf16_t *lo, hipStream_t s) {
+  const int64_t n = (int64_t)K * d * d;
+  if (n <= 0) return SB_OK;
+  hipLaunchKernelGGL(split_upper_kernel, dim3((unsigned)std::min<int64_t>(8192, ceil_div(n, 256))),
+                     dim3(256), 0, s, K, d, L, hi, lo);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
 
 bool quad_gemm_bf16_ok(int d) { return d >= 8 && d % 8 == 0; }
 
@@ -472,7 +567,22 @@ int launch_quad_gemm_bf16(int nprod, const Model &m, const ASrc &a, int64_t M,
   p.Y = (float *)o.Y;
   p.ldy = o.ldy;
   p.qpart = (float *)o.qpart;
+  p.sumsq = o.sumsq ? 1 : 0;
+  p.ymap = o.ymap;
+  p.ycol = o.ycol;
+  p.gcnt = o.gcnt;
+  p.gcap = o.gcap;
+  if (o.gcnt && (a.kind != 0 || !a.rowmap || !o.ymap || o.gcap < M)) {
+    set_error("grouped contraction needs row lists of X and Y rows with capacity >= M");
+    return SB_E_INVAL;
+  }
+  if (o.sumsq && (a.kind != 0 || !o.qpart)) {
+    set_error("sum-of-squares contraction needs rows of X and a qpart output");
+    return SB_E_INVAL;
+  }
   o.ntn = p.ntn;
+  // (grouped: each component lists at most M rows, so at most K ceil(M / BM)
+  // row tiles in all; the tiles past the lists' own end return at once)
   const int64_t ntile = ceil_div(M, BM) * (int64_t)(m.K * p.ntn);
   if (ntile == 0) return SB_OK;
   if (ntile > 0x7fffffffll) {

@@ -95,6 +95,16 @@ struct QuadOut {
   int64_t ldy = 0;
   void *qpart = nullptr;          // [M][K][ntn]
   int ntn = 0;                    // set by the launcher (n-tiles per component)
+  // BF16 kernels only: q partials as sums of squares of (X - mu_k) U_k^T with
+  // the model's B operand U_k = L_k^T (no Y); Y rows through ymap and its
+  // column block at ycol
+  bool sumsq = false;
+  const int32_t *ymap = nullptr;
+  int64_t ycol = 0;
+  // grouped by component: gcnt[k] rows of component k listed at
+  // a.rowmap + k * gcap and ymap + k * gcap (M = list capacity)
+  const int32_t *gcnt = nullptr;
+  int64_t gcap = 0;
 };
 
 // Tile shape used for a GEMM call; chosen by the autotuner.
@@ -113,6 +123,8 @@ int launch_quad_gemm_bf16(int nprod, const Model &m, const ASrc &a, int64_t M,
                           const int32_t *count, QuadOut &o, hipStream_t s, TileCfg t);
 // hi = bf16(fp32(x)), lo = bf16(x - hi) (lo nullable) for n values.
 int launch_split_bf16(int64_t n, const double *x, bf16_t *hi, bf16_t *lo, hipStream_t s);
+// hi/lo split of U_k = L_k^T from K lower Cholesky factors [K][d][d].
+int launch_split_upper(int K, int d, const double *L, bf16_t *hi, bf16_t *lo, hipStream_t s);
 int launch_quad_gemm(int dtype, const Model &m, const ASrc &a, int64_t M, const int32_t *count,
                      QuadOut &o, TileCfg t, hipStream_t s);
 
@@ -132,6 +144,11 @@ struct FinishArgs {
   bool logl_f64 = false;            // l output is FP64 whatever the operand type
 };
 int launch_finish(int dtype, const Model &m, const FinishArgs &f, hipStream_t s);
+// Rows with a non-zero FP32 responsibility per mixture component (the
+// epilogue's own responsibilities), from FP32 q partials.
+int launch_active_lists(const Model &m, int64_t M, const int32_t *count, const float *qpart,
+                        int ntn, const int32_t *rowmap, int32_t *cnt, int32_t *rows,
+                        int32_t *xrows, int64_t cap, hipStream_t s);
 
 struct HvpArgs {
   int64_t M = 0;

@@ -166,34 +166,76 @@ struct Evaluator {
   int64_t ldy = 0;
   TileCfg tile;
   int ntn = 0;
-  static size_t bytes(int dtype, int d, int K, int64_t cap, TileCfg t) {
-    const size_t es = (dtype == DT_F64) ? 8 : 4;
-    const size_t ntn = (size_t)ceil_div(d, std::min(t.bn, 64));  // upper bound over tile choices
-    return align_up(es * (size_t)cap * K * d) + align_up(es * (size_t)cap * K * ntn) + 512;
-  }
+  // Two-stage mixture contraction (split BF16, K > 1): q_k = |Z_k|^2 with
+  // Z_k = (X - mu_k) U_k^T, U_k = L_k^T from P_k = L_k L_k^T (the triangle
+  // halves the contraction), then Y_k = (X - mu_k) P_k^T only for the rows
+  // whose responsibility r_k is not zero.  A separated mixture's start sees
+  // one component, so the K contractions of a row shrink to K/2 + 1.
+  bool two_stage = false;
+  const bf16_t *Uhi = nullptr, *Ulo = nullptr;  // [K][d][d]
+  TileCfg tile1, tile2;                         // tiles of the two stages
+  int32_t *lcnt = nullptr, *lrows = nullptr, *lxrows = nullptr;
   int carve(Arena &ar) {
     const size_t es = (dtype == DT_F64) ? 8 : 4;
     ldy = (int64_t)m.K * m.d;
     Y = ar.take<char>(es * (size_t)cap * ldy);
     qpart = ar.take<char>(es * (size_t)cap * m.K * ceil_div(m.d, 64));
+    if (two_stage) {
+      lcnt = ar.take<int32_t>(m.K);
+      lrows = ar.take<int32_t>((size_t)m.K * cap);
+      lxrows = ar.take<int32_t>((size_t)m.K * cap);
+    }
     return ar.ok() ? SB_OK : SB_E_NOMEM;
+  }
+  // Stage 1 (q partials) and stage 2 (Y of the active components); the
+  // epilogue then reads exactly the Y rows stage 2 wrote.
+  int contract_two_stage(const ASrc &a, int64_t M, const int32_t *count, hipStream_t s) {
+    Model m1 = m;
+    m1.Phi = Uhi;
+    m1.Plo = Ulo;
+    QuadOut o1;
+    o1.ldy = ldy;
+    o1.qpart = qpart;
+    o1.sumsq = true;
+    int st = launch_quad_gemm(DT_F32S, m1, a, M, count, o1, tile1, s);
+    if (st) return st;
+    ntn = o1.ntn;
+    if ((st = launch_fill_i32(m.K, 0, lcnt, s))) return st;
+    if ((st = launch_active_lists(m, M, count, (const float *)qpart, ntn, a.rowmap, lcnt, lrows,
+                                  lxrows, cap, s)))
+      return st;
+    ASrc a2 = a;
+    a2.rowmap = lxrows;
+    a2.rows = a.rows > 0 ? a.rows : M;
+    QuadOut o2;
+    o2.Y = Y;
+    o2.ldy = ldy;
+    o2.ymap = lrows;
+    o2.gcnt = lcnt;
+    o2.gcap = cap;
+    return launch_quad_gemm(DT_F32S, m, a2, cap, nullptr, o2, tile2, s);
   }
   // rows: X rows (via rowmap if given), count: device count or null (M rows)
   int run(const ASrc &a, int64_t M, const int32_t *count, void *logl, void *grad, int64_t ldg,
           const int32_t *outmap, void *aux, bool logl_f64, hipStream_t s, bool want_y = true) {
-    QuadOut o;
-    o.Y = want_y ? Y : nullptr;
-    o.ldy = ldy;
-    o.qpart = qpart;
-    int st = launch_quad_gemm(gemm_dtype >= 0 ? gemm_dtype : dtype, m, a, M, count, o, tile, s);
-    if (st) return st;
-    ntn = o.ntn;
+    int st;
+    if (two_stage && want_y) {
+      if ((st = contract_two_stage(a, M, count, s))) return st;
+    } else {
+      QuadOut o;
+      o.Y = want_y ? Y : nullptr;
+      o.ldy = ldy;
+      o.qpart = qpart;
+      st = launch_quad_gemm(gemm_dtype >= 0 ? gemm_dtype : dtype, m, a, M, count, o, tile, s);
+      if (st) return st;
+      ntn = o.ntn;
+    }
     FinishArgs f;
     f.M = M;
     f.count = count;
     f.outmap = outmap;
     f.qpart = qpart;
-    f.ntn = o.ntn;
+    f.ntn = ntn;
     f.Y = Y;
     f.ldy = ldy;
     f.logl = logl;
@@ -247,6 +289,7 @@ struct Layout {
   int32_t *info = nullptr, *flags = nullptr;
   float *P32 = nullptr, *mu32 = nullptr;
   bf16_t *Pbf = nullptr, *Plo = nullptr;
+  bf16_t *Uhi = nullptr, *Ulo = nullptr;  // split U_k = L_k^T (two-stage mixture bulk)
   // discovery
   double *P0 = nullptr, *P1 = nullptr, *best_l = nullptr, *X0 = nullptr;
   float *P0f = nullptr, *P1f = nullptr;
@@ -276,6 +319,19 @@ struct Layout {
   Arena dedup_ar;
 };
 
+// The mixed bulk runs its contraction as split BF16 when d allows
+// (SB_BULK_GEMM=f32 keeps the FP32 matrix-core kernel), two-stage for
+// mixtures (SB_MIX_TWO_STAGE=0 keeps one stage).
+static bool bulk_split(const sb_loglik *ll, const RunCfg &rc) {
+  const char *bg = getenv("SB_BULK_GEMM");
+  return rc.precision == SB_PREC_MIXED && quad_gemm_bf16_ok(ll->d) && !(bg && bg[0] == 'f');
+}
+static bool bulk_two_stage(const sb_loglik *ll, const RunCfg &rc) {
+  const char *ts = getenv("SB_MIX_TWO_STAGE");
+  return bulk_split(ll, rc) && ll->family == SB_FAMILY_GAUSS_MIX && ll->K > 1 &&
+         !(ts && ts[0] == '0');
+}
+
 static int carve_layout(Arena &ar, Layout &L, const sb_loglik *ll, const RunCfg &rc) {
   const int d = ll->d, K = ll->K;
   const int64_t B = rc.n_starts, R = rc.R, NP = (int64_t)rc.R * rc.n_pts;
@@ -294,6 +350,10 @@ static int carve_layout(Arena &ar, Layout &L, const sb_loglik *ll, const RunCfg 
     L.Pbf = ar.take<bf16_t>((size_t)K * d * d);
     L.Plo = ar.take<bf16_t>((size_t)K * d * d);
     L.mu32 = ar.take<float>((size_t)K * d);
+  }
+  if (bulk_two_stage(ll, rc)) {
+    L.Uhi = ar.take<bf16_t>((size_t)K * d * d);
+    L.Ulo = ar.take<bf16_t>((size_t)K * d * d);
   }
   L.P0 = ar.take<double>((size_t)R * d);
   L.P1 = ar.take<double>((size_t)R * d);
@@ -325,6 +385,7 @@ static int carve_layout(Arena &ar, Layout &L, const sb_loglik *ll, const RunCfg 
   L.bulk.cap = B;
   L.bulk.m.d = d;
   L.bulk.m.K = K;
+  L.bulk.two_stage = bulk_two_stage(ll, rc);
   if (L.bulk.carve(ar)) return SB_E_NOMEM;
   L.X0b = mixed ? (void *)ar.take<float>((size_t)B * d) : (void *)L.X0;
   L.Xend = ar.take<char>(bes * (size_t)B * d);
@@ -574,6 +635,7 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
   if (mixed) {
     if ((st = launch_convert_model(m64, L.P32, L.Pbf, L.mu32, s))) return st;
     if ((st = launch_split_bf16((int64_t)K * d * d, P.prec, L.Pbf, L.Plo, s))) return st;
+    if (L.Uhi && (st = launch_split_upper(K, d, L.Lprep, L.Uhi, L.Ulo, s))) return st;
   }
   {
     int32_t hflag[1];
@@ -660,10 +722,10 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     L.bulk.m = mb;
     L.bulk.dtype = mixed ? DT_F32 : DT_F64;
     // mixed bulk: the contraction on the BF16 matrix cores with split operands
-    // (SB_BULK_GEMM=f32 keeps the FP32 matrix-core kernel)
-    const char *bg = getenv("SB_BULK_GEMM");
-    const bool split = mixed && quad_gemm_bf16_ok(d) && !(bg && bg[0] == 'f');
+    const bool split = bulk_split(&llh, rc);
     L.bulk.gemm_dtype = split ? DT_F32S : -1;
+    L.bulk.Uhi = L.Uhi;
+    L.bulk.Ulo = L.Ulo;
     {
       TuneProbe pr;  // timed on the start points and the bulk's own scratch
       pr.a.kind = 0;
@@ -673,6 +735,18 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
       pr.o.ldy = L.bulk.ldy;
       pr.o.qpart = L.bulk.qpart;
       L.bulk.tile = autotune_tiles(split ? DT_F32S : L.bulk.dtype, mb, rc.n_starts, s, &pr);
+      if (L.bulk.two_stage) {
+        // stage 1 timed in its own mode; stage 2 multiplies about one component's share
+        // of the rows per component, where 128 x 128 tiles keep every CU busy
+        Model m1 = mb;
+        m1.Phi = L.Uhi;
+        m1.Plo = L.Ulo;
+        TuneProbe p1 = pr;
+        p1.o.Y = nullptr;
+        p1.o.sumsq = true;
+        L.bulk.tile1 = autotune_tiles(DT_F32S, m1, rc.n_starts, s, &p1);
+        L.bulk.tile2 = TileCfg();
+      }
     }
     int64_t bulk_evals = 0;
     int steps = 0;

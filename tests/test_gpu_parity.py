@@ -406,8 +406,9 @@ def test_evidence_matches_oracle(L, name, ns, prec):
     _compare(r, ref, 1e-9 if prec == 0 else 1e-6)
 
 
-def test_evidence_device_entry_and_determinism(L):
-    prob, cfg = synth.make_workload("c1", n_starts=256)
+@pytest.mark.parametrize("prec", [0, 1])  # 1: mixed (component lists built with atomics)
+def test_evidence_device_entry_and_determinism(L, prec):
+    prob, cfg = synth.make_workload("c1", n_starts=256, precision=prec)
     run = L.EvidenceRunner(prob, cfg)
     a = run.run()
     b = run.run()
