@@ -691,14 +691,19 @@ __global__ __launch_bounds__(256) void finish_kernel(Model m, FinishArgs f) {
     }
     return;
   }
-  double lse;
   T r[kMaxK];
-  mixture_resp<T>(m, qp, f.ntn, lse, r);
-  if (lane == 0) {
-    if (f.logl_f64)
-      ((double *)f.logl)[orow] = m.c + lse;
-    else
-      ((T *)f.logl)[orow] = (T)(m.c + lse);
+  if (f.resp) {  // l and the responsibilities came from the mixture-rows pass
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k) r[k] = (k < K) ? (T)((const float *)f.resp)[row * K + k] : (T)0;
+  } else {
+    double lse;
+    mixture_resp<T>(m, qp, f.ntn, lse, r);
+    if (lane == 0) {
+      if (f.logl_f64)
+        ((double *)f.logl)[orow] = m.c + lse;
+      else
+        ((T *)f.logl)[orow] = (T)(m.c + lse);
+    }
   }
   if (f.aux && lane < K) {
 #pragma unroll
@@ -740,42 +745,50 @@ __global__ __launch_bounds__(256) void finish_kernel(Model m, FinishArgs f) {
   }
 }
 
-// Per component k, the rows whose responsibility r_k is not zero: row r
-// (GEMM row) is appended to rows[k] and its operand row (rowmap[r], or r) to
-// xrows[k]; cnt[k] (zeroed by the caller) counts them.  Order within a list
-// is arbitrary; every row's outputs are independent of it.
-__global__ void active_lists_kernel(Model m, int64_t M, const int32_t *count, const float *qpart,
-                                    int ntn, const int32_t *rowmap, int32_t *cnt, int32_t *rows,
-                                    int32_t *xrows, int64_t cap) {
-  const int64_t Mr = count ? (int64_t)(*count) : M;
+// Mixture rows (FP32 operands), one thread per row: l = c + logsumexp_k
+// (beta_k - q_k/2) and the responsibilities r_k (the epilogue's own function,
+// FP64 arithmetic, r stored in FP32); per component k the rows with r_k != 0
+// are appended to rows[k] (GEMM row) and xrows[k] (operand row: rowmap[r] or
+// r), cnt[k] (zeroed by the caller) counting them.  The epilogue then takes
+// r from `resp`, so it reads exactly the Y rows formed for these lists.
+// Order within a list is arbitrary; every row's outputs are independent of it.
+__global__ __launch_bounds__(256) void mixture_rows_kernel(Model m, MixRowsArgs a) {
+  const int64_t Mr = a.count ? (int64_t)(*a.count) : a.M;
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= Mr) return;
+  const int K = m.K;
   double lse;
   float r[kMaxK];
-  mixture_resp<float>(m, qpart + (size_t)row * m.K * ntn, ntn, lse, r);
+  mixture_resp<float>(m, a.qpart + (size_t)row * K * a.ntn, a.ntn, lse, r);
+  const int64_t orow = a.outmap ? (int64_t)a.outmap[row] : row;
+  if (a.logl_f64)
+    ((double *)a.logl)[orow] = m.c + lse;
+  else
+    ((float *)a.logl)[orow] = (float)(m.c + lse);
 #pragma unroll
   for (int k = 0; k < kMaxK; ++k)
-    if (k < m.K && r[k] != 0.f) {
-      const int pos = atomicAdd(&cnt[k], 1);
-      rows[(int64_t)k * cap + pos] = (int32_t)row;
-      xrows[(int64_t)k * cap + pos] = rowmap ? rowmap[row] : (int32_t)row;
+    if (k < K) {
+      a.resp[row * K + k] = r[k];
+      if (r[k] != 0.f) {
+        const int pos = atomicAdd(&a.cnt[k], 1);
+        a.rows[(int64_t)k * a.cap + pos] = (int32_t)row;
+        a.xrows[(int64_t)k * a.cap + pos] = a.rowmap ? a.rowmap[row] : (int32_t)row;
+      }
     }
 }
 
-int launch_active_lists(const Model &m, int64_t M, const int32_t *count, const float *qpart,
-                        int ntn, const int32_t *rowmap, int32_t *cnt, int32_t *rows,
-                        int32_t *xrows, int64_t cap, hipStream_t s) {
-  if (m.K > kMaxK) {
-    set_error("K=%d exceeds the supported %d components", m.K, kMaxK);
+int launch_mixture_rows(const Model &m, const MixRowsArgs &a, hipStream_t s) {
+  if (m.K > kMaxK || m.family != SB_FAMILY_GAUSS_MIX) {
+    set_error("mixture rows: Gaussian mixtures of at most %d components", kMaxK);
     return SB_E_UNSUPPORTED;
   }
-  if (M > cap || M > 0x7fffffffll) {
-    set_error("active lists: %lld rows over the capacity %lld", (long long)M, (long long)cap);
+  if (a.M > a.cap || a.M > 0x7fffffffll) {
+    set_error("mixture rows: %lld rows over the capacity %lld", (long long)a.M, (long long)a.cap);
     return SB_E_INVAL;
   }
-  if (M <= 0) return SB_OK;
-  hipLaunchKernelGGL(active_lists_kernel, dim3((unsigned)ceil_div(M, 256)), dim3(256), 0, s, m, M,
-                     count, qpart, ntn, rowmap, cnt, rows, xrows, cap);
+  if (a.M <= 0) return SB_OK;
+  // (one wave per workgroup: the rows spread over every CU)
+  hipLaunchKernelGGL(mixture_rows_kernel, dim3((unsigned)ceil_div(a.M, 64)), dim3(64), 0, s, m, a);
   SB_LAUNCH_CHECK();
   return SB_OK;
 }

@@ -142,13 +142,27 @@ struct FinishArgs {
   int64_t ldg = 0;
   void *aux = nullptr;              // [M][K]: responsibilities (mixture) / q (Student-t)
   bool logl_f64 = false;            // l output is FP64 whatever the operand type
+  // mixture with l and FP32 responsibilities [M][K] already computed (by the
+  // mixture-rows pass): the epilogue forms the gradient only
+  const void *resp = nullptr;
 };
 int launch_finish(int dtype, const Model &m, const FinishArgs &f, hipStream_t s);
-// Rows with a non-zero FP32 responsibility per mixture component (the
-// epilogue's own responsibilities), from FP32 q partials.
-int launch_active_lists(const Model &m, int64_t M, const int32_t *count, const float *qpart,
-                        int ntn, const int32_t *rowmap, int32_t *cnt, int32_t *rows,
-                        int32_t *xrows, int64_t cap, hipStream_t s);
+// Gaussian-mixture rows from FP32 q partials: l, FP32 responsibilities, and
+// per component the rows whose responsibility is not zero.
+struct MixRowsArgs {
+  int64_t M = 0;
+  const int32_t *count = nullptr;   // device row count (nullable -> M)
+  const float *qpart = nullptr;     // [M][K][ntn]
+  int ntn = 0;
+  const int32_t *rowmap = nullptr;  // operand row of each row (nullable: the row)
+  const int32_t *outmap = nullptr;  // l output row (nullable: the row)
+  void *logl = nullptr;
+  bool logl_f64 = false;
+  float *resp = nullptr;            // [M][K]
+  int32_t *cnt = nullptr, *rows = nullptr, *xrows = nullptr;  // [K], [K][cap], [K][cap]
+  int64_t cap = 0;
+};
+int launch_mixture_rows(const Model &m, const MixRowsArgs &a, hipStream_t s);
 
 struct HvpArgs {
   int64_t M = 0;

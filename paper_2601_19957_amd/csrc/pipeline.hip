@@ -175,6 +175,7 @@ struct Evaluator {
   const bf16_t *Uhi = nullptr, *Ulo = nullptr;  // [K][d][d]
   TileCfg tile1, tile2;                         // tiles of the two stages
   int32_t *lcnt = nullptr, *lrows = nullptr, *lxrows = nullptr;
+  float *resp = nullptr;  // [cap][K]
   int carve(Arena &ar) {
     const size_t es = (dtype == DT_F64) ? 8 : 4;
     ldy = (int64_t)m.K * m.d;
@@ -184,12 +185,15 @@ struct Evaluator {
       lcnt = ar.take<int32_t>(m.K);
       lrows = ar.take<int32_t>((size_t)m.K * cap);
       lxrows = ar.take<int32_t>((size_t)m.K * cap);
+      resp = ar.take<float>((size_t)m.K * cap);
     }
     return ar.ok() ? SB_OK : SB_E_NOMEM;
   }
-  // Stage 1 (q partials) and stage 2 (Y of the active components); the
-  // epilogue then reads exactly the Y rows stage 2 wrote.
-  int contract_two_stage(const ASrc &a, int64_t M, const int32_t *count, hipStream_t s) {
+  // Stage 1 (q partials), l and the responsibilities with the row lists,
+  // stage 2 (Y of the active components); the epilogue then takes r from the
+  // rows pass and reads exactly the Y rows stage 2 wrote.
+  int contract_two_stage(const ASrc &a, int64_t M, const int32_t *count, void *logl,
+                         const int32_t *outmap, bool logl_f64, hipStream_t s) {
     Model m1 = m;
     m1.Phi = Uhi;
     m1.Plo = Ulo;
@@ -201,9 +205,21 @@ struct Evaluator {
     if (st) return st;
     ntn = o1.ntn;
     if ((st = launch_fill_i32(m.K, 0, lcnt, s))) return st;
-    if ((st = launch_active_lists(m, M, count, (const float *)qpart, ntn, a.rowmap, lcnt, lrows,
-                                  lxrows, cap, s)))
-      return st;
+    MixRowsArgs mr;
+    mr.M = M;
+    mr.count = count;
+    mr.qpart = (const float *)qpart;
+    mr.ntn = ntn;
+    mr.rowmap = a.rowmap;
+    mr.outmap = outmap;
+    mr.logl = logl;
+    mr.logl_f64 = logl_f64;
+    mr.resp = resp;
+    mr.cnt = lcnt;
+    mr.rows = lrows;
+    mr.xrows = lxrows;
+    mr.cap = cap;
+    if ((st = launch_mixture_rows(m, mr, s))) return st;
     ASrc a2 = a;
     a2.rowmap = lxrows;
     a2.rows = a.rows > 0 ? a.rows : M;
@@ -219,8 +235,9 @@ struct Evaluator {
   int run(const ASrc &a, int64_t M, const int32_t *count, void *logl, void *grad, int64_t ldg,
           const int32_t *outmap, void *aux, bool logl_f64, hipStream_t s, bool want_y = true) {
     int st;
-    if (two_stage && want_y) {
-      if ((st = contract_two_stage(a, M, count, s))) return st;
+    const bool ts = two_stage && want_y && !aux;
+    if (ts) {
+      if ((st = contract_two_stage(a, M, count, logl, outmap, logl_f64, s))) return st;
     } else {
       QuadOut o;
       o.Y = want_y ? Y : nullptr;
@@ -243,6 +260,7 @@ struct Evaluator {
     f.ldg = ldg;
     f.aux = aux;
     f.logl_f64 = logl_f64;
+    f.resp = ts ? resp : nullptr;
     return launch_finish(dtype, m, f, s);
   }
 };
