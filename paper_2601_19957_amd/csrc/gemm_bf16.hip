@@ -37,6 +37,7 @@ struct Bf16Params {
   int sumsq;
   const int32_t *ymap;      // Y row of GEMM row r: ymap[r] (nullable: r)
   int64_t ycol;             // column offset of the Y block
+  int yneg;                 // store -Y (q still uses Y)
   // Grouped by component (nullable): component k multiplies gcnt[k] rows,
   // listed at a.rowmap + k * gcap (X rows) and ymap + k * gcap (Y rows)
   const int32_t *gcnt;
@@ -446,7 +447,7 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
       if (row < M && cin) {
         if (g.Y) {
           const int64_t yrow = ymp ? (int64_t)ymp[row] : row;
-          *(f4v *)&g.Y[yrow * g.ldy + g.ycol + (int64_t)k * d + c0] = y;
+          *(f4v *)&g.Y[yrow * g.ldy + g.ycol + (int64_t)k * d + c0] = g.yneg ? -y : y;
         }
       }
       if (wq && row < M && cin) {
@@ -572,6 +573,7 @@ int launch_quad_gemm_bf16(int nprod, const Model &m, const ASrc &a, int64_t M,
   p.ycol = o.ycol;
   p.gcnt = o.gcnt;
   p.gcap = o.gcap;
+  p.yneg = o.yneg ? 1 : 0;
   if (o.gcnt && (a.kind != 0 || !a.rowmap || !o.ymap || o.gcap < M)) {
     set_error("grouped contraction needs row lists of X and Y rows with capacity >= M");
     return SB_E_INVAL;

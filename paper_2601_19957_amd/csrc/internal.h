@@ -105,6 +105,7 @@ struct QuadOut {
   // a.rowmap + k * gcap and ymap + k * gcap (M = list capacity)
   const int32_t *gcnt = nullptr;
   int64_t gcap = 0;
+  bool yneg = false;  // store -Y (a Gaussian's gradient); q still uses Y
 };
 
 // Tile shape used for a GEMM call; chosen by the autotuner.

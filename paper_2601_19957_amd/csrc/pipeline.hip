@@ -176,6 +176,9 @@ struct Evaluator {
   TileCfg tile1, tile2;                         // tiles of the two stages
   int32_t *lcnt = nullptr, *lrows = nullptr, *lxrows = nullptr;
   float *resp = nullptr;  // [cap][K]
+  // Single Gaussian on the split kernel: grad l = -Y, so the contraction
+  // writes -Y straight into the gradient rows and the epilogue forms l only.
+  bool grad_direct = false;
   int carve(Arena &ar) {
     const size_t es = (dtype == DT_F64) ? 8 : 4;
     ldy = (int64_t)m.K * m.d;
@@ -236,8 +239,18 @@ struct Evaluator {
           const int32_t *outmap, void *aux, bool logl_f64, hipStream_t s, bool want_y = true) {
     int st;
     const bool ts = two_stage && want_y && !aux;
+    const bool gd = grad_direct && want_y && grad && !aux;
     if (ts) {
       if ((st = contract_two_stage(a, M, count, logl, outmap, logl_f64, s))) return st;
+    } else if (gd) {
+      QuadOut o;
+      o.Y = grad;
+      o.ldy = ldg;
+      o.ymap = outmap;
+      o.yneg = true;
+      o.qpart = qpart;
+      if ((st = launch_quad_gemm(DT_F32S, m, a, M, count, o, tile, s))) return st;
+      ntn = o.ntn;
     } else {
       QuadOut o;
       o.Y = want_y ? Y : nullptr;
@@ -261,6 +274,7 @@ struct Evaluator {
     f.aux = aux;
     f.logl_f64 = logl_f64;
     f.resp = ts ? resp : nullptr;
+    if (gd) f.grad = nullptr;  // (written by the contraction)
     return launch_finish(dtype, m, f, s);
   }
 };
@@ -765,6 +779,7 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
         L.bulk.tile1 = autotune_tiles(DT_F32S, m1, rc.n_starts, s, &p1);
         L.bulk.tile2 = TileCfg();
       }
+      L.bulk.grad_direct = split && K == 1 && P.family == SB_FAMILY_GAUSS_MIX;
     }
     int64_t bulk_evals = 0;
     int steps = 0;

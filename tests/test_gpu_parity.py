@@ -406,6 +406,16 @@ def test_evidence_matches_oracle(L, name, ns, prec):
     _compare(r, ref, 1e-9 if prec == 0 else 1e-6)
 
 
+@pytest.mark.parametrize("name,d", [("c0", 64), ("c1", 64)])
+def test_evidence_mixed_split_paths(L, name, d):
+    """Mixed precision at d = 64 (split contraction): a single Gaussian (gradient written by
+    the contraction) and a mixture (two-stage bulk) against the FP64 oracle."""
+    prob, cfg = synth.make_workload(name, n_starts=256, d=d, precision=1)
+    r = L.sb_evidence(prob, cfg)
+    ref = O.evidence(prob, synth.make_run_config(name, n_starts=256, precision=0))
+    _compare(r, ref, 1e-6)
+
+
 @pytest.mark.parametrize("prec", [0, 1])  # 1: mixed (component lists built with atomics)
 def test_evidence_device_entry_and_determinism(L, prec):
     prob, cfg = synth.make_workload("c1", n_starts=256, precision=prec)
