@@ -793,6 +793,277 @@ int launch_mixture_rows(const Model &m, const MixRowsArgs &a, hipStream_t s) {
   return SB_OK;
 }
 
+// Screened mixture rows.  With U_k^T U_k = P_k, s_k(x) = sqrt(q_k(x)) =
+// |U_k (x - mu_k)| is Lipschitz with constant |U_k|_2 <= sigma_k =
+// sqrt(rho_k), rho_k the largest absolute row sum of P_k (Gershgorin).  A row
+// keeps bounds lb_k <= s_k(x_ref) <= ub_k at its last evaluated point, so at x
+//   max(0, lb_k - sigma_k D) <= s_k(x) <= ub_k + sigma_k D,  D = |x - x_ref|,
+// which brackets a_k = beta_k - q_k / 2 in [lo_k, hi_k].  Component k is
+// dropped when hi_k < max_j lo_j - kScreenGap: its exact responsibility is
+// then below e^-kScreenGap, far under FP32's smallest subnormal (e^-103.3),
+// and its share of l far below FP64 resolution; it keeps the widened bounds.
+// A listed component gets new bounds from the split contraction's q_k, whose
+// error is at most c_q rho_k |x - mu_k|^2: the split representation drops
+// 3 2^-16 of each |P_nj delta_j|, FP32 accumulation of the 3d products and
+// of the d-term q sum at most (d + 32) 2^-24 each, and |delta|^T |P| |delta|
+// <= rho |delta|^2 (c_q has a 1.25 margin); s_k of the rounded delta =
+// fl32(x - mu_k) is within sigma_k 2^-23 |delta| of s_k(x).  A NaN anywhere
+// keeps the component (the comparisons fail).
+constexpr double kScreenGap = 120.0;
+
+__device__ inline double screen_cq(int d) {
+  return 1.25 * (3.0 * 0x1p-16 + 4.0 * (d + 32) * 0x1p-24);
+}
+// relative slack of FP32 sums of d squares
+__device__ inline double screen_rq(int d) { return (2.0 * d + 128) * 0x1p-24; }
+__device__ inline double clamp0(double v) {  // max(v, 0), NaN stays NaN
+  return v > 0.0 ? v : (v <= 0.0 ? 0.0 : (double)NAN);
+}
+
+// One wave per row: |x - x_ref|^2 over the row, the decision (the row's
+// component mask), the dropped components' widened bounds and q partials,
+// |x - mu_k|^2 of the listed ones, and x_ref = x.
+__global__ __launch_bounds__(256) void mixture_screen_kernel(Model m, ScreenArgs a) {
+  const int64_t Mr = a.count ? (int64_t)(*a.count) : a.M;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= Mr) return;
+  const int d = m.d, K = m.K;
+  const int32_t xr = a.rowmap ? a.rowmap[row] : (int32_t)row;
+  const float *x = a.X + (int64_t)xr * a.ldx;
+  float *xref = a.xref + (int64_t)xr * d;
+  uint32_t keep = (1u << K) - 1u;  // (K <= 16) no reference yet: every component
+  if (a.hasref[xr] > 0) {
+    float dd = 0.f;
+    for (int j = 4 * lane; j < d; j += 256) {  // (d % 8 == 0, 16-byte rows)
+      const f4v xv = *(const f4v *)(x + j), rv = *(const f4v *)(xref + j);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float t = xv[e] - rv[e];
+        dd += t * t;
+      }
+    }
+    // (the butterfly leaves the same sum in every lane: the decision is uniform)
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) dd += __shfl_xor(dd, o, 64);
+    const double D = sqrt((double)dd * (1.0 + screen_rq(d))) * (1.0 + 0x1p-40);
+    double *lb = a.bnd + (int64_t)xr * 2 * K, *ub = lb + K;
+    double Lk[kMaxK], Uk[kMaxK];
+    double mx = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k) {
+      Lk[k] = Uk[k] = 0.0;
+      if (k < K) {
+        const double w = sqrt(a.rho[k] * (1.0 + 0x1p-40)) * D;
+        Lk[k] = clamp0(lb[k] - w);
+        Uk[k] = ub[k] + w;
+        mx = fmax(mx, m.beta[k] - 0.5 * Uk[k] * Uk[k]);
+      }
+    }
+    keep = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+      if (k < K && !(m.beta[k] - 0.5 * Lk[k] * Lk[k] < mx - kScreenGap)) keep |= 1u << k;
+    // dropped: the widened bounds now hold at x
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+      if (k == lane && k < K && !((keep >> k) & 1u)) {
+        lb[k] = Lk[k];
+        ub[k] = Uk[k];
+      }
+  }
+  // |x - mu_k|^2 of the listed components (for their new bounds) and x_ref = x
+  float nrm[kMaxK];
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) nrm[k] = 0.f;
+  for (int j = 4 * lane; j < d; j += 256) {
+    const f4v xv = *(const f4v *)(x + j);
+    *(f4v *)(xref + j) = xv;
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+      if (k < K && ((keep >> k) & 1u)) {
+        const f4v mv = *(const f4v *)(m.mu32 + (int64_t)k * d + j);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float t = xv[e] - mv[e];  // delta as the contraction forms it
+          nrm[k] += t * t;
+        }
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k)
+    if (k < K && ((keep >> k) & 1u))
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) nrm[k] += __shfl_xor(nrm[k], o, 64);
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k)
+    if (k == lane && k < K) a.nrm[row * K + k] = nrm[k];
+  if (lane == 0) a.mask[row] = keep;
+  // a dropped component's q partials: +inf, 0, ... (one coalesced row block)
+  float *q2 = a.qpart + (size_t)row * K * a.ntn;
+  for (int i = lane; i < K * a.ntn; i += 64)
+    if (!((keep >> (i / a.ntn)) & 1u)) q2[i] = (i % a.ntn == 0) ? INFINITY : 0.f;
+}
+
+// Lists from the masks, one thread per row, 1024 rows per workgroup: ranks
+// within each wave by ballot, wave offsets in LDS, one atomic per workgroup
+// and component (same-address atomics from many workgroups serialise).
+__global__ __launch_bounds__(1024) void mixture_lists_kernel(Model m, ScreenArgs a) {
+  __shared__ int woff[16][kMaxK];
+  __shared__ int base[kMaxK];
+  const int64_t Mr = a.count ? (int64_t)(*a.count) : a.M;
+  const int64_t row = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int K = m.K;
+  const bool valid = row < Mr;
+  const uint32_t mk = valid ? a.mask[row] : 0u;
+  int rank[kMaxK];
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) {
+    rank[k] = 0;
+    if (k < K) {
+      const uint64_t bal = __ballot((mk >> k) & 1u);
+      rank[k] = __popcll(bal & ((1ull << lane) - 1ull));
+      if (lane == 0) woff[wave][k] = __popcll(bal);
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < K) {
+    const int k = threadIdx.x;
+    int tot = 0;
+    for (int w = 0; w < 16; ++w) {
+      const int c = woff[w][k];
+      woff[w][k] = tot;
+      tot += c;
+    }
+    base[k] = tot ? atomicAdd(&a.cnt[k], tot) : 0;
+  }
+  __syncthreads();
+  if (!valid) return;
+  const int32_t xr = a.rowmap ? a.rowmap[row] : (int32_t)row;
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k)
+    if (k < K && ((mk >> k) & 1u)) {
+      const int64_t pos = (int64_t)k * a.cap + base[k] + woff[wave][k] + rank[k];
+      a.rows[pos] = (int32_t)row;
+      a.xrows[pos] = xr;
+    }
+}
+
+// After the contraction, one thread per row: l and the responsibilities from
+// q (the epilogue's own function, FP64 arithmetic, r stored in FP32), and the
+// listed components' bounds from their q_k.
+__global__ __launch_bounds__(64) void mixture_post_kernel(Model m, ScreenArgs a) {
+  const int64_t Mr = a.count ? (int64_t)(*a.count) : a.M;
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= Mr) return;
+  const int d = m.d, K = m.K;
+  const float *qp = a.qpart + (size_t)row * K * a.ntn;
+  double lse;
+  float r[kMaxK];
+  mixture_resp<float>(m, qp, a.ntn, lse, r);
+  const int64_t orow = a.outmap ? (int64_t)a.outmap[row] : row;
+  if (a.logl_f64)
+    ((double *)a.logl)[orow] = m.c + lse;
+  else
+    ((float *)a.logl)[orow] = (float)(m.c + lse);
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k)
+    if (k < K) a.resp[row * K + k] = r[k];
+  const int32_t xr = a.rowmap ? a.rowmap[row] : (int32_t)row;
+  const uint32_t mk = a.mask[row];
+  const double cq = screen_cq(d), rq = screen_rq(d);
+  double *lb = a.bnd + (int64_t)xr * 2 * K, *ub = lb + K;
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k)
+    if (k < K && ((mk >> k) & 1u)) {
+      double q = 0.0;
+      for (int t = 0; t < a.ntn; ++t) q += (double)qp[k * a.ntn + t];
+      const double rk = a.rho[k] * (1.0 + 0x1p-40);
+      const double nk = (double)a.nrm[row * K + k] * (1.0 + rq);
+      const double e = cq * rk * nk;
+      // (+- sigma_k 2^-23 |delta|: delta = fl32(x - mu_k) against the exact x - mu_k)
+      const double rr = sqrt(rk * nk) * 0x1p-23;
+      lb[k] = clamp0(sqrt(clamp0(q - e)) - rr);
+      ub[k] = sqrt(clamp0(q + e)) + rr;
+    }
+  a.hasref[xr] = 1;
+}
+
+static int screen_check(const Model &m, const ScreenArgs &a, const char *what) {
+  if (m.K > kMaxK || m.K > 64 || m.family != SB_FAMILY_GAUSS_MIX) {
+    set_error("%s: Gaussian mixtures of at most %d components", what, kMaxK);
+    return SB_E_UNSUPPORTED;
+  }
+  if (a.M > a.cap || a.M > 0x7fffffffll) {
+    set_error("%s: %lld rows over the capacity %lld", what, (long long)a.M, (long long)a.cap);
+    return SB_E_INVAL;
+  }
+  if (m.d % 8 != 0 || (uintptr_t)a.X % 16 != 0 || a.ldx % 4 != 0 ||
+      (uintptr_t)m.mu32 % 16 != 0 || (uintptr_t)a.xref % 16 != 0 || !a.rho || !a.bnd ||
+      !a.hasref || !a.nrm || !a.qpart || a.ntn < 1 || !a.mask) {
+    set_error("%s: needs d %% 8 == 0, 16-byte rows and the screening state", what);
+    return SB_E_INVAL;
+  }
+  if (a.nstate < a.M) {
+    set_error("%s: %lld operand rows with state for %lld rows", what, (long long)a.nstate,
+              (long long)a.M);
+    return SB_E_INVAL;
+  }
+  return SB_OK;
+}
+
+int launch_mixture_screen(const Model &m, const ScreenArgs &a, hipStream_t s) {
+  int st = screen_check(m, a, "mixture screen");
+  if (st || a.M <= 0) return st;
+  hipLaunchKernelGGL(mixture_screen_kernel, dim3((unsigned)ceil_div(a.M, 4)), dim3(256), 0, s, m,
+                     a);
+  SB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(mixture_lists_kernel, dim3((unsigned)ceil_div(a.M, 1024)), dim3(1024), 0, s,
+                     m, a);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+int launch_mixture_post(const Model &m, const ScreenArgs &a, hipStream_t s) {
+  int st = screen_check(m, a, "mixture post");
+  if (st || a.M <= 0) return st;
+  if (!a.logl || !a.resp) {
+    set_error("mixture post: needs l and responsibility outputs");
+    return SB_E_INVAL;
+  }
+  hipLaunchKernelGGL(mixture_post_kernel, dim3((unsigned)ceil_div(a.M, 64)), dim3(64), 0, s, m,
+                     a);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// One wave per row of P_k: the absolute row sum, folded into rho[k] with an
+// integer max on the bit pattern (order-preserving for non-negative doubles).
+__global__ __launch_bounds__(256) void row_abs_max_kernel(int K, int d, const double *P,
+                                                          double *rho) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= (int64_t)K * d) return;
+  const double *p = P + r * d;
+  double t = 0.0;
+  for (int j = lane; j < d; j += 64) t += fabs(p[j]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o, 64);
+  if (lane == 0)
+    atomicMax((unsigned long long *)&rho[r / d], (unsigned long long)__double_as_longlong(t));
+}
+
+int launch_row_abs_max(int K, int d, const double *P, double *rho, hipStream_t s) {
+  if (K <= 0 || d <= 0) return SB_OK;
+  int st = launch_fill_i32(2 * (int64_t)K, 0, (int32_t *)rho, s);
+  if (st) return st;
+  hipLaunchKernelGGL(row_abs_max_kernel, dim3((unsigned)ceil_div((int64_t)K * d, 4)), dim3(256),
+                     0, s, K, d, P, rho);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
 int launch_finish(int dtype, const Model &m, const FinishArgs &f, hipStream_t s) {
   if (m.K > kMaxK) {
     set_error("K=%d exceeds the supported %d components", m.K, kMaxK);

@@ -39,7 +39,8 @@ struct Bf16Params {
   int64_t ycol;             // column offset of the Y block
   int yneg;                 // store -Y (q still uses Y)
   // Grouped by component (nullable): component k multiplies gcnt[k] rows,
-  // listed at a.rowmap + k * gcap (X rows) and ymap + k * gcap (Y rows)
+  // listed at a.rowmap + k * gcap (X rows) and ymap + k * gcap (Y rows);
+  // qpart is then indexed by the Y row
   const int32_t *gcnt;
   int64_t gcap;
 };
@@ -481,7 +482,8 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
         float q = qs[0][i];
 #pragma unroll
         for (int w2 = 1; w2 < WGN; ++w2) q += qs[w2][i];
-        g.qpart[(row * g.K + k) * g.ntn + nt] = q;
+        const int64_t qr = g.gcnt ? (int64_t)ymp[row] : row;  // (grouped: the Y row)
+        g.qpart[(qr * g.K + k) * g.ntn + nt] = q;
       }
     }
   }

@@ -102,7 +102,8 @@ struct QuadOut {
   const int32_t *ymap = nullptr;
   int64_t ycol = 0;
   // grouped by component: gcnt[k] rows of component k listed at
-  // a.rowmap + k * gcap and ymap + k * gcap (M = list capacity)
+  // a.rowmap + k * gcap and ymap + k * gcap (M = list capacity); qpart is
+  // then indexed by the Y row
   const int32_t *gcnt = nullptr;
   int64_t gcap = 0;
   bool yneg = false;  // store -Y (a Gaussian's gradient); q still uses Y
@@ -164,6 +165,43 @@ struct MixRowsArgs {
   int64_t cap = 0;
 };
 int launch_mixture_rows(const Model &m, const MixRowsArgs &a, hipStream_t s);
+
+// Screened mixture rows (FP32 rows of X).  Each operand row carries its last
+// evaluated point x_ref with bounds lb_k <= sqrt(q_k(x_ref)) <= ub_k; at a new
+// point x the bounds widen by sigma_k |x - x_ref| (sigma_k^2 >= the largest
+// eigenvalue of P_k) and only the components they cannot rule out are listed
+// for the contraction; every other one gets q partials (+inf, 0, ...) in
+// qpart and keeps the widened bounds.  x becomes the new x_ref.  After the
+// contraction the post pass forms l and the responsibilities (the epilogue's
+// own function) and sets the listed components' bounds from their q_k.
+struct ScreenArgs {
+  int64_t M = 0;
+  const int32_t *count = nullptr;   // device row count (nullable -> M)
+  const float *X = nullptr;         // operand rows (FP32), row stride ldx
+  int64_t ldx = 0;
+  const int32_t *rowmap = nullptr;  // operand row of each row (nullable: the row)
+  int64_t nstate = 0;               // operand rows with screening state
+  const double *rho = nullptr;      // [K] max_i sum_j |P_k[i][j]| (>= the largest eigenvalue)
+  float *xref = nullptr;            // [nstate][d] last evaluated points
+  double *bnd = nullptr;            // [nstate][2K] lb_k then ub_k
+  int32_t *hasref = nullptr;        // [nstate] 1: x_ref and bounds set, else none yet
+  float *nrm = nullptr;             // [cap][K] |x - mu_k|^2 of the listed components
+  float *qpart = nullptr;           // [M][K][ntn] q partials of the contraction
+  int ntn = 0;
+  uint32_t *mask = nullptr;         // [cap] components listed per row (bit k)
+  int32_t *cnt = nullptr, *rows = nullptr, *xrows = nullptr;  // [K], [K][cap], [K][cap]
+  int64_t cap = 0;
+  // post pass: l (at outmap[row], FP64 or FP32) and r [M][K]
+  void *logl = nullptr;
+  const int32_t *outmap = nullptr;
+  bool logl_f64 = false;
+  float *resp = nullptr;
+};
+// screen + list passes (cnt zeroed by the caller)
+int launch_mixture_screen(const Model &m, const ScreenArgs &a, hipStream_t s);
+int launch_mixture_post(const Model &m, const ScreenArgs &a, hipStream_t s);
+// rho[k] = max_i sum_j |P_k[i][j]| (FP64 P [K][d][d]); rho is zeroed first.
+int launch_row_abs_max(int K, int d, const double *P, double *rho, hipStream_t s);
 
 struct HvpArgs {
   int64_t M = 0;

@@ -172,6 +172,18 @@ struct Evaluator {
   // whose responsibility r_k is not zero.  A separated mixture's start sees
   // one component, so the K contractions of a row shrink to K/2 + 1.
   bool two_stage = false;
+  // Screened instead: a rows pass bounds every q_k from the row's last
+  // evaluated point (bounds there, widened by the distance moved) and lists
+  // only the components the bounds cannot rule out; the split contraction
+  // forms Y_k and q_k for those, and a post pass forms l and r from its q and
+  // renews the listed components' bounds.
+  bool screen = false;
+  const double *rho = nullptr;  // [K] largest absolute row sum of P_k
+  int64_t nstate = 0;           // operand rows with state (both L-BFGS slots)
+  float *xref = nullptr, *nrm = nullptr;
+  double *bnd = nullptr;
+  int32_t *hasref = nullptr;
+  uint32_t *mask = nullptr;  // [cap]
   const bf16_t *Uhi = nullptr, *Ulo = nullptr;  // [K][d][d]
   TileCfg tile1, tile2;                         // tiles of the two stages
   int32_t *lcnt = nullptr, *lrows = nullptr, *lxrows = nullptr;
@@ -189,14 +201,75 @@ struct Evaluator {
       lrows = ar.take<int32_t>((size_t)m.K * cap);
       lxrows = ar.take<int32_t>((size_t)m.K * cap);
       resp = ar.take<float>((size_t)m.K * cap);
+      if (screen) {
+        nstate = 2 * cap;
+        xref = ar.take<float>((size_t)nstate * m.d);
+        nrm = ar.take<float>((size_t)cap * m.K);
+        bnd = ar.take<double>((size_t)nstate * 2 * m.K);
+        hasref = ar.take<int32_t>(nstate);
+        mask = ar.take<uint32_t>(cap);
+      }
     }
     return ar.ok() ? SB_OK : SB_E_NOMEM;
   }
-  // Stage 1 (q partials), l and the responsibilities with the row lists,
-  // stage 2 (Y of the active components); the epilogue then takes r from the
-  // rows pass and reads exactly the Y rows stage 2 wrote.
+  // Screened: the screen and list passes, the split contraction of the
+  // listed (row, component) pairs (Y and q), the post pass (l, r, refreshed
+  // bounds).  Unscreened: stage 1 (q partials), l and the
+  // responsibilities with the row lists, stage 2 (Y of the active
+  // components); the epilogue takes r from the rows pass.  Either way it reads
+  // exactly the Y rows the contraction wrote.
   int contract_two_stage(const ASrc &a, int64_t M, const int32_t *count, void *logl,
                          const int32_t *outmap, bool logl_f64, hipStream_t s) {
+    int st;
+    if (screen) {
+      ScreenArgs sa;
+      sa.M = M;
+      sa.count = count;
+      sa.X = (const float *)a.X;
+      sa.ldx = a.ldx;
+      sa.rowmap = a.rowmap;
+      sa.nstate = nstate;
+      sa.rho = rho;
+      sa.xref = xref;
+      sa.bnd = bnd;
+      sa.hasref = hasref;
+      sa.nrm = nrm;
+      sa.qpart = (float *)qpart;
+      sa.ntn = (int)ceil_div(m.d, tile2.bn == 256 ? 256 : 128);
+      sa.mask = mask;
+      sa.cnt = lcnt;
+      sa.rows = lrows;
+      sa.xrows = lxrows;
+      sa.cap = cap;
+      sa.logl = logl;
+      sa.outmap = outmap;
+      sa.logl_f64 = logl_f64;
+      sa.resp = resp;
+      if ((a.rows > 0 ? a.rows : M) > nstate) {
+        set_error("screened mixture: %lld operand rows, state for %lld",
+                  (long long)(a.rows > 0 ? a.rows : M), (long long)nstate);
+        return SB_E_INVAL;
+      }
+      if ((st = launch_fill_i32(m.K, 0, lcnt, s))) return st;
+      if ((st = launch_mixture_screen(m, sa, s))) return st;
+      ASrc a2 = a;
+      a2.rowmap = lxrows;
+      a2.rows = a.rows > 0 ? a.rows : M;
+      QuadOut o2;
+      o2.Y = Y;
+      o2.ldy = ldy;
+      o2.ymap = lrows;
+      o2.gcnt = lcnt;
+      o2.gcap = cap;
+      o2.qpart = qpart;
+      if ((st = launch_quad_gemm(DT_F32S, m, a2, cap, nullptr, o2, tile2, s))) return st;
+      if (o2.ntn != sa.ntn) {
+        set_error("screened mixture: %d column tiles, expected %d", o2.ntn, sa.ntn);
+        return SB_E_UNSUPPORTED;
+      }
+      ntn = o2.ntn;
+      return launch_mixture_post(m, sa, s);
+    }
     Model m1 = m;
     m1.Phi = Uhi;
     m1.Plo = Ulo;
@@ -204,7 +277,7 @@ struct Evaluator {
     o1.ldy = ldy;
     o1.qpart = qpart;
     o1.sumsq = true;
-    int st = launch_quad_gemm(DT_F32S, m1, a, M, count, o1, tile1, s);
+    st = launch_quad_gemm(DT_F32S, m1, a, M, count, o1, tile1, s);
     if (st) return st;
     ntn = o1.ntn;
     if ((st = launch_fill_i32(m.K, 0, lcnt, s))) return st;
@@ -322,6 +395,7 @@ struct Layout {
   float *P32 = nullptr, *mu32 = nullptr;
   bf16_t *Pbf = nullptr, *Plo = nullptr;
   bf16_t *Uhi = nullptr, *Ulo = nullptr;  // split U_k = L_k^T (two-stage mixture bulk)
+  double *rho = nullptr;                  // [K] largest absolute row sum of P_k (screen)
   // discovery
   double *P0 = nullptr, *P1 = nullptr, *best_l = nullptr, *X0 = nullptr;
   float *P0f = nullptr, *P1f = nullptr;
@@ -352,11 +426,28 @@ struct Layout {
 };
 
 // The mixed bulk runs its contraction as split BF16 when d allows
-// (SB_BULK_GEMM=f32 keeps the FP32 matrix-core kernel), two-stage for
-// mixtures (SB_MIX_TWO_STAGE=0 keeps one stage).
+// (SB_BULK_GEMM=f32 keeps the FP32 matrix-core kernel), for mixtures behind
+// the screen (SB_MIX_SCREEN=0: the unscreened two stages; SB_MIX_TWO_STAGE=0:
+// one stage over every component).
 static bool bulk_split(const sb_loglik *ll, const RunCfg &rc) {
   const char *bg = getenv("SB_BULK_GEMM");
   return rc.precision == SB_PREC_MIXED && quad_gemm_bf16_ok(ll->d) && !(bg && bg[0] == 'f');
+}
+// SB_TILE2=BMxBN[xBK[xSTAGES]] forces the screened contraction's tile.
+static TileCfg env_tile(const char *name, TileCfg t) {
+  const char *e = getenv(name);
+  int bm = 0, bn = 0, bk = 32, st = 1;
+  if (e && sscanf(e, "%dx%dx%dx%d", &bm, &bn, &bk, &st) >= 2) {
+    t.bm = bm;
+    t.bn = bn;
+    t.bk = bk;
+    t.stages = st;
+  }
+  return t;
+}
+static bool bulk_screen() {
+  const char *e = getenv("SB_MIX_SCREEN");
+  return !(e && e[0] == '0');
 }
 static bool bulk_two_stage(const sb_loglik *ll, const RunCfg &rc) {
   const char *ts = getenv("SB_MIX_TWO_STAGE");
@@ -383,7 +474,9 @@ static int carve_layout(Arena &ar, Layout &L, const sb_loglik *ll, const RunCfg 
     L.Plo = ar.take<bf16_t>((size_t)K * d * d);
     L.mu32 = ar.take<float>((size_t)K * d);
   }
-  if (bulk_two_stage(ll, rc)) {
+  if (bulk_two_stage(ll, rc) && bulk_screen()) {
+    L.rho = ar.take<double>(K);
+  } else if (bulk_two_stage(ll, rc)) {
     L.Uhi = ar.take<bf16_t>((size_t)K * d * d);
     L.Ulo = ar.take<bf16_t>((size_t)K * d * d);
   }
@@ -418,6 +511,7 @@ static int carve_layout(Arena &ar, Layout &L, const sb_loglik *ll, const RunCfg 
   L.bulk.m.d = d;
   L.bulk.m.K = K;
   L.bulk.two_stage = bulk_two_stage(ll, rc);
+  L.bulk.screen = L.bulk.two_stage && bulk_screen();
   if (L.bulk.carve(ar)) return SB_E_NOMEM;
   L.X0b = mixed ? (void *)ar.take<float>((size_t)B * d) : (void *)L.X0;
   L.Xend = ar.take<char>(bes * (size_t)B * d);
@@ -485,6 +579,9 @@ static int run_bulk(Layout &L, const RunCfg &rc, double tol, hipStream_t s,
   Evaluator &ev = L.bulk;
   int st = launch_lbfgs_init(lb, L.X0b, s);
   if (st) return st;
+  if (ev.screen) {  // no reference points yet: the first evaluation of every row takes all K
+    if ((st = launch_fill_i32(ev.nstate, 0, ev.hasref, s))) return st;
+  }
   const int d = lb.d;
   // initial evaluation of every start (slot 0, rows 0..B-1)
   ASrc a0;
@@ -668,6 +765,7 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     if ((st = launch_convert_model(m64, L.P32, L.Pbf, L.mu32, s))) return st;
     if ((st = launch_split_bf16((int64_t)K * d * d, P.prec, L.Pbf, L.Plo, s))) return st;
     if (L.Uhi && (st = launch_split_upper(K, d, L.Lprep, L.Uhi, L.Ulo, s))) return st;
+    if (L.rho && (st = launch_row_abs_max(K, d, P.prec, L.rho, s))) return st;
   }
   {
     int32_t hflag[1];
@@ -758,6 +856,7 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     L.bulk.gemm_dtype = split ? DT_F32S : -1;
     L.bulk.Uhi = L.Uhi;
     L.bulk.Ulo = L.Ulo;
+    L.bulk.rho = L.rho;
     {
       TuneProbe pr;  // timed on the start points and the bulk's own scratch
       pr.a.kind = 0;
@@ -767,7 +866,7 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
       pr.o.ldy = L.bulk.ldy;
       pr.o.qpart = L.bulk.qpart;
       L.bulk.tile = autotune_tiles(split ? DT_F32S : L.bulk.dtype, mb, rc.n_starts, s, &pr);
-      if (L.bulk.two_stage) {
+      if (L.bulk.two_stage && !L.bulk.screen) {
         // stage 1 timed in its own mode; stage 2 multiplies about one component's share
         // of the rows per component, where 128 x 128 tiles keep every CU busy
         Model m1 = mb;
@@ -778,6 +877,10 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
         p1.o.sumsq = true;
         L.bulk.tile1 = autotune_tiles(DT_F32S, m1, rc.n_starts, s, &p1);
         L.bulk.tile2 = TileCfg();
+      } else if (L.bulk.screen) {
+        // each component's list holds about its share of the rows: 128 x 128
+        // tiles spread the uneven lists over every CU (256 x 256 measured slower)
+        L.bulk.tile2 = env_tile("SB_TILE2", TileCfg());
       }
       L.bulk.grad_direct = split && K == 1 && P.family == SB_FAMILY_GAUSS_MIX;
     }

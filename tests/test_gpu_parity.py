@@ -416,6 +416,54 @@ def test_evidence_mixed_split_paths(L, name, d):
     _compare(r, ref, 1e-6)
 
 
+def _close_mixture(a):
+    """d = 64, K = 4, means uniform in [-a, a]^64: at a = 0.8 the closest pair is only
+    ~12 Mahalanobis units apart, so many bulk rows weigh several components."""
+    rng = np.random.Generator(np.random.PCG64(4242))
+    return synth.gaussian_mixture(rng, 64, 4, -a, a, 0.05, 1.0, 0.0, box_half=12.0,
+                                  norm=synth.NORM_DENSITY, linf_min=0.5)
+
+
+MIX_PATHS = {"one_stage": {"SB_MIX_TWO_STAGE": "0"},
+             "two_stage": {"SB_MIX_TWO_STAGE": "1", "SB_MIX_SCREEN": "0"},
+             "screened": {"SB_MIX_TWO_STAGE": "1", "SB_MIX_SCREEN": "1"}}
+
+
+def _run_path(L, prob, cfg, path):
+    import os
+
+    old = {k: os.environ.get(k) for k in ("SB_MIX_TWO_STAGE", "SB_MIX_SCREEN")}
+    os.environ.update(MIX_PATHS[path])
+    try:
+        return L.sb_evidence(prob, cfg)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("which", ["c1", "close"])
+def test_mixture_bulk_paths(L, which):
+    """The three mixed-precision mixture bulks (one stage over every component; two stages;
+    screened by bounds carried from each row's reference point) against the FP64 oracle.
+    The screen only drops components whose weight is below e^-120, so the screened bulk
+    follows the one-stage bulk's trajectory (the same split Y and q) up to rounding: equal
+    L-BFGS work within 2%."""
+    if which == "c1":
+        prob = synth.make_problem("c1")
+    else:
+        prob = _close_mixture(0.8)
+    cfg = synth.make_run_config("c1", n_starts=256, precision=1)
+    ref = O.evidence(prob, synth.make_run_config("c1", n_starts=256, precision=0))
+    rs = {p: _run_path(L, prob, cfg, p) for p in MIX_PATHS}
+    for p, r in rs.items():
+        _compare(r, ref, 1e-6)
+    e1, es = rs["one_stage"].n_grad_evals, rs["screened"].n_grad_evals
+    assert abs(es - e1) <= 0.02 * e1, (e1, es, rs["two_stage"].n_grad_evals)
+
+
 @pytest.mark.parametrize("prec", [0, 1])  # 1: mixed (component lists built with atomics)
 def test_evidence_device_entry_and_determinism(L, prec):
     prob, cfg = synth.make_workload("c1", n_starts=256, precision=prec)
