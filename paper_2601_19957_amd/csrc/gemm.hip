@@ -1054,6 +1054,92 @@ __global__ __launch_bounds__(256) void row_abs_max_kernel(int K, int d, const do
     atomicMax((unsigned long long *)&rho[r / d], (unsigned long long)__double_as_longlong(t));
 }
 
+// Power steps, batched over the K matrices: w = P v (one wave per row), then
+// theta = v . w, v = w / |w| (one workgroup per matrix).
+__global__ __launch_bounds__(256) void pw_gemv_kernel(int K, int d, const double *P,
+                                                      const double *v, double *w) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= (int64_t)K * d) return;
+  const int64_t k = r / d;
+  const double *p = P + r * d, *vk = v + k * d;
+  double t = 0.0;
+  for (int j = lane; j < d; j += 64) t += p[j] * vk[j];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o, 64);
+  if (lane == 0) w[r] = t;
+}
+
+__global__ __launch_bounds__(256) void pw_norm_kernel(int d, double *v, const double *w,
+                                                      double *theta, int init) {
+  const int k = blockIdx.x;
+  double *vk = v + (int64_t)k * d;
+  const double *wk = w + (int64_t)k * d;
+  __shared__ double red[2][256];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < d; i += 256) {
+    const double x = init ? 1.0 : wk[i];
+    a += x * x;
+    b += init ? 0.0 : vk[i] * wk[i];
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] += red[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  const double inv = 1.0 / sqrt(red[0][0]);
+  if (threadIdx.x == 0) theta[k] = red[1][0];
+  for (int i = threadIdx.x; i < d; i += 256) vk[i] = (init ? 1.0 : wk[i]) * inv;
+}
+
+// A_k = 1.25 theta_k I - P_k
+__global__ void pw_shift_kernel(int K, int d, const double *P, const double *theta, double *A) {
+  const int64_t n = (int64_t)K * d * d;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = i / ((int64_t)d * d), rc = i % ((int64_t)d * d);
+    const int r = (int)(rc / d), c = (int)(rc % d);
+    A[i] = (r == c ? 1.25 * theta[k] : 0.0) - P[i];
+  }
+}
+
+__global__ void pw_pick_kernel(int K, const double *theta, const int32_t *info, double *rho) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const double tau = 1.25 * theta[k] * (1.0 + 0x1p-20);
+  if (info[k] == 0 && tau > 0.0 && tau < rho[k]) rho[k] = tau;
+}
+
+int launch_lmax_bound(int K, int d, const double *P, double *rho, double *work, double *A,
+                      int32_t *info, hipStream_t s) {
+  if (K <= 0 || d <= 0) return SB_OK;
+  double *v = work, *w = work + (int64_t)K * d, *theta = work + 2 * (int64_t)K * d;
+  hipLaunchKernelGGL(pw_norm_kernel, dim3((unsigned)K), dim3(256), 0, s, d, v, w, theta, 1);
+  SB_LAUNCH_CHECK();
+  for (int it = 0; it < 16; ++it) {
+    hipLaunchKernelGGL(pw_gemv_kernel, dim3((unsigned)ceil_div((int64_t)K * d, 4)), dim3(256), 0,
+                       s, K, d, P, v, w);
+    SB_LAUNCH_CHECK();
+    hipLaunchKernelGGL(pw_norm_kernel, dim3((unsigned)K), dim3(256), 0, s, d, v, w, theta, 0);
+    SB_LAUNCH_CHECK();
+  }
+  const int64_t n = (int64_t)K * d * d;
+  hipLaunchKernelGGL(pw_shift_kernel, dim3((unsigned)std::min<int64_t>(8192, ceil_div(n, 256))),
+                     dim3(256), 0, s, K, d, P, theta, A);
+  SB_LAUNCH_CHECK();
+  int st = chol_batched(K, d, A, A, info, s);
+  if (st) return st;
+  hipLaunchKernelGGL(pw_pick_kernel, dim3((unsigned)ceil_div(K, 64)), dim3(64), 0, s, K, theta,
+                     info, rho);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
 int launch_row_abs_max(int K, int d, const double *P, double *rho, hipStream_t s) {
   if (K <= 0 || d <= 0) return SB_OK;
   int st = launch_fill_i32(2 * (int64_t)K, 0, (int32_t *)rho, s);

@@ -202,6 +202,14 @@ int launch_mixture_screen(const Model &m, const ScreenArgs &a, hipStream_t s);
 int launch_mixture_post(const Model &m, const ScreenArgs &a, hipStream_t s);
 // rho[k] = max_i sum_j |P_k[i][j]| (FP64 P [K][d][d]); rho is zeroed first.
 int launch_row_abs_max(int K, int d, const double *P, double *rho, hipStream_t s);
+// Tightens rho[k] (an upper bound of P_k's largest eigenvalue) to
+// min(rho[k], tau_k (1 + 2^-20)) where tau_k = 1.25 theta_k, theta_k the
+// Rayleigh quotient after 16 power steps, whenever the Cholesky factorisation
+// of tau_k I - P_k succeeds (which certifies tau_k above every eigenvalue up
+// to the factorisation's backward error).  work: 2 K d + K doubles; A: K d^2
+// doubles of scratch; info: K ints.
+int launch_lmax_bound(int K, int d, const double *P, double *rho, double *work, double *A,
+                      int32_t *info, hipStream_t s);
 
 struct HvpArgs {
   int64_t M = 0;

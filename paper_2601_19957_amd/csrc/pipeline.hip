@@ -395,7 +395,9 @@ struct Layout {
   float *P32 = nullptr, *mu32 = nullptr;
   bf16_t *Pbf = nullptr, *Plo = nullptr;
   bf16_t *Uhi = nullptr, *Ulo = nullptr;  // split U_k = L_k^T (two-stage mixture bulk)
-  double *rho = nullptr;                  // [K] largest absolute row sum of P_k (screen)
+  double *rho = nullptr;     // [K] bound of P_k's largest eigenvalue (screen)
+  double *pw = nullptr;      // [2 K d + K] power steps
+  int32_t *cinfo = nullptr;  // [K] certifying factorisations
   // discovery
   double *P0 = nullptr, *P1 = nullptr, *best_l = nullptr, *X0 = nullptr;
   float *P0f = nullptr, *P1f = nullptr;
@@ -476,6 +478,8 @@ static int carve_layout(Arena &ar, Layout &L, const sb_loglik *ll, const RunCfg 
   }
   if (bulk_two_stage(ll, rc) && bulk_screen()) {
     L.rho = ar.take<double>(K);
+    L.pw = ar.take<double>((size_t)2 * K * d + K);
+    L.cinfo = ar.take<int32_t>(K);
   } else if (bulk_two_stage(ll, rc)) {
     L.Uhi = ar.take<bf16_t>((size_t)K * d * d);
     L.Ulo = ar.take<bf16_t>((size_t)K * d * d);
@@ -765,7 +769,16 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     if ((st = launch_convert_model(m64, L.P32, L.Pbf, L.mu32, s))) return st;
     if ((st = launch_split_bf16((int64_t)K * d * d, P.prec, L.Pbf, L.Plo, s))) return st;
     if (L.Uhi && (st = launch_split_upper(K, d, L.Lprep, L.Uhi, L.Ulo, s))) return st;
-    if (L.rho && (st = launch_row_abs_max(K, d, P.prec, L.rho, s))) return st;
+    if (L.rho) {
+      // sigma_k^2: the Gershgorin bound, tightened by a certified power
+      // estimate where the polish's Hessian scratch holds the K shifted
+      // matrices (SB_LMAX=0: Gershgorin only)
+      if ((st = launch_row_abs_max(K, d, P.prec, L.rho, s))) return st;
+      const char *e = getenv("SB_LMAX");
+      if (rc.polish_chunk >= K && !(e && e[0] == '0') &&
+          (st = launch_lmax_bound(K, d, P.prec, L.rho, L.pw, L.H, L.cinfo, s)))
+        return st;
+    }
   }
   {
     int32_t hflag[1];
