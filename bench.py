@@ -12,9 +12,11 @@ mixture, 16384 rays x 32 points and 16384 starts each.  Inputs are resident
 in HBM when the timed region starts (sb_evidence_dev); the value is the
 number of logL+grad evaluations performed per second of wall time.
 
-Also reported: the roofline of the dominant kernel (the FP32 quadratic-form
-GEMM of the L-BFGS bulk at the mixture's shape, HIP events on its stream)
-and the CPU oracle timed on the host on a bounded sample of the workload.
+Also reported: the roofline of the dominant kernel of the step, the batched
+L-BFGS step of the FP32 bulk (HBM-bound; its launches timed with HIP events
+on their stream at full batch), the roofline of the bulk's split-BF16
+contraction at the mixture's shape (matrix cores), and the CPU oracle timed
+on the host on a bounded sample of the workload.
 """
 from __future__ import annotations
 
@@ -154,8 +156,9 @@ def cpu_model() -> str:
 
 def recorded_lbfgs(summary="profiles/lbfgs_step_B16384_d1024_m8.md",
                    source="paper_2601_19957_amd/csrc/lbfgs.hip"):
-    """HBM roofline of the L-BFGS step at full batch (16384 starts, d = 1024, m = 8) from the
-    committed rocprofv3 trace and counter summary, or None when the kernel source changed."""
+    """HBM bytes per full-batch L-BFGS step launch (16384 starts, d = 1024, m = 8) and the
+    plain-copy rate from the committed rocprofv3 counter summary, or None when the kernel
+    source changed since the counters were taken."""
     import hashlib
     import re
 
@@ -168,18 +171,54 @@ def recorded_lbfgs(summary="profiles/lbfgs_step_B16384_d1024_m8.md",
     if not m_h or m_h.group(1) != sha:
         return None
     val = {}
-    for key in ("lbfgs_full_batch_avg_us", "lbfgs_traffic_bytes_per_launch",
-                "lbfgs_algorithmic_bytes_per_launch", "copy_tbps"):
+    for key in ("lbfgs_traffic_bytes_per_launch", "copy_tbps"):
         m_v = re.search(key + r":\s*([0-9.eE+]+)", txt)
         if not m_v:
             return None
         val[key] = float(m_v.group(1))
-    achieved = val["lbfgs_traffic_bytes_per_launch"] / val["lbfgs_full_batch_avg_us"] / 1e3
-    return dict(bound="hbm", achieved=achieved, peak=PEAK["hbm"], unit="GB/s",
-                frac=achieved / PEAK["hbm"], traffic=val["lbfgs_traffic_bytes_per_launch"],
-                algorithmic_bytes=val["lbfgs_algorithmic_bytes_per_launch"],
-                avg_launch_us=val["lbfgs_full_batch_avg_us"],
-                copy_GBps=val["copy_tbps"] * 1e3, source=summary)
+    return val
+
+
+def time_lbfgs_step(L, prob, cfg, n_timed=40):
+    """The L-BFGS step (A4) as the mixed bulk runs it (FP32, one workgroup per start) at full
+    batch: sb_lbfgs_timed_dev from the BF16 discovery starts, HIP events around each step
+    launch on its stream.  Averaged over the launches in which every start either accepted its
+    trial with its history ring full or halved its step (at least 99% accepting); an accepting
+    start moves (2m + 6) d 4 bytes (the history pairs but the evicted one read, or all m when
+    the curvature test keeps the new pair out and it is not written; x and g read at both
+    slots; s, y, direction and trial point written), a halving one 3 d 4 bytes (point and
+    direction read, trial point written)."""
+    import numpy as np
+
+    mdl = L.DeviceModel(prob, low_precision=True)
+    disc = L.sb_discover_dev(mdl, cfg.n_rays, cfg.n_points, cfg.n_starts, cfg.seed,
+                             dtype=L.DTYPE_BF16)
+    X0 = disc["X0"].float()
+    B, d = X0.shape
+    r = L.sb_lbfgs_timed_dev(mdl, X0, m=cfg.m, max_iter=n_timed + 8, n_timed=n_timed)
+    full, back = r["step_full"].astype(np.int64), r["step_back"].astype(np.int64)
+    sel = [i for i in range(n_timed) if int(r["step_rows"][i]) == B and full[i] + back[i] == B
+           and full[i] >= 0.99 * B]
+    if not sel:
+        return None
+    us = r["step_us"][sel].astype(np.float64)
+    per_launch = ((2 * cfg.m + 6) * full[sel] + 3 * back[sel]) * d * 4.0
+    alg = float(per_launch.mean())
+    avg_us = float(us.mean())
+    achieved = alg / avg_us / 1e3  # GB/s
+    rec = recorded_lbfgs() if (d, cfg.m, B) == (1024, 8, 16384) else None
+    out = dict(bound="hbm", achieved=achieved, peak=PEAK["hbm"], unit="GB/s",
+               frac=achieved / PEAK["hbm"],
+               traffic=rec["lbfgs_traffic_bytes_per_launch"] if rec else None,
+               kernel="lbfgs_step_kernel<float,256,4> (A4 batched L-BFGS step, FP32 bulk)",
+               shape=f"B={B} d={d} m={cfg.m}", algorithmic_bytes=alg, avg_launch_us=avg_us,
+               launches=len(sel), launch_us_range=[float(us.min()), float(us.max())],
+               timed_steps=[int(i) for i in sel],
+               halving_starts=[int(back[i]) for i in sel])
+    if rec:
+        out["copy_GBps"] = rec["copy_tbps"] * 1e3
+        out["frac_of_copy"] = achieved / out["copy_GBps"]
+    return out
 
 
 def calibration_copy() -> int:
@@ -312,24 +351,29 @@ def main() -> int:
     big = names[-1]
     prob_big, cfg_big = wl[big]
 
-    # ---- roofline kernel: the bulk contraction (split BF16) at the largest posterior's shape
+    # ---- roofline of the dominant kernel: the L-BFGS step at full batch
+    log("timing the L-BFGS step at full batch")
+    roofline = time_lbfgs_step(L, prob_big, cfg_big)
+
+    # ---- the bulk contraction (split BF16) at the largest posterior's shape
     log("timing the A3 contraction (split BF16) at the bulk shape")
     kt_s, kflops = time_quadform(L, prob_big, cfg_big.n_starts)
     kt32_s, _ = time_quadform(L, prob_big, cfg_big.n_starts, reps=5, dtype=L.DTYPE_F32)
     traffic = recorded_traffic() if (prob_big.d, prob_big.K, cfg_big.n_starts) == (1024, 8, 16384) \
         else None
     achieved = kflops / kt_s / 1e12
-    roofline = dict(bound="mfma", achieved=achieved, peak=PEAK["bf16"], unit="TFLOP/s",
-                    frac=achieved / PEAK["bf16"], traffic=traffic,
-                    kernel="quad_gemm_bf16_kernel<3,0,...> (A3 contraction, FP32 data as "
-                           "split BF16: 3 MFMA products per multiply-add)",
-                    shape=f"B={cfg_big.n_starts} d={prob_big.d} K={prob_big.K}",
-                    avg_launch_us=kt_s * 1e6,
-                    executed_mfma_frac=3.0 * achieved / PEAK["bf16"],
-                    fp32_equivalent_frac=achieved / PEAK["fp32"],
-                    fp32_kernel_us=kt32_s * 1e6)
+    contraction = dict(bound="mfma", achieved=achieved, peak=PEAK["bf16"], unit="TFLOP/s",
+                       frac=achieved / PEAK["bf16"], traffic=traffic,
+                       kernel="quad_gemm_bf16_kernel<3,0,...> (A3 contraction, FP32 data as "
+                              "split BF16: 3 MFMA products per multiply-add)",
+                       shape=f"B={cfg_big.n_starts} d={prob_big.d} K={prob_big.K}",
+                       avg_launch_us=kt_s * 1e6,
+                       executed_mfma_frac=3.0 * achieved / PEAK["bf16"],
+                       fp32_equivalent_frac=achieved / PEAK["fp32"],
+                       fp32_kernel_us=kt32_s * 1e6)
     if args.kernel_only:
         print(json.dumps(dict(kernel_only=True, roofline=roofline,
+                              contraction_roofline=contraction,
                               copy_calibration_bytes=calibration_copy())), flush=True)
         return 0
 
@@ -464,7 +508,7 @@ def main() -> int:
         "uneven_batch": batch,
         "a3_variants": a3,
         "roofline": roofline,
-        "lbfgs_step_roofline": recorded_lbfgs(),
+        "contraction_roofline": contraction,
         "cpu_baseline": cpu,
     }
     if args.calibrate_copy:

@@ -235,6 +235,25 @@ int32_t sb_lbfgs_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m, int
                      int32_t *iters, int64_t *n_evals, void *workspace, size_t ws_bytes,
                      void *stream);
 
+/* sb_lbfgs_dev with per-launch timing of the L-BFGS step (step A4), for
+ * measuring that kernel against the HBM roofline.  Same arguments and
+ * results, plus: for each of the first n_timed batch steps, step_us [n_timed]
+ * (host) gets the duration of the step kernel's launch in microseconds, from
+ * HIP events recorded on `stream` around it, step_rows [n_timed] (host) the
+ * number of starts active when it began (B for the first step), step_full
+ * [n_timed] (host) the number of starts that accepted their trial point in it
+ * and end it active with a full history ring (each read and wrote the same
+ * (2m + 6) d-vectors), and step_back [n_timed] (host) the number that halved
+ * their step instead (each read two d-vectors and wrote one).  Entries past
+ * the last step are 0.  The host synchronises after every timed step.
+ * SB_E_INVAL if n_timed < 0 or, with n_timed > 0, a timing array is NULL. */
+int32_t sb_lbfgs_timed_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m,
+                           int32_t max_iter, double grad_tol, int32_t dtype, void *logl,
+                           void *grad, int32_t *status, int32_t *iters, int64_t *n_evals,
+                           void *workspace, size_t ws_bytes, void *stream, int32_t n_timed,
+                           float *step_us, int32_t *step_rows, int32_t *step_full,
+                           int32_t *step_back);
+
 /* L-infinity leader de-duplication (step A7): candidates X [C][d] (FP64 or
  * FP32 per dtype) with values l [C] (same dtype) and valid [C] (nullable,
  * nonzero = candidate).  Visiting order l descending, ties lower index;

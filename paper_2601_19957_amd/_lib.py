@@ -32,6 +32,7 @@ EXPORTS = [
     "sb_prep_workspace_bytes", "sb_prep_dev", "sb_logl_grad_workspace_bytes", "sb_logl_grad_dev",
     "sb_quadform_dev", "sb_split_bf16_dev", "sb_hvp_workspace_bytes", "sb_hvp_dev", "sb_discover_workspace_bytes", "sb_discover_dev",
     "sb_lbfgs_direction_dev", "sb_lbfgs_workspace_bytes", "sb_lbfgs_dev",
+    "sb_lbfgs_timed_dev",
     "sb_dedup_workspace_bytes", "sb_dedup_dev", "sb_hessian_workspace_bytes", "sb_hessian_dev",
     "sb_cholesky_logdet_dev", "sb_cholesky_solve_dev", "sb_combine_dev", "sb_status_string",
     "sb_last_error", "sb_abi_version",
@@ -111,6 +112,8 @@ def lib():
             "sb_lbfgs_workspace_bytes": (sz, [i32, i32, i64, i32, i32]),
             "sb_lbfgs_dev": (i32, [vp, i64, vp, i32, i32, f64, i32, vp, vp, vp, vp, vp, vp, sz,
                                    vp]),
+            "sb_lbfgs_timed_dev": (i32, [vp, i64, vp, i32, i32, f64, i32, vp, vp, vp, vp, vp,
+                                         vp, sz, vp, i32, vp, vp, vp, vp]),
             "sb_dedup_workspace_bytes": (sz, [i32]),
             "sb_dedup_dev": (i32, [i32, i32, vp, vp, vp, f64, i32, vp, vp, i32, vp, vp, sz, vp]),
             "sb_hessian_workspace_bytes": (sz, [i32, i32, i32]),
@@ -435,6 +438,38 @@ def sb_lbfgs_dev(model: DeviceModel, X0, m: int = 8, max_iter: int = 0, grad_tol
                             ws.data_ptr(), ws.numel(), _stream())
     _check(st, "sb_lbfgs_dev")
     return dict(x=X, logl=l, grad=g, status=status, iters=iters, n_evals=nev.value)
+
+
+def sb_lbfgs_timed_dev(model: DeviceModel, X0, m: int = 8, max_iter: int = 0,
+                       grad_tol: float = 0.0, n_timed: int = 32):
+    """sb_lbfgs_dev plus, for each of the first n_timed L-BFGS step launches, its duration
+    (us), the number of starts active when it began, the number that accepted their trial and
+    hold a full history ring after it, and the number that halved their step in it."""
+    import torch
+
+    dt = DTYPE_F64 if X0.dtype == torch.float64 else DTYPE_F32
+    X = X0.clone().contiguous()
+    B, d = X.shape
+    l = torch.empty(B, dtype=X.dtype, device=X.device)
+    g = torch.empty_like(X)
+    status = torch.empty(B, dtype=torch.int32, device=X.device)
+    iters = torch.empty(B, dtype=torch.int32, device=X.device)
+    nev = C.c_int64()
+    us = np.zeros(max(n_timed, 1), dtype=np.float32)
+    rows = np.zeros(max(n_timed, 1), dtype=np.int32)
+    full = np.zeros(max(n_timed, 1), dtype=np.int32)
+    back = np.zeros(max(n_timed, 1), dtype=np.int32)
+    ws = _ws(lib().sb_lbfgs_workspace_bytes(d, model.K, B, m, dt), X.device)
+    mv = model.view(dt)
+    st = lib().sb_lbfgs_timed_dev(C.byref(mv), B, X.data_ptr(), m, max_iter, grad_tol, dt,
+                                  l.data_ptr(), g.data_ptr(), status.data_ptr(), iters.data_ptr(),
+                                  C.byref(nev), ws.data_ptr(), ws.numel(), _stream(), n_timed,
+                                  us.ctypes.data, rows.ctypes.data, full.ctypes.data,
+                                  back.ctypes.data)
+    _check(st, "sb_lbfgs_timed_dev")
+    return dict(x=X, logl=l, grad=g, status=status, iters=iters, n_evals=nev.value,
+                step_us=us[:n_timed], step_rows=rows[:n_timed], step_full=full[:n_timed],
+                step_back=back[:n_timed])
 
 
 def sb_dedup_dev(X, l, tau: float, valid=None, max_reps: int = 1024):

@@ -584,24 +584,30 @@ int32_t sb_discover_dev(const sb_model_dev *mdl, const double *lo, const double 
   if ((st = launch_rays(d, lo, hi, R, seed, 0u, p0, p1, bf ? p0f : nullptr, bf ? p1f : nullptr,
                         s)))
     return st;
-  ASrc a;
-  a.kind = 1;
-  a.P0 = bf ? (const void *)p0f : (const void *)p0;
-  a.P1 = bf ? (const void *)p1f : (const void *)p1;
-  a.n_pts = n_pts;
-  QuadOut o;
-  o.Y = nullptr;
-  o.ldy = (int64_t)m.K * d;
-  o.qpart = qp;
-  const TuneProbe pr{a, o};
-  TileCfg t = autotune_tiles(dtype, m, NP, s, &pr);
-  if ((st = launch_quad_gemm(dtype, m, a, NP, nullptr, o, t, s))) return st;
-  FinishArgs f;
-  f.M = NP;
-  f.qpart = qp;
-  f.ntn = o.ntn;
-  f.logl = lpts;
-  if ((st = launch_finish(bf ? SB_DTYPE_F32 : SB_DTYPE_F64, m, f, s))) return st;
+  if (bf && n_pts > 3 && quad_gemm_bf16_ok(d)) {
+    // BF16: the contraction at three nodes per ray, the samples by interpolation
+    if ((st = discover_bf16_nodes(m, p0f, p1f, R, n_pts, (float *)qp, (float *)lpts, s)))
+      return st;
+  } else {
+    ASrc a;
+    a.kind = 1;
+    a.P0 = bf ? (const void *)p0f : (const void *)p0;
+    a.P1 = bf ? (const void *)p1f : (const void *)p1;
+    a.n_pts = n_pts;
+    QuadOut o;
+    o.Y = nullptr;
+    o.ldy = (int64_t)m.K * d;
+    o.qpart = qp;
+    const TuneProbe pr{a, o};
+    TileCfg t = autotune_tiles(dtype, m, NP, s, &pr);
+    if ((st = launch_quad_gemm(dtype, m, a, NP, nullptr, o, t, s))) return st;
+    FinishArgs f;
+    f.M = NP;
+    f.qpart = qp;
+    f.ntn = o.ntn;
+    f.logl = lpts;
+    if ((st = launch_finish(bf ? SB_DTYPE_F32 : SB_DTYPE_F64, m, f, s))) return st;
+  }
   if ((st = launch_ray_argmax(R, n_pts, bf ? SB_DTYPE_F32 : SB_DTYPE_F64, lpts, ray_best_l,
                               ray_best_j, s)))
     return st;
@@ -630,10 +636,14 @@ size_t sb_lbfgs_workspace_bytes(int32_t d, int32_t K, int64_t B, int32_t m, int3
   return lbfgs_state_bytes(dt, B, d, m) + eval_bytes(dt, d, K, B, false) + 4096;
 }
 
-int32_t sb_lbfgs_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m, int32_t max_iter,
-                     double grad_tol, int32_t dtype, void *logl, void *grad, int32_t *status,
-                     int32_t *iters, int64_t *n_evals, void *workspace, size_t ws_bytes,
-                     void *stream) {
+// The loop of sb_lbfgs_dev; with n_timed > 0 it records HIP events around
+// each of the first n_timed step launches and synchronises after each step.
+static int32_t lbfgs_run(const sb_model_dev *mdl, int64_t B, void *X, int32_t m,
+                         int32_t max_iter, double grad_tol, int32_t dtype, void *logl,
+                         void *grad, int32_t *status, int32_t *iters, int64_t *n_evals,
+                         void *workspace, size_t ws_bytes, void *stream, int32_t n_timed,
+                         float *step_us, int32_t *step_rows, int32_t *step_full,
+                         int32_t *step_back) {
   int st = validate_model(mdl);
   if (st) return st;
   if (B < 1 || !X) return fail(SB_E_INVAL, "bad B / X");
@@ -698,22 +708,93 @@ int32_t sb_lbfgs_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m, int
   const int mi = max_iter > 0 ? max_iter : 10 * d + 200;
   const double tol = grad_tol > 0 ? grad_tol : 1e-10;
   int32_t hcount = 1;
-  for (int64_t step = 0; step < 42ll * mi + 64 && hcount > 0; ++step) {
-    if ((st = launch_lbfgs_step(lb, mi, tol, s))) return st;
-    if ((st = launch_compact(lb, s))) return st;
-    if ((st = eval(lb.idx, lb.count))) return st;
-    if ((step & 7) == 7) {
-      if (hipMemcpyAsync(&hcount, lb.count, 4, hipMemcpyDeviceToHost, s) ||
-          hipStreamSynchronize(s))
-        return fail(SB_E_DEVICE, "count readback failed");
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  std::vector<int32_t> h_st, h_ls, h_cnt;
+  if (n_timed > 0) {
+    for (int i = 0; i < n_timed; ++i) {
+      step_us[i] = 0.f;
+      step_rows[i] = 0;
+      step_full[i] = step_back[i] = 0;
+    }
+    h_st.resize(B);
+    h_ls.resize(B);
+    h_cnt.resize(B);
+    if (hipEventCreate(&ev[0]) || hipEventCreate(&ev[1])) {
+      if (ev[0]) hipEventDestroy(ev[0]);
+      return fail(SB_E_DEVICE, "event creation failed");
     }
   }
+  int32_t rows = (int32_t)B;  // starts active entering the next step
+  for (int64_t step = 0; step < 42ll * mi + 64 && hcount > 0; ++step) {
+    const bool timed = step < n_timed;
+    if (timed && hipEventRecord(ev[0], s)) st = fail(SB_E_DEVICE, "event record failed");
+    if (!st) st = launch_lbfgs_step(lb, mi, tol, s);
+    if (!st && timed && hipEventRecord(ev[1], s)) st = fail(SB_E_DEVICE, "event record failed");
+    if (!st) st = launch_compact(lb, s);
+    if (!st) st = eval(lb.idx, lb.count);
+    if (!st && timed) {
+      float ms = 0.f;
+      if (hipMemcpyAsync(&hcount, lb.count, 4, hipMemcpyDeviceToHost, s) ||
+          hipStreamSynchronize(s) || hipEventElapsedTime(&ms, ev[0], ev[1]))
+        st = fail(SB_E_DEVICE, "step timing readback failed");
+      step_us[step] = 1e3f * ms;
+      step_rows[step] = rows;
+      // after the step: starts that accepted their trial and hold a full
+      // history ring, and starts that halved their step (still active)
+      if (!st && rows > 0) {
+        if (hipMemcpy(h_st.data(), lb.status, 4 * B, hipMemcpyDeviceToHost) ||
+            hipMemcpy(h_ls.data(), lb.ls, 4 * B, hipMemcpyDeviceToHost) ||
+            hipMemcpy(h_cnt.data(), lb.cnt, 4 * B, hipMemcpyDeviceToHost))
+          st = fail(SB_E_DEVICE, "step state readback failed");
+        int32_t nf = 0, nb = 0;
+        for (int64_t i = 0; !st && i < B; ++i) {
+          if (h_st[i] != 0) continue;
+          if (h_ls[i] > 0)
+            ++nb;
+          else if (h_cnt[i] == m)
+            ++nf;
+        }
+        step_full[step] = nf;
+        step_back[step] = nb;
+      }
+      rows = hcount;
+    } else if (!st && (step & 7) == 7) {
+      if (hipMemcpyAsync(&hcount, lb.count, 4, hipMemcpyDeviceToHost, s) ||
+          hipStreamSynchronize(s))
+        st = fail(SB_E_DEVICE, "count readback failed");
+    }
+    if (st) break;
+  }
+  if (ev[0]) hipEventDestroy(ev[0]);
+  if (ev[1]) hipEventDestroy(ev[1]);
+  if (st) return st;
   if ((st = launch_lbfgs_gather(lb, X, logl, false, grad, status, iters, s))) return st;
   if (n_evals) {
     if (hipMemcpyAsync(n_evals, lb.evals, 8, hipMemcpyDeviceToHost, s) || hipStreamSynchronize(s))
       return fail(SB_E_DEVICE, "eval count readback failed");
   }
   return SB_OK;
+}
+
+int32_t sb_lbfgs_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m, int32_t max_iter,
+                     double grad_tol, int32_t dtype, void *logl, void *grad, int32_t *status,
+                     int32_t *iters, int64_t *n_evals, void *workspace, size_t ws_bytes,
+                     void *stream) {
+  return lbfgs_run(mdl, B, X, m, max_iter, grad_tol, dtype, logl, grad, status, iters, n_evals,
+                   workspace, ws_bytes, stream, 0, nullptr, nullptr, nullptr, nullptr);
+}
+
+int32_t sb_lbfgs_timed_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m,
+                           int32_t max_iter, double grad_tol, int32_t dtype, void *logl,
+                           void *grad, int32_t *status, int32_t *iters, int64_t *n_evals,
+                           void *workspace, size_t ws_bytes, void *stream, int32_t n_timed,
+                           float *step_us, int32_t *step_rows, int32_t *step_full,
+                           int32_t *step_back) {
+  if (n_timed < 0 || (n_timed > 0 && (!step_us || !step_rows || !step_full || !step_back)))
+    return fail(SB_E_INVAL, "n_timed must be >= 0 with the four timing arrays given");
+  return lbfgs_run(mdl, B, X, m, max_iter, grad_tol, dtype, logl, grad, status, iters, n_evals,
+                   workspace, ws_bytes, stream, n_timed, step_us, step_rows, step_full,
+                   step_back);
 }
 
 // ----------------------------------------------------------------- dedup

@@ -560,6 +560,11 @@ static int launch_t(const GemmParams &p, hipStream_t s) {
 
 int launch_quad_gemm(int dtype, const Model &m, const ASrc &a, int64_t M, const int32_t *count,
                      QuadOut &o, TileCfg t, hipStream_t s) {
+  if (a.kind == 1 && a.dt > 0.f &&
+      !((dtype == DT_F32S || dtype == DT_BF16) && quad_gemm_bf16_ok(m.d))) {
+    set_error("ray nodes need the BF16 matrix-core kernel (d = %d)", m.d);
+    return SB_E_UNSUPPORTED;
+  }
   // BF16 matrix-core kernel: split FP32 always when d allows (else plain
   // FP32), BF16 when d allows and the BF16 copy is given.
   if (dtype == DT_F32S && quad_gemm_bf16_ok(m.d))
@@ -1148,6 +1153,106 @@ int launch_row_abs_max(int K, int d, const double *P, double *rho, hipStream_t s
                      0, s, K, d, P, rho);
   SB_LAUNCH_CHECK();
   return SB_OK;
+}
+
+// Ray-point scores from three nodes per ray.  Along a ray the quadratic
+// form q_k(t) = (p + t (q - p) - mu_k)^T P_k (p + t (q - p) - mu_k) is a
+// polynomial of degree two in t, so its values at t = 0, 1/2, 1 fix it and
+// Lagrange interpolation gives q_k at every sample t_j = (j + 1/2) / n_pts
+// (weights at most 1.25 in absolute sum on [0, 1]: the node errors are not
+// amplified).  RB rays per workgroup: node sums into LDS, then one thread
+// per sample point for the family's l, in FP64 as in the row epilogue.
+constexpr int kNodeRays = 8;
+__global__ __launch_bounds__(256) void ray_nodes_finish_kernel(Model m, int64_t R, int n_pts,
+                                                               int ntn, const float *qpart,
+                                                               float *l) {
+  __shared__ double qn[kNodeRays][3][kMaxK];
+  const int K = m.K;
+  const int64_t r0 = (int64_t)blockIdx.x * kNodeRays;
+  for (int i = threadIdx.x; i < kNodeRays * 3 * K; i += blockDim.x) {
+    const int rb = i / (3 * K), node = (i / K) % 3, k = i % K;
+    const int64_t r = r0 + rb;
+    double q = 0.0;
+    if (r < R) {
+      const float *qp = qpart + ((size_t)(3 * r + node) * K + k) * ntn;
+      for (int t = 0; t < ntn; ++t) q += (double)qp[t];
+    }
+    qn[rb][node][k] = q;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kNodeRays * n_pts; i += blockDim.x) {
+    const int rb = i / n_pts, j = i % n_pts;
+    const int64_t r = r0 + rb;
+    if (r >= R) break;  // (later i only reach later rays)
+    const double t = ((double)j + 0.5) / (double)n_pts;
+    // Lagrange weights of the nodes 0, 1/2, 1
+    const double w0 = 2.0 * (t - 0.5) * (t - 1.0), w1 = -4.0 * t * (t - 1.0),
+                 w2 = 2.0 * t * (t - 0.5);
+    double out;
+    if (m.family == SB_FAMILY_STUDENT_T) {
+      const double q = w0 * qn[rb][0][0] + w1 * qn[rb][1][0] + w2 * qn[rb][2][0];
+      out = m.c + m.beta[0] - 0.5 * (m.nu + (double)m.d) * log1p(q / m.nu);
+    } else {
+      double a[kMaxK];
+      double mx = -INFINITY;
+#pragma unroll
+      for (int k = 0; k < kMaxK; ++k) {
+        if (k < K) {
+          const double q = w0 * qn[rb][0][k] + w1 * qn[rb][1][k] + w2 * qn[rb][2][k];
+          a[k] = m.beta[k] - 0.5 * q;
+          mx = fmax(mx, a[k]);
+        }
+      }
+      double lse = a[0];
+      if (K > 1) {
+        double ssum = 0.0;
+#pragma unroll
+        for (int k = 0; k < kMaxK; ++k)
+          if (k < K) ssum += exp(a[k] - mx);
+        lse = mx + log(ssum);
+      }
+      out = m.c + lse;
+    }
+    l[r * n_pts + j] = (float)out;
+  }
+}
+
+int launch_ray_nodes_finish(const Model &m, int64_t R, int n_pts, int ntn, const float *qpart,
+                            float *l, hipStream_t s) {
+  if (R <= 0) return SB_OK;
+  if (n_pts < 1 || ntn < 1 || m.K < 1 || m.K > kMaxK || !qpart || !l) {
+    set_error("ray nodes: bad arguments");
+    return SB_E_INVAL;
+  }
+  hipLaunchKernelGGL(ray_nodes_finish_kernel, dim3((unsigned)ceil_div(R, kNodeRays)), dim3(256),
+                     0, s, m, R, n_pts, ntn, qpart, l);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+int discover_bf16_nodes(const Model &m, const float *P0, const float *P1, int R, int n_pts,
+                        float *qpart, float *l, hipStream_t s) {
+  if (!quad_gemm_bf16_ok(m.d)) {
+    set_error("ray nodes need the BF16 matrix-core kernel (d = %d)", m.d);
+    return SB_E_UNSUPPORTED;
+  }
+  ASrc a;
+  a.kind = 1;
+  a.P0 = P0;
+  a.P1 = P1;
+  a.n_pts = 3;
+  a.t0 = 0.f;
+  a.dt = 0.5f;
+  QuadOut o;
+  o.Y = nullptr;
+  o.ldy = (int64_t)m.K * m.d;
+  o.qpart = qpart;
+  const int64_t M = 3ll * R;
+  const TuneProbe pr{a, o};
+  TileCfg t = autotune_tiles(DT_BF16, m, M, s, &pr);
+  int st = launch_quad_gemm(DT_BF16, m, a, M, nullptr, o, t, s);
+  if (st) return st;
+  return launch_ray_nodes_finish(m, R, n_pts, o.ntn, qpart, l, s);
 }
 
 int launch_finish(int dtype, const Model &m, const FinishArgs &f, hipStream_t s) {

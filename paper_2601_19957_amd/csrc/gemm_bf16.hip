@@ -189,7 +189,7 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
     } else {
       const int64_t ray = row / g.a.n_pts;
       const int jj = (int)(row % g.a.n_pts);
-      t = ((float)jj + 0.5f) / (float)g.a.n_pts;
+      t = g.a.dt > 0.f ? g.a.t0 + (float)jj * g.a.dt : ((float)jj + 0.5f) / (float)g.a.n_pts;
       off = (uint32_t)(ray * d);
     }
   };

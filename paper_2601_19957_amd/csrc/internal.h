@@ -85,6 +85,9 @@ struct ASrc {
   int64_t rows = 0;               // kind 0: rows of X (0: the GEMM's row count)
   const void *P0 = nullptr, *P1 = nullptr;  // kind 1: [R][d] endpoints, same type as X
   int n_pts = 1;
+  // kind 1: point jj of a ray at t = t0 + jj dt when dt > 0 (BF16 kernel
+  // only; three nodes of the ray-quadratic scores), else (jj + 1/2) / n_pts
+  float t0 = 0.f, dt = 0.f;
   bool zero_mu = false;           // A = X instead of X - mu_k
 };
 
@@ -242,6 +245,19 @@ int launch_chol_solve(int C, int n, const double *L, const double *b, double *x,
 // Rays / discovery.
 int launch_rays(int d, const double *lo, const double *hi, int R, uint64_t seed,
                 uint32_t problem, double *P0, double *P1, float *P0f, float *P1f, hipStream_t s);
+// Scores of R rays x n_pts sample points, t_j = (j + 1/2) / n_pts, from the
+// FP32 q partials of three nodes per ray (t = 0, 1/2, 1; qpart rows 3 r + i):
+// each q_k is a quadratic polynomial in t along a ray, so Lagrange
+// interpolation of the node values gives it at every sample; then the
+// family's l in FP64, written as FP32 l [R][n_pts].
+int launch_ray_nodes_finish(const Model &m, int64_t R, int n_pts, int ntn, const float *qpart,
+                            float *l, hipStream_t s);
+// BF16 discovery scores by the ray-quadratic shortcut: the BF16 contraction at
+// the three nodes of each ray (P0/P1 FP32 endpoints), then the interpolation.
+// qpart holds >= 3 R K ceil(d/64) floats, l R n_pts floats; the tile is
+// autotuned on these operands.  Needs quad_gemm_bf16_ok(d).
+int discover_bf16_nodes(const Model &m, const float *P0, const float *P1, int R, int n_pts,
+                        float *qpart, float *l, hipStream_t s);
 int launch_ray_argmax(int R, int n_pts, int dtype, const void *l, double *best_l, int32_t *best_j,
                       hipStream_t s);
 int launch_topn(int R, int n_starts, const double *best_l, int32_t *start_ray, hipStream_t s);

@@ -276,15 +276,18 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
     cnt = 0;
     head = 0;
   }
-  // history in logical order (loads issued before the reductions below)
+  // history in logical order (loads issued before the reductions below).
+  // With the ring full, the oldest pair is evicted when the curvature test
+  // passes, so its load waits for that test and happens only when it fails.
   T Sr[kMaxHist][EPT], Yr[kMaxHist][EPT], rh[kMaxHist], yyr[kMaxHist];
+  const bool defer_oldest = (mode == M_ACCEPT && cnt == m);
 #pragma unroll
   for (int j = 0; j < kMaxHist; ++j) {
     rh[j] = 0;
     yyr[j] = 0;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) Sr[j][e] = Yr[j][e] = 0;
-    if (mode == M_ACCEPT && j < cnt) {
+    if (mode == M_ACCEPT && j < cnt && !(j == 0 && defer_oldest)) {
       const int ph = (head - cnt + j + 2 * m) % m;
       const T *Sp = a.S + (size_t)m * vo + (size_t)ph * d;
       const T *Yp = a.Yh + (size_t)m * vo + (size_t)ph * d;
@@ -344,6 +347,12 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
       }
       head = (head + 1) % m;
       cnt = full ? m : cnt + 1;
+    } else if (defer_oldest) {
+      // pair kept out: the oldest pair (ring slot head) stays in the history
+      vload<T, EPT>(a.S + (size_t)m * vo + (size_t)head * d, i0, d, vec, Sr[0]);
+      vload<T, EPT>(a.Yh + (size_t)m * vo + (size_t)head * d, i0, d, vec, Yr[0]);
+      rh[0] = a.rho[(size_t)s * m + head];
+      yyr[0] = a.yy[(size_t)s * m + head];
     }
   }
 

@@ -820,7 +820,12 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
       md.Phi = L.Pbf;
     }
     L.disc.m = md;
-    {
+    if (mixed && rc.n_pts > 3 && quad_gemm_bf16_ok(d)) {
+      // the BF16 contraction at three nodes per ray, the samples by interpolation
+      if ((st = discover_bf16_nodes(md, L.P0f, L.P1f, rc.R, rc.n_pts, (float *)L.disc.qpart,
+                                    (float *)L.lpts, s)))
+        return st;
+    } else {
       ASrc a;
       a.kind = 1;
       a.P0 = mixed ? (const void *)L.P0f : (const void *)L.P0;

@@ -139,7 +139,7 @@ def test_split_every_tile_variant(L, forced_tile, d, B):
 
 @pytest.mark.parametrize("forced_tile", ["128x128x32", "128x256x32", "256x256x32", "128x128x32x2",
                                          "256x256x32x2"], indirect=True)
-@pytest.mark.parametrize("npts", [32, 6])  # 6: a thread's rows straddle rays
+@pytest.mark.parametrize("npts", [32, 6, 3])  # 6: rows straddle rays; 3: per-point path
 def test_bf16_discovery_every_tile_variant(L, forced_tile, npts):
     """BF16 ray-point contraction per tile variant: the best BF16 sample of each ray lies
     within the BF16 error bound of the ray's FP64 maximum."""
