@@ -98,6 +98,8 @@ def lib():
         L.or_dedup.argtypes = [i32, i32, vp, vp, vp, f64, vp, vp]
         L.or_log_volume.restype = f64
         L.or_log_volume.argtypes = [i32, vp, vp]
+        L.or_precheck.restype = i32
+        L.or_precheck.argtypes = [vp, vp, vp, vp, f64, f64, vp, vp, vp]
         L.or_mode_log_z.restype = f64
         L.or_mode_log_z.argtypes = [i32, f64, f64, f64]
         L.or_evidence.restype = i32
@@ -303,6 +305,19 @@ def log_volume(lo, hi) -> float:
     lo = _f64(lo)
     hi = _f64(hi)
     return lib().or_log_volume(lo.size, _p(lo), _p(hi))
+
+
+def precheck(prob, eps_flat=0.0, eps_soft=0.0, op: Optional[OracleProblem] = None):
+    """Preprocessing: sensitivities s, classes (0 active, 1 flat, 2 soft nuisance) and the
+    marginal log-evidence of the flagged coordinates."""
+    op = op or OracleProblem(prob)
+    d = prob.d
+    s = np.zeros(d)
+    cls = np.zeros(d, dtype=np.int32)
+    lz = C.c_double(np.nan)
+    st = lib().or_precheck(op.ptr, _p(op.beta()), _p(op.lo), _p(op.hi), eps_flat, eps_soft,
+                           _p(s), _p(cls), C.byref(lz))
+    return dict(status=st, s=s, cls=cls, logz_marginal=lz.value)
 
 
 def mode_log_z(d, logl_v, log_det_h, log_vol) -> float:

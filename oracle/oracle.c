@@ -698,6 +698,72 @@ double or_log_volume(int32_t d, const double *lo, const double *hi) {
 /* Laplace evidence of one mode with the uniform prior (appendix eq. for
  * log Z with log pi; prior density 1/V):
  *   log Z_k = l(theta*) - log V + (d/2) log 2 pi - (1/2) log det H. */
+/* ------------------------------------------------------- preprocessing */
+
+static int cmp_double(const void *A, const void *B) {
+  const double a = *(const double *)A, b = *(const double *)B;
+  return (a > b) - (a < b);
+}
+
+/* Section "Preprocessing: Dimensional Pathology Detection", in the order of
+ * its algorithm summary: the centre, l there, the two boundary probes of each
+ * coordinate, the median and maximum of the sensitivities, the two classes,
+ * the marginal log-evidence of the flagged coordinates. */
+int32_t or_precheck(const or_problem *p, const double *beta, const double *lo, const double *hi,
+                    double eps_flat, double eps_soft, double *s, int32_t *cls,
+                    double *logz_marginal) {
+  const int32_t d = p->d;
+  for (int32_t i = 0; i < d; ++i)
+    if (!(isfinite(lo[i]) && isfinite(hi[i]) && lo[i] < hi[i])) return OR_E_INVAL;
+  if (eps_flat <= 0.0) eps_flat = 1e-6;
+  if (eps_soft <= 0.0) eps_soft = 1e-3;
+  double *c = malloc(sizeof(double) * d), *x = malloc(sizeof(double) * d);
+  double *half = malloc(sizeof(double) * d), *sorted = malloc(sizeof(double) * d);
+  double *term = malloc(sizeof(double) * d);
+  int32_t st = OR_OK;
+  for (int32_t i = 0; i < d; ++i) {
+    c[i] = 0.5 * (lo[i] + hi[i]);
+    half[i] = 0.5 * (hi[i] - lo[i]);
+  }
+  double l0, lp, lm;
+  or_logl(p, beta, 1, c, &l0, NULL);
+  if (!isfinite(l0)) st = OR_E_INVAL;
+  for (int32_t i = 0; i < d && st == OR_OK; ++i) {
+    memcpy(x, c, sizeof(double) * d);
+    x[i] = c[i] + half[i];
+    or_logl(p, beta, 1, x, &lp, NULL);
+    x[i] = c[i] - half[i];
+    or_logl(p, beta, 1, x, &lm, NULL);
+    if (!isfinite(lp) || !isfinite(lm)) st = OR_E_INVAL;
+    s[i] = fabs(lp - l0) + fabs(lm - l0);
+  }
+  if (st == OR_OK) {
+    memcpy(sorted, s, sizeof(double) * d);
+    qsort(sorted, d, sizeof(double), cmp_double);
+    const double med = (d % 2) ? sorted[d / 2] : 0.5 * (sorted[d / 2 - 1] + sorted[d / 2]);
+    const double mx = sorted[d - 1];
+    for (int32_t i = 0; i < d; ++i) {
+      if (s[i] < eps_flat * med) {
+        cls[i] = 1;
+        term[i] = log(hi[i] - lo[i]);
+      } else if (s[i] < eps_soft * mx) {
+        cls[i] = 2;
+        term[i] = 0.5 * LOG_2PI + log(half[i] / sqrt(s[i]));
+      } else {
+        cls[i] = 0;
+        term[i] = 0.0;
+      }
+    }
+    *logz_marginal = or_pairwise_sum(term, d);
+  }
+  free(c);
+  free(x);
+  free(half);
+  free(sorted);
+  free(term);
+  return st;
+}
+
 double or_mode_log_z(int32_t d, double logl, double log_det_h, double log_volume) {
   return logl - log_volume + 0.5 * d * LOG_2PI - 0.5 * log_det_h;
 }

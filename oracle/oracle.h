@@ -126,6 +126,24 @@ int32_t or_dedup(int32_t C, int32_t d, const double *X, const double *l, const u
 
 /* ---- Laplace combine ---- */
 double or_log_volume(int32_t d, const double *lo, const double *hi);
+
+/* ---- preprocessing: dimensional pathology detection ---- */
+/* Section "Preprocessing: Dimensional Pathology Detection" (sensitivity
+ * equation, flat and soft-nuisance criteria, analytical marginalisation,
+ * algorithm summary).  Centre c_i = (a_i + b_i)/2, half-width
+ * D_i = (b_i - a_i)/2, s_i = |l(c + D_i e_i) - l(c)| + |l(c - D_i e_i) - l(c)|
+ * (2d + 1 evaluations).  cls[i] = 1 (flat) if s_i < eps_flat * median(s),
+ * else 2 (soft nuisance) if s_i < eps_soft * max(s), else 0 (active).
+ * *logz_marginal = sum over flat i of log(b_i - a_i) plus sum over soft i of
+ * 1/2 log 2 pi + log(D_i / sqrt(s_i)), summed pairwise in index order (zero
+ * for active i).  Readings: the median of an even count is the mean of the
+ * two middle values; a flat coordinate's term is the integral of a constant
+ * likelihood factor over its whole prior range, log(b_i - a_i) (the paper
+ * writes log D_i); eps <= 0 selects the paper's defaults 1e-6 and 1e-3.
+ * Returns OR_OK, or OR_E_INVAL for a bad box or a non-finite l at a probe. */
+int32_t or_precheck(const or_problem *p, const double *beta, const double *lo, const double *hi,
+                    double eps_flat, double eps_soft, double *s, int32_t *cls,
+                    double *logz_marginal);
 double or_mode_log_z(int32_t d, double logl, double log_det_h, double log_volume);
 
 /* ---- the whole path ---- */

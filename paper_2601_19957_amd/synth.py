@@ -180,6 +180,33 @@ def student_t(rng, d, nu, mu_lo, mu_hi, lam_lo, lam_hi, box_half, name="") -> Pr
                    0.0, np.full(d, -box_half), np.full(d, box_half), np.array([s]), name)
 
 
+def nuisance_gaussian(d: int, n_flat: int, n_soft: int, seed: int, box_half: float = 10.0,
+                      flat_scale: float = 1e6, soft_scale: float = 30.0,
+                      centred: bool = True) -> Problem:
+    """Peak-zero Gaussian with degenerate coordinates, for the preprocessing probe.
+
+    Coordinates 0..n_flat-1 have standard deviation flat_scale box half-widths (unconstrained
+    by the likelihood), the next n_soft soft_scale half-widths (weakly constrained); the others
+    form a dense correlated block with eigenvalues of Sigma log-uniform in [0.05, 1] (squared
+    half-widths).  The flagged coordinates are uncorrelated with the block.  The mean is the
+    box centre (centred) or uniform in the inner half of the box."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    na = d - n_flat - n_soft
+    if na < 1 or n_flat < 0 or n_soft < 0:
+        raise ValueError("need at least one constrained coordinate")
+    p = np.zeros((d, d))
+    nf = n_flat + n_soft
+    sig = np.concatenate([np.full(n_flat, flat_scale), np.full(n_soft, soft_scale)]) * box_half
+    p[np.arange(nf), np.arange(nf)] = 1.0 / sig ** 2
+    pa, sa = random_precision(rng, na, 0.05 * box_half ** 2, box_half ** 2)
+    p[nf:, nf:] = pa
+    mu = np.zeros((1, d)) if centred else rng.uniform(-0.5 * box_half, 0.5 * box_half, (1, d))
+    sll = sa + float(np.sum(2.0 * np.log(sig)))
+    return Problem(FAMILY_GAUSS_MIX, NORM_PEAK_ZERO, d, 1, np.zeros(1), mu, p[None], 0.0, 0.0,
+                   np.full(d, -box_half), np.full(d, box_half), np.array([sll]),
+                   f"nuisance_d{d}")
+
+
 # ------------------------------------------------------------- the workloads
 
 def c3_dimension(u: float) -> int:

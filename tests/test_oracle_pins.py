@@ -565,3 +565,116 @@ def test_validation(oracle_lib):
     t3.prec = np.concatenate([t.prec, t.prec])
     t3.log_w = np.zeros(2)
     assert O.evidence(t3, c).status == O.E_UNSUPPORTED
+
+
+# ------------------------------------------------------------ preprocessing
+
+def probe_points(lo, hi):
+    """The 2d + 1 probe points of the preprocessing: centre, then + and - half-width per axis."""
+    c, h = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    X = [c.copy()]
+    for i in range(c.size):
+        for sgn in (1.0, -1.0):
+            x = c.copy()
+            x[i] = c[i] + sgn * h[i]
+            X.append(x)
+    return np.array(X)
+
+
+def test_precheck_gaussian_sensitivity_closed_form(oracle_lib):
+    """For a Gaussian l = const - (x - mu)^T P (x - mu) / 2 the probe differences are
+    l(c +- D e_i) - l(c) = -(+-D g_i + D^2 P_ii / 2), g = P (c - mu): s_i in closed form."""
+    O = oracle_lib
+    for norm, seed in ((synth.NORM_PEAK_ZERO, 3), (synth.NORM_DENSITY, 4)):
+        rng = np.random.Generator(np.random.PCG64(seed))
+        prob = synth.gaussian_mixture(rng, 9, 1, -4.0, 4.0, 0.1, 1.0, 0.0, box_half=7.0,
+                                      norm=norm)
+        r = O.precheck(prob)
+        assert r["status"] == 0
+        P, mu = prob.prec[0], prob.mu[0]
+        c, D = 0.5 * (prob.lo + prob.hi), 0.5 * (prob.hi - prob.lo)
+        g = P @ (c - mu)
+        ref = np.abs(D * g + 0.5 * D ** 2 * np.diag(P)) + np.abs(-D * g + 0.5 * D ** 2 * np.diag(P))
+        assert np.allclose(r["s"], ref, rtol=1e-11, atol=0)
+
+
+def test_precheck_sensitivity_against_scipy(oracle_lib):
+    """s from library log-densities at the 2d + 1 probe points (mixture and Student-t)."""
+    O = oracle_lib
+    for prob in (small_mixture(d=5, K=3, seed=21), small_t(d=6, nu=4.0, seed=22)):
+        X = probe_points(prob.lo, prob.hi)
+        if prob.family == synth.FAMILY_STUDENT_T:
+            cov = np.linalg.inv(prob.prec[0])
+            l = st.multivariate_t(prob.mu[0], cov, df=prob.nu).logpdf(X)
+        else:
+            comp = [lw + st.multivariate_normal(m, np.linalg.inv(P)).logpdf(X)
+                    for lw, m, P in zip(prob.log_w, prob.mu, prob.prec)]
+            l = sps.logsumexp(np.array(comp), axis=0)
+        ref = np.abs(l[1::2] - l[0]) + np.abs(l[2::2] - l[0])
+        r = O.precheck(prob)
+        assert np.allclose(r["s"], ref, rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("d,n_flat,n_soft", [(12, 2, 3), (13, 1, 1), (40, 5, 4)])
+def test_precheck_classes_and_marginal_closed_form(oracle_lib, d, n_flat, n_soft):
+    """Centred Gaussian with unconstrained and weakly constrained coordinates: s_i = D^2 P_ii,
+    so the classes are the constructed ones and the soft width estimate D / sqrt(s_i) is exactly
+    1 / sqrt(P_ii); the marginal is sum_flat log(b - a) + sum_soft (log 2 pi / 2 + log sigma_i).
+    The classes also follow numpy's median and maximum of the same s."""
+    O = oracle_lib
+    prob = synth.nuisance_gaussian(d, n_flat, n_soft, seed=30 + d)
+    r = O.precheck(prob)
+    assert r["status"] == 0
+    D = 0.5 * (prob.hi - prob.lo)
+    Pd = np.diag(prob.prec[0])
+    assert np.allclose(r["s"], D ** 2 * Pd, rtol=1e-12)
+    want = np.zeros(d, dtype=np.int32)
+    want[:n_flat] = 1
+    want[n_flat:n_flat + n_soft] = 2
+    assert np.array_equal(r["cls"], want)
+    s = r["s"]
+    by_np = np.where(s < 1e-6 * np.median(s), 1, np.where(s < 1e-3 * np.max(s), 2, 0))
+    assert np.array_equal(r["cls"], by_np)
+    sig = 1.0 / np.sqrt(Pd)
+    ref = float(np.sum(np.log(2.0 * D[:n_flat])) +
+                np.sum(0.5 * LOG2PI + np.log(sig[n_flat:n_flat + n_soft])))
+    assert abs(r["logz_marginal"] - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def test_precheck_flat_term_is_the_prior_range_integral(oracle_lib):
+    """A coordinate the likelihood does not constrain contributes the integral of its (constant)
+    likelihood factor over the prior range: for a Gaussian factor of width 1e6 D the exact
+    truncated integral sigma sqrt(2 pi) erf(D / (sigma sqrt 2)) equals b - a to 1e-12, which
+    fixes the flat term as log(b - a) (the half-width D would be off by log 2)."""
+    O = oracle_lib
+    prob = synth.nuisance_gaussian(8, 1, 0, seed=41)
+    r = O.precheck(prob)
+    D = 0.5 * (prob.hi[0] - prob.lo[0])
+    sig = 1.0 / math.sqrt(prob.prec[0][0, 0])
+    exact = math.log(sig * math.sqrt(2 * math.pi) * math.erf(D / (sig * math.sqrt(2.0))))
+    assert r["cls"][0] == 1 and abs(r["logz_marginal"] - exact) < 1e-11
+
+
+def test_precheck_invariants_and_validation(oracle_lib):
+    """A constant added to l changes nothing; scaling P by c scales s by c (classes kept);
+    a median of an even count is the mean of the middle two; a bad box is rejected."""
+    O = oracle_lib
+    prob = synth.nuisance_gaussian(10, 2, 2, seed=50, centred=False)
+    r = O.precheck(prob)
+    p2 = synth.Problem(**{**vars(prob), "logl_offset": 123.25})
+    r2 = O.precheck(p2)
+    assert np.allclose(r2["s"], r["s"], rtol=1e-9, atol=1e-9)
+    assert np.array_equal(r2["cls"], r["cls"])
+    p3 = synth.Problem(**{**vars(prob), "prec": 4.0 * prob.prec})
+    r3 = O.precheck(p3)
+    assert np.allclose(r3["s"], 4.0 * r["s"], rtol=1e-11)
+    assert np.array_equal(r3["cls"], r["cls"])
+    # even d = 4 with s = D^2 P_ii = [1.2e-6, 1, 2, 3]: the mean median 1.5 flags the first
+    # coordinate (1.2e-6 < 1.5e-6), the lower middle value 1 would not
+    P = np.diag([1.2e-6, 1.0, 2.0, 3.0])[None]
+    p4 = synth.Problem(synth.FAMILY_GAUSS_MIX, synth.NORM_PEAK_ZERO, 4, 1, np.zeros(1),
+                       np.zeros((1, 4)), P, 0.0, 0.0, -np.ones(4), np.ones(4), np.zeros(1))
+    r4 = O.precheck(p4)
+    assert list(r4["cls"]) == [1, 0, 0, 0]
+    p5 = synth.Problem(**{**vars(p4), "lo": np.array([-1.0, 1.0, -1.0, -1.0])})
+    assert O.precheck(p5)["status"] == -1
