@@ -266,6 +266,41 @@ def cpu_baseline(prob, cfg, budget_s=20.0):
                 single_thread=dict(value=r1.n_grad_evals / dt1, starts=ns1, seconds=dt1))
 
 
+def precheck_leg(L, prob, name, reps=10):
+    """Preprocessing probe (2d + 1 FP64 l evaluations in one batch, sensitivities, classes,
+    marginal log-evidence): wall time per sb_precheck_dev call (it ends with a stream
+    synchronisation) on the workload's posterior, and on a d = 1024 Gaussian with 64
+    unconstrained and 32 weakly constrained coordinates against its closed form."""
+    import numpy as np
+    import torch
+    from paper_2601_19957_amd import synth
+
+    m = L.DeviceModel(prob)
+    L.sb_precheck_dev(m)  # tile autotune
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = L.sb_precheck_dev(m)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    d, K = prob.d, prob.K
+    flops = (2.0 * d + 1) * K * (2.0 * d * d + 3.0 * d)
+    out = dict(workload=f"{name}: d={d} K={K}", ms=dt * 1e3, logl_evals=2 * d + 1,
+               tflops=flops / dt / 1e12, frac_fp64_peak=flops / dt / 1e12 / PEAK["fp64"],
+               n_flat=r["n_flat"], n_soft=r["n_soft"])
+    nz = synth.nuisance_gaussian(1024, 64, 32, seed=2601199575)
+    rz = L.sb_precheck_dev(L.DeviceModel(nz))
+    cls = rz["cls"].cpu().numpy()
+    D = 0.5 * (nz.hi - nz.lo)
+    sig = 1.0 / np.sqrt(np.diag(nz.prec[0]))
+    ref = float(np.sum(np.log(2 * D[:64])) + np.sum(0.5 * math.log(2 * math.pi) + np.log(sig[64:96])))
+    out["degenerate_d1024"] = dict(
+        classes_as_constructed=bool((cls[:64] == 1).all() and (cls[64:96] == 2).all()
+                                    and (cls[96:] == 0).all()),
+        logz_marginal=float(rz["logz_marginal"].cpu().numpy()[0]), closed_form=ref)
+    return out
+
+
 def uneven_batch(L, serial=False):
     """The 512-problem uneven workload (d log-uniform in 8..512, K in 1..4,
     1024 starts each, FP64) as one sb_evidence_batch call: one warm-up call,
@@ -320,6 +355,8 @@ def main() -> int:
                     help="skip the per-config logL+grad (A3) precision variants")
     ap.add_argument("--batch-serial", action="store_true",
                     help="also time the uneven batch as one call per problem")
+    ap.add_argument("--no-precheck", action="store_true",
+                    help="skip the preprocessing-probe measurement")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the roofline kernel timing (for profiling that kernel)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -460,6 +497,11 @@ def main() -> int:
     if not args.no_batch:
         batch = uneven_batch(L, serial=args.batch_serial)
 
+    pre = None
+    if not args.no_precheck:
+        pre = precheck_leg(L, prob_big, big)
+        log(f"precheck {big}: {pre['ms']:.3f} ms, {pre['tflops']:.1f} TFLOP/s")
+
     a3 = None
     if not args.no_a3:
         a3 = a3_variants(L)
@@ -507,6 +549,7 @@ def main() -> int:
         "max_mode_dist_vs_oracle": dmodes,
         "uneven_batch": batch,
         "a3_variants": a3,
+        "precheck": pre,
         "roofline": roofline,
         "contraction_roofline": contraction,
         "cpu_baseline": cpu,

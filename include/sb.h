@@ -213,6 +213,28 @@ int32_t sb_discover_dev(const sb_model_dev *m, const double *lo, const double *h
                         int32_t *start_ray, double *X0, void *workspace, size_t ws_bytes,
                         void *stream);
 
+/* Preprocessing probe (section "Preprocessing: Dimensional Pathology
+ * Detection": its sensitivity equation, flat and soft-nuisance criteria,
+ * analytical marginalisation and algorithm summary).  With the prior centre
+ * c_i = (lo_i + hi_i)/2 and half-widths D_i = (hi_i - lo_i)/2, the model's l
+ * is evaluated in FP64 at c and at c +- D_i e_i (2d + 1 points in one batch):
+ * s [d] (device) gets s_i = |l(c + D_i e_i) - l(c)| + |l(c - D_i e_i) - l(c)|,
+ * cls [d] (device) 1 where s_i < eps_flat * median(s) (flat), else 2 where
+ * s_i < eps_soft * max(s) (soft nuisance), else 0 (active); *logz_marginal
+ * (device) the sum over flat i of log(hi_i - lo_i) and over soft i of
+ * 1/2 log 2 pi + log(D_i / sqrt(s_i)).  The median of an even count is the
+ * mean of the middle two.  eps <= 0 selects the defaults 1e-6 (flat) and
+ * 1e-3 (soft).  n_flagged [2] (host, nullable) gets the flat and soft counts.
+ * lo, hi [d] are device FP64 arrays with lo < hi (not checked here: the
+ * caller validates the box).  SB_E_INVAL if l is not finite at a probe point
+ * (then *logz_marginal is NaN).  The call synchronises the stream.
+ * Workspace >= sb_precheck_workspace_bytes(d, K). */
+size_t sb_precheck_workspace_bytes(int32_t d, int32_t K);
+int32_t sb_precheck_dev(const sb_model_dev *m, const double *lo, const double *hi,
+                        double eps_flat, double eps_soft, double *s, int32_t *cls,
+                        double *logz_marginal, int32_t *n_flagged, void *workspace,
+                        size_t ws_bytes, void *stream);
+
 /* L-BFGS two-loop direction (appendix "L-BFGS Optimization") for B
  * independent histories: S, Y [B][m][d] in logical order (oldest first),
  * cnt [B] pairs used (0 <= cnt <= m), G [B][d] gradient of f.  Writes the

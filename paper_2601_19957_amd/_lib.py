@@ -32,7 +32,7 @@ EXPORTS = [
     "sb_prep_workspace_bytes", "sb_prep_dev", "sb_logl_grad_workspace_bytes", "sb_logl_grad_dev",
     "sb_quadform_dev", "sb_split_bf16_dev", "sb_hvp_workspace_bytes", "sb_hvp_dev", "sb_discover_workspace_bytes", "sb_discover_dev",
     "sb_lbfgs_direction_dev", "sb_lbfgs_workspace_bytes", "sb_lbfgs_dev",
-    "sb_lbfgs_timed_dev",
+    "sb_lbfgs_timed_dev", "sb_precheck_workspace_bytes", "sb_precheck_dev",
     "sb_dedup_workspace_bytes", "sb_dedup_dev", "sb_hessian_workspace_bytes", "sb_hessian_dev",
     "sb_cholesky_logdet_dev", "sb_cholesky_solve_dev", "sb_combine_dev", "sb_status_string",
     "sb_last_error", "sb_abi_version",
@@ -114,6 +114,8 @@ def lib():
                                    vp]),
             "sb_lbfgs_timed_dev": (i32, [vp, i64, vp, i32, i32, f64, i32, vp, vp, vp, vp, vp,
                                          vp, sz, vp, i32, vp, vp, vp, vp]),
+            "sb_precheck_workspace_bytes": (sz, [i32, i32]),
+            "sb_precheck_dev": (i32, [vp, vp, vp, f64, f64, vp, vp, vp, vp, vp, sz, vp]),
             "sb_dedup_workspace_bytes": (sz, [i32]),
             "sb_dedup_dev": (i32, [i32, i32, vp, vp, vp, f64, i32, vp, vp, i32, vp, vp, sz, vp]),
             "sb_hessian_workspace_bytes": (sz, [i32, i32, i32]),
@@ -470,6 +472,30 @@ def sb_lbfgs_timed_dev(model: DeviceModel, X0, m: int = 8, max_iter: int = 0,
     return dict(x=X, logl=l, grad=g, status=status, iters=iters, n_evals=nev.value,
                 step_us=us[:n_timed], step_rows=rows[:n_timed], step_full=full[:n_timed],
                 step_back=back[:n_timed])
+
+
+def sb_precheck_dev(model: DeviceModel, eps_flat: float = 0.0, eps_soft: float = 0.0,
+                    lo=None, hi=None):
+    """Preprocessing probe on the model's box (or lo/hi device tensors): sensitivities s,
+    classes (0 active, 1 flat, 2 soft nuisance), marginal log-evidence of the flagged
+    coordinates, and the flat and soft counts."""
+    import torch
+
+    dev = model.mu.device
+    d = model.d
+    lo = model.lo if lo is None else lo
+    hi = model.hi if hi is None else hi
+    s = torch.empty(d, dtype=torch.float64, device=dev)
+    cls = torch.empty(d, dtype=torch.int32, device=dev)
+    lz = torch.empty(1, dtype=torch.float64, device=dev)
+    nfl = (C.c_int32 * 2)()
+    ws = _ws(lib().sb_precheck_workspace_bytes(d, model.K), dev)
+    mv = model.view(DTYPE_F64)
+    st = lib().sb_precheck_dev(C.byref(mv), lo.data_ptr(), hi.data_ptr(), eps_flat, eps_soft,
+                               s.data_ptr(), cls.data_ptr(), lz.data_ptr(), nfl, ws.data_ptr(),
+                               ws.numel(), _stream())
+    _check(st, "sb_precheck_dev")
+    return dict(s=s, cls=cls, logz_marginal=lz, n_flat=nfl[0], n_soft=nfl[1])
 
 
 def sb_dedup_dev(X, l, tau: float, valid=None, max_reps: int = 1024):

@@ -615,6 +615,37 @@ int32_t sb_discover_dev(const sb_model_dev *mdl, const double *lo, const double 
   return launch_gather_starts(d, n_pts, n_starts, start_ray, ray_best_j, p0, p1, X0, s);
 }
 
+// ---------------------------------------------------------- preprocessing
+size_t sb_precheck_workspace_bytes(int32_t d, int32_t K) {
+  if (d < 1 || K < 1) return 0;
+  return precheck_ws_bytes(d, K);
+}
+
+int32_t sb_precheck_dev(const sb_model_dev *mdl, const double *lo, const double *hi,
+                        double eps_flat, double eps_soft, double *s, int32_t *cls,
+                        double *logz_marginal, int32_t *n_flagged, void *workspace,
+                        size_t ws_bytes, void *stream) {
+  int st = validate_model(mdl);
+  if (st) return st;
+  if (!lo || !hi || !s || !cls || !logz_marginal) return fail(SB_E_INVAL, "NULL argument");
+  if (!(eps_flat >= 0.0) || !(eps_soft >= 0.0))
+    return fail(SB_E_INVAL, "thresholds must be >= 0 (0: the defaults)");
+  if (!workspace || ws_bytes < sb_precheck_workspace_bytes(mdl->d, mdl->K))
+    return fail(SB_E_NOMEM, "workspace too small");
+  if ((st = device_status())) return st;
+  Model m = model_from(mdl);
+  int32_t counts[4] = {0, 0, 0, 0};
+  st = run_precheck(m, lo, hi, eps_flat > 0.0 ? eps_flat : 1e-6, eps_soft > 0.0 ? eps_soft : 1e-3,
+                    s, cls, logz_marginal, counts, workspace, ws_bytes, (hipStream_t)stream);
+  if (st) return st;
+  if (n_flagged) {
+    n_flagged[0] = counts[1];
+    n_flagged[1] = counts[2];
+  }
+  if (counts[3]) return fail(SB_E_INVAL, "non-finite likelihood at %d probe coordinates", counts[3]);
+  return SB_OK;
+}
+
 // ---------------------------------------------------------------- L-BFGS
 int32_t sb_lbfgs_direction_dev(int64_t B, int32_t d, int32_t m, const int32_t *cnt,
                                const void *S, const void *Y, const void *G, void *P,

@@ -258,6 +258,13 @@ int launch_ray_nodes_finish(const Model &m, int64_t R, int n_pts, int ntn, const
 // autotuned on these operands.  Needs quad_gemm_bf16_ok(d).
 int discover_bf16_nodes(const Model &m, const float *P0, const float *P1, int R, int n_pts,
                         float *qpart, float *l, hipStream_t s);
+// Preprocessing probe (precheck.hip): s [d], cls [d] (0 active, 1 flat,
+// 2 soft nuisance) and the marginal log-evidence *logz (device); the host gets
+// counts_host [4] = active, flat, soft, non-finite sensitivities.
+size_t precheck_ws_bytes(int d, int K);
+int run_precheck(const Model &m, const double *lo, const double *hi, double eps_flat,
+                 double eps_soft, double *s, int32_t *cls, double *logz, int32_t *counts_host,
+                 void *workspace, size_t ws_bytes, hipStream_t st);
 int launch_ray_argmax(int R, int n_pts, int dtype, const void *l, double *best_l, int32_t *best_j,
                       hipStream_t s);
 int launch_topn(int R, int n_starts, const double *best_l, int32_t *start_ray, hipStream_t s);
