@@ -320,6 +320,28 @@ def precheck(prob, eps_flat=0.0, eps_soft=0.0, op: Optional[OracleProblem] = Non
     return dict(status=st, s=s, cls=cls, logz_marginal=lz.value)
 
 
+def eig_reduce(H, lo, hi, eps_inform, eps_nuisance):
+    """Dimensional reduction at a mode (section "Module 4: GraspBirdsTail", its algorithm
+    summary): eigendecomposition of the symmetric part of H = -grad^2 l (numpy.linalg.eigh as
+    the library primitive), eigenvalues in descending order, classes 0 informative
+    (lambda > eps_inform), 1 nuisance (eps_nuisance < lambda <= eps_inform), 2 degenerate
+    (lambda <= eps_nuisance), the marginal log-evidence: 1/2 log(2 pi / lambda) per nuisance
+    direction and, per degenerate direction, the log of the box's extent along it,
+    sum_j |v_j| (hi_j - lo_j) (the paper's prior width Delta_i, read for a rotated direction),
+    summed pairwise in index order; d_eff = number of informative directions."""
+    Hs = 0.5 * (_f64(H) + _f64(H).T)
+    w, V = np.linalg.eigh(Hs)
+    order = np.argsort(-w, kind="stable")
+    w, V = w[order], V[:, order]
+    cls = np.where(w > eps_inform, 0, np.where(w > eps_nuisance, 1, 2)).astype(np.int32)
+    width = np.abs(V).T @ (_f64(hi) - _f64(lo))
+    safe_w = np.where(cls == 1, w, 1.0)
+    terms = np.where(cls == 1, 0.5 * np.log(2.0 * np.pi / safe_w),
+                     np.where(cls == 2, np.log(width), 0.0))
+    return dict(eigval=w, V=V, cls=cls, logz_marginal=pairwise_sum(terms),
+                d_eff=int(np.sum(cls == 0)))
+
+
 def mode_log_z(d, logl_v, log_det_h, log_vol) -> float:
     return lib().or_mode_log_z(d, logl_v, log_det_h, log_vol)
 

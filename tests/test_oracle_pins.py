@@ -678,3 +678,48 @@ def test_precheck_invariants_and_validation(oracle_lib):
     assert list(r4["cls"]) == [1, 0, 0, 0]
     p5 = synth.Problem(**{**vars(p4), "lo": np.array([-1.0, 1.0, -1.0, -1.0])})
     assert O.precheck(p5)["status"] == -1
+
+
+# ------------------------------------------------- reduction at the modes
+
+def constructed_spectrum(n, seed, lam):
+    q = synth.haar_orthogonal(np.random.Generator(np.random.PCG64(seed)), n)
+    return (q * lam[None, :]) @ q.T, q
+
+
+def test_eig_reduce_constructed_spectrum(oracle_lib):
+    """H = Q diag(lam) Q^T with known lam spread over the three classes: eigenvalues, classes,
+    d_eff, nuisance terms 1/2 log(2 pi / lam) and degenerate extents sum_j |Q_ji| (b_j - a_j)
+    in closed form from (lam, Q)."""
+    O = oracle_lib
+    n = 24
+    lam = np.concatenate([np.geomspace(50.0, 2.0, 10), np.geomspace(0.5, 0.02, 8),
+                          np.geomspace(1e-5, 1e-8, 6)])
+    H, q = constructed_spectrum(n, 71, lam)
+    lo, hi = -np.linspace(1.0, 3.0, n), np.linspace(2.0, 5.0, n)
+    r = O.eig_reduce(H, lo, hi, eps_inform=1.0, eps_nuisance=1e-3)
+    assert np.allclose(r["eigval"], lam, rtol=1e-9, atol=1e-13 * lam[0])
+    want = np.array([0] * 10 + [1] * 8 + [2] * 6)
+    assert np.array_equal(r["cls"], want) and r["d_eff"] == 10
+    ext = np.abs(q).T @ (hi - lo)
+    ref = float(np.sum(0.5 * np.log(2 * np.pi / lam[10:18])) + np.sum(np.log(ext[18:])))
+    assert abs(r["logz_marginal"] - ref) <= 1e-9 * abs(ref)
+    # eigenvectors: each column equals the constructed one up to sign (distinct eigenvalues)
+    dots = np.abs(np.sum(r["V"] * q, axis=0))
+    assert np.all(np.abs(dots[:18] - 1.0) < 1e-8)
+
+
+def test_eig_reduce_axis_aligned_and_invariants(oracle_lib):
+    """A diagonal H: the degenerate term of coordinate i is log(b_i - a_i), the flat term of the
+    preprocessing probe; a symmetric permutation of H and the box changes nothing."""
+    O = oracle_lib
+    lam = np.array([3.0, 1e-9, 0.2, 7.0, 1e-10, 0.05])
+    lo, hi = -np.array([1.0, 2.0, 3.0, 4.0, 5.0, 6.0]), np.array([2.0, 2.0, 1.0, 1.0, 3.0, 9.0])
+    r = O.eig_reduce(np.diag(lam), lo, hi, eps_inform=1.0, eps_nuisance=1e-6)
+    ref = (np.log(hi[1] - lo[1]) + np.log(hi[4] - lo[4]) +
+           0.5 * np.log(2 * np.pi / 0.2) + 0.5 * np.log(2 * np.pi / 0.05))
+    assert abs(r["logz_marginal"] - ref) < 1e-13 and r["d_eff"] == 2
+    perm = np.array([4, 0, 5, 2, 1, 3])
+    r2 = O.eig_reduce(np.diag(lam)[perm][:, perm], lo[perm], hi[perm], 1.0, 1e-6)
+    assert np.allclose(r2["eigval"], r["eigval"], rtol=1e-15)
+    assert abs(r2["logz_marginal"] - r["logz_marginal"]) < 1e-13
