@@ -301,6 +301,31 @@ def precheck_leg(L, prob, name, reps=10):
     return out
 
 
+def reduce_leg(L, prob, name):
+    """Dimensional reduction at the modes (Jacobi eigendecomposition of the K mode Hessians,
+    FP64; the precisions, to which the separated mixture's mode Hessians are equal to e^-60):
+    wall time of one sb_eig_reduce_dev call after a warm call, sweeps, d_eff, and the largest
+    eigenvalue difference against numpy.linalg.eigh on the host."""
+    import numpy as np
+    import torch
+
+    H = torch.as_tensor(prob.prec, device="cuda")
+    lo = torch.as_tensor(prob.lo, device="cuda")
+    hi = torch.as_tensor(prob.hi, device="cuda")
+    L.sb_eig_reduce_dev(H[:1], lo, hi, 10.0, 1.5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = L.sb_eig_reduce_dev(H, lo, hi, 10.0, 1.5)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ev = r["eigval"].cpu().numpy()
+    err = max(float(np.max(np.abs(ev[k] - np.sort(np.linalg.eigvalsh(prob.prec[k]))[::-1])))
+              for k in range(prob.K))
+    return dict(workload=f"{name}: {prob.K} matrices of n={prob.d}", ms=dt * 1e3,
+                sweeps=r["sweeps"], d_eff=r["d_eff"], max_abs_eig_err_vs_numpy=err,
+                max_eig=float(ev.max()))
+
+
 def uneven_batch(L, serial=False):
     """The 512-problem uneven workload (d log-uniform in 8..512, K in 1..4,
     1024 starts each, FP64) as one sb_evidence_batch call: one warm-up call,
@@ -357,6 +382,8 @@ def main() -> int:
                     help="also time the uneven batch as one call per problem")
     ap.add_argument("--no-precheck", action="store_true",
                     help="skip the preprocessing-probe measurement")
+    ap.add_argument("--no-reduce", action="store_true",
+                    help="skip the eigen-reduction measurement")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the roofline kernel timing (for profiling that kernel)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -502,6 +529,11 @@ def main() -> int:
         pre = precheck_leg(L, prob_big, big)
         log(f"precheck {big}: {pre['ms']:.3f} ms, {pre['tflops']:.1f} TFLOP/s")
 
+    red = None
+    if not args.no_reduce:
+        red = reduce_leg(L, prob_big, big)
+        log(f"eigen reduction {big}: {red['ms']:.1f} ms, {red['sweeps']} sweeps")
+
     a3 = None
     if not args.no_a3:
         a3 = a3_variants(L)
@@ -550,6 +582,7 @@ def main() -> int:
         "uneven_batch": batch,
         "a3_variants": a3,
         "precheck": pre,
+        "eig_reduce": red,
         "roofline": roofline,
         "contraction_roofline": contraction,
         "cpu_baseline": cpu,

@@ -235,6 +235,33 @@ int32_t sb_precheck_dev(const sb_model_dev *m, const double *lo, const double *h
                         double *logz_marginal, int32_t *n_flagged, void *workspace,
                         size_t ws_bytes, void *stream);
 
+/* Dimensional reduction for sampler handoff (section "Module 4:
+ * GraspBirdsTail": eigendecomposition, direction classes, reduced likelihood
+ * and algorithm summary).  For C symmetric n x n matrices H [C][n][n]
+ * (device, FP64; H = -grad^2 l at a mode, e.g. from sb_hessian_dev; only the
+ * symmetric part (H + H^T)/2 is used, H is not modified): eigval [C][n]
+ * (device) the eigenvalues in descending order, V [C][n][n] (device,
+ * row-major) with column i the unit eigenvector of eigval i (sign
+ * arbitrary), by cyclic Jacobi in FP64 to an off-diagonal norm of at most
+ * 4 n eps |H|_F.  cls [C][n] (device): 0 informative (lambda > eps_inform),
+ * 1 nuisance (eps_nuisance < lambda <= eps_inform), 2 degenerate
+ * (lambda <= eps_nuisance).  logz_marginal [C] (device): the sum over
+ * nuisance directions of 1/2 log(2 pi / lambda) and over degenerate
+ * directions of the log of the box's extent along the direction,
+ * log sum_j |V_ji| (hi_j - lo_j) (lo, hi [n] device).  d_eff [C] (host,
+ * nullable): informative counts; *sweeps (host, nullable): Jacobi sweeps
+ * used.  The reduced likelihood of a mode theta* is
+ * l(theta* + V_inform phi) on the d_eff informative coordinates phi.
+ * SB_E_INVAL for bad sizes, thresholds outside 0 <= eps_nuisance <=
+ * eps_inform < inf, or non-finite H.  The call synchronises the stream.
+ * Workspace >= sb_eig_reduce_workspace_bytes(C, n). */
+size_t sb_eig_reduce_workspace_bytes(int32_t C, int32_t n);
+int32_t sb_eig_reduce_dev(int32_t C, int32_t n, const double *H, const double *lo,
+                          const double *hi, double eps_inform, double eps_nuisance,
+                          double *eigval, double *V, int32_t *cls, double *logz_marginal,
+                          int32_t *d_eff, int32_t *sweeps, void *workspace, size_t ws_bytes,
+                          void *stream);
+
 /* L-BFGS two-loop direction (appendix "L-BFGS Optimization") for B
  * independent histories: S, Y [B][m][d] in logical order (oldest first),
  * cnt [B] pairs used (0 <= cnt <= m), G [B][d] gradient of f.  Writes the

@@ -33,6 +33,7 @@ EXPORTS = [
     "sb_quadform_dev", "sb_split_bf16_dev", "sb_hvp_workspace_bytes", "sb_hvp_dev", "sb_discover_workspace_bytes", "sb_discover_dev",
     "sb_lbfgs_direction_dev", "sb_lbfgs_workspace_bytes", "sb_lbfgs_dev",
     "sb_lbfgs_timed_dev", "sb_precheck_workspace_bytes", "sb_precheck_dev",
+    "sb_eig_reduce_workspace_bytes", "sb_eig_reduce_dev",
     "sb_dedup_workspace_bytes", "sb_dedup_dev", "sb_hessian_workspace_bytes", "sb_hessian_dev",
     "sb_cholesky_logdet_dev", "sb_cholesky_solve_dev", "sb_combine_dev", "sb_status_string",
     "sb_last_error", "sb_abi_version",
@@ -116,6 +117,9 @@ def lib():
                                          vp, sz, vp, i32, vp, vp, vp, vp]),
             "sb_precheck_workspace_bytes": (sz, [i32, i32]),
             "sb_precheck_dev": (i32, [vp, vp, vp, f64, f64, vp, vp, vp, vp, vp, sz, vp]),
+            "sb_eig_reduce_workspace_bytes": (sz, [i32, i32]),
+            "sb_eig_reduce_dev": (i32, [i32, i32, vp, vp, vp, f64, f64, vp, vp, vp, vp, vp, vp,
+                                        vp, sz, vp]),
             "sb_dedup_workspace_bytes": (sz, [i32]),
             "sb_dedup_dev": (i32, [i32, i32, vp, vp, vp, f64, i32, vp, vp, i32, vp, vp, sz, vp]),
             "sb_hessian_workspace_bytes": (sz, [i32, i32, i32]),
@@ -496,6 +500,31 @@ def sb_precheck_dev(model: DeviceModel, eps_flat: float = 0.0, eps_soft: float =
                                ws.numel(), _stream())
     _check(st, "sb_precheck_dev")
     return dict(s=s, cls=cls, logz_marginal=lz, n_flat=nfl[0], n_soft=nfl[1])
+
+
+def sb_eig_reduce_dev(H, lo, hi, eps_inform: float, eps_nuisance: float):
+    """Eigendecomposition of C symmetric matrices H [C][n][n] (device FP64), direction classes
+    (0 informative, 1 nuisance, 2 degenerate), marginal log-evidence of the non-informative
+    directions, d_eff and the Jacobi sweeps used."""
+    import torch
+
+    H = H.contiguous()
+    Cn, n, _ = H.shape
+    dev = H.device
+    ev = torch.empty((Cn, n), dtype=torch.float64, device=dev)
+    V = torch.empty((Cn, n, n), dtype=torch.float64, device=dev)
+    cls = torch.empty((Cn, n), dtype=torch.int32, device=dev)
+    lz = torch.empty(Cn, dtype=torch.float64, device=dev)
+    deff = (C.c_int32 * Cn)()
+    sweeps = C.c_int32(0)
+    ws = _ws(lib().sb_eig_reduce_workspace_bytes(Cn, n), dev)
+    st = lib().sb_eig_reduce_dev(Cn, n, H.data_ptr(), lo.data_ptr(), hi.data_ptr(), eps_inform,
+                                 eps_nuisance, ev.data_ptr(), V.data_ptr(), cls.data_ptr(),
+                                 lz.data_ptr(), deff, C.byref(sweeps), ws.data_ptr(), ws.numel(),
+                                 _stream())
+    _check(st, "sb_eig_reduce_dev")
+    return dict(eigval=ev, V=V, cls=cls, logz_marginal=lz, d_eff=list(deff),
+                sweeps=sweeps.value)
 
 
 def sb_dedup_dev(X, l, tau: float, valid=None, max_reps: int = 1024):

@@ -646,6 +646,29 @@ int32_t sb_precheck_dev(const sb_model_dev *mdl, const double *lo, const double 
   return SB_OK;
 }
 
+// ------------------------------------------------- reduction at the modes
+size_t sb_eig_reduce_workspace_bytes(int32_t C, int32_t n) {
+  if (C < 1 || n < 1) return 0;
+  return reduce_ws_bytes(C, n);
+}
+
+int32_t sb_eig_reduce_dev(int32_t C, int32_t n, const double *H, const double *lo,
+                          const double *hi, double eps_inform, double eps_nuisance,
+                          double *eigval, double *V, int32_t *cls, double *logz_marginal,
+                          int32_t *d_eff, int32_t *sweeps, void *workspace, size_t ws_bytes,
+                          void *stream) {
+  if (C < 1 || n < 1 || !H || !lo || !hi || !eigval || !V || !cls || !logz_marginal)
+    return fail(SB_E_INVAL, "bad eigen-reduction arguments");
+  if (!(eps_nuisance >= 0.0) || !(eps_inform >= eps_nuisance) || !std::isfinite(eps_inform))
+    return fail(SB_E_INVAL, "need 0 <= eps_nuisance <= eps_inform < inf");
+  if (!workspace || ws_bytes < sb_eig_reduce_workspace_bytes(C, n))
+    return fail(SB_E_NOMEM, "workspace too small");
+  int st = device_status();
+  if (st) return st;
+  return run_eig_reduce(C, n, H, lo, hi, eps_inform, eps_nuisance, eigval, V, cls, logz_marginal,
+                        d_eff, sweeps, workspace, ws_bytes, (hipStream_t)stream);
+}
+
 // ---------------------------------------------------------------- L-BFGS
 int32_t sb_lbfgs_direction_dev(int64_t B, int32_t d, int32_t m, const int32_t *cnt,
                                const void *S, const void *Y, const void *G, void *P,

@@ -265,6 +265,15 @@ size_t precheck_ws_bytes(int d, int K);
 int run_precheck(const Model &m, const double *lo, const double *hi, double eps_flat,
                  double eps_soft, double *s, int32_t *cls, double *logz, int32_t *counts_host,
                  void *workspace, size_t ws_bytes, hipStream_t st);
+// Eigendecomposition and dimensional reduction at modes (reduce.hip): C
+// symmetric n x n matrices H; eigval [C][n] descending, V [C][n][n] (column i
+// = eigenvector of eigval i), cls [C][n], marginal log-evidence logz [C]
+// (device); deff_host [C] and *sweeps_host on the host.
+size_t reduce_ws_bytes(int C, int n);
+int run_eig_reduce(int C, int n, const double *H, const double *lo, const double *hi,
+                   double eps_inform, double eps_nuis, double *eigval, double *V, int32_t *cls,
+                   double *logz, int32_t *deff_host, int32_t *sweeps_host, void *workspace,
+                   size_t ws_bytes, hipStream_t st);
 int launch_ray_argmax(int R, int n_pts, int dtype, const void *l, double *best_l, int32_t *best_j,
                       hipStream_t s);
 int launch_topn(int R, int n_starts, const double *best_l, int32_t *start_ray, hipStream_t s);

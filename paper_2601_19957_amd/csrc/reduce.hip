@@ -1,0 +1,299 @@
+// Dimensional reduction for sampler handoff (section "Module 4:
+// GraspBirdsTail"): eigendecomposition of H = -grad^2 l at a mode, the
+// informative / nuisance / degenerate split of the eigen-directions, and the
+// marginal log-evidence of the directions left out.
+//
+// Eigensolver: two-sided cyclic Jacobi in FP64 (Golub & Van Loan, "Matrix
+// Computations", the symmetric Schur decomposition and the parallel
+// ordering of the cyclic Jacobi method).  A sweep is n' - 1 rounds (n' = n
+// rounded up to even) of n'/2 disjoint rotations in the round-robin
+// ("circle") order; within a round the rotation angles come from the matrix
+// before the round, then all row rotations (J^T A), then all column rotations
+// (A J, V J) run as whole-matrix passes, since disjoint pairs touch disjoint
+// rows and columns.  Sweeps stop when the off-diagonal Frobenius norm is at
+// most 4 n eps of the whole norm (read by the host after every sweep) or after
+// 40 sweeps.  C matrices share every launch.
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace sb {
+
+// Pair k of round r for an even count np: k = 0 pairs np-1 with r, k > 0
+// pairs (r + k) and (r - k) modulo np - 1.
+__device__ inline void jacobi_pair(int np, int r, int k, int &p, int &q) {
+  const int m = np - 1;
+  if (k == 0) {
+    p = r;
+    q = m;
+  } else {
+    p = (r + k) % m;
+    q = (r - k + m) % m;
+  }
+  if (p > q) {
+    const int t = p;
+    p = q;
+    q = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void jacobi_init_kernel(int C, int n, const double *H, double *A,
+                                                          double *V) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t nn = (int64_t)n * n;
+  if (e >= (int64_t)C * nn) return;
+  const int64_t c = e / nn, ij = e % nn;
+  const int i = (int)(ij / n), j = (int)(ij % n);
+  const double *h = H + c * nn;
+  A[e] = 0.5 * (h[(int64_t)i * n + j] + h[(int64_t)j * n + i]);  // symmetric part
+  V[e] = (i == j) ? 1.0 : 0.0;
+}
+
+// Rotation (c, s) zeroing a_pq: tau = (a_qq - a_pp) / (2 a_pq),
+// t = sign(tau) / (|tau| + sqrt(1 + tau^2)), c = 1 / sqrt(1 + t^2), s = t c.
+__global__ __launch_bounds__(256) void jacobi_angles_kernel(int C, int n, int np, int r,
+                                                            const double *A, double *cs) {
+  const int half = np / 2;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)C * half) return;
+  const int64_t c = e / half;
+  const int k = (int)(e % half);
+  int p, q;
+  jacobi_pair(np, r, k, p, q);
+  double cc = 1.0, ss = 0.0;
+  if (q < n) {
+    const double *a = A + c * (int64_t)n * n;
+    const double apq = a[(int64_t)p * n + q];
+    if (apq != 0.0) {
+      const double app = a[(int64_t)p * n + p], aqq = a[(int64_t)q * n + q];
+      const double tau = (aqq - app) / (2.0 * apq);
+      const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+      cc = 1.0 / sqrt(1.0 + t * t);
+      ss = t * cc;
+    }
+  }
+  cs[2 * e] = cc;
+  cs[2 * e + 1] = ss;
+}
+
+// Rows p, q of every pair: (row_p, row_q) <- (c row_p - s row_q, s row_p + c row_q).
+__global__ __launch_bounds__(256) void jacobi_rows_kernel(int C, int n, int np, int r, double *A,
+                                                          const double *cs) {
+  const int half = np / 2;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)C * half * n) return;
+  const int j = (int)(e % n);
+  const int64_t ck = e / n;
+  const int64_t c = ck / half;
+  const int k = (int)(ck % half);
+  int p, q;
+  jacobi_pair(np, r, k, p, q);
+  if (q >= n) return;
+  const double cc = cs[2 * ck], ss = cs[2 * ck + 1];
+  double *a = A + c * (int64_t)n * n;
+  const double x = a[(int64_t)p * n + j], y = a[(int64_t)q * n + j];
+  a[(int64_t)p * n + j] = cc * x - ss * y;
+  a[(int64_t)q * n + j] = ss * x + cc * y;
+}
+
+// Columns p, q of A and V: (col_p, col_q) <- (c col_p - s col_q, s col_p + c col_q).
+__global__ __launch_bounds__(256) void jacobi_cols_kernel(int C, int n, int np, int r, double *A,
+                                                          double *V, const double *cs) {
+  const int half = np / 2;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)C * half * n) return;
+  const int k = (int)(e % half);
+  const int64_t ci = e / half;
+  const int64_t c = ci / n;
+  const int i = (int)(ci % n);
+  int p, q;
+  jacobi_pair(np, r, k, p, q);
+  if (q >= n) return;
+  const int64_t ck = c * half + k;
+  const double cc = cs[2 * ck], ss = cs[2 * ck + 1];
+  double *a = A + c * (int64_t)n * n + (int64_t)i * n;
+  double *v = V + c * (int64_t)n * n + (int64_t)i * n;
+  double x = a[p], y = a[q];
+  a[p] = cc * x - ss * y;
+  a[q] = ss * x + cc * y;
+  x = v[p];
+  y = v[q];
+  v[p] = cc * x - ss * y;
+  v[q] = ss * x + cc * y;
+}
+
+// One workgroup per matrix: off-diagonal and total sums of squares.
+__global__ __launch_bounds__(256) void jacobi_norms_kernel(int n, const double *A, double *out) {
+  __shared__ double red[2][4];
+  const int64_t c = blockIdx.x;
+  const double *a = A + c * (int64_t)n * n;
+  double off = 0.0, tot = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += 256) {
+    const double v = a[e] * a[e];
+    tot += v;
+    if (e / n != e % n) off += v;
+  }
+  off = wave_sum(off);
+  tot = wave_sum(tot);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = off;
+    red[1][w] = tot;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[2 * c] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    out[2 * c + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+// Eigenvalues in descending order (ties to the lower index): the rank of
+// lambda_i among the diagonal (thread per matrix and i), then column i of V
+// goes to column rank (thread per matrix, row and i).
+__global__ __launch_bounds__(256) void eig_rank_kernel(int C, int n, const double *A,
+                                                       double *eigval, int32_t *rank_of) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)C * n) return;
+  const int64_t c = e / n;
+  const int i = (int)(e % n);
+  const double *a = A + c * (int64_t)n * n;
+  const double li = a[(int64_t)i * n + i];
+  int rank = 0;
+  for (int j = 0; j < n; ++j) {
+    const double lj = a[(int64_t)j * n + j];
+    rank += (lj > li || (lj == li && j < i)) ? 1 : 0;
+  }
+  rank_of[e] = rank;
+  eigval[c * n + rank] = li;
+}
+
+__global__ __launch_bounds__(256) void eig_permute_kernel(int C, int n, const double *Vw,
+                                                          const int32_t *rank_of, double *V) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t nn = (int64_t)n * n;
+  if (e >= (int64_t)C * nn) return;
+  const int64_t c = e / nn, ri = e % nn;
+  const int row = (int)(ri / n), i = (int)(ri % n);
+  V[c * nn + (int64_t)row * n + rank_of[c * n + i]] = Vw[e];
+}
+
+// One workgroup per matrix: classes of the sorted eigenvalues
+// (0 informative: lambda > eps_inform; 1 nuisance: eps_nuisance < lambda <=
+// eps_inform; 2 degenerate: lambda <= eps_nuisance), the nuisance terms
+// 1/2 log(2 pi / lambda), the degenerate terms log of the box's extent along
+// the eigenvector, sum_j |v_j| (hi_j - lo_j), their sum in index order, and
+// d_eff.
+__global__ __launch_bounds__(256) void eig_classify_kernel(int n, const double *eigval,
+                                                           const double *V, const double *lo,
+                                                           const double *hi, double eps_inform,
+                                                           double eps_nuis, int32_t *cls,
+                                                           double *term, double *logz,
+                                                           int32_t *deff) {
+  const int64_t c = blockIdx.x;
+  const double *lam = eigval + c * n;
+  const double *v = V + c * (int64_t)n * n;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double l = lam[i];
+    int k = 0;
+    double t = 0.0;
+    if (l > eps_inform) {
+      k = 0;
+    } else if (l > eps_nuis) {
+      k = 1;
+      t = 0.5 * log(2.0 * 3.14159265358979323846 / l);
+    } else {
+      k = 2;
+      double w = 0.0;
+      for (int j = 0; j < n; ++j) w += fabs(v[(int64_t)j * n + i]) * (hi[j] - lo[j]);
+      t = log(w);
+    }
+    cls[c * n + i] = k;
+    term[c * n + i] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    int de = 0;
+    for (int i = 0; i < n; ++i) {
+      acc += term[c * n + i];
+      de += cls[c * n + i] == 0;
+    }
+    logz[c] = acc;
+    deff[c] = de;
+  }
+}
+
+size_t reduce_ws_bytes(int C, int n) {
+  const size_t nn = (size_t)n * n, np = (size_t)(n + (n & 1));
+  return 2 * align_up(8 * (size_t)C * nn) + align_up(8 * (size_t)C * np) +
+         align_up(8 * 2 * (size_t)C) + align_up(8 * (size_t)C * n) + align_up(4 * (size_t)C) +
+         align_up(4 * (size_t)C * n) + 1024;
+}
+
+int run_eig_reduce(int C, int n, const double *H, const double *lo, const double *hi,
+                   double eps_inform, double eps_nuis, double *eigval, double *V, int32_t *cls,
+                   double *logz, int32_t *deff_host, int32_t *sweeps_host, void *workspace,
+                   size_t ws_bytes, hipStream_t st) {
+  const int np = n + (n & 1);
+  const int half = np / 2;
+  const int64_t nn = (int64_t)n * n;
+  Arena ar(workspace, ws_bytes);
+  double *A = ar.take<double>((size_t)C * nn);
+  double *Vw = ar.take<double>((size_t)C * nn);
+  double *cs = ar.take<double>((size_t)C * np);
+  double *nrm = ar.take<double>(2 * (size_t)C);
+  double *term = ar.take<double>((size_t)C * n);
+  int32_t *deff = ar.take<int32_t>(C);
+  int32_t *rank_of = ar.take<int32_t>((size_t)C * n);
+  if (!ar.ok()) {
+    set_error("eigen reduction: workspace too small");
+    return SB_E_NOMEM;
+  }
+  const unsigned g_nn = (unsigned)ceil_div((int64_t)C * nn, 256);
+  const unsigned g_pairs = (unsigned)ceil_div((int64_t)C * half, 256);
+  const unsigned g_rot = (unsigned)ceil_div((int64_t)C * half * n, 256);
+  hipLaunchKernelGGL(jacobi_init_kernel, dim3(g_nn), dim3(256), 0, st, C, n, H, A, Vw);
+  SB_LAUNCH_CHECK();
+  std::vector<double> hn(2 * (size_t)C);
+  // off(A) <= 4 n eps |A|_F: rounding leaves off-diagonal entries of order
+  // eps |A|_F after the last rotations, so a tighter target may not be met
+  const double tol = 4.0 * n * 2.220446049250313e-16, tol2 = tol * tol;
+  int sweeps = 0;
+  for (; sweeps < 40 && n > 1; ++sweeps) {
+    hipLaunchKernelGGL(jacobi_norms_kernel, dim3(C), dim3(256), 0, st, n, A, nrm);
+    SB_LAUNCH_CHECK();
+    SB_HIP(hipMemcpyAsync(hn.data(), nrm, 16 * (size_t)C, hipMemcpyDeviceToHost, st));
+    SB_HIP(hipStreamSynchronize(st));
+    bool done = true;
+    for (int c = 0; c < C; ++c) {
+      if (!std::isfinite(hn[2 * c + 1])) {
+        set_error("eigen reduction: matrix %d has non-finite entries", c);
+        return SB_E_INVAL;
+      }
+      if (hn[2 * c] > tol2 * hn[2 * c + 1]) done = false;
+    }
+    if (done) break;
+    for (int r = 0; r < np - 1; ++r) {
+      hipLaunchKernelGGL(jacobi_angles_kernel, dim3(g_pairs), dim3(256), 0, st, C, n, np, r, A,
+                         cs);
+      hipLaunchKernelGGL(jacobi_rows_kernel, dim3(g_rot), dim3(256), 0, st, C, n, np, r, A, cs);
+      hipLaunchKernelGGL(jacobi_cols_kernel, dim3(g_rot), dim3(256), 0, st, C, n, np, r, A, Vw,
+                         cs);
+    }
+    SB_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(eig_rank_kernel, dim3((unsigned)ceil_div((int64_t)C * n, 256)), dim3(256), 0,
+                     st, C, n, A, eigval, rank_of);
+  hipLaunchKernelGGL(eig_permute_kernel, dim3(g_nn), dim3(256), 0, st, C, n, Vw, rank_of, V);
+  SB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(eig_classify_kernel, dim3(C), dim3(256), 0, st, n, eigval, V, lo, hi,
+                     eps_inform, eps_nuis, cls, term, logz, deff);
+  SB_LAUNCH_CHECK();
+  if (deff_host) SB_HIP(hipMemcpyAsync(deff_host, deff, 4 * (size_t)C, hipMemcpyDeviceToHost, st));
+  SB_HIP(hipStreamSynchronize(st));
+  if (sweeps_host) *sweeps_host = sweeps;
+  return SB_OK;
+}
+
+}  // namespace sb

@@ -95,6 +95,9 @@ def test_null_arguments():
     assert L.sb_precheck_dev(None, None, None, 0.0, 0.0, None, None, None, None, None, 0,
                              None) == _lib.E_INVAL
     assert L.sb_precheck_workspace_bytes(0, 1) == 0
+    assert L.sb_eig_reduce_dev(0, 4, None, None, None, 1.0, 0.1, None, None, None, None, None,
+                               None, None, 0, None) == _lib.E_INVAL
+    assert L.sb_eig_reduce_workspace_bytes(1, 0) == 0
     for n_timed in (-1, 4):  # negative count, or timing arrays missing
         assert L.sb_lbfgs_timed_dev(None, 1, None, 8, 0, 0.0, 1, None, None, None, None, None,
                                     None, 0, None, n_timed, None, None, None,
