@@ -90,6 +90,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        # torch first: libsb.so then binds to the HIP runtime torch has loaded (torch
+        # carries its own copy; two runtimes in one process do not share devices)
+        import torch  # noqa: F401
+
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, f64, u64, sz = (C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_uint64,
                                       C.c_size_t)
