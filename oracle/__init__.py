@@ -342,6 +342,49 @@ def eig_reduce(H, lo, hi, eps_inform, eps_nuisance):
                 d_eff=int(np.sum(cls == 0)))
 
 
+def fd_derivatives(f, X, eps, full=False):
+    """Finite-difference derivatives of a generic log-likelihood f (a Python callable on one
+    point) at each row of X (appendix "Gradient and Hessian Computation": central-difference
+    gradient, diagonal Hessian from the same perturbations, off-diagonal entries from the four
+    points x +- eps e_i +- eps e_j), plain loops in the formulas' order.  Returns l [B],
+    grad [B][d], hdiag [B][d] and, with full, H [B][d][d] (symmetric, diagonal = hdiag).
+    Parity unpinned only in the sense that the stencils are the method; they are checked
+    against analytic derivatives in the CPU tests."""
+    X = np.atleast_2d(_f64(X))
+    B, d = X.shape
+    l = np.zeros(B)
+    g = np.zeros((B, d))
+    hd = np.zeros((B, d))
+    H = np.zeros((B, d, d)) if full else None
+    for b in range(B):
+        x = X[b]
+        f0 = f(x)
+        l[b] = f0
+        for i in range(d):
+            xp = x.copy()
+            xp[i] = x[i] + eps
+            xm = x.copy()
+            xm[i] = x[i] - eps
+            fp, fm = f(xp), f(xm)
+            g[b, i] = (fp - fm) / (2.0 * eps)
+            hd[b, i] = (fp - 2.0 * f0 + fm) / (eps * eps)
+        if full:
+            for i in range(d):
+                H[b, i, i] = hd[b, i]
+                for j in range(i + 1, d):
+                    v = {}
+                    for si in (1.0, -1.0):
+                        for sj in (1.0, -1.0):
+                            xx = x.copy()
+                            xx[i] = x[i] + si * eps
+                            xx[j] = x[j] + sj * eps
+                            v[(si, sj)] = f(xx)
+                    h = (v[(1.0, 1.0)] - v[(1.0, -1.0)] - v[(-1.0, 1.0)] + v[(-1.0, -1.0)]) / (
+                        4.0 * eps * eps)
+                    H[b, i, j] = H[b, j, i] = h
+    return dict(l=l, grad=g, hdiag=hd, H=H)
+
+
 def mode_log_z(d, logl_v, log_det_h, log_vol) -> float:
     return lib().or_mode_log_z(d, logl_v, log_det_h, log_vol)
 

@@ -723,3 +723,64 @@ def test_eig_reduce_axis_aligned_and_invariants(oracle_lib):
     r2 = O.eig_reduce(np.diag(lam)[perm][:, perm], lo[perm], hi[perm], 1.0, 1e-6)
     assert np.allclose(r2["eigval"], r["eigval"], rtol=1e-15)
     assert abs(r2["logz_marginal"] - r["logz_marginal"]) < 1e-13
+
+
+# ------------------------------------------- generic likelihoods: FD derivatives
+
+def test_fd_exact_for_quadratics(oracle_lib):
+    """Central differences have no truncation error on a quadratic: gradient -P(x - mu),
+    diagonal and full Hessian -P, up to rounding of order eps_mach |f| / eps^2."""
+    O = oracle_lib
+    rng = np.random.Generator(np.random.PCG64(90))
+    d = 5
+    P, _ = synth.random_precision(rng, d, 0.2, 2.0)
+    mu = rng.uniform(-1, 1, d)
+    f = lambda x: 3.0 - 0.5 * (x - mu) @ P @ (x - mu)
+    X = rng.uniform(-2, 2, (3, d))
+    eps = 1e-3
+    r = O.fd_derivatives(f, X, eps, full=True)
+    fmax = max(abs(f(x)) for x in X) + 10.0
+    tol_g = 4 * 2.2e-16 * fmax / eps
+    tol_h = 16 * 2.2e-16 * fmax / eps ** 2
+    assert np.allclose(r["l"], [f(x) for x in X], rtol=0, atol=1e-15 * fmax)
+    assert np.max(np.abs(r["grad"] + (X - mu) @ P)) <= tol_g
+    assert np.max(np.abs(r["hdiag"] + np.diag(P))) <= tol_h
+    assert np.max(np.abs(r["H"] + P[None])) <= tol_h
+
+
+def test_fd_truncation_error_bound_rosenbrock(oracle_lib):
+    """A non-quadratic (negative Rosenbrock): the central-difference errors are the leading
+    Taylor terms, eps^2/6 f''' for the gradient, eps^2/12 f'''' for the diagonal: checked
+    against the analytic derivatives with those terms bounded by the known fourth and third
+    derivatives of the quartic."""
+    O = oracle_lib
+
+    def f(x):
+        return -np.sum(100.0 * (x[1:] - x[:-1] ** 2) ** 2 + (1.0 - x[:-1]) ** 2)
+
+    def grad(x):
+        g = np.zeros_like(x)
+        g[:-1] += 400.0 * x[:-1] * (x[1:] - x[:-1] ** 2) + 2.0 * (1.0 - x[:-1])
+        g[1:] += -200.0 * (x[1:] - x[:-1] ** 2)
+        return g
+
+    def hess(x):
+        d = x.size
+        H = np.zeros((d, d))
+        for i in range(d - 1):
+            H[i, i] += -(1200.0 * x[i] ** 2 - 400.0 * x[i + 1] + 2.0)
+            H[i + 1, i + 1] += -200.0
+            H[i, i + 1] += 400.0 * x[i]
+            H[i + 1, i] += 400.0 * x[i]
+        return H
+
+    X = np.array([[0.3, -0.2, 0.5, 1.1], [1.0, 1.0, 1.0, 1.0]])
+    eps = 1e-4
+    r = O.fd_derivatives(f, X, eps, full=True)
+    for b, x in enumerate(X):
+        # |f'''| <= 2400 |x_i| + ..., |f''''| = 2400 along x_i: truncation <= eps^2 * 2400 * 3
+        trunc = eps ** 2 * 2400.0 * (3.0 + np.max(np.abs(x)))
+        rnd = 16 * 2.2e-16 * (abs(f(x)) + 1.0) / eps ** 2
+        assert np.max(np.abs(r["grad"][b] - grad(x))) <= trunc
+        assert np.max(np.abs(r["hdiag"][b] - np.diag(hess(x)))) <= trunc + rnd
+        assert np.max(np.abs(r["H"][b] - hess(x))) <= trunc + rnd
