@@ -7,6 +7,7 @@ the product library and its binding never import it.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -382,7 +383,25 @@ def fd_derivatives(f, X, eps, full=False):
                     h = (v[(1.0, 1.0)] - v[(1.0, -1.0)] - v[(-1.0, 1.0)] + v[(-1.0, -1.0)]) / (
                         4.0 * eps * eps)
                     H[b, i, j] = H[b, j, i] = h
-    return dict(l=l, grad=g, hdiag=hd, H=H)
+    return dict(l=l, grad=g, hdiag=hd, H=H, probe_b=_fd_probe(f, X, eps, l, hd))
+
+
+def _fd_probe(f, X, eps, l, hd):
+    """Off-diagonal probe of the rotation detection (appendix "Rotation Detection"):
+    b = (v^T H v - a) / (d - 1), v = (1, ..., 1) / sqrt(d), a = mean(H_ii), with v^T H v from
+    the central second difference along v (two more evaluations); 0 for d = 1."""
+    B, d = X.shape
+    out = np.zeros(B)
+    if d == 1:
+        return out
+    vi = 1.0 / math.sqrt(d)
+    for b in range(B):
+        x = X[b]
+        fp = f(x + eps * vi)
+        fm = f(x - eps * vi)
+        vhv = (fp - 2.0 * l[b] + fm) / (eps * eps)
+        out[b] = (vhv - float(np.mean(hd[b]))) / (d - 1)
+    return out
 
 
 def mode_log_z(d, logl_v, log_det_h, log_vol) -> float:

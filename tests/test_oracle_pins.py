@@ -784,3 +784,18 @@ def test_fd_truncation_error_bound_rosenbrock(oracle_lib):
         assert np.max(np.abs(r["grad"][b] - grad(x))) <= trunc
         assert np.max(np.abs(r["hdiag"][b] - np.diag(hess(x)))) <= trunc + rnd
         assert np.max(np.abs(r["H"][b] - hess(x))) <= trunc + rnd
+
+
+def test_fd_rotation_probe(oracle_lib):
+    """For a quadratic with H = a0 I + b0 (1 1^T - I) (uniform correlation b0) the probe returns
+    b0 exactly (up to rounding): v^T H v = a0 + (d - 1) b0 and mean H_ii = a0; an axis-aligned
+    quadratic gives 0."""
+    O = oracle_lib
+    d, a0, b0 = 6, -3.0, 0.4
+    Hm = a0 * np.eye(d) + b0 * (np.ones((d, d)) - np.eye(d))
+    f = lambda x: 0.5 * x @ Hm @ x
+    X = np.array([[0.1, -0.3, 0.2, 0.0, 0.5, -0.1]])
+    r = O.fd_derivatives(f, X, 1e-3)
+    assert abs(r["probe_b"][0] - b0) <= 1e-8
+    f2 = lambda x: 0.5 * x @ np.diag(np.arange(1.0, d + 1)) @ x
+    assert abs(O.fd_derivatives(f2, X, 1e-3)["probe_b"][0]) <= 1e-8
