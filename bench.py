@@ -326,6 +326,56 @@ def reduce_leg(L, prob, name):
                 max_eig=float(ev.max()))
 
 
+USER_GAUSS_SRC = r"""
+__device__ double gauss(const double *x, int d, const double *p) {
+  const double *P = p, *mu = p + d * d;
+  double q = 0.0;
+  for (int i = 0; i < d; ++i) {
+    double r = 0.0;
+    for (int j = 0; j < d; ++j) r += P[i * d + j] * (x[j] - mu[j]);
+    q += (x[i] - mu[i]) * r;
+  }
+  return -0.5 * q;
+}
+"""
+
+
+def user_fd_leg(L, reps=5):
+    """Generic user likelihood (a d = 64 Gaussian written as HIP source, compiled at run time):
+    finite-difference gradients of 4096 points (2d + 3 evaluations each) and full FD Hessians
+    at 4 points (2d^2 + 3 each), HIP events on the stream; user-function evaluations per second."""
+    import numpy as np
+    import torch
+    from paper_2601_19957_amd import synth
+
+    d, B = 64, 4096
+    rng = np.random.Generator(np.random.PCG64(2601199576))
+    P, _ = synth.random_precision(rng, d, 0.05, 1.0)
+    mu = rng.uniform(-8, 8, d)
+    params = torch.as_tensor(np.concatenate([P.ravel(), mu]), device="cuda")
+    X = torch.as_tensor(mu + rng.standard_normal((B, d)), device="cuda")
+    t0 = time.perf_counter()
+    fn = L.UserLogL(USER_GAUSS_SRC, "gauss")
+    compile_s = time.perf_counter() - t0
+    out = {"workload": f"d={d} Gaussian as user HIP source", "compile_ms": compile_s * 1e3}
+    stream = torch.cuda.current_stream()
+    for name, Xb, full in (("fd_grad", X, False), ("fd_hessian", X[:4], True)):
+        fn.fd(Xb, 1e-4, params, full=full)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            r = fn.fd(Xb, 1e-4, params, full=full)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        n_ev = Xb.shape[0] * ((2 * d * d + 3) if full else (2 * d + 3))
+        out[name] = dict(points=int(Xb.shape[0]), ms=ms, user_evals_per_s=n_ev / (ms * 1e-3))
+    g = r["H"].cpu().numpy()
+    out["fd_hessian"]["max_abs_err_vs_closed_form"] = float(np.max(np.abs(g + P[None])))
+    return out
+
+
 def uneven_batch(L, serial=False):
     """The 512-problem uneven workload (d log-uniform in 8..512, K in 1..4,
     1024 starts each, FP64) as one sb_evidence_batch call: one warm-up call,
@@ -384,6 +434,8 @@ def main() -> int:
                     help="skip the preprocessing-probe measurement")
     ap.add_argument("--no-reduce", action="store_true",
                     help="skip the eigen-reduction measurement")
+    ap.add_argument("--no-user", action="store_true",
+                    help="skip the generic-likelihood finite-difference measurement")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the roofline kernel timing (for profiling that kernel)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -534,6 +586,11 @@ def main() -> int:
         red = reduce_leg(L, prob_big, big)
         log(f"eigen reduction {big}: {red['ms']:.1f} ms, {red['sweeps']} sweeps")
 
+    ufd = None
+    if not args.no_user:
+        ufd = user_fd_leg(L)
+        log(f"user FD: grad {ufd['fd_grad']['ms']:.3f} ms, hessian {ufd['fd_hessian']['ms']:.3f} ms")
+
     a3 = None
     if not args.no_a3:
         a3 = a3_variants(L)
@@ -583,6 +640,7 @@ def main() -> int:
         "a3_variants": a3,
         "precheck": pre,
         "eig_reduce": red,
+        "user_fd": ufd,
         "roofline": roofline,
         "contraction_roofline": contraction,
         "cpu_baseline": cpu,

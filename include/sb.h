@@ -262,6 +262,40 @@ int32_t sb_eig_reduce_dev(int32_t C, int32_t n, const double *H, const double *l
                           int32_t *d_eff, int32_t *sweeps, void *workspace, size_t ws_bytes,
                           void *stream);
 
+/* Generic user log-likelihoods without an analytic backward (the paper's
+ * general case: any l, derivatives by finite differences; appendix "Gradient
+ * and Hessian Computation" for the stencils, "Rotation Detection" for the
+ * off-diagonal probe).  sb_user_compile compiles `source`, which must define
+ *   __device__ double NAME(const double *x, int d, const double *params);
+ * (x: one point, params: the caller's device array, may be NULL), for gfx950
+ * with hipRTC on the current device and returns a handle in *out (release
+ * with sb_user_release).  SB_E_INVAL if `name` is not a C identifier or the
+ * source does not compile (the compiler's message is in sb_last_error);
+ * SB_E_DEVICE if the code object does not load.  A handle is used on the
+ * device it was compiled on.  The user function must not fault: it is run as
+ * given. */
+typedef struct sb_user_fn sb_user_fn;
+int32_t sb_user_compile(const char *source, const char *name, sb_user_fn **out);
+void sb_user_release(sb_user_fn *fn);
+/* l [B] (device) = NAME(X + b d, d, params) for the rows of X [B][d] (device). */
+int32_t sb_user_logl_dev(const sb_user_fn *fn, int64_t B, int32_t d, const double *X,
+                         const double *params, double *l, void *stream);
+/* Central finite differences at the rows of X [B][d] with step eps > 0: all
+ * perturbed points of the batch in one launch of the user function, then
+ * l [B], grad [B][d] ((f(x + eps e_i) - f(x - eps e_i)) / (2 eps)), hdiag [B][d]
+ * ((f(x + eps e_i) - 2 f(x) + f(x - eps e_i)) / eps^2), probe_b [B]
+ * ((v^T H v - mean H_ii) / (d - 1) with v = (1..1)/sqrt(d) and v^T H v the
+ * second difference along v; 0 for d = 1), and, when H is not NULL, the full
+ * Hessian H [B][d][d] with H_ij = (f_{++} - f_{+-} - f_{-+} + f_{--}) /
+ * (4 eps^2), f_{+-} = f(x + eps e_i - eps e_j), diagonal hdiag (2d^2 + 3
+ * evaluations per point; 2d + 3 without H).  Every output but H may be NULL.
+ * Workspace >= sb_user_fd_workspace_bytes(B, d, H != NULL). */
+size_t sb_user_fd_workspace_bytes(int64_t B, int32_t d, int32_t full);
+int32_t sb_user_fd_dev(const sb_user_fn *fn, int64_t B, int32_t d, const double *X,
+                       const double *params, double eps, double *l, double *grad, double *hdiag,
+                       double *H, double *probe_b, void *workspace, size_t ws_bytes,
+                       void *stream);
+
 /* L-BFGS two-loop direction (appendix "L-BFGS Optimization") for B
  * independent histories: S, Y [B][m][d] in logical order (oldest first),
  * cnt [B] pairs used (0 <= cnt <= m), G [B][d] gradient of f.  Writes the

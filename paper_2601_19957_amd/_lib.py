@@ -33,7 +33,8 @@ EXPORTS = [
     "sb_quadform_dev", "sb_split_bf16_dev", "sb_hvp_workspace_bytes", "sb_hvp_dev", "sb_discover_workspace_bytes", "sb_discover_dev",
     "sb_lbfgs_direction_dev", "sb_lbfgs_workspace_bytes", "sb_lbfgs_dev",
     "sb_lbfgs_timed_dev", "sb_precheck_workspace_bytes", "sb_precheck_dev",
-    "sb_eig_reduce_workspace_bytes", "sb_eig_reduce_dev",
+    "sb_eig_reduce_workspace_bytes", "sb_eig_reduce_dev", "sb_user_compile", "sb_user_release",
+    "sb_user_logl_dev", "sb_user_fd_workspace_bytes", "sb_user_fd_dev",
     "sb_dedup_workspace_bytes", "sb_dedup_dev", "sb_hessian_workspace_bytes", "sb_hessian_dev",
     "sb_cholesky_logdet_dev", "sb_cholesky_solve_dev", "sb_combine_dev", "sb_status_string",
     "sb_last_error", "sb_abi_version",
@@ -124,6 +125,11 @@ def lib():
             "sb_eig_reduce_workspace_bytes": (sz, [i32, i32]),
             "sb_eig_reduce_dev": (i32, [i32, i32, vp, vp, vp, f64, f64, vp, vp, vp, vp, vp, vp,
                                         vp, sz, vp]),
+            "sb_user_compile": (i32, [C.c_char_p, C.c_char_p, vp]),
+            "sb_user_release": (None, [vp]),
+            "sb_user_logl_dev": (i32, [vp, i64, i32, vp, vp, vp, vp]),
+            "sb_user_fd_workspace_bytes": (sz, [i64, i32, i32]),
+            "sb_user_fd_dev": (i32, [vp, i64, i32, vp, vp, f64, vp, vp, vp, vp, vp, vp, sz, vp]),
             "sb_dedup_workspace_bytes": (sz, [i32]),
             "sb_dedup_dev": (i32, [i32, i32, vp, vp, vp, f64, i32, vp, vp, i32, vp, vp, sz, vp]),
             "sb_hessian_workspace_bytes": (sz, [i32, i32, i32]),
@@ -529,6 +535,53 @@ def sb_eig_reduce_dev(H, lo, hi, eps_inform: float, eps_nuisance: float):
     _check(st, "sb_eig_reduce_dev")
     return dict(eigval=ev, V=V, cls=cls, logz_marginal=lz, d_eff=list(deff),
                 sweeps=sweeps.value)
+
+
+class UserLogL:
+    """A generic log-likelihood given as HIP source defining
+    ``__device__ double NAME(const double *x, int d, const double *params)``, compiled for the
+    current device at construction."""
+
+    def __init__(self, source: str, name: str):
+        self.h = C.c_void_p()
+        st = lib().sb_user_compile(source.encode(), name.encode(), C.byref(self.h))
+        _check(st, "sb_user_compile")
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sb_user_release(self.h)
+            self.h = None
+
+    def logl(self, X, params=None):
+        import torch
+
+        X = X.contiguous().to(torch.float64)
+        B, d = X.shape
+        l = torch.empty(B, dtype=torch.float64, device=X.device)
+        st = lib().sb_user_logl_dev(self.h, B, d, X.data_ptr(), _ptr(params), l.data_ptr(),
+                                    _stream())
+        _check(st, "sb_user_logl_dev")
+        return l
+
+    def fd(self, X, eps: float, params=None, full: bool = False):
+        """Central finite differences at the rows of X: l, grad, hdiag, probe_b and, with
+        full, the Hessian H [B][d][d]."""
+        import torch
+
+        X = X.contiguous().to(torch.float64)
+        B, d = X.shape
+        f64 = dict(dtype=torch.float64, device=X.device)
+        l = torch.empty(B, **f64)
+        g = torch.empty((B, d), **f64)
+        hd = torch.empty((B, d), **f64)
+        pb = torch.empty(B, **f64)
+        H = torch.empty((B, d, d), **f64) if full else None
+        ws = _ws(lib().sb_user_fd_workspace_bytes(B, d, int(full)), X.device)
+        st = lib().sb_user_fd_dev(self.h, B, d, X.data_ptr(), _ptr(params), eps, l.data_ptr(),
+                                  g.data_ptr(), hd.data_ptr(), _ptr(H), pb.data_ptr(),
+                                  ws.data_ptr(), ws.numel(), _stream())
+        _check(st, "sb_user_fd_dev")
+        return dict(l=l, grad=g, hdiag=hd, H=H, probe_b=pb)
 
 
 def sb_dedup_dev(X, l, tau: float, valid=None, max_reps: int = 1024):

@@ -98,6 +98,26 @@ def test_null_arguments():
     assert L.sb_eig_reduce_dev(0, 4, None, None, None, 1.0, 0.1, None, None, None, None, None,
                                None, None, 0, None) == _lib.E_INVAL
     assert L.sb_eig_reduce_workspace_bytes(1, 0) == 0
+    h = C.c_void_p()
+    assert L.sb_user_compile(None, b"f", C.byref(h)) == _lib.E_INVAL
+    assert L.sb_user_compile(b"__device__ double f(const double *x, int d, const double *p)"
+                             b" { return 0.0; }", b"1f", C.byref(h)) == _lib.E_INVAL
+    assert L.sb_user_fd_workspace_bytes(0, 3, 0) == 0
+
+
+def test_user_likelihood_compiles_on_the_host():
+    """The run-time compilation of a user likelihood needs no GPU: a syntax error is reported
+    with the compiler's message; a valid source compiles and then needs a device to load."""
+    L = _lib.lib()
+    h = C.c_void_p()
+    bad = b"__device__ double f(const double *x, int d, const double *p) { return x[0] + ; }"
+    assert L.sb_user_compile(bad, b"f", C.byref(h)) == _lib.E_INVAL
+    assert "error" in _lib.last_error()
+    good = b"__device__ double f(const double *x, int d, const double *p) { return -x[0]; }"
+    st = L.sb_user_compile(good, b"f", C.byref(h))
+    assert st in (_lib.OK, _lib.E_DEVICE)
+    if st == _lib.OK:
+        L.sb_user_release(h)
     for n_timed in (-1, 4):  # negative count, or timing arrays missing
         assert L.sb_lbfgs_timed_dev(None, 1, None, 8, 0, 0.0, 1, None, None, None, None, None,
                                     None, 0, None, n_timed, None, None, None,
