@@ -404,6 +404,37 @@ def _fd_probe(f, X, eps, l, hd):
     return out
 
 
+def user_mode_evidence(f, modes, lo, hi, eps, rot_tol):
+    """Laplace evidence of a generic log-likelihood at given modes with finite-difference
+    curvature (module BendTheBow's geometry detection and evidence calculation): per mode the
+    diagonal H_ii and the probe b from one batch of perturbations; when |b| > rot_tol * |mean
+    H_ii| the full FD Hessian and log det(-H) by a Cholesky factorisation (numpy), else
+    sum log(-H_ii); log Z_k = l + (d/2) log 2 pi - log det / 2 - log V; log Z = logsumexp.
+    Returns None for a mode whose -H is not positive definite."""
+    modes = np.atleast_2d(_f64(modes))
+    n, d = modes.shape
+    lv = log_volume(lo, hi)
+    r = fd_derivatives(f, modes, eps, full=False)
+    out = dict(logl=r["l"].copy(), logdet=np.zeros(n), full=np.zeros(n, dtype=bool),
+               mode_log_z=np.zeros(n))
+    for k in range(n):
+        a = float(np.mean(r["hdiag"][k]))
+        if abs(r["probe_b"][k]) > rot_tol * abs(a):
+            out["full"][k] = True
+            Hk = fd_derivatives(f, modes[k:k + 1], eps, full=True)["H"][0]
+            st, _ = cholesky(-Hk)
+            if st:
+                return None
+            out["logdet"][k] = logdet_spd(-Hk)
+        else:
+            if np.any(r["hdiag"][k] >= 0):
+                return None
+            out["logdet"][k] = pairwise_sum(np.log(-r["hdiag"][k]))
+        out["mode_log_z"][k] = mode_log_z(d, out["logl"][k], out["logdet"][k], lv)
+    out["log_z"] = logsumexp(np.sort(out["mode_log_z"])[::-1])
+    return out
+
+
 def mode_log_z(d, logl_v, log_det_h, log_vol) -> float:
     return lib().or_mode_log_z(d, logl_v, log_det_h, log_vol)
 

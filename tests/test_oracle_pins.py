@@ -799,3 +799,30 @@ def test_fd_rotation_probe(oracle_lib):
     assert abs(r["probe_b"][0] - b0) <= 1e-8
     f2 = lambda x: 0.5 * x @ np.diag(np.arange(1.0, d + 1)) @ x
     assert abs(O.fd_derivatives(f2, X, 1e-3)["probe_b"][0]) <= 1e-8
+
+
+def test_user_mode_evidence_gaussians_closed_form(oracle_lib):
+    """Laplace with FD curvature is exact for Gaussians (central differences are exact on
+    quadratics): a correlated Gaussian takes the full-Hessian branch, an axis-aligned one the
+    diagonal branch, both give the closed form (d/2) log 2 pi + (1/2) sum log lambda - log V;
+    a normalised two-component mixture at its means gives -log V to the e^-60 overlap."""
+    O = oracle_lib
+    d = 6
+    rng = np.random.Generator(np.random.PCG64(95))
+    P, sll = synth.random_precision(rng, d, 0.1, 1.0)
+    mu = rng.uniform(-2, 2, d)
+    lo, hi = np.full(d, -10.0), np.full(d, 10.0)
+    ref = 0.5 * d * LOG2PI + 0.5 * sll - d * math.log(20.0)
+    f = lambda x: -0.5 * (x - mu) @ P @ (x - mu)
+    r = O.user_mode_evidence(f, mu[None], lo, hi, 1e-3, 1e-3)
+    assert r["full"][0] and abs(r["log_z"] - ref) < 1e-7
+    lam = np.exp(rng.uniform(np.log(0.1), 0.0, d))
+    f2 = lambda x: -0.5 * np.sum((x - mu) ** 2 / lam)
+    r2 = O.user_mode_evidence(f2, mu[None], lo, hi, 1e-3, 1e-3)
+    ref2 = 0.5 * d * LOG2PI + 0.5 * np.sum(np.log(lam)) - d * math.log(20.0)
+    assert not r2["full"][0] and abs(r2["log_z"] - ref2) < 1e-7
+    prob = small_mixture(d=d, K=2, seed=96, box=12.0)
+    op = O.OracleProblem(prob)
+    fm = lambda x: float(O.logl(prob, x[None], grad=False, op=op)[0])
+    r3 = O.user_mode_evidence(fm, prob.mu, prob.lo, prob.hi, 1e-3, 1e-3)
+    assert abs(r3["log_z"] + O.log_volume(prob.lo, prob.hi)) < 1e-6
