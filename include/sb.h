@@ -295,6 +295,25 @@ int32_t sb_user_fd_dev(const sb_user_fn *fn, int64_t B, int32_t d, const double 
                        const double *params, double eps, double *l, double *grad, double *hdiag,
                        double *H, double *probe_b, void *workspace, size_t ws_bytes,
                        void *stream);
+/* Laplace evidence of a user likelihood at n given modes [n][d] (device),
+ * with finite-difference curvature (the geometry detection and evidence
+ * calculation of module BendTheBow): per mode the diagonal H_ii and the probe
+ * b from one batch (2d + 3 evaluations); where |b| > rot_tol |mean H_ii| the
+ * full FD Hessian (2d^2 + 3 evaluations) and log det(-H) by Cholesky, else
+ * sum log(-H_ii).  Writes logl [n], logdet [n] (device), full_used [n] (host,
+ * nullable: 1 where the full Hessian was taken), then the combine of
+ * sb_combine_dev: order [n], mode_log_z [n] (sorted descending), log_z [1]
+ * (device), with lo, hi [d] (device) the box.  SB_E_NOTPD if -H is not
+ * positive definite at some mode (outputs written, that logdet NaN).  The
+ * call synchronises the stream.
+ * Workspace >= sb_user_mode_evidence_workspace_bytes(n, d). */
+size_t sb_user_mode_evidence_workspace_bytes(int32_t n, int32_t d);
+int32_t sb_user_mode_evidence_dev(const sb_user_fn *fn, int32_t n, int32_t d,
+                                  const double *modes, const double *params, const double *lo,
+                                  const double *hi, double eps, double rot_tol, double *logl,
+                                  double *logdet, int32_t *full_used, int32_t *order,
+                                  double *mode_log_z, double *log_z, void *workspace,
+                                  size_t ws_bytes, void *stream);
 
 /* L-BFGS two-loop direction (appendix "L-BFGS Optimization") for B
  * independent histories: S, Y [B][m][d] in logical order (oldest first),

@@ -35,6 +35,7 @@ EXPORTS = [
     "sb_lbfgs_timed_dev", "sb_precheck_workspace_bytes", "sb_precheck_dev",
     "sb_eig_reduce_workspace_bytes", "sb_eig_reduce_dev", "sb_user_compile", "sb_user_release",
     "sb_user_logl_dev", "sb_user_fd_workspace_bytes", "sb_user_fd_dev",
+    "sb_user_mode_evidence_workspace_bytes", "sb_user_mode_evidence_dev",
     "sb_dedup_workspace_bytes", "sb_dedup_dev", "sb_hessian_workspace_bytes", "sb_hessian_dev",
     "sb_cholesky_logdet_dev", "sb_cholesky_solve_dev", "sb_combine_dev", "sb_status_string",
     "sb_last_error", "sb_abi_version",
@@ -130,6 +131,9 @@ def lib():
             "sb_user_logl_dev": (i32, [vp, i64, i32, vp, vp, vp, vp]),
             "sb_user_fd_workspace_bytes": (sz, [i64, i32, i32]),
             "sb_user_fd_dev": (i32, [vp, i64, i32, vp, vp, f64, vp, vp, vp, vp, vp, vp, sz, vp]),
+            "sb_user_mode_evidence_workspace_bytes": (sz, [i32, i32]),
+            "sb_user_mode_evidence_dev": (i32, [vp, i32, i32, vp, vp, vp, vp, f64, f64, vp, vp,
+                                                vp, vp, vp, vp, vp, sz, vp]),
             "sb_dedup_workspace_bytes": (sz, [i32]),
             "sb_dedup_dev": (i32, [i32, i32, vp, vp, vp, f64, i32, vp, vp, i32, vp, vp, sz, vp]),
             "sb_hessian_workspace_bytes": (sz, [i32, i32, i32]),
@@ -582,6 +586,31 @@ class UserLogL:
                                   ws.data_ptr(), ws.numel(), _stream())
         _check(st, "sb_user_fd_dev")
         return dict(l=l, grad=g, hdiag=hd, H=H, probe_b=pb)
+
+    def mode_evidence(self, modes, lo, hi, eps: float, rot_tol: float, params=None):
+        """Laplace evidence at the given modes with FD curvature: log Z, per-mode log Z
+        (sorted), the sort order, l and log det per mode, and which modes took the full
+        Hessian."""
+        import torch
+
+        modes = modes.contiguous().to(torch.float64)
+        n, d = modes.shape
+        f64 = dict(dtype=torch.float64, device=modes.device)
+        l = torch.empty(n, **f64)
+        ld = torch.empty(n, **f64)
+        order = torch.empty(n, dtype=torch.int32, device=modes.device)
+        mlz = torch.empty(n, **f64)
+        lz = torch.empty(1, **f64)
+        full = (C.c_int32 * n)()
+        ws = _ws(lib().sb_user_mode_evidence_workspace_bytes(n, d), modes.device)
+        st = lib().sb_user_mode_evidence_dev(self.h, n, d, modes.data_ptr(), _ptr(params),
+                                             lo.data_ptr(), hi.data_ptr(), eps, rot_tol,
+                                             l.data_ptr(), ld.data_ptr(), full, order.data_ptr(),
+                                             mlz.data_ptr(), lz.data_ptr(), ws.data_ptr(),
+                                             ws.numel(), _stream())
+        _check(st, "sb_user_mode_evidence_dev")
+        return dict(log_z=float(lz.cpu()[0]), mode_log_z=mlz, order=order, logl=l, logdet=ld,
+                    full=list(full))
 
 
 def sb_dedup_dev(X, l, tau: float, valid=None, max_reps: int = 1024):

@@ -128,6 +128,44 @@ __global__ __launch_bounds__(256) void fd_hessian_kernel(int64_t B, int d, int64
   H[e] = h;
 }
 
+// Per mode: the rotation decision |b| > rot_tol |mean H_ii| (host), then the
+// diagonal modes' log det(-H) = sum log(-H_ii) (NaN if some H_ii >= 0).
+__global__ __launch_bounds__(256) void fd_diag_logdet_kernel(int n, int d, const double *hd,
+                                                             const int32_t *full,
+                                                             double *logdet) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n || full[k]) return;
+  double s = 0.0;
+  for (int i = 0; i < d; ++i) {
+    const double h = -hd[(int64_t)k * d + i];
+    s += h > 0.0 ? log(h) : (double)NAN;
+  }
+  logdet[k] = s;
+}
+
+// rows[i] = X[idx[i]] (d values each), thread per element
+__global__ __launch_bounds__(256) void gather_rows_kernel(int m, int d, const int32_t *idx,
+                                                          const double *X, double *out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)m * d) return;
+  out[e] = X[(int64_t)idx[e / d] * d + e % d];
+}
+
+// A = -H (the factorisation wants the positive definite -grad^2 l)
+__global__ __launch_bounds__(256) void negate_kernel(int64_t n, const double *H, double *A) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) A[e] = -H[e];
+}
+
+// logdet[idx[i]] = ld[i], or NaN where the factorisation failed
+__global__ __launch_bounds__(256) void scatter_logdet_kernel(int m, const int32_t *idx,
+                                                             const double *ld,
+                                                             const int32_t *info,
+                                                             double *logdet) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < m) logdet[idx[i]] = info[i] ? (double)NAN : ld[i];
+}
+
 }  // namespace sb
 
 using namespace sb;
@@ -256,6 +294,99 @@ int32_t sb_user_fd_dev(const sb_user_fn *fn, int64_t B, int32_t d, const double 
                        s, B, d, R, F, eps, H);
     SB_LAUNCH_CHECK();
   }
+  return SB_OK;
+}
+
+size_t sb_user_mode_evidence_workspace_bytes(int32_t n, int32_t d) {
+  if (n < 1 || d < 1) return 0;
+  const size_t nd = (size_t)n * d, ndd = nd * d;
+  return sb_user_fd_workspace_bytes(n, d, 0) + sb_user_fd_workspace_bytes(n, d, 1) +
+         3 * align_up(8 * nd) + 2 * align_up(8 * ndd) + 4 * align_up(8 * (size_t)n) +
+         3 * align_up(4 * (size_t)n) + 4096;
+}
+
+int32_t sb_user_mode_evidence_dev(const sb_user_fn *fn, int32_t n, int32_t d,
+                                  const double *modes, const double *params, const double *lo,
+                                  const double *hi, double eps, double rot_tol, double *logl,
+                                  double *logdet, int32_t *full_used, int32_t *order,
+                                  double *mode_log_z, double *log_z, void *workspace,
+                                  size_t ws_bytes, void *stream) {
+  if (!fn || n < 1 || d < 1 || !modes || !lo || !hi || !logl || !logdet || !order ||
+      !mode_log_z || !log_z)
+    return fail(SB_E_INVAL, "bad evidence-at-modes arguments");
+  if (!(eps > 0.0) || !std::isfinite(eps) || !(rot_tol >= 0.0))
+    return fail(SB_E_INVAL, "need eps > 0 and rot_tol >= 0");
+  if (!workspace || ws_bytes < sb_user_mode_evidence_workspace_bytes(n, d))
+    return fail(SB_E_NOMEM, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  Arena ar(workspace, ws_bytes);
+  const size_t ws0 = sb_user_fd_workspace_bytes(n, d, 0), ws1 = sb_user_fd_workspace_bytes(n, d, 1);
+  void *w0 = ar.take<char>(ws0);
+  void *w1 = ar.take<char>(ws1);
+  double *hd = ar.take<double>((size_t)n * d);
+  double *hd1 = ar.take<double>((size_t)n * d);
+  double *Xf = ar.take<double>((size_t)n * d);
+  double *H = ar.take<double>((size_t)n * d * d);
+  double *A = ar.take<double>((size_t)n * d * d);
+  double *pb = ar.take<double>(n);
+  double *l1 = ar.take<double>(n);
+  double *ldf = ar.take<double>(n);
+  ar.take<double>(n);
+  int32_t *fullv = ar.take<int32_t>(n);
+  int32_t *idx = ar.take<int32_t>(n);
+  int32_t *info = ar.take<int32_t>(n);
+  if (!ar.ok()) return fail(SB_E_NOMEM, "workspace too small");
+  // diagonal curvature and the rotation probe of every mode (2d + 3 evaluations each)
+  int st = sb_user_fd_dev(fn, n, d, modes, params, eps, logl, nullptr, hd, nullptr, pb, w0, ws0,
+                          stream);
+  if (st) return st;
+  std::vector<double> h_hd((size_t)n * d), h_pb(n);
+  SB_HIP(hipMemcpyAsync(h_hd.data(), hd, 8 * h_hd.size(), hipMemcpyDeviceToHost, s));
+  SB_HIP(hipMemcpyAsync(h_pb.data(), pb, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
+  SB_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> h_full(n, 0), h_idx;
+  for (int k = 0; k < n; ++k) {
+    double a = 0.0;
+    for (int i = 0; i < d; ++i) a += h_hd[(size_t)k * d + i];
+    a /= d;
+    if (std::fabs(h_pb[k]) > rot_tol * std::fabs(a)) {
+      h_full[k] = 1;
+      h_idx.push_back(k);
+    }
+  }
+  if (full_used) std::memcpy(full_used, h_full.data(), 4 * (size_t)n);
+  SB_HIP(hipMemcpyAsync(fullv, h_full.data(), 4 * (size_t)n, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(fd_diag_logdet_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n,
+                     d, hd, fullv, logdet);
+  SB_LAUNCH_CHECK();
+  const int m = (int)h_idx.size();
+  if (m > 0) {
+    // full FD Hessians of the rotated modes, log det(-H) by Cholesky
+    SB_HIP(hipMemcpyAsync(idx, h_idx.data(), 4 * (size_t)m, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)ceil_div((int64_t)m * d, 256)),
+                       dim3(256), 0, s, m, d, idx, modes, Xf);
+    SB_LAUNCH_CHECK();
+    if ((st = sb_user_fd_dev(fn, m, d, Xf, params, eps, l1, nullptr, hd1, H, nullptr, w1, ws1,
+                             stream)))
+      return st;
+    const int64_t nel = (int64_t)m * d * d;
+    hipLaunchKernelGGL(negate_kernel, dim3((unsigned)ceil_div(nel, 256)), dim3(256), 0, s, nel, H,
+                       A);
+    SB_LAUNCH_CHECK();
+    if ((st = chol_batched(m, d, A, A, info, s))) return st;
+    if ((st = launch_logdet(m, d, A, info, ldf, s))) return st;
+    hipLaunchKernelGGL(scatter_logdet_kernel, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s,
+                       m, idx, ldf, info, logdet);
+    SB_LAUNCH_CHECK();
+  }
+  if ((st = launch_combine(n, d, lo, hi, logl, logdet, modes, order, mode_log_z, log_z, s)))
+    return st;
+  std::vector<double> h_ld(n);
+  SB_HIP(hipMemcpyAsync(h_ld.data(), logdet, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
+  SB_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < n; ++k)
+    if (!std::isfinite(h_ld[k]))
+      return fail(SB_E_NOTPD, "mode %d: -H is not positive definite (not a maximum)", k);
   return SB_OK;
 }
 

@@ -103,6 +103,9 @@ def test_null_arguments():
     assert L.sb_user_compile(b"__device__ double f(const double *x, int d, const double *p)"
                              b" { return 0.0; }", b"1f", C.byref(h)) == _lib.E_INVAL
     assert L.sb_user_fd_workspace_bytes(0, 3, 0) == 0
+    assert L.sb_user_mode_evidence_dev(None, 1, 2, None, None, None, None, 1e-3, 1e-3, None, None,
+                                       None, None, None, None, None, 0, None) == _lib.E_INVAL
+    assert L.sb_user_mode_evidence_workspace_bytes(0, 2) == 0
 
 
 def test_user_likelihood_compiles_on_the_host():
