@@ -343,7 +343,9 @@ __device__ double gauss(const double *x, int d, const double *p) {
 def user_fd_leg(L, reps=5):
     """Generic user likelihood (a d = 64 Gaussian written as HIP source, compiled at run time):
     finite-difference gradients of 4096 points (2d + 3 evaluations each) and full FD Hessians
-    at 4 points (2d^2 + 3 each), HIP events on the stream; user-function evaluations per second."""
+    at 4 points (2d^2 + 3 each), HIP events on the stream, in user-function evaluations per
+    second; then the whole evidence path on it (discovery, FD L-BFGS, dedup, FD Laplace) against
+    the Gaussian's closed form."""
     import numpy as np
     import torch
     from paper_2601_19957_amd import synth
@@ -373,6 +375,23 @@ def user_fd_leg(L, reps=5):
         out[name] = dict(points=int(Xb.shape[0]), ms=ms, user_evals_per_s=n_ev / (ms * 1e-3))
     g = r["H"].cpu().numpy()
     out["fd_hessian"]["max_abs_err_vs_closed_form"] = float(np.max(np.abs(g + P[None])))
+    # the whole evidence path on the user likelihood (1024 rays x 32 points, 1024 starts)
+    lo = torch.full((d,), -30.0, dtype=torch.float64, device="cuda")
+    hi = torch.full((d,), 30.0, dtype=torch.float64, device="cuda")
+    cfg = synth.RunConfig(n_rays=1024, n_points=32, n_starts=1024, m=8, max_iter=0,
+                          max_modes=16, precision=synth.PREC_FP64, grad_tol=1e-7, dedup_tol=0.0,
+                          seed=2601199577)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev = fn.evidence(d, lo, hi, cfg, 1e-5, 1e-3, 1e-3, params)
+    dt = time.perf_counter() - t0
+    lam = np.linalg.eigvalsh(P)
+    ref = 0.5 * d * math.log(2 * math.pi) - 0.5 * float(np.sum(np.log(lam))) - d * math.log(60.0)
+    out["evidence_path"] = dict(status=ev.status, ms=dt * 1e3, n_modes=ev.n_modes,
+                                iterations=ev.iterations, grad_rows=ev.n_grad_evals,
+                                user_evals=ev.n_logl_evals + ev.n_grad_evals * (2 * d + 3),
+                                log_z=ev.log_z, closed_form=ref,
+                                abs_err=abs(ev.log_z - ref))
     return out
 
 

@@ -307,6 +307,25 @@ int32_t sb_user_fd_dev(const sb_user_fn *fn, int64_t B, int32_t d, const double 
  * positive definite at some mode (outputs written, that logdet NaN).  The
  * call synchronises the stream.
  * Workspace >= sb_user_mode_evidence_workspace_bytes(n, d). */
+/* The evidence path for a user likelihood, all in FP64 on the device: ray
+ * discovery (the rays of sb_discover_dev, l at every sample point, per-ray
+ * argmax, top n_starts rays), batched L-BFGS of sb_lbfgs_dev on central
+ * finite-difference gradients with step eps (2d + 3 user evaluations per
+ * row), leader de-duplication of the starts that converged inside the box,
+ * and sb_user_mode_evidence_dev with step eps_hess at the representatives
+ * (second differences divide rounding by eps^2, so their step is larger).  cfg as for
+ * sb_evidence (precision ignored); defaults here: grad_tol 1e-6 (FD
+ * gradients carry rounding of order eps_mach |l| / eps), dedup_tol
+ * 1e-4 max_i(hi_i - lo_i).  lo, hi [d] are device arrays.  Fills res as
+ * sb_evidence does (no seconds, no Newton polish: the modes are the L-BFGS end
+ * points); SB_E_NOMODE if no start converged, SB_E_CAPACITY beyond
+ * max_modes, SB_E_NOTPD if a representative is not a maximum.
+ * Workspace >= sb_user_evidence_workspace_bytes(d, cfg). */
+size_t sb_user_evidence_workspace_bytes(int32_t d, const sb_config *cfg);
+int32_t sb_user_evidence_dev(const sb_user_fn *fn, int32_t d, const double *params,
+                             const double *lo, const double *hi, const sb_config *cfg,
+                             double eps, double eps_hess, double rot_tol, sb_result *res,
+                             void *workspace, size_t ws_bytes, void *stream);
 size_t sb_user_mode_evidence_workspace_bytes(int32_t n, int32_t d);
 int32_t sb_user_mode_evidence_dev(const sb_user_fn *fn, int32_t n, int32_t d,
                                   const double *modes, const double *params, const double *lo,

@@ -36,6 +36,7 @@ EXPORTS = [
     "sb_eig_reduce_workspace_bytes", "sb_eig_reduce_dev", "sb_user_compile", "sb_user_release",
     "sb_user_logl_dev", "sb_user_fd_workspace_bytes", "sb_user_fd_dev",
     "sb_user_mode_evidence_workspace_bytes", "sb_user_mode_evidence_dev",
+    "sb_user_evidence_workspace_bytes", "sb_user_evidence_dev",
     "sb_dedup_workspace_bytes", "sb_dedup_dev", "sb_hessian_workspace_bytes", "sb_hessian_dev",
     "sb_cholesky_logdet_dev", "sb_cholesky_solve_dev", "sb_combine_dev", "sb_status_string",
     "sb_last_error", "sb_abi_version",
@@ -134,6 +135,9 @@ def lib():
             "sb_user_mode_evidence_workspace_bytes": (sz, [i32, i32]),
             "sb_user_mode_evidence_dev": (i32, [vp, i32, i32, vp, vp, vp, vp, f64, f64, vp, vp,
                                                 vp, vp, vp, vp, vp, sz, vp]),
+            "sb_user_evidence_workspace_bytes": (sz, [i32, vp]),
+            "sb_user_evidence_dev": (i32, [vp, i32, vp, vp, vp, vp, f64, f64, f64, vp, vp, sz,
+                                           vp]),
             "sb_dedup_workspace_bytes": (sz, [i32]),
             "sb_dedup_dev": (i32, [i32, i32, vp, vp, vp, f64, i32, vp, vp, i32, vp, vp, sz, vp]),
             "sb_hessian_workspace_bytes": (sz, [i32, i32, i32]),
@@ -611,6 +615,22 @@ class UserLogL:
         _check(st, "sb_user_mode_evidence_dev")
         return dict(log_z=float(lz.cpu()[0]), mode_log_z=mlz, order=order, logl=l, logdet=ld,
                     full=list(full))
+
+    def evidence(self, d: int, lo, hi, cfg, eps: float, eps_hess: float, rot_tol: float,
+                 params=None):
+        """The evidence path on this likelihood (discovery, FD L-BFGS, dedup, Laplace with FD
+        curvature); lo, hi device tensors, cfg a RunConfig."""
+        import torch
+
+        c = make_config(cfg)
+        cap = cfg.max_modes
+        r, arrs = _new_result(cap, d)
+        ws = _ws(lib().sb_user_evidence_workspace_bytes(d, C.byref(c)), lo.device)
+        st = lib().sb_user_evidence_dev(self.h, d, _ptr(params), lo.data_ptr(), hi.data_ptr(),
+                                        C.byref(c), eps, eps_hess, rot_tol, C.byref(r),
+                                        ws.data_ptr(), ws.numel(), _stream())
+        torch.cuda.synchronize()
+        return _to_result(st, r, cap, arrs)
 
 
 def sb_dedup_dev(X, l, tau: float, valid=None, max_reps: int = 1024):

@@ -18,6 +18,7 @@
 // b = (v^T H v - mean H_ii)/(d - 1).
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <cctype>
 #include <cmath>
 #include <cstdarg>
@@ -164,6 +165,45 @@ __global__ __launch_bounds__(256) void scatter_logdet_kernel(int m, const int32_
                                                              double *logdet) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < m) logdet[idx[i]] = info[i] ? (double)NAN : ld[i];
+}
+
+// Ray point j of ray r, p + t (q - p) with t = (j + 1/2)/n_pts, written out
+// for the user kernel (the same two-rounding expression as everywhere).
+__global__ __launch_bounds__(256) void ray_points_kernel(int R, int n_pts, int d,
+                                                         const double *P0, const double *P1,
+                                                         double *X) {
+#pragma clang fp contract(off)
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)R * n_pts * d) return;
+  const int64_t row = e / d;
+  const int j = (int)(e % d);
+  const int64_t ray = row / n_pts;
+  const int jj = (int)(row % n_pts);
+  const double t = ((double)jj + 0.5) / (double)n_pts;
+  const double p = P0[ray * d + j], q = P1[ray * d + j];
+  X[e] = p + t * (q - p);
+}
+
+// The L-BFGS rows listed in idx [count] (row r = slot * B + start) gathered
+// from the state's points, and their l and gradient scattered back.
+__global__ __launch_bounds__(256) void gather_state_rows_kernel(int count, int d,
+                                                                const int32_t *idx,
+                                                                const double *X, double *out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)count * d) return;
+  out[e] = X[(int64_t)idx[e / d] * d + e % d];
+}
+
+__global__ __launch_bounds__(256) void scatter_state_rows_kernel(int count, int d,
+                                                                 const int32_t *idx,
+                                                                 const double *l, const double *g,
+                                                                 double *F, double *G) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)count * d) return;
+  const int64_t i = e / d;
+  const int64_t r = idx[i];
+  G[r * d + e % d] = g[e];
+  if (e % d == 0) F[r] = l[i];
 }
 
 }  // namespace sb
@@ -387,6 +427,217 @@ int32_t sb_user_mode_evidence_dev(const sb_user_fn *fn, int32_t n, int32_t d,
   for (int k = 0; k < n; ++k)
     if (!std::isfinite(h_ld[k]))
       return fail(SB_E_NOTPD, "mode %d: -H is not positive definite (not a maximum)", k);
+  return SB_OK;
+}
+
+// Rows of the evidence pipeline's workspace for a user likelihood.
+struct UserLayout {
+  double *P0, *P1, *Xpts, *lpts, *best_l, *X0, *Xg, *lg, *gg, *Xend, *lend, *modes;
+  int32_t *best_j, *start_ray, *status, *rep_of, *reps, *order;
+  uint8_t *valid;
+  double *mlogl, *mlogdet, *mlz, *logz;
+  void *fd_ws, *dd_ws, *me_ws;
+  size_t fd_bytes, dd_bytes, me_bytes;
+  LbfgsBuffers lb;
+};
+
+static int user_layout(Arena &ar, UserLayout &U, int d, const sb_config *c) {
+  const int64_t R = c->n_rays, NP = (int64_t)c->n_rays * c->n_points, B = c->n_starts;
+  const int cap = c->max_modes;
+  U.P0 = ar.take<double>((size_t)R * d);
+  U.P1 = ar.take<double>((size_t)R * d);
+  U.Xpts = ar.take<double>((size_t)NP * d);
+  U.lpts = ar.take<double>(NP);
+  U.best_l = ar.take<double>(R);
+  U.best_j = ar.take<int32_t>(R);
+  U.start_ray = ar.take<int32_t>(B);
+  U.X0 = ar.take<double>((size_t)B * d);
+  U.Xg = ar.take<double>((size_t)2 * B * d);
+  U.lg = ar.take<double>(2 * B);
+  U.gg = ar.take<double>((size_t)2 * B * d);
+  U.Xend = ar.take<double>((size_t)B * d);
+  U.lend = ar.take<double>(B);
+  U.status = ar.take<int32_t>(B);
+  U.valid = ar.take<uint8_t>(B);
+  U.rep_of = ar.take<int32_t>(B);
+  U.reps = ar.take<int32_t>(cap);
+  U.modes = ar.take<double>((size_t)cap * d);
+  U.order = ar.take<int32_t>(cap);
+  U.mlogl = ar.take<double>(cap);
+  U.mlogdet = ar.take<double>(cap);
+  U.mlz = ar.take<double>(cap);
+  U.logz = ar.take<double>(4);
+  U.fd_bytes = sb_user_fd_workspace_bytes(2 * B, d, 0);
+  U.fd_ws = ar.take<char>(U.fd_bytes);
+  U.dd_bytes = dedup_ws_bytes((int)B) + 1024;
+  U.dd_ws = ar.take<char>(U.dd_bytes);
+  U.me_bytes = sb_user_mode_evidence_workspace_bytes(cap, d);
+  U.me_ws = ar.take<char>(U.me_bytes);
+  U.lb.dtype = DT_F64;
+  U.lb.B = B;
+  U.lb.d = d;
+  U.lb.m = c->m;
+  if (lbfgs_carve(ar, U.lb)) return SB_E_NOMEM;
+  return ar.ok() ? SB_OK : SB_E_NOMEM;
+}
+
+static bool user_cfg_ok(const sb_config *c) {
+  return c && c->n_rays >= 1 && c->n_points >= 1 && c->n_starts >= 1 &&
+         c->n_starts <= c->n_rays && c->m >= 1 && c->m <= kMaxHist && c->max_modes >= 1;
+}
+
+size_t sb_user_evidence_workspace_bytes(int32_t d, const sb_config *cfg) {
+  if (d < 1 || !user_cfg_ok(cfg)) return 0;
+  Arena ar(nullptr, 0);
+  UserLayout U;
+  user_layout(ar, U, d, cfg);
+  return ar.off + 4096;
+}
+
+// FD l and gradient at `count` L-BFGS rows listed in idx (host count).
+static int user_eval_rows(const sb_user_fn *fn, UserLayout &U, int d, const double *params,
+                          double eps, const int32_t *idx, int count, hipStream_t s) {
+  if (count <= 0) return SB_OK;
+  hipLaunchKernelGGL(gather_state_rows_kernel, dim3((unsigned)ceil_div((int64_t)count * d, 256)),
+                     dim3(256), 0, s, count, d, idx, (const double *)U.lb.X, U.Xg);
+  SB_LAUNCH_CHECK();
+  int st = sb_user_fd_dev(fn, count, d, U.Xg, params, eps, U.lg, U.gg, nullptr, nullptr,
+                          nullptr, U.fd_ws, U.fd_bytes, s);
+  if (st) return st;
+  hipLaunchKernelGGL(scatter_state_rows_kernel, dim3((unsigned)ceil_div((int64_t)count * d, 256)),
+                     dim3(256), 0, s, count, d, idx, U.lg, U.gg, (double *)U.lb.F,
+                     (double *)U.lb.G);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+int32_t sb_user_evidence_dev(const sb_user_fn *fn, int32_t d, const double *params,
+                             const double *lo, const double *hi, const sb_config *cfg,
+                             double eps, double eps_hess, double rot_tol, sb_result *res,
+                             void *workspace, size_t ws_bytes, void *stream) {
+  if (!fn || d < 1 || !lo || !hi || !res) return fail(SB_E_INVAL, "bad user evidence arguments");
+  if (!user_cfg_ok(cfg)) return fail(SB_E_INVAL, "bad configuration");
+  if (!(eps > 0.0) || !std::isfinite(eps) || !(eps_hess > 0.0) || !std::isfinite(eps_hess) ||
+      !(rot_tol >= 0.0))
+    return fail(SB_E_INVAL, "need eps > 0, eps_hess > 0 and rot_tol >= 0");
+  if (!workspace || ws_bytes < sb_user_evidence_workspace_bytes(d, cfg))
+    return fail(SB_E_NOMEM, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  for (double &t : res->seconds) t = 0.0;
+  Arena ar(workspace, ws_bytes);
+  UserLayout U;
+  if (user_layout(ar, U, d, cfg)) return fail(SB_E_NOMEM, "workspace too small");
+  const int R = cfg->n_rays, NPTS = cfg->n_points, B = cfg->n_starts, cap = cfg->max_modes;
+  const int max_iter = cfg->max_iter > 0 ? cfg->max_iter : 10 * d + 200;
+  const double tol = cfg->grad_tol > 0 ? cfg->grad_tol : 1e-6;
+  std::vector<double> hlo(d), hhi(d);
+  SB_HIP(hipMemcpyAsync(hlo.data(), lo, 8 * (size_t)d, hipMemcpyDeviceToHost, s));
+  SB_HIP(hipMemcpyAsync(hhi.data(), hi, 8 * (size_t)d, hipMemcpyDeviceToHost, s));
+  SB_HIP(hipStreamSynchronize(s));
+  double wmax = 0.0;
+  for (int i = 0; i < d; ++i) {
+    if (!(std::isfinite(hlo[i]) && std::isfinite(hhi[i]) && hlo[i] < hhi[i]))
+      return fail(SB_E_INVAL, "box coordinate %d is not a finite interval", i);
+    wmax = std::max(wmax, hhi[i] - hlo[i]);
+  }
+  const double tau = cfg->dedup_tol > 0 ? cfg->dedup_tol : 1e-4 * wmax;
+  int st;
+  // discovery: rays, l at every sample point, per-ray argmax, top starts
+  if ((st = launch_rays(d, lo, hi, R, cfg->seed, 0u, U.P0, U.P1, nullptr, nullptr, s)))
+    return st;
+  const int64_t NP = (int64_t)R * NPTS;
+  hipLaunchKernelGGL(ray_points_kernel, dim3((unsigned)ceil_div(NP * d, 256)), dim3(256), 0, s, R,
+                     NPTS, d, U.P0, U.P1, U.Xpts);
+  SB_LAUNCH_CHECK();
+  if ((st = user_eval(fn, NP, d, U.Xpts, d, params, U.lpts, s))) return st;
+  if ((st = launch_ray_argmax(R, NPTS, SB_DTYPE_F64, U.lpts, U.best_l, U.best_j, s))) return st;
+  if ((st = launch_topn(R, B, U.best_l, U.start_ray, s))) return st;
+  if ((st = launch_gather_starts(d, NPTS, B, U.start_ray, U.best_j, U.P0, U.P1, U.X0, s)))
+    return st;
+  // batched L-BFGS on FD gradients (2d + 3 user evaluations per row)
+  LbfgsBuffers &lb = U.lb;
+  if ((st = launch_lbfgs_init(lb, U.X0, s))) return st;
+  std::vector<int32_t> all(B);
+  for (int i = 0; i < B; ++i) all[i] = i;
+  SB_HIP(hipMemcpyAsync(lb.idx, all.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s));
+  if ((st = user_eval_rows(fn, U, d, params, eps, lb.idx, B, s))) return st;
+  int64_t grad_evals = B;
+  int steps = 0;
+  for (; steps < 42 * max_iter + 64; ++steps) {
+    if ((st = launch_lbfgs_step(lb, max_iter, tol, s))) return st;
+    if ((st = launch_compact(lb, s))) return st;
+    int32_t cnt = 0;
+    SB_HIP(hipMemcpyAsync(&cnt, lb.count, 4, hipMemcpyDeviceToHost, s));
+    SB_HIP(hipStreamSynchronize(s));
+    if (cnt <= 0) break;
+    if ((st = user_eval_rows(fn, U, d, params, eps, lb.idx, cnt, s))) return st;
+    grad_evals += cnt;
+  }
+  if ((st = launch_lbfgs_gather(lb, U.Xend, U.lend, true, nullptr, U.status, nullptr, s)))
+    return st;
+  // converged (or iteration-capped) end points inside the box, leader dedup
+  std::vector<int32_t> h_st(B);
+  std::vector<double> h_x((size_t)B * d);
+  SB_HIP(hipMemcpyAsync(h_st.data(), U.status, 4 * (size_t)B, hipMemcpyDeviceToHost, s));
+  SB_HIP(hipMemcpyAsync(h_x.data(), U.Xend, 8 * h_x.size(), hipMemcpyDeviceToHost, s));
+  SB_HIP(hipStreamSynchronize(s));
+  std::vector<uint8_t> h_valid(B, 0);
+  int n_dead = 0;
+  for (int b = 0; b < B; ++b) {
+    bool ok = h_st[b] == 1;
+    for (int i = 0; ok && i < d; ++i)
+      ok = h_x[(size_t)b * d + i] >= hlo[i] && h_x[(size_t)b * d + i] <= hhi[i];
+    h_valid[b] = ok ? 1 : 0;
+    n_dead += h_st[b] == 4;
+  }
+  SB_HIP(hipMemcpyAsync(U.valid, h_valid.data(), (size_t)B, hipMemcpyHostToDevice, s));
+  int n_reps = 0;
+  Arena dar(U.dd_ws, U.dd_bytes);
+  st = dedup_run(B, d, U.Xend, SB_DTYPE_F64, U.lend, SB_DTYPE_F64, U.valid, tau, U.rep_of, U.reps,
+                 cap, &n_reps, dar, s);
+  res->n_modes = n_reps;
+  res->iterations = steps;
+  res->n_logl_evals = NP;
+  res->n_grad_evals = grad_evals;
+  res->n_dead_starts = n_dead;
+  if (st) {
+    res->log_z = NAN;
+    return st == SB_E_CAPACITY ? fail(st, "%d modes exceed max_modes = %d", n_reps, cap) : st;
+  }
+  if (n_reps == 0) {
+    res->log_z = -INFINITY;
+    return fail(SB_E_NOMODE, "no start converged to a maximum inside the box");
+  }
+  hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)ceil_div((int64_t)n_reps * d, 256)),
+                     dim3(256), 0, s, n_reps, d, U.reps, U.Xend, U.modes);
+  SB_LAUNCH_CHECK();
+  std::vector<int32_t> full(n_reps);
+  st = sb_user_mode_evidence_dev(fn, n_reps, d, U.modes, params, lo, hi, eps_hess, rot_tol, U.mlogl,
+                                 U.mlogdet, full.data(), U.order, U.mlz, U.logz, U.me_ws,
+                                 U.me_bytes, s);
+  if (st) {
+    res->log_z = NAN;
+    return st;
+  }
+  std::vector<int32_t> h_order(n_reps);
+  std::vector<double> h_modes((size_t)n_reps * d), h_l(n_reps), h_ld(n_reps), h_mlz(n_reps);
+  double h_lz = NAN;
+  SB_HIP(hipMemcpyAsync(h_order.data(), U.order, 4 * (size_t)n_reps, hipMemcpyDeviceToHost, s));
+  SB_HIP(hipMemcpyAsync(h_modes.data(), U.modes, 8 * h_modes.size(), hipMemcpyDeviceToHost, s));
+  SB_HIP(hipMemcpyAsync(h_l.data(), U.mlogl, 8 * (size_t)n_reps, hipMemcpyDeviceToHost, s));
+  SB_HIP(hipMemcpyAsync(h_ld.data(), U.mlogdet, 8 * (size_t)n_reps, hipMemcpyDeviceToHost, s));
+  SB_HIP(hipMemcpyAsync(h_mlz.data(), U.mlz, 8 * (size_t)n_reps, hipMemcpyDeviceToHost, s));
+  SB_HIP(hipMemcpyAsync(&h_lz, U.logz, 8, hipMemcpyDeviceToHost, s));
+  SB_HIP(hipStreamSynchronize(s));
+  res->log_z = h_lz;
+  for (int k = 0; k < n_reps; ++k) {
+    const int src = h_order[k];
+    if (res->modes)
+      std::memcpy(res->modes + (size_t)k * d, h_modes.data() + (size_t)src * d, 8 * (size_t)d);
+    if (res->mode_log_z) res->mode_log_z[k] = h_mlz[k];
+    if (res->mode_logl) res->mode_logl[k] = h_l[src];
+    if (res->log_det_h) res->log_det_h[k] = h_ld[src];
+  }
   return SB_OK;
 }
 

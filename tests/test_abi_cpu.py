@@ -106,6 +106,9 @@ def test_null_arguments():
     assert L.sb_user_mode_evidence_dev(None, 1, 2, None, None, None, None, 1e-3, 1e-3, None, None,
                                        None, None, None, None, None, 0, None) == _lib.E_INVAL
     assert L.sb_user_mode_evidence_workspace_bytes(0, 2) == 0
+    assert L.sb_user_evidence_workspace_bytes(3, None) == 0
+    assert L.sb_user_evidence_dev(None, 3, None, None, None, None, 1e-5, 1e-3, 1e-3, None, None,
+                                  0, None) == _lib.E_INVAL
 
 
 def test_user_likelihood_compiles_on_the_host():

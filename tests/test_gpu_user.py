@@ -200,3 +200,30 @@ def test_user_mode_evidence_diagonal_branch(L):
     bad = np.concatenate([-np.diag(1.0 / lam).ravel(), mu, [0.0]])
     with pytest.raises(L.SbError):
         fn.mode_evidence(dev(mu[None]), lo, hi, 1e-3, 1e-3, dev(bad))
+
+
+def test_user_evidence_path_mixture(L):
+    """The whole path on a user likelihood: a normalised K = 3 mixture in d = 7 written as HIP
+    source; discovery, FD L-BFGS, dedup and the FD Laplace evidence find the three modes and
+    log Z = -log V (the mixture's mass) to the accuracy FD gradients allow, as the oracle's
+    reference mode set does."""
+    rng = np.random.Generator(np.random.PCG64(98))
+    d, K = 7, 3
+    prob = synth.gaussian_mixture(rng, d, K, -8.0, 8.0, 0.05, 1.0, 12.0, box_half=12.0,
+                                  norm=synth.NORM_DENSITY, linf_min=1.0)
+    st, beta, _ = O.prep(prob)
+    params = [float(K)]
+    for k in range(K):
+        params += [beta[k]] + list(prob.mu[k]) + list(prob.prec[k].ravel())
+    fn = L.UserLogL(MIX_SRC, "mix")
+    cfg = synth.RunConfig(n_rays=512, n_points=32, n_starts=512, m=8, max_iter=0, max_modes=16,
+                          precision=synth.PREC_FP64, grad_tol=1e-7, dedup_tol=0.0,
+                          seed=2601199599)
+    r = fn.evidence(d, dev(prob.lo), dev(prob.hi), cfg, 1e-5, 1e-3, 1e-3, dev(np.array(params)))
+    assert r.status == 0, L.last_error()
+    ref = O.reference_modes(prob)
+    assert r.n_modes == K == ref.n_modes
+    assert abs(r.log_z - ref.log_z) < 1e-6
+    # modes: each within the FD-gradient accuracy of a reference mode
+    dist = np.max(np.abs(r.modes[:, None, :] - ref.modes[None, :, :]), axis=2)
+    assert np.all(np.min(dist, axis=1) < 1e-5)
