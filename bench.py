@@ -455,6 +455,8 @@ def main() -> int:
                     help="skip the eigen-reduction measurement")
     ap.add_argument("--no-user", action="store_true",
                     help="skip the generic-likelihood finite-difference measurement")
+    ap.add_argument("--modules-only", action="store_true",
+                    help="only the preprocessing, eigen-reduction and user-likelihood legs")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the roofline kernel timing (for profiling that kernel)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -485,6 +487,11 @@ def main() -> int:
     wl = workload(names, args.starts)
     big = names[-1]
     prob_big, cfg_big = wl[big]
+    if args.modules_only:
+        print(json.dumps(dict(modules_only=True, precheck=precheck_leg(L, prob_big, big),
+                              eig_reduce=reduce_leg(L, prob_big, big), user_fd=user_fd_leg(L))),
+              flush=True)
+        return 0
 
     # ---- roofline of the dominant kernel: the L-BFGS step at full batch
     log("timing the L-BFGS step at full batch")

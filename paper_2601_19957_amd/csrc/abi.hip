@@ -439,9 +439,13 @@ int32_t sb_logl_grad_dev(const sb_model_dev *mdl, int64_t B, const void *X, void
   a.kind = 0;
   a.X = X;
   a.ldx = m.d;
+  // a single Gaussian's gradient is -Y: the contraction stores it straight
+  // into grad and the epilogue forms l only
+  const bool direct = grad && m.K == 1 && m.family == SB_FAMILY_GAUSS_MIX;
   QuadOut o;
-  o.Y = Y;
-  o.ldy = (int64_t)m.K * m.d;
+  o.Y = direct ? grad : Y;
+  o.ldy = direct ? (int64_t)m.d : (int64_t)m.K * m.d;
+  o.yneg = direct;
   o.qpart = qp;
   const TuneProbe pr{a, o};
   TileCfg t = autotune_tiles(dtype, m, B, (hipStream_t)stream, &pr);
@@ -450,10 +454,10 @@ int32_t sb_logl_grad_dev(const sb_model_dev *mdl, int64_t B, const void *X, void
   f.M = B;
   f.qpart = qp;
   f.ntn = o.ntn;
-  f.Y = Y;
+  f.Y = direct ? nullptr : Y;
   f.ldy = o.ldy;
   f.logl = logl;
-  f.grad = grad;
+  f.grad = direct ? nullptr : grad;
   f.ldg = m.d;
   return launch_finish(dtype, m, f, (hipStream_t)stream);
 }

@@ -81,6 +81,7 @@ struct GemmParams {
   int64_t ldy;
   void *qpart;
   GroupView gv;  // grouped mode only
+  int yneg = 0;  // store -Y (a single Gaussian's gradient); q still uses Y
 };
 
 // Value of point `row` at coordinate j (type TIn), without the mean.
@@ -197,7 +198,7 @@ __global__ __launch_bounds__(256) void quad_gemm_kernel(GemmParams g) {
         const int n = n0 + wn * WN + j * 16 + lc;
         if (n >= d) continue;
         TAcc yv = acc[i][j][v];
-        if (Y) Y[row * g.ldy + (int64_t)k * d + n] = yv;
+        if (Y) Y[row * g.ldy + (int64_t)k * d + n] = g.yneg ? -yv : yv;
         TIn x = point_value<TIn>(g.a, row, d, n);
         TAcc dl = (TAcc)(mu ? x - mu[n] : x);
         qrow[i][v] += dl * yv;
@@ -497,7 +498,7 @@ __global__ __launch_bounds__(256) void quad_gemm_vec_kernel(GemmParams g) {
         const int n = n0 + wn * WN + j * 16 + lc;
         if (n >= d) continue;
         TAcc yv = acc[i][j][v];
-        if (Y) Y[ybase + row * ystride + (int64_t)k * d + n] = yv;
+        if (Y) Y[ybase + row * ystride + (int64_t)k * d + n] = g.yneg ? -yv : yv;
         TIn x;
         if constexpr (KIND == 0) {
           x = pa[n];
@@ -575,12 +576,17 @@ int launch_quad_gemm(int dtype, const Model &m, const ASrc &a, int64_t M, const 
     if (!mb.Phi) mb.Phi = (const bf16_t *)m.Plp;
     return launch_quad_gemm_bf16(1, mb, a, M, count, o, s, t);
   }
+  if (o.ymap || o.sumsq || o.gcnt) {
+    set_error("row-mapped, grouped or sum-of-squares outputs need the BF16 matrix-core kernel");
+    return SB_E_UNSUPPORTED;
+  }
   GemmParams p;
   p.a = a;
   p.M = M;
   p.count = count;
   p.d = m.d;
   p.K = m.K;
+  p.yneg = o.yneg ? 1 : 0;
   if (t.bn != 64 && t.bn != 128) t.bn = 128;
   if (t.bm != 64 && t.bm != 128) t.bm = 128;
   o.ntn = (int)ceil_div(m.d, t.bn);
