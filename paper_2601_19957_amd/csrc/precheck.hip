@@ -71,20 +71,22 @@ __global__ __launch_bounds__(256) void precheck_rank_kernel(int d, const double 
 }
 
 // One workgroup: median and maximum, the classes, the marginal terms and
-// their sum in index order, and the counts (active, flat, soft, non-finite).
+// their sum (strided per-thread sums, then a fixed tree), and the counts
+// (active, flat, soft, non-finite).
 __global__ __launch_bounds__(256) void precheck_classify_kernel(int d, const double *lo,
                                                                 const double *hi, double eps_flat,
                                                                 double eps_soft, const double *s,
                                                                 const double *sorted,
-                                                                int32_t *cls, double *term,
-                                                                double *logz,
+                                                                int32_t *cls, double *logz,
                                                                 int32_t *counts) {
   __shared__ int cnt[4];
+  __shared__ double part[256];
   if (threadIdx.x < 4) cnt[threadIdx.x] = 0;
   __syncthreads();
   const double med = (d % 2) ? sorted[d / 2] : 0.5 * (sorted[d / 2 - 1] + sorted[d / 2]);
   const double mx = sorted[d - 1];
   int na = 0, nf = 0, ns = 0, nb = 0;
+  double acc = 0.0;
   for (int i = threadIdx.x; i < d; i += 256) {
     const double si = s[i];
     int c = 0;
@@ -102,7 +104,14 @@ __global__ __launch_bounds__(256) void precheck_classify_kernel(int d, const dou
     nf += c == 1;
     ns += c == 2;
     cls[i] = c;
-    term[i] = t;
+    acc += t;
+  }
+  // the terms' sum: per-thread strided partial sums, then a fixed tree
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
   }
   na = wave_sum(na);
   nf = wave_sum(nf);
@@ -116,9 +125,7 @@ __global__ __launch_bounds__(256) void precheck_classify_kernel(int d, const dou
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double acc = 0.0;
-    for (int i = 0; i < d; ++i) acc += term[i];
-    *logz = cnt[3] ? (double)NAN : acc;
+    *logz = cnt[3] ? (double)NAN : part[0];
     for (int k = 0; k < 4; ++k) counts[k] = cnt[k];
   }
 }
@@ -139,8 +146,7 @@ int run_precheck(const Model &m, const double *lo, const double *hi, double eps_
   double *l = ar.take<double>(rows);
   double *qp = ar.take<double>((size_t)rows * m.K * ceil_div(d, 64));
   double *sorted = ar.take<double>(d);
-  double *term = ar.take<double>(d);
-  ar.take<double>(d);
+  ar.take<double>(2 * (size_t)d);
   int32_t *counts = ar.take<int32_t>(4);
   if (!ar.ok()) {
     set_error("precheck: workspace too small");
@@ -172,7 +178,7 @@ int run_precheck(const Model &m, const double *lo, const double *hi, double eps_
                      l, s, sorted);
   SB_LAUNCH_CHECK();
   hipLaunchKernelGGL(precheck_classify_kernel, dim3(1), dim3(256), 0, st, d, lo, hi, eps_flat,
-                     eps_soft, s, sorted, cls, term, logz, counts);
+                     eps_soft, s, sorted, cls, logz, counts);
   SB_LAUNCH_CHECK();
   SB_HIP(hipMemcpyAsync(counts_host, counts, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   SB_HIP(hipStreamSynchronize(st));

@@ -8,8 +8,9 @@
 // ordering of the cyclic Jacobi method).  A sweep is n' - 1 rounds (n' = n
 // rounded up to even) of n'/2 disjoint rotations in the round-robin
 // ("circle") order; within a round the rotation angles come from the matrix
-// before the round, then all row rotations (J^T A), then all column rotations
-// (A J, V J) run as whole-matrix passes, since disjoint pairs touch disjoint
+// before the round, then J^T A J and V J are formed: for n up to 4096 by one
+// workgroup per pair that stages its two rows in LDS, otherwise by a row pass
+// (J^T A) and a column pass (A J, V J), since disjoint pairs touch disjoint
 // rows and columns.  Sweeps stop when the off-diagonal Frobenius norm is at
 // most 4 n eps of the whole norm (read by the host after every sweep) or after
 // 40 sweeps.  C matrices share every launch.
@@ -123,13 +124,80 @@ __global__ __launch_bounds__(256) void jacobi_cols_kernel(int C, int n, int np, 
   v[q] = ss * x + cc * y;
 }
 
-// One workgroup per matrix: off-diagonal and total sums of squares.
-__global__ __launch_bounds__(256) void jacobi_norms_kernel(int n, const double *A, double *out) {
+// Whole round for one pair (p, q) of one matrix, rows p and q only: row p of
+// J^T A J is (c A_p - s A_q) J and row q is (s A_p + c A_q) J, so the row
+// rotation of the pair and then every pair's column rotation apply within
+// these two rows, staged in LDS; rows p and q of V get the column rotations
+// (V J).  Every row belongs to one pair, so the launch covers A and V, each
+// row read and written once, coalesced.  A pair with the padding index
+// (odd n) carries its real row through the column rotations only.
+constexpr int kJacobiLdsN = 4096;  // rows staged in LDS up to this n
+__global__ __launch_bounds__(256) void jacobi_round_kernel(int C, int n, int np, int r, double *A,
+                                                           double *V, const double *cs) {
+  extern __shared__ double rows[];  // [2][n]
+  const int half = np / 2;
+  const int64_t ck = blockIdx.x;
+  if (ck >= (int64_t)C * half) return;
+  const int64_t c = ck / half;
+  const int k = (int)(ck % half);
+  int p, q;
+  jacobi_pair(np, r, k, p, q);
+  const bool two = q < n;  // else p pairs with the padding index
+  const double cc = cs[2 * ck], ss = cs[2 * ck + 1];
+  double *rp = rows, *rq = rows + n;
+  const int64_t nn = (int64_t)n * n;
+  for (int pass = 0; pass < 2; ++pass) {  // 0: A, 1: V
+    double *M = (pass == 0 ? A : V) + c * nn;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      const double x = M[(int64_t)p * n + j];
+      const double y = two ? M[(int64_t)q * n + j] : 0.0;
+      if (pass == 0 && two) {
+        rp[j] = cc * x - ss * y;
+        rq[j] = ss * x + cc * y;
+      } else {
+        rp[j] = x;
+        rq[j] = y;
+      }
+    }
+    __syncthreads();
+    for (int k2 = threadIdx.x; k2 < half; k2 += blockDim.x) {
+      int p2, q2;
+      jacobi_pair(np, r, k2, p2, q2);
+      if (q2 >= n) continue;
+      const double c2 = cs[2 * (c * half + k2)], s2 = cs[2 * (c * half + k2) + 1];
+      double x = rp[p2], y = rp[q2];
+      rp[p2] = c2 * x - s2 * y;
+      rp[q2] = s2 * x + c2 * y;
+      if (two) {
+        x = rq[p2];
+        y = rq[q2];
+        rq[p2] = c2 * x - s2 * y;
+        rq[q2] = s2 * x + c2 * y;
+      }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      M[(int64_t)p * n + j] = rp[j];
+      if (two) M[(int64_t)q * n + j] = rq[j];
+    }
+    __syncthreads();
+  }
+}
+
+// Off-diagonal and total sums of squares: kNormParts workgroups per matrix
+// write partial sums of rows [part n / kNormParts, ...), then one thread per
+// matrix adds the parts in order (a fixed summation order, so the sweep count
+// is reproducible).
+constexpr int kNormParts = 64;
+__global__ __launch_bounds__(256) void jacobi_norms_kernel(int n, const double *A,
+                                                           double *part) {
   __shared__ double red[2][4];
-  const int64_t c = blockIdx.x;
+  const int64_t c = blockIdx.x / kNormParts;
+  const int pi = blockIdx.x % kNormParts;
+  const int r0 = (int)((int64_t)n * pi / kNormParts), r1 = (int)((int64_t)n * (pi + 1) / kNormParts);
   const double *a = A + c * (int64_t)n * n;
   double off = 0.0, tot = 0.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += 256) {
+  for (int64_t e = (int64_t)r0 * n + threadIdx.x; e < (int64_t)r1 * n; e += 256) {
     const double v = a[e] * a[e];
     tot += v;
     if (e / n != e % n) off += v;
@@ -143,9 +211,21 @@ __global__ __launch_bounds__(256) void jacobi_norms_kernel(int n, const double *
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    out[2 * c] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    out[2 * c + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    part[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    part[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
   }
+}
+
+__global__ void jacobi_norms_sum_kernel(int C, const double *part, double *out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  double off = 0.0, tot = 0.0;
+  for (int i = 0; i < kNormParts; ++i) {
+    off += part[2 * ((int64_t)c * kNormParts + i)];
+    tot += part[2 * ((int64_t)c * kNormParts + i) + 1];
+  }
+  out[2 * c] = off;
+  out[2 * c + 1] = tot;
 }
 
 // Eigenvalues in descending order (ties to the lower index): the rank of
@@ -228,7 +308,7 @@ size_t reduce_ws_bytes(int C, int n) {
   const size_t nn = (size_t)n * n, np = (size_t)(n + (n & 1));
   return 2 * align_up(8 * (size_t)C * nn) + align_up(8 * (size_t)C * np) +
          align_up(8 * 2 * (size_t)C) + align_up(8 * (size_t)C * n) + align_up(4 * (size_t)C) +
-         align_up(4 * (size_t)C * n) + 1024;
+         align_up(4 * (size_t)C * n) + align_up(16 * (size_t)C * kNormParts) + 1024;
 }
 
 int run_eig_reduce(int C, int n, const double *H, const double *lo, const double *hi,
@@ -246,6 +326,7 @@ int run_eig_reduce(int C, int n, const double *H, const double *lo, const double
   double *term = ar.take<double>((size_t)C * n);
   int32_t *deff = ar.take<int32_t>(C);
   int32_t *rank_of = ar.take<int32_t>((size_t)C * n);
+  double *nparts = ar.take<double>(2 * (size_t)C * kNormParts);
   if (!ar.ok()) {
     set_error("eigen reduction: workspace too small");
     return SB_E_NOMEM;
@@ -261,7 +342,10 @@ int run_eig_reduce(int C, int n, const double *H, const double *lo, const double
   const double tol = 4.0 * n * 2.220446049250313e-16, tol2 = tol * tol;
   int sweeps = 0;
   for (; sweeps < 40 && n > 1; ++sweeps) {
-    hipLaunchKernelGGL(jacobi_norms_kernel, dim3(C), dim3(256), 0, st, n, A, nrm);
+    hipLaunchKernelGGL(jacobi_norms_kernel, dim3((unsigned)(C * kNormParts)), dim3(256), 0, st, n,
+                       A, nparts);
+    hipLaunchKernelGGL(jacobi_norms_sum_kernel, dim3((unsigned)ceil_div(C, 64)), dim3(64), 0, st,
+                       C, nparts, nrm);
     SB_LAUNCH_CHECK();
     SB_HIP(hipMemcpyAsync(hn.data(), nrm, 16 * (size_t)C, hipMemcpyDeviceToHost, st));
     SB_HIP(hipStreamSynchronize(st));
@@ -277,9 +361,15 @@ int run_eig_reduce(int C, int n, const double *H, const double *lo, const double
     for (int r = 0; r < np - 1; ++r) {
       hipLaunchKernelGGL(jacobi_angles_kernel, dim3(g_pairs), dim3(256), 0, st, C, n, np, r, A,
                          cs);
-      hipLaunchKernelGGL(jacobi_rows_kernel, dim3(g_rot), dim3(256), 0, st, C, n, np, r, A, cs);
-      hipLaunchKernelGGL(jacobi_cols_kernel, dim3(g_rot), dim3(256), 0, st, C, n, np, r, A, Vw,
-                         cs);
+      if (n <= kJacobiLdsN) {
+        hipLaunchKernelGGL(jacobi_round_kernel, dim3((unsigned)((int64_t)C * half)), dim3(256),
+                           2 * sizeof(double) * (size_t)n, st, C, n, np, r, A, Vw, cs);
+      } else {
+        hipLaunchKernelGGL(jacobi_rows_kernel, dim3(g_rot), dim3(256), 0, st, C, n, np, r, A,
+                           cs);
+        hipLaunchKernelGGL(jacobi_cols_kernel, dim3(g_rot), dim3(256), 0, st, C, n, np, r, A, Vw,
+                           cs);
+      }
     }
     SB_LAUNCH_CHECK();
   }
