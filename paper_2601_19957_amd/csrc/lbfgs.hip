@@ -84,6 +84,38 @@ __device__ inline void vstore(T *p, int i0, int d, bool vec, const T (&v)[EPT]) 
     if (i0 + e < d) p[i0 + e] = v[e];
 }
 
+// Streaming variants for the history ring, read and written once per step and
+// not again before the whole batch has moved several times the size of the
+// last-level cache: non-temporal accesses keep it from displacing the points
+// and gradients the contraction reads next.
+template <typename T, int EPT>
+__device__ inline void vload_nt(const T *p, int i0, int d, bool vec, T (&v)[EPT]) {
+  if constexpr (EPT > 1) {
+    typedef T vt __attribute__((ext_vector_type(EPT)));
+    if (vec && i0 + EPT <= d) {
+      const vt w = __builtin_nontemporal_load((const vt *)(p + i0));
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) v[e] = w[e];
+      return;
+    }
+  }
+  vload<T, EPT>(p, i0, d, vec, v);
+}
+template <typename T, int EPT>
+__device__ inline void vstore_nt(T *p, int i0, int d, bool vec, const T (&v)[EPT]) {
+  if constexpr (EPT > 1) {
+    typedef T vt __attribute__((ext_vector_type(EPT)));
+    if (vec && i0 + EPT <= d) {
+      vt w;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) w[e] = v[e];
+      __builtin_nontemporal_store(w, (vt *)(p + i0));
+      return;
+    }
+  }
+  vstore<T, EPT>(p, i0, d, vec, v);
+}
+
 // Workgroup reductions over a two-slot LDS ring, one barrier each (the
 // summation order of block_sum: butterfly within each wave, then the wave
 // totals in order, so results are the same).  Reduction k writes slot
@@ -291,8 +323,8 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
       const int ph = (head - cnt + j + 2 * m) % m;
       const T *Sp = a.S + (size_t)m * vo + (size_t)ph * d;
       const T *Yp = a.Yh + (size_t)m * vo + (size_t)ph * d;
-      vload<T, EPT>(Sp, i0, d, vec, Sr[j]);
-      vload<T, EPT>(Yp, i0, d, vec, Yr[j]);
+      vload_nt<T, EPT>(Sp, i0, d, vec, Sr[j]);
+      vload_nt<T, EPT>(Yp, i0, d, vec, Yr[j]);
       rh[j] = a.rho[(size_t)s * m + ph];
       yyr[j] = a.yy[(size_t)s * m + ph];
     }
@@ -313,8 +345,8 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
       // store the pair in the ring and append it to the logical history
       T *Sp = a.S + (size_t)m * vo + (size_t)head * d;
       T *Yp = a.Yh + (size_t)m * vo + (size_t)head * d;
-      vstore<T, EPT>(Sp, i0, d, vec, sv);
-      vstore<T, EPT>(Yp, i0, d, vec, yv);
+      vstore_nt<T, EPT>(Sp, i0, d, vec, sv);
+      vstore_nt<T, EPT>(Yp, i0, d, vec, yv);
       if (tid == 0) {
         a.rho[(size_t)s * m + head] = (T)1 / sy;
         a.yy[(size_t)s * m + head] = yy;
@@ -349,8 +381,8 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
       cnt = full ? m : cnt + 1;
     } else if (defer_oldest) {
       // pair kept out: the oldest pair (ring slot head) stays in the history
-      vload<T, EPT>(a.S + (size_t)m * vo + (size_t)head * d, i0, d, vec, Sr[0]);
-      vload<T, EPT>(a.Yh + (size_t)m * vo + (size_t)head * d, i0, d, vec, Yr[0]);
+      vload_nt<T, EPT>(a.S + (size_t)m * vo + (size_t)head * d, i0, d, vec, Sr[0]);
+      vload_nt<T, EPT>(a.Yh + (size_t)m * vo + (size_t)head * d, i0, d, vec, Yr[0]);
       rh[0] = a.rho[(size_t)s * m + head];
       yyr[0] = a.yy[(size_t)s * m + head];
     }
@@ -432,7 +464,7 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
   T xtv[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) xtv[e] = x[e] + p[e];
-  vstore<T, EPT>(pd, i0, d, vec, p);
+  vstore_nt<T, EPT>(pd, i0, d, vec, p);
   vstore<T, EPT>(xt, i0, d, vec, xtv);
   if (tid == 0) {
     a.alpha[s] = (T)1;
