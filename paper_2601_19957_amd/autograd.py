@@ -71,3 +71,30 @@ class LogL(torch.autograd.Function):
 def logl(model, X):
     """Differentiable l at the rows of X; ``model`` is a ``_lib.DeviceModel``."""
     return LogL.apply(X, model)
+
+
+class UserLogL(torch.autograd.Function):
+    """l(X) of a run-time compiled user likelihood (``_lib.UserLogL``), FP64; its backward is
+    the central finite-difference gradient of the same batch kernels (step ``eps``), the
+    derivative a likelihood without an analytic backward has (appendix "Gradient and Hessian
+    Computation").  Second derivatives are not provided here (``UserLogL.fd(full=True)`` gives
+    the FD Hessian)."""
+
+    @staticmethod
+    def forward(ctx, X, fn, params, eps):
+        X64 = X.detach().to(torch.float64)
+        l = fn.logl(X64, params)
+        ctx.save_for_backward(X64)
+        ctx.fn, ctx.params, ctx.eps = fn, params, eps
+        return l.to(X.dtype)
+
+    @staticmethod
+    def backward(ctx, gl):
+        (X,) = ctx.saved_tensors
+        G = ctx.fn.fd(X, ctx.eps, ctx.params)["grad"]
+        return (gl.to(torch.float64)[:, None] * G).to(gl.dtype), None, None, None
+
+
+def user_logl(fn, X, params=None, eps: float = 1e-5):
+    """Differentiable l of a user likelihood at the rows of X (FD gradient on backward)."""
+    return UserLogL.apply(X, fn, params, eps)

@@ -227,3 +227,54 @@ def test_user_evidence_path_mixture(L):
     # modes: each within the FD-gradient accuracy of a reference mode
     dist = np.max(np.abs(r.modes[:, None, :] - ref.modes[None, :, :]), axis=2)
     assert np.all(np.min(dist, axis=1) < 1e-5)
+
+
+def test_user_autograd_backward_is_the_fd_gradient(L):
+    """torch.autograd through a user likelihood: the backward is the FD gradient kernel; on a
+    Gaussian it equals -P (x - mu) to the stencil's rounding."""
+    from paper_2601_19957_amd import autograd
+
+    d = 12
+    P, mu, f, params = gauss_case(d, 303)
+    fn = L.UserLogL(GAUSS_SRC, "gauss")
+    X = torch.tensor(np.random.default_rng(4).uniform(-2, 2, (5, d)), device="cuda",
+                     requires_grad=True)
+    l = autograd.user_logl(fn, X, dev(params), eps=1e-3)
+    (g,) = torch.autograd.grad(l.sum(), X)
+    ref = -(X.detach().cpu().numpy() - mu) @ P
+    fs = max(abs(f(x)) for x in X.detach().cpu().numpy()) + 1.0
+    assert np.max(np.abs(g.cpu().numpy() - ref)) <= 16 * d * EPSM * fs / 1e-3
+
+
+LINEAR_SRC = r"""
+__device__ double lin(const double *x, int d, const double *p) {
+  double s = 0.0;
+  for (int i = 0; i < d; ++i) s += x[i];
+  return s;
+}
+"""
+
+
+def test_user_evidence_error_paths(L):
+    """No maximum inside the box (a linear l: no start converges) -> SB_E_NOMODE; more modes
+    than max_modes -> SB_E_CAPACITY."""
+    d = 4
+    fn = L.UserLogL(LINEAR_SRC, "lin")
+    lo, hi = dev(np.full(d, -1.0)), dev(np.full(d, 1.0))
+    cfg = synth.RunConfig(n_rays=64, n_points=8, n_starts=32, m=8, max_iter=20, max_modes=8,
+                          precision=synth.PREC_FP64, grad_tol=1e-7, dedup_tol=0.0, seed=5)
+    r = fn.evidence(d, lo, hi, cfg, 1e-5, 1e-3, 1e-3)
+    assert r.status == L.E_NOMODE
+    rng = np.random.Generator(np.random.PCG64(98))
+    prob = synth.gaussian_mixture(rng, 7, 3, -8.0, 8.0, 0.05, 1.0, 12.0, box_half=12.0,
+                                  norm=synth.NORM_DENSITY, linf_min=1.0)
+    st, beta, _ = O.prep(prob)
+    params = [3.0]
+    for k in range(3):
+        params += [beta[k]] + list(prob.mu[k]) + list(prob.prec[k].ravel())
+    fm = L.UserLogL(MIX_SRC, "mix")
+    cfg2 = synth.RunConfig(n_rays=512, n_points=32, n_starts=512, m=8, max_iter=0, max_modes=1,
+                           precision=synth.PREC_FP64, grad_tol=1e-7, dedup_tol=0.0,
+                           seed=2601199599)
+    r2 = fm.evidence(7, dev(prob.lo), dev(prob.hi), cfg2, 1e-5, 1e-3, 1e-3, dev(np.array(params)))
+    assert r2.status == L.E_CAPACITY
