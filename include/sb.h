@@ -37,6 +37,12 @@
  *    identical outputs.  Calls on different streams are independent.
  *  - The caller owns every buffer.  sb_last_error() describes the last
  *    failure on the calling thread.
+ *
+ * Beyond the evidence path: the preprocessing probe for flat and weakly
+ * constrained coordinates (sb_precheck_dev), the eigendecomposition-based
+ * reduction at the modes for sampler handoff (sb_eig_reduce_dev), and
+ * generic user likelihoods given as HIP source, compiled at run time, with
+ * finite-difference derivatives and their own evidence path (sb_user_*).
  */
 #ifndef SB_H
 #define SB_H
