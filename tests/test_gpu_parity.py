@@ -295,7 +295,7 @@ def test_discovery_bf16_ranks(L):
 
 # ------------------------------------------------------------ two-loop / A4
 
-@pytest.mark.parametrize("d", [4, 64, 100, 256, 700, 1024])
+@pytest.mark.parametrize("d", [4, 64, 100, 256, 700, 1024, 2047, 4096])
 def test_two_loop_direction(L, d):
     B, m = 6, 8
     cnts = [0, 1, 3, 5, 8, 8]
@@ -532,3 +532,39 @@ def test_evidence_statuses(L):
     p1, c1 = synth.make_workload("c0")
     p1.prec[0] = -p1.prec[0]
     assert L.sb_evidence(p1, c1).status == L.E_NOTPD
+
+
+# ------------------------------------------------------------- edge cases
+
+def test_empty_inputs(L):
+    """Empty batches are valid calls that write nothing: l + grad of 0 rows, dedup of 0
+    candidates, Cholesky of 0 matrices."""
+    prob = PROBLEMS["mix_d37_K3"]()
+    m = L.DeviceModel(prob)
+    l, g = L.sb_logl_grad_dev(m, torch.empty((0, prob.d), dtype=torch.float64, device="cuda"))
+    assert l.numel() == 0 and g.shape == (0, prob.d)
+    rep_of, reps = L.sb_dedup_dev(torch.empty((0, 3), dtype=torch.float64, device="cuda"),
+                                  torch.empty(0, dtype=torch.float64, device="cuda"), 0.1)
+    assert rep_of.numel() == 0 and reps.numel() == 0
+    Lf, ld, info = L.sb_cholesky_logdet_dev(torch.empty((0, 5, 5), dtype=torch.float64,
+                                                        device="cuda"))
+    assert ld.numel() == 0
+
+
+def test_logl_grad_largest_supported_dimension(L):
+    """d = 4096 (the largest the L-BFGS step supports) with a ragged batch: l and grad
+    against the oracle."""
+    rng = np.random.Generator(np.random.PCG64(4096))
+    d = 4096
+    # dense SPD precision, cheap to build at this size: diagonal plus two rank-one terms
+    lam = np.exp(rng.uniform(np.log(0.1), 0.0, d))
+    u, v = rng.standard_normal(d) / 64.0, rng.standard_normal(d) / 64.0
+    P = np.diag(1.0 / lam) + np.outer(u, u) + np.outer(v, v)
+    mu = rng.uniform(-1, 1, (1, d))
+    prob = synth.Problem(synth.FAMILY_GAUSS_MIX, synth.NORM_PEAK_ZERO, d, 1, np.zeros(1), mu,
+                         P[None], 0.0, 0.0, np.full(d, -5.0), np.full(d, 5.0), np.zeros(1))
+    X = mu + 0.5 * rng.standard_normal((3, d))
+    lo, go = O.logl(prob, X)
+    l, g = L.sb_logl_grad_dev(L.DeviceModel(prob), dev(X))
+    assert rel(l.cpu().numpy(), lo) < 1e-10
+    assert rel(g.cpu().numpy(), go, axis=1) < 1e-10
