@@ -847,7 +847,8 @@ __global__ __launch_bounds__(256) void mixture_screen_kernel(Model m, ScreenArgs
   if (a.hasref[xr] > 0) {
     float dd = 0.f;
     for (int j = 4 * lane; j < d; j += 256) {  // (d % 8 == 0, 16-byte rows)
-      const f4v xv = *(const f4v *)(x + j), rv = *(const f4v *)(xref + j);
+      const f4v xv = *(const f4v *)(x + j);
+      const f4v rv = __builtin_nontemporal_load((const f4v *)(xref + j));
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const float t = xv[e] - rv[e];
@@ -889,7 +890,7 @@ __global__ __launch_bounds__(256) void mixture_screen_kernel(Model m, ScreenArgs
   for (int k = 0; k < kMaxK; ++k) nrm[k] = 0.f;
   for (int j = 4 * lane; j < d; j += 256) {
     const f4v xv = *(const f4v *)(x + j);
-    *(f4v *)(xref + j) = xv;
+    __builtin_nontemporal_store(xv, (f4v *)(xref + j));
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k)
       if (k < K && ((keep >> k) & 1u)) {
