@@ -302,6 +302,61 @@ def dedup(X, l, tau, valid=None):
     return rep_of, reps[:n].copy()
 
 
+def chisao_stick(l, G, grad_tol):
+    """Stick detection of the ChiSao cycle (section "ChiSao Exploration", the oscillation
+    cycle's second step and the algorithm summary of CarryTiger): a sample sticks when its
+    gradient's L-infinity norm is below grad_tol and its l is at least l_max + log 0.1, with
+    l_max the largest finite l of the batch.  Reading: a sample with a non-finite l or
+    gradient entry never sticks."""
+    l = _f64(l)
+    G = _f64(np.atleast_2d(G))
+    stuck = np.zeros(l.size, dtype=np.uint8)
+    fin = [i for i in range(l.size) if math.isfinite(l[i])]
+    if not fin:
+        return stuck
+    lmax = max(l[i] for i in fin)
+    thr = lmax + math.log(0.1)
+    for i in fin:
+        g = G[i]
+        if not np.all(np.isfinite(g)):
+            continue
+        if float(np.max(np.abs(g))) < grad_tol and l[i] >= thr:
+            stuck[i] = 1
+    return stuck
+
+
+def chisao_explore(prob, X, stuck, Z, sigma, alpha_cloud, n_anti, alpha, mu,
+                   op: Optional[OracleProblem] = None):
+    """The ChiSao cycle's moves of the samples that are not stuck (section "ChiSao
+    Exploration"): Hands Like Clouds, then the anti-convergence phase.
+
+    Hands Like Clouds: for each of Z's n_cloud steps, the smoothed gradient is the mean over
+    its K perturbations of grad l(x + sigma z_k) (the equation of that step; Z [n_cloud][K]
+    [B][d] holds the standard normal draws), and the sample moves x <- x + alpha_cloud times
+    it.  Anti-convergence: n_anti momentum descent steps v <- mu v - alpha grad l(x),
+    x <- x + v (the momentum equation of that phase), from v = 0.  Readings: the step sizes
+    are parameters; every move is clipped to the prior box; stuck samples do not move."""
+    op = op or OracleProblem(prob)
+    X = _f64(np.atleast_2d(X)).copy()
+    free = np.asarray(stuck).reshape(-1) == 0
+    lo, hi = op.lo, op.hi
+    Z = _f64(Z)
+    n_cloud, K = Z.shape[0], Z.shape[1]
+    for s in range(n_cloud):
+        acc = np.zeros_like(X)
+        for k in range(K):
+            _, g = logl(prob, X + sigma * Z[s, k], op=op)
+            acc = acc + g
+        step = alpha_cloud * (acc / K)
+        X[free] = np.minimum(np.maximum(X[free] + step[free], lo), hi)
+    V = np.zeros_like(X)
+    for _ in range(n_anti):
+        _, g = logl(prob, X, op=op)
+        V = mu * V - alpha * g
+        X[free] = np.minimum(np.maximum(X[free] + V[free], lo), hi)
+    return X
+
+
 def log_volume(lo, hi) -> float:
     lo = _f64(lo)
     hi = _f64(hi)

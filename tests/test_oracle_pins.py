@@ -826,3 +826,96 @@ def test_user_mode_evidence_gaussians_closed_form(oracle_lib):
     fm = lambda x: float(O.logl(prob, x[None], grad=False, op=op)[0])
     r3 = O.user_mode_evidence(fm, prob.mu, prob.lo, prob.hi, 1e-3, 1e-3)
     assert abs(r3["log_z"] + O.log_volume(prob.lo, prob.hi)) < 1e-6
+
+
+# ---------------------------------------------------------------- ChiSao moves (section
+# "ChiSao Exploration": stick detection, Hands Like Clouds, anti-convergence)
+
+def test_chisao_stick_special_cases(oracle_lib):
+    """Both conditions at their boundaries: l = l_max + log 0.1 sticks (>=), one ulp below
+    does not; |g|_inf equal to the tolerance does not (<); non-finite l or g never sticks and
+    a non-finite l does not set l_max."""
+    O = oracle_lib
+    t = math.log(0.1)
+    l = np.array([0.0, t, np.nextafter(t, -np.inf), 0.0, -5.0, np.inf, np.nan, 0.0])
+    G = np.zeros((8, 3))
+    G[3, 1] = -1e-6          # |g|_inf == tol: not below
+    G[7, 2] = np.nan
+    assert O.chisao_stick(l, G, 1e-6).tolist() == [1, 1, 0, 0, 0, 0, 0, 0]
+    G[3, 1] = -np.nextafter(1e-6, 0.0)
+    assert O.chisao_stick(l, G, 1e-6)[3] == 1
+    # l_max from the finite values only; none finite: nothing sticks
+    assert O.chisao_stick(np.array([np.nan, -np.inf]), np.zeros((2, 2)), 1.0).tolist() == [0, 0]
+    assert O.chisao_stick(np.array([-1.0, -3.0]), np.zeros((2, 2)), 1.0).tolist() == [1, 1]
+    assert O.chisao_stick(np.array([-1.0, -3.4]), np.zeros((2, 2)), 1.0).tolist() == [1, 0]
+
+
+def _isotropic_or_dense(seed, d, dense):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    prob = synth.gaussian_mixture(rng, d, 1, -1.0, 1.0, 0.5, 2.0, 0.0, box_half=1e6,
+                                  norm=synth.NORM_PEAK_ZERO)
+    if not dense:
+        prob.prec = np.eye(d)[None] * 1.7
+    return prob
+
+
+@pytest.mark.parametrize("dense", [False, True])
+def test_chisao_anticonverge_closed_form(oracle_lib, dense):
+    """On a Gaussian l = -(x - mu)^T P (x - mu)/2 the momentum descent is linear: in an
+    eigenvector basis of P (eigenvalue p) the offset e and velocity v evolve by the 2 x 2
+    matrix [[1 + a p, m], [a p, m]] from (e0, 0); its n-th power from the eigenvalues of
+    that matrix gives the end point.  Stuck samples keep their coordinates bit for bit."""
+    O = oracle_lib
+    d, a, m, n = 6, 0.05, 0.9, 7
+    prob = _isotropic_or_dense(31 + dense, d, dense)
+    rng = np.random.Generator(np.random.PCG64(5))
+    X = prob.mu[0] + rng.normal(size=(4, d))
+    stuck = np.array([0, 1, 0, 0], dtype=np.uint8)
+    out = O.chisao_explore(prob, X, stuck, np.zeros((0, 1, 4, d)), 0.0, 0.0, n, a, m)
+    w, Q = np.linalg.eigh(prob.prec[0])
+    for b in range(4):
+        if stuck[b]:
+            assert np.array_equal(out[b], X[b])
+            continue
+        e0 = Q.T @ (X[b] - prob.mu[0])
+        e = np.empty(d)
+        for i, p in enumerate(w):
+            M = np.array([[1.0 + a * p, m], [a * p, m]])
+            lam, U = np.linalg.eig(M)
+            Mn = (U @ np.diag(lam ** n) @ np.linalg.inv(U)).real
+            e[i] = (Mn @ np.array([e0[i], 0.0]))[0]
+        assert np.allclose(out[b], prob.mu[0] + Q @ e, rtol=1e-11, atol=1e-11)
+
+
+def test_chisao_clouds_closed_form_and_invariants(oracle_lib):
+    """Antithetic perturbations (z, -z) make the smoothed gradient of a Gaussian exactly
+    -P (x - mu), so n steps of size a give e_n = (I - a P)^n e_0 (per eigenvalue p:
+    (1 - a p)^n).  K identical perturbations equal one; sigma = 0 equals plain gradient
+    ascent whatever Z holds; a step that overshoots the box ends on its faces."""
+    O = oracle_lib
+    d, a, n = 5, 0.2, 4
+    prob = _isotropic_or_dense(41, d, True)
+    rng = np.random.Generator(np.random.PCG64(6))
+    X = prob.mu[0] + rng.normal(size=(3, d))
+    z = rng.normal(size=(n, 1, 3, d))
+    Z = np.concatenate([z, -z], axis=1)
+    out = O.chisao_explore(prob, X, np.zeros(3, np.uint8), Z, 0.7, a, 0, 0.0, 0.9)
+    w, Q = np.linalg.eigh(prob.prec[0])
+    for b in range(3):
+        e = (1.0 - a * w) ** n * (Q.T @ (X[b] - prob.mu[0]))
+        assert np.allclose(out[b], prob.mu[0] + Q @ e, rtol=1e-11, atol=1e-11)
+    one = O.chisao_explore(prob, X, np.zeros(3, np.uint8), z, 0.3, a, 0, 0.0, 0.9)
+    three = O.chisao_explore(prob, X, np.zeros(3, np.uint8), np.repeat(z, 3, axis=1), 0.3, a,
+                             0, 0.0, 0.9)
+    assert np.allclose(one, three, rtol=1e-13, atol=1e-13)
+    flat = O.chisao_explore(prob, X, np.zeros(3, np.uint8), Z * 0.0, 0.0, a, 0, 0.0, 0.9)
+    assert np.allclose(flat, out, rtol=1e-11, atol=1e-11)
+    # overshoot: a tiny box around mu and a huge step
+    prob.lo = prob.mu[0] - 0.5
+    prob.hi = prob.mu[0] + 0.5
+    Xs = prob.mu[0] + np.array([[0.3, -0.3, 0.1, -0.1, 0.2]])
+    big = O.chisao_explore(prob, Xs, np.zeros(1, np.uint8), np.zeros((1, 1, 1, d)), 0.0, 1e3,
+                           0, 0.0, 0.9)
+    g = -prob.prec[0] @ (Xs[0] - prob.mu[0])
+    ref = np.where(g > 0, prob.hi, np.where(g < 0, prob.lo, Xs[0]))
+    assert np.array_equal(big[0], ref)
