@@ -306,7 +306,9 @@ def chisao_stick(l, G, grad_tol):
     """Stick detection of the ChiSao cycle (section "ChiSao Exploration", the oscillation
     cycle's second step and the algorithm summary of CarryTiger): a sample sticks when its
     gradient's L-infinity norm is below grad_tol and its l is at least l_max + log 0.1, with
-    l_max the largest finite l of the batch.  Reading: a sample with a non-finite l or
+    l_max the largest finite l of the batch.  Readings: log 0.1 is -ln 10 (a tenth of the
+    maximum likelihood, exactly), in FP64 the correctly rounded -ln 10, not the logarithm of the
+    double nearest 0.1 (one unit in the last place apart); a sample with a non-finite l or
     gradient entry never sticks."""
     l = _f64(l)
     G = _f64(np.atleast_2d(G))
@@ -315,7 +317,7 @@ def chisao_stick(l, G, grad_tol):
     if not fin:
         return stuck
     lmax = max(l[i] for i in fin)
-    thr = lmax + math.log(0.1)
+    thr = lmax - math.log(10.0)
     for i in fin:
         g = G[i]
         if not np.all(np.isfinite(g)):

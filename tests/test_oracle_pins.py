@@ -836,7 +836,7 @@ def test_chisao_stick_special_cases(oracle_lib):
     does not; |g|_inf equal to the tolerance does not (<); non-finite l or g never sticks and
     a non-finite l does not set l_max."""
     O = oracle_lib
-    t = math.log(0.1)
+    t = -math.log(10.0)
     l = np.array([0.0, t, np.nextafter(t, -np.inf), 0.0, -5.0, np.inf, np.nan, 0.0])
     G = np.zeros((8, 3))
     G[3, 1] = -1e-6          # |g|_inf == tol: not below
