@@ -301,6 +301,47 @@ def precheck_leg(L, prob, name, reps=10):
     return out
 
 
+def chisao_leg(L, prob, name, reps=3):
+    """ChiSao moves at the bulk's batch (16384 samples of the workload's posterior, every
+    seventh stuck): one Hands Like Clouds step of four draws plus four anti-convergence steps,
+    FP64 (8 batches of gradients), then stick detection on the result; wall time per call after
+    a warm call, gradient evaluations per second and the contraction's FP64 rate."""
+    import numpy as np
+    import torch
+    from paper_2601_19957_amd import synth
+
+    B, ns, n_anti = 16384, 4, 4
+    d, K = prob.d, prob.K
+    m = L.DeviceModel(prob)
+    X0 = torch.as_tensor(synth.random_points(prob, B, seed=2601199576), device="cuda")
+    g = torch.Generator(device="cuda").manual_seed(2601199577)
+    Z = torch.randn((1, ns, B, d), generator=g, dtype=torch.float64, device="cuda")
+    stuck = torch.zeros(B, dtype=torch.uint8, device="cuda")
+    stuck[::7] = 1
+    X = X0.clone()
+    L.sb_chisao_explore_dev(m, X, stuck, Z, 0.1, 0.05, n_anti, 0.02, 0.9)  # tile autotune
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        X.copy_(X0)
+        L.sb_chisao_explore_dev(m, X, stuck, Z, 0.1, 0.05, n_anti, 0.02, 0.9)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    l, gr = L.sb_logl_grad_dev(m, X)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sm = L.sb_chisao_stick_dev(l, gr, 1e-3)
+    torch.cuda.synchronize()
+    ds = time.perf_counter() - t1
+    n_ev = B * (ns + n_anti)
+    flops = n_ev * K * 2.0 * d * d
+    return dict(workload=f"{name}: B={B} d={d} K={K} n_smooth={ns} n_anti={n_anti}",
+                ms=dt * 1e3, grad_evals=n_ev, grad_evals_per_s=n_ev / dt,
+                contraction_tflops=flops / dt / 1e12,
+                frac_fp64_peak=flops / dt / 1e12 / PEAK["fp64"], stick_ms=ds * 1e3,
+                n_stuck_after=int(sm.sum().item()))
+
+
 def reduce_leg(L, prob, name):
     """Dimensional reduction at the modes (Jacobi eigendecomposition of the K mode Hessians,
     FP64; the precisions, to which the separated mixture's mode Hessians are equal to e^-60):
@@ -455,8 +496,10 @@ def main() -> int:
                     help="skip the eigen-reduction measurement")
     ap.add_argument("--no-user", action="store_true",
                     help="skip the generic-likelihood finite-difference measurement")
+    ap.add_argument("--no-chisao", action="store_true",
+                    help="skip the ChiSao-moves measurement")
     ap.add_argument("--modules-only", action="store_true",
-                    help="only the preprocessing, eigen-reduction and user-likelihood legs")
+                    help="only the preprocessing, eigen-reduction, user-likelihood and ChiSao legs")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the roofline kernel timing (for profiling that kernel)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -489,7 +532,8 @@ def main() -> int:
     prob_big, cfg_big = wl[big]
     if args.modules_only:
         print(json.dumps(dict(modules_only=True, precheck=precheck_leg(L, prob_big, big),
-                              eig_reduce=reduce_leg(L, prob_big, big), user_fd=user_fd_leg(L))),
+                              eig_reduce=reduce_leg(L, prob_big, big), user_fd=user_fd_leg(L),
+                              chisao=chisao_leg(L, prob_big, big))),
               flush=True)
         return 0
 
@@ -617,6 +661,11 @@ def main() -> int:
         ufd = user_fd_leg(L)
         log(f"user FD: grad {ufd['fd_grad']['ms']:.3f} ms, hessian {ufd['fd_hessian']['ms']:.3f} ms")
 
+    chi = None
+    if not args.no_chisao:
+        chi = chisao_leg(L, prob_big, big)
+        log(f"ChiSao moves {big}: {chi['ms']:.1f} ms, {chi['grad_evals_per_s']:.3g} grad evals/s")
+
     a3 = None
     if not args.no_a3:
         a3 = a3_variants(L)
@@ -667,6 +716,7 @@ def main() -> int:
         "precheck": pre,
         "eig_reduce": red,
         "user_fd": ufd,
+        "chisao": chi,
         "roofline": roofline,
         "contraction_roofline": contraction,
         "cpu_baseline": cpu,

@@ -268,6 +268,38 @@ int32_t sb_eig_reduce_dev(int32_t C, int32_t n, const double *H, const double *l
                           int32_t *d_eff, int32_t *sweeps, void *workspace, size_t ws_bytes,
                           void *stream);
 
+/* ChiSao stick detection (section "ChiSao Exploration": the oscillation
+ * cycle's stick step and the CarryTiger algorithm summary).  For B samples
+ * with values logl [B] and gradients grad [B][d] (device FP64), stuck [B]
+ * (device) gets 1 where max_j |grad_bj| < grad_tol and logl_b >= l_max +
+ * log 0.1, l_max being the largest finite logl of the batch, else 0; a
+ * non-finite logl or gradient entry gives 0.  SB_E_INVAL for B < 0, d < 1,
+ * a non-finite grad_tol or NULL arrays (B > 0).  Workspace >= 8 bytes. */
+int32_t sb_chisao_stick_dev(int64_t B, int32_t d, const double *logl, const double *grad,
+                            double grad_tol, uint8_t *stuck, void *workspace, size_t ws_bytes,
+                            void *stream);
+
+/* ChiSao moves of the samples that are not stuck (section "ChiSao
+ * Exploration": the Hands Like Clouds smoothed gradient and the momentum
+ * equation of the anti-convergence phase), in place on X [B][d] (device
+ * FP64), stuck [B] (device, nonzero = frozen).  First n_cloud Hands Like
+ * Clouds steps: step c evaluates the model's gradient at the n_smooth points
+ * x + sigma z for z = Z[c][k][b] (Z [n_cloud][n_smooth][B][d] device FP64
+ * standard normal draws, drawn by the caller) and moves x by alpha_cloud
+ * times their mean.  Then n_anti anti-convergence steps v <- mu v - alpha
+ * grad l(x), x <- x + v from v = 0.  Each move is clipped to the box
+ * [lo, hi] (device [d]).  Gradients run through the FP64 path of
+ * sb_logl_grad_dev (the model needs its FP64 data only).  SB_E_INVAL for
+ * negative counts, n_cloud > 0 with n_smooth < 1 or Z NULL, sigma < 0 or
+ * non-finite parameters; B = 0 or no steps is a no-op.  Workspace >=
+ * sb_chisao_explore_workspace_bytes(d, K, B, n_smooth). */
+size_t sb_chisao_explore_workspace_bytes(int32_t d, int32_t K, int64_t B, int32_t n_smooth);
+int32_t sb_chisao_explore_dev(const sb_model_dev *m, const double *lo, const double *hi,
+                              int64_t B, double *X, const uint8_t *stuck, int32_t n_cloud,
+                              int32_t n_smooth, const double *Z, double sigma, double alpha_cloud,
+                              int32_t n_anti, double alpha, double mu, void *workspace,
+                              size_t ws_bytes, void *stream);
+
 /* Generic user log-likelihoods without an analytic backward (the paper's
  * general case: any l, derivatives by finite differences; appendix "Gradient
  * and Hessian Computation" for the stencils, "Rotation Detection" for the

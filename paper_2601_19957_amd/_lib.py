@@ -33,7 +33,8 @@ EXPORTS = [
     "sb_quadform_dev", "sb_split_bf16_dev", "sb_hvp_workspace_bytes", "sb_hvp_dev", "sb_discover_workspace_bytes", "sb_discover_dev",
     "sb_lbfgs_direction_dev", "sb_lbfgs_workspace_bytes", "sb_lbfgs_dev",
     "sb_lbfgs_timed_dev", "sb_precheck_workspace_bytes", "sb_precheck_dev",
-    "sb_eig_reduce_workspace_bytes", "sb_eig_reduce_dev", "sb_user_compile", "sb_user_release",
+    "sb_eig_reduce_workspace_bytes", "sb_eig_reduce_dev", "sb_chisao_stick_dev",
+    "sb_chisao_explore_workspace_bytes", "sb_chisao_explore_dev", "sb_user_compile", "sb_user_release",
     "sb_user_logl_dev", "sb_user_fd_workspace_bytes", "sb_user_fd_dev",
     "sb_user_mode_evidence_workspace_bytes", "sb_user_mode_evidence_dev",
     "sb_user_evidence_workspace_bytes", "sb_user_evidence_dev",
@@ -127,6 +128,10 @@ def lib():
             "sb_eig_reduce_workspace_bytes": (sz, [i32, i32]),
             "sb_eig_reduce_dev": (i32, [i32, i32, vp, vp, vp, f64, f64, vp, vp, vp, vp, vp, vp,
                                         vp, sz, vp]),
+            "sb_chisao_stick_dev": (i32, [i64, i32, vp, vp, f64, vp, vp, sz, vp]),
+            "sb_chisao_explore_workspace_bytes": (sz, [i32, i32, i64, i32]),
+            "sb_chisao_explore_dev": (i32, [vp, vp, vp, i64, vp, vp, i32, i32, vp, f64, f64, i32,
+                                            f64, f64, vp, sz, vp]),
             "sb_user_compile": (i32, [C.c_char_p, C.c_char_p, vp]),
             "sb_user_release": (None, [vp]),
             "sb_user_logl_dev": (i32, [vp, i64, i32, vp, vp, vp, vp]),
@@ -543,6 +548,48 @@ def sb_eig_reduce_dev(H, lo, hi, eps_inform: float, eps_nuisance: float):
     _check(st, "sb_eig_reduce_dev")
     return dict(eigval=ev, V=V, cls=cls, logz_marginal=lz, d_eff=list(deff),
                 sweeps=sweeps.value)
+
+
+def sb_chisao_stick_dev(logl, grad, grad_tol: float):
+    """ChiSao stick mask [B] (uint8, device) of samples with values logl [B] and gradients
+    grad [B][d] (device FP64)."""
+    import torch
+
+    logl = logl.contiguous()
+    grad = grad.contiguous()
+    B, d = grad.shape
+    dev = grad.device
+    stuck = torch.empty(B, dtype=torch.uint8, device=dev)
+    ws = _ws(256, dev)
+    st = lib().sb_chisao_stick_dev(B, d, logl.data_ptr(), grad.data_ptr(), grad_tol,
+                                   stuck.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    _check(st, "sb_chisao_stick_dev")
+    return stuck
+
+
+def sb_chisao_explore_dev(model: DeviceModel, X, stuck, Z, sigma: float, alpha_cloud: float,
+                          n_anti: int, alpha: float, mu: float, lo=None, hi=None):
+    """ChiSao moves of the free samples, in place on X [B][d] (device FP64): Z [n_cloud]
+    [n_smooth][B][d] Hands Like Clouds draws, then n_anti anti-convergence steps.  Returns X."""
+    import torch
+
+    assert X.is_contiguous() and X.dtype == torch.float64
+    B, d = X.shape
+    dev = X.device
+    lo = model.lo if lo is None else lo
+    hi = model.hi if hi is None else hi
+    stuck = stuck.to(torch.uint8).contiguous()
+    n_cloud, n_smooth = (Z.shape[0], Z.shape[1]) if Z is not None else (0, 1)
+    Zp = Z.contiguous().data_ptr() if Z is not None and Z.numel() else None
+    if n_cloud == 0:
+        Zp = None
+    ws = _ws(lib().sb_chisao_explore_workspace_bytes(d, model.K, max(B, 1), n_smooth), dev)
+    mv = model.view(DTYPE_F64)
+    st = lib().sb_chisao_explore_dev(C.byref(mv), lo.data_ptr(), hi.data_ptr(), B, X.data_ptr(),
+                                     stuck.data_ptr(), n_cloud, n_smooth, Zp, sigma, alpha_cloud,
+                                     n_anti, alpha, mu, ws.data_ptr(), ws.numel(), _stream())
+    _check(st, "sb_chisao_explore_dev")
+    return X
 
 
 class UserLogL:

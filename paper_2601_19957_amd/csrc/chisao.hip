@@ -1,0 +1,215 @@
+// ChiSao moves of the exploration samples (section "ChiSao Exploration"):
+// stick detection, the Hands Like Clouds smoothed-gradient ascent and the
+// momentum anti-convergence phase, on FP64 samples [B][d].
+//
+// Stick detection: sample b sticks when max_j |g_bj| < grad_tol and
+// l_b >= l_max + log 0.1 (l_max the largest finite l of the batch); a
+// non-finite l or gradient entry never sticks.  One workgroup finds l_max,
+// then one wave per sample reduces its gradient row.
+//
+// Hands Like Clouds: per step, the n_smooth perturbed copies x + sigma z_k of
+// every sample (z_k standard normal, supplied by the caller) go through the
+// FP64 contraction and backward in one batch; the mean of their gradients
+// (summed in k order, then divided by n_smooth) times alpha_cloud moves each
+// free sample.  Anti-convergence: v <- mu v - alpha grad l(x), x <- x + v,
+// starting from v = 0.  Every move is clipped to the prior box; stuck samples
+// keep their coordinates.  The elementwise kernels round each operation
+// separately (no contraction into FMAs), in the order the steps are written.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+
+#include "internal.h"
+
+namespace sb {
+
+// log 0.1 = -ln 10, correctly rounded (not the logarithm of the double nearest 0.1)
+constexpr double kLogTenth = -2.3025850929940456840179914546844;
+
+// One workgroup of 1024 threads: the largest finite l (-inf if none).
+__global__ __launch_bounds__(1024) void stick_lmax_kernel(int64_t B, const double *l,
+                                                          double *lmax) {
+  __shared__ double part[16];
+  double m = -INFINITY;
+  for (int64_t i = threadIdx.x; i < B; i += 1024) {
+    const double v = l[i];
+    if (isfinite(v)) m = fmax(m, v);
+  }
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = part[0];
+    for (int w = 1; w < 16; ++w) r = fmax(r, part[w]);
+    *lmax = r;
+  }
+}
+
+// One wave per sample: the gradient row's largest magnitude and finiteness,
+// then both conditions.
+__global__ __launch_bounds__(256) void stick_mask_kernel(int64_t B, int d, const double *l,
+                                                         const double *G, double grad_tol,
+                                                         const double *lmax, uint8_t *stuck) {
+  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (b >= B) return;
+  const double *g = G + b * d;
+  double m = 0.0;
+  int bad = 0;
+  for (int j = lane; j < d; j += 64) {
+    const double v = g[j];
+    bad |= !isfinite(v);
+    m = fmax(m, fabs(v));
+  }
+  m = wave_max(m);
+  bad = __any(bad);
+  if (lane == 0) {
+    const double lb = l[b];
+    const double thr = *lmax + kLogTenth;
+    stuck[b] = (isfinite(lb) && !bad && m < grad_tol && lb >= thr) ? 1 : 0;
+  }
+}
+
+// P[k][b][:] = X[b][:] + sigma Z[k][b][:] over n = n_smooth B d values.
+__global__ __launch_bounds__(256) void cloud_points_kernel(int64_t n, int64_t bd, const double *X,
+                                                           const double *Z, double sigma,
+                                                           double *P) {
+#pragma clang fp contract(off)
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const double dz = sigma * Z[e];
+  P[e] = X[e % bd] + dz;
+}
+
+__device__ inline double clip_box(double x, double lo, double hi) {
+  return x < lo ? lo : (x > hi ? hi : x);
+}
+
+// x <- clip(x + alpha (sum_k G[k] / n_smooth)) for free samples.
+__global__ __launch_bounds__(256) void cloud_move_kernel(int64_t bd, int d, int n_smooth,
+                                                         const double *G, const uint8_t *stuck,
+                                                         const double *lo, const double *hi,
+                                                         double alpha, double *X) {
+#pragma clang fp contract(off)
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= bd) return;
+  if (stuck[e / d]) return;
+  double acc = 0.0;
+  for (int k = 0; k < n_smooth; ++k) acc = acc + G[(int64_t)k * bd + e];
+  const double mean = acc / (double)n_smooth;
+  const double step = alpha * mean;
+  const int j = (int)(e % d);
+  X[e] = clip_box(X[e] + step, lo[j], hi[j]);
+}
+
+// v <- mu v - alpha g (v = 0 before the first step); free samples x <- clip(x + v).
+__global__ __launch_bounds__(256) void anti_move_kernel(int64_t bd, int d, const double *G,
+                                                        const uint8_t *stuck, const double *lo,
+                                                        const double *hi, double alpha, double mu,
+                                                        int first, double *V, double *X) {
+#pragma clang fp contract(off)
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= bd) return;
+  const double v0 = first ? 0.0 : V[e];
+  const double mv = mu * v0;
+  const double ag = alpha * G[e];
+  const double v = mv - ag;
+  V[e] = v;
+  if (stuck[e / d]) return;
+  const int j = (int)(e % d);
+  X[e] = clip_box(X[e] + v, lo[j], hi[j]);
+}
+
+}  // namespace sb
+
+using namespace sb;
+
+static int fail(int st, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  char buf[512];
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  set_error("%s", buf);
+  return st;
+}
+
+extern "C" {
+
+int32_t sb_chisao_stick_dev(int64_t B, int32_t d, const double *logl, const double *grad,
+                            double grad_tol, uint8_t *stuck, void *workspace, size_t ws_bytes,
+                            void *stream) {
+  if (B < 0 || d < 1) return fail(SB_E_INVAL, "stick detection: bad B or d");
+  if (!std::isfinite(grad_tol)) return fail(SB_E_INVAL, "grad_tol must be finite");
+  if (B == 0) return SB_OK;
+  if (!logl || !grad || !stuck) return fail(SB_E_INVAL, "stick detection: NULL array");
+  if (B > (int64_t)4 * INT32_MAX) return fail(SB_E_INVAL, "stick detection: B too large");
+  if (!workspace || ws_bytes < sizeof(double)) return fail(SB_E_NOMEM, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  double *lmax = (double *)workspace;
+  hipLaunchKernelGGL(stick_lmax_kernel, dim3(1), dim3(1024), 0, s, B, logl, lmax);
+  SB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(stick_mask_kernel, dim3((unsigned)ceil_div(B, 4)), dim3(256), 0, s, B, d,
+                     logl, grad, grad_tol, lmax, stuck);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+size_t sb_chisao_explore_workspace_bytes(int32_t d, int32_t K, int64_t B, int32_t n_smooth) {
+  if (d < 1 || K < 1 || B < 1) return 0;
+  const int64_t rows = B * (n_smooth > 1 ? n_smooth : 1);
+  return 2 * align_up(8ull * rows * d) + align_up(8ull * rows) + align_up(8ull * B * d) +
+         sb_logl_grad_workspace_bytes(d, K, rows, SB_DTYPE_F64) + 1024;
+}
+
+int32_t sb_chisao_explore_dev(const sb_model_dev *m, const double *lo, const double *hi,
+                              int64_t B, double *X, const uint8_t *stuck, int32_t n_cloud,
+                              int32_t n_smooth, const double *Z, double sigma, double alpha_cloud,
+                              int32_t n_anti, double alpha, double mu, void *workspace,
+                              size_t ws_bytes, void *stream) {
+  if (!m) return fail(SB_E_INVAL, "model is NULL");
+  if (B < 0 || n_cloud < 0 || n_anti < 0) return fail(SB_E_INVAL, "negative B or step count");
+  if (n_cloud > 0 && (n_smooth < 1 || !Z))
+    return fail(SB_E_INVAL, "Hands Like Clouds needs n_smooth >= 1 and Z");
+  if (!std::isfinite(sigma) || sigma < 0.0 || !std::isfinite(alpha_cloud) ||
+      !std::isfinite(alpha) || !std::isfinite(mu))
+    return fail(SB_E_INVAL, "sigma, step sizes and momentum must be finite (sigma >= 0)");
+  if (B == 0 || (n_cloud == 0 && n_anti == 0)) return SB_OK;
+  if (!X || !stuck || !lo || !hi) return fail(SB_E_INVAL, "NULL X, stuck or box");
+  const int d = m->d;
+  if (d < 1) return fail(SB_E_INVAL, "model d must be >= 1");
+  const int ns = n_cloud > 0 ? n_smooth : 1;
+  if (!workspace || ws_bytes < sb_chisao_explore_workspace_bytes(d, m->K, B, ns))
+    return fail(SB_E_NOMEM, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t bd = B * d, rows = B * ns;
+  if (rows * d > ((int64_t)1 << 38)) return fail(SB_E_INVAL, "too many perturbed values");
+  Arena ar(workspace, ws_bytes);
+  double *P = ar.take<double>((size_t)(rows * d));
+  double *G = ar.take<double>((size_t)(rows * d));
+  double *L = ar.take<double>((size_t)rows);
+  double *V = ar.take<double>((size_t)bd);
+  const size_t gws_bytes = sb_logl_grad_workspace_bytes(d, m->K, rows, SB_DTYPE_F64);
+  void *gws = ar.take<char>(gws_bytes);
+  if (!ar.ok()) return fail(SB_E_NOMEM, "workspace too small");
+  int st;
+  for (int c = 0; c < n_cloud; ++c) {
+    const double *Zc = Z + (int64_t)c * rows * d;
+    hipLaunchKernelGGL(cloud_points_kernel, dim3((unsigned)ceil_div(rows * d, 256)), dim3(256),
+                       0, s, rows * d, bd, X, Zc, sigma, P);
+    SB_LAUNCH_CHECK();
+    if ((st = sb_logl_grad_dev(m, rows, P, L, G, SB_DTYPE_F64, gws, gws_bytes, stream))) return st;
+    hipLaunchKernelGGL(cloud_move_kernel, dim3((unsigned)ceil_div(bd, 256)), dim3(256), 0, s, bd,
+                       d, ns, G, stuck, lo, hi, alpha_cloud, X);
+    SB_LAUNCH_CHECK();
+  }
+  for (int t = 0; t < n_anti; ++t) {
+    if ((st = sb_logl_grad_dev(m, B, X, L, G, SB_DTYPE_F64, gws, gws_bytes, stream))) return st;
+    hipLaunchKernelGGL(anti_move_kernel, dim3((unsigned)ceil_div(bd, 256)), dim3(256), 0, s, bd, d,
+                       G, stuck, lo, hi, alpha, mu, t == 0 ? 1 : 0, V, X);
+    SB_LAUNCH_CHECK();
+  }
+  return SB_OK;
+}
+
+}  // extern "C"

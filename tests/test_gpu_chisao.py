@@ -1,0 +1,142 @@
+"""ChiSao moves on the GPU (stick detection, Hands Like Clouds, anti-convergence) against the
+oracle.
+
+Stick detection compares FP64 values with thresholds in the same precision on both sides, so
+the masks must agree bit for bit.  The moves are per sample: each row's trajectory depends on
+its own coordinates and draws only, so the oracle can follow any subset of rows.  The two sides
+sum the contraction in different orders (relative differences ~1e-14 in each gradient), which
+the steps carry forward with a gain of at most (1 + alpha |P|)^n; the bound below is 1e-9 of
+the box's scale.  Stuck rows must come back bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2601_19957_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2601_19957_amd import _lib
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    _lib.lib()
+    return _lib
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def mixture(d, K, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return synth.gaussian_mixture(rng, d, K, -8.0, 8.0, 0.05, 1.0, 12.0 if K > 1 else 0.0,
+                                  box_half=12.0, norm=synth.NORM_DENSITY, linf_min=1.0)
+
+
+def t_problem(d, seed, nu):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return synth.student_t(rng, d, nu, -5.0, 5.0, 0.01, 1.0, 20.0)
+
+
+def test_stick_special_cases_and_random(L):
+    t = -math.log(10.0)
+    l = np.array([0.0, t, np.nextafter(t, -np.inf), 0.0, -5.0, np.inf, np.nan, 0.0])
+    G = np.zeros((8, 3))
+    G[3, 1] = -1e-6
+    G[7, 2] = np.nan
+    got = L.sb_chisao_stick_dev(_dev(l), _dev(G), 1e-6).cpu().numpy()
+    assert got.tolist() == O.chisao_stick(l, G, 1e-6).tolist() == [1, 1, 0, 0, 0, 0, 0, 0]
+    rng = np.random.Generator(np.random.PCG64(71))
+    for B, d in ((1, 1), (3001, 70), (4097, 1024)):
+        l = rng.normal(scale=1.5, size=B)
+        l[rng.integers(0, B, size=B // 50)] = -np.inf
+        G = rng.normal(scale=1e-3, size=(B, d)) * (rng.random((B, 1)) < 0.5)
+        if B > 10:
+            G[5, d - 1] = np.nan
+            l[7] = float(np.max(l[np.isfinite(l)])) + t  # exactly on the threshold
+        got = L.sb_chisao_stick_dev(_dev(l), _dev(G), 2e-3).cpu().numpy()
+        assert np.array_equal(got, O.chisao_stick(l, G, 2e-3)), (B, d)
+    assert L.sb_chisao_stick_dev(_dev(np.zeros(0)), _dev(np.zeros((0, 4))), 1.0).numel() == 0
+
+
+CASES = {
+    # name: (problem, B, n_cloud, n_smooth, sigma, alpha_cloud, n_anti, alpha, mu)
+    "mix_d64_K3": (lambda: mixture(64, 3, 72), 37, 2, 3, 0.3, 0.02, 4, 0.01, 0.9),
+    "mix_d33_K2_box": (lambda: mixture(33, 2, 73), 21, 1, 2, 0.5, 2.0, 3, 0.5, 0.9),
+    "t_d70": (lambda: t_problem(70, 74, 4.0), 19, 2, 4, 0.2, 0.01, 3, 0.005, 0.5),
+    "gauss_d129": (lambda: mixture(129, 1, 75), 9, 1, 1, 0.0, 0.05, 2, 0.02, 0.9),
+    "c4b_rows": (lambda: synth.make_problem("c4b"), 6, 1, 2, 0.1, 0.05, 2, 0.02, 0.9),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_explore_matches_oracle(L, name):
+    mk, B, n_cloud, ns, sigma, ac, n_anti, a, mu = CASES[name]
+    prob = mk()
+    d = prob.d
+    X0 = synth.random_points(prob, B, seed=76)
+    rng = np.random.Generator(np.random.PCG64(77))
+    Z = rng.normal(size=(n_cloud, ns, B, d))
+    stuck = (rng.random(B) < 0.3).astype(np.uint8)
+    ref = O.chisao_explore(prob, X0, stuck, Z, sigma, ac, n_anti, a, mu)
+    m = L.DeviceModel(prob)
+    X = _dev(X0)
+    L.sb_chisao_explore_dev(m, X, _dev(stuck, torch.uint8), _dev(Z), sigma, ac, n_anti, a, mu)
+    got = X.cpu().numpy()
+    assert np.array_equal(got[stuck == 1], X0[stuck == 1])
+    scale = float(np.max(prob.hi - prob.lo))
+    err = np.abs(got - ref)
+    assert float(err.max()) <= 1e-9 * scale, float(err.max())
+    assert np.all(got >= prob.lo) and np.all(got <= prob.hi)
+    assert not np.array_equal(got[stuck == 0], X0[stuck == 0])
+
+
+def test_explore_full_batch_sampled_rows(L):
+    """The K = 8 mixture at d = 1024 with 16384 samples (the bulk's batch), one smoothing step
+    of four draws and four momentum steps; the oracle follows 12 sampled rows."""
+    prob = synth.make_problem("c4b")
+    B, d, ns = 16384, prob.d, 4
+    g = torch.Generator(device="cuda").manual_seed(78)
+    X0 = synth.random_points(prob, B, seed=79)
+    Zd = torch.randn((1, ns, B, d), generator=g, dtype=torch.float64, device="cuda")
+    stuck = np.zeros(B, np.uint8)
+    stuck[::7] = 1
+    m = L.DeviceModel(prob)
+    X = _dev(X0)
+    L.sb_chisao_explore_dev(m, X, _dev(stuck, torch.uint8), Zd, 0.1, 0.05, 4, 0.02, 0.9)
+    got = X.cpu().numpy()
+    rows = np.array([0, 1, 2, 777, 4095, 4096, 8191, 9000, 12345, 16381, 16382, 16383])
+    Zs = Zd[:, :, rows].cpu().numpy()
+    ref = O.chisao_explore(prob, X0[rows], stuck[rows], Zs, 0.1, 0.05, 4, 0.02, 0.9)
+    assert float(np.abs(got[rows] - ref).max()) <= 1e-9 * float(np.max(prob.hi - prob.lo))
+    assert np.array_equal(got[stuck == 1], X0[stuck == 1])
+
+
+def test_explore_degenerate_and_errors(L):
+    prob = mixture(16, 2, 80)
+    m = L.DeviceModel(prob)
+    X0 = synth.random_points(prob, 5, seed=81)
+    X = _dev(X0)
+    free = _dev(np.zeros(5), torch.uint8)
+    # no steps: unchanged; empty batch: no-op
+    L.sb_chisao_explore_dev(m, X, free, None, 0.1, 0.1, 0, 0.1, 0.9)
+    assert np.array_equal(X.cpu().numpy(), X0)
+    L.sb_chisao_explore_dev(m, _dev(np.zeros((0, 16))), _dev(np.zeros(0), torch.uint8),
+                            None, 0.1, 0.1, 3, 0.1, 0.9)
+    # all stuck: unchanged after both phases
+    Z = _dev(np.ones((1, 2, 5, 16)))
+    L.sb_chisao_explore_dev(m, X, _dev(np.ones(5), torch.uint8), Z, 0.1, 0.1, 2, 0.1, 0.9)
+    assert np.array_equal(X.cpu().numpy(), X0)
+    with pytest.raises(RuntimeError):
+        L.sb_chisao_explore_dev(m, X, free, Z, -1.0, 0.1, 1, 0.1, 0.9)
+    with pytest.raises(RuntimeError):
+        L.sb_chisao_explore_dev(m, X, free, Z, 0.1, float("nan"), 1, 0.1, 0.9)
+    with pytest.raises(RuntimeError):
+        L.sb_chisao_stick_dev(_dev(np.zeros(2)), _dev(np.zeros((2, 2))), float("inf"))
