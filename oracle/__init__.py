@@ -359,6 +359,45 @@ def chisao_explore(prob, X, stuck, Z, sigma, alpha_cloud, n_anti, alpha, mu,
     return X
 
 
+def chisao_reseed(prob, X, U, n_pts, op: Optional[OracleProblem] = None):
+    """The reseeding ray of the ChiSao cycle (section "ChiSao Exploration", the Repulse Monkey /
+    Golden Rooster step: rays shot from existing samples in given directions), sampled as the
+    coarse pass samples a ray (section "Ray Generation": uniform points along r(t), keep the
+    best).  From origin x along direction u the ray ends where it leaves the box, at
+    t_exit = min over u_i != 0 of (hi_i - x_i)/u_i (u_i > 0) or (lo_i - x_i)/u_i (u_i < 0),
+    at least 0 (0 when u = 0); its points are x + (t_j t_exit) u with t_j = (j + 1/2)/n_pts; the
+    new sample is the point of highest l (ties: lowest j; non-finite l never chosen; none
+    finite: x stays).  Returns the new samples and their l (NaN where x stayed)."""
+    op = op or OracleProblem(prob)
+    X = _f64(np.atleast_2d(X))
+    U = _f64(np.atleast_2d(U))
+    lo, hi = op.lo, op.hi
+    out = X.copy()
+    best = np.full(X.shape[0], np.nan)
+    for b in range(X.shape[0]):
+        x, u = X[b], U[b]
+        te = math.inf
+        for i in range(x.size):
+            if u[i] > 0:
+                te = min(te, (hi[i] - x[i]) / u[i])
+            elif u[i] < 0:
+                te = min(te, (lo[i] - x[i]) / u[i])
+        te = 0.0 if te == math.inf else max(te, 0.0)
+        P = np.empty((n_pts, x.size))
+        for j in range(n_pts):
+            s = ((j + 0.5) / n_pts) * te
+            P[j] = x + s * u
+        l = logl(prob, P, grad=False, op=op)
+        jb = -1
+        for j in range(n_pts):
+            if math.isfinite(l[j]) and (jb < 0 or l[j] > l[jb]):
+                jb = j
+        if jb >= 0:
+            out[b] = P[jb]
+            best[b] = l[jb]
+    return out, best
+
+
 def log_volume(lo, hi) -> float:
     lo = _f64(lo)
     hi = _f64(hi)

@@ -919,3 +919,40 @@ def test_chisao_clouds_closed_form_and_invariants(oracle_lib):
     g = -prob.prec[0] @ (Xs[0] - prob.mu[0])
     ref = np.where(g > 0, prob.hi, np.where(g < 0, prob.lo, Xs[0]))
     assert np.array_equal(big[0], ref)
+
+
+def test_chisao_reseed_ray_closed_form(oracle_lib):
+    """On a Gaussian peak-zero l the best sample of a ray is the sample nearest (in the
+    P-metric) to the ray's maximiser t* = u^T P (mu - x) / u^T P u: the ray's l is a parabola
+    in t.  The exit point lies on a face of the box and the samples inside it; u = 0 keeps
+    x; a ray along one axis ends at that axis's face."""
+    O = oracle_lib
+    d, n = 7, 32
+    prob = _isotropic_or_dense(51, d, True)
+    prob.lo = np.full(d, -3.0)
+    prob.hi = np.full(d, 4.0)
+    rng = np.random.Generator(np.random.PCG64(52))
+    X = rng.uniform(-2.5, 3.5, (6, d))
+    U = rng.normal(size=(6, d))
+    U[4] = 0.0
+    U[5] = 0.0
+    U[5, 2] = -0.5
+    out, best = O.chisao_reseed(prob, X, U, n)
+    P, mu = prob.prec[0], prob.mu[0]
+    for b in range(4):
+        x, u = X[b], U[b]
+        te = np.min(np.where(u > 0, (prob.hi - x) / u, (prob.lo - x) / u))
+        end = x + te * u
+        assert np.min(np.minimum(np.abs(end - prob.lo), np.abs(end - prob.hi))) < 1e-12
+        ts = (np.arange(n) + 0.5) / n * te
+        tstar = float(u @ P @ (mu - x)) / float(u @ P @ u)
+        curv = float(u @ P @ u)
+        val = -0.5 * curv * (ts - tstar) ** 2  # l along the ray up to a constant
+        j = int(np.argmax(val))
+        assert np.allclose(out[b], x + ts[j] * u, rtol=0, atol=1e-12)
+        assert np.all(out[b] >= prob.lo - 1e-12) and np.all(out[b] <= prob.hi + 1e-12)
+    assert np.array_equal(out[4], X[4])
+    assert np.allclose(out[5][[0, 1, 3, 4, 5, 6]], X[5][[0, 1, 3, 4, 5, 6]], rtol=0, atol=0)
+    te5 = (prob.lo[2] - X[5, 2]) / -0.5
+    assert np.any(np.isclose(out[5][2], X[5, 2] - 0.5 * (np.arange(n) + 0.5) / n * te5,
+                             rtol=0, atol=1e-12))
