@@ -305,7 +305,8 @@ def chisao_leg(L, prob, name, reps=3):
     """ChiSao moves at the bulk's batch (16384 samples of the workload's posterior, every
     seventh stuck): one Hands Like Clouds step of four draws plus four anti-convergence steps,
     FP64 (8 batches of gradients), then stick detection on the result; wall time per call after
-    a warm call, gradient evaluations per second and the contraction's FP64 rate."""
+    a warm call, gradient evaluations per second and the contraction's FP64 rate; and reseeding
+    rays (32 points each) from 2048 of the samples."""
     import numpy as np
     import torch
     from paper_2601_19957_amd import synth
@@ -333,13 +334,27 @@ def chisao_leg(L, prob, name, reps=3):
     sm = L.sb_chisao_stick_dev(l, gr, 1e-3)
     torch.cuda.synchronize()
     ds = time.perf_counter() - t1
+    # reseeding rays from 2048 of the samples, 32 points each (65536 FP64 l evaluations)
+    Br, npt = 2048, 32
+    U = torch.randn((Br, d), generator=g, dtype=torch.float64, device="cuda")
+    Xr = X[:Br].clone()
+    L.sb_chisao_reseed_dev(m, Xr, U, npt)  # tile autotune at this row count
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(reps):
+        Xr.copy_(X[:Br])
+        L.sb_chisao_reseed_dev(m, Xr, U, npt)
+    torch.cuda.synchronize()
+    dr = (time.perf_counter() - t2) / reps
     n_ev = B * (ns + n_anti)
     flops = n_ev * K * 2.0 * d * d
     return dict(workload=f"{name}: B={B} d={d} K={K} n_smooth={ns} n_anti={n_anti}",
                 ms=dt * 1e3, grad_evals=n_ev, grad_evals_per_s=n_ev / dt,
                 contraction_tflops=flops / dt / 1e12,
                 frac_fp64_peak=flops / dt / 1e12 / PEAK["fp64"], stick_ms=ds * 1e3,
-                n_stuck_after=int(sm.sum().item()))
+                n_stuck_after=int(sm.sum().item()),
+                reseed=dict(rays=Br, n_pts=npt, ms=dr * 1e3,
+                            logl_evals_per_s=Br * npt / dr))
 
 
 def reduce_leg(L, prob, name):

@@ -279,6 +279,23 @@ int32_t sb_chisao_stick_dev(int64_t B, int32_t d, const double *logl, const doub
                             double grad_tol, uint8_t *stuck, void *workspace, size_t ws_bytes,
                             void *stream);
 
+/* ChiSao reseeding ray (section "ChiSao Exploration": the Repulse Monkey /
+ * Golden Rooster step shoots rays from existing samples; they are sampled as
+ * the coarse pass of section "Ray Generation" samples a ray).  For each of B
+ * samples X [B][d] (device FP64, in place) and direction U [B][d] (device
+ * FP64, chosen by the caller: random for Repulse Monkey, orthonormal for
+ * Golden Rooster), the ray runs from x to where it leaves the box [lo, hi]:
+ * t_exit = min over u_i != 0 of (hi_i - x_i)/u_i (u_i > 0) or (lo_i - x_i)/u_i
+ * (u_i < 0), at least 0, and 0 for u = 0.  l is evaluated in FP64 at
+ * x + (t_j t_exit) u, t_j = (j + 1/2)/n_pts, and the first point of highest
+ * finite l replaces x (none finite: x stays); best_l [B] (device, nullable)
+ * gets that l or NaN.  SB_E_INVAL for B < 0, n_pts < 1 or NULL arrays.
+ * Workspace >= sb_chisao_reseed_workspace_bytes(d, K, B, n_pts). */
+size_t sb_chisao_reseed_workspace_bytes(int32_t d, int32_t K, int64_t B, int32_t n_pts);
+int32_t sb_chisao_reseed_dev(const sb_model_dev *m, const double *lo, const double *hi,
+                             int64_t B, double *X, const double *U, int32_t n_pts,
+                             double *best_l, void *workspace, size_t ws_bytes, void *stream);
+
 /* ChiSao moves of the samples that are not stuck (section "ChiSao
  * Exploration": the Hands Like Clouds smoothed gradient and the momentum
  * equation of the anti-convergence phase), in place on X [B][d] (device

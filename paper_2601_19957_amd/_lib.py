@@ -34,7 +34,8 @@ EXPORTS = [
     "sb_lbfgs_direction_dev", "sb_lbfgs_workspace_bytes", "sb_lbfgs_dev",
     "sb_lbfgs_timed_dev", "sb_precheck_workspace_bytes", "sb_precheck_dev",
     "sb_eig_reduce_workspace_bytes", "sb_eig_reduce_dev", "sb_chisao_stick_dev",
-    "sb_chisao_explore_workspace_bytes", "sb_chisao_explore_dev", "sb_user_compile", "sb_user_release",
+    "sb_chisao_explore_workspace_bytes", "sb_chisao_explore_dev",
+    "sb_chisao_reseed_workspace_bytes", "sb_chisao_reseed_dev", "sb_user_compile", "sb_user_release",
     "sb_user_logl_dev", "sb_user_fd_workspace_bytes", "sb_user_fd_dev",
     "sb_user_mode_evidence_workspace_bytes", "sb_user_mode_evidence_dev",
     "sb_user_evidence_workspace_bytes", "sb_user_evidence_dev",
@@ -132,6 +133,8 @@ def lib():
             "sb_chisao_explore_workspace_bytes": (sz, [i32, i32, i64, i32]),
             "sb_chisao_explore_dev": (i32, [vp, vp, vp, i64, vp, vp, i32, i32, vp, f64, f64, i32,
                                             f64, f64, vp, sz, vp]),
+            "sb_chisao_reseed_workspace_bytes": (sz, [i32, i32, i64, i32]),
+            "sb_chisao_reseed_dev": (i32, [vp, vp, vp, i64, vp, vp, i32, vp, vp, sz, vp]),
             "sb_user_compile": (i32, [C.c_char_p, C.c_char_p, vp]),
             "sb_user_release": (None, [vp]),
             "sb_user_logl_dev": (i32, [vp, i64, i32, vp, vp, vp, vp]),
@@ -590,6 +593,27 @@ def sb_chisao_explore_dev(model: DeviceModel, X, stuck, Z, sigma: float, alpha_c
                                      n_anti, alpha, mu, ws.data_ptr(), ws.numel(), _stream())
     _check(st, "sb_chisao_explore_dev")
     return X
+
+
+def sb_chisao_reseed_dev(model: DeviceModel, X, U, n_pts: int, lo=None, hi=None):
+    """ChiSao reseeding rays from the samples X [B][d] (device FP64, replaced in place by the
+    best point of each ray) along directions U [B][d]; returns (X, best_l)."""
+    import torch
+
+    assert X.is_contiguous() and X.dtype == torch.float64
+    U = U.contiguous()
+    B, d = X.shape
+    dev = X.device
+    lo = model.lo if lo is None else lo
+    hi = model.hi if hi is None else hi
+    best = torch.empty(B, dtype=torch.float64, device=dev)
+    ws = _ws(lib().sb_chisao_reseed_workspace_bytes(d, model.K, max(B, 1), max(n_pts, 1)), dev)
+    mv = model.view(DTYPE_F64)
+    st = lib().sb_chisao_reseed_dev(C.byref(mv), lo.data_ptr(), hi.data_ptr(), B, X.data_ptr(),
+                                    U.data_ptr(), n_pts, best.data_ptr(), ws.data_ptr(),
+                                    ws.numel(), _stream())
+    _check(st, "sb_chisao_reseed_dev")
+    return X, best
 
 
 class UserLogL:

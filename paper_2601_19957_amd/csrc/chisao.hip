@@ -13,8 +13,12 @@
 // (summed in k order, then divided by n_smooth) times alpha_cloud moves each
 // free sample.  Anti-convergence: v <- mu v - alpha grad l(x), x <- x + v,
 // starting from v = 0.  Every move is clipped to the prior box; stuck samples
-// keep their coordinates.  The elementwise kernels round each operation
-// separately (no contraction into FMAs), in the order the steps are written.
+// keep their coordinates.  Reseeding (Repulse Monkey / Golden Rooster): from
+// each sample along a given direction to where the ray leaves the box, n_pts
+// points at t_j = (j + 1/2)/n_pts of that span, l in one FP64 batch, and the
+// first point of highest finite l replaces the sample.  The elementwise
+// kernels round each operation separately (no contraction into FMAs), in the
+// order the steps are written.
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -120,6 +124,65 @@ __global__ __launch_bounds__(256) void anti_move_kernel(int64_t bd, int d, const
   X[e] = clip_box(X[e] + v, lo[j], hi[j]);
 }
 
+
+// Reseeding rays: t_exit per sample (one wave), then the n_pts points per ray,
+// then the best of them.  te[b] = min over u_i != 0 of the distance parameter
+// to the face u points at, at least 0; 0 when u = 0.
+__global__ __launch_bounds__(256) void reseed_exit_kernel(int64_t B, int d, const double *X,
+                                                          const double *U, const double *lo,
+                                                          const double *hi, double *te) {
+  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (b >= B) return;
+  double m = INFINITY;
+  for (int i = lane; i < d; i += 64) {
+    const double u = U[b * d + i], x = X[b * d + i];
+    if (u > 0.0) m = fmin(m, (hi[i] - x) / u);
+    else if (u < 0.0) m = fmin(m, (lo[i] - x) / u);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+  if (lane == 0) te[b] = isinf(m) ? 0.0 : fmax(m, 0.0);
+}
+
+// P[b][j][i] = x_bi + ((j + 1/2)/n_pts * te_b) u_bi, each operation rounded.
+__global__ __launch_bounds__(256) void reseed_points_kernel(int64_t B, int d, int n_pts,
+                                                            const double *X, const double *U,
+                                                            const double *te, double *P) {
+#pragma clang fp contract(off)
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= B * n_pts * d) return;
+  const int i = (int)(e % d);
+  const int64_t r = e / d;
+  const int j = (int)(r % n_pts);
+  const int64_t b = r / n_pts;
+  const double tj = ((double)j + 0.5) / (double)n_pts;
+  const double s = tj * te[b];
+  const double su = s * U[b * d + i];
+  P[e] = X[b * d + i] + su;
+}
+
+// One wave per sample: the first point of highest finite l replaces x.
+__global__ __launch_bounds__(256) void reseed_pick_kernel(int64_t B, int d, int n_pts,
+                                                          const double *P, const double *L,
+                                                          double *X, double *best_l) {
+  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (b >= B) return;
+  int jb = -1;
+  double lb = 0.0;
+  for (int j = 0; j < n_pts; ++j) {
+    const double v = L[b * n_pts + j];
+    if (isfinite(v) && (jb < 0 || v > lb)) {
+      jb = j;
+      lb = v;
+    }
+  }
+  if (jb >= 0)
+    for (int i = lane; i < d; i += 64) X[b * d + i] = P[(b * n_pts + jb) * d + i];
+  if (lane == 0 && best_l) best_l[b] = jb >= 0 ? lb : (double)NAN;
+}
+
 }  // namespace sb
 
 using namespace sb;
@@ -209,6 +272,49 @@ int32_t sb_chisao_explore_dev(const sb_model_dev *m, const double *lo, const dou
                        G, stuck, lo, hi, alpha, mu, t == 0 ? 1 : 0, V, X);
     SB_LAUNCH_CHECK();
   }
+  return SB_OK;
+}
+
+size_t sb_chisao_reseed_workspace_bytes(int32_t d, int32_t K, int64_t B, int32_t n_pts) {
+  if (d < 1 || K < 1 || B < 1 || n_pts < 1) return 0;
+  const int64_t rows = B * n_pts;
+  return align_up(8ull * rows * d) + align_up(8ull * rows) + align_up(8ull * B) +
+         sb_logl_grad_workspace_bytes(d, K, rows, SB_DTYPE_F64) + 1024;
+}
+
+int32_t sb_chisao_reseed_dev(const sb_model_dev *m, const double *lo, const double *hi,
+                             int64_t B, double *X, const double *U, int32_t n_pts,
+                             double *best_l, void *workspace, size_t ws_bytes, void *stream) {
+  if (!m) return fail(SB_E_INVAL, "model is NULL");
+  if (B < 0 || n_pts < 1) return fail(SB_E_INVAL, "reseeding needs B >= 0 and n_pts >= 1");
+  if (B == 0) return SB_OK;
+  if (!X || !U || !lo || !hi) return fail(SB_E_INVAL, "NULL X, U or box");
+  const int d = m->d;
+  if (d < 1) return fail(SB_E_INVAL, "model d must be >= 1");
+  const int64_t rows = B * n_pts;
+  if (rows * d > ((int64_t)1 << 38) || B > (int64_t)4 * INT32_MAX)
+    return fail(SB_E_INVAL, "too many ray points");
+  if (!workspace || ws_bytes < sb_chisao_reseed_workspace_bytes(d, m->K, B, n_pts))
+    return fail(SB_E_NOMEM, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  Arena ar(workspace, ws_bytes);
+  double *P = ar.take<double>((size_t)(rows * d));
+  double *L = ar.take<double>((size_t)rows);
+  double *te = ar.take<double>((size_t)B);
+  const size_t gws_bytes = sb_logl_grad_workspace_bytes(d, m->K, rows, SB_DTYPE_F64);
+  void *gws = ar.take<char>(gws_bytes);
+  if (!ar.ok()) return fail(SB_E_NOMEM, "workspace too small");
+  hipLaunchKernelGGL(reseed_exit_kernel, dim3((unsigned)ceil_div(B, 4)), dim3(256), 0, s, B, d,
+                     X, U, lo, hi, te);
+  SB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(reseed_points_kernel, dim3((unsigned)ceil_div(rows * d, 256)), dim3(256), 0,
+                     s, B, d, n_pts, X, U, te, P);
+  SB_LAUNCH_CHECK();
+  int st = sb_logl_grad_dev(m, rows, P, L, nullptr, SB_DTYPE_F64, gws, gws_bytes, stream);
+  if (st) return st;
+  hipLaunchKernelGGL(reseed_pick_kernel, dim3((unsigned)ceil_div(B, 4)), dim3(256), 0, s, B, d,
+                     n_pts, P, L, X, best_l);
+  SB_LAUNCH_CHECK();
   return SB_OK;
 }
 

@@ -140,3 +140,35 @@ def test_explore_degenerate_and_errors(L):
         L.sb_chisao_explore_dev(m, X, free, Z, 0.1, float("nan"), 1, 0.1, 0.9)
     with pytest.raises(RuntimeError):
         L.sb_chisao_stick_dev(_dev(np.zeros(2)), _dev(np.zeros((2, 2))), float("inf"))
+
+
+@pytest.mark.parametrize("name,d,K,B,n_pts", [("mix_d64_K3", 64, 3, 33, 32),
+                                              ("mix_d1_K1", 1, 1, 5, 7),
+                                              ("c4b", 1024, 8, 40, 32)])
+def test_reseed_matches_oracle(L, name, d, K, B, n_pts):
+    """Ray points are bit-identical on both sides (same operations, each rounded); the chosen
+    point must be the oracle's wherever the best l leads the runner-up by more than the
+    rounding of l, and otherwise be one of the tied points; its l agrees to 1e-12 relative."""
+    prob = synth.make_problem("c4b") if name == "c4b" else mixture(d, K, 82 + d)
+    X0 = synth.random_points(prob, B, seed=83)
+    rng = np.random.Generator(np.random.PCG64(84))
+    U = rng.normal(size=(B, prob.d))
+    U[0] = 0.0
+    if prob.d > 1:
+        U[1, 1:] = 0.0
+    ref, ref_l = O.chisao_reseed(prob, X0, U, n_pts)
+    m = L.DeviceModel(prob)
+    X = _dev(X0)
+    got, best = L.sb_chisao_reseed_dev(m, X, _dev(U), n_pts)
+    got = got.cpu().numpy()
+    best = best.cpu().numpy()
+    assert np.array_equal(got[0], X0[0])
+    op = O.OracleProblem(prob)
+    for b in range(B):
+        assert abs(best[b] - ref_l[b]) <= 1e-12 * max(1.0, abs(ref_l[b])), b
+        if np.array_equal(got[b], ref[b]):
+            continue
+        # a near tie: the GPU's point must be a ray point whose l is within rounding of the best
+        lg = float(O.logl(prob, got[b][None], grad=False, op=op)[0])
+        assert abs(lg - ref_l[b]) <= 1e-12 * max(1.0, abs(ref_l[b])), b
+    assert np.all(got >= prob.lo) and np.all(got <= prob.hi)
