@@ -398,6 +398,20 @@ def chisao_reseed(prob, X, U, n_pts, op: Optional[OracleProblem] = None):
     return out, best
 
 
+def chisao_orthonormal(G):
+    """Golden Rooster's orthonormal ray directions (section "ChiSao Exploration": the
+    near-exhaustion refill shoots rays in orthonormal directions obtained by QR): for each
+    peak c, the n <= d rows of G [C][n][d] (Gaussian draws) are replaced by the rows of Q from
+    G_c^T = Q R with R's diagonal positive, which makes Q unique."""
+    G = _f64(G)
+    out = np.empty_like(G)
+    for c in range(G.shape[0]):
+        Q, R = np.linalg.qr(G[c].T)
+        sgn = np.where(np.diag(R) < 0, -1.0, 1.0)
+        out[c] = (Q * sgn).T
+    return out
+
+
 def log_volume(lo, hi) -> float:
     lo = _f64(lo)
     hi = _f64(hi)

@@ -956,3 +956,19 @@ def test_chisao_reseed_ray_closed_form(oracle_lib):
     te5 = (prob.lo[2] - X[5, 2]) / -0.5
     assert np.any(np.isclose(out[5][2], X[5, 2] - 0.5 * (np.arange(n) + 0.5) / n * te5,
                              rtol=0, atol=1e-12))
+
+
+def test_chisao_orthonormal_properties(oracle_lib):
+    """The rows are orthonormal, the draws are recovered as G = R' Q with R' lower triangular
+    and a positive diagonal (R' = R^T), and the first row is the first draw normalised."""
+    O = oracle_lib
+    rng = np.random.Generator(np.random.PCG64(53))
+    for n, d in ((1, 1), (3, 3), (5, 9), (16, 40)):
+        G = rng.normal(size=(2, n, d))
+        Q = O.chisao_orthonormal(G)
+        for c in range(2):
+            assert np.allclose(Q[c] @ Q[c].T, np.eye(n), atol=1e-13)
+            Rt = G[c] @ Q[c].T
+            assert np.allclose(np.triu(Rt, 1), 0.0, atol=1e-12)
+            assert np.all(np.diag(Rt) > 0)
+            assert np.allclose(Q[c, 0], G[c, 0] / np.linalg.norm(G[c, 0]), atol=1e-14)
