@@ -402,13 +402,20 @@ def chisao_orthonormal(G):
     """Golden Rooster's orthonormal ray directions (section "ChiSao Exploration": the
     near-exhaustion refill shoots rays in orthonormal directions obtained by QR): for each
     peak c, the n <= d rows of G [C][n][d] (Gaussian draws) are replaced by the rows of Q from
-    G_c^T = Q R with R's diagonal positive, which makes Q unique."""
+    G_c^T = Q R with R's diagonal positive, which makes Q unique.  Reading: a row whose
+    |R_kk| (its norm after removing the earlier directions) is at most 1e-12 of its own norm
+    depends on the earlier rows; it and every later row become NaN, since the rows after it
+    have no well-defined orthonormal completion from these draws."""
     G = _f64(G)
     out = np.empty_like(G)
     for c in range(G.shape[0]):
         Q, R = np.linalg.qr(G[c].T)
-        sgn = np.where(np.diag(R) < 0, -1.0, 1.0)
+        r = np.diag(R)
+        sgn = np.where(r < 0, -1.0, 1.0)
         out[c] = (Q * sgn).T
+        bad = np.abs(r) <= 1e-12 * np.linalg.norm(G[c], axis=1)
+        if bad.any():
+            out[c, int(np.argmax(bad)):] = np.nan
     return out
 
 

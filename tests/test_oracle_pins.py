@@ -972,3 +972,7 @@ def test_chisao_orthonormal_properties(oracle_lib):
             assert np.allclose(np.triu(Rt, 1), 0.0, atol=1e-12)
             assert np.all(np.diag(Rt) > 0)
             assert np.allclose(Q[c, 0], G[c, 0] / np.linalg.norm(G[c, 0]), atol=1e-14)
+    G = rng.normal(size=(1, 4, 6))
+    G[0, 2] = 2.0 * G[0, 0] - G[0, 1]
+    Q = O.chisao_orthonormal(G)
+    assert np.all(np.isfinite(Q[0, :2])) and np.all(np.isnan(Q[0, 2:]))
