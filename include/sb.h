@@ -296,6 +296,17 @@ int32_t sb_chisao_reseed_dev(const sb_model_dev *m, const double *lo, const doub
                              int64_t B, double *X, const double *U, int32_t n_pts,
                              double *best_l, void *workspace, size_t ws_bytes, void *stream);
 
+/* Golden Rooster's orthonormal ray directions (section "ChiSao Exploration":
+ * the near-exhaustion refill from converged peaks uses directions made
+ * orthonormal by QR).  For each of C peaks the n rows of G [C][n][d] (device
+ * FP64, in place; Gaussian draws chosen by the caller) become the rows of Q in
+ * G_c^T = Q R with R's diagonal positive (modified Gram-Schmidt, one workgroup
+ * per peak; n^2 d multiply-adds per peak).  A row whose norm after removing
+ * its projections on the earlier rows is at most 1e-12 of its own norm (it
+ * depends on them), or not finite, becomes NaN, and so does every later row.  SB_E_INVAL
+ * unless C >= 0 and 1 <= n <= d; G may be NULL when C = 0. */
+int32_t sb_chisao_orthonormal_dev(int32_t C, int32_t n, int32_t d, double *G, void *stream);
+
 /* ChiSao moves of the samples that are not stuck (section "ChiSao
  * Exploration": the Hands Like Clouds smoothed gradient and the momentum
  * equation of the anti-convergence phase), in place on X [B][d] (device

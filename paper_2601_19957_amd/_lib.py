@@ -35,7 +35,8 @@ EXPORTS = [
     "sb_lbfgs_timed_dev", "sb_precheck_workspace_bytes", "sb_precheck_dev",
     "sb_eig_reduce_workspace_bytes", "sb_eig_reduce_dev", "sb_chisao_stick_dev",
     "sb_chisao_explore_workspace_bytes", "sb_chisao_explore_dev",
-    "sb_chisao_reseed_workspace_bytes", "sb_chisao_reseed_dev", "sb_user_compile", "sb_user_release",
+    "sb_chisao_reseed_workspace_bytes", "sb_chisao_reseed_dev", "sb_chisao_orthonormal_dev",
+    "sb_user_compile", "sb_user_release",
     "sb_user_logl_dev", "sb_user_fd_workspace_bytes", "sb_user_fd_dev",
     "sb_user_mode_evidence_workspace_bytes", "sb_user_mode_evidence_dev",
     "sb_user_evidence_workspace_bytes", "sb_user_evidence_dev",
@@ -135,6 +136,7 @@ def lib():
                                             f64, f64, vp, sz, vp]),
             "sb_chisao_reseed_workspace_bytes": (sz, [i32, i32, i64, i32]),
             "sb_chisao_reseed_dev": (i32, [vp, vp, vp, i64, vp, vp, i32, vp, vp, sz, vp]),
+            "sb_chisao_orthonormal_dev": (i32, [i32, i32, i32, vp, vp]),
             "sb_user_compile": (i32, [C.c_char_p, C.c_char_p, vp]),
             "sb_user_release": (None, [vp]),
             "sb_user_logl_dev": (i32, [vp, i64, i32, vp, vp, vp, vp]),
@@ -614,6 +616,16 @@ def sb_chisao_reseed_dev(model: DeviceModel, X, U, n_pts: int, lo=None, hi=None)
                                     ws.numel(), _stream())
     _check(st, "sb_chisao_reseed_dev")
     return X, best
+
+
+def sb_chisao_orthonormal_dev(G):
+    """Golden Rooster directions: the rows of each G [C][n][d] (device FP64) made orthonormal
+    in place (QR with a positive R diagonal).  Returns G."""
+    assert G.is_contiguous() and G.dtype == __import__("torch").float64 and G.dim() == 3
+    Cn, n, d = G.shape
+    _check(lib().sb_chisao_orthonormal_dev(Cn, n, d, G.data_ptr(), _stream()),
+           "sb_chisao_orthonormal_dev")
+    return G
 
 
 class UserLogL:

@@ -183,6 +183,36 @@ __global__ __launch_bounds__(256) void reseed_pick_kernel(int64_t B, int d, int 
   if (lane == 0 && best_l) best_l[b] = jb >= 0 ? lb : (double)NAN;
 }
 
+// Golden Rooster's orthonormal directions: modified Gram-Schmidt in FP64, one
+// workgroup per peak, rows of G [C][n][d] in place.  Row k loses its
+// projection on each earlier (already normalised) row in turn, then is
+// divided by its norm, so the triangular factor's diagonal is positive.  A
+// row whose remaining norm is at most 1e-12 of its own norm (dependent on the
+// earlier rows), or not finite, becomes NaN.  Each thread
+// owns the coordinates i = tid (mod 256) of every row.
+__global__ __launch_bounds__(256) void mgs_rows_kernel(int n, int d, double *G) {
+  __shared__ double red[4];
+  double *V = G + (int64_t)blockIdx.x * n * d;
+  for (int k = 0; k < n; ++k) {
+    double *v = V + (int64_t)k * d;
+    double p0 = 0.0;
+    for (int i = threadIdx.x; i < d; i += 256) p0 += v[i] * v[i];
+    const double nrm0 = sqrt(block_sum<256>(p0, red));
+    for (int j = 0; j < k; ++j) {
+      const double *q = V + (int64_t)j * d;
+      double p = 0.0;
+      for (int i = threadIdx.x; i < d; i += 256) p += q[i] * v[i];
+      const double dot = block_sum<256>(p, red);
+      for (int i = threadIdx.x; i < d; i += 256) v[i] -= dot * q[i];
+    }
+    double p = 0.0;
+    for (int i = threadIdx.x; i < d; i += 256) p += v[i] * v[i];
+    const double nrm = sqrt(block_sum<256>(p, red));
+    const bool ok = nrm > 1e-12 * nrm0 && isfinite(nrm);
+    for (int i = threadIdx.x; i < d; i += 256) v[i] = ok ? v[i] / nrm : (double)NAN;
+  }
+}
+
 }  // namespace sb
 
 using namespace sb;
@@ -314,6 +344,16 @@ int32_t sb_chisao_reseed_dev(const sb_model_dev *m, const double *lo, const doub
   if (st) return st;
   hipLaunchKernelGGL(reseed_pick_kernel, dim3((unsigned)ceil_div(B, 4)), dim3(256), 0, s, B, d,
                      n_pts, P, L, X, best_l);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+int32_t sb_chisao_orthonormal_dev(int32_t C, int32_t n, int32_t d, double *G, void *stream) {
+  if (C < 0 || n < 1 || d < 1 || n > d) return fail(SB_E_INVAL, "need C >= 0 and 1 <= n <= d");
+  if (C == 0) return SB_OK;
+  if (!G) return fail(SB_E_INVAL, "G is NULL");
+  hipLaunchKernelGGL(mgs_rows_kernel, dim3((unsigned)C), dim3(256), 0, (hipStream_t)stream, n, d,
+                     G);
   SB_LAUNCH_CHECK();
   return SB_OK;
 }

@@ -172,3 +172,27 @@ def test_reseed_matches_oracle(L, name, d, K, B, n_pts):
         lg = float(O.logl(prob, got[b][None], grad=False, op=op)[0])
         assert abs(lg - ref_l[b]) <= 1e-12 * max(1.0, abs(ref_l[b])), b
     assert np.all(got >= prob.lo) and np.all(got <= prob.hi)
+
+
+@pytest.mark.parametrize("C,n,d", [(1, 1, 1), (3, 7, 7), (5, 13, 300), (2, 64, 1024)])
+def test_orthonormal_matches_oracle(L, C, n, d):
+    """Modified Gram-Schmidt against Householder QR (numpy): both give the unique Q with a
+    positive R diagonal; Gaussian draws with n <= d are well conditioned, so the two agree to
+    1e-11 and the rows are orthonormal to 1e-12."""
+    rng = np.random.Generator(np.random.PCG64(85 + n))
+    G0 = rng.normal(size=(C, n, d))
+    ref = O.chisao_orthonormal(G0)
+    G = _dev(G0)
+    got = L.sb_chisao_orthonormal_dev(G).cpu().numpy()
+    assert float(np.abs(got - ref).max()) <= 1e-11
+    for c in range(C):
+        assert np.allclose(got[c] @ got[c].T, np.eye(n), atol=1e-12)
+
+
+def test_orthonormal_dependent_rows_and_errors(L):
+    G0 = np.random.Generator(np.random.PCG64(86)).normal(size=(1, 3, 5))
+    G0[0, 2] = 2.0 * G0[0, 0] - G0[0, 1]
+    got = L.sb_chisao_orthonormal_dev(_dev(G0)).cpu().numpy()
+    assert np.all(np.isfinite(got[0, :2])) and np.all(np.isnan(got[0, 2]))
+    with pytest.raises(RuntimeError):
+        L.sb_chisao_orthonormal_dev(_dev(np.zeros((1, 4, 3))))
