@@ -42,7 +42,10 @@
  * constrained coordinates (sb_precheck_dev), the eigendecomposition-based
  * reduction at the modes for sampler handoff (sb_eig_reduce_dev), and
  * generic user likelihoods given as HIP source, compiled at run time, with
- * finite-difference derivatives and their own evidence path (sb_user_*).
+ * finite-difference derivatives and their own evidence path (sb_user_*),
+ * and the building blocks of the ChiSao exploration cycle: stick detection,
+ * the Hands Like Clouds and anti-convergence moves, the reseeding ray and
+ * Golden Rooster's orthonormal directions (sb_chisao_*).
  */
 #ifndef SB_H
 #define SB_H
