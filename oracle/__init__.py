@@ -107,6 +107,8 @@ def lib():
         L.or_evidence.argtypes = [vp, vp, vp, vp, vp]
         L.or_reference_modes.restype = i32
         L.or_reference_modes.argtypes = [vp, vp, vp, f64, i32, vp]
+        L.or_finish_points.restype = i32
+        L.or_finish_points.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -618,3 +620,268 @@ def reference_modes(prob, dedup_tol: float = 0.0, max_modes: int = 64) -> Oracle
                                                        _p(mll).value, _p(ldh).value)
     st = lib().or_reference_modes(op.ptr, _p(op.lo), _p(op.hi), dedup_tol, max_modes, C.byref(r))
     return _result(st, r, d, max_modes, modes, mlz, mll, ldh)
+
+
+# ------------------------------------------------------------- ChiSao cycle
+
+# Counter word 2 of the cycle's draws: CHISAO_STREAM0 + 8 * oscillation + purpose, purpose 0
+# (Repulse Monkey directions), 2 (Golden Rooster rows), 4 (Hands Like Clouds perturbations);
+# each normal takes the uniforms of streams s and s + 1 (the discovery rays use 0..2).
+CHISAO_STREAM0 = 16
+
+
+def chisao_normal(seed, problem, row, stream, i) -> float:
+    """Standard normal draw i of counter row `row`: the cosine branch of Box-Muller, as the
+    sunburst rays draw their directions, from uniform i of streams `stream` and `stream` + 1."""
+    u1 = rng_uniform(seed, problem, row, stream, i)
+    u2 = rng_uniform(seed, problem, row, stream + 1, i)
+    return math.sqrt(-2.0 * math.log(1.0 - u1)) * math.cos(2.0 * math.pi * u2)
+
+
+@dataclass
+class ChiSaoParams:
+    """Parameters of the oscillation cycle (section "ChiSao Exploration").  The paper gives
+    n_osc = 3 and the momentum 0.9; the rest are left open there and are parameters here."""
+    n_osc: int = 3
+    n_conv: int = 0            # L-BFGS steps per convergence phase (<= 0: the run's max_iter)
+    stick_tol: float = 1e-6    # gradient L-infinity tolerance of stick detection
+    n_reseed_pts: int = 32     # samples along a reseeding ray
+    n_cloud: int = 1           # Hands Like Clouds steps
+    n_smooth: int = 4          # perturbations per smoothed gradient
+    sigma: float = 0.0         # smoothing scale (<= 0: from the free samples' spread)
+    alpha_cloud: float = 0.01  # ascent step of Hands Like Clouds
+    n_anti: int = 8            # anti-convergence steps
+    alpha_anti: float = 0.01   # descent step of the anti-convergence phase
+    momentum: float = 0.9
+
+
+def chisao_sigma(X, free) -> float:
+    """Automatic smoothing scale (reading of "auto-estimated from sample spread"): half the
+    median over coordinates of the population standard deviation of the free samples'
+    coordinates; 0 with fewer than two free samples."""
+    F = _f64(np.atleast_2d(X))[np.asarray(free, dtype=bool)]
+    if F.shape[0] < 2:
+        return 0.0
+    sd = np.sqrt(np.mean((F - np.mean(F, axis=0)) ** 2, axis=0))
+    return 0.5 * float(np.median(sd))
+
+
+def chisao_cycle(prob, X0, prm: ChiSaoParams, m=8, max_iter=None, grad_tol=1e-10,
+                 dedup_tol=0.25, seed=0, problem=0, op: Optional[OracleProblem] = None):
+    """The oscillation cycle of CarryTiger (section "ChiSao Exploration": the oscillation
+    cycle and the algorithm summary of CarryTiger) on samples X0 [N][d], FP64.
+
+    For oscillation k = 0 .. n_osc - 1:
+      1. convergence: every active sample runs L-BFGS (fresh history, memory m) for at most
+         n_conv accepted steps toward a local maximum (all stuck masks released);
+      2. stick detection: converged-to-stick_tol and l >= l_max - ln 10 (chisao_stick over
+         the active samples);
+      3. dedup of the stuck samples by L-infinity leader clustering (radius dedup_tol,
+         highest l first): every stuck sample that joins another's cluster is lost (its slot
+         is freed); the leaders are the distinct peaks;
+      4. unless k is the last oscillation and if samples were lost: with >= 5 active samples
+         that did not converge, Repulse Monkey refills lost slot j (in slot order) with the
+         best point of a ray from unconverged sample j mod n_unconv (slot order) in a random
+         direction (chisao_reseed); with fewer, Golden Rooster (unless disabled) refills the
+         lost slots round-robin over the peaks (l descending), each peak's slots taking the
+         rows of QR-orthonormalised Gaussian draws (chisao_orthonormal, in chunks of d rows)
+         as directions of rays from the peak; otherwise the lost slots stay empty.  Refilled
+         slots are active and not stuck.  Golden Rooster disables itself for the remaining
+         oscillations when the oscillation after one in which it refilled ends with no more
+         distinct converged peaks (leaders of the converged samples, stuck or not) than the
+         one before;
+      5. unless k is the last oscillation: the free samples (active, not stuck) take n_cloud
+         Hands Like Clouds steps and n_anti anti-convergence steps (chisao_explore).
+    Draws: Repulse Monkey direction of slot b, coordinate i: chisao_normal(seed, problem, b,
+    CHISAO_STREAM0 + 8k, i), normalised; Golden Rooster row of slot b: stream + 2; Hands Like
+    Clouds perturbation (step c, draw q) of slot b: stream + 4, index (c n_smooth + q) d + i.
+    Returns a dict: X [N][d], l [N], status [N] of the last convergence phase (ST_* codes,
+    ST_DEAD for empty slots), active [N], and per-oscillation counts (peaks, lost, reseed
+    kind: 0 none, 1 Repulse Monkey, 2 Golden Rooster)."""
+    op = op or OracleProblem(prob)
+    d = prob.d
+    X = _f64(np.atleast_2d(X0)).copy()
+    N = X.shape[0]
+    lo, hi = op.lo, op.hi
+    mi = max_iter if max_iter is not None else 10 * d + 200
+    n_conv = prm.n_conv if prm.n_conv > 0 else mi
+    active = np.ones(N, dtype=bool)
+    l = np.full(N, np.nan)
+    G = np.zeros((N, d))
+    status = np.full(N, ST_DEAD, dtype=np.int32)
+    gr_enabled, gr_used, prev_peaks = True, False, -1
+    log = []
+    for k in range(prm.n_osc):
+        # 1. convergence phase
+        for b in range(N):
+            if not active[b]:
+                status[b] = ST_DEAD
+                continue
+            r = lbfgs(prob, X[b], m=m, max_iter=n_conv, grad_tol=grad_tol, op=op)
+            X[b], l[b], G[b], status[b] = r["x"], r["logl"], r["grad"], r["status"]
+        conv = active & (status == ST_CONVERGED)
+        # 2. stick detection over the active samples
+        idx = np.flatnonzero(active)
+        stuck = np.zeros(N, dtype=bool)
+        if idx.size:
+            stuck[idx] = chisao_stick(l[idx], G[idx], prm.stick_tol).astype(bool)
+        # 3. dedup of the stuck samples
+        rep_of, reps = dedup(X, l, dedup_tol, valid=stuck.astype(np.uint8))
+        lost = [b for b in range(N) if stuck[b] and rep_of[b] != b]
+        peaks = list(reps)
+        # distinct peaks the converged samples reached (stuck or below the stick threshold)
+        n_found = len(dedup(X, l, dedup_tol, valid=conv.astype(np.uint8))[1])
+        if gr_used and n_found <= prev_peaks:
+            gr_enabled = False
+        gr_used = False
+        prev_peaks = n_found
+        for b in lost:
+            active[b] = False
+            stuck[b] = False
+        kind = 0
+        last = k == prm.n_osc - 1
+        if not last and lost:
+            base = CHISAO_STREAM0 + 8 * k
+            unconv = [b for b in range(N) if active[b] and not conv[b]]
+            if len(unconv) >= 5:
+                kind = 1
+                O_ = np.array([X[unconv[j % len(unconv)]] for j in range(len(lost))])
+                U = np.zeros((len(lost), d))
+                for j, b in enumerate(lost):
+                    z = np.array([chisao_normal(seed, problem, b, base, i) for i in range(d)])
+                    U[j] = z / np.linalg.norm(z)
+                newx, _ = chisao_reseed(prob, O_, U, prm.n_reseed_pts, op=op)
+                for j, b in enumerate(lost):
+                    X[b] = newx[j]
+            elif gr_enabled and peaks:
+                kind = 2
+                gr_used = True
+                P = len(peaks)
+                for p in range(P):
+                    slots = lost[p::P]
+                    for c0 in range(0, len(slots), d):
+                        chunk = slots[c0:c0 + d]
+                        Gr = np.array([[chisao_normal(seed, problem, b, base + 2, i)
+                                        for i in range(d)] for b in chunk])
+                        U = chisao_orthonormal(Gr[None])[0]
+                        O_ = np.repeat(X[peaks[p]][None], len(chunk), axis=0)
+                        newx, _ = chisao_reseed(prob, O_, U, prm.n_reseed_pts, op=op)
+                        for j, b in enumerate(chunk):
+                            X[b] = newx[j]
+            if kind:
+                for b in lost:
+                    active[b] = True
+        log.append(dict(peaks=len(peaks), found=n_found, lost=len(lost), reseed=kind,
+                        converged=int(conv.sum()), golden_rooster=gr_enabled))
+        if last:
+            break
+        # 5. Hands Like Clouds and anti-convergence on the free samples
+        free = active & ~stuck
+        sigma = prm.sigma if prm.sigma > 0 else chisao_sigma(X, free)
+        base = CHISAO_STREAM0 + 8 * k + 4
+        Z = np.zeros((prm.n_cloud, prm.n_smooth, N, d))
+        for c in range(prm.n_cloud):
+            for q in range(prm.n_smooth):
+                for b in range(N):
+                    if free[b]:
+                        for i in range(d):
+                            Z[c, q, b, i] = chisao_normal(seed, problem, b, base,
+                                                          (c * prm.n_smooth + q) * d + i)
+        frozen = (~free).astype(np.uint8)
+        X = chisao_explore(prob, X, frozen, Z, sigma, prm.alpha_cloud, prm.n_anti,
+                           prm.alpha_anti, prm.momentum, op=op)
+    return dict(X=X, l=l, status=status, active=active, log=log)
+
+
+def refine_rays(prob, P0, P1, n_pts, n_ref, delta, op: Optional[OracleProblem] = None):
+    """Two-pass sampling along rays (section "Two-Pass Sampling").  Coarse pass: l at
+    t_j = (j + 1/2)/n_pts.  Active region of a ray: the cells [t_j - h/2, t_j + h/2]
+    (h = 1/n_pts) of its coarse samples with l_j > l_max - delta, l_max the ray's coarse
+    maximum.  Refinement pass: n_ref points placed with density proportional to the
+    likelihood within the active region, read as the piecewise-constant density
+    exp(l_j - l_max) on the active cells and its quantiles (i + 1/2)/n_ref (stratified, so
+    deterministic).  Returns per ray the best point over the coarse and refined samples
+    (highest l; ties: coarse before refined, then lowest index), its l and its t."""
+    op = op or OracleProblem(prob)
+    P0, P1 = _f64(np.atleast_2d(P0)), _f64(np.atleast_2d(P1))
+    R = P0.shape[0]
+    h = 1.0 / n_pts
+    best_t = np.zeros(R)
+    best_l = np.full(R, -np.inf)
+    T = np.zeros((R, n_ref))
+    for r in range(R):
+        tc = (np.arange(n_pts) + 0.5) * h
+        lc = logl(prob, P0[r] + tc[:, None] * (P1[r] - P0[r]), grad=False, op=op)
+        fin = np.isfinite(lc)
+        if not fin.any():
+            best_l[r] = np.nan
+            continue
+        lmax = float(np.max(lc[fin]))
+        act = [j for j in range(n_pts) if fin[j] and lc[j] > lmax - delta]
+        w = np.array([math.exp(lc[j] - lmax) * h for j in act])
+        cw = np.concatenate([[0.0], np.cumsum(w)])
+        tot = cw[-1]
+        tr = np.zeros(n_ref)
+        for i in range(n_ref):
+            u = (i + 0.5) / n_ref * tot
+            a = int(np.searchsorted(cw, u, side="right")) - 1
+            a = min(max(a, 0), len(act) - 1)
+            tr[i] = tc[act[a]] - 0.5 * h + (u - cw[a]) / w[a] * h
+        T[r] = tr
+        lr = logl(prob, P0[r] + tr[:, None] * (P1[r] - P0[r]), grad=False, op=op) \
+            if n_ref else np.zeros(0)
+        cand_t = np.concatenate([tc, tr])
+        cand_l = np.concatenate([lc, lr])
+        jb = -1
+        for j in range(cand_l.size):
+            if math.isfinite(cand_l[j]) and (jb < 0 or cand_l[j] > cand_l[jb]):
+                jb = j
+        best_t[r], best_l[r] = cand_t[jb], cand_l[jb]
+    return dict(best_t=best_t, best_l=best_l, t_refined=T)
+
+
+def finish_points(prob, cfg, X, l, valid, n_threads: int = 0, problem: int = 0) -> OracleResult:
+    """The whole path's tail from given end points (or_finish_points): pre-dedup, Newton
+    polish, filters, final dedup and the Laplace combine."""
+    op = OracleProblem(prob)
+    X = _f64(np.atleast_2d(X))
+    n = X.shape[0]
+    c = _Config(cfg.n_rays, cfg.n_points, cfg.n_starts, cfg.m, cfg.max_iter, cfg.max_modes,
+                cfg.grad_tol, cfg.dedup_tol, cfg.dedup_tol_pre, cfg.seed, n_threads, problem)
+    cap = cfg.max_modes
+    d = prob.d
+    modes = np.zeros((cap, d))
+    mlz = np.zeros(cap)
+    mll = np.zeros(cap)
+    ldh = np.zeros(cap)
+    r = _Result()
+    r.modes, r.mode_log_z, r.mode_logl, r.log_det_h = (_p(modes).value, _p(mlz).value,
+                                                       _p(mll).value, _p(ldh).value)
+    v = np.ascontiguousarray(valid, dtype=np.uint8)
+    lv = _f64(l)
+    st = lib().or_finish_points(op.ptr, _p(op.lo), _p(op.hi), C.byref(c), n, _p(X), _p(lv),
+                                _p(v), C.byref(r))
+    return _result(st, r, d, cap, modes, mlz, mll, ldh)
+
+
+def evidence_chisao(prob, cfg, prm: ChiSaoParams, n_ref: int = 0, delta: float = 10.0,
+                    problem: int = 0) -> OracleResult:
+    """The whole path with the ChiSao cycle as its convergence (CarryTiger's algorithm
+    summary): rays (or_rays), the coarse pass and, with n_ref > 0, the refinement pass
+    (refine_rays); the n_starts rays of highest best l (ties: lowest ray) seed the cycle
+    from their best points; the cycle's end points that are active with a finite l enter the
+    tail of the single-phase path (finish_points).  FP64 throughout."""
+    op = OracleProblem(prob)
+    P0, P1 = rays(prob.d, prob.lo, prob.hi, cfg.n_rays, cfg.seed, problem)
+    rf = refine_rays(prob, P0, P1, cfg.n_points, n_ref, delta, op=op)
+    key = np.where(np.isfinite(rf["best_l"]), rf["best_l"], -np.inf)
+    order = sorted(range(cfg.n_rays), key=lambda r: (-key[r], r))[:cfg.n_starts]
+    X0 = np.array([P0[r] + rf["best_t"][r] * (P1[r] - P0[r]) for r in order])
+    tol = cfg.grad_tol if cfg.grad_tol > 0 else 1e-10
+    tau_pre = cfg.dedup_tol_pre if cfg.dedup_tol_pre > 0 else 0.25
+    cyc = chisao_cycle(prob, X0, prm, m=cfg.m, max_iter=cfg.max_iter or None, grad_tol=tol,
+                       dedup_tol=tau_pre, seed=cfg.seed, problem=problem, op=op)
+    valid = cyc["active"] & np.isfinite(cyc["l"]) & (cyc["status"] != ST_DEAD)
+    res = finish_points(prob, cfg, cyc["X"], cyc["l"], valid, problem=problem)
+    res.cycle = cyc["log"]
+    return res

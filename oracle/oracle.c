@@ -956,6 +956,55 @@ int32_t or_evidence(const or_problem *p, const double *lo, const double *hi, con
   return st;
 }
 
+/* The tail of or_evidence from given optimiser end points X [n][d] with their
+ * l [n] and validity [n]: pre-polish dedup (tau_pre), then finish_modes
+ * (Newton polish, filters, final dedup, Laplace combine).  The ChiSao cycle's
+ * end points enter the same steps as the single convergence phase's. */
+int32_t or_finish_points(const or_problem *p, const double *lo, const double *hi,
+                         const or_config *cfg, int32_t n, const double *X, const double *l,
+                         const uint8_t *valid, or_result *res) {
+  int32_t st = validate_all(p, lo, hi, cfg);
+  if (st) {
+    if (res) res->log_z = NAN;
+    return st;
+  }
+  const int32_t d = p->d;
+  int32_t nt = cfg->n_threads;
+#ifdef _OPENMP
+  if (nt <= 0) nt = omp_get_max_threads();
+#else
+  nt = 1;
+#endif
+  double *beta = (double *)malloc(sizeof(double) * p->K);
+  st = or_prep(p, beta, NULL);
+  if (st) {
+    free(beta);
+    res->log_z = NAN;
+    return st;
+  }
+  int32_t *rep_of = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+  int32_t *reps = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+  int32_t ncand = 0;
+  for (int32_t s = 0; s < n; ++s) ncand += valid[s] ? 1 : 0;
+  res->n_candidates = ncand;
+  double tau_pre = cfg->dedup_tol_pre > 0 ? cfg->dedup_tol_pre : 0.25;
+  int32_t nr = or_dedup(n, d, X, l, valid, tau_pre, rep_of, reps);
+  res->n_reps_pre = nr;
+  double *Xr = (double *)malloc(sizeof(double) * (size_t)(nr > 0 ? nr : 1) * d);
+  for (int32_t i = 0; i < nr; ++i)
+    memcpy(Xr + (size_t)i * d, X + (size_t)reps[i] * d, sizeof(double) * d);
+  double wmax = 0.0;
+  for (int32_t i = 0; i < d; ++i)
+    if (hi[i] - lo[i] > wmax) wmax = hi[i] - lo[i];
+  double tau = cfg->dedup_tol > 0 ? cfg->dedup_tol : 1e-6 * wmax;
+  st = finish_modes(p, beta, lo, hi, tau, cfg->max_modes, nr, Xr, nt, res);
+  free(Xr);
+  free(rep_of);
+  free(reps);
+  free(beta);
+  return st;
+}
+
 int32_t or_reference_modes(const or_problem *p, const double *lo, const double *hi,
                            double dedup_tol, int32_t max_modes, or_result *res) {
   int32_t st = or_validate_problem(p);

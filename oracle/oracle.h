@@ -149,6 +149,10 @@ double or_mode_log_z(int32_t d, double logl, double log_det_h, double log_volume
 /* ---- the whole path ---- */
 int32_t or_evidence(const or_problem *p, const double *lo, const double *hi, const or_config *cfg,
                     or_result *res);
+/* the tail of or_evidence from given end points: pre-dedup, polish, filters, dedup, combine */
+int32_t or_finish_points(const or_problem *p, const double *lo, const double *hi,
+                         const or_config *cfg, int32_t n, const double *X, const double *l,
+                         const uint8_t *valid, or_result *res);
 /* reference mode set: Newton from each mu_k, then filters and dedup as in or_evidence */
 int32_t or_reference_modes(const or_problem *p, const double *lo, const double *hi,
                            double dedup_tol, int32_t max_modes, or_result *res);

@@ -173,6 +173,24 @@ def gaussian_mixture(rng, d, K, mu_lo, mu_hi, lam_lo, lam_hi, sep, box_half=None
                    lo, hi, np.array(sll), name)
 
 
+def hidden_mode_mixture(d: int, seed: int, offset: float = 5.0, box_half: float = 10.0,
+                        name: str = "hidden") -> Problem:
+    """Two equally weighted Gaussians (density-normalised) in the box +-box_half: a narrow
+    component at the box centre (lambda in [0.2, 0.3]) and a wide one (lambda in [6, 12])
+    whose mean sits at +offset in the first two coordinates.  The narrow component's peak is
+    far higher, so every coarse ray that passes near the centre outranks every point of the
+    wide component's basin; its basin is small, so moving a sample a few units from the
+    centre puts it in the wide component's basin."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    PA, slA = random_precision(rng, d, 0.2, 0.3)
+    PB, slB = random_precision(rng, d, 6.0, 12.0)
+    mu = np.zeros((2, d))
+    mu[1, :min(2, d)] = offset
+    return Problem(FAMILY_GAUSS_MIX, NORM_DENSITY, d, 2, np.log(np.array([0.5, 0.5])), mu,
+                   np.stack([PA, PB]), 0.0, 0.0, np.full(d, -box_half), np.full(d, box_half),
+                   np.array([slA, slB]), name=name)
+
+
 def student_t(rng, d, nu, mu_lo, mu_hi, lam_lo, lam_hi, box_half, name="") -> Problem:
     p, s = random_precision(rng, d, lam_lo, lam_hi)
     mu = rng.uniform(mu_lo, mu_hi, (1, d))

@@ -976,3 +976,148 @@ def test_chisao_orthonormal_properties(oracle_lib):
     G[0, 2] = 2.0 * G[0, 0] - G[0, 1]
     Q = O.chisao_orthonormal(G)
     assert np.all(np.isfinite(Q[0, :2])) and np.all(np.isnan(Q[0, 2:]))
+
+
+# --------------------------------------------------- ChiSao cycle, refinement pass
+
+def test_chisao_normals_are_standard_normal(oracle_lib):
+    """The cycle's draws (Box-Muller on the pinned Philox uniforms) are N(0, 1): mean,
+    variance and a Kolmogorov-Smirnov test on 250000 draws (a sample of 20000 is too small to
+    tell a mild distortion from noise), and draws of two streams are uncorrelated."""
+    O = oracle_lib
+    z = np.array([O.chisao_normal(5, 0, r, O.CHISAO_STREAM0 + 4, i)
+                  for r in range(500) for i in range(500)])
+    assert abs(float(z.mean())) < 4.0 / math.sqrt(z.size)
+    assert abs(float(z.var()) - 1.0) < 0.01
+    assert st.kstest(z, "norm").pvalue > 1e-3
+    w = np.array([O.chisao_normal(5, 0, r, O.CHISAO_STREAM0 + 2, i)
+                  for r in range(100) for i in range(200)])
+    assert abs(float(np.corrcoef(z[:w.size], w)[0, 1])) < 4.0 / math.sqrt(w.size)
+
+
+def _hidden(d=8, seed=11):
+    return synth.hidden_mode_mixture(d, seed)
+
+
+def test_chisao_cycle_finds_what_one_phase_provably_misses(oracle_lib):
+    """A narrow high component at the centre and a wide low one off-centre.  Every start of the
+    coarse pass has l above the wide component's mode value, so a monotone optimiser (Armijo
+    L-BFGS never lowers l) cannot reach that mode from any start: one convergence phase finds
+    only the narrow mode.  The oscillation cycle (reseeding, smoothing, momentum descent) finds
+    both, and its result equals the reference set (Newton from each mean) to 1e-8 / 1e-9."""
+    O = oracle_lib
+    prob = _hidden()
+    cfg = synth.RunConfig(n_rays=256, n_points=32, n_starts=16, seed=77)
+    ref = O.reference_modes(prob)
+    assert ref.status == 0 and ref.n_modes == 2
+    l_wide = float(np.min(ref.mode_logl))
+    disc = O.discover(prob, cfg.n_rays, cfg.n_points, cfg.n_starts, cfg.seed)
+    l0 = O.logl(prob, disc["X0"], grad=False)
+    assert float(np.min(l0)) > l_wide + 1.0
+    one = O.evidence(prob, cfg)
+    assert one.status == 0 and one.n_modes == 1
+    prm = O.ChiSaoParams(n_osc=3, n_anti=10, alpha_anti=0.05)
+    cyc = O.evidence_chisao(prob, cfg, prm)
+    assert cyc.status == 0 and cyc.n_modes == 2, cyc.cycle
+    assert float(np.max(np.abs(cyc.modes - ref.modes))) <= 1e-8
+    assert abs(cyc.log_z - ref.log_z) <= 1e-9
+    assert float(np.max(np.abs(cyc.mode_log_z - ref.mode_log_z))) <= 1e-9
+    assert cyc.cycle[0]["reseed"] == 2  # every start converged to one peak: Golden Rooster
+
+
+def test_chisao_cycle_single_oscillation_is_the_single_phase(oracle_lib):
+    """n_osc = 1 without refinement: the coarse pass, one convergence phase and the same tail,
+    so the mode set and log Z equal the single-phase path's (starts agree to rounding of the
+    ray points)."""
+    O = oracle_lib
+    for name, ns in (("c0", None), ("c1", 128)):
+        prob, cfg = synth.make_workload(name, n_starts=ns)
+        a = O.evidence(prob, cfg)
+        b = O.evidence_chisao(prob, cfg, O.ChiSaoParams(n_osc=1))
+        assert a.status == b.status == 0 and a.n_modes == b.n_modes
+        assert abs(a.log_z - b.log_z) <= 1e-12
+        assert float(np.max(np.abs(a.modes - b.modes))) <= 1e-10
+        assert b.cycle[0]["reseed"] == 0
+
+
+def test_chisao_cycle_golden_rooster_disables_itself(oracle_lib):
+    """One Gaussian: every sample converges to its mode, the duplicates are lost and Golden
+    Rooster refills them; the next oscillation finds no new peak, so Golden Rooster is off
+    and the lost slots stay empty; the result is the closed form."""
+    O = oracle_lib
+    prob, cfg = synth.make_workload("c0")
+    cfg.n_starts = 16
+    cyc = O.evidence_chisao(prob, cfg, O.ChiSaoParams(n_osc=3, n_anti=6, alpha_anti=0.05))
+    kinds = [c["reseed"] for c in cyc.cycle]
+    assert kinds == [2, 0, 0], cyc.cycle
+    assert [c["golden_rooster"] for c in cyc.cycle] == [True, False, False]
+    assert cyc.cycle[1]["found"] == 1 and cyc.cycle[2]["lost"] == 0
+    ref = O.reference_modes(prob)
+    assert cyc.n_modes == 1 and abs(cyc.log_z - ref.log_z) <= 1e-10
+
+
+@pytest.mark.parametrize("n_far,kind", [(6, 1), (5, 1), (4, 2)])
+def test_chisao_cycle_reseed_rule_boundary(oracle_lib, n_far, kind):
+    """Ten samples start at the mode (they converge at once, stick, and nine are lost) and
+    n_far start far away (one L-BFGS step leaves them unconverged): with at least five
+    unconverged samples Repulse Monkey reseeds, with fewer Golden Rooster."""
+    O = oracle_lib
+    prob, _ = synth.make_workload("c0")
+    mode = O.reference_modes(prob).modes[0]
+    far = mode + np.array([6.0, -5.0, 4.0, -3.0])
+    X0 = np.array([mode] * 10 + [far * (1.0 - 0.05 * j) for j in range(n_far)])
+    prm = O.ChiSaoParams(n_osc=2, n_conv=1, n_anti=2, alpha_anti=0.01)
+    cyc = O.chisao_cycle(prob, X0, prm, grad_tol=1e-10, dedup_tol=0.25, seed=3)
+    c0 = cyc["log"][0]
+    assert c0["lost"] == 9 and c0["peaks"] == 1 and c0["reseed"] == kind, c0
+    assert c0["converged"] == 10
+
+
+def test_refine_rays_closed_forms(oracle_lib):
+    """Refinement pass: on a flat likelihood the refined points are the uniform quantiles
+    (i + 1/2)/n_ref of the whole ray; on a Gaussian the ray's l is a parabola in t and the best
+    refined point lies closer to its maximiser than half a coarse spacing, shrinking as n_ref
+    grows; with n_ref = 0 the best point is the coarse argmax of the discovery pass."""
+    O = oracle_lib
+    prob, cfg = synth.make_workload("c0")
+    R = 16
+    P0, P1 = O.rays(prob.d, prob.lo, prob.hi, R, 9)
+    flat = prob.copy()
+    flat.prec = flat.prec * 0.0 + np.eye(prob.d)[None] * 1e-300
+    rf = O.refine_rays(flat, P0, P1, 8, 10, 10.0)
+    assert np.allclose(rf["t_refined"], ((np.arange(10) + 0.5) / 10)[None], atol=1e-15)
+    n_pts = 8
+    errs = []
+    for n_ref in (0, 8, 64):
+        rf = O.refine_rays(prob, P0, P1, n_pts, n_ref, 10.0)
+        e = 0.0
+        for r in range(R):
+            D = P1[r] - P0[r]
+            a = O.logl(prob, P0[r][None], grad=False)[0]
+            # t* maximises the parabola l(P0 + t D): from the gradient at P0 and the curvature
+            _, g = O.logl(prob, P0[r][None])
+            curv = -float(D @ prob.prec[0] @ D)
+            tstar = min(1.0, max(0.0, -float(g[0] @ D) / curv))
+            e = max(e, abs(rf["best_t"][r] - tstar))
+        errs.append(e)
+    assert errs[0] <= 0.5 / n_pts + 1e-12
+    assert errs[1] < errs[0] and errs[2] < errs[1]
+    d0 = O.discover(prob, R, n_pts, R, 9)
+    rf0 = O.refine_rays(prob, P0, P1, n_pts, 0, 10.0)
+    assert np.allclose(rf0["best_l"], d0["ray_best_l"], rtol=1e-13, atol=1e-12)
+    assert np.allclose(rf0["best_t"], (d0["ray_best_j"] + 0.5) / n_pts, atol=0)
+
+
+def test_chisao_whole_path_with_refinement_equals_reference(oracle_lib):
+    """The coarse and refinement passes feeding the cycle on c1's mixture (fewer starts):
+    the mode set and log Z equal the reference set's (the refinement changes only where the
+    starts sit)."""
+    O = oracle_lib
+    prob, cfg = synth.make_workload("c1", n_starts=64)
+    ref = O.reference_modes(prob)
+    for n_osc in (1, 2):
+        r = O.evidence_chisao(prob, cfg, O.ChiSaoParams(n_osc=n_osc, n_anti=4, alpha_anti=0.01),
+                              n_ref=8)
+        assert r.status == 0 and r.n_modes == ref.n_modes == prob.K
+        assert float(np.max(np.abs(r.modes - ref.modes))) <= 1e-8
+        assert abs(r.log_z - ref.log_z) <= 1e-9
