@@ -405,17 +405,21 @@ def chisao_orthonormal(G):
     near-exhaustion refill shoots rays in orthonormal directions obtained by QR): for each
     peak c, the n <= d rows of G [C][n][d] (Gaussian draws) are replaced by the rows of Q from
     G_c^T = Q R with R's diagonal positive, which makes Q unique.  Reading: a row whose
-    |R_kk| (its norm after removing the earlier directions) is at most 1e-12 of its own norm
-    depends on the earlier rows; it and every later row become NaN, since the rows after it
-    have no well-defined orthonormal completion from these draws."""
+    |R_kk| (its norm after removing the earlier directions) is at most 8 n eps of its own norm
+    (eps = 2^-52) depends on the earlier rows: removing n projections leaves a rounding residue
+    of order n eps |g_k| even from an exactly dependent row, so a residual at that level carries
+    no direction of its own.  It and every later row become NaN, since the rows after it have no
+    well-defined orthonormal completion from these draws."""
     G = _f64(G)
     out = np.empty_like(G)
+    n = G.shape[1]
+    thr = 8.0 * n * np.finfo(np.float64).eps
     for c in range(G.shape[0]):
         Q, R = np.linalg.qr(G[c].T)
         r = np.diag(R)
         sgn = np.where(r < 0, -1.0, 1.0)
         out[c] = (Q * sgn).T
-        bad = np.abs(r) <= 1e-12 * np.linalg.norm(G[c], axis=1)
+        bad = np.abs(r) <= thr * np.linalg.norm(G[c], axis=1)
         if bad.any():
             out[c, int(np.argmax(bad)):] = np.nan
     return out

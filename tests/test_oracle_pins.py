@@ -1121,3 +1121,32 @@ def test_chisao_whole_path_with_refinement_equals_reference(oracle_lib):
         assert r.status == 0 and r.n_modes == ref.n_modes == prob.K
         assert float(np.max(np.abs(r.modes - ref.modes))) <= 1e-8
         assert abs(r.log_z - ref.log_z) <= 1e-9
+
+
+@pytest.mark.parametrize("n,d", [(4, 6), (16, 16), (24, 64)])
+def test_chisao_orthonormal_dependence_threshold(oracle_lib, n, d):
+    """A draw whose component outside the earlier rows' span has relative size delta is
+    dependent (it and the later rows NaN) when delta <= 8 n eps, independent above: exact
+    combinations and delta = 0.5 x threshold give NaN, delta = 2 x threshold and 1e3 x give
+    finite orthonormal rows (rounding of the projections, ~n eps, is far from either side)."""
+    O = oracle_lib
+    thr = 8.0 * n * np.finfo(np.float64).eps
+    rng = np.random.Generator(np.random.PCG64(100 + n))
+    k = n // 2
+    base = rng.normal(size=(n, d))
+    Qs, _ = np.linalg.qr(base[:k].T, mode="complete")
+    v = Qs[:, k]  # unit vector orthogonal to the first k rows
+    comb = rng.normal(size=k) @ base[:k]
+    for delta, dependent in ((0.0, True), (0.5 * thr, True), (2.0 * thr, False),
+                             (1e3 * thr, False)):
+        G = base.copy()
+        # |comb + t v| = |g|, t = delta |g|:  t^2 (1 - delta^2) = delta^2 |comb|^2
+        t = delta * np.linalg.norm(comb) / math.sqrt(1.0 - delta * delta)
+        G[k] = comb + t * v
+        Q = O.chisao_orthonormal(G[None])[0]
+        assert np.all(np.isfinite(Q[:k]))
+        if dependent:
+            assert np.all(np.isnan(Q[k:])), delta
+        else:
+            assert np.all(np.isfinite(Q[k:])), delta
+            assert np.allclose(Q @ Q.T, np.eye(n), atol=1e-10)
