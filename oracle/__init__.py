@@ -814,7 +814,7 @@ def refine_rays(prob, P0, P1, n_pts, n_ref, delta, op: Optional[OracleProblem] =
     best_l = np.full(R, -np.inf)
     T = np.zeros((R, n_ref))
     for r in range(R):
-        tc = (np.arange(n_pts) + 0.5) * h
+        tc = (np.arange(n_pts) + 0.5) / n_pts
         lc = logl(prob, P0[r] + tc[:, None] * (P1[r] - P0[r]), grad=False, op=op)
         fin = np.isfinite(lc)
         if not fin.any():
