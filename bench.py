@@ -578,14 +578,17 @@ def main() -> int:
                               copy_calibration_bytes=calibration_copy())), flush=True)
         return 0
 
-    # ---- whole path, inputs resident in HBM
-    runners = {n: L.EvidenceRunner(p, c) for n, (p, c) in wl.items()}
+    # ---- whole path, inputs resident in HBM, on one stream; the iteration blocks replay
+    # the execution context's HIP graphs (captured in the first warm-up call)
+    stream = torch.cuda.Stream()
+    ex = L.ExecContext()
+    runners = {n: L.EvidenceRunner(p, c, exec=ex) for n, (p, c) in wl.items()}
     ref = {n: closed_form_logz(p) for n, (p, _) in wl.items()}
     cold = {}
     for w in range(args.warmup):
         for n, r in runners.items():
             tc = time.perf_counter()
-            res = r.run()
+            res = r.run(stream)
             if w == 0:
                 cold[n] = time.perf_counter() - tc
             log(f"warmup {w} {n}: status {res.status} log Z {res.log_z:.9f} "
@@ -593,6 +596,7 @@ def main() -> int:
                 f"evals {res.n_grad_evals} t {res.seconds[7]*1e3:.1f} ms "
                 f"phases {[round(s*1e3, 2) for s in res.seconds[:7]]}")
     torch.cuda.synchronize()
+    exec_before = ex.stats()
     per = {n: [] for n in names}
     last = {}
     evals = 0
@@ -600,7 +604,7 @@ def main() -> int:
     for k in range(args.steps):
         for n, r in runners.items():
             ts = time.perf_counter()
-            res = r.run()
+            res = r.run(stream)
             per[n].append(time.perf_counter() - ts)
             evals += res.n_grad_evals
             last[n] = res
@@ -609,6 +613,27 @@ def main() -> int:
         log(f"step {k} done")
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
+    exec_after = ex.stats()
+    exec_stats = {"timed_region": {k: exec_after[k] - exec_before[k] for k in exec_after},
+                  "total": exec_after}
+    log(f"execution context: {exec_stats}")
+
+    # ---- the same calls through sb_evidence_dev: no context, nothing allocated, the blocks
+    # launched directly
+    direct = {}
+    for n, (p, c) in wl.items():
+        rd = L.EvidenceRunner(p, c)
+        rd.run(stream)
+        ts = []
+        for _ in range(3):
+            t1 = time.perf_counter()
+            resd = rd.run(stream)
+            ts.append(time.perf_counter() - t1)
+        direct[n] = float(np.median(ts)) * 1e3
+        same = resd.log_z == last[n].log_z and np.array_equal(resd.modes, last[n].modes)
+        log(f"direct launches {n}: {direct[n]:.1f} ms, same result as the graph path: {same}")
+        del rd
+        torch.cuda.empty_cache()
 
     # ---- plain FP64 path, same pipeline and starts
     t64 = {}
@@ -618,12 +643,12 @@ def main() -> int:
 
         for n, (p, c) in wl.items():
             c64 = synth.RunConfig(**{**vars(c), "precision": synth.PREC_FP64})
-            r64 = L.EvidenceRunner(p, c64)
-            r64.run()  # warm (code objects, tile cache)
+            r64 = L.EvidenceRunner(p, c64, exec=ex)
+            r64.run(stream)  # warm (code objects, tile cache, block graph)
             ts = []
             for _ in range(args.fp64_steps):
                 t1 = time.perf_counter()
-                res64[n] = r64.run()
+                res64[n] = r64.run(stream)
                 ts.append(time.perf_counter() - t1)
             t64[n] = float(np.median(ts))
             log(f"fp64 {n}: {t64[n]*1e3:.1f} ms log Z {res64[n].log_z:.9f} "
@@ -717,6 +742,8 @@ def main() -> int:
         "time_to_logz_range_ms": {n: [min(per[n]) * 1e3, max(per[n]) * 1e3] for n in names},
         "time_to_logz_cold_ms": {n: cold[n] * 1e3 for n in cold},
         "time_to_logz_host_entry_ms": host or None,
+        "time_to_logz_direct_ms": direct,
+        "exec_context": exec_stats,
         "phases_ms": {n: dict(zip(("prep", "discovery", "bulk", "dedup_pre",
                                    "polish_hessian_chol", "dedup_combine"),
                                   [round(last[n].seconds[i] * 1e3, 2) for i in (0, 1, 2, 3, 4, 6)]))

@@ -107,8 +107,10 @@ typedef struct {
 /* Run parameters.  Non-positive tolerances and max_iter select defaults:
  * grad_tol 1e-10 (FP64 bulk; the FP32 bulk of SB_PREC_MIXED stops at its
  * rounding floor), dedup_tol 1e-6 * max_i(hi_i - lo_i), dedup_tol_pre 0.25,
- * max_iter 10 d + 200.  Requires 1 <= m <= 8, 1 <= n_starts <= n_rays,
- * n_points >= 1, max_modes >= 1. */
+ * max_iter 10 d + 200.  Requires 1 <= m <= 32, 1 <= n_starts <= n_rays,
+ * n_points >= 1, max_modes >= 1.  Memories up to 8 pairs are held in
+ * registers during a step; larger ones are read from the history ring in
+ * each loop of the two-loop recursion (same arithmetic, more traffic). */
 typedef struct {
   int32_t n_rays, n_points, n_starts, m, max_iter, max_modes, precision;
   double grad_tol, dedup_tol, dedup_tol_pre;
@@ -147,10 +149,43 @@ int32_t sb_evidence_batch(int32_t n, const sb_loglik *ll, const sb_box *box,
 
 /* Device-resident variant of sb_evidence: ll and box hold device pointers,
  * the workspace (>= sb_evidence_workspace_bytes) is caller-owned device
- * memory; results are written to host memory in res.  Synchronises stream. */
+ * memory; results are written to host memory in res.  The call allocates
+ * nothing, on the device or the host: it launches each L-BFGS iteration
+ * block directly and reads its 4-byte active count into a host stack word;
+ * res->seconds holds only the total (seconds[7]).  The box is checked on the
+ * device (SB_E_INVAL if some lo_i >= hi_i or a bound is not finite).  The
+ * first call for a new shape runs the tile autotuner, which times its
+ * candidates on this call's own workspace and keeps the choice in the
+ * process-wide tile cache.  stream may be NULL (the null stream).
+ * Synchronises stream. */
 size_t sb_evidence_workspace_bytes(const sb_loglik *ll, const sb_config *cfg);
 int32_t sb_evidence_dev(const sb_loglik *ll_dev, const sb_box *box_dev, const sb_config *cfg,
                         sb_result *res, void *workspace, size_t ws_bytes, void *stream);
+
+/* Execution context for repeated whole-path calls on one device (the
+ * batching form: an iteration block of the L-BFGS bulk, 8 steps of step,
+ * compaction, contraction and epilogue launches, replayed as one HIP graph).
+ * sb_exec_create allocates, on the current device, a pinned host word for
+ * the per-block count readback, ten timing events and room for four
+ * instantiated block graphs; sb_exec_destroy frees them.
+ * sb_evidence_exec_dev is sb_evidence_dev with that state: the block graph
+ * for this call's buffers, model and box pointers, configuration, stream
+ * and tiles is looked up in the context; a call that finds it captures and
+ * instantiates nothing, a new combination captures the block once and
+ * updates the least recently used executable in place (or instantiates one
+ * when the update is refused).  res->seconds gets the phase times.  A NULL
+ * stream cannot be captured: the blocks are then launched directly.  A
+ * context is used by one call at a time (calls that share one race) and on
+ * the device it was created on (else SB_E_INVAL).  sb_exec_stats writes
+ * counts [4]: graphs captured, instantiated, updated in place, and block
+ * graph launches, since creation. */
+typedef struct sb_exec sb_exec;
+int32_t sb_exec_create(sb_exec **out);
+void sb_exec_destroy(sb_exec *ex);
+int32_t sb_exec_stats(const sb_exec *ex, int32_t *counts);
+int32_t sb_evidence_exec_dev(sb_exec *ex, const sb_loglik *ll_dev, const sb_box *box_dev,
+                             const sb_config *cfg, sb_result *res, void *workspace,
+                             size_t ws_bytes, void *stream);
 
 /* --------------------------------------------------------------- single steps
  * Device pointers throughout; nothing allocates.  "model" arrays:
@@ -405,8 +440,9 @@ int32_t sb_user_mode_evidence_dev(const sb_user_fn *fn, int32_t n, int32_t d,
 
 /* L-BFGS two-loop direction (appendix "L-BFGS Optimization") for B
  * independent histories: S, Y [B][m][d] in logical order (oldest first),
- * cnt [B] pairs used (0 <= cnt <= m), G [B][d] gradient of f.  Writes the
- * direction P [B][d] = -H_k G.  FP64 (dtype F64) or FP32 (dtype F32). */
+ * cnt [B] pairs used (0 <= cnt <= m, clamped), G [B][d] gradient of f.
+ * Writes the direction P [B][d] = -H_k G.  FP64 (dtype F64) or FP32 (dtype
+ * F32); 1 <= m <= 32, 1 <= d <= 4096 (SB_E_INVAL / SB_E_UNSUPPORTED). */
 int32_t sb_lbfgs_direction_dev(int64_t B, int32_t d, int32_t m, const int32_t *cnt,
                                const void *S, const void *Y, const void *G, void *P,
                                int32_t dtype, void *stream);

@@ -29,6 +29,7 @@ ST_CONVERGED, ST_STALLED, ST_MAXITER, ST_DEAD = 1, 2, 3, 4
 # every extern "C" symbol declared in include/sb.h
 EXPORTS = [
     "sb_evidence", "sb_evidence_batch", "sb_evidence_workspace_bytes", "sb_evidence_dev",
+    "sb_exec_create", "sb_exec_destroy", "sb_exec_stats", "sb_evidence_exec_dev",
     "sb_prep_workspace_bytes", "sb_prep_dev", "sb_logl_grad_workspace_bytes", "sb_logl_grad_dev",
     "sb_quadform_dev", "sb_split_bf16_dev", "sb_hvp_workspace_bytes", "sb_hvp_dev", "sb_discover_workspace_bytes", "sb_discover_dev",
     "sb_lbfgs_direction_dev", "sb_lbfgs_workspace_bytes", "sb_lbfgs_dev",
@@ -108,6 +109,10 @@ def lib():
             "sb_evidence_batch": (i32, [i32, vp, vp, vp, vp]),
             "sb_evidence_workspace_bytes": (sz, [vp, vp]),
             "sb_evidence_dev": (i32, [vp, vp, vp, vp, vp, sz, vp]),
+            "sb_exec_create": (i32, [vp]),
+            "sb_exec_destroy": (None, [vp]),
+            "sb_exec_stats": (i32, [vp, vp]),
+            "sb_evidence_exec_dev": (i32, [vp, vp, vp, vp, vp, vp, sz, vp]),
             "sb_prep_workspace_bytes": (sz, [i32, i32]),
             "sb_prep_dev": (i32, [vp, vp, vp, vp, vp, vp, vp, sz, vp]),
             "sb_logl_grad_workspace_bytes": (sz, [i32, i32, i64, i32]),
@@ -787,14 +792,47 @@ def sb_combine_dev(lo, hi, logl, logdet, modes):
     return order, mlz, lz
 
 
-class EvidenceRunner:
-    """Device-resident evidence: inputs in HBM, workspace allocated once (sb_evidence_dev)."""
+class ExecContext:
+    """sb_exec: pinned readback word, timing events and instantiated block graphs kept
+    across whole-path calls on one device (created on the current device)."""
 
-    def __init__(self, prob, cfg, device="cuda"):
+    def __init__(self):
+        h = C.c_void_p()
+        _check(lib().sb_exec_create(C.byref(h)), "sb_exec_create")
+        self.handle = h
+
+    def stats(self) -> dict:
+        c = (C.c_int32 * 4)()
+        _check(lib().sb_exec_stats(self.handle, c), "sb_exec_stats")
+        return {"captured": c[0], "instantiated": c[1], "updated": c[2], "launched": c[3]}
+
+    def close(self):
+        if self.handle:
+            lib().sb_exec_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class EvidenceRunner:
+    """Device-resident evidence: inputs in HBM, workspace allocated once.  Without an
+    execution context run() calls sb_evidence_dev (allocation-free, blocks launched
+    directly); with one (exec=True: a context of its own, or an ExecContext) it calls
+    sb_evidence_exec_dev (iteration blocks as the context's HIP graphs)."""
+
+    def __init__(self, prob, cfg, device="cuda", exec=None):
         import torch
 
         self.prob, self.cfg = prob, cfg
         dev = torch.device(device)
+        if exec is True:
+            with torch.cuda.device(dev):
+                exec = ExecContext()
+        self.exec = exec or None
         self.log_w = torch.as_tensor(_f64(prob.log_w), device=dev)
         self.mu = torch.as_tensor(_f64(prob.mu), device=dev)
         self.prec = torch.as_tensor(_f64(prob.prec), device=dev)
@@ -812,7 +850,13 @@ class EvidenceRunner:
 
     def run(self, stream=None) -> EvidenceResult:
         r, arrs = _new_result(self.cfg.max_modes, self.prob.d)
-        st = lib().sb_evidence_dev(C.byref(self.ll), C.byref(self.box), C.byref(self.c),
-                                   C.byref(r), self.ws.data_ptr(), self.ws.numel(),
-                                   _stream(stream))
+        if self.exec is not None:
+            st = lib().sb_evidence_exec_dev(self.exec.handle, C.byref(self.ll),
+                                            C.byref(self.box), C.byref(self.c), C.byref(r),
+                                            self.ws.data_ptr(), self.ws.numel(),
+                                            _stream(stream))
+        else:
+            st = lib().sb_evidence_dev(C.byref(self.ll), C.byref(self.box), C.byref(self.c),
+                                       C.byref(r), self.ws.data_ptr(), self.ws.numel(),
+                                       _stream(stream))
         return _to_result(st, r, self.cfg.max_modes, arrs)

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "internal.h"
@@ -73,10 +74,8 @@ int validate_shape(const sb_loglik *ll) {
 
 int validate_cfg(const sb_loglik *ll, const sb_config *c) {
   if (!c) return fail(SB_E_INVAL, "config is NULL");
-  if (c->m < 1 || c->m > 32) return fail(SB_E_INVAL, "m must be in [1, 32] (got %d)", c->m);
-  if (c->m > kMaxHist)
-    return fail(SB_E_UNSUPPORTED, "m = %d: the register-resident history holds at most %d pairs",
-                c->m, kMaxHist);
+  if (c->m < 1 || c->m > kMaxMem)
+    return fail(SB_E_INVAL, "m must be in [1, %d] (got %d)", kMaxMem, c->m);
   if (c->n_rays < 1 || c->n_points < 1) return fail(SB_E_INVAL, "n_rays, n_points must be >= 1");
   if (c->n_starts < 1 || c->n_starts > c->n_rays)
     return fail(SB_E_INVAL, "need 1 <= n_starts <= n_rays");
@@ -205,8 +204,12 @@ size_t sb_evidence_workspace_bytes(const sb_loglik *ll, const sb_config *cfg) {
   return evidence_ws_bytes(ll, cfg);
 }
 
-int32_t sb_evidence_dev(const sb_loglik *ll, const sb_box *box, const sb_config *cfg,
-                        sb_result *res, void *workspace, size_t ws_bytes, void *stream) {
+// Shared by sb_evidence_dev and sb_evidence_exec_dev: argument checks that
+// need no array contents (the box is checked on the device in prep), then
+// the path on the caller's stream.
+static int32_t evidence_dev(const sb_loglik *ll, const sb_box *box, const sb_config *cfg,
+                            sb_result *res, void *workspace, size_t ws_bytes, void *stream,
+                            ExecCtx *ex) {
   int st = validate_shape(ll);
   if (!st) st = validate_cfg(ll, cfg);
   if (!st && (!box || !box->lo || !box->hi)) st = fail(SB_E_INVAL, "box is NULL");
@@ -219,26 +222,14 @@ int32_t sb_evidence_dev(const sb_loglik *ll, const sb_box *box, const sb_config 
     res->log_z = NAN;
     return st;
   }
-  hipStream_t s = (hipStream_t)stream;
-  // box contents are validated on the host (2d values)
-  {
-    std::vector<double> lo(ll->d), hi(ll->d);
-    if (hipMemcpy(lo.data(), box->lo, sizeof(double) * ll->d, hipMemcpyDeviceToHost) ||
-        hipMemcpy(hi.data(), box->hi, sizeof(double) * ll->d, hipMemcpyDeviceToHost)) {
+  if (ex) {
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != ex->device) {
       res->log_z = NAN;
-      return fail(SB_E_DEVICE, "reading the box failed");
+      return fail(SB_E_INVAL, "execution context of device %d used on device %d", ex->device,
+                  dev);
     }
-    if ((st = validate_box_host(ll->d, lo.data(), hi.data()))) {
-      res->log_z = NAN;
-      return st;
-    }
-  }
-  hipStream_t own = nullptr;
-  if (s == nullptr) {
-    if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess)
-      return fail(SB_E_DEVICE, "stream creation failed");
-    (void)hipDeviceSynchronize();
-    s = own;
   }
   DevProblem P;
   P.family = ll->family;
@@ -252,13 +243,73 @@ int32_t sb_evidence_dev(const sb_loglik *ll, const sb_box *box, const sb_config 
   P.hi = box->hi;
   P.nu = ll->nu;
   P.c = ll->logl_offset;
-  st = run_evidence(P, cfg, res, workspace, ws_bytes, s);
-  if (own) {
-    (void)hipStreamSynchronize(own);
-    (void)hipStreamDestroy(own);
-  }
+  st = run_evidence(P, cfg, res, workspace, ws_bytes, (hipStream_t)stream, ex);
   if (st && st != SB_E_NOMODE && st != SB_E_CAPACITY) res->log_z = NAN;
   return st;
+}
+
+int32_t sb_evidence_dev(const sb_loglik *ll, const sb_box *box, const sb_config *cfg,
+                        sb_result *res, void *workspace, size_t ws_bytes, void *stream) {
+  return evidence_dev(ll, box, cfg, res, workspace, ws_bytes, stream, nullptr);
+}
+
+int32_t sb_exec_create(sb_exec **out) {
+  if (!out) return fail(SB_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int st = device_status();
+  if (st) return st;
+  ExecCtx *ex = new (std::nothrow) ExecCtx();
+  if (!ex) return fail(SB_E_NOMEM, "out of host memory");
+  (void)hipGetDevice(&ex->device);
+  if (hipHostMalloc((void **)&ex->pinned, sizeof(int32_t) * 16, hipHostMallocDefault) !=
+      hipSuccess) {
+    delete ex;
+    return fail(SB_E_NOMEM, "pinned host allocation failed");
+  }
+  ex->ev_ok = true;
+  int made = 0;
+  for (; made < 10; ++made)
+    if (hipEventCreate(&ex->ev[made]) != hipSuccess) break;
+  if (made < 10) {
+    for (int i = 0; i < made; ++i) (void)hipEventDestroy(ex->ev[i]);
+    (void)hipHostFree(ex->pinned);
+    delete ex;
+    return fail(SB_E_DEVICE, "event creation failed");
+  }
+  *out = reinterpret_cast<sb_exec *>(ex);
+  return SB_OK;
+}
+
+void sb_exec_destroy(sb_exec *h) {
+  ExecCtx *ex = reinterpret_cast<ExecCtx *>(h);
+  if (!ex) return;
+  for (int i = 0; i < ExecCtx::kSlots; ++i)
+    if (ex->slot[i].exec) (void)hipGraphExecDestroy(ex->slot[i].exec);
+  if (ex->ev_ok)
+    for (int i = 0; i < 10; ++i) (void)hipEventDestroy(ex->ev[i]);
+  if (ex->pinned) (void)hipHostFree(ex->pinned);
+  delete ex;
+}
+
+int32_t sb_exec_stats(const sb_exec *h, int32_t *counts) {
+  const ExecCtx *ex = reinterpret_cast<const ExecCtx *>(h);
+  if (!ex || !counts) return fail(SB_E_INVAL, "bad arguments");
+  counts[0] = ex->n_capture;
+  counts[1] = ex->n_instantiate;
+  counts[2] = ex->n_update;
+  counts[3] = ex->n_launch;
+  return SB_OK;
+}
+
+int32_t sb_evidence_exec_dev(sb_exec *h, const sb_loglik *ll, const sb_box *box,
+                             const sb_config *cfg, sb_result *res, void *workspace,
+                             size_t ws_bytes, void *stream) {
+  if (!h) {
+    if (res) res->log_z = NAN;
+    return fail(SB_E_INVAL, "execution context is NULL");
+  }
+  return evidence_dev(ll, box, cfg, res, workspace, ws_bytes, stream,
+                      reinterpret_cast<ExecCtx *>(h));
 }
 
 int32_t sb_evidence(const sb_loglik *ll, const sb_box *box, const sb_config *cfg,
@@ -325,8 +376,17 @@ int32_t sb_evidence(const sb_loglik *ll, const sb_box *box, const sb_config *cfg
   P.hi = hi;
   P.nu = ll->nu;
   P.c = ll->logl_offset;
-  st = run_evidence(P, cfg, res, p, ws, s);
+  // a host entry point may allocate: a context of its own for the graphs,
+  // the pinned readback word and the phase timing
+  sb_exec *ex = nullptr;
+  if ((st = sb_exec_create(&ex))) {
+    (void)hipStreamDestroy(s);
+    res->log_z = NAN;
+    return st;
+  }
+  st = run_evidence(P, cfg, res, p, ws, s, reinterpret_cast<ExecCtx *>(ex));
   (void)hipStreamSynchronize(s);
+  sb_exec_destroy(ex);
   (void)hipStreamDestroy(s);
   if (st && st != SB_E_NOMODE && st != SB_E_CAPACITY) res->log_z = NAN;
   return st;
@@ -681,7 +741,7 @@ int32_t sb_lbfgs_direction_dev(int64_t B, int32_t d, int32_t m, const int32_t *c
     return fail(SB_E_INVAL, "bad two-loop arguments");
   if (dtype != SB_DTYPE_F64 && dtype != SB_DTYPE_F32)
     return fail(SB_E_INVAL, "dtype must be F64 or F32");
-  if (m > kMaxHist) return fail(SB_E_UNSUPPORTED, "m > %d", kMaxHist);
+  if (m > kMaxMem) return fail(SB_E_INVAL, "m must be in [1, %d]", kMaxMem);
   if (B == 0) return SB_OK;
   int st = device_status();
   if (st) return st;
@@ -705,7 +765,7 @@ static int32_t lbfgs_run(const sb_model_dev *mdl, int64_t B, void *X, int32_t m,
   int st = validate_model(mdl);
   if (st) return st;
   if (B < 1 || !X) return fail(SB_E_INVAL, "bad B / X");
-  if (m < 1 || m > kMaxHist) return fail(SB_E_UNSUPPORTED, "m must be in [1, %d]", kMaxHist);
+  if (m < 1 || m > kMaxMem) return fail(SB_E_INVAL, "m must be in [1, %d]", kMaxMem);
   if (dtype != SB_DTYPE_F64 && dtype != SB_DTYPE_F32)
     return fail(SB_E_INVAL, "dtype must be F64 or F32");
   if (dtype == SB_DTYPE_F32 && (!mdl->prec_lp || !mdl->mu_lp))

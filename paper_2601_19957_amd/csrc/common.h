@@ -11,7 +11,10 @@ namespace sb {
 
 constexpr double kLog2Pi = 1.8378770664093454835606594728112;
 constexpr int kWave = 64;
-constexpr int kMaxHist = 8;  // largest L-BFGS memory held in registers
+constexpr int kMaxHist = 8;   // largest L-BFGS memory held in registers
+constexpr int kMaxComp = 16;  // largest mixture (responsibilities held per row in registers)
+constexpr int kMaxMem = 32;   // largest L-BFGS memory (beyond kMaxHist the history is
+                              // streamed from memory in each loop of the recursion)
 
 typedef uint16_t bf16_t;  // raw bit pattern; converted with round-to-nearest-even
 

@@ -397,8 +397,45 @@ struct DevProblem {
   const double *log_w, *mu, *prec, *lo, *hi;
   double nu, c;
 };
+// Identity of a captured L-BFGS iteration block: every value the block's
+// launches take as an argument or that selects a kernel.  Zero-filled before
+// the fields are set, so equal blocks compare equal bytewise.
+struct BlockKey {
+  void *stream, *ws;
+  size_t ws_bytes;
+  DevProblem P;
+  sb_config cfg;
+  double tol;
+  int32_t max_iter, blk, dtype, gemm_dtype, two_stage, screen, grad_direct, pad;
+  TileCfg tile, tile1, tile2;
+};
+
+// Execution state a caller keeps across whole-path calls (sb_exec): a pinned
+// host word for the per-block active-count readback, phase-timing events,
+// and instantiated graphs of the L-BFGS iteration block, looked up by
+// BlockKey (a miss captures the block and updates the least recently used
+// executable in place, or instantiates one).  Used by one call at a time.
+struct ExecCtx {
+  int device = -1;
+  int32_t *pinned = nullptr;  // [16], hipHostMalloc
+  hipEvent_t ev[10];
+  bool ev_ok = false;
+  static constexpr int kSlots = 4;
+  struct Slot {
+    bool used = false;
+    BlockKey key;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last = 0;
+  } slot[kSlots];
+  uint64_t tick = 0;
+  int32_t n_capture = 0, n_instantiate = 0, n_update = 0, n_launch = 0;
+};
+
+// ex == nullptr: no graph, no events and no pinned memory (readbacks into
+// host stack words); the phase times in res->seconds are then 0 and only the
+// total is measured.
 int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void *ws,
-                 size_t ws_bytes, hipStream_t s);
+                 size_t ws_bytes, hipStream_t s, ExecCtx *ex);
 size_t evidence_ws_bytes(const sb_loglik *ll, const sb_config *cfg);
 
 // Autotuner: tile choice for the quadratic-form GEMM (cached per shape class).

@@ -128,7 +128,7 @@ struct BlockRed {
   T *buf;  // LDS, 2 * NMAX * NW elements
   int slot;
   template <int N, bool MAX>
-  __device__ void reduce(T (&v)[N]) {
+  __device__ __forceinline__ void reduce(T (&v)[N]) {
     static_assert(N <= NMAX, "values per reduction");
 #pragma unroll
     for (int j = 0; j < N; ++j) v[j] = MAX ? wave_max(v[j]) : wave_sum(v[j]);
@@ -149,7 +149,7 @@ struct BlockRed {
       }
     }
   }
-  __device__ T sum(T x) {
+  __device__ __forceinline__ T sum(T x) {
     T v[1] = {x};
     reduce<1, false>(v);
     return v[0];
@@ -198,8 +198,105 @@ __device__ inline void two_loop(const T (&Sr)[kMaxHist][EPT], const T (&Yr)[kMax
   for (int e = 0; e < EPT; ++e) p[e] = -q[e];
 }
 
-// One step of start s (the whole workgroup; every branch is uniform in s).
+// The same recursion with the history left in memory, for memories beyond
+// what registers hold (m up to kMaxMem).  Pair j (logical order, oldest
+// first) sits at Sb + slot(j) * d and Yb + slot(j) * d with its rho at
+// rho[slot(j)], slot(j) = (head - cnt + j) mod m.  The backward loop reads
+// the pairs newest first, the forward loop oldest first, so each pair is
+// read twice; the oldest pairs are the last read by the first loop and the
+// first by the second, and the second read of a pair is its last use
+// (non-temporal).  The next pair's chunks are loaded before the current
+// pair's reduction so that the load latency overlaps it.  When `reg_new`,
+// the newest pair (logical cnt - 1) is taken from sn, yn, rn instead.  The
+// arithmetic and its order are those of two_loop.
 template <typename T, int TPB, int EPT>
+__device__ __forceinline__ void two_loop_stream(const T *Sb, const T *Yb, const T *rho, int d, int m,
+                                       int head, int cnt, bool vec, bool reg_new,
+                                       const T (&sn)[EPT], const T (&yn)[EPT], T rn, T gamma,
+                                       const T (&g)[EPT], T (&p)[EPT], BlockRed<TPB, T> &red) {
+  const int i0 = threadIdx.x * EPT;
+  T q[EPT], al[kMaxMem];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) q[e] = g[e];
+  auto slot = [&](int j) { return (head - cnt + j + 2 * m) % m; };
+  auto fetch = [&](int j, T (&sv)[EPT], T (&yv)[EPT], T &rv, bool last) {
+    if (reg_new && j == cnt - 1) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        sv[e] = sn[e];
+        yv[e] = yn[e];
+      }
+      rv = rn;
+      return;
+    }
+    const int ph = slot(j);
+    if (last) {
+      vload_nt<T, EPT>(Sb + (size_t)ph * d, i0, d, vec, sv);
+      vload_nt<T, EPT>(Yb + (size_t)ph * d, i0, d, vec, yv);
+    } else {
+      vload<T, EPT>(Sb + (size_t)ph * d, i0, d, vec, sv);
+      vload<T, EPT>(Yb + (size_t)ph * d, i0, d, vec, yv);
+    }
+    rv = rho[ph];
+  };
+  T cs[EPT], cy[EPT], cr = 0;
+  if (cnt > 0) fetch(cnt - 1, cs, cy, cr, false);
+#pragma unroll
+  for (int j = kMaxMem - 1; j >= 0; --j) {
+    if (j < cnt) {
+      T ns[EPT], ny[EPT], nr = 0;
+      if (j > 0) fetch(j - 1, ns, ny, nr, false);
+      T dd = 0;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) dd += cs[e] * q[e];
+      dd = red.sum(dd);
+      al[j] = cr * dd;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) q[e] -= al[j] * cy[e];
+      if (j > 0) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          cs[e] = ns[e];
+          cy[e] = ny[e];
+        }
+        cr = nr;
+      }
+    } else {
+      al[j] = 0;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) q[e] *= gamma;
+  if (cnt > 0) fetch(0, cs, cy, cr, true);
+#pragma unroll
+  for (int j = 0; j < kMaxMem; ++j) {
+    if (j < cnt) {
+      T ns[EPT], ny[EPT], nr = 0;
+      if (j + 1 < cnt) fetch(j + 1, ns, ny, nr, true);
+      T bb = 0;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) bb += cy[e] * q[e];
+      bb = cr * red.sum(bb);
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) q[e] += (al[j] - bb) * cs[e];
+      if (j + 1 < cnt) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          cs[e] = ns[e];
+          cy[e] = ny[e];
+        }
+        cr = nr;
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) p[e] = -q[e];
+}
+
+// One step of start s (the whole workgroup; every branch is uniform in s).
+// HREG: the history is held in registers (m <= kMaxHist); otherwise it stays
+// in memory and two_loop_stream reads it (m <= kMaxMem).
+template <typename T, int TPB, int EPT, bool HREG>
 __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t s,
                                                BlockRed<TPB, T> &red) {
   const int tid = threadIdx.x;
@@ -311,24 +408,30 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
   // history in logical order (loads issued before the reductions below).
   // With the ring full, the oldest pair is evicted when the curvature test
   // passes, so its load waits for that test and happens only when it fails.
-  T Sr[kMaxHist][EPT], Yr[kMaxHist][EPT], rh[kMaxHist], yyr[kMaxHist];
+  constexpr int MH = HREG ? kMaxHist : 1;
+  T Sr[MH][EPT], Yr[MH][EPT], rh[MH], yyr[MH];
   const bool defer_oldest = (mode == M_ACCEPT && cnt == m);
+  if constexpr (HREG) {
 #pragma unroll
-  for (int j = 0; j < kMaxHist; ++j) {
-    rh[j] = 0;
-    yyr[j] = 0;
+    for (int j = 0; j < kMaxHist; ++j) {
+      rh[j] = 0;
+      yyr[j] = 0;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) Sr[j][e] = Yr[j][e] = 0;
-    if (mode == M_ACCEPT && j < cnt && !(j == 0 && defer_oldest)) {
-      const int ph = (head - cnt + j + 2 * m) % m;
-      const T *Sp = a.S + (size_t)m * vo + (size_t)ph * d;
-      const T *Yp = a.Yh + (size_t)m * vo + (size_t)ph * d;
-      vload_nt<T, EPT>(Sp, i0, d, vec, Sr[j]);
-      vload_nt<T, EPT>(Yp, i0, d, vec, Yr[j]);
-      rh[j] = a.rho[(size_t)s * m + ph];
-      yyr[j] = a.yy[(size_t)s * m + ph];
+      for (int e = 0; e < EPT; ++e) Sr[j][e] = Yr[j][e] = 0;
+      if (mode == M_ACCEPT && j < cnt && !(j == 0 && defer_oldest)) {
+        const int ph = (head - cnt + j + 2 * m) % m;
+        const T *Sp = a.S + (size_t)m * vo + (size_t)ph * d;
+        const T *Yp = a.Yh + (size_t)m * vo + (size_t)ph * d;
+        vload_nt<T, EPT>(Sp, i0, d, vec, Sr[j]);
+        vload_nt<T, EPT>(Yp, i0, d, vec, Yr[j]);
+        rh[j] = a.rho[(size_t)s * m + ph];
+        yyr[j] = a.yy[(size_t)s * m + ph];
+      }
     }
   }
+  // streamed history: the pair pushed in this step stays in registers
+  bool reg_new = false;
+  T r_new = 0, yy_new = 1;
   if (mode == M_ACCEPT) {
     T v3[3] = {0, 0, 0};
 #pragma unroll
@@ -352,39 +455,47 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
         a.yy[(size_t)s * m + head] = yy;
       }
       const bool full = (cnt == m);
-      if (full) {
+      if constexpr (HREG) {
+        if (full) {
 #pragma unroll
-        for (int j = 0; j < kMaxHist - 1; ++j) {
+          for (int j = 0; j < kMaxHist - 1; ++j) {
 #pragma unroll
-          for (int e = 0; e < EPT; ++e) {
-            Sr[j][e] = Sr[j + 1][e];
-            Yr[j][e] = Yr[j + 1][e];
+            for (int e = 0; e < EPT; ++e) {
+              Sr[j][e] = Sr[j + 1][e];
+              Yr[j][e] = Yr[j + 1][e];
+            }
+            rh[j] = rh[j + 1];
+            yyr[j] = yyr[j + 1];
           }
-          rh[j] = rh[j + 1];
-          yyr[j] = yyr[j + 1];
         }
-      }
-      const int pos = full ? m - 1 : cnt;
+        const int pos = full ? m - 1 : cnt;
 #pragma unroll
-      for (int j = 0; j < kMaxHist; ++j) {
-        if (j == pos) {
+        for (int j = 0; j < kMaxHist; ++j) {
+          if (j == pos) {
 #pragma unroll
-          for (int e = 0; e < EPT; ++e) {
-            Sr[j][e] = sv[e];
-            Yr[j][e] = yv[e];
+            for (int e = 0; e < EPT; ++e) {
+              Sr[j][e] = sv[e];
+              Yr[j][e] = yv[e];
+            }
+            rh[j] = (T)1 / sy;
+            yyr[j] = yy;
           }
-          rh[j] = (T)1 / sy;
-          yyr[j] = yy;
         }
+      } else {
+        reg_new = true;
+        r_new = (T)1 / sy;
+        yy_new = yy;
       }
       head = (head + 1) % m;
       cnt = full ? m : cnt + 1;
     } else if (defer_oldest) {
-      // pair kept out: the oldest pair (ring slot head) stays in the history
-      vload_nt<T, EPT>(a.S + (size_t)m * vo + (size_t)head * d, i0, d, vec, Sr[0]);
-      vload_nt<T, EPT>(a.Yh + (size_t)m * vo + (size_t)head * d, i0, d, vec, Yr[0]);
-      rh[0] = a.rho[(size_t)s * m + head];
-      yyr[0] = a.yy[(size_t)s * m + head];
+      if constexpr (HREG) {
+        // pair kept out: the oldest pair (ring slot head) stays in the history
+        vload_nt<T, EPT>(a.S + (size_t)m * vo + (size_t)head * d, i0, d, vec, Sr[0]);
+        vload_nt<T, EPT>(a.Yh + (size_t)m * vo + (size_t)head * d, i0, d, vec, Yr[0]);
+        rh[0] = a.rho[(size_t)s * m + head];
+        yyr[0] = a.yy[(size_t)s * m + head];
+      }
     }
   }
 
@@ -430,14 +541,30 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
   if (!sd) {
     // gamma = s^T y / y^T y of the newest pair (logical index cnt - 1)
     T rnew = 0, yynew = 1;
+    if constexpr (HREG) {
 #pragma unroll
-    for (int j = 0; j < kMaxHist; ++j)
-      if (j == cnt - 1) {
-        rnew = rh[j];
-        yynew = yyr[j];
+      for (int j = 0; j < kMaxHist; ++j)
+        if (j == cnt - 1) {
+          rnew = rh[j];
+          yynew = yyr[j];
+        }
+    } else {
+      if (reg_new) {
+        rnew = r_new;
+        yynew = yy_new;
+      } else {
+        const int ph = (head - 1 + m) % m;
+        rnew = a.rho[(size_t)s * m + ph];
+        yynew = a.yy[(size_t)s * m + ph];
       }
+    }
     const T gamma = ((T)1 / rnew) / yynew;
-    two_loop<T, TPB, EPT>(Sr, Yr, rh, gamma, cnt, g, p, red);
+    if constexpr (HREG)
+      two_loop<T, TPB, EPT>(Sr, Yr, rh, gamma, cnt, g, p, red);
+    else
+      two_loop_stream<T, TPB, EPT>(a.S + (size_t)m * vo, a.Yh + (size_t)m * vo,
+                                   a.rho + (size_t)s * m, d, m, head, cnt, vec, reg_new, sv, yv,
+                                   r_new, gamma, g, p, red);
     T t = 0;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) t += g[e] * p[e];
@@ -482,19 +609,20 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
 }
 
 // Start s_base + blockIdx.x (one workgroup per start of the launch's range).
-template <typename T, int TPB, int EPT>
+template <typename T, int TPB, int EPT, bool HREG>
 __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
   __shared__ T rbuf[2 * BlockRed<TPB, T>::NMAX * (TPB / 64)];
   BlockRed<TPB, T> red{rbuf, 0};
   // the compaction that follows counts from zero; every reader of the
   // previous count ran before this launch
   if (a.count_reset && blockIdx.x == 0 && threadIdx.x == 0) *a.count_reset = 0;
-  if ((int64_t)blockIdx.x < a.s_count) lbfgs_step_one<T, TPB, EPT>(a, a.s_base + blockIdx.x, red);
+  if ((int64_t)blockIdx.x < a.s_count)
+    lbfgs_step_one<T, TPB, EPT, HREG>(a, a.s_base + blockIdx.x, red);
 }
 
 // Two-loop direction only, for B independent histories given in logical
 // order (used to check the recursion in isolation).
-template <typename T, int TPB, int EPT>
+template <typename T, int TPB, int EPT, bool HREG>
 __global__ __launch_bounds__(TPB) void two_loop_kernel(int d, int m, const int32_t *cntv,
                                                        const T *S, const T *Y, const T *G, T *P) {
   const int64_t b = blockIdx.x;
@@ -502,6 +630,36 @@ __global__ __launch_bounds__(TPB) void two_loop_kernel(int d, int m, const int32
   __shared__ T rbuf[2 * BlockRed<TPB, T>::NMAX * (TPB / 64)];
   BlockRed<TPB, T> red{rbuf, 0};
   const int cnt = min(max(cntv[b], 0), m);  // never read past this start's m slots
+  if constexpr (!HREG) {
+    // rho_j and gamma from one pass over the pairs, then the streamed
+    // recursion (logical order is the slot order: head = cnt mod m)
+    __shared__ T rho_s[kMaxMem];
+    const int i0 = tid * EPT;
+    const bool vec = (d % EPT == 0);
+    T g[EPT], p[EPT], z[EPT], gamma = 1;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) z[e] = 0;
+    vload<T, EPT>(G + (size_t)b * d, i0, d, vec, g);
+    for (int j = 0; j < cnt; ++j) {
+      T sv[EPT], yv[EPT];
+      vload<T, EPT>(S + ((size_t)b * m + j) * d, i0, d, vec, sv);
+      vload<T, EPT>(Y + ((size_t)b * m + j) * d, i0, d, vec, yv);
+      T v2[2] = {0, 0};
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        v2[0] += sv[e] * yv[e];
+        v2[1] += yv[e] * yv[e];
+      }
+      red.template reduce<2, false>(v2);
+      if (tid == 0) rho_s[j] = (T)1 / v2[0];
+      if (j == cnt - 1) gamma = v2[0] / v2[1];
+    }
+    __syncthreads();
+    two_loop_stream<T, TPB, EPT>(S + (size_t)b * m * d, Y + (size_t)b * m * d, rho_s, d, m,
+                                 cnt % m, cnt, vec, false, z, z, (T)0, gamma, g, p, red);
+    vstore<T, EPT>(P + (size_t)b * d, i0, d, vec, p);
+    return;
+  }
   T Sr[kMaxHist][EPT], Yr[kMaxHist][EPT], rh[kMaxHist], g[EPT], p[EPT];
   T gamma = 1;
   const int i0 = tid * EPT;
@@ -535,21 +693,30 @@ __global__ __launch_bounds__(TPB) void two_loop_kernel(int d, int m, const int32
 
 // ------------------------------------------------------------- dispatch
 
-#define SB_LB_CASES(KERNEL, T, ...)                                                  \
-  if (d <= 64) {                                                                      \
-    hipLaunchKernelGGL((KERNEL<T, 64, 1>), dim3((unsigned)B), dim3(64), 0, s, __VA_ARGS__);   \
-  } else if (d <= 128) {                                                              \
-    hipLaunchKernelGGL((KERNEL<T, 64, 2>), dim3((unsigned)B), dim3(64), 0, s, __VA_ARGS__);   \
-  } else if (d <= 256) {                                                              \
-    hipLaunchKernelGGL((KERNEL<T, 64, 4>), dim3((unsigned)B), dim3(64), 0, s, __VA_ARGS__);   \
-  } else if (d <= 512) {                                                              \
-    hipLaunchKernelGGL((KERNEL<T, 128, 4>), dim3((unsigned)B), dim3(128), 0, s, __VA_ARGS__); \
-  } else if (d <= 1024) {                                                             \
-    hipLaunchKernelGGL((KERNEL<T, 256, 4>), dim3((unsigned)B), dim3(256), 0, s, __VA_ARGS__); \
-  } else if (d <= 2048) {                                                             \
-    hipLaunchKernelGGL((KERNEL<T, 512, 4>), dim3((unsigned)B), dim3(512), 0, s, __VA_ARGS__); \
-  } else {                                                                            \
-    hipLaunchKernelGGL((KERNEL<T, 1024, 4>), dim3((unsigned)B), dim3(1024), 0, s, __VA_ARGS__); \
+// Workgroup size and elements per thread by d; HR: history in registers.
+#define SB_LB_CASES_H(KERNEL, T, HR, ...)                                                     \
+  if (d <= 64) {                                                                              \
+    hipLaunchKernelGGL((KERNEL<T, 64, 1, HR>), dim3((unsigned)B), dim3(64), 0, s, __VA_ARGS__);   \
+  } else if (d <= 128) {                                                                      \
+    hipLaunchKernelGGL((KERNEL<T, 64, 2, HR>), dim3((unsigned)B), dim3(64), 0, s, __VA_ARGS__);   \
+  } else if (d <= 256) {                                                                      \
+    hipLaunchKernelGGL((KERNEL<T, 64, 4, HR>), dim3((unsigned)B), dim3(64), 0, s, __VA_ARGS__);   \
+  } else if (d <= 512) {                                                                      \
+    hipLaunchKernelGGL((KERNEL<T, 128, 4, HR>), dim3((unsigned)B), dim3(128), 0, s, __VA_ARGS__); \
+  } else if (d <= 1024) {                                                                     \
+    hipLaunchKernelGGL((KERNEL<T, 256, 4, HR>), dim3((unsigned)B), dim3(256), 0, s, __VA_ARGS__); \
+  } else if (d <= 2048) {                                                                     \
+    hipLaunchKernelGGL((KERNEL<T, 512, 4, HR>), dim3((unsigned)B), dim3(512), 0, s, __VA_ARGS__); \
+  } else {                                                                                    \
+    hipLaunchKernelGGL((KERNEL<T, 1024, 4, HR>), dim3((unsigned)B), dim3(1024), 0, s,          \
+                       __VA_ARGS__);                                                          \
+  }
+// Register-resident history for m <= kMaxHist, streamed beyond.
+#define SB_LB_CASES(KERNEL, T, M, ...)              \
+  if ((M) <= kMaxHist) {                            \
+    SB_LB_CASES_H(KERNEL, T, true, __VA_ARGS__)     \
+  } else {                                          \
+    SB_LB_CASES_H(KERNEL, T, false, __VA_ARGS__)    \
   }
 
 static int check_d(int d, int m) {
@@ -557,8 +724,8 @@ static int check_d(int d, int m) {
     set_error("L-BFGS supports 1 <= d <= 4096 (got %d)", d);
     return SB_E_UNSUPPORTED;
   }
-  if (m < 1 || m > kMaxHist) {
-    set_error("L-BFGS memory m must be in [1, %d] (got %d)", kMaxHist, m);
+  if (m < 1 || m > kMaxMem) {
+    set_error("L-BFGS memory m must be in [1, %d] (got %d)", kMaxMem, m);
     return SB_E_INVAL;
   }
   return SB_OK;
@@ -618,11 +785,11 @@ int launch_lbfgs_step(const LbfgsBuffers &b, int max_iter, double grad_tol, hipS
   if (b.dtype == DT_F64) {
     LbArgs<double> a = make_args<double>(b, max_iter, grad_tol);
     a.count_reset = b.count;
-    SB_LB_CASES(lbfgs_step_kernel, double, a);
+    SB_LB_CASES(lbfgs_step_kernel, double, b.m, a);
   } else {
     LbArgs<float> a = make_args<float>(b, max_iter, grad_tol);
     a.count_reset = b.count;
-    SB_LB_CASES(lbfgs_step_kernel, float, a);
+    SB_LB_CASES(lbfgs_step_kernel, float, b.m, a);
   }
   SB_LAUNCH_CHECK();
   return SB_OK;
@@ -644,12 +811,12 @@ int launch_lbfgs_step_range(const LbfgsBuffers &b, int64_t s_begin, int64_t coun
     LbArgs<double> a = make_args<double>(b, max_iter, grad_tol);
     a.s_base = s_begin;
     a.s_count = count;
-    SB_LB_CASES(lbfgs_step_kernel, double, a);
+    SB_LB_CASES(lbfgs_step_kernel, double, b.m, a);
   } else {
     LbArgs<float> a = make_args<float>(b, max_iter, grad_tol);
     a.s_base = s_begin;
     a.s_count = count;
-    SB_LB_CASES(lbfgs_step_kernel, float, a);
+    SB_LB_CASES(lbfgs_step_kernel, float, b.m, a);
   }
   SB_LAUNCH_CHECK();
   return SB_OK;
@@ -661,10 +828,10 @@ int launch_two_loop(int64_t B, int d, int m, const int32_t *cnt, const void *S, 
   if (st) return st;
   if (B <= 0) return SB_OK;
   if (dtype == DT_F64) {
-    SB_LB_CASES(two_loop_kernel, double, d, m, cnt, (const double *)S, (const double *)Y,
+    SB_LB_CASES(two_loop_kernel, double, m, d, m, cnt, (const double *)S, (const double *)Y,
                 (const double *)G, (double *)P);
   } else {
-    SB_LB_CASES(two_loop_kernel, float, d, m, cnt, (const float *)S, (const float *)Y,
+    SB_LB_CASES(two_loop_kernel, float, m, d, m, cnt, (const float *)S, (const float *)Y,
                 (const float *)G, (float *)P);
   }
   SB_LAUNCH_CHECK();

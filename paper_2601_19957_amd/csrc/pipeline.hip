@@ -132,14 +132,16 @@ __global__ void gather_scalars_kernel(int n, const int32_t *idx, const double *a
 
 // ------------------------------------------------------------ helpers
 
+// Phase marks on the events of an execution context (none without one).
 struct Timer {
-  hipEvent_t ev[10];
+  hipEvent_t *ev = nullptr;
   int n = 0;
   bool ok = false;
-  void init() {
-    ok = true;
-    for (int i = 0; i < 10; ++i)
-      if (hipEventCreate(&ev[i]) != hipSuccess) ok = false;
+  void init(ExecCtx *ex) {
+    if (ex && ex->ev_ok) {
+      ev = ex->ev;
+      ok = true;
+    }
   }
   void mark(hipStream_t s) {
     if (ok && n < 10) hipEventRecord(ev[n++], s);
@@ -150,11 +152,36 @@ struct Timer {
     hipEventElapsedTime(&ms, ev[a], ev[b]);
     return ms * 1e-3;
   }
-  ~Timer() {
-    if (ok)
-      for (int i = 0; i < 10; ++i) hipEventDestroy(ev[i]);
-  }
 };
+
+// The prior box on the device: info[0] = 1 where some bound is not finite or
+// lo_i >= hi_i (else 0), info[1] = max_i max(|lo_i|, |hi_i|), info[2] =
+// max_i (hi_i - lo_i).  One workgroup; maxima need no fixed order.
+__global__ __launch_bounds__(256) void box_info_kernel(int d, const double *lo, const double *hi,
+                                                       double *info) {
+  __shared__ double part[3][4];
+  double bad = 0.0, mabs = 0.0, mw = 0.0;
+  for (int i = threadIdx.x; i < d; i += 256) {
+    const double a = lo[i], b = hi[i];
+    if (!(isfinite(a) && isfinite(b) && a < b)) bad = 1.0;
+    mabs = fmax(mabs, fmax(fabs(a), fabs(b)));
+    mw = fmax(mw, b - a);
+  }
+  bad = wave_max(bad);
+  mabs = wave_max(mabs);
+  mw = wave_max(mw);
+  const int w = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) {
+    part[0][w] = bad;
+    part[1][w] = mabs;
+    part[2][w] = mw;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int j = threadIdx.x;
+    info[j] = fmax(fmax(part[j][0], part[j][1]), fmax(part[j][2], part[j][3]));
+  }
+}
 
 // One evaluation of l (+grad, +aux) at B rows of X through GEMM + finish.
 struct Evaluator {
@@ -391,6 +418,7 @@ static RunCfg resolve(const sb_loglik *ll, const sb_config *c) {
 struct Layout {
   // prep
   double *Lprep = nullptr, *logdetP = nullptr, *beta = nullptr, *mx = nullptr;
+  double *boxinfo = nullptr;  // [4] from box_info_kernel
   int32_t *info = nullptr, *flags = nullptr;
   float *P32 = nullptr, *mu32 = nullptr;
   bf16_t *Pbf = nullptr, *Plo = nullptr;
@@ -470,6 +498,7 @@ static int carve_layout(Arena &ar, Layout &L, const sb_loglik *ll, const RunCfg 
   L.mx = ar.take<double>(K);
   L.info = ar.take<int32_t>(K);
   L.flags = ar.take<int32_t>(16);
+  L.boxinfo = ar.take<double>(4);
   if (mixed) {
     L.P32 = ar.take<float>((size_t)K * d * d);
     L.Pbf = ar.take<bf16_t>((size_t)K * d * d);
@@ -576,9 +605,75 @@ size_t evidence_ws_bytes(const sb_loglik *ll, const sb_config *cfg) {
 
 // ------------------------------------------------------------ the path
 
-// Bulk L-BFGS over all starts in dtype of lb; X0 in that dtype.
+// The executable graph of an iteration block for `key`: a cached one, or
+// the block captured from `record` and written into the least recently used
+// slot (updated in place when the slot's executable accepts it, else
+// instantiated anew).  nullptr on failure (error set).
+template <typename F>
+static hipGraphExec_t block_graph(ExecCtx *ex, const BlockKey &key, hipStream_t s, F record,
+                                  int *st) {
+  ExecCtx::Slot *hit = nullptr, *victim = &ex->slot[0];
+  for (int i = 0; i < ExecCtx::kSlots; ++i) {
+    ExecCtx::Slot &sl = ex->slot[i];
+    if (sl.used && memcmp(&sl.key, &key, sizeof(BlockKey)) == 0) hit = &sl;
+    if (!sl.used || (victim->used && sl.last < victim->last)) victim = &sl;
+  }
+  if (hit) {
+    hit->last = ++ex->tick;
+    return hit->exec;
+  }
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    set_error("graph capture could not begin");
+    *st = SB_E_DEVICE;
+    return nullptr;
+  }
+  const int r = record();
+  hipGraph_t graph = nullptr;
+  const hipError_t e1 = hipStreamEndCapture(s, &graph);
+  if (r || e1 != hipSuccess) {
+    set_error("graph capture failed (%d, %s)", r, hipGetErrorString(e1));
+    if (graph) (void)hipGraphDestroy(graph);
+    *st = r ? r : SB_E_DEVICE;
+    return nullptr;
+  }
+  ++ex->n_capture;
+  bool ok = false;
+  if (victim->exec) {
+    hipGraphNode_t bad_node = nullptr;
+    hipGraphExecUpdateResult ur;
+    ok = hipGraphExecUpdate(victim->exec, graph, &bad_node, &ur) == hipSuccess &&
+         ur == hipGraphExecUpdateSuccess;
+    (void)hipGetLastError();
+    if (ok) {
+      ++ex->n_update;
+    } else {
+      (void)hipGraphExecDestroy(victim->exec);
+      victim->exec = nullptr;
+    }
+  }
+  if (!ok) {
+    if (hipGraphInstantiate(&victim->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      victim->exec = nullptr;
+      victim->used = false;
+      (void)hipGraphDestroy(graph);
+      set_error("graph instantiate failed");
+      *st = SB_E_DEVICE;
+      return nullptr;
+    }
+    ++ex->n_instantiate;
+  }
+  (void)hipGraphDestroy(graph);
+  victim->used = true;
+  victim->key = key;
+  victim->last = ++ex->tick;
+  return victim->exec;
+}
+
+// Bulk L-BFGS over all starts in dtype of lb; X0 in that dtype.  With an
+// execution context (and a stream that can be captured) the iteration blocks
+// run as its graph for `key`; without one they are launched directly.
 static int run_bulk(Layout &L, const RunCfg &rc, double tol, hipStream_t s,
-                    int64_t *evals_out, int *steps_out) {
+                    int64_t *evals_out, int *steps_out, ExecCtx *ex, const BlockKey &key) {
   LbfgsBuffers &lb = L.lb;
   Evaluator &ev = L.bulk;
   int st = launch_lbfgs_init(lb, L.X0b, s);
@@ -607,41 +702,35 @@ static int run_bulk(Layout &L, const RunCfg &rc, double tol, hipStream_t s,
     if (r) return r;
     return ev.run(at, lb.B, lb.count, lb.F, lb.G, d, lb.idx, nullptr, true, s);
   };
-  int32_t *hcount = nullptr;
-  SB_HIP(hipHostMalloc((void **)&hcount, sizeof(int32_t) * 4, hipHostMallocDefault));
+  // the per-block active count lands in pinned memory of the context, else
+  // in a host stack word (the copy then completes before the synchronise)
+  int32_t hstack[4] = {0, 0, 0, 0};
+  int32_t *hcount = ex ? ex->pinned : hstack;
+  const bool graphs = ex && rc.use_graph && s != nullptr;
   hipGraphExec_t exec = nullptr;
-  hipGraph_t graph = nullptr;
   int steps = 0;
   const int max_steps = 42 * rc.max_iter + 64;
   int rc_st = SB_OK;
-  bool captured = false;
   while (steps < max_steps) {
-    if (rc.use_graph) {
-      if (!captured) {
-        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-          rc_st = SB_E_DEVICE;
-          break;
-        }
+    if (graphs) {
+      if (!exec) {
         int r = SB_OK;
-        for (int k = 0; k < rc.blk && r == SB_OK; ++k) r = one_step();
-        hipError_t e1 = hipStreamEndCapture(s, &graph);
-        if (r || e1 != hipSuccess) {
-          set_error("graph capture failed (%d, %s)", r, hipGetErrorString(e1));
+        exec = block_graph(ex, key, s, [&]() -> int {
+          int q = SB_OK;
+          for (int k = 0; k < rc.blk && q == SB_OK; ++k) q = one_step();
+          return q;
+        }, &r);
+        if (!exec) {
           rc_st = r ? r : SB_E_DEVICE;
           break;
         }
-        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-          set_error("graph instantiate failed");
-          rc_st = SB_E_DEVICE;
-          break;
-        }
-        captured = true;
       }
       if (hipGraphLaunch(exec, s) != hipSuccess) {
         set_error("graph launch failed");
         rc_st = SB_E_DEVICE;
         break;
       }
+      ++ex->n_launch;
     } else {
       int r = SB_OK;
       for (int k = 0; k < rc.blk && r == SB_OK; ++k) r = one_step();
@@ -660,14 +749,13 @@ static int run_bulk(Layout &L, const RunCfg &rc, double tol, hipStream_t s,
     }
     if (hcount[0] == 0) break;
   }
-  if (exec) hipGraphExecDestroy(exec);
-  if (graph) hipGraphDestroy(graph);
   int64_t ev_h = 0;
   if (rc_st == SB_OK) {
-    if (hipMemcpy(&ev_h, lb.evals, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpyAsync(&ev_h, lb.evals, sizeof(int64_t), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
       rc_st = SB_E_DEVICE;
   }
-  hipHostFree(hcount);
   *evals_out = ev_h;
   *steps_out = steps;
   if (rc_st) return rc_st;
@@ -729,7 +817,7 @@ static int polish_chunk(Layout &L, const Model &m64, const DevProblem &P, int n,
 }
 
 int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void *ws,
-                 size_t ws_bytes, hipStream_t s) {
+                 size_t ws_bytes, hipStream_t s, ExecCtx *ex) {
   const auto t_start = std::chrono::steady_clock::now();
   sb_loglik llh;
   llh.family = P.family;
@@ -746,7 +834,7 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     return SB_E_NOMEM;
   }
   Timer tm;
-  tm.init();
+  tm.init(ex);
   tm.mark(s);  // 0
   int st;
   // ---------------- A1 prep
@@ -761,6 +849,8 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
   m64.nu = P.nu;
   m64.c = P.c;
   if ((st = launch_fill_i32(16, 0, L.flags, s))) return st;
+  hipLaunchKernelGGL(box_info_kernel, dim3(1), dim3(256), 0, s, d, P.lo, P.hi, L.boxinfo);
+  SB_LAUNCH_CHECK();
   if ((st = launch_symmetry_check(P.prec, K, d, L.mx, L.flags, s))) return st;
   if ((st = chol_batched(K, d, P.prec, L.Lprep, L.info, s))) return st;
   if ((st = launch_logdet(K, d, L.Lprep, L.info, L.logdetP, s))) return st;
@@ -782,12 +872,18 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
   }
   {
     int32_t hflag[1];
-    std::vector<int32_t> hinfo(K);
-    std::vector<double> hmx(K);
+    int32_t hinfo[kMaxComp];
+    double hmx[kMaxComp], hbox[4];
     SB_HIP(hipMemcpyAsync(hflag, L.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    SB_HIP(hipMemcpyAsync(hinfo.data(), L.info, sizeof(int32_t) * K, hipMemcpyDeviceToHost, s));
-    SB_HIP(hipMemcpyAsync(hmx.data(), L.mx, sizeof(double) * K, hipMemcpyDeviceToHost, s));
+    SB_HIP(hipMemcpyAsync(hinfo, L.info, sizeof(int32_t) * K, hipMemcpyDeviceToHost, s));
+    SB_HIP(hipMemcpyAsync(hmx, L.mx, sizeof(double) * K, hipMemcpyDeviceToHost, s));
+    SB_HIP(hipMemcpyAsync(hbox, L.boxinfo, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
     SB_HIP(hipStreamSynchronize(s));
+    if (hbox[0] != 0.0) {
+      set_error("box: need finite lo_i < hi_i in every coordinate");
+      res->log_z = NAN;
+      return SB_E_INVAL;
+    }
     if (hflag[0]) {
       set_error("precision matrix is not symmetric to 1e-12 relative");
       res->log_z = NAN;
@@ -855,13 +951,7 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
       mb.Plp = L.P32;
       mb.Phi = L.Pbf;
       mb.Plo = L.Plo;
-      double maxabs_theta = 0.0;
-      std::vector<double> hlo(d), hhi(d);
-      SB_HIP(hipMemcpyAsync(hlo.data(), P.lo, sizeof(double) * d, hipMemcpyDeviceToHost, s));
-      SB_HIP(hipMemcpyAsync(hhi.data(), P.hi, sizeof(double) * d, hipMemcpyDeviceToHost, s));
-      SB_HIP(hipStreamSynchronize(s));
-      for (int i = 0; i < d; ++i)
-        maxabs_theta = std::max(maxabs_theta, std::max(std::fabs(hlo[i]), std::fabs(hhi[i])));
+      const double maxabs_theta = hbox[1];  // max_i max(|lo_i|, |hi_i|)
       tol = 32.0 * 5.9604644775390625e-08 * pmax * (1.0 + maxabs_theta);
       if (rc.grad_tol > 0) tol = std::max(tol, rc.grad_tol);
       if ((st = launch_cast_f64_f32((int64_t)rc.n_starts * d, L.X0, (float *)L.X0b, s)))
@@ -904,7 +994,36 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     }
     int64_t bulk_evals = 0;
     int steps = 0;
-    if ((st = run_bulk(L, rc, tol, s, &bulk_evals, &steps))) return st;
+    BlockKey key;
+    memset(&key, 0, sizeof(key));
+    key.stream = (void *)s;
+    key.ws = ws;
+    key.ws_bytes = ws_bytes;
+    key.P = P;
+    // field by field: the caller's padding bytes stay out of the key
+    key.cfg.n_rays = cfg->n_rays;
+    key.cfg.n_points = cfg->n_points;
+    key.cfg.n_starts = cfg->n_starts;
+    key.cfg.m = cfg->m;
+    key.cfg.max_iter = cfg->max_iter;
+    key.cfg.max_modes = cfg->max_modes;
+    key.cfg.precision = cfg->precision;
+    key.cfg.grad_tol = cfg->grad_tol;
+    key.cfg.dedup_tol = cfg->dedup_tol;
+    key.cfg.dedup_tol_pre = cfg->dedup_tol_pre;
+    key.cfg.seed = cfg->seed;
+    key.tol = tol;
+    key.max_iter = rc.max_iter;
+    key.blk = rc.blk;
+    key.dtype = L.bulk.dtype;
+    key.gemm_dtype = L.bulk.gemm_dtype;
+    key.two_stage = L.bulk.two_stage;
+    key.screen = L.bulk.screen;
+    key.grad_direct = L.bulk.grad_direct;
+    key.tile = L.bulk.tile;
+    key.tile1 = L.bulk.tile1;
+    key.tile2 = L.bulk.tile2;
+    if ((st = run_bulk(L, rc, tol, s, &bulk_evals, &steps, ex, key))) return st;
     tm.mark(s);  // 3
     // ---------------- A7 pre-dedup
     const int64_t B = rc.n_starts;
@@ -944,15 +1063,7 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     tm.mark(s);  // 5
     // ---------------- A7 final dedup
     double tau = rc.dedup_tol;
-    if (!(tau > 0)) {
-      std::vector<double> hlo(d), hhi(d);
-      SB_HIP(hipMemcpyAsync(hlo.data(), P.lo, sizeof(double) * d, hipMemcpyDeviceToHost, s));
-      SB_HIP(hipMemcpyAsync(hhi.data(), P.hi, sizeof(double) * d, hipMemcpyDeviceToHost, s));
-      SB_HIP(hipStreamSynchronize(s));
-      double w = 0.0;
-      for (int i = 0; i < d; ++i) w = std::max(w, hhi[i] - hlo[i]);
-      tau = 1e-6 * w;
-    }
+    if (!(tau > 0)) tau = 1e-6 * hbox[2];  // max_i (hi_i - lo_i)
     Arena ar2(L.dedup_ar.base, L.dedup_ar.cap);
     int nm = 0;
     st = dedup_run(nrep, d, L.XA, DT_F64, L.lA, DT_F64, L.okA, tau, L.rep2_of, L.rep2,

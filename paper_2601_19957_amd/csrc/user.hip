@@ -483,7 +483,7 @@ static int user_layout(Arena &ar, UserLayout &U, int d, const sb_config *c) {
 
 static bool user_cfg_ok(const sb_config *c) {
   return c && c->n_rays >= 1 && c->n_points >= 1 && c->n_starts >= 1 &&
-         c->n_starts <= c->n_rays && c->m >= 1 && c->m <= kMaxHist && c->max_modes >= 1;
+         c->n_starts <= c->n_rays && c->m >= 1 && c->m <= kMaxMem && c->max_modes >= 1;
 }
 
 size_t sb_user_evidence_workspace_bytes(int32_t d, const sb_config *cfg) {

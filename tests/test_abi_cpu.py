@@ -61,7 +61,6 @@ def test_validation_before_device():
         (lambda p: p.prec.__setitem__((0, 1, 1), np.nan), None, _lib.E_INVAL),
         (None, lambda c: setattr(c, "m", 0), _lib.E_INVAL),
         (None, lambda c: setattr(c, "m", 33), _lib.E_INVAL),
-        (None, lambda c: setattr(c, "m", 12), _lib.E_UNSUPPORTED),
         (None, lambda c: setattr(c, "max_modes", 0), _lib.E_INVAL),
         (None, lambda c: setattr(c, "n_starts", 10 ** 6), _lib.E_INVAL),
         (None, lambda c: setattr(c, "n_points", 0), _lib.E_INVAL),
@@ -89,6 +88,16 @@ def test_student_t_validation():
 def test_null_arguments():
     L = _lib.lib()
     assert L.sb_evidence(None, None, None, None) == _lib.E_INVAL
+    assert L.sb_exec_create(None) == _lib.E_INVAL
+    assert L.sb_exec_stats(None, None) == _lib.E_INVAL
+    L.sb_exec_destroy(None)
+    prob, cfg = synth.make_workload("c0")
+    hp = _lib._HostProblem(prob)
+    r = _lib.sb_result()
+    assert L.sb_evidence_exec_dev(None, C.byref(hp.ll), C.byref(hp.box),
+                                  C.byref(_lib.make_config(cfg)), C.byref(r), None, 0,
+                                  None) == _lib.E_INVAL
+    assert math.isnan(r.log_z)
     assert L.sb_evidence_workspace_bytes(None, None) == 0
     assert L.sb_lbfgs_direction_dev(1, 4, 8, None, None, None, None, None, 0, None) == _lib.E_INVAL
     assert L.sb_cholesky_logdet_dev(1, 0, None, None, None, None, None) == _lib.E_INVAL

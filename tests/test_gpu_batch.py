@@ -79,6 +79,16 @@ def test_batch_matches_oracle(L, precision):
         _compare(r, ref, 1e-9 if precision == 0 else 1e-6)
 
 
+def test_batch_long_memory(L):
+    """A batch whose starts keep 24 history pairs (read from memory in the recursion)."""
+    probs = mixed_batch()[:5]
+    cfgs = [cfg_for(j, 0, m=24) for j in range(len(probs))]
+    res = L.sb_evidence_batch(probs, cfgs)
+    for j, (p, r) in enumerate(zip(probs, res)):
+        ref = O.evidence(p, cfg_for(j, 0, m=24), problem=j)
+        _compare(r, ref, 1e-9)
+
+
 def test_batch_of_one_matches_single(L):
     prob, cfg = synth.make_workload("c1", n_starts=256)
     [rb] = L.sb_evidence_batch([prob], [cfg])

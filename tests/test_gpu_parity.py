@@ -313,6 +313,35 @@ def test_two_loop_direction(L, d):
         assert e <= 1e-12, (b, e)
 
 
+@pytest.mark.parametrize("m", [16, 32])
+@pytest.mark.parametrize("d", [4, 100, 1024, 4096])
+def test_two_loop_direction_long_memory(L, d, m):
+    """Memories beyond the register-resident 8 pairs: the history is read from memory in
+    each loop of the recursion; same direction as the oracle's two-loop in FP64, and in
+    FP32 within its rounding (inputs rounded to FP32 for both sides)."""
+    B = 6
+    cnts = [0, 1, 9, m - 1, m, m]
+    S = np.zeros((B, m, d))
+    Y = np.zeros((B, m, d))
+    G = np.zeros((B, d))
+    for b in range(B):
+        s_, y_, g_ = synth.lbfgs_history(d, m, cnts[b], seed=170 + b)
+        S[b], Y[b], G[b] = s_[0], y_[0], g_[0]
+    cnt = dev(np.array(cnts, dtype=np.int32))
+    P = L.sb_lbfgs_direction_dev(dev(S), dev(Y), dev(G), cnt).cpu().numpy()
+    S32, Y32, G32 = (a.astype(np.float32).astype(np.float64) for a in (S, Y, G))
+    P32 = L.sb_lbfgs_direction_dev(dev(S).float(), dev(Y).float(), dev(G).float(),
+                                   cnt).cpu().numpy()
+    for b in range(B):
+        c = cnts[b]
+        ref = O.two_loop(S[b, :c], Y[b, :c], G[b]) if c else -G[b]
+        e = absmax(P[b] - ref) / absmax(ref)
+        assert e <= 1e-12, (b, e)
+        ref32 = O.two_loop(S32[b, :c], Y32[b, :c], G32[b]) if c else -G32[b]
+        e32 = absmax(P32[b] - ref32) / absmax(ref32)
+        assert e32 <= 1e-3, (b, e32)
+
+
 # -------------------------------------------------------------- L-BFGS / A4-A5
 
 @pytest.mark.parametrize("name", ["c0", "mix_d37_K3", "t_d70"])
@@ -338,14 +367,20 @@ def test_lbfgs_reaches_oracle_points(L, name):
 
 @pytest.mark.parametrize("name,m,scale,max_iter", [("mix_d37_K3", 8, 2.0, 20),
                                                     ("t_d70", 8, 2.0, 15),
-                                                    ("t_d70", 1, 8.0, 30)])
+                                                    ("t_d70", 1, 8.0, 30),
+                                                    ("mix_d37_K3", 16, 2.0, 30),
+                                                    ("t_d70", 16, 2.0, 40),
+                                                    ("t_d70", 32, 2.0, 45),
+                                                    ("mix_d200_K2", 32, 2.0, 45)])
 def test_lbfgs_path_matches_oracle(L, name, m, scale, max_iter):
     """FP64, the same starts stopped after max_iter accepted steps, past the point where the
     history ring is full: the GPU points equal the oracle's up to rounding order, so the
     two-loop sees the oracle's history (ring order, the evicted pair dropped, a pair the
     curvature test keeps out leaving the oldest one in place; the m = 1 case from far starts
-    on the heavy-tailed t meets that test's failure with the ring full).  The oracle's own
-    paths move by at most ~2e-9 relative under 1e-15 perturbations of the starts."""
+    on the heavy-tailed t meets that test's failure with the ring full; m = 16 and 32 run
+    the step whose history is read from memory in each loop of the recursion).  The oracle's own
+    paths move by at most ~1.2e-10 relative under 1e-15 perturbations of the starts in these
+    cases (far starts with m = 16 on the nu = 4 t move by 3e-8, so none are used here)."""
     prob = PROBLEMS[name]()
     X0 = synth.points_near_modes(prob, 16, 91, scale=scale)
     md = L.DeviceModel(prob)
@@ -448,6 +483,75 @@ def test_evidence_matches_oracle(L, name, ns, prec):
     r = L.sb_evidence(prob, cfg)
     ref = O.evidence(prob, synth.make_run_config(name, n_starts=ns, precision=0))
     _compare(r, ref, 1e-9 if prec == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("m,prec", [(16, 0), (32, 0), (32, 1)])
+def test_evidence_long_memory(L, m, prec):
+    """The whole path with L-BFGS memories beyond the register-resident 8 pairs (c1's
+    mixture, 512 starts): the same mode set and log Z as the oracle run with that memory."""
+    prob, cfg = synth.make_workload("c1", n_starts=512, precision=prec)
+    cfg.m = m
+    r = L.sb_evidence(prob, cfg)
+    rc = synth.make_run_config("c1", n_starts=512, precision=0)
+    rc.m = m
+    ref = O.evidence(prob, rc)
+    _compare(r, ref, 1e-9 if prec == 0 else 1e-6)
+
+
+def _same_result(a, b):
+    assert a.status == b.status == 0
+    assert a.log_z == b.log_z and a.n_modes == b.n_modes
+    assert np.array_equal(a.modes, b.modes) and np.array_equal(a.mode_log_z, b.mode_log_z)
+    assert np.array_equal(a.log_det_h, b.log_det_h)
+    assert a.n_grad_evals == b.n_grad_evals and a.iterations == b.iterations
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_exec_context_graphs(L, prec):
+    """sb_evidence_exec_dev runs the L-BFGS iteration blocks as the context's HIP graphs:
+    results bitwise equal to sb_evidence_dev (blocks launched directly, nothing allocated) on
+    a stream and on the null stream, and to the host entry point.  A repeated call captures
+    nothing; another problem on the same context captures its own block once, and the first
+    problem's graph is still found afterwards."""
+    p1, c1 = synth.make_workload("c1", n_starts=256, precision=prec)
+    p2, c2 = synth.make_workload("c0", precision=prec)
+    ex = L.ExecContext()
+    stream = torch.cuda.Stream()
+    r1 = L.EvidenceRunner(p1, c1, exec=ex)
+    r2 = L.EvidenceRunner(p2, c2, exec=ex)
+    plain = L.EvidenceRunner(p1, c1)
+    with torch.cuda.stream(stream):
+        a = r1.run(stream)
+        s1 = ex.stats()
+        b = r1.run(stream)
+        s2 = ex.stats()
+        c = r2.run(stream)
+        s3 = ex.stats()
+        e = r1.run(stream)
+        s4 = ex.stats()
+        f = plain.run(stream)
+    torch.cuda.synchronize()
+    g = plain.run()  # the null stream
+    h = L.sb_evidence(p1, c1)
+    assert s1["captured"] == 1 and s1["instantiated"] == 1 and s1["launched"] >= 1, s1
+    assert s2["captured"] == 1 and s2["instantiated"] == 1 and s2["launched"] > s1["launched"]
+    assert s3["captured"] == 2, s3
+    assert s4["captured"] == 2 and s4["launched"] > s3["launched"], s4
+    assert c.status == 0 and c.n_modes == 1
+    for r in (b, e, f, g, h):
+        _same_result(a, r)
+    assert a.seconds[2] > 0 and a.seconds[7] > 0  # phase times with a context
+    assert f.seconds[2] == 0 and f.seconds[7] > 0  # only the total without one
+    ex.close()
+
+
+def test_evidence_dev_rejects_bad_box_on_device(L):
+    """The allocation-free entry point checks the box on the device."""
+    prob, cfg = synth.make_workload("c0")
+    prob.lo = prob.lo.copy()
+    prob.lo[2] = prob.hi[2]
+    r = L.EvidenceRunner(prob, cfg).run()
+    assert r.status == L.E_INVAL and math.isnan(r.log_z)
 
 
 @pytest.mark.parametrize("name,d", [("c0", 64), ("c1", 64)])
