@@ -889,3 +889,169 @@ def evidence_chisao(prob, cfg, prm: ChiSaoParams, n_ref: int = 0, delta: float =
     res = finish_points(prob, cfg, cyc["X"], cyc["l"], valid, problem=problem)
     res.cycle = cyc["log"]
     return res
+
+
+# ------------------------------------------------ trajectory-based geometry detection
+
+def lbfgs_user(f, x0, eps, m=8, max_iter=20, grad_tol=0.0):
+    """L-BFGS on -f for a generic log-likelihood f with central finite-difference gradients
+    (the rules of or_lbfgs: first step -grad f / max(1, |grad f|_inf), Armijo c1 = 1e-4 with
+    halving up to 40 times, history reset then stall on failure, curvature skip
+    s^T y > 1e-10 |s| |y|, stop at |grad l|_inf <= grad_tol or max_iter accepted steps),
+    recording its trajectory: the start and every accepted point, with the gradient of l
+    there (the TrajectoryBank of module GreenDragon, section "Trajectory Storage").
+    Returns dict(X [T+1][d], G [T+1][d], status)."""
+    x = _f64(x0).copy()
+    d = x.size
+
+    def lg(p):
+        r = fd_derivatives(f, p[None], eps)
+        return float(r["l"][0]), r["grad"][0].copy()
+
+    l, gl = lg(x)
+    Xs, Gs = [x.copy()], [gl.copy()]
+    if not (math.isfinite(l) and np.all(np.isfinite(gl))):
+        return dict(X=np.array(Xs), G=np.array(Gs), status=ST_DEAD)
+    S, Y = [], []
+    it = 0
+    status = ST_MAXITER
+    while True:
+        g = -gl
+        gn = float(np.max(np.abs(gl)))
+        if gn <= grad_tol:
+            status = ST_CONVERGED
+            break
+        if it >= max_iter:
+            status = ST_MAXITER
+            break
+        gtp = 0.0
+        if S:
+            p = two_loop(np.array(S), np.array(Y), g)
+            gtp = float(np.dot(g, p))
+        if not S or not gtp < 0.0:
+            S, Y = [], []
+            p = -g * (1.0 / (gn if gn > 1.0 else 1.0))
+            gtp = float(np.dot(g, p))
+        alpha, ok = 1.0, False
+        for _ in range(41):
+            xt = x + alpha * p
+            lt, glt = lg(xt)
+            if math.isfinite(lt) and -lt <= -l + 1e-4 * alpha * gtp:
+                ok = True
+                break
+            alpha *= 0.5
+        if not ok:
+            if S:
+                S, Y = [], []
+                continue
+            status = ST_STALLED
+            break
+        sv, yv = xt - x, -glt - g
+        if float(np.dot(sv, yv)) > 1e-10 * float(np.linalg.norm(sv)) * float(np.linalg.norm(yv)):
+            if len(S) == m:
+                S.pop(0)
+                Y.pop(0)
+            S.append(sv)
+            Y.append(yv)
+        x, l, gl = xt, lt, glt
+        it += 1
+        Xs.append(x.copy())
+        Gs.append(gl.copy())
+    return dict(X=np.array(Xs), G=np.array(Gs), status=status)
+
+
+def perpendicular_step_fraction(X, G, h, rel_floor=1e-3):
+    """Perpendicular step fraction of one trajectory (section "Automatic Geometry Detection",
+    Step 1, and the appendix "Rotation Detection"): in coordinates whitened by sqrt(h)
+    (h_i = -H_ii > 0, u = sqrt(h) theta), step t from X[t] to X[t+1] has du = sqrt(h) dtheta
+    and the gradient of l at X[t] becomes gw = G[t] / sqrt(h); f_perp = |du_perp| / |du| with
+    du_perp the part of du perpendicular to gw.  Reading: a step counts only while its whitened
+    gradient is at least rel_floor of the trajectory's first (closer to the mode the gradient
+    is at the level of the stopping rule's noise and carries no direction).  Returns the f_perp
+    of the counted steps."""
+    X, G = _f64(X), _f64(G)
+    sh = np.sqrt(_f64(h))
+    out = []
+    g0 = float(np.linalg.norm(G[0] / sh)) if len(G) else 0.0
+    for t in range(len(X) - 1):
+        gw = G[t] / sh
+        if not float(np.linalg.norm(gw)) >= rel_floor * g0 or g0 == 0.0:
+            continue
+        du = sh * (X[t + 1] - X[t])
+        nd = float(np.linalg.norm(du))
+        if nd == 0.0:
+            continue
+        perp = du - (float(np.dot(du, gw)) / float(np.dot(gw, gw))) * gw
+        out.append(float(np.linalg.norm(perp)) / nd)
+    return np.array(out)
+
+
+def greendragon_seeds(mode, hdiag):
+    """GreenDragon's seeds of a peak (its algorithm summary: 2d samples at
+    theta* +- 0.9 w e_i): with the width read from the diagonal curvature, w_i =
+    1/sqrt(-H_ii); seed 2i is theta* + 0.9 w_i e_i, seed 2i + 1 theta* - 0.9 w_i e_i."""
+    mode, hdiag = _f64(mode), _f64(hdiag)
+    d = mode.size
+    w = 1.0 / np.sqrt(-hdiag)
+    S = np.repeat(mode[None], 2 * d, axis=0)
+    for i in range(d):
+        S[2 * i, i] = mode[i] + 0.9 * w[i]
+        S[2 * i + 1, i] = mode[i] - 0.9 * w[i]
+    return S
+
+
+def trajectory_geometry(f, modes, hdiag, eps, n_iter, m=8, grad_tol=0.0, rel_floor=1e-3):
+    """Per mode, the largest perpendicular step fraction over the trajectories of its
+    GreenDragon seeds (n_iter L-BFGS steps each, whitening h = -hdiag of the mode); NaN when no
+    step counts."""
+    modes, hdiag = np.atleast_2d(_f64(modes)), np.atleast_2d(_f64(hdiag))
+    out = np.full(modes.shape[0], np.nan)
+    for k in range(modes.shape[0]):
+        vals = []
+        for x0 in greendragon_seeds(modes[k], hdiag[k]):
+            tr = lbfgs_user(f, x0, eps, m=m, max_iter=n_iter, grad_tol=grad_tol)
+            vals.extend(perpendicular_step_fraction(tr["X"], tr["G"], -hdiag[k], rel_floor))
+        if vals:
+            out[k] = max(vals)
+    return out
+
+
+def user_mode_evidence_geo(f, modes, lo, hi, eps, rot_tol, n_iter, eps_axis, eps_rot, m=8,
+                           grad_tol=0.0):
+    """Laplace evidence at given modes with the two-step geometry detection of the algorithm
+    "BendTheBow Evidence Calculation": Step 1, the perpendicular step fraction of the
+    GreenDragon trajectories (trajectory_geometry); f_perp > eps_rot: rotated; f_perp <=
+    eps_axis: axis-aligned; otherwise (or with no counted step) inconclusive, and Step 2, the
+    probe b, decides (|b| > rot_tol |mean H_ii|: rotated).  Rotated modes take the full FD
+    Hessian and its Cholesky log det, the others sum log(-H_ii).  decision [n]: 0 axis-aligned
+    by the trajectories, 1 rotated by them, 2 axis-aligned by the probe, 3 rotated by it.
+    Returns None if some mode is not a maximum."""
+    modes = np.atleast_2d(_f64(modes))
+    n, d = modes.shape
+    lv = log_volume(lo, hi)
+    r = fd_derivatives(f, modes, eps, full=False)
+    if np.any(r["hdiag"] >= 0):
+        return None
+    fp = trajectory_geometry(f, modes, r["hdiag"], eps, n_iter, m=m, grad_tol=grad_tol)
+    out = dict(logl=r["l"].copy(), logdet=np.zeros(n), fperp=fp,
+               decision=np.zeros(n, dtype=np.int32), mode_log_z=np.zeros(n))
+    for k in range(n):
+        if fp[k] > eps_rot:
+            dec = 1
+        elif fp[k] <= eps_axis:
+            dec = 0
+        else:
+            a = float(np.mean(r["hdiag"][k]))
+            dec = 3 if abs(r["probe_b"][k]) > rot_tol * abs(a) else 2
+        out["decision"][k] = dec
+        if dec in (1, 3):
+            Hk = fd_derivatives(f, modes[k:k + 1], eps, full=True)["H"][0]
+            st, _ = cholesky(-Hk)
+            if st:
+                return None
+            out["logdet"][k] = logdet_spd(-Hk)
+        else:
+            out["logdet"][k] = pairwise_sum(np.log(-r["hdiag"][k]))
+        out["mode_log_z"][k] = mode_log_z(d, out["logl"][k], out["logdet"][k], lv)
+    out["log_z"] = logsumexp(np.sort(out["mode_log_z"])[::-1])
+    return out

@@ -1150,3 +1150,100 @@ def test_chisao_orthonormal_dependence_threshold(oracle_lib, n, d):
         else:
             assert np.all(np.isfinite(Q[k:])), delta
             assert np.allclose(Q @ Q.T, np.eye(n), atol=1e-10)
+
+
+# ------------------------------------------- trajectory-based rotation detection
+
+def _quad(H, mu):
+    def f(x):
+        dlt = x - mu
+        return -0.5 * float(dlt @ H @ dlt)
+    return f
+
+
+def _quad_logz(H, lo, hi):
+    d = H.shape[0]
+    return 0.5 * d * math.log(2 * math.pi) - 0.5 * float(np.linalg.slogdet(H)[1]) \
+        - float(np.sum(np.log(hi - lo)))
+
+
+def test_perpendicular_fraction_axis_aligned_is_zero(oracle_lib):
+    """Axis-aligned anisotropic quadratic: from the axis seeds every L-BFGS step stays on its
+    axis, so in whitened coordinates steps and gradients are parallel: f_perp = 0 to
+    rounding, the mode is classed axis-aligned without the probe, log Z is the closed form."""
+    O = oracle_lib
+    d = 6
+    h = synth.log_uniform(np.random.Generator(np.random.PCG64(3)), 0.1, 10.0, d)
+    H = np.diag(h)
+    mu = np.linspace(-1.0, 1.0, d)
+    f = _quad(H, mu)
+    lo, hi = np.full(d, -10.0), np.full(d, 10.0)
+    fp = O.trajectory_geometry(f, mu[None], -h[None], 1e-4, 12)
+    assert fp[0] <= 1e-8, fp
+    r = O.user_mode_evidence_geo(f, mu[None], lo, hi, 1e-4, 1e-3, 12, 1e-4, 1e-2)
+    assert r["decision"][0] == 0
+    assert abs(r["log_z"] - _quad_logz(H, lo, hi)) <= 1e-6
+
+
+def test_perpendicular_fraction_first_step_closed_form(oracle_lib):
+    """From the seed mu + delta e_i the first step follows the gradient -delta H[:, i], so its
+    fraction is |D^1/2 c - proj| / |D^1/2 c| with c = H[:, i], D = diag(H), projected on
+    D^-1/2 c: equal to the trajectory's first recorded step for every seed."""
+    O = oracle_lib
+    d = 5
+    rng = np.random.Generator(np.random.PCG64(8))
+    P, _ = synth.random_precision(rng, d, 0.2, 2.0)
+    mu = rng.normal(size=d)
+    f = _quad(P, mu)
+    hd = np.diag(P)
+    seeds = O.greendragon_seeds(mu, -hd)
+    for j, x0 in enumerate(seeds):
+        tr = O.lbfgs_user(f, x0, 1e-4, max_iter=1)
+        got = O.perpendicular_step_fraction(tr["X"], tr["G"], hd)[0]
+        c = P[:, j // 2]
+        du = np.sqrt(hd) * c
+        gw = c / np.sqrt(hd)
+        want = np.linalg.norm(du - (du @ gw) / (gw @ gw) * gw) / np.linalg.norm(du)
+        assert abs(got - want) <= 1e-8, (j, got, want)
+
+
+def test_rotated_gaussian_with_zero_offdiagonal_sum_needs_the_trajectories(oracle_lib):
+    """A rotated Gaussian whose off-diagonal entries sum to zero: the probe sees b = 0 (it only
+    measures the uniform part of the correlation), so the probe alone takes the diagonal
+    Laplace and misses log Z; the trajectories see the rotation, the full Hessian is taken and
+    log Z is the closed form."""
+    O = oracle_lib
+    d = 6
+    rng = np.random.Generator(np.random.PCG64(21))
+    P, _ = synth.random_precision(rng, d, 0.3, 1.0)
+    off = P - np.diag(np.diag(P))
+    c = float(off.sum()) / (d * (d - 1))
+    H = P - c * (np.ones((d, d)) - np.eye(d))
+    assert abs(float((H - np.diag(np.diag(H))).sum())) < 1e-12
+    assert np.all(np.linalg.eigvalsh(H) > 0)
+    mu = rng.normal(size=d)
+    f = _quad(H, mu)
+    lo, hi = np.full(d, -10.0), np.full(d, 10.0)
+    exact = _quad_logz(H, lo, hi)
+    probe = O.fd_derivatives(f, mu[None], 1e-4)
+    assert abs(probe["probe_b"][0]) <= 1e-6 * abs(float(np.mean(probe["hdiag"][0])))
+    old = O.user_mode_evidence(f, mu[None], lo, hi, 1e-4, 1e-3)
+    assert abs(old["log_z"] - exact) > 0.05
+    new = O.user_mode_evidence_geo(f, mu[None], lo, hi, 1e-4, 1e-3, 12, 1e-4, 1e-2)
+    assert new["decision"][0] == 1 and new["fperp"][0] > 0.05
+    assert abs(new["log_z"] - exact) <= 1e-6
+
+
+def test_uniform_correlation_detected_by_both_steps(oracle_lib):
+    """H = a I + b 1 1^T (uniformly correlated): the trajectories and the probe both see it."""
+    O = oracle_lib
+    d = 5
+    H = 1.0 * np.eye(d) + 0.3 * np.ones((d, d))
+    mu = np.zeros(d)
+    f = _quad(H, mu)
+    lo, hi = np.full(d, -8.0), np.full(d, 8.0)
+    r = O.user_mode_evidence_geo(f, mu[None], lo, hi, 1e-4, 1e-3, 12, 1e-4, 1e-2)
+    assert r["decision"][0] == 1
+    pr = O.fd_derivatives(f, mu[None], 1e-4)
+    assert abs(pr["probe_b"][0] + 0.3) <= 1e-6  # b of the Hessian of l, -0.3 off the diagonal
+    assert abs(r["log_z"] - _quad_logz(H, lo, hi)) <= 1e-6
