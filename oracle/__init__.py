@@ -1017,7 +1017,7 @@ def trajectory_geometry(f, modes, hdiag, eps, n_iter, m=8, grad_tol=0.0, rel_flo
 
 
 def user_mode_evidence_geo(f, modes, lo, hi, eps, rot_tol, n_iter, eps_axis, eps_rot, m=8,
-                           grad_tol=0.0):
+                           grad_tol=0.0, eps_grad=None):
     """Laplace evidence at given modes with the two-step geometry detection of the algorithm
     "BendTheBow Evidence Calculation": Step 1, the perpendicular step fraction of the
     GreenDragon trajectories (trajectory_geometry); f_perp > eps_rot: rotated; f_perp <=
@@ -1025,14 +1025,16 @@ def user_mode_evidence_geo(f, modes, lo, hi, eps, rot_tol, n_iter, eps_axis, eps
     probe b, decides (|b| > rot_tol |mean H_ii|: rotated).  Rotated modes take the full FD
     Hessian and its Cholesky log det, the others sum log(-H_ii).  decision [n]: 0 axis-aligned
     by the trajectories, 1 rotated by them, 2 axis-aligned by the probe, 3 rotated by it.
-    Returns None if some mode is not a maximum."""
+    The trajectories' gradients take the step eps_grad (default eps).  Returns None if some
+    mode is not a maximum."""
     modes = np.atleast_2d(_f64(modes))
     n, d = modes.shape
     lv = log_volume(lo, hi)
     r = fd_derivatives(f, modes, eps, full=False)
     if np.any(r["hdiag"] >= 0):
         return None
-    fp = trajectory_geometry(f, modes, r["hdiag"], eps, n_iter, m=m, grad_tol=grad_tol)
+    fp = trajectory_geometry(f, modes, r["hdiag"], eps if eps_grad is None else eps_grad,
+                             n_iter, m=m, grad_tol=grad_tol)
     out = dict(logl=r["l"].copy(), logdet=np.zeros(n), fperp=fp,
                decision=np.zeros(n, dtype=np.int32), mode_log_z=np.zeros(n))
     for k in range(n):
