@@ -179,7 +179,7 @@ def recorded_lbfgs(summary="profiles/lbfgs_step_B16384_d1024_m8.md",
     return val
 
 
-def time_lbfgs_step(L, prob, cfg, n_timed=40):
+def time_lbfgs_step(L, prob, cfg, n_timed=40, dtype="f32"):
     """The L-BFGS step (A4) as the mixed bulk runs it (FP32, one workgroup per start) at full
     batch: sb_lbfgs_timed_dev from the BF16 discovery starts, HIP events around each step
     launch on its stream.  Averaged over the launches in which every start either accepted its
@@ -187,13 +187,16 @@ def time_lbfgs_step(L, prob, cfg, n_timed=40):
     start moves (2m + 6) d 4 bytes (the history pairs but the evicted one read, or all m when
     the curvature test keeps the new pair out and it is not written; x and g read at both
     slots; s, y, direction and trial point written), a halving one 3 d 4 bytes (point and
-    direction read, trial point written)."""
+    direction read, trial point written).  dtype "f64": the same step in FP64 (the plain
+    path and the polish), 8-byte elements, from the FP64 discovery starts."""
     import numpy as np
 
-    mdl = L.DeviceModel(prob, low_precision=True)
+    f64 = dtype == "f64"
+    es = 8 if f64 else 4
+    mdl = L.DeviceModel(prob, low_precision=not f64)
     disc = L.sb_discover_dev(mdl, cfg.n_rays, cfg.n_points, cfg.n_starts, cfg.seed,
-                             dtype=L.DTYPE_BF16)
-    X0 = disc["X0"].float()
+                             dtype=L.DTYPE_F64 if f64 else L.DTYPE_BF16)
+    X0 = disc["X0"] if f64 else disc["X0"].float()
     B, d = X0.shape
     r = L.sb_lbfgs_timed_dev(mdl, X0, m=cfg.m, max_iter=n_timed + 8, n_timed=n_timed)
     full, back = r["step_full"].astype(np.int64), r["step_back"].astype(np.int64)
@@ -202,15 +205,18 @@ def time_lbfgs_step(L, prob, cfg, n_timed=40):
     if not sel:
         return None
     us = r["step_us"][sel].astype(np.float64)
-    per_launch = ((2 * cfg.m + 6) * full[sel] + 3 * back[sel]) * d * 4.0
+    per_launch = ((2 * cfg.m + 6) * full[sel] + 3 * back[sel]) * d * float(es)
     alg = float(per_launch.mean())
     avg_us = float(us.mean())
     achieved = alg / avg_us / 1e3  # GB/s
-    rec = recorded_lbfgs() if (d, cfg.m, B) == (1024, 8, 16384) else None
+    rec = recorded_lbfgs() if (d, cfg.m, B) == (1024, 8, 16384) and not f64 else None
+    tpb = 64 if d <= 256 else (128 if d <= 512 else (256 if d <= 1024 else 512))
+    ept = 1 if d <= 64 else (2 if d <= 128 else 4)
     out = dict(bound="hbm", achieved=achieved, peak=PEAK["hbm"], unit="GB/s",
                frac=achieved / PEAK["hbm"],
                traffic=rec["lbfgs_traffic_bytes_per_launch"] if rec else None,
-               kernel="lbfgs_step_kernel<float,256,4> (A4 batched L-BFGS step, FP32 bulk)",
+               kernel=f"lbfgs_step_kernel<{'double' if f64 else 'float'},{tpb},{ept},true> "
+                      f"(A4 batched L-BFGS step, {'FP64' if f64 else 'FP32 bulk'})",
                shape=f"B={B} d={d} m={cfg.m}", algorithmic_bytes=alg, avg_launch_us=avg_us,
                launches=len(sel), launch_us_range=[float(us.min()), float(us.max())],
                timed_steps=[int(i) for i in sel],
@@ -219,6 +225,86 @@ def time_lbfgs_step(L, prob, cfg, n_timed=40):
         out["copy_GBps"] = rec["copy_tbps"] * 1e3
         out["frac_of_copy"] = achieved / out["copy_GBps"]
     return out
+
+
+def lbfgs_step_variants(L):
+    """The L-BFGS step's HBM roofline at c1 (d = 64, 4096 starts), c2 (d = 256, 8192) and c4b
+    (d = 1024, 16384) in FP32 and FP64 (algorithmic bytes (2m + 6) d s per accepting start)."""
+    from paper_2601_19957_amd import synth
+
+    out = {}
+    for name in ("c1", "c2", "c4b"):
+        prob, cfg = synth.make_workload(name)
+        for dt in ("f32", "f64"):
+            r = time_lbfgs_step(L, prob, cfg, n_timed=24, dtype=dt)
+            if r:
+                out[f"{name}_{dt}"] = {k: r[k] for k in ("achieved", "frac", "avg_launch_us",
+                                                         "algorithmic_bytes", "shape", "kernel",
+                                                         "launches")}
+                log(f"L-BFGS step {name} {dt}: {r['avg_launch_us']:.1f} us, "
+                    f"{r['achieved']:.0f} GB/s = {r['frac']:.3f} of HBM peak")
+            torch_empty_cache()
+    return out
+
+
+def torch_empty_cache():
+    import torch
+
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def time_quadform_pairs(L, prob, B, reps=20):
+    """The bulk's screened mixture contraction as it runs near the modes: every start listed
+    for the one component it sits at (the mixture's starts spread over its K components),
+    split BF16, 128 x 128 tiles; average duration by HIP events on its stream, algorithmic
+    FLOPs 2 d^2 + 2 d per listed pair."""
+    import numpy as np
+    import torch
+    from paper_2601_19957_amd import synth
+
+    m = L.DeviceModel(prob, low_precision=True)
+    Xh = synth.points_near_modes(prob, B, 5, scale=0.3)
+    comp = np.arange(B) % prob.K  # the component each start was drawn at
+    counts = np.bincount(comp, minlength=prob.K).astype(np.int32)
+    rows = np.zeros((prob.K, B), dtype=np.int32)
+    for k in range(prob.K):
+        idx = np.flatnonzero(comp == k).astype(np.int32)
+        rows[k, :idx.size] = idx
+    X = torch.as_tensor(Xh, device="cuda").float()
+    g = torch.as_tensor(counts, device="cuda")
+    rw = torch.as_tensor(rows, device="cuda")
+    Y = torch.empty((B, prob.K * prob.d), dtype=torch.float32, device="cuda")
+    qp = torch.empty((B, prob.K, (prob.d + 63) // 64), dtype=torch.float32, device="cuda")
+    mv = m.view(L.DTYPE_F32_SPLIT)
+    import ctypes as C
+    nt = C.c_int32()
+    stream = torch.cuda.current_stream()
+
+    def launch():
+        st = L.lib().sb_quadform_pairs_dev(C.byref(mv), B, X.data_ptr(), g.data_ptr(),
+                                           rw.data_ptr(), B, Y.data_ptr(), qp.data_ptr(),
+                                           C.byref(nt), stream.cuda_stream)
+        L._check(st, "sb_quadform_pairs_dev")
+
+    for _ in range(3):
+        launch()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    avg_s = e0.elapsed_time(e1) * 1e-3 / reps
+    pairs = int(counts.sum())
+    flops = 2.0 * pairs * prob.d * prob.d + 2.0 * pairs * prob.d
+    achieved = flops / avg_s / 1e12
+    return dict(bound="mfma", achieved=achieved, peak=PEAK["bf16"], unit="TFLOP/s",
+                frac=achieved / PEAK["bf16"], executed_mfma_frac=3.0 * achieved / PEAK["bf16"],
+                kernel="quad_gemm_bf16_kernel<3,0,128,128,...> grouped (screened mixture bulk)",
+                pairs_per_launch=pairs, pairs_per_component=counts.tolist(),
+                avg_launch_us=avg_s * 1e6, shape=f"B={B} d={prob.d} K={prob.K}")
 
 
 def calibration_copy() -> int:
@@ -513,6 +599,8 @@ def main() -> int:
                     help="skip the generic-likelihood finite-difference measurement")
     ap.add_argument("--no-chisao", action="store_true",
                     help="skip the ChiSao-moves measurement")
+    ap.add_argument("--no-step-variants", action="store_true",
+                    help="skip the L-BFGS step roofline at c1, c2, c4b in FP32 and FP64")
     ap.add_argument("--modules-only", action="store_true",
                     help="only the preprocessing, eigen-reduction, user-likelihood and ChiSao legs")
     ap.add_argument("--kernel-only", action="store_true",
@@ -572,9 +660,14 @@ def main() -> int:
                        executed_mfma_frac=3.0 * achieved / PEAK["bf16"],
                        fp32_equivalent_frac=achieved / PEAK["fp32"],
                        fp32_kernel_us=kt32_s * 1e6)
+    log("timing the screened mixture contraction (listed start-component pairs)")
+    pairs = time_quadform_pairs(L, prob_big, cfg_big.n_starts) if prob_big.K > 1 else None
+    if pairs:
+        log(f"pairs contraction: {pairs['avg_launch_us']:.1f} us, "
+            f"{pairs['achieved']:.1f} TFLOP/s = {pairs['frac']:.3f} of BF16 peak")
     if args.kernel_only:
         print(json.dumps(dict(kernel_only=True, roofline=roofline,
-                              contraction_roofline=contraction,
+                              contraction_roofline=contraction, pairs_roofline=pairs,
                               copy_calibration_bytes=calibration_copy())), flush=True)
         return 0
 
@@ -709,6 +802,9 @@ def main() -> int:
     a3 = None
     if not args.no_a3:
         a3 = a3_variants(L)
+    steps_v = None
+    if not args.no_step_variants:
+        steps_v = lbfgs_step_variants(L)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -755,6 +851,8 @@ def main() -> int:
         "max_mode_dist_vs_oracle": dmodes,
         "uneven_batch": batch,
         "a3_variants": a3,
+        "lbfgs_step_variants": steps_v,
+        "pairs_contraction_roofline": pairs,
         "precheck": pre,
         "eig_reduce": red,
         "user_fd": ufd,

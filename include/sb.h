@@ -162,6 +162,70 @@ size_t sb_evidence_workspace_bytes(const sb_loglik *ll, const sb_config *cfg);
 int32_t sb_evidence_dev(const sb_loglik *ll_dev, const sb_box *box_dev, const sb_config *cfg,
                         sb_result *res, void *workspace, size_t ws_bytes, void *stream);
 
+/* The whole path with the ChiSao oscillation cycle as its convergence and,
+ * optionally, the refinement pass of the two-pass ray sampling (section
+ * "ChiSao Exploration": the oscillation cycle and CarryTiger's algorithm
+ * summary; section "Two-Pass Sampling").  FP64 throughout (cfg->precision
+ * must be SB_PREC_FP64, else SB_E_UNSUPPORTED).
+ *
+ * Discovery: the rays and coarse pass of sb_discover_dev; with n_ref > 0, per
+ * ray the cells [t_j - h/2, t_j + h/2] (h = 1/n_points) of the coarse scores
+ * above the ray's maximum minus ref_delta carry the density exp(l_j - l_max)
+ * and n_ref more points sit at its quantiles (i + 1/2)/n_ref; each ray keeps
+ * its best sample over both passes (ties: coarse first, lower index), and the
+ * n_starts best rays seed the cycle.
+ * Cycle, n_osc oscillations over the n_starts sample slots:
+ *  1. convergence: L-BFGS (fresh history, memory cfg->m) on every active slot
+ *     for at most n_conv accepted steps;
+ *  2. stick detection (sb_chisao_stick_dev over the active slots, stick_tol);
+ *  3. L-infinity leader dedup (radius cfg->dedup_tol_pre, default 0.25) of the
+ *     stuck slots: a stuck slot in another's cluster is lost (emptied);
+ *  4. not on the last oscillation, when slots were lost: with >= 5 active
+ *     slots that did not converge, Repulse Monkey refills lost slot j with the
+ *     best of n_reseed_pts samples on the ray (sb_chisao_reseed_dev) from
+ *     unconverged slot j mod n_unconverged in a random direction; with fewer,
+ *     Golden Rooster refills the lost slots round-robin over the distinct
+ *     stuck peaks (l descending), each peak's slots taking QR-orthonormal
+ *     directions (sb_chisao_orthonormal_dev, chunks of at most d rows) for rays
+ *     from the peak; else the slots stay empty.  Golden Rooster switches off
+ *     for good when the oscillation after one in which it refilled ends with no
+ *     more distinct converged peaks than the one before;
+ *  5. not on the last oscillation: the free slots (active, not stuck) take
+ *     n_cloud Hands Like Clouds steps of n_smooth perturbations at scale sigma
+ *     and n_anti anti-convergence steps (sb_chisao_explore_dev).
+ * The last phase's active slots with a finite l then go through the tail of
+ * sb_evidence_dev (pre-dedup, Newton polish, Hessian, Cholesky, filters,
+ * dedup, combine).  Draws are Philox4x32-10 normals (cosine branch of
+ * Box-Muller on the uniforms of two streams) keyed by cfg->seed, counter (slot,
+ * block, 16 + 8 k + purpose, 0) on oscillation k, purpose 0 Repulse Monkey
+ * directions, 2 Golden Rooster draws, 4 Hands Like Clouds perturbations
+ * (index (c n_smooth + q) d + i).  With n_osc = 1 and n_ref = 0 the result is
+ * that of sb_evidence_dev in FP64.  res->iterations counts the L-BFGS batch
+ * steps of all phases, res->n_grad_evals also the moves' evaluations.  The
+ * per-oscillation bookkeeping uses O(n_starts) bytes of host memory.
+ * Workspace >= sb_evidence_chisao_workspace_bytes. */
+typedef struct {
+  int32_t n_osc;        /* oscillations, >= 1 (the paper's default is 3) */
+  int32_t n_conv;       /* L-BFGS steps per convergence phase (<= 0: max_iter) */
+  double stick_tol;     /* gradient L-infinity bound of stick detection (<= 0: 1e-6) */
+  int32_t n_reseed_pts; /* samples along a reseeding ray (<= 0: 32) */
+  int32_t n_cloud;      /* Hands Like Clouds steps (>= 0) */
+  int32_t n_smooth;     /* perturbations per smoothed gradient (<= 0: 4) */
+  double sigma;         /* smoothing scale; <= 0: half the median over coordinates of
+                           the population standard deviation of the free slots */
+  double alpha_cloud;   /* ascent step (<= 0: 0.01) */
+  int32_t n_anti;       /* anti-convergence steps (>= 0) */
+  double alpha_anti;    /* descent step (<= 0: 0.01) */
+  double momentum;      /* in [0, 1) */
+  int32_t n_ref;        /* refinement-pass points per ray (0: coarse pass only) */
+  double ref_delta;     /* active region: l > l_max - ref_delta (<= 0: 10) */
+} sb_chisao_config;
+size_t sb_evidence_chisao_workspace_bytes(const sb_loglik *ll, const sb_config *cfg,
+                                          const sb_chisao_config *cc);
+int32_t sb_evidence_chisao_dev(const sb_loglik *ll_dev, const sb_box *box_dev,
+                               const sb_config *cfg, const sb_chisao_config *cc,
+                               sb_result *res, void *workspace, size_t ws_bytes, void *stream);
+
 /* Execution context for repeated whole-path calls on one device (the
  * batching form: an iteration block of the L-BFGS bulk, 8 steps of step,
  * compaction, contraction and epilogue launches, replayed as one HIP graph).
@@ -229,6 +293,17 @@ int32_t sb_logl_grad_dev(const sb_model_dev *m, int64_t B, const void *X, void *
  * must hold B*K*ceil(d/64) values.  For measurement and testing. */
 int32_t sb_quadform_dev(const sb_model_dev *m, int64_t B, const void *X, int32_t dtype, void *Y,
                         void *qpart, int32_t *n_tiles, void *stream);
+
+/* The contraction of listed (row, component) pairs, as the bulk's screened
+ * mixture path runs it (dtype F32_SPLIT, 128 x 128 tiles): component k
+ * multiplies the gcnt[k] rows listed at rows + k * cap of X [B][d] (FP32),
+ * writing Y[r][k*d + n] and qpart[r][k][t] for those pairs only (Y, qpart as
+ * for sb_quadform_dev; other entries untouched).  gcnt [K], rows [K][cap]
+ * device int32, each row < B.  Gaussian mixtures only.  For measurement and
+ * testing. */
+int32_t sb_quadform_pairs_dev(const sb_model_dev *m, int64_t B, const void *X,
+                              const int32_t *gcnt, const int32_t *rows, int64_t cap, void *Y,
+                              void *qpart, int32_t *n_tiles, void *stream);
 
 /* Split copy for the F32_SPLIT contraction: hi[i] = bf16(fp32(x[i])) and,
  * when lo != NULL, lo[i] = bf16(x[i] - hi[i]) (round to nearest even; uint16
@@ -338,10 +413,11 @@ int32_t sb_chisao_reseed_dev(const sb_model_dev *m, const double *lo, const doub
  * the near-exhaustion refill from converged peaks uses directions made
  * orthonormal by QR).  For each of C peaks the n rows of G [C][n][d] (device
  * FP64, in place; Gaussian draws chosen by the caller) become the rows of Q in
- * G_c^T = Q R with R's diagonal positive (modified Gram-Schmidt, one workgroup
- * per peak; n^2 d multiply-adds per peak).  A row whose norm after removing
- * its projections on the earlier rows is at most 1e-12 of its own norm (it
- * depends on them), or not finite, becomes NaN, and so does every later row.  SB_E_INVAL
+ * G_c^T = Q R with R's diagonal positive (modified Gram-Schmidt with a second
+ * projection pass, one workgroup per peak; 2 n^2 d multiply-adds per peak).  A row whose norm after removing
+ * its projections on the earlier rows is at most 8 n eps (eps = 2^-52) of its
+ * own norm (it depends on them), or not finite, becomes NaN, and so does every
+ * later row.  SB_E_INVAL
  * unless C >= 0 and 1 <= n <= d; G may be NULL when C = 0. */
 int32_t sb_chisao_orthonormal_dev(int32_t C, int32_t n, int32_t d, double *G, void *stream);
 
@@ -416,8 +492,12 @@ int32_t sb_user_fd_dev(const sb_user_fn *fn, int64_t B, int32_t d, const double 
  * argmax, top n_starts rays), batched L-BFGS of sb_lbfgs_dev on central
  * finite-difference gradients with step eps (2d + 3 user evaluations per
  * row), leader de-duplication of the starts that converged inside the box,
- * and sb_user_mode_evidence_dev with step eps_hess at the representatives
- * (second differences divide rounding by eps^2, so their step is larger).  cfg as for
+ * and the Laplace evidence of sb_user_mode_evidence_geo_dev at the
+ * representatives: both steps of the geometry detection with the default
+ * sb_geometry_config (its seeds on FD gradients of step eps with cfg's m
+ * and grad_tol, the probe threshold rot_tol), the curvature with step
+ * eps_hess (second differences divide rounding by eps^2, so their step is
+ * larger).  cfg as for
  * sb_evidence (precision ignored); defaults here: grad_tol 1e-6 (FD
  * gradients carry rounding of order eps_mach |l| / eps), dedup_tol
  * 1e-4 max_i(hi_i - lo_i).  lo, hi [d] are device arrays.  Fills res as
@@ -437,6 +517,57 @@ int32_t sb_user_mode_evidence_dev(const sb_user_fn *fn, int32_t n, int32_t d,
                                   double *logdet, int32_t *full_used, int32_t *order,
                                   double *mode_log_z, double *log_z, void *workspace,
                                   size_t ws_bytes, void *stream);
+
+/* Geometry detection in two steps (section "Automatic Geometry Detection",
+ * the algorithm "BendTheBow Evidence Calculation" and the appendix "Rotation
+ * Detection").  Step 1, the TrajectoryBank: GreenDragon's seeds of each mode,
+ * theta* +- 0.9 w_i e_i (2d per mode; w_i = 1/sqrt(-H_ii) from the FD diagonal
+ * at the mode; seed 2i is +, 2i + 1 is -), run batched L-BFGS on central-FD
+ * gradients (step eps, memory m, n_iter steps or grad_tol); for every
+ * accepted step of a seed's trajectory, in coordinates whitened by
+ * sqrt(-H_ii) (du = sqrt(h) dtheta, gradient g / sqrt(h) at the step's start),
+ * f_perp = |du perpendicular to the gradient| / |du|; a step counts while the
+ * whitened gradient at its start is at least 1e-3 of the seed's first.  A
+ * mode's f_perp is the largest over its seeds' counted steps (NaN if none).
+ * f_perp > eps_rot: rotated; f_perp <= eps_axis: axis-aligned; otherwise, or
+ * NaN, Step 2: the probe b of sb_user_fd_dev decides (|b| > rot_tol |mean
+ * H_ii|: rotated).  Rotated modes take the full FD Hessian and its Cholesky
+ * log det, the others sum log(-H_ii). */
+typedef struct {
+  int32_t n_iter;  /* seeds' L-BFGS steps (<= 0: max(10, 3 ceil(log2 d))) */
+  int32_t m;       /* their memory (<= 0: 8; at most 32) */
+  double grad_tol; /* their stopping gradient (<= 0: 1e-6) */
+  double eps_axis; /* f_perp at most this: axis-aligned (<= 0: 1e-4) */
+  double eps_rot;  /* f_perp above this: rotated (<= 0: 1e-2) */
+  double rot_tol;  /* Step 2 threshold (>= 0) */
+} sb_geometry_config;
+/* Step 1 alone for n modes [n][d] with the FD diagonal hdiag [n][d] (device,
+ * negative at a maximum): fperp [n] (device).  Xbank, Gbank (device, both
+ * or neither; [n][2d][n_iter + 1][d]) get each seed's start and accepted
+ * points and the gradients of l there, bank_len [n][2d] (device, nullable)
+ * the number recorded.  Workspace >= sb_user_trajectories_workspace_bytes. */
+size_t sb_user_trajectories_workspace_bytes(int32_t n, int32_t d, int32_t m);
+int32_t sb_user_trajectories_dev(const sb_user_fn *fn, int32_t n, int32_t d, const double *modes,
+                                 const double *params, const double *hdiag, double eps,
+                                 int32_t n_iter, int32_t m, double grad_tol, double *fperp,
+                                 double *Xbank, double *Gbank, int32_t *bank_len,
+                                 void *workspace, size_t ws_bytes, void *stream);
+/* sb_user_mode_evidence_dev with both steps: FD gradients of the
+ * trajectories with step eps_grad, the diagonal, probe and full Hessian with
+ * eps_hess; fperp [n] (device, nullable) and decision [n] (host, nullable: 0
+ * axis-aligned by the trajectories, 1 rotated by them, 2 axis-aligned by the
+ * probe, 3 rotated by it).  SB_E_NOTPD if some H_ii >= 0 or a full -H is not
+ * positive definite.  Workspace >= sb_user_mode_evidence_geo_workspace_bytes. */
+size_t sb_user_mode_evidence_geo_workspace_bytes(int32_t n, int32_t d,
+                                                 const sb_geometry_config *gc);
+int32_t sb_user_mode_evidence_geo_dev(const sb_user_fn *fn, int32_t n, int32_t d,
+                                      const double *modes, const double *params,
+                                      const double *lo, const double *hi, double eps_grad,
+                                      double eps_hess, const sb_geometry_config *gc,
+                                      double *logl, double *logdet, double *fperp,
+                                      int32_t *decision, int32_t *order, double *mode_log_z,
+                                      double *log_z, void *workspace, size_t ws_bytes,
+                                      void *stream);
 
 /* L-BFGS two-loop direction (appendix "L-BFGS Optimization") for B
  * independent histories: S, Y [B][m][d] in logical order (oldest first),

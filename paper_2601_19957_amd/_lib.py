@@ -30,8 +30,11 @@ ST_CONVERGED, ST_STALLED, ST_MAXITER, ST_DEAD = 1, 2, 3, 4
 EXPORTS = [
     "sb_evidence", "sb_evidence_batch", "sb_evidence_workspace_bytes", "sb_evidence_dev",
     "sb_exec_create", "sb_exec_destroy", "sb_exec_stats", "sb_evidence_exec_dev",
+    "sb_evidence_chisao_workspace_bytes", "sb_evidence_chisao_dev",
+    "sb_user_trajectories_workspace_bytes", "sb_user_trajectories_dev",
+    "sb_user_mode_evidence_geo_workspace_bytes", "sb_user_mode_evidence_geo_dev",
     "sb_prep_workspace_bytes", "sb_prep_dev", "sb_logl_grad_workspace_bytes", "sb_logl_grad_dev",
-    "sb_quadform_dev", "sb_split_bf16_dev", "sb_hvp_workspace_bytes", "sb_hvp_dev", "sb_discover_workspace_bytes", "sb_discover_dev",
+    "sb_quadform_dev", "sb_quadform_pairs_dev", "sb_split_bf16_dev", "sb_hvp_workspace_bytes", "sb_hvp_dev", "sb_discover_workspace_bytes", "sb_discover_dev",
     "sb_lbfgs_direction_dev", "sb_lbfgs_workspace_bytes", "sb_lbfgs_dev",
     "sb_lbfgs_timed_dev", "sb_precheck_workspace_bytes", "sb_precheck_dev",
     "sb_eig_reduce_workspace_bytes", "sb_eig_reduce_dev", "sb_chisao_stick_dev",
@@ -45,6 +48,43 @@ EXPORTS = [
     "sb_cholesky_logdet_dev", "sb_cholesky_solve_dev", "sb_combine_dev", "sb_status_string",
     "sb_last_error", "sb_abi_version",
 ]
+
+
+class sb_geometry_config(C.Structure):
+    _fields_ = [("n_iter", C.c_int32), ("m", C.c_int32), ("grad_tol", C.c_double),
+                ("eps_axis", C.c_double), ("eps_rot", C.c_double), ("rot_tol", C.c_double)]
+
+
+class sb_chisao_config(C.Structure):
+    _fields_ = [("n_osc", C.c_int32), ("n_conv", C.c_int32), ("stick_tol", C.c_double),
+                ("n_reseed_pts", C.c_int32), ("n_cloud", C.c_int32), ("n_smooth", C.c_int32),
+                ("sigma", C.c_double), ("alpha_cloud", C.c_double), ("n_anti", C.c_int32),
+                ("alpha_anti", C.c_double), ("momentum", C.c_double), ("n_ref", C.c_int32),
+                ("ref_delta", C.c_double)]
+
+
+@dataclass
+class ChiSaoConfig:
+    """Parameters of the ChiSao cycle and the refinement pass (sb_chisao_config)."""
+    n_osc: int = 3
+    n_conv: int = 0
+    stick_tol: float = 1e-6
+    n_reseed_pts: int = 32
+    n_cloud: int = 1
+    n_smooth: int = 4
+    sigma: float = 0.0
+    alpha_cloud: float = 0.01
+    n_anti: int = 8
+    alpha_anti: float = 0.01
+    momentum: float = 0.9
+    n_ref: int = 0
+    ref_delta: float = 10.0
+
+    def c(self) -> sb_chisao_config:
+        return sb_chisao_config(self.n_osc, self.n_conv, self.stick_tol, self.n_reseed_pts,
+                                self.n_cloud, self.n_smooth, self.sigma, self.alpha_cloud,
+                                self.n_anti, self.alpha_anti, self.momentum, self.n_ref,
+                                self.ref_delta)
 
 
 class SbError(RuntimeError):
@@ -113,11 +153,20 @@ def lib():
             "sb_exec_destroy": (None, [vp]),
             "sb_exec_stats": (i32, [vp, vp]),
             "sb_evidence_exec_dev": (i32, [vp, vp, vp, vp, vp, vp, sz, vp]),
+            "sb_evidence_chisao_workspace_bytes": (sz, [vp, vp, vp]),
+            "sb_evidence_chisao_dev": (i32, [vp, vp, vp, vp, vp, vp, sz, vp]),
+            "sb_user_trajectories_workspace_bytes": (sz, [i32, i32, i32]),
+            "sb_user_trajectories_dev": (i32, [vp, i32, i32, vp, vp, vp, f64, i32, i32, f64, vp,
+                                               vp, vp, vp, vp, sz, vp]),
+            "sb_user_mode_evidence_geo_workspace_bytes": (sz, [i32, i32, vp]),
+            "sb_user_mode_evidence_geo_dev": (i32, [vp, i32, i32, vp, vp, vp, vp, f64, f64, vp,
+                                                    vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
             "sb_prep_workspace_bytes": (sz, [i32, i32]),
             "sb_prep_dev": (i32, [vp, vp, vp, vp, vp, vp, vp, sz, vp]),
             "sb_logl_grad_workspace_bytes": (sz, [i32, i32, i64, i32]),
             "sb_logl_grad_dev": (i32, [vp, i64, vp, vp, vp, i32, vp, sz, vp]),
             "sb_quadform_dev": (i32, [vp, i64, vp, i32, vp, vp, vp, vp]),
+            "sb_quadform_pairs_dev": (i32, [vp, i64, vp, vp, vp, i64, vp, vp, vp, vp]),
             "sb_split_bf16_dev": (i32, [i64, vp, vp, vp, vp]),
             "sb_hvp_workspace_bytes": (sz, [i32, i32, i64]),
             "sb_hvp_dev": (i32, [vp, i64, vp, vp, vp, vp, sz, vp]),
@@ -704,6 +753,60 @@ class UserLogL:
         return dict(log_z=float(lz.cpu()[0]), mode_log_z=mlz, order=order, logl=l, logdet=ld,
                     full=list(full))
 
+    def trajectories(self, modes, hdiag, eps: float, n_iter: int, m: int = 8,
+                     grad_tol: float = 1e-6, params=None, bank: bool = False):
+        """Step 1 of the geometry detection: the perpendicular step fraction per mode of the
+        trajectories of GreenDragon's seeds (and, with bank, the recorded positions, gradients
+        and lengths)."""
+        import torch
+
+        modes = modes.contiguous().to(torch.float64)
+        n, d = modes.shape
+        f64 = dict(dtype=torch.float64, device=modes.device)
+        fp = torch.empty(n, **f64)
+        Xb = Gb = bl = None
+        if bank:
+            Xb = torch.empty((n, 2 * d, n_iter + 1, d), **f64)
+            Gb = torch.empty_like(Xb)
+            bl = torch.zeros((n, 2 * d), dtype=torch.int32, device=modes.device)
+        ws = _ws(lib().sb_user_trajectories_workspace_bytes(n, d, m), modes.device)
+        st = lib().sb_user_trajectories_dev(self.h, n, d, modes.data_ptr(), _ptr(params),
+                                            hdiag.contiguous().data_ptr(), eps, n_iter, m,
+                                            grad_tol, fp.data_ptr(), _ptr(Xb), _ptr(Gb),
+                                            _ptr(bl), ws.data_ptr(), ws.numel(), _stream())
+        _check(st, "sb_user_trajectories_dev")
+        return dict(fperp=fp, X=Xb, G=Gb, length=bl)
+
+    def mode_evidence_geo(self, modes, lo, hi, eps_grad: float, eps_hess: float,
+                          rot_tol: float, n_iter: int = 0, m: int = 0, grad_tol: float = 0.0,
+                          eps_axis: float = 0.0, eps_rot: float = 0.0, params=None):
+        """Laplace evidence at the given modes with both steps of the geometry detection."""
+        import torch
+
+        modes = modes.contiguous().to(torch.float64)
+        n, d = modes.shape
+        f64 = dict(dtype=torch.float64, device=modes.device)
+        l = torch.empty(n, **f64)
+        ld = torch.empty(n, **f64)
+        fp = torch.empty(n, **f64)
+        order = torch.empty(n, dtype=torch.int32, device=modes.device)
+        mlz = torch.empty(n, **f64)
+        lz = torch.empty(1, **f64)
+        dec = (C.c_int32 * n)()
+        gc = sb_geometry_config(n_iter, m, grad_tol, eps_axis, eps_rot, rot_tol)
+        ws = _ws(lib().sb_user_mode_evidence_geo_workspace_bytes(n, d, C.byref(gc)),
+                 modes.device)
+        st = lib().sb_user_mode_evidence_geo_dev(self.h, n, d, modes.data_ptr(), _ptr(params),
+                                                 lo.data_ptr(), hi.data_ptr(), eps_grad,
+                                                 eps_hess, C.byref(gc), l.data_ptr(),
+                                                 ld.data_ptr(), fp.data_ptr(), dec,
+                                                 order.data_ptr(), mlz.data_ptr(),
+                                                 lz.data_ptr(), ws.data_ptr(), ws.numel(),
+                                                 _stream())
+        _check(st, "sb_user_mode_evidence_geo_dev")
+        return dict(log_z=float(lz.cpu()[0]), mode_log_z=mlz, order=order, logl=l, logdet=ld,
+                    fperp=fp, decision=list(dec))
+
     def evidence(self, d: int, lo, hi, cfg, eps: float, eps_hess: float, rot_tol: float,
                  params=None):
         """The evidence path on this likelihood (discovery, FD L-BFGS, dedup, Laplace with FD
@@ -824,10 +927,11 @@ class EvidenceRunner:
     directly); with one (exec=True: a context of its own, or an ExecContext) it calls
     sb_evidence_exec_dev (iteration blocks as the context's HIP graphs)."""
 
-    def __init__(self, prob, cfg, device="cuda", exec=None):
+    def __init__(self, prob, cfg, device="cuda", exec=None, chisao: "ChiSaoConfig" = None):
         import torch
 
         self.prob, self.cfg = prob, cfg
+        self.chisao = chisao.c() if chisao is not None else None
         dev = torch.device(device)
         if exec is True:
             with torch.cuda.device(dev):
@@ -843,14 +947,23 @@ class EvidenceRunner:
                             float(prob.logl_offset))
         self.box = sb_box(self.lo.data_ptr(), self.hi.data_ptr())
         self.c = make_config(cfg)
-        nb = lib().sb_evidence_workspace_bytes(C.byref(self.ll), C.byref(self.c))
+        if self.chisao is not None:
+            nb = lib().sb_evidence_chisao_workspace_bytes(C.byref(self.ll), C.byref(self.c),
+                                                          C.byref(self.chisao))
+        else:
+            nb = lib().sb_evidence_workspace_bytes(C.byref(self.ll), C.byref(self.c))
         if nb == 0:
             raise SbError(E_INVAL, "sb_evidence_workspace_bytes")
         self.ws = torch.empty(int(nb), dtype=torch.uint8, device=dev)
 
     def run(self, stream=None) -> EvidenceResult:
         r, arrs = _new_result(self.cfg.max_modes, self.prob.d)
-        if self.exec is not None:
+        if self.chisao is not None:
+            st = lib().sb_evidence_chisao_dev(C.byref(self.ll), C.byref(self.box),
+                                              C.byref(self.c), C.byref(self.chisao), C.byref(r),
+                                              self.ws.data_ptr(), self.ws.numel(),
+                                              _stream(stream))
+        elif self.exec is not None:
             st = lib().sb_evidence_exec_dev(self.exec.handle, C.byref(self.ll),
                                             C.byref(self.box), C.byref(self.c), C.byref(r),
                                             self.ws.data_ptr(), self.ws.numel(),

@@ -253,6 +253,66 @@ int32_t sb_evidence_dev(const sb_loglik *ll, const sb_box *box, const sb_config 
   return evidence_dev(ll, box, cfg, res, workspace, ws_bytes, stream, nullptr);
 }
 
+static int validate_chisao(const sb_config *cfg, const sb_chisao_config *cc) {
+  if (!cc) return fail(SB_E_INVAL, "ChiSao configuration is NULL");
+  if (cfg->precision != SB_PREC_FP64)
+    return fail(SB_E_UNSUPPORTED, "the ChiSao cycle runs in FP64 (precision must be FP64)");
+  if (cc->n_osc < 1 || cc->n_osc > 64) return fail(SB_E_INVAL, "n_osc must be in [1, 64]");
+  if (cc->n_cloud < 0 || cc->n_anti < 0) return fail(SB_E_INVAL, "negative step counts");
+  if (cc->n_smooth > 256 || cc->n_cloud > 256 || cc->n_anti > 100000)
+    return fail(SB_E_INVAL, "step counts too large");
+  if (!(cc->momentum >= 0.0 && cc->momentum < 1.0))
+    return fail(SB_E_INVAL, "momentum must be in [0, 1)");
+  if (!std::isfinite(cc->sigma) || !std::isfinite(cc->alpha_cloud) ||
+      !std::isfinite(cc->alpha_anti) || !std::isfinite(cc->stick_tol) ||
+      !std::isfinite(cc->ref_delta))
+    return fail(SB_E_INVAL, "non-finite ChiSao parameter");
+  if (cc->n_ref < 0 || cc->n_ref > 4096) return fail(SB_E_INVAL, "n_ref must be in [0, 4096]");
+  if ((int64_t)cfg->n_rays * cc->n_ref > (int64_t)1 << 28)
+    return fail(SB_E_INVAL, "n_rays * n_ref too large");
+  if (cc->n_reseed_pts > 65536) return fail(SB_E_INVAL, "n_reseed_pts too large");
+  return SB_OK;
+}
+
+size_t sb_evidence_chisao_workspace_bytes(const sb_loglik *ll, const sb_config *cfg,
+                                          const sb_chisao_config *cc) {
+  if (validate_shape(ll) || validate_cfg(ll, cfg) || validate_chisao(cfg, cc)) return 0;
+  return evidence_ws_bytes(ll, cfg, cc);
+}
+
+int32_t sb_evidence_chisao_dev(const sb_loglik *ll, const sb_box *box, const sb_config *cfg,
+                               const sb_chisao_config *cc, sb_result *res, void *workspace,
+                               size_t ws_bytes, void *stream) {
+  int st = validate_shape(ll);
+  if (!st) st = validate_cfg(ll, cfg);
+  if (!st) st = validate_chisao(cfg, cc);
+  if (!st && (!box || !box->lo || !box->hi)) st = fail(SB_E_INVAL, "box is NULL");
+  if (!st && !res) st = fail(SB_E_INVAL, "result is NULL");
+  if (st) {
+    if (res) res->log_z = NAN;
+    return st;
+  }
+  if ((st = device_status())) {
+    res->log_z = NAN;
+    return st;
+  }
+  DevProblem P;
+  P.family = ll->family;
+  P.norm = ll->norm;
+  P.d = ll->d;
+  P.K = ll->K;
+  P.log_w = ll->log_w;
+  P.mu = ll->mu;
+  P.prec = ll->prec;
+  P.lo = box->lo;
+  P.hi = box->hi;
+  P.nu = ll->nu;
+  P.c = ll->logl_offset;
+  st = run_evidence(P, cfg, res, workspace, ws_bytes, (hipStream_t)stream, nullptr, cc);
+  if (st && st != SB_E_NOMODE && st != SB_E_CAPACITY) res->log_z = NAN;
+  return st;
+}
+
 int32_t sb_exec_create(sb_exec **out) {
   if (!out) return fail(SB_E_INVAL, "out is NULL");
   *out = nullptr;
@@ -479,22 +539,19 @@ size_t sb_logl_grad_workspace_bytes(int32_t d, int32_t K, int64_t B, int32_t dty
   return eval_bytes(dtype == SB_DTYPE_F64 ? SB_DTYPE_F64 : SB_DTYPE_F32, d, K, B, false);
 }
 
-int32_t sb_logl_grad_dev(const sb_model_dev *mdl, int64_t B, const void *X, void *logl,
-                         void *grad, int32_t dtype, void *workspace, size_t ws_bytes,
-                         void *stream) {
-  int st = validate_model(mdl);
-  if (st) return st;
-  if (B < 0 || (B > 0 && (!X || !logl))) return fail(SB_E_INVAL, "bad B / X / logl");
-  if ((st = check_gemm_dtype(mdl, dtype))) return st;
-  if (B == 0) return SB_OK;
-  if (!workspace || ws_bytes < sb_logl_grad_workspace_bytes(mdl->d, mdl->K, B, dtype))
-    return fail(SB_E_NOMEM, "workspace too small");
-  if ((st = device_status())) return st;
+// The contraction and epilogue of sb_logl_grad_dev with Y and the q partials
+// carved from `scratch`; tune: time the tile candidates on this launch's
+// operands (first call per shape), else the cached choice or the heuristic.
+static int32_t logl_grad_core(const sb_model_dev *mdl, int64_t B, const void *X, void *logl,
+                              void *grad, int32_t dtype, void *scratch, size_t scratch_bytes,
+                              bool tune, void *stream) {
+  int st;
   Model m = model_for(mdl, dtype);
   const size_t es = dtype == SB_DTYPE_F64 ? 8 : 4;
-  Arena ar(workspace, ws_bytes);
+  Arena ar(scratch, scratch_bytes);
   void *Y = ar.take<char>(es * (size_t)B * m.K * m.d);
   void *qp = ar.take<char>(es * (size_t)B * m.K * ceil_div(m.d, 64));
+  if (!ar.ok() || !Y || !qp) return fail(SB_E_NOMEM, "scratch too small");
   ASrc a;
   a.kind = 0;
   a.X = X;
@@ -508,7 +565,7 @@ int32_t sb_logl_grad_dev(const sb_model_dev *mdl, int64_t B, const void *X, void
   o.yneg = direct;
   o.qpart = qp;
   const TuneProbe pr{a, o};
-  TileCfg t = autotune_tiles(dtype, m, B, (hipStream_t)stream, &pr);
+  TileCfg t = autotune_tiles(dtype, m, B, (hipStream_t)stream, tune ? &pr : nullptr, false);
   if ((st = launch_quad_gemm(dtype, m, a, B, nullptr, o, t, (hipStream_t)stream))) return st;
   FinishArgs f;
   f.M = B;
@@ -520,6 +577,20 @@ int32_t sb_logl_grad_dev(const sb_model_dev *mdl, int64_t B, const void *X, void
   f.grad = direct ? nullptr : grad;
   f.ldg = m.d;
   return launch_finish(dtype, m, f, (hipStream_t)stream);
+}
+
+int32_t sb_logl_grad_dev(const sb_model_dev *mdl, int64_t B, const void *X, void *logl,
+                         void *grad, int32_t dtype, void *workspace, size_t ws_bytes,
+                         void *stream) {
+  int st = validate_model(mdl);
+  if (st) return st;
+  if (B < 0 || (B > 0 && (!X || !logl))) return fail(SB_E_INVAL, "bad B / X / logl");
+  if ((st = check_gemm_dtype(mdl, dtype))) return st;
+  if (B == 0) return SB_OK;
+  if (!workspace || ws_bytes < sb_logl_grad_workspace_bytes(mdl->d, mdl->K, B, dtype))
+    return fail(SB_E_NOMEM, "workspace too small");
+  if ((st = device_status())) return st;
+  return logl_grad_core(mdl, B, X, logl, grad, dtype, workspace, ws_bytes, true, stream);
 }
 
 int32_t sb_quadform_dev(const sb_model_dev *mdl, int64_t B, const void *X, int32_t dtype, void *Y,
@@ -541,6 +612,37 @@ int32_t sb_quadform_dev(const sb_model_dev *mdl, int64_t B, const void *X, int32
   const TuneProbe pr{a, o};
   TileCfg t = autotune_tiles(dtype, m, B, (hipStream_t)stream, &pr);
   st = launch_quad_gemm(dtype, m, a, B, nullptr, o, t, (hipStream_t)stream);
+  if (n_tiles) *n_tiles = o.ntn;
+  return st;
+}
+
+int32_t sb_quadform_pairs_dev(const sb_model_dev *mdl, int64_t B, const void *X,
+                              const int32_t *gcnt, const int32_t *rows, int64_t cap, void *Y,
+                              void *qpart, int32_t *n_tiles, void *stream) {
+  int st = validate_model(mdl);
+  if (st) return st;
+  if (B < 0 || cap < 0 || (cap > 0 && (!X || !Y || !qpart || !gcnt || !rows)))
+    return fail(SB_E_INVAL, "bad B / cap / arrays");
+  if ((st = check_gemm_dtype(mdl, SB_DTYPE_F32_SPLIT))) return st;
+  if (mdl->family != SB_FAMILY_GAUSS_MIX)
+    return fail(SB_E_UNSUPPORTED, "pairs: Gaussian mixtures only");
+  if ((st = device_status())) return st;
+  if (cap == 0) return SB_OK;
+  Model m = model_for(mdl, SB_DTYPE_F32_SPLIT);
+  ASrc a;
+  a.kind = 0;
+  a.X = X;
+  a.ldx = m.d;
+  a.rowmap = rows;
+  a.rows = B;
+  QuadOut o;
+  o.Y = Y;
+  o.ldy = (int64_t)m.K * m.d;
+  o.ymap = rows;
+  o.gcnt = gcnt;
+  o.gcap = cap;
+  o.qpart = qpart;
+  st = launch_quad_gemm(DT_F32S, m, a, cap, nullptr, o, TileCfg(), (hipStream_t)stream);
   if (n_tiles) *n_tiles = o.ntn;
   return st;
 }

@@ -183,34 +183,67 @@ __global__ __launch_bounds__(256) void reseed_pick_kernel(int64_t B, int d, int 
   if (lane == 0 && best_l) best_l[b] = jb >= 0 ? lb : (double)NAN;
 }
 
-// Golden Rooster's orthonormal directions: modified Gram-Schmidt in FP64, one
-// workgroup per peak, rows of G [C][n][d] in place.  Row k loses its
-// projection on each earlier (already normalised) row in turn, then is
+// Golden Rooster's orthonormal directions: modified Gram-Schmidt with
+// re-orthogonalisation in FP64, one workgroup per peak, rows of G [C][n][d] in
+// place.  Row k loses its projection on each earlier (already normalised) row
+// in turn, twice, then is
 // divided by its norm, so the triangular factor's diagonal is positive.  A
-// row whose remaining norm is at most 1e-12 of its own norm (dependent on the
-// earlier rows), or not finite, becomes NaN.  Each thread
-// owns the coordinates i = tid (mod 256) of every row.
-__global__ __launch_bounds__(256) void mgs_rows_kernel(int n, int d, double *G) {
-  __shared__ double red[4];
-  double *V = G + (int64_t)blockIdx.x * n * d;
+// row whose remaining norm is at most 8 n eps of its own norm (eps = 2^-52:
+// below the rounding residue of n projections it carries no direction of its
+// own, so it depends on the earlier rows), or not finite, becomes NaN, and so
+// does every later row.  Each thread owns the coordinates i = tid (mod 256)
+// of every row.
+__device__ void mgs_block(int n, int d, double *V, double *red) {
   for (int k = 0; k < n; ++k) {
     double *v = V + (int64_t)k * d;
     double p0 = 0.0;
     for (int i = threadIdx.x; i < d; i += 256) p0 += v[i] * v[i];
     const double nrm0 = sqrt(block_sum<256>(p0, red));
-    for (int j = 0; j < k; ++j) {
-      const double *q = V + (int64_t)j * d;
-      double p = 0.0;
-      for (int i = threadIdx.x; i < d; i += 256) p += q[i] * v[i];
-      const double dot = block_sum<256>(p, red);
-      for (int i = threadIdx.x; i < d; i += 256) v[i] -= dot * q[i];
-    }
+    // two passes of projections (re-orthogonalisation): one pass leaves the
+    // rounding of the projections, a fraction ~eps/residual of the residual
+    // itself, in the earlier directions; the second removes it, so the rows
+    // stay orthonormal to rounding even for nearly dependent draws
+    for (int pass = 0; pass < 2; ++pass)
+      for (int j = 0; j < k; ++j) {
+        const double *q = V + (int64_t)j * d;
+        double p = 0.0;
+        for (int i = threadIdx.x; i < d; i += 256) p += q[i] * v[i];
+        const double dot = block_sum<256>(p, red);
+        for (int i = threadIdx.x; i < d; i += 256) v[i] -= dot * q[i];
+      }
     double p = 0.0;
     for (int i = threadIdx.x; i < d; i += 256) p += v[i] * v[i];
     const double nrm = sqrt(block_sum<256>(p, red));
-    const bool ok = nrm > 1e-12 * nrm0 && isfinite(nrm);
+    const bool ok = nrm > 8.0 * n * 2.220446049250313e-16 * nrm0 && isfinite(nrm);
     for (int i = threadIdx.x; i < d; i += 256) v[i] = ok ? v[i] / nrm : (double)NAN;
+    if (!ok) {
+      for (int r = k + 1; r < n; ++r)
+        for (int i = threadIdx.x; i < d; i += 256) V[(int64_t)r * d + i] = (double)NAN;
+      return;
+    }
   }
+}
+
+__global__ __launch_bounds__(256) void mgs_rows_kernel(int n, int d, double *G) {
+  __shared__ double red[4];
+  mgs_block(n, d, G + (int64_t)blockIdx.x * n * d, red);
+}
+
+// The same for chunks of uneven size: chunk c is the cnt[c] rows starting at
+// row off[c] of U [*][d] (cnt[c] <= d).
+__global__ __launch_bounds__(256) void mgs_chunks_kernel(int d, const int32_t *off,
+                                                         const int32_t *cnt, double *U) {
+  __shared__ double red[4];
+  mgs_block(cnt[blockIdx.x], d, U + (int64_t)off[blockIdx.x] * d, red);
+}
+
+int launch_mgs_chunks(int n_chunks, int d, const int32_t *off, const int32_t *cnt, double *U,
+                      hipStream_t s) {
+  if (n_chunks <= 0) return SB_OK;
+  hipLaunchKernelGGL(mgs_chunks_kernel, dim3((unsigned)n_chunks), dim3(256), 0, s, d, off, cnt,
+                     U);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
 }
 
 }  // namespace sb

@@ -433,10 +433,37 @@ struct ExecCtx {
 
 // ex == nullptr: no graph, no events and no pinned memory (readbacks into
 // host stack words); the phase times in res->seconds are then 0 and only the
-// total is measured.
+// total is measured.  cc != nullptr: the ChiSao cycle (and the refinement
+// pass when cc->n_ref > 0) replaces the single convergence phase (FP64).
 int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void *ws,
-                 size_t ws_bytes, hipStream_t s, ExecCtx *ex);
-size_t evidence_ws_bytes(const sb_loglik *ll, const sb_config *cfg);
+                 size_t ws_bytes, hipStream_t s, ExecCtx *ex,
+                 const sb_chisao_config *cc = nullptr);
+size_t evidence_ws_bytes(const sb_loglik *ll, const sb_config *cfg,
+                         const sb_chisao_config *cc = nullptr);
+
+// ChiSao cycle and two-pass sampling kernels (cycle.hip, chisao.hip)
+int launch_normal_rows(uint64_t seed, uint32_t problem, uint32_t stream, int64_t n, int d,
+                       const int32_t *rows, uint32_t i0, double *out, int64_t ld, hipStream_t s);
+int launch_normalize_rows(int64_t n, int d, double *U, hipStream_t s);
+int launch_gather_idx(int64_t n, int d, const int32_t *src, const double *X, double *out,
+                      hipStream_t s);
+int launch_scatter_idx(int64_t n, int d, const int32_t *dst, const double *in, double *X,
+                       hipStream_t s);
+int launch_cycle_flags(int64_t B, const uint8_t *active, const int32_t *status, const double *l,
+                       uint8_t *conv, double *lmask, hipStream_t s);
+int launch_mask_dead(int64_t B, const uint8_t *active, int32_t *status, hipStream_t s);
+int launch_coord_spread(int64_t B, int d, const double *X, const uint8_t *free, double *sd,
+                        hipStream_t s);
+int launch_refine_t(int R, int n_pts, int n_ref, double delta, const double *lc, double *tref,
+                    hipStream_t s);
+int launch_refine_points(int R, int n_ref, int d, const double *P0, const double *P1,
+                         const double *tref, double *Xr, hipStream_t s);
+int launch_refine_best(int R, int n_pts, int n_ref, const double *lc, const double *lr,
+                       const double *tref, double *best_l, double *best_t, hipStream_t s);
+int launch_gather_starts_t(int d, int n_starts, const int32_t *start_ray, const double *best_t,
+                           const double *P0, const double *P1, double *X0, hipStream_t s);
+int launch_mgs_chunks(int n_chunks, int d, const int32_t *off, const int32_t *cnt, double *U,
+                      hipStream_t s);
 
 // Autotuner: tile choice for the quadratic-form GEMM (cached per shape class).
 // Candidates are timed on the caller's own operands and scratch outputs

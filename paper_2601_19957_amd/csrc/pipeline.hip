@@ -389,9 +389,12 @@ struct RunCfg {
   int polish_chunk;  // reps per Newton batch
   int blk;           // batch steps per captured graph
   bool use_graph;
+  bool cyc = false;     // the ChiSao cycle replaces the single convergence phase
+  sb_chisao_config cc;  // its parameters, defaults filled in
 };
 
-static RunCfg resolve(const sb_loglik *ll, const sb_config *c) {
+static RunCfg resolve(const sb_loglik *ll, const sb_config *c,
+                      const sb_chisao_config *cc = nullptr) {
   RunCfg r;
   r.R = c->n_rays;
   r.n_pts = c->n_points;
@@ -411,6 +414,18 @@ static RunCfg resolve(const sb_loglik *ll, const sb_config *c) {
   r.blk = 8;
   const char *e = getenv("SB_NO_GRAPH");
   r.use_graph = !(e && e[0] == '1');
+  if (cc) {
+    r.cyc = true;
+    r.cc = *cc;
+    if (r.cc.n_conv <= 0) r.cc.n_conv = r.max_iter;
+    if (!(r.cc.stick_tol > 0)) r.cc.stick_tol = 1e-6;
+    if (r.cc.n_reseed_pts <= 0) r.cc.n_reseed_pts = 32;
+    if (r.cc.n_smooth <= 0) r.cc.n_smooth = 4;
+    if (!(r.cc.alpha_cloud > 0)) r.cc.alpha_cloud = 0.01;
+    if (!(r.cc.alpha_anti > 0)) r.cc.alpha_anti = 0.01;
+    if (!(r.cc.ref_delta > 0)) r.cc.ref_delta = 10.0;
+    if (r.cc.n_ref < 0) r.cc.n_ref = 0;
+  }
   return r;
 }
 
@@ -453,6 +468,18 @@ struct Layout {
          *Xs = nullptr, *ls_ = nullptr, *lds = nullptr;
   int32_t *order = nullptr;
   Arena dedup_ar;
+  // ChiSao cycle: slot flags, l of the active slots, end gradients, dedup
+  // outputs, host-built index lists, directions and ray origins, the spread
+  // per coordinate, the perturbations, and the moves' own workspaces
+  uint8_t *cactive = nullptr, *cstuck = nullptr, *cconv = nullptr, *cfrozen = nullptr;
+  double *clmask = nullptr, *Gend = nullptr, *U = nullptr, *Xo = nullptr, *sd = nullptr,
+         *Z = nullptr;
+  int32_t *crep_of = nullptr, *creps = nullptr, *clist = nullptr;  // clist [4][B]
+  void *reseed_ws = nullptr, *explore_ws = nullptr;
+  size_t reseed_bytes = 0, explore_bytes = 0;
+  // refinement pass: refined parameters, points and scores, best t per ray
+  double *tref = nullptr, *Xref = nullptr, *lref = nullptr, *best_t = nullptr;
+  Evaluator refe;
 };
 
 // The mixed bulk runs its contraction as split BF16 when d allows
@@ -592,11 +619,45 @@ static int carve_layout(Arena &ar, Layout &L, const sb_loglik *ll, const RunCfg 
   void *dd = ar.take<char>(dedup_ws_bytes(0) * 2);
   L.dedup_ar = Arena(dd, dedup_ws_bytes(0) * 2);
   if (ar.measure) L.dedup_ar.measure = true;
+  if (rc.cyc) {
+    const sb_chisao_config &cc = rc.cc;
+    L.cactive = ar.take<uint8_t>(B);
+    L.cstuck = ar.take<uint8_t>(B);
+    L.cconv = ar.take<uint8_t>(B);
+    L.cfrozen = ar.take<uint8_t>(B);
+    L.clmask = ar.take<double>(B);
+    L.Gend = ar.take<double>((size_t)B * d);
+    L.U = ar.take<double>((size_t)B * d);
+    L.Xo = ar.take<double>((size_t)B * d);
+    L.sd = ar.take<double>(d);
+    L.crep_of = ar.take<int32_t>(B);
+    L.creps = ar.take<int32_t>(B);
+    L.clist = ar.take<int32_t>((size_t)4 * B);
+    L.Z = ar.take<double>((size_t)std::max(cc.n_cloud, 1) * cc.n_smooth * B * d);
+    L.reseed_bytes = sb_chisao_reseed_workspace_bytes(d, K, B, cc.n_reseed_pts);
+    L.reseed_ws = ar.take<char>(L.reseed_bytes);
+    L.explore_bytes = sb_chisao_explore_workspace_bytes(d, K, B, cc.n_smooth);
+    L.explore_ws = ar.take<char>(L.explore_bytes);
+    if (cc.n_ref > 0) {
+      const int64_t NR = R * cc.n_ref;
+      L.tref = ar.take<double>(NR);
+      L.Xref = ar.take<double>((size_t)NR * d);
+      L.lref = ar.take<double>(NR);
+      L.best_t = ar.take<double>(R);
+      L.refe.dtype = DT_F64;
+      L.refe.cap = NR;
+      L.refe.m.d = d;
+      L.refe.m.K = K;
+      L.refe.qpart = ar.take<char>(8 * (size_t)NR * K * ceil_div(d, 64));
+      L.refe.Y = nullptr;
+      L.refe.ldy = (int64_t)K * d;
+    }
+  }
   return ar.ok() ? SB_OK : SB_E_NOMEM;
 }
 
-size_t evidence_ws_bytes(const sb_loglik *ll, const sb_config *cfg) {
-  RunCfg rc = resolve(ll, cfg);
+size_t evidence_ws_bytes(const sb_loglik *ll, const sb_config *cfg, const sb_chisao_config *cc) {
+  RunCfg rc = resolve(ll, cfg, cc);
   Arena ar(nullptr, 0);
   Layout L;
   carve_layout(ar, L, ll, rc);
@@ -673,11 +734,14 @@ static hipGraphExec_t block_graph(ExecCtx *ex, const BlockKey &key, hipStream_t 
 // execution context (and a stream that can be captured) the iteration blocks
 // run as its graph for `key`; without one they are launched directly.
 static int run_bulk(Layout &L, const RunCfg &rc, double tol, hipStream_t s,
-                    int64_t *evals_out, int *steps_out, ExecCtx *ex, const BlockKey &key) {
+                    int64_t *evals_out, int *steps_out, ExecCtx *ex, const BlockKey &key,
+                    const uint8_t *active = nullptr, void *grad_out = nullptr) {
   LbfgsBuffers &lb = L.lb;
   Evaluator &ev = L.bulk;
   int st = launch_lbfgs_init(lb, L.X0b, s);
   if (st) return st;
+  // empty slots of the ChiSao cycle: dead from the start
+  if (active && (st = launch_mask_dead(lb.B, active, lb.status, s))) return st;
   if (ev.screen) {  // no reference points yet: the first evaluation of every row takes all K
     if ((st = launch_fill_i32(ev.nstate, 0, ev.hasref, s))) return st;
   }
@@ -759,7 +823,7 @@ static int run_bulk(Layout &L, const RunCfg &rc, double tol, hipStream_t s,
   *evals_out = ev_h;
   *steps_out = steps;
   if (rc_st) return rc_st;
-  return launch_lbfgs_gather(lb, L.Xend, L.lend, true, nullptr, L.status, nullptr, s);
+  return launch_lbfgs_gather(lb, L.Xend, L.lend, true, grad_out, L.status, nullptr, s);
 }
 
 // FP64 Newton polish + final Hessian/Cholesky/filters for reps [c0, c0+n).
@@ -816,21 +880,212 @@ static int polish_chunk(Layout &L, const Model &m64, const DevProblem &P, int n,
   return SB_OK;
 }
 
+// The ChiSao oscillation cycle over the n_starts slots, FP64, from the start
+// points in L.X0 (section "ChiSao Exploration"; the steps and readings are
+// those of sb_evidence_chisao_dev).  Leaves the last convergence phase's end
+// points, l and statuses in L.Xend, L.lend, L.status (empty slots dead) for
+// the tail of the path.  Host bookkeeping per oscillation: the slots' stuck,
+// converged and representative flags are read back, the lost / unconverged /
+// peak lists formed in slot order and uploaded as index lists.
+static int run_cycle(Layout &L, const RunCfg &rc, const Model &m64, const DevProblem &P,
+                     double tol, hipStream_t s, int64_t *bulk_evals, int *steps,
+                     int64_t *grad_evals, int64_t *logl_evals, const BlockKey &key) {
+  const sb_chisao_config &cc = rc.cc;
+  const int64_t B = rc.n_starts;
+  const int d = m64.d;
+  int st;
+  RunCfg rconv = rc;
+  rconv.max_iter = cc.n_conv;
+  sb_model_dev md;
+  md.family = m64.family;
+  md.norm = m64.norm;
+  md.d = d;
+  md.K = m64.K;
+  md.log_w = P.log_w;
+  md.mu = P.mu;
+  md.prec = P.prec;
+  md.nu = P.nu;
+  md.logl_offset = P.c;
+  md.beta = m64.beta;
+  md.prec_lp = nullptr;
+  md.mu_lp = nullptr;
+  std::vector<uint8_t> act(B, 1), stk(B), cnv(B);
+  std::vector<int32_t> rep_of(B), reps(B), lst;
+  SB_HIP(hipMemcpyAsync(L.cactive, act.data(), B, hipMemcpyHostToDevice, s));
+  bool gr_enabled = true, gr_used = false;
+  int prev_found = -1;
+  for (int k = 0; k < cc.n_osc; ++k) {
+    const bool last = k == cc.n_osc - 1;
+    // 1. convergence phase from the slots' points (fresh history)
+    int64_t ev = 0;
+    int stp = 0;
+    if ((st = run_bulk(L, rconv, tol, s, &ev, &stp, nullptr, key, L.cactive, L.Gend))) return st;
+    *bulk_evals += ev;
+    *steps += stp;
+    // 2. stick detection over the active slots
+    if ((st = launch_cycle_flags(B, L.cactive, L.status, (const double *)L.lend, L.cconv,
+                                 L.clmask, s)))
+      return st;
+    if ((st = sb_chisao_stick_dev(B, d, L.clmask, L.Gend, cc.stick_tol, L.cstuck, L.sd,
+                                  sizeof(double) * d, s)))
+      return st;
+    // 3. dedup of the stuck slots; the converged slots' distinct peaks
+    int npk = 0, nfound = 0;
+    Arena ar3(L.dedup_ar.base, L.dedup_ar.cap);
+    if ((st = dedup_run((int)B, d, L.Xend, DT_F64, L.lend, DT_F64, L.cstuck, rc.dedup_tol_pre,
+                        L.crep_of, L.creps, (int)B, &npk, ar3, s)))
+      return st;
+    SB_HIP(hipMemcpyAsync(stk.data(), L.cstuck, B, hipMemcpyDeviceToHost, s));
+    SB_HIP(hipMemcpyAsync(cnv.data(), L.cconv, B, hipMemcpyDeviceToHost, s));
+    SB_HIP(hipMemcpyAsync(rep_of.data(), L.crep_of, sizeof(int32_t) * B, hipMemcpyDeviceToHost,
+                          s));
+    SB_HIP(hipMemcpyAsync(reps.data(), L.creps, sizeof(int32_t) * std::max(npk, 1),
+                          hipMemcpyDeviceToHost, s));
+    SB_HIP(hipStreamSynchronize(s));
+    Arena ar4(L.dedup_ar.base, L.dedup_ar.cap);
+    if ((st = dedup_run((int)B, d, L.Xend, DT_F64, L.lend, DT_F64, L.cconv, rc.dedup_tol_pre,
+                        L.crep_of, L.clist, (int)B, &nfound, ar4, s)))
+      return st;
+    if (gr_used && nfound <= prev_found) gr_enabled = false;
+    gr_used = false;
+    prev_found = nfound;
+    std::vector<int32_t> lost;
+    for (int64_t b = 0; b < B; ++b)
+      if (stk[b] && rep_of[b] != (int32_t)b) lost.push_back((int32_t)b);
+    for (int32_t b : lost) {
+      act[b] = 0;
+      stk[b] = 0;
+    }
+    // 4. reseeding
+    const uint32_t base = 16u + 8u * (uint32_t)k;
+    int kind = 0;
+    const int64_t nl = (int64_t)lost.size();
+    if (!last && nl > 0) {
+      std::vector<int32_t> unc;
+      for (int64_t b = 0; b < B; ++b)
+        if (act[b] && !cnv[b]) unc.push_back((int32_t)b);
+      std::vector<int32_t> slot, orig, coff, ccnt;
+      if (unc.size() >= 5) {
+        kind = 1;  // Repulse Monkey
+        for (int64_t j = 0; j < nl; ++j) {
+          slot.push_back(lost[j]);
+          orig.push_back(unc[j % (int64_t)unc.size()]);
+        }
+      } else if (gr_enabled && npk > 0) {
+        kind = 2;  // Golden Rooster
+        gr_used = true;
+        for (int p = 0; p < npk; ++p) {
+          std::vector<int32_t> mine;
+          for (int64_t j = p; j < nl; j += npk) mine.push_back(lost[j]);
+          for (size_t c0 = 0; c0 < mine.size(); c0 += (size_t)d) {
+            const size_t c1 = std::min(mine.size(), c0 + (size_t)d);
+            coff.push_back((int32_t)slot.size());
+            ccnt.push_back((int32_t)(c1 - c0));
+            for (size_t q = c0; q < c1; ++q) {
+              slot.push_back(mine[q]);
+              orig.push_back(reps[p]);
+            }
+          }
+        }
+      }
+      if (kind) {
+        const int64_t n = (int64_t)slot.size();
+        int32_t *dslot = L.clist, *dorig = L.clist + B, *doff = L.clist + 2 * B,
+                *dcnt = L.clist + 3 * B;
+        SB_HIP(hipMemcpyAsync(dslot, slot.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+        SB_HIP(hipMemcpyAsync(dorig, orig.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+        if ((st = launch_normal_rows(rc.seed, 0u, kind == 1 ? base : base + 2u, n, d, dslot, 0u,
+                                     L.U, d, s)))
+          return st;
+        if (kind == 1) {
+          if ((st = launch_normalize_rows(n, d, L.U, s))) return st;
+        } else {
+          const int nc = (int)coff.size();
+          SB_HIP(hipMemcpyAsync(doff, coff.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice,
+                                s));
+          SB_HIP(hipMemcpyAsync(dcnt, ccnt.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice,
+                                s));
+          if ((st = launch_mgs_chunks(nc, d, doff, dcnt, L.U, s))) return st;
+        }
+        if ((st = launch_gather_idx(n, d, dorig, (const double *)L.Xend, L.Xo, s))) return st;
+        if ((st = sb_chisao_reseed_dev(&md, P.lo, P.hi, n, L.Xo, L.U, cc.n_reseed_pts, nullptr,
+                                       L.reseed_ws, L.reseed_bytes, s)))
+          return st;
+        *logl_evals += n * cc.n_reseed_pts;
+        if ((st = launch_scatter_idx(n, d, dslot, L.Xo, (double *)L.Xend, s))) return st;
+        for (int32_t b : lost) act[b] = 1;
+        // the upload of the host lists must finish before they are reused
+        SB_HIP(hipStreamSynchronize(s));
+      }
+    }
+    SB_HIP(hipMemcpyAsync(L.cactive, act.data(), B, hipMemcpyHostToDevice, s));
+    SB_HIP(hipStreamSynchronize(s));
+    if (last) {
+      // the last dedup's lost duplicates leave the candidates
+      if ((st = launch_mask_dead(B, L.cactive, L.status, s))) return st;
+      break;
+    }
+    // 5. Hands Like Clouds and anti-convergence of the free slots
+    std::vector<uint8_t> frz(B);
+    int64_t nfree = 0;
+    for (int64_t b = 0; b < B; ++b) {
+      const bool fr = act[b] && !stk[b];
+      frz[b] = fr ? 0 : 1;
+      nfree += fr ? 1 : 0;
+    }
+    SB_HIP(hipMemcpyAsync(L.cfrozen, frz.data(), B, hipMemcpyHostToDevice, s));
+    double sigma = cc.sigma;
+    if (!(sigma > 0)) {
+      sigma = 0.0;
+      if (nfree >= 2) {
+        // the free flags: 1 - frozen, formed on the host beside it
+        std::vector<uint8_t> fre(B);
+        for (int64_t b = 0; b < B; ++b) fre[b] = (uint8_t)(1 - frz[b]);
+        SB_HIP(hipMemcpyAsync(L.cconv, fre.data(), B, hipMemcpyHostToDevice, s));
+        if ((st = launch_coord_spread(B, d, (const double *)L.Xend, L.cconv, L.sd, s))) return st;
+        std::vector<double> sdh(d);
+        SB_HIP(hipMemcpyAsync(sdh.data(), L.sd, sizeof(double) * d, hipMemcpyDeviceToHost, s));
+        SB_HIP(hipStreamSynchronize(s));
+        std::sort(sdh.begin(), sdh.end());
+        const double med = (d % 2) ? sdh[d / 2] : 0.5 * (sdh[d / 2 - 1] + sdh[d / 2]);
+        sigma = 0.5 * med;
+      }
+    }
+    for (int c = 0; c < cc.n_cloud; ++c)
+      for (int q = 0; q < cc.n_smooth; ++q) {
+        const uint32_t i0 = (uint32_t)((c * cc.n_smooth + q) * d);
+        if ((st = launch_normal_rows(rc.seed, 0u, base + 4u, B, d, nullptr, i0,
+                                     L.Z + ((size_t)c * cc.n_smooth + q) * B * d, d, s)))
+          return st;
+      }
+    if ((st = sb_chisao_explore_dev(&md, P.lo, P.hi, B, (double *)L.Xend, L.cfrozen, cc.n_cloud,
+                                    cc.n_smooth, L.Z, sigma, cc.alpha_cloud, cc.n_anti,
+                                    cc.alpha_anti, cc.momentum, L.explore_ws, L.explore_bytes,
+                                    s)))
+      return st;
+    *grad_evals += B * ((int64_t)cc.n_cloud * cc.n_smooth + cc.n_anti);
+    // the moved points start the next convergence phase
+    SB_HIP(hipMemcpyAsync(L.X0, L.Xend, sizeof(double) * B * d, hipMemcpyDeviceToDevice, s));
+    SB_HIP(hipStreamSynchronize(s));
+  }
+  return SB_OK;
+}
+
 int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void *ws,
-                 size_t ws_bytes, hipStream_t s, ExecCtx *ex) {
+                 size_t ws_bytes, hipStream_t s, ExecCtx *ex, const sb_chisao_config *cc) {
   const auto t_start = std::chrono::steady_clock::now();
   sb_loglik llh;
   llh.family = P.family;
   llh.norm = P.norm;
   llh.d = P.d;
   llh.K = P.K;
-  RunCfg rc = resolve(&llh, cfg);
+  RunCfg rc = resolve(&llh, cfg, cc);
   const int d = P.d, K = P.K;
   const bool mixed = rc.precision == SB_PREC_MIXED;
   Arena ar(ws, ws_bytes);
   Layout L;
   if (carve_layout(ar, L, &llh, rc) != SB_OK || !ws) {
-    set_error("workspace too small: need %zu bytes", evidence_ws_bytes(&llh, cfg));
+    set_error("workspace too small: need %zu bytes", evidence_ws_bytes(&llh, cfg, cc));
     return SB_E_NOMEM;
   }
   Timer tm;
@@ -937,11 +1192,44 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
       if ((st = L.disc.run(a, NP, nullptr, L.lpts, nullptr, 0, nullptr, nullptr, false, s, false)))
         return st;
     }
-    if ((st = launch_ray_argmax(rc.R, rc.n_pts, ddt, L.lpts, L.best_l, L.best_j, s))) return st;
-    if ((st = launch_topn(rc.R, rc.n_starts, L.best_l, L.start_ray, s))) return st;
-    if ((st = launch_gather_starts(d, rc.n_pts, rc.n_starts, L.start_ray, L.best_j, L.P0, L.P1,
-                                   L.X0, s)))
-      return st;
+    if (rc.cyc && rc.cc.n_ref > 0) {
+      // refinement pass (FP64): points at the quantiles of the likelihood on
+      // each ray's active cells, scored by the same contraction as rows
+      const int nref = rc.cc.n_ref;
+      const int64_t NR = (int64_t)rc.R * nref;
+      if ((st = launch_refine_t(rc.R, rc.n_pts, nref, rc.cc.ref_delta, (const double *)L.lpts,
+                                L.tref, s)))
+        return st;
+      if ((st = launch_refine_points(rc.R, nref, d, L.P0, L.P1, L.tref, L.Xref, s))) return st;
+      ASrc a;
+      a.kind = 0;
+      a.X = L.Xref;
+      a.ldx = d;
+      L.refe.m = md;
+      TuneProbe pr;
+      pr.a = a;
+      pr.o.Y = nullptr;
+      pr.o.ldy = L.refe.ldy;
+      pr.o.qpart = L.refe.qpart;
+      L.refe.tile = autotune_tiles(DT_F64, md, NR, s, &pr);
+      if ((st = L.refe.run(a, NR, nullptr, L.lref, nullptr, 0, nullptr, nullptr, false, s,
+                           false)))
+        return st;
+      if ((st = launch_refine_best(rc.R, rc.n_pts, nref, (const double *)L.lpts, L.lref, L.tref,
+                                   L.best_l, L.best_t, s)))
+        return st;
+      if ((st = launch_topn(rc.R, rc.n_starts, L.best_l, L.start_ray, s))) return st;
+      if ((st = launch_gather_starts_t(d, rc.n_starts, L.start_ray, L.best_t, L.P0, L.P1, L.X0,
+                                       s)))
+        return st;
+    } else {
+      if ((st = launch_ray_argmax(rc.R, rc.n_pts, ddt, L.lpts, L.best_l, L.best_j, s)))
+        return st;
+      if ((st = launch_topn(rc.R, rc.n_starts, L.best_l, L.start_ray, s))) return st;
+      if ((st = launch_gather_starts(d, rc.n_pts, rc.n_starts, L.start_ray, L.best_j, L.P0,
+                                     L.P1, L.X0, s)))
+        return st;
+    }
     tm.mark(s);  // 2
     // ---------------- A3-A5 bulk L-BFGS
     Model mb = m64;
@@ -1023,7 +1311,13 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     key.tile = L.bulk.tile;
     key.tile1 = L.bulk.tile1;
     key.tile2 = L.bulk.tile2;
-    if ((st = run_bulk(L, rc, tol, s, &bulk_evals, &steps, ex, key))) return st;
+    int64_t cyc_grad_evals = 0, cyc_logl_evals = 0;
+    if (!rc.cyc) {
+      if ((st = run_bulk(L, rc, tol, s, &bulk_evals, &steps, ex, key))) return st;
+    } else if ((st = run_cycle(L, rc, m64, P, tol, s, &bulk_evals, &steps, &cyc_grad_evals,
+                               &cyc_logl_evals, key))) {
+      return st;
+    }
     tm.mark(s);  // 3
     // ---------------- A7 pre-dedup
     const int64_t B = rc.n_starts;
@@ -1073,8 +1367,8 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     int32_t hcounts[8];
     SB_HIP(hipMemcpyAsync(hcounts, L.counts, sizeof(hcounts), hipMemcpyDeviceToHost, s));
     SB_HIP(hipStreamSynchronize(s));
-    res->n_logl_evals = (int64_t)rc.R * rc.n_pts;
-    res->n_grad_evals = bulk_evals + pol_evals;
+    res->n_logl_evals = (int64_t)rc.R * (rc.n_pts + (rc.cyc ? rc.cc.n_ref : 0)) + cyc_logl_evals;
+    res->n_grad_evals = bulk_evals + pol_evals + cyc_grad_evals;
     res->n_hess_evals = hess_evals;
     res->iterations = steps;
     res->n_dead_starts = hcounts[0];

@@ -13,40 +13,9 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "rng.h"
 
 namespace sb {
-
-__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int round = 0; round < 10; ++round) {
-    if (round) {
-      k0 += 0x9E3779B9u;
-      k1 += 0xBB67AE85u;
-    }
-    const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
-    const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
-    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = lo1;
-    c[2] = n2;
-    c[3] = lo0;
-  }
-}
-
-__device__ inline uint32_t rng_word(uint64_t seed, uint32_t problem, uint32_t ray, uint32_t stream,
-                                    uint32_t i) {
-  uint32_t c[4] = {ray, i >> 2, stream, problem};
-  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-  return c[i & 3u];
-}
-
-__device__ inline double rng_uniform(uint64_t seed, uint32_t problem, uint32_t ray,
-                                     uint32_t stream, uint32_t i) {
-  uint32_t c[4] = {ray, i >> 1, stream, problem};
-  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-  const uint32_t a = c[2u * (i & 1u)], b = c[2u * (i & 1u) + 1u];
-  return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
-}
 
 __global__ __launch_bounds__(256) void rays_kernel(int d, const double *lo, const double *hi,
                                                    uint64_t seed, uint32_t problem, double *P0,

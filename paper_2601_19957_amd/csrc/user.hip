@@ -206,6 +206,239 @@ __global__ __launch_bounds__(256) void scatter_state_rows_kernel(int count, int 
   if (e % d == 0) F[r] = l[i];
 }
 
+// ------------------------------------------------------------ TrajectoryBank
+//
+// Step 1 of BendTheBow's geometry detection (section "Automatic Geometry
+// Detection"; appendix "Rotation Detection"): GreenDragon's seeds of each
+// mode, theta* +- 0.9 w_i e_i with w_i = 1/sqrt(-H_ii) (seed 2i: +, 2i + 1:
+// -), run batched L-BFGS on FD gradients; after every batch step each seed's
+// newly accepted point (its iteration count advanced) closes a step of its
+// trajectory, whose perpendicular fraction in coordinates whitened by
+// sqrt(-H_ii) is folded into the seed's maximum.  A step counts while the
+// whitened gradient at its start is at least rel_floor of the seed's first.
+// The positions and gradients are also written to a caller's bank when one is
+// given.
+
+__global__ __launch_bounds__(256) void gd_seeds_kernel(int d, const double *modes,
+                                                       const double *hdiag, double *X0) {
+#pragma clang fp contract(off)
+  const int64_t row = blockIdx.x;
+  const int64_t k = row / (2 * d);
+  const int j = (int)(row % (2 * d)), i = j / 2;
+  for (int c = threadIdx.x; c < d; c += 256) {
+    double x = modes[k * d + c];
+    if (c == i) {
+      const double w = 1.0 / sqrt(-hdiag[k * d + i]);
+      x = (j & 1) ? x - 0.9 * w : x + 0.9 * w;
+    }
+    X0[row * d + c] = x;
+  }
+}
+
+__global__ __launch_bounds__(256) void traj_step_kernel(
+    int64_t S, int d, int n_max, const double *X, const double *G, const int32_t *cur,
+    const int32_t *iters, const double *hdiag, double rel_floor, double *xprev, double *gprev,
+    int32_t *tprev, double *g0w, double *fmx, int32_t *nct, double *Xbank, double *Gbank,
+    int32_t *blen) {
+  __shared__ double red[4];
+  const int64_t s = blockIdx.x;
+  const int64_t k = s / (2 * d);
+  const int t = iters[s], tp = tprev[s];
+  const int64_t row = (int64_t)cur[s] * S + s;
+  const double *x = X + row * d, *g = G + row * d, *hd = hdiag + k * d;
+  double *xp = xprev + s * d, *gp = gprev + s * d;
+  if (tp >= 0 && t <= tp) return;  // no new accepted point
+  if (tp >= 0) {
+    // the step from the previous point to this one
+    double a = 0.0;
+    for (int i = threadIdx.x; i < d; i += 256) {
+      const double gw = gp[i] / sqrt(-hd[i]);
+      a += gw * gw;
+    }
+    const double gg = block_sum<256>(a, red);
+    const double g0 = g0w[s];
+    if (g0 > 0.0 && sqrt(gg) >= rel_floor * g0) {
+      double b = 0.0, c = 0.0;
+      for (int i = threadIdx.x; i < d; i += 256) {
+        const double sh = sqrt(-hd[i]);
+        const double du = sh * (x[i] - xp[i]), gw = gp[i] / sh;
+        b += du * gw;
+        c += du * du;
+      }
+      const double dg = block_sum<256>(b, red);
+      const double dd = block_sum<256>(c, red);
+      if (dd > 0.0) {
+        const double coef = dg / gg;
+        double e = 0.0;
+        for (int i = threadIdx.x; i < d; i += 256) {
+          const double sh = sqrt(-hd[i]);
+          const double pr = sh * (x[i] - xp[i]) - coef * (gp[i] / sh);
+          e += pr * pr;
+        }
+        const double pp = block_sum<256>(e, red);
+        if (threadIdx.x == 0) {
+          fmx[s] = fmax(fmx[s], sqrt(pp) / sqrt(dd));
+          nct[s] += 1;
+        }
+      }
+    }
+  } else {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < d; i += 256) {
+      const double gw = g[i] / sqrt(-hd[i]);
+      a += gw * gw;
+    }
+    const double n0 = sqrt(block_sum<256>(a, red));
+    if (threadIdx.x == 0) g0w[s] = n0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < d; i += 256) {
+    xp[i] = x[i];
+    gp[i] = g[i];
+  }
+  if (Xbank && t <= n_max)
+    for (int i = threadIdx.x; i < d; i += 256) {
+      Xbank[(s * (n_max + 1) + t) * d + i] = x[i];
+      Gbank[(s * (n_max + 1) + t) * d + i] = g[i];
+    }
+  if (threadIdx.x == 0) {
+    tprev[s] = t;
+    if (blen) blen[s] = t + 1;
+  }
+}
+
+__global__ void traj_init_kernel(int64_t S, int32_t *tprev, double *fmx, int32_t *nct) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  tprev[s] = -1;
+  fmx[s] = 0.0;
+  nct[s] = 0;
+}
+
+// f_perp of mode k: the largest seed maximum over its 2d seeds that counted a
+// step; NaN when none did.
+__global__ void traj_mode_kernel(int n, int d, const double *fmx, const int32_t *nct,
+                                 double *fperp) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double m = 0.0;
+  bool any = false;
+  for (int j = 0; j < 2 * d; ++j) {
+    const int64_t s = (int64_t)k * 2 * d + j;
+    if (nct[s] > 0) {
+      any = true;
+      m = fmax(m, fmx[s]);
+    }
+  }
+  fperp[k] = any ? m : (double)NAN;
+}
+
+__global__ void iota_kernel(int64_t n, int32_t *idx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) idx[i] = (int32_t)i;
+}
+
+struct TrajBuffers {
+  int64_t S = 0;
+  LbfgsBuffers lb;
+  double *X0 = nullptr, *Xg = nullptr, *lg = nullptr, *gg = nullptr;
+  double *xprev = nullptr, *gprev = nullptr, *g0w = nullptr, *fmax = nullptr;
+  int32_t *tprev = nullptr, *nct = nullptr, *all = nullptr;
+  double *fperp = nullptr;  // [n] per-mode result when the caller keeps none
+  void *fd_ws = nullptr;
+  size_t fd_bytes = 0;
+};
+
+static int traj_layout(Arena &ar, TrajBuffers &T, int n, int d, int m) {
+  const int64_t S = 2ll * n * d;
+  T.S = S;
+  T.X0 = ar.take<double>((size_t)S * d);
+  T.Xg = ar.take<double>((size_t)S * d);
+  T.lg = ar.take<double>(S);
+  T.gg = ar.take<double>((size_t)S * d);
+  T.xprev = ar.take<double>((size_t)S * d);
+  T.gprev = ar.take<double>((size_t)S * d);
+  T.g0w = ar.take<double>(S);
+  T.fmax = ar.take<double>(S);
+  T.tprev = ar.take<int32_t>(S);
+  T.nct = ar.take<int32_t>(S);
+  T.all = ar.take<int32_t>(S);
+  T.fperp = ar.take<double>(n);
+  T.fd_bytes = sb_user_fd_workspace_bytes(S, d, 0);
+  T.fd_ws = ar.take<char>(T.fd_bytes);
+  T.lb.dtype = DT_F64;
+  T.lb.B = S;
+  T.lb.d = d;
+  T.lb.m = m;
+  if (lbfgs_carve(ar, T.lb)) return SB_E_NOMEM;
+  return ar.ok() ? SB_OK : SB_E_NOMEM;
+}
+
+// FD l and gradient of `count` L-BFGS rows listed in idx into the state's
+// slots (gather the rows, one batch of perturbed points, scatter back).
+static int eval_state_rows(const sb_user_fn *fn, LbfgsBuffers &lb, int d, const double *params,
+                           double eps, const int32_t *idx, int count, double *Xg, double *lg,
+                           double *gg, void *fd_ws, size_t fd_bytes, hipStream_t s) {
+  if (count <= 0) return SB_OK;
+  hipLaunchKernelGGL(gather_state_rows_kernel, dim3((unsigned)ceil_div((int64_t)count * d, 256)),
+                     dim3(256), 0, s, count, d, idx, (const double *)lb.X, Xg);
+  SB_LAUNCH_CHECK();
+  int st = sb_user_fd_dev(fn, count, d, Xg, params, eps, lg, gg, nullptr, nullptr, nullptr,
+                          fd_ws, fd_bytes, s);
+  if (st) return st;
+  hipLaunchKernelGGL(scatter_state_rows_kernel, dim3((unsigned)ceil_div((int64_t)count * d, 256)),
+                     dim3(256), 0, s, count, d, idx, lg, gg, (double *)lb.F, (double *)lb.G);
+  SB_LAUNCH_CHECK();
+  return SB_OK;
+}
+
+// The seeds' L-BFGS with the bank recording; fperp [n] (device) per mode.
+static int run_trajectories(const sb_user_fn *fn, int n, int d, const double *modes,
+                            const double *params, const double *hdiag, double eps, int n_iter,
+                            double grad_tol, TrajBuffers &T, double *fperp, double *Xbank,
+                            double *Gbank, int32_t *blen, int64_t *evals, hipStream_t s) {
+  const int64_t S = T.S;
+  LbfgsBuffers &lb = T.lb;
+  hipLaunchKernelGGL(gd_seeds_kernel, dim3((unsigned)S), dim3(256), 0, s, d, modes, hdiag, T.X0);
+  SB_LAUNCH_CHECK();
+  int st;
+  if ((st = launch_lbfgs_init(lb, T.X0, s))) return st;
+  hipLaunchKernelGGL(iota_kernel, dim3((unsigned)ceil_div(S, 256)), dim3(256), 0, s, S, T.all);
+  hipLaunchKernelGGL(traj_init_kernel, dim3((unsigned)ceil_div(S, 256)), dim3(256), 0, s, S,
+                     T.tprev, T.fmax, T.nct);
+  SB_LAUNCH_CHECK();
+  if ((st = eval_state_rows(fn, lb, d, params, eps, T.all, (int)S, T.Xg, T.lg, T.gg, T.fd_ws,
+                            T.fd_bytes, s)))
+    return st;
+  int64_t ev = S;
+  auto record = [&]() {
+    hipLaunchKernelGGL(traj_step_kernel, dim3((unsigned)S), dim3(256), 0, s, S, d, n_iter,
+                       (const double *)lb.X, (const double *)lb.G, lb.cur, lb.iters, hdiag, 1e-3,
+                       T.xprev, T.gprev, T.tprev, T.g0w, T.fmax, T.nct, Xbank, Gbank, blen);
+  };
+  record();
+  SB_LAUNCH_CHECK();
+  for (int step = 0; step < 42 * n_iter + 64; ++step) {
+    if ((st = launch_lbfgs_step(lb, n_iter, grad_tol, s))) return st;
+    record();
+    SB_LAUNCH_CHECK();
+    if ((st = launch_compact(lb, s))) return st;
+    int32_t cnt = 0;
+    SB_HIP(hipMemcpyAsync(&cnt, lb.count, 4, hipMemcpyDeviceToHost, s));
+    SB_HIP(hipStreamSynchronize(s));
+    if (cnt <= 0) break;
+    if ((st = eval_state_rows(fn, lb, d, params, eps, lb.idx, cnt, T.Xg, T.lg, T.gg, T.fd_ws,
+                              T.fd_bytes, s)))
+      return st;
+    ev += cnt;
+  }
+  hipLaunchKernelGGL(traj_mode_kernel, dim3((unsigned)ceil_div(n, 64)), dim3(64), 0, s, n, d,
+                     T.fmax, T.nct, fperp);
+  SB_LAUNCH_CHECK();
+  if (evals) *evals = ev;
+  return SB_OK;
+}
+
 }  // namespace sb
 
 using namespace sb;
@@ -337,6 +570,38 @@ int32_t sb_user_fd_dev(const sb_user_fn *fn, int64_t B, int32_t d, const double 
   return SB_OK;
 }
 
+}  // extern "C"
+
+namespace sb {
+// Geometry detection parameters with their defaults filled in.
+struct GeoCfg {
+  int n_iter, m;
+  double grad_tol, eps_axis, eps_rot, rot_tol, eps_grad;
+};
+static GeoCfg geo_resolve(const sb_geometry_config *gc, int d, double eps_grad) {
+  GeoCfg g;
+  int lg = 0;
+  while ((1 << lg) < d) ++lg;  // ceil(log2 d)
+  g.n_iter = gc->n_iter > 0 ? gc->n_iter : std::max(10, 3 * lg);
+  g.m = gc->m > 0 ? gc->m : 8;
+  g.grad_tol = gc->grad_tol > 0 ? gc->grad_tol : 1e-6;
+  g.eps_axis = gc->eps_axis > 0 ? gc->eps_axis : 1e-4;
+  g.eps_rot = gc->eps_rot > 0 ? gc->eps_rot : 1e-2;
+  g.rot_tol = gc->rot_tol;
+  g.eps_grad = eps_grad;
+  return g;
+}
+
+static size_t traj_bytes(int n, int d, int m) {
+  Arena ar(nullptr, 0);
+  TrajBuffers T;
+  traj_layout(ar, T, n, d, m);
+  return ar.off + 1024;
+}
+}  // namespace sb
+
+extern "C" {
+
 size_t sb_user_mode_evidence_workspace_bytes(int32_t n, int32_t d) {
   if (n < 1 || d < 1) return 0;
   const size_t nd = (size_t)n * d, ndd = nd * d;
@@ -345,19 +610,17 @@ size_t sb_user_mode_evidence_workspace_bytes(int32_t n, int32_t d) {
          3 * align_up(4 * (size_t)n) + 4096;
 }
 
-int32_t sb_user_mode_evidence_dev(const sb_user_fn *fn, int32_t n, int32_t d,
+// Laplace evidence at given modes; geo == nullptr: the probe alone decides
+// (Step 2), else Step 1 (the trajectories' perpendicular fraction) and the
+// probe only where it is inconclusive.  decision (host, nullable): 0 axis by
+// trajectories, 1 rotated by them, 2 axis by the probe, 3 rotated by it.
+static int32_t mode_evidence_impl(const sb_user_fn *fn, int32_t n, int32_t d,
                                   const double *modes, const double *params, const double *lo,
-                                  const double *hi, double eps, double rot_tol, double *logl,
-                                  double *logdet, int32_t *full_used, int32_t *order,
-                                  double *mode_log_z, double *log_z, void *workspace,
-                                  size_t ws_bytes, void *stream) {
-  if (!fn || n < 1 || d < 1 || !modes || !lo || !hi || !logl || !logdet || !order ||
-      !mode_log_z || !log_z)
-    return fail(SB_E_INVAL, "bad evidence-at-modes arguments");
-  if (!(eps > 0.0) || !std::isfinite(eps) || !(rot_tol >= 0.0))
-    return fail(SB_E_INVAL, "need eps > 0 and rot_tol >= 0");
-  if (!workspace || ws_bytes < sb_user_mode_evidence_workspace_bytes(n, d))
-    return fail(SB_E_NOMEM, "workspace too small");
+                                  const double *hi, double eps, double rot_tol,
+                                  const GeoCfg *geo, double *fperp, int32_t *decision,
+                                  double *logl, double *logdet, int32_t *full_used,
+                                  int32_t *order, double *mode_log_z, double *log_z,
+                                  void *workspace, size_t ws_bytes, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   Arena ar(workspace, ws_bytes);
   const size_t ws0 = sb_user_fd_workspace_bytes(n, d, 0), ws1 = sb_user_fd_workspace_bytes(n, d, 1);
@@ -384,16 +647,42 @@ int32_t sb_user_mode_evidence_dev(const sb_user_fn *fn, int32_t n, int32_t d,
   SB_HIP(hipMemcpyAsync(h_hd.data(), hd, 8 * h_hd.size(), hipMemcpyDeviceToHost, s));
   SB_HIP(hipMemcpyAsync(h_pb.data(), pb, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
   SB_HIP(hipStreamSynchronize(s));
-  std::vector<int32_t> h_full(n, 0), h_idx;
+  std::vector<int32_t> h_full(n, 0), h_idx, h_dec(n, 2);
+  std::vector<double> h_fp(n, (double)NAN);
+  if (geo) {
+    for (int64_t i = 0; i < (int64_t)n * d; ++i)
+      if (!(h_hd[i] < 0.0))
+        return fail(SB_E_NOTPD, "mode %lld: H_ii >= 0 (not a maximum)", (long long)(i / d));
+    // Step 1: GreenDragon's seeds and the perpendicular step fraction
+    const size_t o = align_up(ar.off);
+    Arena tar((char *)ar.base + o, ar.cap > o ? ar.cap - o : 0);
+    TrajBuffers T;
+    if (traj_layout(tar, T, n, d, geo->m)) return fail(SB_E_NOMEM, "workspace too small");
+    double *fp = fperp ? fperp : T.fperp;
+    if ((st = run_trajectories(fn, n, d, modes, params, hd, geo->eps_grad, geo->n_iter,
+                               geo->grad_tol, T, fp, nullptr, nullptr, nullptr, nullptr, s)))
+      return st;
+    SB_HIP(hipMemcpyAsync(h_fp.data(), fp, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
+    SB_HIP(hipStreamSynchronize(s));
+  }
   for (int k = 0; k < n; ++k) {
     double a = 0.0;
     for (int i = 0; i < d; ++i) a += h_hd[(size_t)k * d + i];
     a /= d;
-    if (std::fabs(h_pb[k]) > rot_tol * std::fabs(a)) {
+    int dec;
+    if (geo && h_fp[k] > geo->eps_rot)
+      dec = 1;
+    else if (geo && h_fp[k] <= geo->eps_axis)
+      dec = 0;
+    else
+      dec = std::fabs(h_pb[k]) > rot_tol * std::fabs(a) ? 3 : 2;
+    h_dec[k] = dec;
+    if (dec == 1 || dec == 3) {
       h_full[k] = 1;
       h_idx.push_back(k);
     }
   }
+  if (decision) std::memcpy(decision, h_dec.data(), 4 * (size_t)n);
   if (full_used) std::memcpy(full_used, h_full.data(), 4 * (size_t)n);
   SB_HIP(hipMemcpyAsync(fullv, h_full.data(), 4 * (size_t)n, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(fd_diag_logdet_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n,
@@ -428,6 +717,82 @@ int32_t sb_user_mode_evidence_dev(const sb_user_fn *fn, int32_t n, int32_t d,
     if (!std::isfinite(h_ld[k]))
       return fail(SB_E_NOTPD, "mode %d: -H is not positive definite (not a maximum)", k);
   return SB_OK;
+}
+
+int32_t sb_user_mode_evidence_dev(const sb_user_fn *fn, int32_t n, int32_t d,
+                                  const double *modes, const double *params, const double *lo,
+                                  const double *hi, double eps, double rot_tol, double *logl,
+                                  double *logdet, int32_t *full_used, int32_t *order,
+                                  double *mode_log_z, double *log_z, void *workspace,
+                                  size_t ws_bytes, void *stream) {
+  if (!fn || n < 1 || d < 1 || !modes || !lo || !hi || !logl || !logdet || !order ||
+      !mode_log_z || !log_z)
+    return fail(SB_E_INVAL, "bad evidence-at-modes arguments");
+  if (!(eps > 0.0) || !std::isfinite(eps) || !(rot_tol >= 0.0))
+    return fail(SB_E_INVAL, "need eps > 0 and rot_tol >= 0");
+  if (!workspace || ws_bytes < sb_user_mode_evidence_workspace_bytes(n, d))
+    return fail(SB_E_NOMEM, "workspace too small");
+  return mode_evidence_impl(fn, n, d, modes, params, lo, hi, eps, rot_tol, nullptr, nullptr,
+                            nullptr, logl, logdet, full_used, order, mode_log_z, log_z,
+                            workspace, ws_bytes, stream);
+}
+
+static bool geo_ok(const sb_geometry_config *gc) {
+  return gc && gc->rot_tol >= 0.0 && std::isfinite(gc->rot_tol) && std::isfinite(gc->grad_tol) &&
+         std::isfinite(gc->eps_axis) && std::isfinite(gc->eps_rot) && gc->n_iter <= 100000 &&
+         gc->m <= kMaxMem;
+}
+
+size_t sb_user_mode_evidence_geo_workspace_bytes(int32_t n, int32_t d,
+                                                 const sb_geometry_config *gc) {
+  if (n < 1 || d < 1 || !geo_ok(gc)) return 0;
+  const GeoCfg g = geo_resolve(gc, d, 1.0);
+  return sb_user_mode_evidence_workspace_bytes(n, d) + traj_bytes(n, d, g.m);
+}
+
+int32_t sb_user_mode_evidence_geo_dev(const sb_user_fn *fn, int32_t n, int32_t d,
+                                      const double *modes, const double *params,
+                                      const double *lo, const double *hi, double eps_grad,
+                                      double eps_hess, const sb_geometry_config *gc,
+                                      double *logl, double *logdet, double *fperp,
+                                      int32_t *decision, int32_t *order, double *mode_log_z,
+                                      double *log_z, void *workspace, size_t ws_bytes,
+                                      void *stream) {
+  if (!fn || n < 1 || d < 1 || !modes || !lo || !hi || !logl || !logdet || !order ||
+      !mode_log_z || !log_z)
+    return fail(SB_E_INVAL, "bad evidence-at-modes arguments");
+  if (!(eps_grad > 0.0) || !std::isfinite(eps_grad) || !(eps_hess > 0.0) ||
+      !std::isfinite(eps_hess) || !geo_ok(gc))
+    return fail(SB_E_INVAL, "need eps_grad, eps_hess > 0 and a valid geometry configuration");
+  if (!workspace || ws_bytes < sb_user_mode_evidence_geo_workspace_bytes(n, d, gc))
+    return fail(SB_E_NOMEM, "workspace too small");
+  const GeoCfg g = geo_resolve(gc, d, eps_grad);
+  return mode_evidence_impl(fn, n, d, modes, params, lo, hi, eps_hess, g.rot_tol, &g, fperp,
+                            decision, logl, logdet, nullptr, order, mode_log_z, log_z,
+                            workspace, ws_bytes, stream);
+}
+
+size_t sb_user_trajectories_workspace_bytes(int32_t n, int32_t d, int32_t m) {
+  if (n < 1 || d < 1 || m < 1 || m > kMaxMem) return 0;
+  return traj_bytes(n, d, m);
+}
+
+int32_t sb_user_trajectories_dev(const sb_user_fn *fn, int32_t n, int32_t d, const double *modes,
+                                 const double *params, const double *hdiag, double eps,
+                                 int32_t n_iter, int32_t m, double grad_tol, double *fperp,
+                                 double *Xbank, double *Gbank, int32_t *bank_len,
+                                 void *workspace, size_t ws_bytes, void *stream) {
+  if (!fn || n < 1 || d < 1 || !modes || !hdiag || !fperp || n_iter < 1 || m < 1 ||
+      m > kMaxMem || !(eps > 0.0) || !std::isfinite(eps) || !std::isfinite(grad_tol) ||
+      (Xbank && !Gbank) || (!Xbank && Gbank))
+    return fail(SB_E_INVAL, "bad trajectory arguments");
+  if (!workspace || ws_bytes < sb_user_trajectories_workspace_bytes(n, d, m))
+    return fail(SB_E_NOMEM, "workspace too small");
+  Arena ar(workspace, ws_bytes);
+  TrajBuffers T;
+  if (traj_layout(ar, T, n, d, m)) return fail(SB_E_NOMEM, "workspace too small");
+  return run_trajectories(fn, n, d, modes, params, hdiag, eps, n_iter, grad_tol, T, fperp, Xbank,
+                          Gbank, bank_len, nullptr, (hipStream_t)stream);
 }
 
 // Rows of the evidence pipeline's workspace for a user likelihood.
@@ -471,7 +836,9 @@ static int user_layout(Arena &ar, UserLayout &U, int d, const sb_config *c) {
   U.fd_ws = ar.take<char>(U.fd_bytes);
   U.dd_bytes = dedup_ws_bytes((int)B) + 1024;
   U.dd_ws = ar.take<char>(U.dd_bytes);
-  U.me_bytes = sb_user_mode_evidence_workspace_bytes(cap, d);
+  // the mode evidence with both steps of the geometry detection (defaults)
+  sb_geometry_config gc = {0, 0, 0.0, 0.0, 0.0, 0.0};
+  U.me_bytes = sb_user_mode_evidence_geo_workspace_bytes(cap, d, &gc);
   U.me_ws = ar.take<char>(U.me_bytes);
   U.lb.dtype = DT_F64;
   U.lb.B = B;
@@ -611,10 +978,13 @@ int32_t sb_user_evidence_dev(const sb_user_fn *fn, int32_t d, const double *para
   hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)ceil_div((int64_t)n_reps * d, 256)),
                      dim3(256), 0, s, n_reps, d, U.reps, U.Xend, U.modes);
   SB_LAUNCH_CHECK();
-  std::vector<int32_t> full(n_reps);
-  st = sb_user_mode_evidence_dev(fn, n_reps, d, U.modes, params, lo, hi, eps_hess, rot_tol, U.mlogl,
-                                 U.mlogdet, full.data(), U.order, U.mlz, U.logz, U.me_ws,
-                                 U.me_bytes, s);
+  // geometry by the trajectories of GreenDragon's seeds (FD gradients with
+  // step eps), the probe where they are inconclusive
+  sb_geometry_config gc = {0, cfg->m, tol, 0.0, 0.0, rot_tol};
+  const GeoCfg g = geo_resolve(&gc, d, eps);
+  st = mode_evidence_impl(fn, n_reps, d, U.modes, params, lo, hi, eps_hess, rot_tol, &g, nullptr,
+                          nullptr, U.mlogl, U.mlogdet, nullptr, U.order, U.mlz, U.logz, U.me_ws,
+                          U.me_bytes, s);
   if (st) {
     res->log_z = NAN;
     return st;

@@ -189,10 +189,36 @@ def test_orthonormal_matches_oracle(L, C, n, d):
         assert np.allclose(got[c] @ got[c].T, np.eye(n), atol=1e-12)
 
 
-def test_orthonormal_dependent_rows_and_errors(L):
-    G0 = np.random.Generator(np.random.PCG64(86)).normal(size=(1, 3, 5))
-    G0[0, 2] = 2.0 * G0[0, 0] - G0[0, 1]
+@pytest.mark.parametrize("n,d", [(3, 5), (16, 16), (24, 64)])
+def test_orthonormal_dependent_rows_and_errors(L, n, d):
+    """A draw with an out-of-span component of relative size delta: exact combinations and
+    delta = 0.5 x the dependence threshold 8 n eps give NaN for it and every later row,
+    2 x and 1000 x give finite rows; the NaN pattern equals the oracle's exactly.  The rows
+    before the draw equal the oracle's to 1e-10; the draw's own direction is its residual
+    after the projections, whose rounding (~n eps relative to the draw) is a fraction
+    ~n eps / delta of it, so from there on the two factorisations agree to 16 n eps / delta
+    and the GPU rows stay orthonormal to 1e-10."""
+    thr = 8.0 * n * np.finfo(np.float64).eps
+    rng = np.random.Generator(np.random.PCG64(86 + n))
+    k = max(1, n // 2)
+    base = rng.normal(size=(n, d))
+    Qs, _ = np.linalg.qr(base[:k].T, mode="complete")
+    v = Qs[:, k]
+    comb = rng.normal(size=k) @ base[:k]
+    G0 = np.zeros((4, n, d))
+    for c, delta in enumerate((0.0, 0.5 * thr, 2.0 * thr, 1e3 * thr)):
+        G0[c] = base
+        t = delta * np.linalg.norm(comb) / math.sqrt(1.0 - delta * delta)
+        G0[c, k] = comb + t * v
     got = L.sb_chisao_orthonormal_dev(_dev(G0)).cpu().numpy()
-    assert np.all(np.isfinite(got[0, :2])) and np.all(np.isnan(got[0, 2]))
+    ref = O.chisao_orthonormal(G0)
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    assert np.all(np.isnan(got[:2, k:])) and np.all(np.isfinite(got[2:]))
+    eps = np.finfo(np.float64).eps
+    for c, delta in enumerate((0.0, 0.5 * thr, 2.0 * thr, 1e3 * thr)):
+        assert float(np.abs(got[c, :k] - ref[c, :k]).max()) <= 1e-10
+        if c >= 2:
+            assert float(np.abs(got[c, k:] - ref[c, k:]).max()) <= 16 * n * eps / delta
+            assert np.allclose(got[c] @ got[c].T, np.eye(n), atol=1e-10)
     with pytest.raises(RuntimeError):
         L.sb_chisao_orthonormal_dev(_dev(np.zeros((1, 4, 3))))

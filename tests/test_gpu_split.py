@@ -157,3 +157,59 @@ def test_bf16_discovery_every_tile_variant(L, forced_tile, npts):
     gap = ref["ray_best_l"] - lv
     assert float(gap.min()) >= -1e-9
     assert float(np.max(gap / np.maximum(1.0, np.abs(ref["ray_best_l"])))) < 0.05
+
+
+@pytest.mark.parametrize("d,K,B", [(64, 4, 300), (200, 3, 129), (1024, 8, 260)])
+def test_split_pairs_contraction(L, d, K, B):
+    """The contraction of listed (row, component) pairs, as the screened mixture bulk runs it:
+    every listed pair's Y block and q partial sum to the split bound of the oracle's
+    P_k (x - mu_k); unlisted blocks are left untouched.  Rows are listed for one or two
+    components each, with uneven list lengths and an empty component."""
+    import ctypes as C
+
+    rng = np.random.Generator(np.random.PCG64(950 + d))
+    prob = synth.gaussian_mixture(rng, d, K, -8.0, 8.0, 1e-3, 1.0, 0.0, box_half=30.0,
+                                  norm=synth.NORM_DENSITY, linf_min=0.5)
+    prob.mu = prob.mu.astype(np.float32).astype(np.float64)
+    X = synth.random_points(prob, B, 951, spread=0.7).astype(np.float32).astype(np.float64)
+    lists = [[] for _ in range(K)]
+    for r in range(B):
+        lists[r % (K - 1)].append(r)  # component K - 1 gets no rows
+        if r % 3 == 0:
+            lists[(r + 1) % (K - 1)].append(r)
+    cnt = np.array([len(v) for v in lists], dtype=np.int32)
+    rows = np.zeros((K, B), dtype=np.int32)
+    for k in range(K):
+        rows[k, :cnt[k]] = lists[k]
+    m = L.DeviceModel(prob, low_precision=True)
+    Xd = torch.as_tensor(X, device="cuda").float()
+    ntn_max = (d + 63) // 64
+    Y = torch.full((B, K * d), float("nan"), dtype=torch.float32, device="cuda")
+    qp = torch.zeros((B, K, ntn_max), dtype=torch.float32, device="cuda")
+    mv = m.view(L.DTYPE_F32_SPLIT)
+    nt = C.c_int32()
+    g = torch.as_tensor(cnt, device="cuda")
+    rw = torch.as_tensor(rows, device="cuda")
+    st = L.lib().sb_quadform_pairs_dev(C.byref(mv), B, Xd.data_ptr(), g.data_ptr(),
+                                       rw.data_ptr(), B, Y.data_ptr(), qp.data_ptr(),
+                                       C.byref(nt), None)
+    assert st == 0, L.last_error()
+    torch.cuda.synchronize()
+    Yh = Y.double().cpu().numpy().reshape(B, K, d)
+    ntn = nt.value  # q partials are [B][K][ntn] with the launch's tile count
+    qh = qp.double().cpu().numpy().reshape(-1)[:B * K * ntn].reshape(B, K, ntn)
+    listed = np.zeros((B, K), dtype=bool)
+    for k in range(K):
+        listed[rows[k, :cnt[k]], k] = True
+    for b in range(B):
+        for k in range(K):
+            if not listed[b, k]:
+                assert np.all(np.isnan(Yh[b, k]))
+                continue
+            delta = X[b] - prob.mu[k]
+            y_ref = prob.prec[k] @ delta
+            bound = 2.0 ** -14 * (np.abs(prob.prec[k]) @ np.abs(delta)) + 1e-30
+            assert float(np.max(np.abs(Yh[b, k] - y_ref) / bound)) <= 1.0, (b, k)
+            q_ref = float(delta @ y_ref)
+            qb = 2.0 ** -13 * float(np.abs(delta) @ np.abs(prob.prec[k]) @ np.abs(delta)) + 1e-30
+            assert abs(float(qh[b, k].sum()) - q_ref) <= qb, (b, k)

@@ -278,3 +278,102 @@ def test_user_evidence_error_paths(L):
                            seed=2601199599)
     r2 = fm.evidence(7, dev(prob.lo), dev(prob.hi), cfg2, 1e-5, 1e-3, 1e-3, dev(np.array(params)))
     assert r2.status == L.E_CAPACITY
+
+
+# ------------------------------------------- trajectory-based geometry detection
+
+def _zero_sum_rotated(d, seed):
+    """A rotated precision whose off-diagonal entries sum to zero (the probe's b is 0)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    P, _ = synth.random_precision(rng, d, 0.3, 1.0)
+    c = float((P - np.diag(np.diag(P))).sum()) / (d * (d - 1))
+    return P - c * (np.ones((d, d)) - np.eye(d)), rng.uniform(-1, 1, d)
+
+
+def _gauss_params(P, mu, c=0.0):
+    return np.concatenate([P.ravel(), mu, [c]])
+
+
+@pytest.mark.parametrize("kind", ["axis", "rotated", "zero_sum"])
+def test_trajectories_match_oracle(L, kind):
+    """Step 1 on user Gaussians: the largest perpendicular step fraction of GreenDragon's seeds
+    equals the oracle's (both follow the same L-BFGS rules on FD gradients of the same
+    function; the FD rounding, ~eps_mach |f| / eps, moves it by far less than 1e-6); ~0 for an
+    axis-aligned precision; the bank starts at the seeds theta* +- 0.9 / sqrt(-H_ii) e_i."""
+    d = 6
+    if kind == "axis":
+        P = np.diag(np.exp(np.random.default_rng(5).uniform(np.log(0.2), np.log(5.0), d)))
+        mu = np.linspace(-1, 1, d)
+    elif kind == "rotated":
+        P, mu, _, _ = gauss_case(d, 301)
+    else:
+        P, mu = _zero_sum_rotated(d, 302)
+    f = lambda x: -0.5 * (x - mu) @ P @ (x - mu)
+    fn = L.UserLogL(GAUSS_SRC, "gauss")
+    pd = dev(_gauss_params(P, mu))
+    eps, n_iter = 1e-5, 12
+    hd = fn.fd(dev(mu[None]), 1e-3, pd)["hdiag"]
+    out = fn.trajectories(dev(mu[None]), hd, eps, n_iter, m=8, grad_tol=1e-8, params=pd, bank=True)
+    hd_ref = O.fd_derivatives(f, mu[None], 1e-3)["hdiag"]
+    ref = O.trajectory_geometry(f, mu[None], hd_ref, eps, n_iter, m=8, grad_tol=1e-8)
+    got = float(out["fperp"].cpu()[0])
+    print(f"{kind}: f_perp GPU {got:.3e} oracle {ref[0]:.3e}", flush=True)
+    if kind == "axis":
+        assert got <= 1e-6 and ref[0] <= 1e-6
+    else:
+        assert got > 0.05 and abs(got - ref[0]) <= 1e-6
+    # the recorded starts are the seeds theta* +- 0.9 w_i e_i, w_i = 1 / sqrt(-H_ii)
+    h = hd.cpu().numpy()[0]
+    w = 1.0 / np.sqrt(-h)
+    Xb = out["X"].cpu().numpy()[0]
+    for i in range(d):
+        want_p, want_m = mu.copy(), mu.copy()
+        want_p[i] = mu[i] + 0.9 * w[i]
+        want_m[i] = mu[i] - 0.9 * w[i]
+        assert np.array_equal(Xb[2 * i, 0], want_p) and np.array_equal(Xb[2 * i + 1, 0], want_m)
+    assert np.all(out["length"].cpu().numpy() >= 2)
+
+
+def test_geometry_zero_offdiagonal_sum_takes_full_hessian(L):
+    """A rotated Gaussian whose off-diagonals sum to zero: the probe alone (Step 2) takes the
+    diagonal Laplace and misses log Z; with Step 1 the trajectories see the rotation, the full
+    Hessian is taken and log Z is the closed form, as in the oracle."""
+    d = 6
+    P, mu = _zero_sum_rotated(d, 302)
+    f = lambda x: -0.5 * (x - mu) @ P @ (x - mu)
+    fn = L.UserLogL(GAUSS_SRC, "gauss")
+    pd = dev(_gauss_params(P, mu))
+    lo, hi = np.full(d, -10.0), np.full(d, 10.0)
+    exact = 0.5 * d * np.log(2 * np.pi) - 0.5 * np.linalg.slogdet(P)[1] - d * np.log(20.0)
+    probe_only = fn.mode_evidence(dev(mu[None]), dev(lo), dev(hi), 1e-3, 1e-3, pd)
+    assert probe_only["full"] == [0] and abs(probe_only["log_z"] - exact) > 0.05
+    geo = fn.mode_evidence_geo(dev(mu[None]), dev(lo), dev(hi), 1e-5, 1e-3, 1e-3, n_iter=12,
+                               grad_tol=1e-8, params=pd)
+    ref = O.user_mode_evidence_geo(f, mu[None], lo, hi, 1e-3, 1e-3, 12, 1e-4, 1e-2,
+                                   grad_tol=1e-8, eps_grad=1e-5)
+    assert geo["decision"] == [1] and list(ref["decision"]) == [1]
+    assert abs(geo["log_z"] - exact) < 1e-6 and abs(geo["log_z"] - ref["log_z"]) < 1e-7
+
+
+@pytest.mark.parametrize("off,rot_tol,want", [(0.0, 1e-3, 0), (1e-5, 1e-3, 2), (1e-5, 1e-6, 3),
+                                              (3e-3, 1e-3, 1)])
+def test_geometry_decisions_match_oracle(L, off, rot_tol, want):
+    """Axis-aligned (Step 1 says so), a faint uniform correlation whose trajectories are
+    inconclusive (f_perp ~ 3e-4, between 1e-4 and 1e-2, so the probe decides either way with
+    its threshold), and a clearer one (Step 1 says rotated): the GPU's decisions and log Z
+    equal the oracle's."""
+    d = 5
+    P = np.diag(np.linspace(0.5, 2.0, d)) + off * (np.ones((d, d)) - np.eye(d))
+    mu = np.linspace(-0.5, 0.5, d)
+    f = lambda x: -0.5 * (x - mu) @ P @ (x - mu)
+    fn = L.UserLogL(GAUSS_SRC, "gauss")
+    pd = dev(_gauss_params(P, mu))
+    lo, hi = np.full(d, -8.0), np.full(d, 8.0)
+    geo = fn.mode_evidence_geo(dev(mu[None]), dev(lo), dev(hi), 1e-5, 1e-3, rot_tol, n_iter=12,
+                               grad_tol=1e-8, params=pd)
+    ref = O.user_mode_evidence_geo(f, mu[None], lo, hi, 1e-3, rot_tol, 12, 1e-4, 1e-2,
+                                   grad_tol=1e-8, eps_grad=1e-5)
+    print(f"off={off}: decision {geo['decision']} oracle {list(ref['decision'])} "
+          f"f_perp {float(geo['fperp'].cpu()[0]):.3e} / {ref['fperp'][0]:.3e}", flush=True)
+    assert geo["decision"] == list(ref["decision"]) == [want]
+    assert abs(geo["log_z"] - ref["log_z"]) < 1e-7
