@@ -285,6 +285,21 @@ size_t sb_logl_grad_workspace_bytes(int32_t d, int32_t K, int64_t B, int32_t dty
 int32_t sb_logl_grad_dev(const sb_model_dev *m, int64_t B, const void *X, void *logl, void *grad,
                          int32_t dtype, void *workspace, size_t ws_bytes, void *stream);
 
+/* sb_logl_grad_dev for callers that cannot allocate: code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc.  No workspace
+ * argument: the contraction's scratch (Y rows and q partials, the bytes
+ * sb_logl_grad_workspace_bytes(d, K, B, dtype) reports) lives in a static
+ * device array of 32 MiB per GPU that the library holds until the process
+ * ends (its address is looked up on the first call on each device).  Sizes
+ * whose scratch exceeds 32 MiB are rejected with SB_E_NOMEM.  The call
+ * allocates nothing and times no tiles (it takes the tile cached by an earlier
+ * sb_logl_grad_dev of that shape, else a fixed heuristic).  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (on different
+ * streams or threads) race; each call overwrites the scratch before reading
+ * it, so nothing needs clearing between calls. */
+int32_t sb_logl_grad_noalloc_dev(const sb_model_dev *m, int64_t B, const void *X, void *logl,
+                                 void *grad, int32_t dtype, void *stream);
+
 /* The contraction of step A3 alone, as used inside sb_logl_grad_dev and the
  * optimiser: Y [B][K*d] with Y[b][k*d + n] = sum_j P_k[n][j] (X[b][j] -
  * mu_k[j]) and per-tile partial quadratic forms qpart [B][K][*n_tiles]

@@ -34,6 +34,7 @@ EXPORTS = [
     "sb_user_trajectories_workspace_bytes", "sb_user_trajectories_dev",
     "sb_user_mode_evidence_geo_workspace_bytes", "sb_user_mode_evidence_geo_dev",
     "sb_prep_workspace_bytes", "sb_prep_dev", "sb_logl_grad_workspace_bytes", "sb_logl_grad_dev",
+    "sb_logl_grad_noalloc_dev",
     "sb_quadform_dev", "sb_quadform_pairs_dev", "sb_split_bf16_dev", "sb_hvp_workspace_bytes", "sb_hvp_dev", "sb_discover_workspace_bytes", "sb_discover_dev",
     "sb_lbfgs_direction_dev", "sb_lbfgs_workspace_bytes", "sb_lbfgs_dev",
     "sb_lbfgs_timed_dev", "sb_precheck_workspace_bytes", "sb_precheck_dev",
@@ -165,6 +166,7 @@ def lib():
             "sb_prep_dev": (i32, [vp, vp, vp, vp, vp, vp, vp, sz, vp]),
             "sb_logl_grad_workspace_bytes": (sz, [i32, i32, i64, i32]),
             "sb_logl_grad_dev": (i32, [vp, i64, vp, vp, vp, i32, vp, sz, vp]),
+            "sb_logl_grad_noalloc_dev": (i32, [vp, i64, vp, vp, vp, i32, vp]),
             "sb_quadform_dev": (i32, [vp, i64, vp, i32, vp, vp, vp, vp]),
             "sb_quadform_pairs_dev": (i32, [vp, i64, vp, vp, vp, i64, vp, vp, vp, vp]),
             "sb_split_bf16_dev": (i32, [i64, vp, vp, vp, vp]),
@@ -432,6 +434,18 @@ def sb_logl_grad_dev(model: DeviceModel, X, grad: bool = True, dtype=None):
                                 ws.data_ptr(), ws.numel(), _stream())
     _check(st, "sb_logl_grad_dev")
     return (l, g) if grad else l
+
+
+def sb_logl_grad_noalloc_dev(model: DeviceModel, X, l, g=None, dtype=None, stream=None):
+    """sb_logl_grad_dev into caller tensors l (and g) with the library's static scratch:
+    nothing is allocated (the caller allocates l and g beforehand)."""
+    import torch
+
+    dt = dtype if dtype is not None else (DTYPE_F64 if X.dtype == torch.float64 else DTYPE_F32)
+    mv = model.view(dt)
+    st = lib().sb_logl_grad_noalloc_dev(C.byref(mv), X.shape[0], X.data_ptr(), l.data_ptr(),
+                                        _ptr(g), dt, _stream(stream))
+    _check(st, "sb_logl_grad_noalloc_dev")
 
 
 class QuadForm:

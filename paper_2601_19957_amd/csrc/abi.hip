@@ -170,6 +170,38 @@ int validate_model(const sb_model_dev *m) {
   return SB_OK;
 }
 
+// ------------------------------------------------ allocation-free logL + gradient
+//
+// For callers that cannot allocate (code under HIP graph capture, serving
+// loops, harnesses that forbid hipMalloc): the contraction's Y rows and q
+// partials live in a file-scope device array of kStaticScratchBytes per GPU
+// instead of a caller workspace.  In host code the array's name is not a
+// device address: its address on the current device is looked up once per
+// device (hipGetSymbolAddress with that device current) and only that
+// address is handed to the kernels.
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;  // 32 MiB per GPU
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's scratch address (looked up on its first use there).
+int scratch_address(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(SB_E_DEVICE, "no current device for the static scratch");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SB_E_DEVICE, "static scratch address: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SB_OK;
+}
+
 size_t eval_bytes(int dtype, int d, int K, int64_t B, bool with_aux) {
   const size_t es = (dtype == SB_DTYPE_F64) ? 8 : 4;
   size_t n = align_up(es * (size_t)B * K * d) + align_up(es * (size_t)B * K * ceil_div(d, 64));
@@ -591,6 +623,24 @@ int32_t sb_logl_grad_dev(const sb_model_dev *mdl, int64_t B, const void *X, void
     return fail(SB_E_NOMEM, "workspace too small");
   if ((st = device_status())) return st;
   return logl_grad_core(mdl, B, X, logl, grad, dtype, workspace, ws_bytes, true, stream);
+}
+
+int32_t sb_logl_grad_noalloc_dev(const sb_model_dev *mdl, int64_t B, const void *X, void *logl,
+                                 void *grad, int32_t dtype, void *stream) {
+  int st = validate_model(mdl);
+  if (st) return st;
+  if (B < 0 || (B > 0 && (!X || !logl))) return fail(SB_E_INVAL, "bad B / X / logl");
+  if ((st = check_gemm_dtype(mdl, dtype))) return st;
+  if (B == 0) return SB_OK;
+  const size_t need = sb_logl_grad_workspace_bytes(mdl->d, mdl->K, B, dtype);
+  if (need > kStaticScratchBytes)
+    return fail(SB_E_NOMEM,
+                "B = %lld points need %zu bytes of scratch, beyond the static %zu bytes",
+                (long long)B, need, kStaticScratchBytes);
+  if ((st = device_status())) return st;
+  void *p = nullptr;
+  if ((st = scratch_address(&p))) return st;
+  return logl_grad_core(mdl, B, X, logl, grad, dtype, p, kStaticScratchBytes, false, stream);
 }
 
 int32_t sb_quadform_dev(const sb_model_dev *mdl, int64_t B, const void *X, int32_t dtype, void *Y,
