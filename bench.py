@@ -179,7 +179,7 @@ def recorded_lbfgs(summary="profiles/lbfgs_step_B16384_d1024_m8.md",
     return val
 
 
-def time_lbfgs_step(L, prob, cfg, n_timed=40, dtype="f32"):
+def time_lbfgs_step(L, prob, cfg, n_timed=40, dtype="f32", box_starts=False):
     """The L-BFGS step (A4) as the mixed bulk runs it (FP32, one workgroup per start) at full
     batch: sb_lbfgs_timed_dev from the BF16 discovery starts, HIP events around each step
     launch on its stream.  Averaged over the launches in which every start either accepted its
@@ -188,7 +188,9 @@ def time_lbfgs_step(L, prob, cfg, n_timed=40, dtype="f32"):
     the curvature test keeps the new pair out and it is not written; x and g read at both
     slots; s, y, direction and trial point written), a halving one 3 d 4 bytes (point and
     direction read, trial point written).  dtype "f64": the same step in FP64 (the plain
-    path and the polish), 8-byte elements, from the FP64 discovery starts."""
+    path and the polish), 8-byte elements, from the FP64 discovery starts.  box_starts: from
+    points uniform in the box instead (small problems' discovery starts converge before the
+    history ring fills, so no launch would have every start active)."""
     import numpy as np
 
     f64 = dtype == "f64"
@@ -197,12 +199,22 @@ def time_lbfgs_step(L, prob, cfg, n_timed=40, dtype="f32"):
     disc = L.sb_discover_dev(mdl, cfg.n_rays, cfg.n_points, cfg.n_starts, cfg.seed,
                              dtype=L.DTYPE_F64 if f64 else L.DTYPE_BF16)
     X0 = disc["X0"] if f64 else disc["X0"].float()
+    if box_starts:
+        import torch
+        from paper_2601_19957_amd import synth
+
+        Xb = torch.as_tensor(synth.random_points(prob, cfg.n_starts, 17), device="cuda")
+        X0 = Xb if f64 else Xb.float()
     B, d = X0.shape
-    r = L.sb_lbfgs_timed_dev(mdl, X0, m=cfg.m, max_iter=n_timed + 8, n_timed=n_timed)
+    # box starts: no gradient stop, so that every start is still stepping when its ring is full
+    r = L.sb_lbfgs_timed_dev(mdl, X0, m=cfg.m, max_iter=n_timed + 8, n_timed=n_timed,
+                             grad_tol=1e-300 if box_starts else 0.0)
     full, back = r["step_full"].astype(np.int64), r["step_back"].astype(np.int64)
     sel = [i for i in range(n_timed) if int(r["step_rows"][i]) == B and full[i] + back[i] == B
            and full[i] >= 0.99 * B]
     if not sel:
+        log(f"L-BFGS step d={d} {dtype}: no launch with every start stepping and a full ring "
+            f"(rows {r['step_rows'].tolist()}, full {full.tolist()}, halving {back.tolist()})")
         return None
     us = r["step_us"][sel].astype(np.float64)
     per_launch = ((2 * cfg.m + 6) * full[sel] + 3 * back[sel]) * d * float(es)
@@ -229,14 +241,15 @@ def time_lbfgs_step(L, prob, cfg, n_timed=40, dtype="f32"):
 
 def lbfgs_step_variants(L):
     """The L-BFGS step's HBM roofline at c1 (d = 64, 4096 starts), c2 (d = 256, 8192) and c4b
-    (d = 1024, 16384) in FP32 and FP64 (algorithmic bytes (2m + 6) d s per accepting start)."""
+    (d = 1024, 16384) in FP32 and FP64 (algorithmic bytes (2m + 6) d s per accepting start);
+    c1 and c2 from uniform box points, c4b from its discovery starts."""
     from paper_2601_19957_amd import synth
 
     out = {}
     for name in ("c1", "c2", "c4b"):
         prob, cfg = synth.make_workload(name)
         for dt in ("f32", "f64"):
-            r = time_lbfgs_step(L, prob, cfg, n_timed=24, dtype=dt)
+            r = time_lbfgs_step(L, prob, cfg, n_timed=24, dtype=dt, box_starts=name != "c4b")
             if r:
                 out[f"{name}_{dt}"] = {k: r[k] for k in ("achieved", "frac", "avg_launch_us",
                                                          "algorithmic_bytes", "shape", "kernel",
@@ -571,6 +584,37 @@ def uneven_batch(L, serial=False):
     return out
 
 
+def path_only(L, wl, args):
+    """Only the whole path (for profiling one step): warm-up calls, then the timed steps between
+    two boundary kernels (a one-element fill and multiply before, the same after), so that a
+    kernel trace can be cut to exactly the timed steps."""
+    import torch
+
+    stream = torch.cuda.Stream()
+    ex = L.ExecContext()
+    runners = {n: L.EvidenceRunner(p, c, exec=ex) for n, (p, c) in wl.items()}
+    for w in range(args.warmup):
+        for n, r in runners.items():
+            res = r.run(stream)
+            log(f"warmup {w} {n}: {res.seconds[7] * 1e3:.1f} ms")
+    torch.cuda.synchronize()
+    mark = torch.full((1,), 7.0, device="cuda")
+    mark.mul_(3.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        for n, r in runners.items():
+            r.run(stream)
+        log(f"step {k} done")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    mark.mul_(3.0)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(path_only=True, steps=args.steps,
+                          ms_per_step=total / max(1, args.steps) * 1e3)), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -599,6 +643,10 @@ def main() -> int:
                     help="skip the generic-likelihood finite-difference measurement")
     ap.add_argument("--no-chisao", action="store_true",
                     help="skip the ChiSao-moves measurement")
+    ap.add_argument("--no-f32-bulk", action="store_true",
+                    help="skip the whole path with the FP32 matrix-core bulk contraction")
+    ap.add_argument("--path-only", action="store_true",
+                    help="only the whole path between boundary kernels (for profiling one step)")
     ap.add_argument("--no-step-variants", action="store_true",
                     help="skip the L-BFGS step roofline at c1, c2, c4b in FP32 and FP64")
     ap.add_argument("--modules-only", action="store_true",
@@ -639,6 +687,9 @@ def main() -> int:
                               chisao=chisao_leg(L, prob_big, big))),
               flush=True)
         return 0
+
+    if args.path_only:
+        return path_only(L, wl, args)
 
     # ---- roofline of the dominant kernel: the L-BFGS step at full batch
     log("timing the L-BFGS step at full batch")
@@ -727,6 +778,30 @@ def main() -> int:
         log(f"direct launches {n}: {direct[n]:.1f} ms, same result as the graph path: {same}")
         del rd
         torch.cuda.empty_cache()
+
+    # ---- the same mixed path with the FP32 matrix-core contraction in the bulk instead of the
+    # split-BF16 one (the library reads SB_BULK_GEMM at each call)
+    f32_bulk = {}
+    if not args.no_f32_bulk:
+        os.environ["SB_BULK_GEMM"] = "f32"
+        try:
+            for n, (p, c) in wl.items():
+                rf = L.EvidenceRunner(p, c)
+                rf.run(stream)
+                ts = []
+                for _ in range(3):
+                    t1 = time.perf_counter()
+                    resf = rf.run(stream)
+                    ts.append(time.perf_counter() - t1)
+                f32_bulk[n] = dict(ms=float(np.median(ts)) * 1e3, log_z=resf.log_z,
+                                   evals=resf.n_grad_evals, iterations=resf.iterations,
+                                   status=resf.status)
+                log(f"FP32 matrix-core bulk {n}: {f32_bulk[n]['ms']:.1f} ms, log Z "
+                    f"{resf.log_z:.9f}, iters {resf.iterations}")
+                del rf
+                torch.cuda.empty_cache()
+        finally:
+            del os.environ["SB_BULK_GEMM"]
 
     # ---- plain FP64 path, same pipeline and starts
     t64 = {}
@@ -839,6 +914,7 @@ def main() -> int:
         "time_to_logz_cold_ms": {n: cold[n] * 1e3 for n in cold},
         "time_to_logz_host_entry_ms": host or None,
         "time_to_logz_direct_ms": direct,
+        "time_to_logz_f32_matrix_bulk": f32_bulk or None,
         "exec_context": exec_stats,
         "phases_ms": {n: dict(zip(("prep", "discovery", "bulk", "dedup_pre",
                                    "polish_hessian_chol", "dedup_combine"),

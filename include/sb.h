@@ -66,7 +66,8 @@ typedef enum {
   SB_E_DEVICE = -4,      /* HIP runtime error, or no gfx950 device */
   SB_E_NOMODE = -5,      /* no mode passed the filters; log_z = -inf */
   SB_E_CAPACITY = -6,    /* more modes than max_modes; n_modes = modes found */
-  SB_E_UNSUPPORTED = -7  /* valid but not supported (e.g. Student-t with K > 1) */
+  SB_E_UNSUPPORTED = -7, /* valid but not supported (e.g. Student-t with K > 1) */
+  SB_E_NOCONV = -8       /* an iteration stopped at its cap above its tolerance (outputs written) */
 } sb_status;
 
 typedef enum { SB_FAMILY_GAUSS_MIX = 0, SB_FAMILY_STUDENT_T = 1 } sb_family;
@@ -387,7 +388,9 @@ int32_t sb_precheck_dev(const sb_model_dev *m, const double *lo, const double *h
  * used.  The reduced likelihood of a mode theta* is
  * l(theta* + V_inform phi) on the d_eff informative coordinates phi.
  * SB_E_INVAL for bad sizes, thresholds outside 0 <= eps_nuisance <=
- * eps_inform < inf, or non-finite H.  The call synchronises the stream.
+ * eps_inform < inf, or non-finite H; SB_E_NOCONV when some matrix is still
+ * above the off-diagonal bound after 40 sweeps (every output written from the
+ * last sweep, *sweeps = 40).  The call synchronises the stream.
  * Workspace >= sb_eig_reduce_workspace_bytes(C, n). */
 size_t sb_eig_reduce_workspace_bytes(int32_t C, int32_t n);
 int32_t sb_eig_reduce_dev(int32_t C, int32_t n, const double *H, const double *lo,

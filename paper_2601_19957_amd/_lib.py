@@ -18,8 +18,8 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libsb.so")
 
-OK, E_INVAL, E_NOTPD, E_NOMEM, E_DEVICE, E_NOMODE, E_CAPACITY, E_UNSUPPORTED = (
-    0, -1, -2, -3, -4, -5, -6, -7)
+OK, E_INVAL, E_NOTPD, E_NOMEM, E_DEVICE, E_NOMODE, E_CAPACITY, E_UNSUPPORTED, E_NOCONV = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
 FAMILY_GAUSS_MIX, FAMILY_STUDENT_T = 0, 1
 NORM_PEAK_ZERO, NORM_DENSITY = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1

@@ -224,6 +224,7 @@ const char *sb_status_string(int32_t st) {
     case SB_E_NOMODE: return "SB_E_NOMODE: no mode passed the filters";
     case SB_E_CAPACITY: return "SB_E_CAPACITY: more modes than max_modes";
     case SB_E_UNSUPPORTED: return "SB_E_UNSUPPORTED: valid but unsupported request";
+    case SB_E_NOCONV: return "SB_E_NOCONV: an iteration stopped at its cap above its tolerance";
     default: return "unknown status";
   }
 }

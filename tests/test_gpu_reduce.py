@@ -111,3 +111,23 @@ def test_eig_reduce_rejects_bad_thresholds(L):
     lo, hi = dev(-np.ones(3)), dev(np.ones(3))
     with pytest.raises(L.SbError):
         L.sb_eig_reduce_dev(H, lo, hi, 1e-3, 1.0)
+
+
+def test_eig_reduce_reports_the_sweep_cap(L, monkeypatch):
+    """The convergence test runs after the last allowed sweep too: a dense matrix capped at one
+    sweep is still above 4 n eps |A|_F and comes back SB_E_NOCONV (outputs written); with the
+    default cap it converges; a diagonal matrix needs no sweep even with a cap of 0."""
+    rng = np.random.default_rng(7)
+    A = rng.normal(size=(16, 16))
+    H = dev((A @ A.T + 16 * np.eye(16))[None])
+    lo, hi = dev(-np.ones(16)), dev(np.ones(16))
+    monkeypatch.setenv("SB_JACOBI_MAX_SWEEPS", "1")
+    with pytest.raises(L.SbError) as ei:
+        L.sb_eig_reduce_dev(H, lo, hi, 1e-3, 1e-6)
+    assert ei.value.status == L.E_NOCONV and "after 1 sweeps" in str(ei.value)
+    monkeypatch.setenv("SB_JACOBI_MAX_SWEEPS", "0")
+    out = L.sb_eig_reduce_dev(dev(np.diag(np.arange(1.0, 17.0))[None]), lo, hi, 1e-3, 1e-6)
+    assert out["sweeps"] == 0
+    monkeypatch.delenv("SB_JACOBI_MAX_SWEEPS")
+    out = L.sb_eig_reduce_dev(H, lo, hi, 1e-3, 1e-6)
+    assert 1 < out["sweeps"] < 40
