@@ -131,12 +131,24 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
   int64_t mt = 0, M;
   const int32_t *rmap = g.a.rowmap, *ymp = g.ymap;
   if (g.gcnt) {
-    // row tiles of the components one after another (ceil(gcnt[k] / BM) each)
-    const int64_t tt = w / g.ntn;
+    // row tiles of the components one after another (ceil(gcnt[k] / BM) each,
+    // a count above the lists' capacity taken as the capacity), each row tile
+    // followed by its ntn column tiles: T tiles in all.  The grid is a
+    // multiple of 8 and at least T; XCD x takes tiles [x c, (x + 1) c),
+    // c = ceil(T / 8), in order, so the column tiles of a row tile (which
+    // read the same rows of X) run together on one L2.
+    auto cnt = [&](int q) { return (int64_t)min((int64_t)g.gcnt[q], g.gcap); };
+    int64_t nrt = 0;
+    for (int q = 0; q < g.K; ++q) nrt += (cnt(q) + BM - 1) / BM;
+    const int64_t per = (nrt * g.ntn + 7) / 8, li = w / 8;
+    if (li >= per) return;
+    const int64_t t = (w % 8) * per + li;
+    if (t >= nrt * g.ntn) return;
+    const int64_t tt = t / g.ntn;
     int kk = -1;
     int64_t acc = 0;
     for (int q = 0; q < g.K; ++q) {
-      const int64_t nq = ((int64_t)g.gcnt[q] + BM - 1) / BM;
+      const int64_t nq = (cnt(q) + BM - 1) / BM;
       if (kk < 0 && tt < acc + nq) {
         kk = q;
         mt = tt - acc;
@@ -144,8 +156,8 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
       acc += nq;
     }
     if (kk < 0) return;
-    col = kk * g.ntn + (int)(w % g.ntn);
-    M = g.gcnt[kk];
+    col = kk * g.ntn + (int)(t % g.ntn);
+    M = cnt(kk);
     rmap += (int64_t)kk * g.gcap;
     ymp += (int64_t)kk * g.gcap;
   } else {
@@ -587,8 +599,9 @@ int launch_quad_gemm_bf16(int nprod, const Model &m, const ASrc &a, int64_t M,
   o.ntn = p.ntn;
   // (grouped: each component lists at most M rows, so at most K ceil(M / BM)
   // row tiles in all; the tiles past the lists' own end return at once)
-  const int64_t ntile = ceil_div(M, BM) * (int64_t)(m.K * p.ntn);
+  int64_t ntile = ceil_div(M, BM) * (int64_t)(m.K * p.ntn);
   if (ntile == 0) return SB_OK;
+  if (o.gcnt) ntile = ceil_div(ntile, 8) * 8;  // the grouped tile order's XCD split
   if (ntile > 0x7fffffffll) {
     set_error("contraction too large for one launch (%lld tiles)", (long long)ntile);
     return SB_E_UNSUPPORTED;

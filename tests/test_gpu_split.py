@@ -159,12 +159,13 @@ def test_bf16_discovery_every_tile_variant(L, forced_tile, npts):
     assert float(np.max(gap / np.maximum(1.0, np.abs(ref["ray_best_l"])))) < 0.05
 
 
-@pytest.mark.parametrize("d,K,B", [(64, 4, 300), (200, 3, 129), (1024, 8, 260)])
+@pytest.mark.parametrize("d,K,B", [(64, 4, 300), (200, 3, 129), (1024, 8, 260), (256, 6, 2000)])
 def test_split_pairs_contraction(L, d, K, B):
     """The contraction of listed (row, component) pairs, as the screened mixture bulk runs it:
     every listed pair's Y block and q partial sum to the split bound of the oracle's
     P_k (x - mu_k); unlisted blocks are left untouched.  Rows are listed for one or two
-    components each, with uneven list lengths and an empty component."""
+    components each, with uneven list lengths and an empty component; the last case spans
+    several row tiles per component."""
     import ctypes as C
 
     rng = np.random.Generator(np.random.PCG64(950 + d))
