@@ -466,6 +466,41 @@ def eig_reduce(H, lo, hi, eps_inform, eps_nuisance):
                 d_eff=int(np.sum(cls == 0)))
 
 
+def reduced_logl(prob, theta_star, V, r, Phi):
+    """The reduced likelihood of section "Module 4: GraspBirdsTail" (compacted likelihood and
+    algorithm summary): l_red(phi) = l(theta* + V_inform phi) with V_inform the first r
+    columns of V (the informative eigenvectors, eigenvalues in descending order), phi in R^r;
+    the paper writes the displacement as V_info^T phi, read here as the combination of the
+    informative columns (the only product whose shapes agree).  Returns l_red [B] and its
+    gradient V_inform^T grad l [B][r] (chain rule)."""
+    th = _f64(theta_star)
+    Vi = _f64(V)[:, :r]
+    P = np.atleast_2d(_f64(Phi))
+    X = th[None, :] + P @ Vi.T
+    l, g = logl(prob, X)
+    return l, g @ Vi
+
+
+def reduced_bounds(theta_star, V, r, lo, hi):
+    """Bounds in the reduced space (section "Module 4: GraspBirdsTail", its exports): for each
+    informative direction i the interval of t with theta* + t V[:, i] inside the box, i.e.
+    the intersection over coordinates j with V_ji != 0 of the t where lo_j <= theta*_j +
+    t V_ji <= hi_j (a direction that never leaves the box along some coordinate puts no
+    bound there).  Returns (phi_lo [r], phi_hi [r])."""
+    th, Vm, lo, hi = _f64(theta_star), _f64(V), _f64(lo), _f64(hi)
+    plo = np.full(r, -np.inf)
+    phi = np.full(r, np.inf)
+    for i in range(r):
+        for j in range(th.size):
+            v = Vm[j, i]
+            if v == 0.0:
+                continue
+            a, b = (lo[j] - th[j]) / v, (hi[j] - th[j]) / v
+            plo[i] = max(plo[i], min(a, b))
+            phi[i] = min(phi[i], max(a, b))
+    return plo, phi
+
+
 def fd_derivatives(f, X, eps, full=False):
     """Finite-difference derivatives of a generic log-likelihood f (a Python callable on one
     point) at each row of X (appendix "Gradient and Hessian Computation": central-difference

@@ -725,6 +725,67 @@ def test_eig_reduce_axis_aligned_and_invariants(oracle_lib):
     assert abs(r2["logz_marginal"] - r["logz_marginal"]) < 1e-13
 
 
+def _gauss_from_spectrum(mu, P, box=20.0):
+    d = mu.size
+    P = 0.5 * (P + P.T)
+    lam = np.linalg.eigvalsh(P)
+    return synth.Problem(synth.FAMILY_GAUSS_MIX, synth.NORM_DENSITY, d, 1, np.zeros(1), mu[None],
+                         P[None], 0.0, 0.0, np.full(d, -box), np.full(d, box),
+                         np.array([-np.log(lam).sum()]), "spectrum")
+
+
+def test_reduced_logl_closed_form(oracle_lib):
+    """The reduced likelihood of a Gaussian with P = Q diag(lam) Q^T (lam descending) at its
+    mode theta* = mu, along the first r columns of Q: l_red(phi) = (1/2) sum log lam -
+    (d/2) log 2 pi - (1/2) sum_{i<r} lam_i phi_i^2 and its gradient -lam_i phi_i, in closed
+    form from (lam, Q); a displacement read as V^T phi, or another column set, fails both."""
+    O = oracle_lib
+    d, r = 9, 4
+    lam = np.array([40.0, 20.0, 9.0, 5.0, 1.0, 0.5, 0.1, 0.01, 0.001])
+    P, q = constructed_spectrum(d, 73, lam)
+    mu = np.linspace(-1.0, 1.0, d)
+    prob = _gauss_from_spectrum(mu, P)
+    phi = np.random.Generator(np.random.PCG64(74)).normal(size=(5, r))
+    l, g = O.reduced_logl(prob, mu, q, r, phi)
+    ref = 0.5 * np.log(lam).sum() - 0.5 * d * np.log(2 * np.pi) - 0.5 * (phi ** 2 @ lam[:r])
+    assert np.max(np.abs(l - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert np.max(np.abs(g - (-lam[:r] * phi))) <= 1e-11
+
+
+def test_reduced_logl_gradient_central_differences(oracle_lib):
+    """Away from a mode, on a two-component mixture with a Haar-random V: the gradient in phi
+    is the central difference of l_red (the chain rule V_inform^T grad l)."""
+    O = oracle_lib
+    rng = np.random.Generator(np.random.PCG64(75))
+    prob = synth.gaussian_mixture(rng, 6, 2, -3.0, 3.0, 0.2, 2.0, 4.0, box_half=12.0)
+    V = synth.haar_orthogonal(rng, 6)
+    th = rng.uniform(-1.0, 1.0, 6)
+    phi = rng.normal(size=(3, 3))
+    _, g = O.reduced_logl(prob, th, V, 3, phi)
+    h = 1e-6
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = h
+        lp, _ = O.reduced_logl(prob, th, V, 3, phi + e)
+        lm, _ = O.reduced_logl(prob, th, V, 3, phi - e)
+        assert np.allclose((lp - lm) / (2 * h), g[:, i], rtol=1e-6, atol=1e-7)
+
+
+def test_reduced_bounds_hand_values(oracle_lib):
+    """Bounds in the reduced space: axis directions give lo - theta* and hi - theta* (a negated
+    axis the negated, swapped pair); a 45-degree direction in [-1, 1]^2 from (1/2, 0) leaves
+    through x = 1 at t = sqrt(2)/2 and through y = -1 at t = -sqrt(2); a zero component puts
+    no bound."""
+    O = oracle_lib
+    lo, hi = np.array([-1.0, -1.0]), np.array([1.0, 1.0])
+    th = np.array([0.5, 0.0])
+    c = 1.0 / np.sqrt(2.0)
+    V = np.array([[c, 0.0, 1.0], [c, -1.0, 0.0]])
+    plo, phi = O.reduced_bounds(th, V, 3, lo, hi)
+    assert np.allclose(plo, [-np.sqrt(2.0), -1.0, -1.5], atol=1e-15)
+    assert np.allclose(phi, [np.sqrt(2.0) / 2.0, 1.0, 0.5], atol=1e-15)
+
+
 # ------------------------------------------- generic likelihoods: FD derivatives
 
 def test_fd_exact_for_quadratics(oracle_lib):
