@@ -13,7 +13,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsb.so")
 SOURCES = ["gemm.hip", "gemm_bf16.hip", "linalg.hip", "rays.hip", "lbfgs.hip", "dedup.hip", "pipeline.hip",
            "autotune.hip", "batch.hip", "precheck.hip", "reduce.hip", "user.hip", "chisao.hip",
-           "cycle.hip", "abi.hip"]
+           "cycle.hip", "fused.hip", "handoff.hip", "abi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -580,6 +580,16 @@ static int32_t logl_grad_core(const sb_model_dev *mdl, int64_t B, const void *X,
                               bool tune, void *stream) {
   int st;
   Model m = model_for(mdl, dtype);
+  {
+    ASrc a;
+    a.kind = 0;
+    a.X = X;
+    a.ldx = m.d;
+    // small FP64 problems: contraction and epilogue in one launch, no scratch
+    if (dtype == SB_DTYPE_F64 && fused_logl_grad_ok(m, a))
+      return launch_fused_logl_grad(m, a, B, nullptr, nullptr, (double *)logl, (double *)grad,
+                                    m.d, nullptr, (hipStream_t)stream);
+  }
   const size_t es = dtype == SB_DTYPE_F64 ? 8 : 4;
   Arena ar(scratch, scratch_bytes);
   void *Y = ar.take<char>(es * (size_t)B * m.K * m.d);
@@ -644,6 +654,56 @@ int32_t sb_logl_grad_noalloc_dev(const sb_model_dev *mdl, int64_t B, const void 
   return logl_grad_core(mdl, B, X, logl, grad, dtype, p, kStaticScratchBytes, false, stream);
 }
 
+size_t sb_reduced_logl_workspace_bytes(int32_t d, int32_t K, int64_t B) {
+  if (d < 1 || K < 1 || B < 0) return 0;
+  return 2 * align_up(8 * (size_t)B * d) + sb_logl_grad_workspace_bytes(d, K, B, SB_DTYPE_F64);
+}
+
+int32_t sb_reduced_logl_dev(const sb_model_dev *mdl, const double *theta_star, const double *V,
+                            int32_t ldv, int32_t r, int64_t B, const double *phi, double *logl,
+                            double *grad_phi, void *workspace, size_t ws_bytes, void *stream) {
+  int st = validate_model(mdl);
+  if (st) return st;
+  const int d = mdl->d;
+  if (r < 0 || r > d || ldv < (r > 0 ? r : 1) || B < 0 ||
+      (B > 0 && (!theta_star || !logl || (r > 0 && (!V || !phi)))))
+    return fail(SB_E_INVAL, "bad r / ldv / B / arrays");
+  if ((st = check_gemm_dtype(mdl, SB_DTYPE_F64))) return st;
+  if (B == 0) return SB_OK;
+  if (!workspace || ws_bytes < sb_reduced_logl_workspace_bytes(d, mdl->K, B))
+    return fail(SB_E_NOMEM, "workspace too small");
+  if ((st = device_status())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Arena ar(workspace, ws_bytes);
+  double *X = ar.take<double>((size_t)B * d);
+  double *G = ar.take<double>((size_t)B * d);
+  const size_t rest = sb_logl_grad_workspace_bytes(d, mdl->K, B, SB_DTYPE_F64);
+  char *lw = ar.take<char>(rest);
+  if (!ar.ok()) return fail(SB_E_NOMEM, "workspace too small");
+  // theta = theta* + V_inform phi: X[b][j] = theta*_j + sum_i phi[b][i] V[j][i]
+  if ((st = launch_small_gemm_f64(B, d, r, phi, r, V, 1, ldv, theta_star, X, d, s))) return st;
+  if ((st = logl_grad_core(mdl, B, X, logl, grad_phi ? G : nullptr, SB_DTYPE_F64, lw, rest, true,
+                           stream)))
+    return st;
+  // grad_phi[b][i] = sum_j grad[b][j] V[j][i]
+  if (grad_phi && r > 0)
+    return launch_small_gemm_f64(B, r, d, G, d, V, ldv, 1, nullptr, grad_phi, r, s);
+  return SB_OK;
+}
+
+int32_t sb_reduced_bounds_dev(int32_t d, const double *theta_star, const double *V, int32_t ldv,
+                              int32_t r, const double *lo, const double *hi, double *phi_lo,
+                              double *phi_hi, void *stream) {
+  if (d < 1 || r < 0 || r > d || ldv < (r > 0 ? r : 1) ||
+      (r > 0 && (!theta_star || !V || !lo || !hi || !phi_lo || !phi_hi)))
+    return fail(SB_E_INVAL, "bad d / r / ldv / arrays");
+  if (r == 0) return SB_OK;
+  int st = device_status();
+  if (st) return st;
+  return launch_reduced_bounds(d, theta_star, V, ldv, r, lo, hi, phi_lo, phi_hi,
+                               (hipStream_t)stream);
+}
+
 int32_t sb_quadform_dev(const sb_model_dev *mdl, int64_t B, const void *X, int32_t dtype, void *Y,
                         void *qpart, int32_t *n_tiles, void *stream) {
   int st = validate_model(mdl);
@@ -693,7 +753,9 @@ int32_t sb_quadform_pairs_dev(const sb_model_dev *mdl, int64_t B, const void *X,
   o.gcnt = gcnt;
   o.gcap = cap;
   o.qpart = qpart;
-  st = launch_quad_gemm(DT_F32S, m, a, cap, nullptr, o, TileCfg(), (hipStream_t)stream);
+  TileCfg t;  // 128 x 128 (SB_TILE2 overrides it, for measurement)
+  (void)parse_tile(getenv("SB_TILE2"), &t);
+  st = launch_quad_gemm(DT_F32S, m, a, cap, nullptr, o, t, (hipStream_t)stream);
   if (n_tiles) *n_tiles = o.ntn;
   return st;
 }

@@ -117,9 +117,13 @@ struct TileCfg {
   int bm = 128, bn = 128;
   int bk = 32;      // k-tile of the BF16 matrix-core kernels
   int stages = 1;  // BF16 kernels: LDS stages (2 = ping-pong, square tiles, k-tile 32)
+  int sched = 0;   // split ping-pong kernels: bit 0 staggered waves, bit 1 persistent grid
 };
 
 int quad_gemm_ntn(int dtype, int d, TileCfg t);
+// "BMxBN[xBK[xSTAGES[xSCHED]]]" (an environment override) into *t; false if
+// e is null or malformed (t untouched).
+bool parse_tile(const char *e, TileCfg *t);
 // BF16 matrix-core contraction (d a multiple of 8): nprod 1 = BF16 operands,
 // 3 = split FP32 operands (hi*hi + hi*lo + lo*hi); Y and qpart in FP32.
 bool quad_gemm_bf16_ok(int d);
@@ -152,6 +156,24 @@ struct FinishArgs {
   const void *resp = nullptr;
 };
 int launch_finish(int dtype, const Model &m, const FinishArgs &f, hipStream_t s);
+// FP64 logL + gradient of rows of X in one launch (contraction and row
+// epilogue fused; small dimensions: d <= 128, K * round_up(d, 32) <= 384, Gaussian
+// mixture or single-component Student-t).  Same outputs as launch_quad_gemm +
+// launch_finish with FP64 l (aux: responsibilities / q), no Y.
+// C[b][n] = c0[n] + sum_k A[b][k] Bp[k sk + n sn] in FP64 on the matrix
+// cores (c0 nullable; b < B, n < N, k < Kd).
+int launch_small_gemm_f64(int64_t B, int N, int Kd, const double *A, int64_t lda, const double *Bp,
+                          int64_t sk, int64_t sn, const double *c0, double *C, int64_t ldc,
+                          hipStream_t s);
+// Bounds of the reduced box: per column i < r of V [d][ldv] the interval of t
+// with theta* + t V[:, i] inside [lo, hi].
+int launch_reduced_bounds(int d, const double *th, const double *V, int64_t ldv, int r,
+                          const double *lo, const double *hi, double *plo, double *phi,
+                          hipStream_t s);
+bool fused_logl_grad_ok(const Model &m, const ASrc &a);
+int launch_fused_logl_grad(const Model &m, const ASrc &a, int64_t M, const int32_t *count,
+                           const int32_t *outmap, double *logl, double *grad, int64_t ldg,
+                           double *aux, hipStream_t s);
 // Gaussian-mixture rows from FP32 q partials: l, FP32 responsibilities, and
 // per component the rows whose responsibility is not zero.
 struct MixRowsArgs {

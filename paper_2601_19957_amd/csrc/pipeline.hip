@@ -340,6 +340,12 @@ struct Evaluator {
     int st;
     const bool ts = two_stage && want_y && !aux;
     const bool gd = grad_direct && want_y && grad && !aux;
+    // small FP64 problems without a Y consumer (the Hessian assembly reads Y
+    // and passes aux): contraction and epilogue fused in one launch
+    if (!aux && !ts && !gd && dtype == DT_F64 && (gemm_dtype < 0 || gemm_dtype == DT_F64) &&
+        fused_logl_grad_ok(m, a))
+      return launch_fused_logl_grad(m, a, M, count, outmap, (double *)logl, (double *)grad, ldg,
+                                    nullptr, s);
     if (ts) {
       if ((st = contract_two_stage(a, M, count, logl, outmap, logl_f64, s))) return st;
     } else if (gd) {
@@ -492,14 +498,7 @@ static bool bulk_split(const sb_loglik *ll, const RunCfg &rc) {
 }
 // SB_TILE2=BMxBN[xBK[xSTAGES]] forces the screened contraction's tile.
 static TileCfg env_tile(const char *name, TileCfg t) {
-  const char *e = getenv(name);
-  int bm = 0, bn = 0, bk = 32, st = 1;
-  if (e && sscanf(e, "%dx%dx%dx%d", &bm, &bn, &bk, &st) >= 2) {
-    t.bm = bm;
-    t.bn = bn;
-    t.bk = bk;
-    t.stages = st;
-  }
+  (void)parse_tile(getenv(name), &t);
   return t;
 }
 static bool bulk_screen() {

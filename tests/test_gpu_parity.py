@@ -107,6 +107,29 @@ def test_logl_grad_fp64(L, name, B):
     assert el < 1e-11 and eg < 1e-11, (el, eg)
 
 
+@pytest.mark.parametrize("make", [lambda: small_mixture(96, 4, 21), lambda: t_problem(5, 22),
+                                  lambda: small_mixture(1, 1, 23), lambda: t_problem(128, 24)],
+                         ids=["mix_d96_K4", "t_d5", "gauss_d1", "t_d128"])
+def test_logl_grad_fp64_fused_equals_two_launch(L, make, monkeypatch):
+    """Small FP64 problems take the fused launch (contraction and row epilogue in one kernel,
+    d <= 128 and K * round_up(d, 32) <= 384: the first case sits at the second edge, the last
+    at the first); on a ragged last row
+    tile its l equals the two-launch path's (SB_FUSED=0) to a few ulps of the O(d) sums, and l
+    and the gradient equal the oracle's to 1e-11.  The two paths' gradients agree only as
+    closely as their responsibilities: r_k = exp(a_k - lse) moves by r_k |dq_k| / 2, and q
+    of a few 1e4 at these points carries ~1e-12 of summation-order rounding."""
+    prob = make()
+    B = 16 * 7 + 3
+    X = synth.random_points(prob, B, 25, spread=0.9)
+    m = L.DeviceModel(prob)
+    l1, g1 = (t.cpu().numpy() for t in L.sb_logl_grad_dev(m, dev(X)))
+    monkeypatch.setenv("SB_FUSED", "0")
+    l2, g2 = (t.cpu().numpy() for t in L.sb_logl_grad_dev(m, dev(X)))
+    lo, go = O.logl(prob, X)
+    assert rel(l1, l2) < 1e-13 and rel(g1, g2, axis=1) < 1e-11
+    assert rel(l1, lo) < 1e-11 and rel(g1, go, axis=1) < 1e-11
+
+
 @pytest.mark.parametrize("name", ["mix_d37_K3", "c1", "t_d256"])
 def test_logl_grad_fp32(L, name):
     prob = PROBLEMS[name]()
