@@ -399,6 +399,35 @@ int32_t sb_eig_reduce_dev(int32_t C, int32_t n, const double *H, const double *l
                           int32_t *d_eff, int32_t *sweeps, void *workspace, size_t ws_bytes,
                           void *stream);
 
+/* The reduced likelihood for sampler handoff (section "Module 4:
+ * GraspBirdsTail": compacted likelihood, algorithm summary and exports):
+ * l_red(phi) = l(theta* + V_inform phi), V_inform the first r columns of V
+ * [d][ldv] (device, row-major; column i a direction, e.g. the informative
+ * eigenvectors sb_eig_reduce_dev returns first, r = d_eff), theta* [d]
+ * (device) the mode, phi [B][r] (device) points in the reduced coordinates.
+ * Writes logl [B] (device) and, if grad_phi != NULL, grad_phi [B][r] =
+ * V_inform^T grad l (device).  FP64 throughout: the points by one FP64
+ * matrix-core product, then sb_logl_grad_dev's FP64 path, then the chain rule
+ * by a second product.  0 <= r <= d, ldv >= max(r, 1); the model needs its
+ * FP64 data.  SB_E_INVAL for bad sizes or NULL arrays, SB_E_NOMEM for a
+ * short workspace.  Workspace >= sb_reduced_logl_workspace_bytes(d, K, B). */
+size_t sb_reduced_logl_workspace_bytes(int32_t d, int32_t K, int64_t B);
+int32_t sb_reduced_logl_dev(const sb_model_dev *m, const double *theta_star, const double *V,
+                            int32_t ldv, int32_t r, int64_t B, const double *phi, double *logl,
+                            double *grad_phi, void *workspace, size_t ws_bytes, void *stream);
+
+/* Bounds of the reduced box (section "Module 4: GraspBirdsTail", exports):
+ * for each of the first r columns v of V [d][ldv] (device) the interval
+ * [phi_lo_i, phi_hi_i] (device [r]) of t with theta* + t v inside the box
+ * [lo, hi] (device [d]): the intersection over the coordinates j with v_j != 0
+ * of the t where lo_j <= theta*_j + t v_j <= hi_j (a column of zeros gives
+ * [-inf, inf]; theta* outside the box an empty interval, lo > hi).  Exact
+ * IEEE divisions, minima and maxima: no rounding beyond the divisions.
+ * SB_E_INVAL for bad sizes or NULL arrays.  No workspace. */
+int32_t sb_reduced_bounds_dev(int32_t d, const double *theta_star, const double *V, int32_t ldv,
+                              int32_t r, const double *lo, const double *hi, double *phi_lo,
+                              double *phi_hi, void *stream);
+
 /* ChiSao stick detection (section "ChiSao Exploration": the oscillation
  * cycle's stick step and the CarryTiger algorithm summary).  For B samples
  * with values logl [B] and gradients grad [B][d] (device FP64), stuck [B]

@@ -38,7 +38,8 @@ EXPORTS = [
     "sb_quadform_dev", "sb_quadform_pairs_dev", "sb_split_bf16_dev", "sb_hvp_workspace_bytes", "sb_hvp_dev", "sb_discover_workspace_bytes", "sb_discover_dev",
     "sb_lbfgs_direction_dev", "sb_lbfgs_workspace_bytes", "sb_lbfgs_dev",
     "sb_lbfgs_timed_dev", "sb_precheck_workspace_bytes", "sb_precheck_dev",
-    "sb_eig_reduce_workspace_bytes", "sb_eig_reduce_dev", "sb_chisao_stick_dev",
+    "sb_eig_reduce_workspace_bytes", "sb_eig_reduce_dev", "sb_reduced_logl_workspace_bytes",
+    "sb_reduced_logl_dev", "sb_reduced_bounds_dev", "sb_chisao_stick_dev",
     "sb_chisao_explore_workspace_bytes", "sb_chisao_explore_dev",
     "sb_chisao_reseed_workspace_bytes", "sb_chisao_reseed_dev", "sb_chisao_orthonormal_dev",
     "sb_user_compile", "sb_user_release",
@@ -184,6 +185,9 @@ def lib():
             "sb_precheck_workspace_bytes": (sz, [i32, i32]),
             "sb_precheck_dev": (i32, [vp, vp, vp, f64, f64, vp, vp, vp, vp, vp, sz, vp]),
             "sb_eig_reduce_workspace_bytes": (sz, [i32, i32]),
+            "sb_reduced_logl_workspace_bytes": (sz, [i32, i32, i64]),
+            "sb_reduced_logl_dev": (i32, [vp, vp, vp, i32, i32, i64, vp, vp, vp, vp, sz, vp]),
+            "sb_reduced_bounds_dev": (i32, [i32, vp, vp, i32, i32, vp, vp, vp, vp, vp]),
             "sb_eig_reduce_dev": (i32, [i32, i32, vp, vp, vp, f64, f64, vp, vp, vp, vp, vp, vp,
                                         vp, sz, vp]),
             "sb_chisao_stick_dev": (i32, [i64, i32, vp, vp, f64, vp, vp, sz, vp]),
@@ -448,6 +452,29 @@ def sb_logl_grad_noalloc_dev(model: DeviceModel, X, l, g=None, dtype=None, strea
     _check(st, "sb_logl_grad_noalloc_dev")
 
 
+class LoglGrad:
+    """Repeated sb_logl_grad_dev calls on fixed buffers (outputs and workspace allocated once),
+    so that a timing loop measures the launches, not the allocations."""
+
+    def __init__(self, model: DeviceModel, X, dtype=None, grad: bool = True):
+        import torch
+
+        self.dt = dtype if dtype is not None else (
+            DTYPE_F64 if X.dtype == torch.float64 else DTYPE_F32)
+        self.X = X.contiguous()
+        B = X.shape[0]
+        self.l = torch.empty(B, dtype=X.dtype, device=X.device)
+        self.g = torch.empty_like(self.X) if grad else None
+        self.ws = _ws(lib().sb_logl_grad_workspace_bytes(model.d, model.K, B, self.dt), X.device)
+        self.mv = model.view(self.dt)
+        self.args = (C.byref(self.mv), B, self.X.data_ptr(), self.l.data_ptr(), _ptr(self.g),
+                     self.dt, self.ws.data_ptr(), self.ws.numel())
+
+    def __call__(self, stream=None):
+        st = lib().sb_logl_grad_dev(*self.args, _stream(stream))
+        _check(st, "sb_logl_grad_dev")
+
+
 class QuadForm:
     """Repeated launches of the A3 contraction alone (sb_quadform_dev) on fixed buffers."""
 
@@ -596,6 +623,44 @@ def sb_precheck_dev(model: DeviceModel, eps_flat: float = 0.0, eps_soft: float =
                                ws.numel(), _stream())
     _check(st, "sb_precheck_dev")
     return dict(s=s, cls=cls, logz_marginal=lz, n_flat=nfl[0], n_soft=nfl[1])
+
+
+def sb_reduced_logl_dev(model: DeviceModel, theta_star, V, r: int, phi, grad: bool = True):
+    """The reduced likelihood l(theta* + V[:, :r] phi) (device FP64) and its gradient in phi."""
+    import torch
+
+    dev = model.mu.device
+    th = theta_star.to(device=dev, dtype=torch.float64).contiguous()
+    Vd = V.to(device=dev, dtype=torch.float64).contiguous()
+    P = phi.to(device=dev, dtype=torch.float64).contiguous().reshape(-1, max(r, 1))[:, :r]
+    P = P.contiguous()
+    B, d = P.shape[0], model.d
+    logl = torch.empty(B, dtype=torch.float64, device=dev)
+    gp = torch.empty((B, r), dtype=torch.float64, device=dev) if grad else None
+    ws = _ws(lib().sb_reduced_logl_workspace_bytes(d, model.K, B), dev)
+    st = lib().sb_reduced_logl_dev(C.byref(model.view(DTYPE_F64)), th.data_ptr(), Vd.data_ptr(),
+                                   Vd.shape[1], r, B, P.data_ptr(), logl.data_ptr(),
+                                   gp.data_ptr() if grad else None, ws.data_ptr(), ws.numel(),
+                                   _stream())
+    _check(st, "sb_reduced_logl_dev")
+    return (logl, gp) if grad else logl
+
+
+def sb_reduced_bounds_dev(theta_star, V, r: int, lo, hi):
+    """Per direction i < r the interval of t with theta* + t V[:, i] inside [lo, hi]."""
+    import torch
+
+    dev = theta_star.device
+    Vd = V.to(dtype=torch.float64).contiguous()
+    d = Vd.shape[0]
+    plo = torch.empty(r, dtype=torch.float64, device=dev)
+    phi = torch.empty(r, dtype=torch.float64, device=dev)
+    st = lib().sb_reduced_bounds_dev(d, theta_star.contiguous().data_ptr(), Vd.data_ptr(),
+                                     Vd.shape[1], r, lo.contiguous().data_ptr(),
+                                     hi.contiguous().data_ptr(), plo.data_ptr(), phi.data_ptr(),
+                                     _stream())
+    _check(st, "sb_reduced_bounds_dev")
+    return plo, phi
 
 
 def sb_eig_reduce_dev(H, lo, hi, eps_inform: float, eps_nuisance: float):

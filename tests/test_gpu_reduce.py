@@ -131,3 +131,95 @@ def test_eig_reduce_reports_the_sweep_cap(L, monkeypatch):
     monkeypatch.delenv("SB_JACOBI_MAX_SWEEPS")
     out = L.sb_eig_reduce_dev(H, lo, hi, 1e-3, 1e-6)
     assert 1 < out["sweeps"] < 40
+
+
+# ------------------------------------------------- reduced likelihood (sampler handoff)
+
+def _rel(a, ref, axis=None):
+    a, ref = np.asarray(a, dtype=np.float64), np.asarray(ref, dtype=np.float64)
+    sc = np.maximum(1.0, np.abs(ref) if axis is None else np.abs(ref).max(axis=axis, keepdims=True))
+    return float(np.max(np.abs(a - ref) / sc)) if a.size else 0.0
+
+
+@pytest.mark.parametrize("r,pad", [(0, 0), (5, 0), (37, 0), (7, 3)])
+def test_reduced_logl_matches_oracle(L, r, pad):
+    """l(theta* + V_inform phi) and its gradient in phi against the oracle's, on a three-
+    component mixture at d = 37 with a Haar-random V (r of its columns; pad: V's rows wider
+    than r, ldv = r + pad), 131 points (ragged row tiles)."""
+    rng = np.random.Generator(np.random.PCG64(880 + r))
+    prob = synth.gaussian_mixture(rng, 37, 3, -4.0, 4.0, 0.1, 2.0, 5.0, box_half=15.0)
+    V = synth.haar_orthogonal(rng, 37)[:, :max(r, 1)]
+    if pad:
+        V = np.concatenate([V, rng.normal(size=(37, pad))], axis=1)
+    th = rng.uniform(-2.0, 2.0, 37)
+    phi = rng.normal(size=(131, r))
+    m = L.DeviceModel(prob)
+    l, g = L.sb_reduced_logl_dev(m, dev(th), dev(V), r, dev(phi))
+    lo, go = O.reduced_logl(prob, th, V, r, phi)
+    assert _rel(l.cpu().numpy(), lo) < 1e-11
+    if r:
+        assert _rel(g.cpu().numpy(), go, axis=1) < 1e-11
+
+
+def test_reduced_logl_after_eig_reduce_closed_form(L):
+    """The handoff chain on the GPU: Hessian at the mode of a Gaussian of constructed spectrum
+    (sb_hessian_dev), its reduction (sb_eig_reduce_dev: d_eff and V), then the reduced
+    likelihood, which equals l(mu) - (1/2) sum_{i < d_eff} lam_i phi_i^2 in closed form.  The
+    constant l(mu) = (1/2) log det P - (d/2) log 2 pi is compared on its own to a looser bound:
+    with eigenvalues down to 1e-9 next to 80, log det P carries ~1e-6 of rounding on any FP64
+    route (eigvalsh's or a Cholesky's)."""
+    d = 24
+    rng = np.random.Generator(np.random.PCG64(881))
+    q = synth.haar_orthogonal(rng, d)
+    lam = np.concatenate([np.geomspace(80.0, 3.0, 9), np.geomspace(0.5, 0.01, 10),
+                          np.geomspace(1e-7, 1e-9, 5)])
+    P = (q * lam[None, :]) @ q.T
+    P = 0.5 * (P + P.T)
+    mu = rng.uniform(-1.0, 1.0, d)
+    prob = synth.Problem(synth.FAMILY_GAUSS_MIX, synth.NORM_DENSITY, d, 1, np.zeros(1),
+                         mu[None], P[None], 0.0, 0.0, np.full(d, -1e3), np.full(d, 1e3),
+                         np.array([-np.log(np.linalg.eigvalsh(P)).sum()]), "spectrum")
+    m = L.DeviceModel(prob)
+    H = L.sb_hessian_dev(m, dev(mu[None]))
+    r = L.sb_eig_reduce_dev(H, dev(prob.lo), dev(prob.hi), 1.0, 1e-4)
+    d_eff = int(r["d_eff"][0])
+    assert d_eff == 9
+    V = r["V"][0]
+    phi = rng.normal(size=(50, d_eff))
+    phi[0] = 0.0
+    l, g = L.sb_reduced_logl_dev(m, dev(mu), V, d_eff, dev(phi))
+    l = l.cpu().numpy()
+    l0 = 0.5 * np.log(lam).sum() - 0.5 * d * np.log(2 * np.pi)
+    assert abs(l[0] - l0) < 1e-5
+    assert _rel(l - l[0], -0.5 * (phi ** 2 @ lam[:d_eff])) < 1e-9
+    assert _rel(g.cpu().numpy(), -lam[:d_eff] * phi, axis=1) < 1e-9
+
+
+def test_reduced_bounds_match_oracle(L):
+    """Bounds of the reduced box equal the oracle's bit for bit (divisions, minima and maxima
+    only), for a Haar-random V with one zero column and one axis column, theta* inside the
+    box; errors for r > d and ldv < r."""
+    import ctypes as C
+
+    d = 50
+    rng = np.random.Generator(np.random.PCG64(882))
+    V = synth.haar_orthogonal(rng, d)
+    V[:, 3] = 0.0
+    V[:, 4] = 0.0
+    V[7, 4] = -1.0
+    lo, hi = -rng.uniform(1.0, 3.0, d), rng.uniform(1.0, 3.0, d)
+    th = rng.uniform(-0.5, 0.5, d)
+    plo, phi = L.sb_reduced_bounds_dev(dev(th), dev(V), d, dev(lo), dev(hi))
+    rlo, rhi = O.reduced_bounds(th, V, d, lo, hi)
+    assert np.array_equal(plo.cpu().numpy(), rlo) and np.array_equal(phi.cpu().numpy(), rhi)
+    assert rlo[3] == -np.inf and rhi[3] == np.inf
+    t = dev(np.zeros(2))
+    for rr, ldv in ((d + 1, d + 1), (5, 4)):
+        st = L.lib().sb_reduced_bounds_dev(d, t.data_ptr(), t.data_ptr(), ldv, rr, t.data_ptr(),
+                                           t.data_ptr(), t.data_ptr(), t.data_ptr(), None)
+        assert st == L.E_INVAL
+    m = L.DeviceModel(synth.make_problem("c0"))
+    st = L.lib().sb_reduced_logl_dev(C.byref(m.view(L.DTYPE_F64)), t.data_ptr(), t.data_ptr(),
+                                     4, 2, 8, t.data_ptr(), t.data_ptr(), None, t.data_ptr(), 8,
+                                     None)
+    assert st == L.E_NOMEM
