@@ -122,17 +122,22 @@ def a3_variants(L):
         flops = 2.0 * B * prob.K * prob.d ** 2 + 4.0 * B * prob.K * prob.d
         for dt in dts:
             X = X64 if dt == L.DTYPE_F64 else X64.float()
-            reps = 5 if prob.d * prob.K >= 4096 and dt == L.DTYPE_F64 else 10
-            L.sb_logl_grad_dev(m, X, dtype=dt)  # warm (code objects, tile cache)
+            # small problems: many launches, so that the GPU time, not the host's submission
+            # time, sets the pace (buffers and workspace allocated once)
+            reps = 5 if prob.d * prob.K >= 4096 and dt == L.DTYPE_F64 else (
+                10 if prob.d >= 1024 else 200)
+            call = L.LoglGrad(m, X, dtype=dt)
+            call()  # warm (code objects, tile cache)
             st = torch.cuda.current_stream()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
             e0.record(st)
             for _ in range(reps):
-                L.sb_logl_grad_dev(m, X, dtype=dt)
+                call(st)
             e1.record(st)
             torch.cuda.synchronize()
             sec = e0.elapsed_time(e1) / reps / 1e3
+            del call
             lab, pk = names[dt]
             out.append(dict(config=name, d=prob.d, K=prob.K, batch=B, dtype=lab,
                             ms=sec * 1e3, evals_per_s=B / sec, tflops=flops / sec / 1e12,
@@ -189,8 +194,10 @@ def time_lbfgs_step(L, prob, cfg, n_timed=40, dtype="f32", box_starts=False):
     slots; s, y, direction and trial point written), a halving one 3 d 4 bytes (point and
     direction read, trial point written).  dtype "f64": the same step in FP64 (the plain
     path and the polish), 8-byte elements, from the FP64 discovery starts.  box_starts: from
-    points uniform in the box instead (small problems' discovery starts converge before the
-    history ring fills, so no launch would have every start active)."""
+    points one standard deviation around the modes instead, without a gradient stop (small
+    problems' discovery starts converge before the history ring fills, and from far points
+    the curvature test keeps pairs out of a non-convex region, so no launch would have every
+    start accepting with a full ring)."""
     import numpy as np
 
     f64 = dtype == "f64"
@@ -203,10 +210,11 @@ def time_lbfgs_step(L, prob, cfg, n_timed=40, dtype="f32", box_starts=False):
         import torch
         from paper_2601_19957_amd import synth
 
-        Xb = torch.as_tensor(synth.random_points(prob, cfg.n_starts, 17), device="cuda")
+        Xb = torch.as_tensor(synth.points_near_modes(prob, cfg.n_starts, 17, scale=1.0),
+                             device="cuda")
         X0 = Xb if f64 else Xb.float()
     B, d = X0.shape
-    # box starts: no gradient stop, so that every start is still stepping when its ring is full
+    # near starts: no gradient stop, so that every start is still stepping when its ring is full
     r = L.sb_lbfgs_timed_dev(mdl, X0, m=cfg.m, max_iter=n_timed + 8, n_timed=n_timed,
                              grad_tol=1e-300 if box_starts else 0.0)
     full, back = r["step_full"].astype(np.int64), r["step_back"].astype(np.int64)
@@ -242,7 +250,7 @@ def time_lbfgs_step(L, prob, cfg, n_timed=40, dtype="f32", box_starts=False):
 def lbfgs_step_variants(L):
     """The L-BFGS step's HBM roofline at c1 (d = 64, 4096 starts), c2 (d = 256, 8192) and c4b
     (d = 1024, 16384) in FP32 and FP64 (algorithmic bytes (2m + 6) d s per accepting start);
-    c1 and c2 from uniform box points, c4b from its discovery starts."""
+    c1 and c2 from points around the modes, c4b from its discovery starts."""
     from paper_2601_19957_amd import synth
 
     out = {}
@@ -456,6 +464,42 @@ def chisao_leg(L, prob, name, reps=3):
                             logl_evals_per_s=Br * npt / dr))
 
 
+def chisao_cycle_leg(L):
+    """The ChiSao oscillation cycle (sb_evidence_chisao_dev, FP64) beside the single
+    convergence phase: on the hidden-mode mixture at d = 16 (a narrow heavy component the
+    coarse rays miss beside a wide one: one phase finds one mode, the cycle both; 256 rays x
+    32 points, 16 starts, three oscillations) and on c1's K = 4 mixture at d = 64 with its
+    4096 starts (three oscillations): wall time of each after a warm call, modes found, and
+    |log Z - the reference mode set's| (Newton from every component mean, on the host)."""
+    import oracle as O
+    from paper_2601_19957_amd import synth
+
+    out = {}
+    cases = [("hidden_d16", synth.hidden_mode_mixture(16, 13),
+              synth.RunConfig(n_rays=256, n_points=32, n_starts=16, seed=79),
+              L.ChiSaoConfig(n_osc=3, n_anti=10, alpha_anti=0.05))]
+    p1, c1 = synth.make_workload("c1")
+    cases.append(("c1", p1, c1, L.ChiSaoConfig(n_osc=3, n_anti=4, alpha_anti=0.01)))
+    for name, prob, cfg, cc in cases:
+        ref = O.reference_modes(prob)
+        row = dict(d=prob.d, K=prob.K, n_starts=cfg.n_starts, n_osc=cc.n_osc,
+                   reference_modes=int(ref.n_modes))
+        for lab, run in (("single_phase", L.EvidenceRunner(prob, cfg)),
+                         ("cycle", L.EvidenceRunner(prob, cfg, chisao=cc))):
+            run.run()
+            t0 = time.perf_counter()
+            r = run.run()
+            dt = time.perf_counter() - t0
+            row[lab] = dict(ms=dt * 1e3, modes=int(r.n_modes), log_z=float(r.log_z),
+                            dlogz_vs_reference=abs(float(r.log_z) - float(ref.log_z)),
+                            grad_evals=int(r.n_grad_evals))
+        out[name] = row
+        log(f"ChiSao cycle {name}: single phase {row['single_phase']['modes']} modes in "
+            f"{row['single_phase']['ms']:.1f} ms, cycle {row['cycle']['modes']} modes in "
+            f"{row['cycle']['ms']:.1f} ms (reference {row['reference_modes']})")
+    return out
+
+
 def reduce_leg(L, prob, name):
     """Dimensional reduction at the modes (Jacobi eigendecomposition of the K mode Hessians,
     FP64; the precisions, to which the separated mixture's mode Hessians are equal to e^-60):
@@ -655,6 +699,8 @@ def main() -> int:
                     help="only the roofline kernel timing (for profiling that kernel)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with the 1 GiB device copy that calibrates HBM byte counters")
+    ap.add_argument("--a3-only", action="store_true",
+                    help="only the logL+grad legs (a3_variants) and the L-BFGS step variants")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -675,6 +721,10 @@ def main() -> int:
     if args.batch_only:
         print(json.dumps(dict(batch_only=True, uneven_batch=uneven_batch(L, args.batch_serial))),
               flush=True)
+        return 0
+    if args.a3_only:
+        print(json.dumps(dict(a3_only=True, a3_variants=a3_variants(L),
+                              lbfgs_step_variants=lbfgs_step_variants(L))), flush=True)
         return 0
     names = [n.strip() for n in args.workload.split(",") if n.strip()]
     log(f"generating {names}")
@@ -873,6 +923,7 @@ def main() -> int:
     if not args.no_chisao:
         chi = chisao_leg(L, prob_big, big)
         log(f"ChiSao moves {big}: {chi['ms']:.1f} ms, {chi['grad_evals_per_s']:.3g} grad evals/s")
+        chi["cycle"] = chisao_cycle_leg(L)
 
     a3 = None
     if not args.no_a3:
