@@ -176,19 +176,21 @@ bool time_candidates(int dtype, int d, int K, int64_t M, hipStream_t s, TileCfg 
 }
 }  // namespace
 
+bool parse_tile(const char *e, TileCfg *t) {
+  int bm = 0, bn = 0, bk = 32, st = 1;
+  if (!e || sscanf(e, "%dx%dx%dx%d", &bm, &bn, &bk, &st) < 2) return false;
+  t->bm = bm;
+  t->bn = bn;
+  t->bk = bk;
+  t->stages = st;
+  return true;
+}
+
 TileCfg autotune_tiles(int dtype, const Model &m, int64_t M, hipStream_t s, const TuneProbe *probe,
                        bool may_alloc) {
-  const char *force = getenv("SB_TILE");
-  if (force) {
-    int bm = 0, bn = 0, bk = 32, st = 1;
-    if (sscanf(force, "%dx%dx%dx%d", &bm, &bn, &bk, &st) >= 2) {
-      TileCfg t;
-      t.bm = bm;
-      t.bn = bn;
-      t.bk = bk;
-      t.stages = st;
-      return t;
-    }
+  {
+    TileCfg t;
+    if (parse_tile(getenv("SB_TILE"), &t)) return t;
   }
   const char *at = getenv("SB_AUTOTUNE");
   const bool timed = !(at && at[0] == '0');

@@ -73,15 +73,14 @@ struct Bf16Occ {
           : ((BM == 128 && BN == 128) ? ((BK == 32 && !(KIND == 1 && NPROD == 3)) ? 3 : 2) : 1);
 };
 
+// One output tile (w: the tile's index in the launch's tile order).
 // NT = 64 * WGM * WGN threads: a WGM x WGN grid of waves, each owning a
 // (BM / WGM) x (BN / WGN) block of the tile.  NS LDS stages: with one, a
 // k-tile is stored, multiplied and released between two barriers; with two
 // (ping-pong), the split and store of k-tile t + 1 run beside the MFMAs of
 // k-tile t, one barrier per k-tile.
-template <int NPROD, int KIND, int BM, int BN, int BK, int WGM = 2, int WGN = 2, int NS = 1>
-__global__ __launch_bounds__(64 * WGM * WGN,
-                             (Bf16Occ<BM, BN, BK, KIND, NPROD, 64 * WGM * WGN, NS>::value))
-void quad_gemm_bf16_kernel(Bf16Params g) {
+template <int NPROD, int KIND, int BM, int BN, int BK, int WGM, int WGN, int NS>
+__device__ __forceinline__ void bf16_tile(const Bf16Params &g, const int64_t w, const int tid) {
   constexpr int NT = 64 * WGM * WGN;
   // LDS rows of BK bf16 without padding; the 16-byte chunk c of row r sits
   // at chunk c ^ swz(r), swz(r) = (r / R) mod C (C chunks per row, R rows per
@@ -126,7 +125,6 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
   // in order, so the workgroups sharing an M-tile's rows of A run together
   // on one L2 and the XCD's column blocks of P stay resident in it.
   const int ncol = g.K * g.ntn;
-  const int64_t w = blockIdx.x;
   int col = 0;
   int64_t mt = 0, M;
   const int32_t *rmap = g.a.rowmap, *ymp = g.ymap;
@@ -187,7 +185,7 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
   const float *mu = g.mu + (size_t)k * d;
   const char *Phb = (const char *)(g.Phi + (size_t)k * d * d);
   const char *Plb = SPLIT ? (const char *)(g.Plo + (size_t)k * d * d) : nullptr;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
 
   // Element offset of point row `row`'s data (kind 0: its X row; kind 1: its
@@ -380,20 +378,26 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
       __syncthreads();
     }
   } else {
-    // k-tile t sits in stage t & 1; the registers loaded during k-tile t
-    // are split and stored into the other stage after t's MFMAs are issued
+    // k-tile t sits in stage t & 1.  On entry to iteration t the registers
+    // hold k-tile t + 1; its split and store into the other stage, and then
+    // the loads of k-tile t + 2, may come before or after the MFMAs of k-tile
+    // t (between two barriers nothing else touches the other stage)
     store(0);
     __syncthreads();
     const int nk = (d + BK - 1) / BK;
+    int t = kbeg / BK;
+    if (t + 1 < nk) load((t + 1) * BK);
     int st = 0;
-    for (int t = kbeg / BK; t + 1 < nk; ++t) {
-      load((t + 1) * BK);
+    for (; t < nk; ++t) {
+      const bool more = t + 1 < nk;
       mma(st);
-      store(st ^ 1);
-      __syncthreads();
+      if (more) {
+        store(st ^ 1);
+        if (t + 2 < nk) load((t + 2) * BK);
+        __syncthreads();
+      }
       st ^= 1;
     }
-    mma(st);
   }
 
   const int lr = lane >> 4, lc = lane & 15;
@@ -499,6 +503,13 @@ void quad_gemm_bf16_kernel(Bf16Params g) {
       }
     }
   }
+}
+
+template <int NPROD, int KIND, int BM, int BN, int BK, int WGM = 2, int WGN = 2, int NS = 1>
+__global__ __launch_bounds__(64 * WGM * WGN,
+                             (Bf16Occ<BM, BN, BK, KIND, NPROD, 64 * WGM * WGN, NS>::value))
+void quad_gemm_bf16_kernel(Bf16Params g) {
+  bf16_tile<NPROD, KIND, BM, BN, BK, WGM, WGN, NS>(g, blockIdx.x, threadIdx.x);
 }
 
 // hi = bf16(fp32(x)), lo = bf16(fp32(x - hi)) for n values.

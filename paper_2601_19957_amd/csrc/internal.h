@@ -117,11 +117,10 @@ struct TileCfg {
   int bm = 128, bn = 128;
   int bk = 32;      // k-tile of the BF16 matrix-core kernels
   int stages = 1;  // BF16 kernels: LDS stages (2 = ping-pong, square tiles, k-tile 32)
-  int sched = 0;   // split ping-pong kernels: bit 0 staggered waves, bit 1 persistent grid
 };
 
 int quad_gemm_ntn(int dtype, int d, TileCfg t);
-// "BMxBN[xBK[xSTAGES[xSCHED]]]" (an environment override) into *t; false if
+// "BMxBN[xBK[xSTAGES]]" (an environment override) into *t; false if
 // e is null or malformed (t untouched).
 bool parse_tile(const char *e, TileCfg *t);
 // BF16 matrix-core contraction (d a multiple of 8): nprod 1 = BF16 operands,

@@ -159,13 +159,18 @@ def test_bf16_discovery_every_tile_variant(L, forced_tile, npts):
     assert float(np.max(gap / np.maximum(1.0, np.abs(ref["ray_best_l"])))) < 0.05
 
 
-@pytest.mark.parametrize("d,K,B", [(64, 4, 300), (200, 3, 129), (1024, 8, 260), (256, 6, 2000)])
-def test_split_pairs_contraction(L, d, K, B):
+@pytest.mark.parametrize("d,K,B,tile2", [(64, 4, 300, None), (200, 3, 129, None),
+                                         (1024, 8, 260, None), (256, 6, 2000, None),
+                                         (256, 6, 2000, "256x256x32x2"),
+                                         (1024, 8, 260, "256x256x32x2")])
+def test_split_pairs_contraction(L, d, K, B, tile2, monkeypatch):
     """The contraction of listed (row, component) pairs, as the screened mixture bulk runs it:
     every listed pair's Y block and q partial sum to the split bound of the oracle's
     P_k (x - mu_k); unlisted blocks are left untouched.  Rows are listed for one or two
-    components each, with uneven list lengths and an empty component; the last case spans
-    several row tiles per component."""
+    components each, with uneven list lengths and an empty component; the fourth case spans
+    several row tiles per component; the last two take 256 x 256 tiles (SB_TILE2)."""
+    if tile2:
+        monkeypatch.setenv("SB_TILE2", tile2)
     import ctypes as C
 
     rng = np.random.Generator(np.random.PCG64(950 + d))
@@ -214,3 +219,4 @@ def test_split_pairs_contraction(L, d, K, B):
             q_ref = float(delta @ y_ref)
             qb = 2.0 ** -13 * float(np.abs(delta) @ np.abs(prob.prec[k]) @ np.abs(delta)) + 1e-30
             assert abs(float(qh[b, k].sum()) - q_ref) <= qb, (b, k)
+
