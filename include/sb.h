@@ -649,14 +649,20 @@ int32_t sb_lbfgs_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m, int
  * and end it active with a full history ring (each read and wrote the same
  * (2m + 6) d-vectors), and step_back [n_timed] (host) the number that halved
  * their step instead (each read two d-vectors and wrote one).  Entries past
- * the last step are 0.  The host synchronises after every timed step.
- * SB_E_INVAL if n_timed < 0 or, with n_timed > 0, a timing array is NULL. */
+ * the last step are 0.  step_bytes [n_timed] (host, nullable) gets the
+ * launch's algorithmic bytes when every start active entering it accepted or
+ * halved: 3 d per halving start; per accepting start with c history pairs,
+ * (2 c + 6) d plus 2 d when the new pair is stored, and (2 m + 6) d with the
+ * ring full (d-vectors of the dtype's size); -1 for the first step and for a
+ * step in which some start reset its history or stopped.  The host
+ * synchronises after every timed step.  SB_E_INVAL if n_timed < 0 or, with
+ * n_timed > 0, one of the four counting arrays is NULL. */
 int32_t sb_lbfgs_timed_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m,
                            int32_t max_iter, double grad_tol, int32_t dtype, void *logl,
                            void *grad, int32_t *status, int32_t *iters, int64_t *n_evals,
                            void *workspace, size_t ws_bytes, void *stream, int32_t n_timed,
                            float *step_us, int32_t *step_rows, int32_t *step_full,
-                           int32_t *step_back);
+                           int32_t *step_back, double *step_bytes);
 
 /* L-infinity leader de-duplication (step A7): candidates X [C][d] (FP64 or
  * FP32 per dtype) with values l [C] (same dtype) and valid [C] (nullable,

@@ -181,7 +181,7 @@ def lib():
             "sb_lbfgs_dev": (i32, [vp, i64, vp, i32, i32, f64, i32, vp, vp, vp, vp, vp, vp, sz,
                                    vp]),
             "sb_lbfgs_timed_dev": (i32, [vp, i64, vp, i32, i32, f64, i32, vp, vp, vp, vp, vp,
-                                         vp, sz, vp, i32, vp, vp, vp, vp]),
+                                         vp, sz, vp, i32, vp, vp, vp, vp, vp]),
             "sb_precheck_workspace_bytes": (sz, [i32, i32]),
             "sb_precheck_dev": (i32, [vp, vp, vp, f64, f64, vp, vp, vp, vp, vp, sz, vp]),
             "sb_eig_reduce_workspace_bytes": (sz, [i32, i32]),
@@ -573,7 +573,8 @@ def sb_lbfgs_timed_dev(model: DeviceModel, X0, m: int = 8, max_iter: int = 0,
                        grad_tol: float = 0.0, n_timed: int = 32):
     """sb_lbfgs_dev plus, for each of the first n_timed L-BFGS step launches, its duration
     (us), the number of starts active when it began, the number that accepted their trial and
-    hold a full history ring after it, and the number that halved their step in it."""
+    hold a full history ring after it, the number that halved their step in it, and its
+    algorithmic bytes (-1 where some start reset or stopped in it, and for the first)."""
     import torch
 
     dt = DTYPE_F64 if X0.dtype == torch.float64 else DTYPE_F32
@@ -588,17 +589,18 @@ def sb_lbfgs_timed_dev(model: DeviceModel, X0, m: int = 8, max_iter: int = 0,
     rows = np.zeros(max(n_timed, 1), dtype=np.int32)
     full = np.zeros(max(n_timed, 1), dtype=np.int32)
     back = np.zeros(max(n_timed, 1), dtype=np.int32)
+    nbytes = np.zeros(max(n_timed, 1), dtype=np.float64)
     ws = _ws(lib().sb_lbfgs_workspace_bytes(d, model.K, B, m, dt), X.device)
     mv = model.view(dt)
     st = lib().sb_lbfgs_timed_dev(C.byref(mv), B, X.data_ptr(), m, max_iter, grad_tol, dt,
                                   l.data_ptr(), g.data_ptr(), status.data_ptr(), iters.data_ptr(),
                                   C.byref(nev), ws.data_ptr(), ws.numel(), _stream(), n_timed,
                                   us.ctypes.data, rows.ctypes.data, full.ctypes.data,
-                                  back.ctypes.data)
+                                  back.ctypes.data, nbytes.ctypes.data)
     _check(st, "sb_lbfgs_timed_dev")
     return dict(x=X, logl=l, grad=g, status=status, iters=iters, n_evals=nev.value,
                 step_us=us[:n_timed], step_rows=rows[:n_timed], step_full=full[:n_timed],
-                step_back=back[:n_timed])
+                step_back=back[:n_timed], step_bytes=nbytes[:n_timed])
 
 
 def sb_precheck_dev(model: DeviceModel, eps_flat: float = 0.0, eps_soft: float = 0.0,

@@ -976,7 +976,7 @@ static int32_t lbfgs_run(const sb_model_dev *mdl, int64_t B, void *X, int32_t m,
                          void *grad, int32_t *status, int32_t *iters, int64_t *n_evals,
                          void *workspace, size_t ws_bytes, void *stream, int32_t n_timed,
                          float *step_us, int32_t *step_rows, int32_t *step_full,
-                         int32_t *step_back) {
+                         int32_t *step_back, double *step_bytes) {
   int st = validate_model(mdl);
   if (st) return st;
   if (B < 1 || !X) return fail(SB_E_INVAL, "bad B / X");
@@ -1042,16 +1042,19 @@ static int32_t lbfgs_run(const sb_model_dev *mdl, int64_t B, void *X, int32_t m,
   const double tol = grad_tol > 0 ? grad_tol : 1e-10;
   int32_t hcount = 1;
   hipEvent_t ev[2] = {nullptr, nullptr};
-  std::vector<int32_t> h_st, h_ls, h_cnt;
+  std::vector<int32_t> h_st, h_ls, h_cnt, p_st, p_cnt;
   if (n_timed > 0) {
     for (int i = 0; i < n_timed; ++i) {
       step_us[i] = 0.f;
       step_rows[i] = 0;
       step_full[i] = step_back[i] = 0;
+      if (step_bytes) step_bytes[i] = -1.0;
     }
     h_st.resize(B);
     h_ls.resize(B);
     h_cnt.resize(B);
+    p_st.assign(B, 0);  // every start active, no history, before the first step
+    p_cnt.assign(B, 0);
     if (hipEventCreate(&ev[0]) || hipEventCreate(&ev[1])) {
       if (ev[0]) hipEventDestroy(ev[0]);
       return fail(SB_E_DEVICE, "event creation failed");
@@ -1089,6 +1092,35 @@ static int32_t lbfgs_run(const sb_model_dev *mdl, int64_t B, void *X, int32_t m,
         }
         step_full[step] = nf;
         step_back[step] = nb;
+        // algorithmic bytes of the launch, when every start active entering it
+        // accepted or halved (the first step, a reset (history cleared) or a
+        // stop in it leave the entry at -1): a halving start reads the point
+        // and direction and writes the trial point (3 d); an accepting start
+        // with c pairs in its ring reads them, x and g at both slots, and
+        // writes the direction and the trial point, plus s and y when the
+        // curvature test stores the new pair (2 c + 6 (+ 2)) d; with the ring
+        // full the pair the new one evicts is read only when the new one is
+        // kept out, so (2 m + 6) d either way
+        if (step_bytes && !st && step > 0) {
+          const double vec = (double)d * (dtype == SB_DTYPE_F64 ? 8.0 : 4.0);
+          double bytes = 0.0;
+          bool exact = true;
+          for (int64_t i = 0; i < B && exact; ++i) {
+            if (p_st[i] != 0) continue;  // stopped before this step
+            if (h_st[i] != 0 || (h_ls[i] == 0 && h_cnt[i] < p_cnt[i])) {
+              exact = false;
+            } else if (h_ls[i] > 0) {
+              bytes += 3.0 * vec;
+            } else if (p_cnt[i] == m) {
+              bytes += (2.0 * m + 6.0) * vec;
+            } else {
+              bytes += (2.0 * p_cnt[i] + 6.0 + (h_cnt[i] > p_cnt[i] ? 2.0 : 0.0)) * vec;
+            }
+          }
+          step_bytes[step] = exact ? bytes : -1.0;
+        }
+        p_st.swap(h_st);
+        p_cnt.swap(h_cnt);
       }
       rows = hcount;
     } else if (!st && (step & 7) == 7) {
@@ -1114,7 +1146,7 @@ int32_t sb_lbfgs_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m, int
                      int32_t *iters, int64_t *n_evals, void *workspace, size_t ws_bytes,
                      void *stream) {
   return lbfgs_run(mdl, B, X, m, max_iter, grad_tol, dtype, logl, grad, status, iters, n_evals,
-                   workspace, ws_bytes, stream, 0, nullptr, nullptr, nullptr, nullptr);
+                   workspace, ws_bytes, stream, 0, nullptr, nullptr, nullptr, nullptr, nullptr);
 }
 
 int32_t sb_lbfgs_timed_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m,
@@ -1122,12 +1154,12 @@ int32_t sb_lbfgs_timed_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t 
                            void *grad, int32_t *status, int32_t *iters, int64_t *n_evals,
                            void *workspace, size_t ws_bytes, void *stream, int32_t n_timed,
                            float *step_us, int32_t *step_rows, int32_t *step_full,
-                           int32_t *step_back) {
+                           int32_t *step_back, double *step_bytes) {
   if (n_timed < 0 || (n_timed > 0 && (!step_us || !step_rows || !step_full || !step_back)))
     return fail(SB_E_INVAL, "n_timed must be >= 0 with the four timing arrays given");
   return lbfgs_run(mdl, B, X, m, max_iter, grad_tol, dtype, logl, grad, status, iters, n_evals,
                    workspace, ws_bytes, stream, n_timed, step_us, step_rows, step_full,
-                   step_back);
+                   step_back, step_bytes);
 }
 
 // ----------------------------------------------------------------- dedup

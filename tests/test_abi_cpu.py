@@ -136,7 +136,7 @@ def test_user_likelihood_compiles_on_the_host():
     for n_timed in (-1, 4):  # negative count, or timing arrays missing
         assert L.sb_lbfgs_timed_dev(None, 1, None, 8, 0, 0.0, 1, None, None, None, None, None,
                                     None, 0, None, n_timed, None, None, None,
-                                    None) == _lib.E_INVAL
+                                    None, None) == _lib.E_INVAL
     assert L.sb_dedup_dev(4, 2, None, None, None, 0.1, 0, None, None, 4, None, None, 0,
                           None) == _lib.E_INVAL
     assert L.sb_combine_dev(1, 0, None, None, None, None, None, None, None, None,

@@ -436,6 +436,14 @@ def test_lbfgs_timed_matches_untimed(L, dtype):
     # the first step only chooses directions; counts stay within the active starts
     assert b["step_full"][0] == 0 and b["step_back"][0] == 0
     assert np.all(b["step_full"] + b["step_back"] <= b["step_rows"])
+    # per-launch algorithmic bytes: -1 for the first step; where every active start accepted
+    # with a full ring or halved, the (2m + 6) d and 3 d counts
+    nb, es, d = b["step_bytes"], (8 if dtype == "f64" else 4), prob.d
+    assert nb[0] == -1 and np.all((nb == -1) | (nb > 0) | ~ran)
+    whole = ran & (b["step_full"] + b["step_back"] == b["step_rows"]) & (nb > 0)
+    assert whole.any()
+    ref = ((2 * 8 + 6) * b["step_full"] + 3 * b["step_back"]) * d * es
+    assert np.array_equal(nb[whole], ref[whole].astype(np.float64))
 
 
 # -------------------------------------------------------------- dedup / A7
