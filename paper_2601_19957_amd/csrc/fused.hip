@@ -42,9 +42,8 @@ struct FusedArgs {
   int dp;                       // d rounded up to a multiple of 32
 };
 
-// RB row blocks of 16 points per workgroup: each B pair a lane loads feeds
-// 2 RB MFMAs, so P's traffic from the L2 and the loads' latency per MFMA
-// both fall by RB.
+// RB row blocks of 16 points per workgroup (each B value a lane loads feeds
+// RB MFMAs); the launcher uses RB = 1.
 template <int RB>
 __global__ __launch_bounds__(256) void fused_logl_grad_kernel(FusedArgs f) {
   constexpr int R = 16 * RB;  // points per workgroup
