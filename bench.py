@@ -184,7 +184,8 @@ def recorded_lbfgs(summary="profiles/lbfgs_step_B16384_d1024_m8.md",
     return val
 
 
-def time_lbfgs_step(L, prob, cfg, n_timed=40, dtype="f32", box_starts=False, min_full=0.99):
+def time_lbfgs_step(L, prob, cfg, n_timed=40, dtype="f32", box_starts=False, min_full=0.99,
+                    hist_bf16=False):
     """The L-BFGS step (A4) as the mixed bulk runs it (FP32, one workgroup per start) at full
     batch: sb_lbfgs_timed_dev from the BF16 discovery starts, HIP events around each step
     launch on its stream.  Averaged over the full-batch launches in which every start either
@@ -194,7 +195,8 @@ def time_lbfgs_step(L, prob, cfg, n_timed=40, dtype="f32", box_starts=False, min
     evicted one read, or all m when the curvature test keeps the new pair out and it is not
     written; x and g read at both slots; s, y, direction and trial point written), one with c
     pairs (2c + 6) d 4 plus 2 d 4 when it stores the new pair, a halving one 3 d 4 bytes (point
-    and direction read, trial point written).  dtype "f64": the same step in FP64 (the plain
+    and direction read, trial point written); with hist_bf16 the ring's vectors count 2 d
+    bytes each instead of 4 d.  dtype "f64": the same step in FP64 (the plain
     path and the polish), 8-byte elements, from the FP64 discovery starts.  box_starts: from
     points one standard deviation around the modes instead, without a gradient stop (small
     problems' discovery starts converge before the history ring fills, and from far points
@@ -218,7 +220,8 @@ def time_lbfgs_step(L, prob, cfg, n_timed=40, dtype="f32", box_starts=False, min
     B, d = X0.shape
     # near starts: no gradient stop, so that every start is still stepping when its ring is full
     r = L.sb_lbfgs_timed_dev(mdl, X0, m=cfg.m, max_iter=n_timed + 8, n_timed=n_timed,
-                             grad_tol=1e-300 if box_starts else 0.0)
+                             grad_tol=1e-300 if box_starts else 0.0,
+                             hist_bf16=hist_bf16 and not f64)
     full, back = r["step_full"].astype(np.int64), r["step_back"].astype(np.int64)
     nbytes = r["step_bytes"]
     # steady-state full-batch launches: every start accepted or halved, at least min_full of
@@ -236,14 +239,20 @@ def time_lbfgs_step(L, prob, cfg, n_timed=40, dtype="f32", box_starts=False, min
     alg = float(per_launch.mean())
     avg_us = float(us.mean())
     achieved = alg / avg_us / 1e3  # GB/s
-    rec = recorded_lbfgs() if (d, cfg.m, B) == (1024, 8, 16384) and not f64 else None
+    rec = recorded_lbfgs() if (d, cfg.m, B) == (1024, 8, 16384) and hist_bf16 and not f64 \
+        else None
+    h16 = hist_bf16 and not f64
+    # the library's launch shape for this d (threads per start, values per thread)
     tpb = 64 if d <= 256 else (128 if d <= 512 else (256 if d <= 1024 else 512))
     ept = 1 if d <= 64 else (2 if d <= 128 else 4)
+    if h16 and d > 256:
+        tpb, ept = tpb // 2, 8
     out = dict(bound="hbm", achieved=achieved, peak=PEAK["hbm"], unit="GB/s",
                frac=achieved / PEAK["hbm"],
                traffic=rec["lbfgs_traffic_bytes_per_launch"] if rec else None,
-               kernel=f"lbfgs_step_kernel<{'double' if f64 else 'float'},{tpb},{ept},true> "
-                      f"(A4 batched L-BFGS step, {'FP64' if f64 else 'FP32 bulk'})",
+               kernel=f"lbfgs_step_kernel<{'double' if f64 else 'float'},{tpb},{ept},true"
+                      f"{',true' if h16 else ''}> (A4 batched L-BFGS step, "
+                      f"{'FP64' if f64 else ('FP32 bulk, BF16 history ring' if h16 else 'FP32')})",
                shape=f"B={B} d={d} m={cfg.m}", algorithmic_bytes=alg, avg_launch_us=avg_us,
                launches=len(sel), launch_us_range=[float(us.min()), float(us.max())],
                timed_steps=[int(i) for i in sel],
@@ -258,17 +267,19 @@ def time_lbfgs_step(L, prob, cfg, n_timed=40, dtype="f32", box_starts=False, min
 
 def lbfgs_step_variants(L):
     """The L-BFGS step's HBM roofline at c1 (d = 64, 4096 starts), c2 (d = 256, 8192) and c4b
-    (d = 1024, 16384) in FP32 and FP64 (algorithmic bytes (2m + 6) d s per accepting start);
+    (d = 1024, 16384) in FP32 (FP32 and BF16 history ring) and FP64 (algorithmic bytes per
+    launch counted by the library from the starts' ring counts);
     c1 and c2 from points around the modes, c4b from its discovery starts."""
     from paper_2601_19957_amd import synth
 
     out = {}
     for name in ("c1", "c2", "c4b"):
         prob, cfg = synth.make_workload(name)
-        for dt in ("f32", "f64"):
+        for dt in ("f32", "f32_h16", "f64"):
             # (c1, c2: at least 90% with a full ring; their rings fill unevenly near the modes)
-            r = time_lbfgs_step(L, prob, cfg, n_timed=24, dtype=dt, box_starts=name != "c4b",
-                                min_full=0.99 if name == "c4b" else 0.9)
+            r = time_lbfgs_step(L, prob, cfg, n_timed=24, dtype=dt[:3], box_starts=name != "c4b",
+                                min_full=0.99 if name == "c4b" else 0.9,
+                                hist_bf16=dt == "f32_h16")
             if r:
                 out[f"{name}_{dt}"] = {k: r[k] for k in ("achieved", "frac", "avg_launch_us",
                                                          "algorithmic_bytes", "shape", "kernel",
@@ -754,7 +765,7 @@ def main() -> int:
 
     # ---- roofline of the dominant kernel: the L-BFGS step at full batch
     log("timing the L-BFGS step at full batch")
-    roofline = time_lbfgs_step(L, prob_big, cfg_big)
+    roofline = time_lbfgs_step(L, prob_big, cfg_big, hist_bf16=True)
 
     # ---- the bulk contraction (split BF16) at the largest posterior's shape
     log("timing the A3 contraction (split BF16) at the bulk shape")
@@ -840,29 +851,37 @@ def main() -> int:
         del rd
         torch.cuda.empty_cache()
 
-    # ---- the same mixed path with the FP32 matrix-core contraction in the bulk instead of the
-    # split-BF16 one (the library reads SB_BULK_GEMM at each call)
-    f32_bulk = {}
+    # ---- the same mixed path with parts of the bulk in plain FP32 (the library reads the
+    # switches at each call): the FP32 matrix-core contraction and the FP32 history ring
+    # (SB_BULK_GEMM=f32, SB_BULK_HIST=f32), and the split contraction with the FP32 ring
+    # (SB_BULK_HIST=f32)
+    variants = {"f32_matrix_bulk": {"SB_BULK_GEMM": "f32", "SB_BULK_HIST": "f32"},
+                "f32_history": {"SB_BULK_HIST": "f32"}}
+    bulk_var = {}
     if not args.no_f32_bulk:
-        os.environ["SB_BULK_GEMM"] = "f32"
-        try:
-            for n, (p, c) in wl.items():
-                rf = L.EvidenceRunner(p, c)
-                rf.run(stream)
-                ts = []
-                for _ in range(3):
-                    t1 = time.perf_counter()
-                    resf = rf.run(stream)
-                    ts.append(time.perf_counter() - t1)
-                f32_bulk[n] = dict(ms=float(np.median(ts)) * 1e3, log_z=resf.log_z,
-                                   evals=resf.n_grad_evals, iterations=resf.iterations,
-                                   status=resf.status)
-                log(f"FP32 matrix-core bulk {n}: {f32_bulk[n]['ms']:.1f} ms, log Z "
-                    f"{resf.log_z:.9f}, iters {resf.iterations}")
-                del rf
-                torch.cuda.empty_cache()
-        finally:
-            del os.environ["SB_BULK_GEMM"]
+        for vname, env in variants.items():
+            bulk_var[vname] = {}
+            os.environ.update(env)
+            try:
+                for n, (p, c) in wl.items():
+                    rf = L.EvidenceRunner(p, c)
+                    rf.run(stream)
+                    ts = []
+                    for _ in range(3):
+                        t1 = time.perf_counter()
+                        resf = rf.run(stream)
+                        ts.append(time.perf_counter() - t1)
+                    bulk_var[vname][n] = dict(ms=float(np.median(ts)) * 1e3, log_z=resf.log_z,
+                                              evals=resf.n_grad_evals,
+                                              iterations=resf.iterations, status=resf.status)
+                    log(f"{vname} {n}: {bulk_var[vname][n]['ms']:.1f} ms, log Z "
+                        f"{resf.log_z:.9f}, iters {resf.iterations}")
+                    del rf
+                    torch.cuda.empty_cache()
+            finally:
+                for k in env:
+                    del os.environ[k]
+    f32_bulk = bulk_var.get("f32_matrix_bulk", {})
 
     # ---- plain FP64 path, same pipeline and starts
     t64 = {}
@@ -977,6 +996,7 @@ def main() -> int:
         "time_to_logz_host_entry_ms": host or None,
         "time_to_logz_direct_ms": direct,
         "time_to_logz_f32_matrix_bulk": f32_bulk or None,
+        "time_to_logz_f32_history": bulk_var.get("f32_history") or None,
         "exec_context": exec_stats,
         "phases_ms": {n: dict(zip(("prep", "discovery", "bulk", "dedup_pre",
                                    "polish_hessian_chol", "dedup_combine"),

@@ -73,18 +73,23 @@ typedef enum {
 typedef enum { SB_FAMILY_GAUSS_MIX = 0, SB_FAMILY_STUDENT_T = 1 } sb_family;
 typedef enum { SB_NORM_PEAK_ZERO = 0, SB_NORM_DENSITY = 1 } sb_norm;
 /* SB_PREC_FP64: every step in FP64.  SB_PREC_MIXED: discovery GEMM in BF16
- * with FP32 accumulation, L-BFGS bulk in FP32, then Newton polish, Hessian,
- * Cholesky, log det and the logsumexp combine in FP64. */
+ * with FP32 accumulation, L-BFGS bulk in FP32 (its history pairs rounded to
+ * BF16 when m <= 8), then Newton polish, Hessian, Cholesky, log det and the
+ * logsumexp combine in FP64. */
 typedef enum { SB_PREC_FP64 = 0, SB_PREC_MIXED = 1 } sb_precision;
 /* SB_DTYPE_F32_SPLIT: FP32 data whose contraction runs on the BF16 matrix
  * cores as three products of split operands (v = hi + lo, hi = bf16(v),
  * lo = bf16(v - hi); hi*hi + hi*lo + lo*hi with FP32 accumulation, about
- * 2^-16 relative per product); needs d a multiple of 8. */
+ * 2^-16 relative per product); needs d a multiple of 8.
+ * SB_DTYPE_F32_H16 (sb_lbfgs_dev, sb_lbfgs_timed_dev only): FP32 points,
+ * gradients and directions with the L-BFGS history ring in BF16 (each pair
+ * s, y rounded to BF16 when formed, then used and stored as rounded); m <= 8. */
 typedef enum {
   SB_DTYPE_F64 = 0,
   SB_DTYPE_F32 = 1,
   SB_DTYPE_BF16 = 2,
-  SB_DTYPE_F32_SPLIT = 3
+  SB_DTYPE_F32_SPLIT = 3,
+  SB_DTYPE_F32_H16 = 4
 } sb_dtype;
 
 /* Likelihood: family, normalisation and parameters.
@@ -631,8 +636,9 @@ int32_t sb_lbfgs_direction_dev(int64_t B, int32_t d, int32_t m, const int32_t *c
  * ||grad l||_inf <= grad_tol or max_iter accepted steps.  Writes logl [B],
  * grad [B][d] at the final points, status [B] (1 converged, 2 stalled,
  * 3 max-iter, 4 dead) and iters [B]; *n_evals (host) gets the number of
- * l+grad evaluations.  dtype F64 or F32 (model needs prec_lp/mu_lp for F32).
- * Workspace >= sb_lbfgs_workspace_bytes(d, K, B, m, dtype). */
+ * l+grad evaluations.  dtype F64, F32 or F32_H16 (FP32 with the BF16 history
+ * ring, m <= 8; SB_E_UNSUPPORTED beyond); the model needs prec_lp/mu_lp for
+ * the FP32 forms.  Workspace >= sb_lbfgs_workspace_bytes(d, K, B, m, dtype). */
 size_t sb_lbfgs_workspace_bytes(int32_t d, int32_t K, int64_t B, int32_t m, int32_t dtype);
 int32_t sb_lbfgs_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m, int32_t max_iter,
                      double grad_tol, int32_t dtype, void *logl, void *grad, int32_t *status,
@@ -652,8 +658,9 @@ int32_t sb_lbfgs_dev(const sb_model_dev *mdl, int64_t B, void *X, int32_t m, int
  * the last step are 0.  step_bytes [n_timed] (host, nullable) gets the
  * launch's algorithmic bytes when every start active entering it accepted or
  * halved: 3 d per halving start; per accepting start with c history pairs,
- * (2 c + 6) d plus 2 d when the new pair is stored, and (2 m + 6) d with the
- * ring full (d-vectors of the dtype's size); -1 for the first step and for a
+ * 2 c d (ring) + 6 d plus 2 d (ring) when the new pair is stored, and
+ * 2 m d (ring) + 6 d with the ring full (d-vectors of the dtype's size, ring
+ * vectors of the ring's: BF16 for F32_H16); -1 for the first step and for a
  * step in which some start reset its history or stopped.  The host
  * synchronises after every timed step.  SB_E_INVAL if n_timed < 0 or, with
  * n_timed > 0, one of the four counting arrays is NULL. */

@@ -23,7 +23,7 @@ OK, E_INVAL, E_NOTPD, E_NOMEM, E_DEVICE, E_NOMODE, E_CAPACITY, E_UNSUPPORTED, E_
 FAMILY_GAUSS_MIX, FAMILY_STUDENT_T = 0, 1
 NORM_PEAK_ZERO, NORM_DENSITY = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
-DTYPE_F64, DTYPE_F32, DTYPE_BF16, DTYPE_F32_SPLIT = 0, 1, 2, 3
+DTYPE_F64, DTYPE_F32, DTYPE_BF16, DTYPE_F32_SPLIT, DTYPE_F32_H16 = 0, 1, 2, 3, 4
 ST_CONVERGED, ST_STALLED, ST_MAXITER, ST_DEAD = 1, 2, 3, 4
 
 # every extern "C" symbol declared in include/sb.h
@@ -404,7 +404,7 @@ class DeviceModel:
 
     def view(self, dtype: int = DTYPE_F64) -> sb_model_dev:
         lp = None
-        if dtype == DTYPE_F32:
+        if dtype in (DTYPE_F32, DTYPE_F32_H16):
             lp = _ptr(self.prec_f32)
         elif dtype == DTYPE_BF16:
             lp = _ptr(self.prec_bf16)
@@ -549,10 +549,13 @@ def sb_lbfgs_direction_dev(S, Y, G, cnt):
     return P
 
 
-def sb_lbfgs_dev(model: DeviceModel, X0, m: int = 8, max_iter: int = 0, grad_tol: float = 0.0):
+def sb_lbfgs_dev(model: DeviceModel, X0, m: int = 8, max_iter: int = 0, grad_tol: float = 0.0,
+                 hist_bf16: bool = False):
+    """Batched L-BFGS from X0 (float64: FP64; float32: FP32, with hist_bf16 the BF16 history
+    ring of dtype F32_H16)."""
     import torch
 
-    dt = DTYPE_F64 if X0.dtype == torch.float64 else DTYPE_F32
+    dt = DTYPE_F64 if X0.dtype == torch.float64 else (DTYPE_F32_H16 if hist_bf16 else DTYPE_F32)
     X = X0.clone().contiguous()
     B, d = X.shape
     l = torch.empty(B, dtype=X.dtype, device=X.device)
@@ -570,14 +573,14 @@ def sb_lbfgs_dev(model: DeviceModel, X0, m: int = 8, max_iter: int = 0, grad_tol
 
 
 def sb_lbfgs_timed_dev(model: DeviceModel, X0, m: int = 8, max_iter: int = 0,
-                       grad_tol: float = 0.0, n_timed: int = 32):
+                       grad_tol: float = 0.0, n_timed: int = 32, hist_bf16: bool = False):
     """sb_lbfgs_dev plus, for each of the first n_timed L-BFGS step launches, its duration
     (us), the number of starts active when it began, the number that accepted their trial and
     hold a full history ring after it, the number that halved their step in it, and its
     algorithmic bytes (-1 where some start reset or stopped in it, and for the first)."""
     import torch
 
-    dt = DTYPE_F64 if X0.dtype == torch.float64 else DTYPE_F32
+    dt = DTYPE_F64 if X0.dtype == torch.float64 else (DTYPE_F32_H16 if hist_bf16 else DTYPE_F32)
     X = X0.clone().contiguous()
     B, d = X.shape
     l = torch.empty(B, dtype=X.dtype, device=X.device)

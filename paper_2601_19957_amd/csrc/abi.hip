@@ -981,8 +981,12 @@ static int32_t lbfgs_run(const sb_model_dev *mdl, int64_t B, void *X, int32_t m,
   if (st) return st;
   if (B < 1 || !X) return fail(SB_E_INVAL, "bad B / X");
   if (m < 1 || m > kMaxMem) return fail(SB_E_INVAL, "m must be in [1, %d]", kMaxMem);
-  if (dtype != SB_DTYPE_F64 && dtype != SB_DTYPE_F32)
-    return fail(SB_E_INVAL, "dtype must be F64 or F32");
+  if (dtype != SB_DTYPE_F64 && dtype != SB_DTYPE_F32 && dtype != SB_DTYPE_F32_H16)
+    return fail(SB_E_INVAL, "dtype must be F64, F32 or F32_H16");
+  const bool h16 = dtype == SB_DTYPE_F32_H16;
+  if (h16 && m > kMaxHist)
+    return fail(SB_E_UNSUPPORTED, "F32_H16 (BF16 history) needs m <= %d", kMaxHist);
+  if (h16) dtype = SB_DTYPE_F32;
   if (dtype == SB_DTYPE_F32 && (!mdl->prec_lp || !mdl->mu_lp))
     return fail(SB_E_INVAL, "F32 needs prec_lp (FP32) and mu_lp");
   if (!workspace || ws_bytes < sb_lbfgs_workspace_bytes(mdl->d, mdl->K, B, m, dtype))
@@ -994,6 +998,7 @@ static int32_t lbfgs_run(const sb_model_dev *mdl, int64_t B, void *X, int32_t m,
   Arena ar(workspace, ws_bytes);
   LbfgsBuffers lb;
   lb.dtype = dtype;
+  lb.hist_bf16 = h16;
   lb.B = B;
   lb.d = d;
   lb.m = m;
@@ -1102,7 +1107,9 @@ static int32_t lbfgs_run(const sb_model_dev *mdl, int64_t B, void *X, int32_t m,
         // full the pair the new one evicts is read only when the new one is
         // kept out, so (2 m + 6) d either way
         if (step_bytes && !st && step > 0) {
+          // (d-vectors of the dtype; ring pairs of the ring's element type)
           const double vec = (double)d * (dtype == SB_DTYPE_F64 ? 8.0 : 4.0);
+          const double rv = h16 ? (double)d * 2.0 : vec;
           double bytes = 0.0;
           bool exact = true;
           for (int64_t i = 0; i < B && exact; ++i) {
@@ -1112,9 +1119,9 @@ static int32_t lbfgs_run(const sb_model_dev *mdl, int64_t B, void *X, int32_t m,
             } else if (h_ls[i] > 0) {
               bytes += 3.0 * vec;
             } else if (p_cnt[i] == m) {
-              bytes += (2.0 * m + 6.0) * vec;
+              bytes += 2.0 * m * rv + 6.0 * vec;
             } else {
-              bytes += (2.0 * p_cnt[i] + 6.0 + (h_cnt[i] > p_cnt[i] ? 2.0 : 0.0)) * vec;
+              bytes += (2.0 * p_cnt[i] + (h_cnt[i] > p_cnt[i] ? 2.0 : 0.0)) * rv + 6.0 * vec;
             }
           }
           step_bytes[step] = exact ? bytes : -1.0;

@@ -310,6 +310,7 @@ int launch_fill_i32(int64_t n, int32_t v, int32_t *p, hipStream_t s);
 // Batched L-BFGS (state machine over starts).
 struct LbfgsBuffers {
   int dtype = DT_F64;
+  bool hist_bf16 = false;  // FP32 starts: the history ring holds BF16 pairs (m <= kMaxHist)
   int64_t B = 0;
   int d = 0, m = 8;
   void *X = nullptr, *G = nullptr, *F = nullptr;  // [2][B][d], [2][B][d], [2][B] (F: FP64)
@@ -427,7 +428,7 @@ struct BlockKey {
   DevProblem P;
   sb_config cfg;
   double tol;
-  int32_t max_iter, blk, dtype, gemm_dtype, two_stage, screen, grad_direct, pad;
+  int32_t max_iter, blk, dtype, gemm_dtype, two_stage, screen, grad_direct, hist_bf16;
   TileCfg tile, tile1, tile2;
 };
 

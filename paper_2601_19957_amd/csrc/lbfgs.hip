@@ -116,6 +116,154 @@ __device__ inline void vstore_nt(T *p, int i0, int d, bool vec, const T (&v)[EPT
   vstore<T, EPT>(p, i0, d, vec, v);
 }
 
+// The history ring in BF16 (FP32 starts): a thread's EPT values as EPT
+// 16-bit words, widened on load (exact) and rounded to nearest on store; the
+// pair is rounded before any use, so the stored values are the ones used.
+__device__ inline float bf16_round(float v) {
+  const __bf16 h = (__bf16)v;
+  return (float)h;
+}
+template <int EPT>
+__device__ inline void hload_nt(const uint16_t *p, int i0, int d, bool vec, float (&v)[EPT]) {
+  if constexpr (EPT == 4) {
+    if (vec && i0 + 4 <= d) {
+      typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+      const u2v w = __builtin_nontemporal_load((const u2v *)(p + i0));
+      v[0] = __builtin_bit_cast(float, w[0] << 16);
+      v[1] = __builtin_bit_cast(float, w[0] & 0xffff0000u);
+      v[2] = __builtin_bit_cast(float, w[1] << 16);
+      v[3] = __builtin_bit_cast(float, w[1] & 0xffff0000u);
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e)
+    v[e] = (i0 + e < d) ? __builtin_bit_cast(float, (uint32_t)p[i0 + e] << 16) : 0.f;
+}
+template <int EPT>
+__device__ inline void hstore_nt(uint16_t *p, int i0, int d, bool vec, const float (&v)[EPT]) {
+  // (v already holds BF16 values: the top 16 bits are exact)
+  auto pk = [&](int e) {
+    return (__builtin_bit_cast(uint32_t, v[e]) >> 16) |
+           (__builtin_bit_cast(uint32_t, v[e + 1]) & 0xffff0000u);
+  };
+  if constexpr (EPT % 8 == 0) {
+    if (vec && i0 + EPT <= d) {
+      typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+#pragma unroll
+      for (int q = 0; q < EPT; q += 8) {
+        u4v w;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[e] = pk(q + 2 * e);
+        __builtin_nontemporal_store(w, (u4v *)(p + i0 + q));
+      }
+      return;
+    }
+  }
+  if constexpr (EPT == 4) {
+    if (vec && i0 + 4 <= d) {
+      typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+      u2v w;
+      w[0] = pk(0);
+      w[1] = pk(2);
+      __builtin_nontemporal_store(w, (u2v *)(p + i0));
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e)
+    if (i0 + e < d) p[i0 + e] = (uint16_t)(__builtin_bit_cast(uint32_t, v[e]) >> 16);
+}
+// The raw words of a thread's EPT BF16 values (EPT even, whole aligned
+// chunk), kept packed in registers: no conversion between the loads, so the
+// loads of a whole history issue back to back.
+template <int EPT>
+__device__ inline void hload_raw_nt(const uint16_t *p, int i0, uint32_t (&w)[EPT / 2]) {
+  static_assert(EPT % 2 == 0, "whole 32-bit words");
+  typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+  typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+  if constexpr (EPT % 8 == 0) {
+#pragma unroll
+    for (int q = 0; q < EPT / 2; q += 4) {
+      const u4v t = __builtin_nontemporal_load((const u4v *)(p + i0 + 2 * q));
+#pragma unroll
+      for (int e = 0; e < 4; ++e) w[q + e] = t[e];
+    }
+  } else if constexpr (EPT % 4 == 0) {
+#pragma unroll
+    for (int q = 0; q < EPT / 2; q += 2) {
+      const u2v t = __builtin_nontemporal_load((const u2v *)(p + i0 + 2 * q));
+      w[q] = t[0];
+      w[q + 1] = t[1];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < EPT / 2; ++q)
+      w[q] = __builtin_nontemporal_load((const uint32_t *)(p + i0 + 2 * q));
+  }
+}
+// Ring access for history type HB (BF16 when true, else T).
+template <typename T, int EPT, bool HB>
+__device__ inline void ring_load(const T *base, size_t off, int i0, int d, bool vec, T (&v)[EPT]) {
+  if constexpr (HB)
+    hload_nt<EPT>((const uint16_t *)base + off, i0, d, vec, v);
+  else
+    vload_nt<T, EPT>(base + off, i0, d, vec, v);
+}
+template <typename T, int EPT, bool HB>
+__device__ inline void ring_store(T *base, size_t off, int i0, int d, bool vec, const T (&v)[EPT]) {
+  if constexpr (HB)
+    hstore_nt<EPT>((uint16_t *)base + off, i0, d, vec, v);
+  else
+    vstore_nt<T, EPT>(base + off, i0, d, vec, v);
+}
+
+// A thread's slices of the kMaxHist register-resident history vectors:
+// EPT values of type T each, or (PK: FP32 starts with the history in BF16,
+// EPT even) the same values packed two per 32-bit word and widened on each
+// read, which halves the registers the history holds.  Values given to set
+// must be BF16-exact in the packed form (the low 16 bits are dropped).
+template <typename T, int EPT, bool PK>
+struct HistReg {
+  T v[kMaxHist][EPT];
+  __device__ T get(int j, int e) const { return v[j][e]; }
+  __device__ void set(int j, const T (&x)[EPT]) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) v[j][e] = x[e];
+  }
+  __device__ void zero(int j) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) v[j][e] = 0;
+  }
+  __device__ void move(int j, int k) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) v[j][e] = v[k][e];
+  }
+};
+template <int EPT>
+struct HistReg<float, EPT, true> {
+  static_assert(EPT % 2 == 0, "two BF16 values per word");
+  uint32_t w[kMaxHist][EPT / 2];
+  __device__ float get(int j, int e) const {
+    const uint32_t x = w[j][e >> 1];
+    return __builtin_bit_cast(float, (e & 1) ? (x & 0xffff0000u) : (x << 16));
+  }
+  __device__ void set(int j, const float (&x)[EPT]) {
+#pragma unroll
+    for (int q = 0; q < EPT / 2; ++q)
+      w[j][q] = (__builtin_bit_cast(uint32_t, x[2 * q]) >> 16) |
+                (__builtin_bit_cast(uint32_t, x[2 * q + 1]) & 0xffff0000u);
+  }
+  __device__ void zero(int j) {
+#pragma unroll
+    for (int q = 0; q < EPT / 2; ++q) w[j][q] = 0;
+  }
+  __device__ void move(int j, int k) {
+#pragma unroll
+    for (int q = 0; q < EPT / 2; ++q) w[j][q] = w[k][q];
+  }
+};
+
 // Workgroup reductions over a two-slot LDS ring, one barrier each (the
 // summation order of block_sum: butterfly within each wave, then the wave
 // totals in order, so results are the same).  Reduction k writes slot
@@ -160,10 +308,9 @@ struct BlockRed {
 // first).  q <- g; backward: alpha_j = rho_j s_j^T q, q -= alpha_j y_j;
 // r = gamma q, gamma = s^T y / y^T y of the newest pair; forward:
 // beta = rho_j y_j^T r, r += (alpha_j - beta) s_j; returns p = -r.
-template <typename T, int TPB, int EPT>
-__device__ inline void two_loop(const T (&Sr)[kMaxHist][EPT], const T (&Yr)[kMaxHist][EPT],
-                                const T (&rh)[kMaxHist], T gamma, int cnt, const T (&g)[EPT],
-                                T (&p)[EPT], BlockRed<TPB, T> &red) {
+template <typename T, int TPB, int EPT, class H>
+__device__ inline void two_loop(const H &Sr, const H &Yr, const T (&rh)[kMaxHist], T gamma,
+                                int cnt, const T (&g)[EPT], T (&p)[EPT], BlockRed<TPB, T> &red) {
   T q[EPT], al[kMaxHist];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) q[e] = g[e];
@@ -172,11 +319,11 @@ __device__ inline void two_loop(const T (&Sr)[kMaxHist][EPT], const T (&Yr)[kMax
     if (j < cnt) {
       T dd = 0;
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) dd += Sr[j][e] * q[e];
+      for (int e = 0; e < EPT; ++e) dd += Sr.get(j, e) * q[e];
       dd = red.sum(dd);
       al[j] = rh[j] * dd;
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) q[e] -= al[j] * Yr[j][e];
+      for (int e = 0; e < EPT; ++e) q[e] -= al[j] * Yr.get(j, e);
     } else {
       al[j] = 0;
     }
@@ -188,10 +335,10 @@ __device__ inline void two_loop(const T (&Sr)[kMaxHist][EPT], const T (&Yr)[kMax
     if (j < cnt) {
       T bb = 0;
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) bb += Yr[j][e] * q[e];
+      for (int e = 0; e < EPT; ++e) bb += Yr.get(j, e) * q[e];
       bb = rh[j] * red.sum(bb);
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) q[e] += (al[j] - bb) * Sr[j][e];
+      for (int e = 0; e < EPT; ++e) q[e] += (al[j] - bb) * Sr.get(j, e);
     }
   }
 #pragma unroll
@@ -295,10 +442,12 @@ __device__ __forceinline__ void two_loop_stream(const T *Sb, const T *Yb, const 
 
 // One step of start s (the whole workgroup; every branch is uniform in s).
 // HREG: the history is held in registers (m <= kMaxHist); otherwise it stays
-// in memory and two_loop_stream reads it (m <= kMaxMem).
-template <typename T, int TPB, int EPT, bool HREG>
+// in memory and two_loop_stream reads it (m <= kMaxMem).  HB (FP32, HREG):
+// the ring holds BF16 pairs (s and y rounded to BF16 when formed).
+template <typename T, int TPB, int EPT, bool HREG, bool HB = false>
 __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t s,
                                                BlockRed<TPB, T> &red) {
+  static_assert(!HB || (HREG && sizeof(T) == 4), "BF16 history: FP32, register-resident");
   const int tid = threadIdx.x;
   const int64_t B = a.B;
   // every per-start scalar is read before the first decision, so the reads
@@ -398,6 +547,10 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
       for (int e = 0; e < EPT; ++e) {
         sv[e] = x[e] - xov[e];
         yv[e] = gov[e] - gl[e];  // grad f(x_t) - grad f(x), grad f = -grad l
+        if constexpr (HB) {
+          sv[e] = bf16_round(sv[e]);
+          yv[e] = bf16_round(yv[e]);
+        }
       }
     }
   }
@@ -409,21 +562,38 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
   // With the ring full, the oldest pair is evicted when the curvature test
   // passes, so its load waits for that test and happens only when it fails.
   constexpr int MH = HREG ? kMaxHist : 1;
-  T Sr[MH][EPT], Yr[MH][EPT], rh[MH], yyr[MH];
+  constexpr bool PK = HB && EPT % 2 == 0;
+  HistReg<T, EPT, PK> Sr, Yr;
+  T rh[MH], yyr[MH];
   const bool defer_oldest = (mode == M_ACCEPT && cnt == m);
   if constexpr (HREG) {
+    // packed BF16 history in whole aligned chunks: the raw words go straight
+    // to registers, every load issued before the first use
+    const bool raw = PK && vec && i0 + EPT <= d;
 #pragma unroll
     for (int j = 0; j < kMaxHist; ++j) {
       rh[j] = 0;
       yyr[j] = 0;
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) Sr[j][e] = Yr[j][e] = 0;
+      Sr.zero(j);
+      Yr.zero(j);
       if (mode == M_ACCEPT && j < cnt && !(j == 0 && defer_oldest)) {
         const int ph = (head - cnt + j + 2 * m) % m;
-        const T *Sp = a.S + (size_t)m * vo + (size_t)ph * d;
-        const T *Yp = a.Yh + (size_t)m * vo + (size_t)ph * d;
-        vload_nt<T, EPT>(Sp, i0, d, vec, Sr[j]);
-        vload_nt<T, EPT>(Yp, i0, d, vec, Yr[j]);
+        const size_t off = (size_t)m * vo + (size_t)ph * d;
+        if constexpr (PK) {
+          if (raw) {
+            hload_raw_nt<EPT>((const uint16_t *)a.S + off, i0, Sr.w[j]);
+            hload_raw_nt<EPT>((const uint16_t *)a.Yh + off, i0, Yr.w[j]);
+          } else {
+            T t[EPT];
+            ring_load<T, EPT, HB>(a.S, off, i0, d, vec, t);
+            Sr.set(j, t);
+            ring_load<T, EPT, HB>(a.Yh, off, i0, d, vec, t);
+            Yr.set(j, t);
+          }
+        } else {
+          ring_load<T, EPT, HB>(a.S, off, i0, d, vec, Sr.v[j]);
+          ring_load<T, EPT, HB>(a.Yh, off, i0, d, vec, Yr.v[j]);
+        }
         rh[j] = a.rho[(size_t)s * m + ph];
         yyr[j] = a.yy[(size_t)s * m + ph];
       }
@@ -446,10 +616,8 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
     ++it;
     if (sy > (T)1e-10 * sqrt(ss) * sqrt(yy)) {
       // store the pair in the ring and append it to the logical history
-      T *Sp = a.S + (size_t)m * vo + (size_t)head * d;
-      T *Yp = a.Yh + (size_t)m * vo + (size_t)head * d;
-      vstore_nt<T, EPT>(Sp, i0, d, vec, sv);
-      vstore_nt<T, EPT>(Yp, i0, d, vec, yv);
+      ring_store<T, EPT, HB>(a.S, (size_t)m * vo + (size_t)head * d, i0, d, vec, sv);
+      ring_store<T, EPT, HB>(a.Yh, (size_t)m * vo + (size_t)head * d, i0, d, vec, yv);
       if (tid == 0) {
         a.rho[(size_t)s * m + head] = (T)1 / sy;
         a.yy[(size_t)s * m + head] = yy;
@@ -459,11 +627,8 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
         if (full) {
 #pragma unroll
           for (int j = 0; j < kMaxHist - 1; ++j) {
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-              Sr[j][e] = Sr[j + 1][e];
-              Yr[j][e] = Yr[j + 1][e];
-            }
+            Sr.move(j, j + 1);
+            Yr.move(j, j + 1);
             rh[j] = rh[j + 1];
             yyr[j] = yyr[j + 1];
           }
@@ -472,11 +637,8 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
 #pragma unroll
         for (int j = 0; j < kMaxHist; ++j) {
           if (j == pos) {
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-              Sr[j][e] = sv[e];
-              Yr[j][e] = yv[e];
-            }
+            Sr.set(j, sv);
+            Yr.set(j, yv);
             rh[j] = (T)1 / sy;
             yyr[j] = yy;
           }
@@ -491,8 +653,11 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
     } else if (defer_oldest) {
       if constexpr (HREG) {
         // pair kept out: the oldest pair (ring slot head) stays in the history
-        vload_nt<T, EPT>(a.S + (size_t)m * vo + (size_t)head * d, i0, d, vec, Sr[0]);
-        vload_nt<T, EPT>(a.Yh + (size_t)m * vo + (size_t)head * d, i0, d, vec, Yr[0]);
+        T t[EPT];
+        ring_load<T, EPT, HB>(a.S, (size_t)m * vo + (size_t)head * d, i0, d, vec, t);
+        Sr.set(0, t);
+        ring_load<T, EPT, HB>(a.Yh, (size_t)m * vo + (size_t)head * d, i0, d, vec, t);
+        Yr.set(0, t);
         rh[0] = a.rho[(size_t)s * m + head];
         yyr[0] = a.yy[(size_t)s * m + head];
       }
@@ -609,7 +774,7 @@ __device__ __forceinline__ void lbfgs_step_one(const LbArgs<T> &a, const int64_t
 }
 
 // Start s_base + blockIdx.x (one workgroup per start of the launch's range).
-template <typename T, int TPB, int EPT, bool HREG>
+template <typename T, int TPB, int EPT, bool HREG, bool HB = false>
 __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
   __shared__ T rbuf[2 * BlockRed<TPB, T>::NMAX * (TPB / 64)];
   BlockRed<TPB, T> red{rbuf, 0};
@@ -617,7 +782,7 @@ __global__ __launch_bounds__(TPB) void lbfgs_step_kernel(LbArgs<T> a) {
   // previous count ran before this launch
   if (a.count_reset && blockIdx.x == 0 && threadIdx.x == 0) *a.count_reset = 0;
   if ((int64_t)blockIdx.x < a.s_count)
-    lbfgs_step_one<T, TPB, EPT, HREG>(a, a.s_base + blockIdx.x, red);
+    lbfgs_step_one<T, TPB, EPT, HREG, HB>(a, a.s_base + blockIdx.x, red);
 }
 
 // Two-loop direction only, for B independent histories given in logical
@@ -660,7 +825,8 @@ __global__ __launch_bounds__(TPB) void two_loop_kernel(int d, int m, const int32
     vstore<T, EPT>(P + (size_t)b * d, i0, d, vec, p);
     return;
   }
-  T Sr[kMaxHist][EPT], Yr[kMaxHist][EPT], rh[kMaxHist], g[EPT], p[EPT];
+  HistReg<T, EPT, false> Sr, Yr;
+  T rh[kMaxHist], g[EPT], p[EPT];
   T gamma = 1;
   const int i0 = tid * EPT;
   const bool vec = (d % EPT == 0);
@@ -669,18 +835,18 @@ __global__ __launch_bounds__(TPB) void two_loop_kernel(int d, int m, const int32
   for (int j = 0; j < kMaxHist; ++j) {
     rh[j] = 0;
     if (j < cnt) {
-      vload<T, EPT>(S + ((size_t)b * m + j) * d, i0, d, vec, Sr[j]);
-      vload<T, EPT>(Y + ((size_t)b * m + j) * d, i0, d, vec, Yr[j]);
+      vload<T, EPT>(S + ((size_t)b * m + j) * d, i0, d, vec, Sr.v[j]);
+      vload<T, EPT>(Y + ((size_t)b * m + j) * d, i0, d, vec, Yr.v[j]);
     } else {
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) Sr[j][e] = Yr[j][e] = (T)0;
+      Sr.zero(j);
+      Yr.zero(j);
     }
     if (j < cnt) {
       T v2[2] = {0, 0};
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
-        v2[0] += Sr[j][e] * Yr[j][e];
-        v2[1] += Yr[j][e] * Yr[j][e];
+        v2[0] += Sr.v[j][e] * Yr.v[j][e];
+        v2[1] += Yr.v[j][e] * Yr.v[j][e];
       }
       red.template reduce<2, false>(v2);
       rh[j] = (T)1 / v2[0];
@@ -718,6 +884,30 @@ __global__ __launch_bounds__(TPB) void two_loop_kernel(int d, int m, const int32
   } else {                                          \
     SB_LB_CASES_H(KERNEL, T, false, __VA_ARGS__)    \
   }
+// FP32 starts with the BF16 history ring (register-resident, m <= kMaxHist).
+#define SB_LB_CASES_HB(KERNEL, ...)                                                            \
+  if (d <= 64) {                                                                               \
+    hipLaunchKernelGGL((KERNEL<float, 64, 1, true, true>), dim3((unsigned)B), dim3(64), 0, s,   \
+                       __VA_ARGS__);                                                           \
+  } else if (d <= 128) {                                                                       \
+    hipLaunchKernelGGL((KERNEL<float, 64, 2, true, true>), dim3((unsigned)B), dim3(64), 0, s,   \
+                       __VA_ARGS__);                                                           \
+  } else if (d <= 256) {                                                                       \
+    hipLaunchKernelGGL((KERNEL<float, 64, 4, true, true>), dim3((unsigned)B), dim3(64), 0, s,   \
+                       __VA_ARGS__);                                                           \
+  } else if (d <= 512) {                                                                       \
+    hipLaunchKernelGGL((KERNEL<float, 64, 8, true, true>), dim3((unsigned)B), dim3(64), 0, s,   \
+                       __VA_ARGS__);                                                           \
+  } else if (d <= 1024) {                                                                      \
+    hipLaunchKernelGGL((KERNEL<float, 128, 8, true, true>), dim3((unsigned)B), dim3(128), 0, s, \
+                       __VA_ARGS__);                                                           \
+  } else if (d <= 2048) {                                                                      \
+    hipLaunchKernelGGL((KERNEL<float, 256, 8, true, true>), dim3((unsigned)B), dim3(256), 0, s, \
+                       __VA_ARGS__);                                                           \
+  } else {                                                                                     \
+    hipLaunchKernelGGL((KERNEL<float, 512, 8, true, true>), dim3((unsigned)B), dim3(512), 0,    \
+                       s, __VA_ARGS__);                                                        \
+  }
 
 static int check_d(int d, int m) {
   if (d < 1 || d > 4096) {
@@ -727,6 +917,13 @@ static int check_d(int d, int m) {
   if (m < 1 || m > kMaxMem) {
     set_error("L-BFGS memory m must be in [1, %d] (got %d)", kMaxMem, m);
     return SB_E_INVAL;
+  }
+  return SB_OK;
+}
+static int check_hist(const LbfgsBuffers &b) {
+  if (b.hist_bf16 && (b.dtype != DT_F32 || b.m > kMaxHist)) {
+    set_error("BF16 history needs FP32 starts and m <= %d (got m = %d)", kMaxHist, b.m);
+    return SB_E_UNSUPPORTED;
   }
   return SB_OK;
 }
@@ -778,6 +975,7 @@ static int64_t step_grid(int64_t count) { return count; }
 
 int launch_lbfgs_step(const LbfgsBuffers &b, int max_iter, double grad_tol, hipStream_t s) {
   int st = check_d(b.d, b.m);
+  if (!st) st = check_hist(b);
   if (st) return st;
   const int d = b.d;
   const int64_t B = step_grid(b.B);
@@ -786,6 +984,10 @@ int launch_lbfgs_step(const LbfgsBuffers &b, int max_iter, double grad_tol, hipS
     LbArgs<double> a = make_args<double>(b, max_iter, grad_tol);
     a.count_reset = b.count;
     SB_LB_CASES(lbfgs_step_kernel, double, b.m, a);
+  } else if (b.hist_bf16) {
+    LbArgs<float> a = make_args<float>(b, max_iter, grad_tol);
+    a.count_reset = b.count;
+    SB_LB_CASES_HB(lbfgs_step_kernel, a);
   } else {
     LbArgs<float> a = make_args<float>(b, max_iter, grad_tol);
     a.count_reset = b.count;
@@ -798,6 +1000,7 @@ int launch_lbfgs_step(const LbfgsBuffers &b, int max_iter, double grad_tol, hipS
 int launch_lbfgs_step_range(const LbfgsBuffers &b, int64_t s_begin, int64_t count, int d_class,
                             double grad_tol, int max_iter, hipStream_t s) {
   int st = check_d(d_class, b.m);
+  if (!st) st = check_hist(b);
   if (st) return st;
   if (count <= 0) return SB_OK;
   if (s_begin < 0 || s_begin + count > b.B) {
@@ -812,6 +1015,11 @@ int launch_lbfgs_step_range(const LbfgsBuffers &b, int64_t s_begin, int64_t coun
     a.s_base = s_begin;
     a.s_count = count;
     SB_LB_CASES(lbfgs_step_kernel, double, b.m, a);
+  } else if (b.hist_bf16) {
+    LbArgs<float> a = make_args<float>(b, max_iter, grad_tol);
+    a.s_base = s_begin;
+    a.s_count = count;
+    SB_LB_CASES_HB(lbfgs_step_kernel, a);
   } else {
     LbArgs<float> a = make_args<float>(b, max_iter, grad_tol);
     a.s_base = s_begin;

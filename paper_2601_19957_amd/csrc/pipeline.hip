@@ -501,6 +501,14 @@ static TileCfg env_tile(const char *name, TileCfg t) {
   (void)parse_tile(getenv(name), &t);
   return t;
 }
+// The mixed bulk keeps its L-BFGS history ring in BF16 (SB_BULK_HIST=f32 keeps
+// it in FP32): the ring is most of the step's traffic, and the pairs only
+// shape the search direction, whose descent is checked and whose stop is the
+// FP32 gradient test; the FP64 polish sets the final accuracy.
+static bool bulk_hist_bf16(const RunCfg &rc) {
+  const char *e = getenv("SB_BULK_HIST");
+  return rc.precision == SB_PREC_MIXED && rc.m <= kMaxHist && !(e && e[0] == 'f');
+}
 static bool bulk_screen() {
   const char *e = getenv("SB_MIX_SCREEN");
   return !(e && e[0] == '0');
@@ -561,6 +569,7 @@ static int carve_layout(Arena &ar, Layout &L, const sb_loglik *ll, const RunCfg 
   }
   // bulk
   L.lb.dtype = bdt;
+  L.lb.hist_bf16 = bulk_hist_bf16(rc);
   L.lb.B = B;
   L.lb.d = d;
   L.lb.m = rc.m;
@@ -1307,6 +1316,7 @@ int run_evidence(const DevProblem &P, const sb_config *cfg, sb_result *res, void
     key.two_stage = L.bulk.two_stage;
     key.screen = L.bulk.screen;
     key.grad_direct = L.bulk.grad_direct;
+    key.hist_bf16 = L.lb.hist_bf16;
     key.tile = L.bulk.tile;
     key.tile1 = L.bulk.tile1;
     key.tile2 = L.bulk.tile2;

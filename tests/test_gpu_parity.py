@@ -446,6 +446,40 @@ def test_lbfgs_timed_matches_untimed(L, dtype):
     assert np.array_equal(nb[whole], ref[whole].astype(np.float64))
 
 
+@pytest.mark.parametrize("d,seed", [(200, 4), (300, 8), (520, 7)])
+def test_lbfgs_bf16_history(L, d, seed):
+    """FP32 L-BFGS with the history ring in BF16 (dtype F32_H16): timed and untimed runs are
+    bit-identical; from points near the modes of a K = 2 mixture every start ends within the
+    FP32 bulk's reach of the oracle's mode (1e-2 in L-inf, well inside the basin: the modes
+    are 12 Mahalanobis units apart; the polish's job from there), as the FP32 ring does; each
+    launch's byte count uses 2-byte ring vectors; m > 8 is refused.  d = 200: four values per
+    thread; d = 300 (not a multiple of 8) and 520 (ragged last chunk): eight per thread, the
+    element-wise ring access and the whole-chunk loads beside it."""
+    prob = small_mixture(d, 2, seed)
+    X0 = synth.points_near_modes(prob, 64, 84, scale=1.0)
+    md = L.DeviceModel(prob, low_precision=True)
+    Xd = dev(X0).float()
+    a = L.sb_lbfgs_dev(md, Xd, m=8, max_iter=400, hist_bf16=True)
+    b = L.sb_lbfgs_timed_dev(md, Xd, m=8, max_iter=400, n_timed=24, hist_bf16=True)
+    for k in ("x", "logl", "grad", "status", "iters"):
+        assert torch.equal(a[k], b[k]), k
+    ref = O.reference_modes(prob)
+    modes = ref.modes[:ref.n_modes]
+    f = L.sb_lbfgs_dev(md, Xd, m=8, max_iter=400)
+    for r in (a, f):
+        x = r["x"].double().cpu().numpy()
+        dist = np.abs(x[:, None, :] - modes[None, :, :]).max(axis=2).min(axis=1)
+        assert float(dist.max()) < 1e-2, float(dist.max())
+    ran = b["step_rows"] > 0
+    nb, d = b["step_bytes"], prob.d
+    whole = ran & (b["step_full"] + b["step_back"] == b["step_rows"]) & (nb > 0)
+    assert whole.any()
+    ref_b = ((2 * 8 * 2 + 6 * 4) * b["step_full"] + 3 * 4 * b["step_back"]) * d
+    assert np.array_equal(nb[whole], ref_b[whole].astype(np.float64))
+    with pytest.raises(L.SbError) as e:
+        L.sb_lbfgs_dev(md, Xd, m=9, max_iter=10, hist_bf16=True)
+    assert e.value.status == L.E_UNSUPPORTED
+
 # -------------------------------------------------------------- dedup / A7
 
 def test_dedup_handmade(L):
