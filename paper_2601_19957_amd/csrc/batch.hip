@@ -752,8 +752,9 @@ int run_evidence_batch(int n, const sb_loglik *ll, const sb_box *box, const sb_c
     int max_it = 0;
     for (int q = 0; q < n; ++q) max_it = std::max(max_it, pmaxit[q]);
     const int max_steps = 42 * max_it + 64;
-    int32_t *hcounts = nullptr;
-    SB_HIP(hipHostMalloc((void **)&hcounts, sizeof(int32_t) * (size_t)n, hipHostMallocDefault));
+    // (pageable host copy of the counts, read after a stream synchronisation:
+    // no pinned allocation per call)
+    std::vector<int32_t> hcounts((size_t)n);
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int rc_st = SB_OK;
@@ -793,7 +794,7 @@ int run_evidence_batch(int n, const sb_loglik *ll, const sb_box *box, const sb_c
         }
       }
       steps += blk;
-      if (hipMemcpyAsync(hcounts, D.pcounts, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost,
+      if (hipMemcpyAsync(hcounts.data(), D.pcounts, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost,
                          s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess) {
         set_error("count readback failed");
@@ -806,7 +807,6 @@ int run_evidence_batch(int n, const sb_loglik *ll, const sb_box *box, const sb_c
     }
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    (void)hipHostFree(hcounts);
     if (rc_st) return rc_st;
     if ((st = launch_lbfgs_gather_group(lb, D.Xend, D.lend, D.status_end, s))) return st;
   }

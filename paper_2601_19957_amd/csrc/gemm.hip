@@ -800,7 +800,11 @@ __device__ inline double clamp0(double v) {  // max(v, 0), NaN stays NaN
 
 // One wave per row: |x - x_ref|^2 over the row, the decision (the row's
 // component mask), the dropped components' widened bounds and q partials,
-// |x - mu_k|^2 of the listed ones, and x_ref = x.
+// |x - mu_k|^2 of the listed ones, and x_ref = x.  NX > 0 (d <= 256 NX): the
+// row's x and x_ref sit in registers, NX 16-byte chunks per lane, their loads
+// and the bounds' issued together, and x is read once; NX = 0: any d, the row
+// streamed twice.  Both forms sum in the same order.
+template <int NX>
 __global__ __launch_bounds__(256) void mixture_screen_kernel(Model m, ScreenArgs a) {
   const int64_t Mr = a.count ? (int64_t)(*a.count) : a.M;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -810,64 +814,94 @@ __global__ __launch_bounds__(256) void mixture_screen_kernel(Model m, ScreenArgs
   const int32_t xr = a.rowmap ? a.rowmap[row] : (int32_t)row;
   const float *x = a.X + (int64_t)xr * a.ldx;
   float *xref = a.xref + (int64_t)xr * d;
-  uint32_t keep = (1u << K) - 1u;  // (K <= 16) no reference yet: every component
-  if (a.hasref[xr] > 0) {
-    float dd = 0.f;
-    for (int j = 4 * lane; j < d; j += 256) {  // (d % 8 == 0, 16-byte rows)
-      const f4v xv = *(const f4v *)(x + j);
-      const f4v rv = __builtin_nontemporal_load((const f4v *)(xref + j));
+  const bool href = a.hasref[xr] > 0;
+  constexpr int NR = NX > 0 ? NX : 1;
+  f4v xv[NR], rv[NR];
+  if constexpr (NX > 0) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float t = xv[e] - rv[e];
-        dd += t * t;
+    for (int i = 0; i < NX; ++i) {
+      const int j = 4 * lane + 256 * i;  // (d % 8 == 0: a chunk is whole or absent)
+      xv[i] = rv[i] = f4v{0.f, 0.f, 0.f, 0.f};
+      if (j < d) {
+        xv[i] = *(const f4v *)(x + j);
+        if (href) rv[i] = __builtin_nontemporal_load((const f4v *)(xref + j));
+      }
+    }
+  }
+  uint32_t keep = (1u << K) - 1u;  // (K <= 16) no reference yet: every component
+  if (href) {
+    // component k's bounds in lane k
+    double *lb = a.bnd + (int64_t)xr * 2 * K, *ub = lb + K;
+    const bool act = lane < K;
+    const double L0 = act ? lb[lane] : 0.0, U0 = act ? ub[lane] : 0.0;
+    float dd = 0.f;
+    if constexpr (NX > 0) {
+#pragma unroll
+      for (int i = 0; i < NX; ++i)
+        if (4 * lane + 256 * i < d)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float t = xv[i][e] - rv[i][e];
+            dd += t * t;
+          }
+    } else {
+      for (int j = 4 * lane; j < d; j += 256) {  // (d % 8 == 0, 16-byte rows)
+        const f4v xw = *(const f4v *)(x + j);
+        const f4v rw = __builtin_nontemporal_load((const f4v *)(xref + j));
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float t = xw[e] - rw[e];
+          dd += t * t;
+        }
       }
     }
     // (the butterfly leaves the same sum in every lane: the decision is uniform)
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) dd += __shfl_xor(dd, o, 64);
     const double D = sqrt((double)dd * (1.0 + screen_rq(d))) * (1.0 + 0x1p-40);
-    double *lb = a.bnd + (int64_t)xr * 2 * K, *ub = lb + K;
-    double Lk[kMaxK], Uk[kMaxK];
-    double mx = -INFINITY;
-#pragma unroll
-    for (int k = 0; k < kMaxK; ++k) {
-      Lk[k] = Uk[k] = 0.0;
-      if (k < K) {
-        const double w = sqrt(a.rho[k] * (1.0 + 0x1p-40)) * D;
-        Lk[k] = clamp0(lb[k] - w);
-        Uk[k] = ub[k] + w;
-        mx = fmax(mx, m.beta[k] - 0.5 * Uk[k] * Uk[k]);
-      }
+    double Lk = 0.0, Uk = 0.0, hi = -INFINITY;
+    if (act) {
+      const double w = sqrt(a.rho[lane] * (1.0 + 0x1p-40)) * D;
+      Lk = clamp0(L0 - w);
+      Uk = U0 + w;
+      hi = m.beta[lane] - 0.5 * Uk * Uk;
     }
-    keep = 0;
+    // largest upper end over the components (fmax drops a NaN: the maximum of
+    // the others, as a running fmax over k would give)
+    double mx = hi;
 #pragma unroll
-    for (int k = 0; k < kMaxK; ++k)
-      if (k < K && !(m.beta[k] - 0.5 * Lk[k] * Lk[k] < mx - kScreenGap)) keep |= 1u << k;
+    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    const bool kb = act && !(m.beta[lane] - 0.5 * Lk * Lk < mx - kScreenGap);
+    keep = (uint32_t)__ballot(kb);
     // dropped: the widened bounds now hold at x
-#pragma unroll
-    for (int k = 0; k < kMaxK; ++k)
-      if (k == lane && k < K && !((keep >> k) & 1u)) {
-        lb[k] = Lk[k];
-        ub[k] = Uk[k];
-      }
+    if (act && !kb) {
+      lb[lane] = Lk;
+      ub[lane] = Uk;
+    }
   }
   // |x - mu_k|^2 of the listed components (for their new bounds) and x_ref = x
   float nrm[kMaxK];
 #pragma unroll
   for (int k = 0; k < kMaxK; ++k) nrm[k] = 0.f;
-  for (int j = 4 * lane; j < d; j += 256) {
-    const f4v xv = *(const f4v *)(x + j);
-    __builtin_nontemporal_store(xv, (f4v *)(xref + j));
+  auto chunk = [&](int j, const f4v &xw) {
+    __builtin_nontemporal_store(xw, (f4v *)(xref + j));
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k)
       if (k < K && ((keep >> k) & 1u)) {
         const f4v mv = *(const f4v *)(m.mu32 + (int64_t)k * d + j);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const float t = xv[e] - mv[e];  // delta as the contraction forms it
+          const float t = xw[e] - mv[e];  // delta as the contraction forms it
           nrm[k] += t * t;
         }
       }
+  };
+  if constexpr (NX > 0) {
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+      if (4 * lane + 256 * i < d) chunk(4 * lane + 256 * i, xv[i]);
+  } else {
+    for (int j = 4 * lane; j < d; j += 256) chunk(j, *(const f4v *)(x + j));
   }
 #pragma unroll
   for (int k = 0; k < kMaxK; ++k)
@@ -995,8 +1029,14 @@ static int screen_check(const Model &m, const ScreenArgs &a, const char *what) {
 int launch_mixture_screen(const Model &m, const ScreenArgs &a, hipStream_t s) {
   int st = screen_check(m, a, "mixture screen");
   if (st || a.M <= 0) return st;
-  hipLaunchKernelGGL(mixture_screen_kernel, dim3((unsigned)ceil_div(a.M, 4)), dim3(256), 0, s, m,
-                     a);
+  const dim3 grid((unsigned)ceil_div(a.M, 4));
+  switch (ceil_div(m.d, 256)) {
+    case 1: hipLaunchKernelGGL(mixture_screen_kernel<1>, grid, dim3(256), 0, s, m, a); break;
+    case 2: hipLaunchKernelGGL(mixture_screen_kernel<2>, grid, dim3(256), 0, s, m, a); break;
+    case 3: hipLaunchKernelGGL(mixture_screen_kernel<3>, grid, dim3(256), 0, s, m, a); break;
+    case 4: hipLaunchKernelGGL(mixture_screen_kernel<4>, grid, dim3(256), 0, s, m, a); break;
+    default: hipLaunchKernelGGL(mixture_screen_kernel<0>, grid, dim3(256), 0, s, m, a); break;
+  }
   SB_LAUNCH_CHECK();
   hipLaunchKernelGGL(mixture_lists_kernel, dim3((unsigned)ceil_div(a.M, 1024)), dim3(1024), 0, s,
                      m, a);
