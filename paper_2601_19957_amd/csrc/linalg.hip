@@ -138,10 +138,18 @@ __global__ __launch_bounds__(256) void chol_trsm_kernel(int n, int j0, double *L
   __shared__ double D[NB][NB + 1];  // L_jj, identity-padded past nb
   __shared__ double Rd[NB];         // reciprocals of its diagonal
   __shared__ double Xc[2][64][4];   // the step's solved tile column
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e / NB, k = e % NB;
-    D[i][k] = (i < nb && k < nb) ? (k <= i ? A[(size_t)(j0 + i) * n + j0 + k] : 0.0)
+  {
+    // every load issued before the first LDS store
+    const int k = tid & 63;
+    double dv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int i = (tid >> 6) + 4 * q;
+      dv[q] = (i < nb && k < nb) ? (k <= i ? A[(size_t)(j0 + i) * n + j0 + k] : 0.0)
                                  : (i == k ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) D[(tid >> 6) + 4 * q][k] = dv[q];
   }
   if (tid < NB) Rd[tid] = tid < nb ? 1.0 / A[(size_t)(j0 + tid) * n + j0 + tid] : 1.0;
   double a[4][4];
@@ -207,13 +215,40 @@ __global__ __launch_bounds__(256) void chol_syrk_kernel(int n, int j0, double *L
   __shared__ double LI[64][NB + 1];
   __shared__ double LJ[64][NB + 1];
   const int tid = threadIdx.x;
-  for (int e = tid; e < 64 * nb; e += 256) {
-    int r = e / nb, cc = e % nb;
-    LI[r][cc] = (i0 + r < n) ? A[(size_t)(i0 + r) * n + j0 + cc] : 0.0;
-    LJ[r][cc] = (k0 + r < n) ? A[(size_t)(k0 + r) * n + j0 + cc] : 0.0;
+  const int ti = (tid >> 4) * 4, tk = (tid & 15) * 4;
+  // this thread's outputs, fetched with the panels (their loads overlap)
+  double old[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + ti + u, k = k0 + tk + v;
+      old[u][v] = (i < n && k < n && k <= i) ? A[(size_t)i * n + k] : 0.0;
+    }
+  if (nb == NB) {
+    // a whole panel: every load issued before the first LDS store
+    const int cc = tid & 63;
+    double vi[16], vj[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int r = (tid >> 6) + 4 * q;
+      vi[q] = (i0 + r < n) ? A[(size_t)(i0 + r) * n + j0 + cc] : 0.0;
+      vj[q] = (k0 + r < n) ? A[(size_t)(k0 + r) * n + j0 + cc] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int r = (tid >> 6) + 4 * q;
+      LI[r][cc] = vi[q];
+      LJ[r][cc] = vj[q];
+    }
+  } else {
+    for (int e = tid; e < 64 * nb; e += 256) {
+      int r = e / nb, cc = e % nb;
+      LI[r][cc] = (i0 + r < n) ? A[(size_t)(i0 + r) * n + j0 + cc] : 0.0;
+      LJ[r][cc] = (k0 + r < n) ? A[(size_t)(k0 + r) * n + j0 + cc] : 0.0;
+    }
   }
   __syncthreads();
-  const int ti = (tid >> 4) * 4, tk = (tid & 15) * 4;
   double acc[4][4] = {};
   for (int cc = 0; cc < nb; ++cc) {
     double a[4], b[4];
@@ -232,7 +267,7 @@ __global__ __launch_bounds__(256) void chol_syrk_kernel(int n, int j0, double *L
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       int i = i0 + ti + u, k = k0 + tk + v;
-      if (i < n && k < n && k <= i) A[(size_t)i * n + k] -= acc[u][v];
+      if (i < n && k < n && k <= i) A[(size_t)i * n + k] = old[u][v] - acc[u][v];
     }
 }
 
