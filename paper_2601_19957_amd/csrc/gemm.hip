@@ -963,44 +963,67 @@ __global__ __launch_bounds__(1024) void mixture_lists_kernel(Model m, ScreenArgs
     }
 }
 
-// After the contraction, one thread per row: l and the responsibilities from
-// q (the epilogue's own function, FP64 arithmetic, r stored in FP32), and the
-// listed components' bounds from their q_k.
-__global__ __launch_bounds__(64) void mixture_post_kernel(Model m, ScreenArgs a) {
+// After the contraction, 16 lanes per row with component k in lane k of the
+// row's group: l and the responsibilities from q, the arithmetic of the
+// epilogue's own function (mixture_resp) in its order: lane k sums q_k's
+// tile partials in turn and forms exp(a_k - max), and every lane adds the
+// gathered terms over k = 0, 1, ...; r stored in FP32.  Then the listed
+// components' bounds from their q_k.
+__global__ __launch_bounds__(256) void mixture_post_kernel(Model m, ScreenArgs a) {
+  static_assert(kMaxK <= 16, "a row's components fit its 16 lanes");
   const int64_t Mr = a.count ? (int64_t)(*a.count) : a.M;
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= Mr) return;
+  const int64_t row = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int c = threadIdx.x & 15, base = (threadIdx.x & 63) & ~15;
+  if (row >= Mr) return;  // (whole groups: the shuffles below stay in the group)
   const int d = m.d, K = m.K;
+  const bool act = c < K;
   const float *qp = a.qpart + (size_t)row * K * a.ntn;
+  double q = 0.0, ak = 0.0;
+  if (act) {
+    for (int t = 0; t < a.ntn; ++t) q += (double)qp[c * a.ntn + t];
+    ak = m.beta[c] - 0.5 * q;
+  }
   double lse;
-  float r[kMaxK];
-  mixture_resp<float>(m, qp, a.ntn, lse, r);
-  const int64_t orow = a.outmap ? (int64_t)a.outmap[row] : row;
-  if (a.logl_f64)
-    ((double *)a.logl)[orow] = m.c + lse;
-  else
-    ((float *)a.logl)[orow] = (float)(m.c + lse);
+  if (K == 1) {
+    lse = __shfl(ak, base, 64);
+  } else {
+    double mx = -INFINITY;
 #pragma unroll
-  for (int k = 0; k < kMaxK; ++k)
-    if (k < K) a.resp[row * K + k] = r[k];
+    for (int k = 0; k < kMaxK; ++k) {
+      const double v = __shfl(ak, base + k, 64);
+      if (k < K) mx = fmax(mx, v);
+    }
+    const double ek = act ? exp(ak - mx) : 0.0;
+    double ssum = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k) {
+      const double v = __shfl(ek, base + k, 64);
+      if (k < K) ssum += v;
+    }
+    lse = mx + log(ssum);
+  }
+  if (c == 0) {
+    const int64_t orow = a.outmap ? (int64_t)a.outmap[row] : row;
+    if (a.logl_f64)
+      ((double *)a.logl)[orow] = m.c + lse;
+    else
+      ((float *)a.logl)[orow] = (float)(m.c + lse);
+  }
+  if (act) a.resp[row * K + c] = K == 1 ? 1.f : (float)exp(ak - lse);
   const int32_t xr = a.rowmap ? a.rowmap[row] : (int32_t)row;
   const uint32_t mk = a.mask[row];
-  const double cq = screen_cq(d), rq = screen_rq(d);
-  double *lb = a.bnd + (int64_t)xr * 2 * K, *ub = lb + K;
-#pragma unroll
-  for (int k = 0; k < kMaxK; ++k)
-    if (k < K && ((mk >> k) & 1u)) {
-      double q = 0.0;
-      for (int t = 0; t < a.ntn; ++t) q += (double)qp[k * a.ntn + t];
-      const double rk = a.rho[k] * (1.0 + 0x1p-40);
-      const double nk = (double)a.nrm[row * K + k] * (1.0 + rq);
-      const double e = cq * rk * nk;
-      // (+- sigma_k 2^-23 |delta|: delta = fl32(x - mu_k) against the exact x - mu_k)
-      const double rr = sqrt(rk * nk) * 0x1p-23;
-      lb[k] = clamp0(sqrt(clamp0(q - e)) - rr);
-      ub[k] = sqrt(clamp0(q + e)) + rr;
-    }
-  a.hasref[xr] = 1;
+  if (act && ((mk >> c) & 1u)) {
+    const double cq = screen_cq(d), rq = screen_rq(d);
+    double *lb = a.bnd + (int64_t)xr * 2 * K, *ub = lb + K;
+    const double rk = a.rho[c] * (1.0 + 0x1p-40);
+    const double nk = (double)a.nrm[row * K + c] * (1.0 + rq);
+    const double e = cq * rk * nk;
+    // (+- sigma_k 2^-23 |delta|: delta = fl32(x - mu_k) against the exact x - mu_k)
+    const double rr = sqrt(rk * nk) * 0x1p-23;
+    lb[c] = clamp0(sqrt(clamp0(q - e)) - rr);
+    ub[c] = sqrt(clamp0(q + e)) + rr;
+  }
+  if (c == 0) a.hasref[xr] = 1;
 }
 
 static int screen_check(const Model &m, const ScreenArgs &a, const char *what) {
@@ -1051,7 +1074,7 @@ int launch_mixture_post(const Model &m, const ScreenArgs &a, hipStream_t s) {
     set_error("mixture post: needs l and responsibility outputs");
     return SB_E_INVAL;
   }
-  hipLaunchKernelGGL(mixture_post_kernel, dim3((unsigned)ceil_div(a.M, 64)), dim3(64), 0, s, m,
+  hipLaunchKernelGGL(mixture_post_kernel, dim3((unsigned)ceil_div(a.M, 16)), dim3(256), 0, s, m,
                      a);
   SB_LAUNCH_CHECK();
   return SB_OK;
