@@ -746,7 +746,8 @@ def main() -> int:
         return 0
     if args.a3_only:
         print(json.dumps(dict(a3_only=True, a3_variants=a3_variants(L),
-                              lbfgs_step_variants=lbfgs_step_variants(L))), flush=True)
+                              lbfgs_step_variants=None if args.no_step_variants
+                              else lbfgs_step_variants(L))), flush=True)
         return 0
     names = [n.strip() for n in args.workload.split(",") if n.strip()]
     log(f"generating {names}")

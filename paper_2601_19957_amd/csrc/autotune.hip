@@ -1,7 +1,8 @@
 // Tile-shape autotuner for the quadratic-form GEMM.
 //
 // The first time a shape class (dtype, d, K, M rounded up to a power of two)
-// is seen, each candidate tile (BM x BN in {64, 128}^2; for the BF16 and
+// is seen, each candidate tile (BM x BN in {64, 128}^2, the FP64 ones but
+// 128 x 128 with a 32-wide k-tile; for the BF16 and
 // split contractions BM x BN x k-tile in {128x128x32, 128x128x64, 256x128x32,
 // 128x256x32, 256x256x32 on eight waves}, the square 32-wide ones also with
 // two ping-pong LDS stages) is timed with HIP events, one warm-up and five timed launches,

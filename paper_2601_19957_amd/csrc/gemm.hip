@@ -598,6 +598,11 @@ int launch_quad_gemm(int dtype, const Model &m, const ASrc &a, int64_t M, const 
   if (dtype == DT_F64) {
     p.mu = m.mu64;
     p.P = m.P64;
+    if (t.bk == 32) {  // 32-wide k-tiles: half the barriers per MFMA
+      if (t.bm == 64 && t.bn == 64) return launch_t<double, double, 64, 64, 32>(p, s);
+      if (t.bm == 128 && t.bn == 64) return launch_t<double, double, 128, 64, 32>(p, s);
+      if (t.bm == 64 && t.bn == 128) return launch_t<double, double, 64, 128, 32>(p, s);
+    }
     if (t.bm == 64 && t.bn == 64) return launch_t<double, double, 64, 64, 16>(p, s);
     if (t.bm == 128 && t.bn == 64) return launch_t<double, double, 128, 64, 16>(p, s);
     if (t.bm == 64 && t.bn == 128) return launch_t<double, double, 64, 128, 16>(p, s);

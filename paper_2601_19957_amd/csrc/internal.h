@@ -115,7 +115,7 @@ struct QuadOut {
 // Tile shape used for a GEMM call; chosen by the autotuner.
 struct TileCfg {
   int bm = 128, bn = 128;
-  int bk = 32;      // k-tile of the BF16 matrix-core kernels
+  int bk = 32;      // k-tile of the BF16 kernels; FP64: 32 at 64x64, 128x64, 64x128, else 16
   int stages = 1;  // BF16 kernels: LDS stages (2 = ping-pong, square tiles, k-tile 32)
 };
 

@@ -107,6 +107,31 @@ def test_logl_grad_fp64(L, name, B):
     assert el < 1e-11 and eg < 1e-11, (el, eg)
 
 
+FP64_TILES = ["64x64x16", "128x64x16", "64x128x16", "128x128x16", "64x64x32", "128x64x32",
+              "64x128x32"]
+
+
+@pytest.mark.parametrize("tile", FP64_TILES)
+@pytest.mark.parametrize("make", [lambda: small_mixture(200, 3, 31), lambda: small_mixture(37, 3, 32),
+                                  lambda: t_problem(70, 33)], ids=["mix_d200_K3", "mix_d37_K3",
+                                                                   "t_d70"])
+def test_logl_grad_fp64_every_tile(L, tile, make, monkeypatch):
+    """Each FP64 tile the autotuner may pick (BM x BN x k-tile; SB_TILE forces it) on ragged
+    row and column tails: d = 200 (16-byte rows, 7 of 13 32-wide k-tiles whole), d = 37 (odd:
+    the element-wise kernel), a Student-t at d = 70, 131 rows; l and the gradient equal the
+    oracle's to 1e-11.  (d <= 128 problems would take the fused launch: SB_FUSED=0 keeps the
+    tiled contraction.)"""
+    monkeypatch.setenv("SB_TILE", tile)
+    monkeypatch.setenv("SB_FUSED", "0")
+    prob = make()
+    X = synth.random_points(prob, 131, 34, spread=0.9)
+    lo, go = O.logl(prob, X)
+    m = L.DeviceModel(prob)
+    l, g = (t.cpu().numpy() for t in L.sb_logl_grad_dev(m, dev(X)))
+    el, eg = rel(l, lo), rel(g, go, axis=1)
+    assert el < 1e-11 and eg < 1e-11, (el, eg)
+
+
 @pytest.mark.parametrize("make", [lambda: small_mixture(96, 4, 21), lambda: t_problem(5, 22),
                                   lambda: small_mixture(1, 1, 23), lambda: t_problem(128, 24)],
                          ids=["mix_d96_K4", "t_d5", "gauss_d1", "t_d128"])
