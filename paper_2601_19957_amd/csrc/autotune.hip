@@ -2,7 +2,7 @@
 //
 // The first time a shape class (dtype, d, K, M rounded up to a power of two)
 // is seen, each candidate tile (BM x BN in {64, 128}^2, the FP64 ones but
-// 128 x 128 with a 32-wide k-tile; for the BF16 and
+// 128 x 128 with a 32-wide k-tile, and for FP64 32 x 64 x 32; for the BF16 and
 // split contractions BM x BN x k-tile in {128x128x32, 128x128x64, 256x128x32,
 // 128x256x32, 256x256x32 on eight waves}, the square 32-wide ones also with
 // two ping-pong LDS stages) is timed with HIP events, one warm-up and five timed launches,
@@ -75,11 +75,11 @@ bool time_launches(int dtype, const Model &m, const ASrc &a, QuadOut o, int64_t 
   float best_ms = 0.f;
   bool have = false;
   // GEMM tiles (BM, BN); for the BF16 kernels (BM, BN, k-tile)
-  const int cands[4][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}};
+  const int cands[5][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}, {32, 64}};
   const int cands_bf[7][4] = {{128, 128, 32, 1}, {128, 128, 64, 1}, {256, 128, 32, 1},
                               {128, 256, 32, 1}, {256, 256, 32, 1}, {128, 128, 32, 2},
                               {256, 256, 32, 2}};
-  const int nc = bf ? 7 : 4;
+  const int nc = bf ? 7 : (dtype == DT_F64 ? 5 : 4);  // (32 x 64: FP64 only)
   for (int c = 0; c < nc && ok; ++c) {
     TileCfg t;
     t.bm = bf ? cands_bf[c][0] : cands[c][0];

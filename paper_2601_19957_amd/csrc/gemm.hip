@@ -589,7 +589,9 @@ int launch_quad_gemm(int dtype, const Model &m, const ASrc &a, int64_t M, const 
   p.K = m.K;
   p.yneg = o.yneg ? 1 : 0;
   if (t.bn != 64 && t.bn != 128) t.bn = 128;
-  if (t.bm != 64 && t.bm != 128) t.bm = 128;
+  // (32-row tiles: FP64 with a 32-wide k-tile and 64 columns only)
+  const bool f64_32 = dtype == DT_F64 && t.bm == 32 && t.bn == 64 && t.bk == 32;
+  if (t.bm != 64 && t.bm != 128 && !f64_32) t.bm = 128;
   o.ntn = (int)ceil_div(m.d, t.bn);
   p.ntn = o.ntn;
   p.Y = o.Y;
@@ -599,6 +601,7 @@ int launch_quad_gemm(int dtype, const Model &m, const ASrc &a, int64_t M, const 
     p.mu = m.mu64;
     p.P = m.P64;
     if (t.bk == 32) {  // 32-wide k-tiles: half the barriers per MFMA
+      if (f64_32) return launch_t<double, double, 32, 64, 32>(p, s);
       if (t.bm == 64 && t.bn == 64) return launch_t<double, double, 64, 64, 32>(p, s);
       if (t.bm == 128 && t.bn == 64) return launch_t<double, double, 128, 64, 32>(p, s);
       if (t.bm == 64 && t.bn == 128) return launch_t<double, double, 64, 128, 32>(p, s);

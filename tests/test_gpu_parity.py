@@ -108,7 +108,7 @@ def test_logl_grad_fp64(L, name, B):
 
 
 FP64_TILES = ["64x64x16", "128x64x16", "64x128x16", "128x128x16", "64x64x32", "128x64x32",
-              "64x128x32"]
+              "64x128x32", "32x64x32"]
 
 
 @pytest.mark.parametrize("tile", FP64_TILES)
