@@ -814,6 +814,8 @@ __device__ inline double clamp0(double v) {  // max(v, 0), NaN stays NaN
 // streamed twice.  Both forms sum in the same order.
 template <int NX>
 __global__ __launch_bounds__(256) void mixture_screen_kernel(Model m, ScreenArgs a) {
+  // the list pass (the next launch) counts into cnt: zero it here
+  if (blockIdx.x == 0 && threadIdx.x < m.K) a.cnt[threadIdx.x] = 0;
   const int64_t Mr = a.count ? (int64_t)(*a.count) : a.M;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -1059,7 +1061,12 @@ static int screen_check(const Model &m, const ScreenArgs &a, const char *what) {
 
 int launch_mixture_screen(const Model &m, const ScreenArgs &a, hipStream_t s) {
   int st = screen_check(m, a, "mixture screen");
-  if (st || a.M <= 0) return st;
+  if (st) return st;
+  if (!a.cnt || !a.rows || !a.xrows) {
+    set_error("mixture screen: needs the component lists");
+    return SB_E_INVAL;
+  }
+  if (a.M <= 0) return launch_fill_i32(m.K, 0, a.cnt, s);  // empty lists
   const dim3 grid((unsigned)ceil_div(a.M, 4));
   switch (ceil_div(m.d, 256)) {
     case 1: hipLaunchKernelGGL(mixture_screen_kernel<1>, grid, dim3(256), 0, s, m, a); break;

@@ -221,7 +221,7 @@ struct ScreenArgs {
   bool logl_f64 = false;
   float *resp = nullptr;
 };
-// screen + list passes (cnt zeroed by the caller)
+// screen + list passes (the screen zeroes cnt)
 int launch_mixture_screen(const Model &m, const ScreenArgs &a, hipStream_t s);
 int launch_mixture_post(const Model &m, const ScreenArgs &a, hipStream_t s);
 // rho[k] = max_i sum_j |P_k[i][j]| (FP64 P [K][d][d]); rho is zeroed first.

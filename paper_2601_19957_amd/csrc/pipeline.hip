@@ -277,7 +277,6 @@ struct Evaluator {
                   (long long)(a.rows > 0 ? a.rows : M), (long long)nstate);
         return SB_E_INVAL;
       }
-      if ((st = launch_fill_i32(m.K, 0, lcnt, s))) return st;
       if ((st = launch_mixture_screen(m, sa, s))) return st;
       ASrc a2 = a;
       a2.rowmap = lxrows;
