@@ -11,7 +11,8 @@
 // overwrites) or, for host-level callers, on private seeded buffers of the
 // shape (up to 8192 rows, values in [-1, 1)).  Timing synchronises the
 // stream, so a stream under graph capture gets the heuristic choice (not
-// cached).  SB_TILE=BMxBN[xBK[xSTAGES]] forces a shape;
+// cached).  kt = 16 restricts the FP64 and FP32 candidates to 16-wide
+// k-tiles.  SB_TILE=BMxBN[xBK[xSTAGES]] forces a shape;
 // SB_AUTOTUNE=0 uses the heuristic without timing.
 #include <algorithm>
 #include <cstdio>
@@ -67,7 +68,7 @@ TileCfg heuristic(int d, int64_t M) {
 // Times the candidates of one launch; returns false on any runtime error (the
 // caller then uses the heuristic).
 bool time_launches(int dtype, const Model &m, const ASrc &a, QuadOut o, int64_t M, hipStream_t s,
-                   TileCfg *best) {
+                   TileCfg *best, int kt) {
   const bool bf = (dtype == DT_BF16 || dtype == DT_F32S) && quad_gemm_bf16_ok(m.d);
   hipEvent_t e0, e1;
   bool ok = hipEventCreate(&e0) == hipSuccess;
@@ -79,12 +80,12 @@ bool time_launches(int dtype, const Model &m, const ASrc &a, QuadOut o, int64_t 
   const int cands_bf[7][4] = {{128, 128, 32, 1}, {128, 128, 64, 1}, {256, 128, 32, 1},
                               {128, 256, 32, 1}, {256, 256, 32, 1}, {128, 128, 32, 2},
                               {256, 256, 32, 2}};
-  const int nc = bf ? 7 : (dtype == DT_F64 ? 5 : 4);  // (32 x 64: FP64 only)
+  const int nc = bf ? 7 : (dtype == DT_F64 && kt == 32 ? 5 : 4);  // (32 x 64: FP64 only)
   for (int c = 0; c < nc && ok; ++c) {
     TileCfg t;
     t.bm = bf ? cands_bf[c][0] : cands[c][0];
     t.bn = bf ? cands_bf[c][1] : cands[c][1];
-    t.bk = bf ? cands_bf[c][2] : 32;
+    t.bk = bf ? cands_bf[c][2] : kt;
     t.stages = bf ? cands_bf[c][3] : 1;
     // ray points run only the 32-wide k-tiles, no 256 x 128, and two stages only for
     // the BF16 operand
@@ -112,7 +113,7 @@ bool time_launches(int dtype, const Model &m, const ASrc &a, QuadOut o, int64_t 
 }
 
 // Times the candidates on private buffers of shape (min(M, 8192), d, K).
-bool time_candidates(int dtype, int d, int K, int64_t M, hipStream_t s, TileCfg *best) {
+bool time_candidates(int dtype, int d, int K, int64_t M, hipStream_t s, TileCfg *best, int kt) {
   const int64_t Mt = std::max<int64_t>(1, std::min<int64_t>(M, 8192));
   const bool bf = (dtype == DT_BF16 || dtype == DT_F32S) && quad_gemm_bf16_ok(d);
   const size_t in_es = (dtype == DT_F64) ? 8 : 4;
@@ -169,7 +170,7 @@ bool time_candidates(int dtype, int d, int K, int64_t M, hipStream_t s, TileCfg 
   o.Y = Y;
   o.ldy = (int64_t)K * d;
   o.qpart = q;
-  const bool ok = time_launches(dtype, m, a, o, Mt, s, best);
+  const bool ok = time_launches(dtype, m, a, o, Mt, s, best, kt);
   (void)hipStreamSynchronize(s);
   (void)hipFree(buf);
   (void)hipGetLastError();
@@ -188,7 +189,7 @@ bool parse_tile(const char *e, TileCfg *t) {
 }
 
 TileCfg autotune_tiles(int dtype, const Model &m, int64_t M, hipStream_t s, const TuneProbe *probe,
-                       bool may_alloc) {
+                       bool may_alloc, int kt) {
   {
     TileCfg t;
     if (parse_tile(getenv("SB_TILE"), &t)) return t;
@@ -197,24 +198,29 @@ TileCfg autotune_tiles(int dtype, const Model &m, int64_t M, hipStream_t s, cons
   const bool timed = !(at && at[0] == '0');
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess) cs = hipStreamCaptureStatusNone;
-  if (!timed || cs != hipStreamCaptureStatusNone || M <= 0) return heuristic(m.d, M);
+  auto heur = [&]() {
+    TileCfg h = heuristic(m.d, M);
+    if (dtype == DT_F64) h.bk = kt;
+    return h;
+  };
+  if (!timed || cs != hipStreamCaptureStatusNone || M <= 0) return heur();
   std::lock_guard<std::mutex> lk(g_mu);
   int dev = 0;
   (void)hipGetDevice(&dev);
   // (the operand kind and the sum-of-squares mode select kernels of their own)
-  const int variant = probe ? probe->a.kind + 2 * (probe->o.sumsq ? 1 : 0) : 0;
+  const int variant = (probe ? probe->a.kind + 2 * (probe->o.sumsq ? 1 : 0) : 0) + 4 * (kt != 32);
   auto key = std::make_tuple(dev, dtype, m.d, m.K, bucket(M), variant);
   auto it = g_cache.find(key);
   if (it != g_cache.end()) return it->second;
-  TileCfg t = heuristic(m.d, M);
+  TileCfg t = heur();
   bool ok = false;
   if (probe)  // a prefix of the caller's launch is enough to rank the tiles
-    ok = time_launches(dtype, m, probe->a, probe->o, std::min<int64_t>(M, 65536), s, &t);
+    ok = time_launches(dtype, m, probe->a, probe->o, std::min<int64_t>(M, 65536), s, &t, kt);
   else if (may_alloc)
-    ok = time_candidates(dtype, m.d, m.K, M, s, &t);
+    ok = time_candidates(dtype, m.d, m.K, M, s, &t, kt);
   else
     return t;  // no buffers to time on: heuristic, not cached
-  if (!ok) t = heuristic(m.d, M);
+  if (!ok) t = heur();
   g_cache[key] = t;
   return t;
 }

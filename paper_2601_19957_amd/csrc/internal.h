@@ -498,7 +498,8 @@ struct TuneProbe {
   QuadOut o;
 };
 TileCfg autotune_tiles(int dtype, const Model &m, int64_t M, hipStream_t s,
-                       const TuneProbe *probe = nullptr, bool may_alloc = false);
+                       const TuneProbe *probe = nullptr, bool may_alloc = false,
+                       int kt = 32);
 
 }  // namespace sb
 
