@@ -677,6 +677,8 @@ __global__ __launch_bounds__(256) void finish_kernel(Model m, FinishArgs f) {
     }
     return;
   }
+  // (its gradient written by the contraction: one listed component, r = 1)
+  if (f.resp && f.skip1 && __popc(f.skip1[row]) == 1) return;
   T r[kMaxK];
   if (f.resp) {  // l and the responsibilities came from the mixture-rows pass
 #pragma unroll
@@ -970,6 +972,8 @@ __global__ __launch_bounds__(1024) void mixture_lists_kernel(Model m, ScreenArgs
       const int64_t pos = (int64_t)k * a.cap + base[k] + woff[wave][k] + rank[k];
       a.rows[pos] = (int32_t)row;
       a.xrows[pos] = xr;
+      if (a.gdst)
+        a.gdst[pos] = __popc(mk) == 1 ? (a.outmap ? a.outmap[row] : (int32_t)row) : -1;
     }
 }
 
@@ -1311,6 +1315,10 @@ int launch_finish(int dtype, const Model &m, const FinishArgs &f, hipStream_t s)
   if (m.K > kMaxK) {
     set_error("K=%d exceeds the supported %d components", m.K, kMaxK);
     return SB_E_UNSUPPORTED;
+  }
+  if (f.skip1 && (!f.resp || f.aux)) {
+    set_error("finish: skipped rows need precomputed responsibilities and no aux output");
+    return SB_E_INVAL;
   }
   dim3 grid((unsigned)ceil_div(f.M, 4));
   if (grid.x == 0) return SB_OK;

@@ -43,6 +43,11 @@ struct Bf16Params {
   // qpart is then indexed by the Y row
   const int32_t *gcnt;
   int64_t gcap;
+  // grouped: gradient rows of the rows with a single listed component, -Y
+  // into them instead of Y (QuadOut::gdst)
+  const int32_t *gdst;
+  float *gdir;
+  int64_t ldg;
 };
 
 typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
@@ -127,7 +132,7 @@ __device__ __forceinline__ void bf16_tile(const Bf16Params &g, const int64_t w, 
   const int ncol = g.K * g.ntn;
   int col = 0;
   int64_t mt = 0, M;
-  const int32_t *rmap = g.a.rowmap, *ymp = g.ymap;
+  const int32_t *rmap = g.a.rowmap, *ymp = g.ymap, *gdp = nullptr;
   if (g.gcnt) {
     // row tiles of the components one after another (ceil(gcnt[k] / BM) each,
     // a count above the lists' capacity taken as the capacity), each row tile
@@ -158,6 +163,7 @@ __device__ __forceinline__ void bf16_tile(const Bf16Params &g, const int64_t w, 
     M = cnt(kk);
     rmap += (int64_t)kk * g.gcap;
     ymp += (int64_t)kk * g.gcap;
+    if (g.gdst) gdp = g.gdst + (int64_t)kk * g.gcap;
   } else {
     if (ncol % 8 == 0) {
       const int per = ncol / 8;
@@ -464,7 +470,12 @@ __device__ __forceinline__ void bf16_tile(const Bf16Params &g, const int64_t w, 
       if (row < M && cin) {
         if (g.Y) {
           const int64_t yrow = ymp ? (int64_t)ymp[row] : row;
-          *(f4v *)&g.Y[yrow * g.ldy + g.ycol + (int64_t)k * d + c0] = g.yneg ? -y : y;
+          const int32_t grow = gdp ? gdp[row] : -1;
+          if (grow >= 0) {
+            *(f4v *)&g.gdir[(int64_t)grow * g.ldg + c0] = -y;
+          } else {
+            *(f4v *)&g.Y[yrow * g.ldy + g.ycol + (int64_t)k * d + c0] = g.yneg ? -y : y;
+          }
         }
       }
       if (wq && row < M && cin) {
@@ -599,6 +610,14 @@ int launch_quad_gemm_bf16(int nprod, const Model &m, const ASrc &a, int64_t M,
   p.gcnt = o.gcnt;
   p.gcap = o.gcap;
   p.yneg = o.yneg ? 1 : 0;
+  p.gdst = o.gdst;
+  p.gdir = (float *)o.gdir;
+  p.ldg = o.ldg;
+  if (o.gdst && (!o.gcnt || !o.Y || !o.gdir || o.yneg || (uintptr_t)o.gdir % 16 != 0 ||
+                 o.ldg % 4 != 0 || o.ldg < m.d)) {
+    set_error("direct gradient rows need grouped Y rows and a 16-byte aligned gradient");
+    return SB_E_INVAL;
+  }
   if (o.gcnt && (a.kind != 0 || !a.rowmap || !o.ymap || o.gcap < M)) {
     set_error("grouped contraction needs row lists of X and Y rows with capacity >= M");
     return SB_E_INVAL;

@@ -110,6 +110,13 @@ struct QuadOut {
   const int32_t *gcnt = nullptr;
   int64_t gcap = 0;
   bool yneg = false;  // store -Y (a Gaussian's gradient); q still uses Y
+  // BF16 kernels, grouped: gdst + k * gcap lists beside ymap the gradient
+  // row of each listed row that has no other listed component (its only
+  // responsibility is exactly 1), else -1; such a row takes -Y in that row
+  // of gdir [*][ldg] instead of its Y block (q still uses Y)
+  const int32_t *gdst = nullptr;
+  void *gdir = nullptr;
+  int64_t ldg = 0;
 };
 
 // Tile shape used for a GEMM call; chosen by the autotuner.
@@ -153,6 +160,9 @@ struct FinishArgs {
   // mixture with l and FP32 responsibilities [M][K] already computed (by the
   // mixture-rows pass): the epilogue forms the gradient only
   const void *resp = nullptr;
+  // with resp: rows whose component mask has a single bit had their gradient
+  // written by the contraction (QuadOut::gdst) and are skipped
+  const uint32_t *skip1 = nullptr;
 };
 int launch_finish(int dtype, const Model &m, const FinishArgs &f, hipStream_t s);
 // FP64 logL + gradient of rows of X in one launch (contraction and row
@@ -213,6 +223,8 @@ struct ScreenArgs {
   float *qpart = nullptr;           // [M][K][ntn] q partials of the contraction
   int ntn = 0;
   uint32_t *mask = nullptr;         // [cap] components listed per row (bit k)
+  int32_t *gdst = nullptr;  // [K][cap] (nullable): beside rows, the output row of a row
+                            // listed for one component only, else -1
   int32_t *cnt = nullptr, *rows = nullptr, *xrows = nullptr;  // [K], [K][cap], [K][cap]
   int64_t cap = 0;
   // post pass: l (at outmap[row], FP64 or FP32) and r [M][K]

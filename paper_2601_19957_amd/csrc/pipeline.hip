@@ -213,7 +213,7 @@ struct Evaluator {
   uint32_t *mask = nullptr;  // [cap]
   const bf16_t *Uhi = nullptr, *Ulo = nullptr;  // [K][d][d]
   TileCfg tile1, tile2;                         // tiles of the two stages
-  int32_t *lcnt = nullptr, *lrows = nullptr, *lxrows = nullptr;
+  int32_t *lcnt = nullptr, *lrows = nullptr, *lxrows = nullptr, *lgdst = nullptr;
   float *resp = nullptr;  // [cap][K]
   // Single Gaussian on the split kernel: grad l = -Y, so the contraction
   // writes -Y straight into the gradient rows and the epilogue forms l only.
@@ -235,6 +235,7 @@ struct Evaluator {
         bnd = ar.take<double>((size_t)nstate * 2 * m.K);
         hasref = ar.take<int32_t>(nstate);
         mask = ar.take<uint32_t>(cap);
+        lgdst = ar.take<int32_t>((size_t)m.K * cap);
       }
     }
     return ar.ok() ? SB_OK : SB_E_NOMEM;
@@ -245,8 +246,11 @@ struct Evaluator {
   // responsibilities with the row lists, stage 2 (Y of the active
   // components); the epilogue takes r from the rows pass.  Either way it reads
   // exactly the Y rows the contraction wrote.
+  // (screened, with grad: the rows with a single listed component take their
+  // gradient from the contraction, the epilogue skips them)
   int contract_two_stage(const ASrc &a, int64_t M, const int32_t *count, void *logl,
-                         const int32_t *outmap, bool logl_f64, hipStream_t s) {
+                         const int32_t *outmap, bool logl_f64, void *grad, int64_t ldg,
+                         hipStream_t s) {
     int st;
     if (screen) {
       ScreenArgs sa;
@@ -272,6 +276,8 @@ struct Evaluator {
       sa.outmap = outmap;
       sa.logl_f64 = logl_f64;
       sa.resp = resp;
+      const bool gdir = grad && dtype == DT_F32;  // (the contraction writes FP32 rows)
+      sa.gdst = gdir ? lgdst : nullptr;
       if ((a.rows > 0 ? a.rows : M) > nstate) {
         set_error("screened mixture: %lld operand rows, state for %lld",
                   (long long)(a.rows > 0 ? a.rows : M), (long long)nstate);
@@ -288,6 +294,11 @@ struct Evaluator {
       o2.gcnt = lcnt;
       o2.gcap = cap;
       o2.qpart = qpart;
+      if (gdir) {
+        o2.gdst = lgdst;
+        o2.gdir = grad;
+        o2.ldg = ldg;
+      }
       if ((st = launch_quad_gemm(DT_F32S, m, a2, cap, nullptr, o2, tile2, s))) return st;
       if (o2.ntn != sa.ntn) {
         set_error("screened mixture: %d column tiles, expected %d", o2.ntn, sa.ntn);
@@ -346,7 +357,7 @@ struct Evaluator {
       return launch_fused_logl_grad(m, a, M, count, outmap, (double *)logl, (double *)grad, ldg,
                                     nullptr, s);
     if (ts) {
-      if ((st = contract_two_stage(a, M, count, logl, outmap, logl_f64, s))) return st;
+      if ((st = contract_two_stage(a, M, count, logl, outmap, logl_f64, grad, ldg, s))) return st;
     } else if (gd) {
       QuadOut o;
       o.Y = grad;
@@ -379,6 +390,8 @@ struct Evaluator {
     f.aux = aux;
     f.logl_f64 = logl_f64;
     f.resp = ts ? resp : nullptr;
+    if (ts && screen && grad && dtype == DT_F32)
+      f.skip1 = mask;  // (single-component rows: by the contraction)
     if (gd) f.grad = nullptr;  // (written by the contraction)
     return launch_finish(dtype, m, f, s);
   }
