@@ -200,7 +200,7 @@ TileCfg autotune_tiles(int dtype, const Model &m, int64_t M, hipStream_t s, cons
   if (hipStreamIsCapturing(s, &cs) != hipSuccess) cs = hipStreamCaptureStatusNone;
   auto heur = [&]() {
     TileCfg h = heuristic(m.d, M);
-    if (dtype == DT_F64) h.bk = kt;
+    if (dtype == DT_F64 || dtype == DT_F32) h.bk = kt;
     return h;
   };
   if (!timed || cs != hipStreamCaptureStatusNone || M <= 0) return heur();

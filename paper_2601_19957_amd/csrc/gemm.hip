@@ -618,6 +618,12 @@ int launch_quad_gemm(int dtype, const Model &m, const ASrc &a, int64_t M, const 
     return SB_E_INVAL;
   }
   if (dtype == DT_F32) {
+    if (t.bk == 32) {  // 32-wide k-tiles: half the barriers per MFMA
+      if (t.bm == 64 && t.bn == 64) return launch_t<float, float, 64, 64, 32>(p, s);
+      if (t.bm == 128 && t.bn == 64) return launch_t<float, float, 128, 64, 32>(p, s);
+      if (t.bm == 64 && t.bn == 128) return launch_t<float, float, 64, 128, 32>(p, s);
+      return launch_t<float, float, 128, 128, 32>(p, s);
+    }
     if (t.bm == 64 && t.bn == 64) return launch_t<float, float, 64, 64, 16>(p, s);
     if (t.bm == 128 && t.bn == 64) return launch_t<float, float, 128, 64, 16>(p, s);
     if (t.bm == 64 && t.bn == 128) return launch_t<float, float, 64, 128, 16>(p, s);

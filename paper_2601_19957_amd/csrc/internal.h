@@ -122,7 +122,8 @@ struct QuadOut {
 // Tile shape used for a GEMM call; chosen by the autotuner.
 struct TileCfg {
   int bm = 128, bn = 128;
-  int bk = 32;      // k-tile of the BF16 kernels; FP64: 32 at 64x64, 128x64, 64x128, else 16
+  int bk = 32;      // k-tile: BF16 kernels 32 or 64; FP32 16 or 32; FP64 16 or 32 (32 at
+                    // 32x64, 64x64, 128x64, 64x128 only)
   int stages = 1;  // BF16 kernels: LDS stages (2 = ping-pong, square tiles, k-tile 32)
 };
 

@@ -170,6 +170,29 @@ def test_logl_grad_fp32(L, name):
     assert el < 5e-5 and eg < 5e-5, (el, eg)
 
 
+FP32_TILES = ["64x64x16", "128x64x16", "64x128x16", "128x128x16", "64x64x32", "128x64x32",
+              "64x128x32", "128x128x32"]
+
+
+@pytest.mark.parametrize("tile", FP32_TILES)
+@pytest.mark.parametrize("name", ["mix_d37_K3", "t_d256"])
+def test_logl_grad_fp32_every_tile(L, tile, name, monkeypatch):
+    """Each FP32 matrix-core tile (SB_TILE forces it; 16- and 32-wide k-tiles) against the
+    oracle to the FP32 bound of test_logl_grad_fp32, on d = 37 (odd: the element-wise kernel)
+    and a Student-t at d = 256, 131 rows (a ragged last row tile)."""
+    monkeypatch.setenv("SB_TILE", tile)
+    prob = PROBLEMS[name]()
+    X = synth.points_near_modes(prob, 131, 14, scale=0.5)
+    lo, go = O.logl(prob, X)
+    m = L.DeviceModel(prob, low_precision=True)
+    l, g = L.sb_logl_grad_dev(m, dev(X).float(), dtype=L.DTYPE_F32)
+    l, g = l.double().cpu().numpy(), g.double().cpu().numpy()
+    q_scale = np.maximum(1.0, np.abs(lo - O.prep(prob)[1].max()))
+    el = float(np.max(np.abs(l - lo) / (q_scale + np.abs(lo))))
+    eg = rel(g, go, axis=1)
+    assert el < 5e-5 and eg < 5e-5, (el, eg)
+
+
 def test_gradient_central_differences_on_gpu(L):
     """The hand-written backward against central differences of the GPU's own l (h = 1e-6)."""
     prob = synth.make_problem("c1")
