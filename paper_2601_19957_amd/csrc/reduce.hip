@@ -186,6 +186,190 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(int C, int n, int np,
   }
 }
 
+// ------------------------------------------------------------ blocked
+//
+// Block form of the same method for n a multiple of 64 (Golub & Van Loan,
+// block Jacobi): the indices fall into n / 32 blocks of 32, paired in the
+// round-robin order of the blocks, so a sweep is n / 32 - 1 rounds.  In a
+// round each pair (I, J) diagonalises (approximately) its 64 x 64 submatrix
+// S = A[I u J, I u J] by kJbInner cyclic Jacobi sweeps of its own, giving
+// the orthogonal U with U^T S U nearly diagonal, and then A <- Q^T A Q,
+// V <- V Q with Q the block rotation of all the round's pairs: rows I u J of
+// A times U^T, then columns I u J of A and V times U, as 64 x 64 products.
+// Each A and V element moves three times per round instead of once per
+// scalar round, n / 32 - 1 rounds per sweep instead of n - 1.
+constexpr int kJb = 32, kJb2 = 2 * kJb;
+constexpr int kJbInner = 1;
+
+// Local index i of a pair's 64 (i < 32: block I, else block J) -> global index.
+__device__ inline int jb_index(int I, int J, int i) {
+  return i < kJb ? I * kJb + i : J * kJb + (i - kJb);
+}
+
+// One workgroup per (matrix, pair): S from A, U = the product of S's own
+// Jacobi rotations (the scalar rotation and order of jacobi_angles_kernel
+// and jacobi_round_kernel), written to U [C][pairs][64][64].  An inner round
+// pairs all 64 indices, so S's new 2 x 2 block of pairs (a, b) is
+// R_a^T S_ab R_b: one thread forms it (the rows' rotation, then the
+// columns', the two passes' arithmetic), with no barrier between the passes.
+__global__ __launch_bounds__(256) void jb_solve_kernel(int C, int n, int r, const double *A,
+                                                       double *U) {
+  const int nb = n / kJb, half = nb / 2;
+  const int64_t ck = blockIdx.x;
+  if (ck >= (int64_t)C * half) return;
+  const int64_t c = ck / half;
+  int I, J;
+  jacobi_pair(nb, r, (int)(ck % half), I, J);
+  __shared__ double S[kJb2][kJb2 + 1];
+  __shared__ double W[kJb2][kJb2 + 1];
+  __shared__ double rot[kJb][2];
+  __shared__ int pr[kJb][2];
+  const double *a = A + c * (int64_t)n * n;
+  for (int e = threadIdx.x; e < kJb2 * kJb2; e += 256) {
+    const int i = e / kJb2, j = e % kJb2;
+    S[i][j] = a[(int64_t)jb_index(I, J, i) * n + jb_index(I, J, j)];
+    W[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sw = 0; sw < kJbInner; ++sw) {
+    for (int rr = 0; rr < kJb2 - 1; ++rr) {
+      if (threadIdx.x < kJb) {
+        int p, q;
+        jacobi_pair(kJb2, rr, threadIdx.x, p, q);
+        double cc = 1.0, ss = 0.0;
+        const double apq = S[p][q];
+        if (apq != 0.0) {
+          const double tau = (S[q][q] - S[p][p]) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          cc = 1.0 / sqrt(1.0 + t * t);
+          ss = t * cc;
+        }
+        rot[threadIdx.x][0] = cc;
+        rot[threadIdx.x][1] = ss;
+        pr[threadIdx.x][0] = p;
+        pr[threadIdx.x][1] = q;
+      }
+      __syncthreads();
+      // S: block (ta, tb) of the pairs, rows then columns
+      for (int e = threadIdx.x; e < kJb * kJb; e += 256) {
+        const int ta = e / kJb, tb = e % kJb;
+        const int p = pr[ta][0], q = pr[ta][1], p2 = pr[tb][0], q2 = pr[tb][1];
+        const double ca = rot[ta][0], sa = rot[ta][1], cb = rot[tb][0], sb = rot[tb][1];
+        const double x0 = S[p][p2], y0 = S[q][p2], x1 = S[p][q2], y1 = S[q][q2];
+        const double rp0 = ca * x0 - sa * y0, rq0 = sa * x0 + ca * y0;  // rows, column p2
+        const double rp1 = ca * x1 - sa * y1, rq1 = sa * x1 + ca * y1;  // rows, column q2
+        S[p][p2] = cb * rp0 - sb * rp1;
+        S[p][q2] = sb * rp0 + cb * rp1;
+        S[q][p2] = cb * rq0 - sb * rq1;
+        S[q][q2] = sb * rq0 + cb * rq1;
+      }
+      // W: columns p2, q2 of every row
+      for (int e = threadIdx.x; e < kJb * kJb2; e += 256) {
+        const int tb = e % kJb, i = e / kJb;
+        const int p2 = pr[tb][0], q2 = pr[tb][1];
+        const double cb = rot[tb][0], sb = rot[tb][1];
+        const double x = W[i][p2], y = W[i][q2];
+        W[i][p2] = cb * x - sb * y;
+        W[i][q2] = sb * x + cb * y;
+      }
+      __syncthreads();
+    }
+  }
+  double *u = U + ck * kJb2 * kJb2;
+  for (int e = threadIdx.x; e < kJb2 * kJb2; e += 256) u[e] = W[e / kJb2][e % kJb2];
+}
+
+// Rows I u J of A times U^T, 64 columns per workgroup: out[i][j] =
+// sum_m U[m][i] A[g(m)][j0 + j], 4 x 4 outputs per thread.
+__global__ __launch_bounds__(256) void jb_rows_kernel(int C, int n, int r, double *A,
+                                                      const double *U) {
+  const int nb = n / kJb, half = nb / 2, nct = n / kJb2;
+  const int64_t b = blockIdx.x;
+  if (b >= (int64_t)C * half * nct) return;
+  const int j0 = (int)(b % nct) * kJb2;
+  const int64_t ck = b / nct;
+  const int64_t c = ck / half;
+  int I, J;
+  jacobi_pair(nb, r, (int)(ck % half), I, J);
+  __shared__ double Us[kJb2][kJb2 + 1];
+  __shared__ double Ms[kJb2][kJb2 + 1];
+  double *a = A + c * (int64_t)n * n;
+  const double *u = U + ck * kJb2 * kJb2;
+  for (int e = threadIdx.x; e < kJb2 * kJb2; e += 256) {
+    const int i = e / kJb2, j = e % kJb2;
+    Us[i][j] = u[e];
+    Ms[i][j] = a[(int64_t)jb_index(I, J, i) * n + j0 + j];
+  }
+  __syncthreads();
+  const int ti = (threadIdx.x >> 4) * 4, tj = (threadIdx.x & 15) * 4;
+  double acc[4][4] = {};
+  for (int m = 0; m < kJb2; ++m) {
+    double x[4], y[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      x[v] = Us[m][ti + v];
+      y[v] = Ms[m][tj + v];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int w = 0; w < 4; ++w) acc[v][w] += x[v] * y[w];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) a[(int64_t)jb_index(I, J, ti + v) * n + j0 + tj + w] = acc[v][w];
+}
+
+// Columns I u J of A (which = 0) or V (which = 1) times U, 64 rows per
+// workgroup: out[i][j] = sum_m M[i0 + i][g(m)] U[m][j].
+__global__ __launch_bounds__(256) void jb_cols_kernel(int C, int n, int r, double *A, double *V,
+                                                      const double *U) {
+  const int nb = n / kJb, half = nb / 2, nrt = n / kJb2;
+  const int64_t b = blockIdx.x;
+  if (b >= (int64_t)C * half * nrt * 2) return;
+  const int which = (int)(b & 1);
+  const int64_t b2 = b >> 1;
+  const int i0 = (int)(b2 % nrt) * kJb2;
+  const int64_t ck = b2 / nrt;
+  const int64_t c = ck / half;
+  int I, J;
+  jacobi_pair(nb, r, (int)(ck % half), I, J);
+  __shared__ double Us[kJb2][kJb2 + 1];
+  __shared__ double Ms[kJb2][kJb2 + 1];
+  double *mat = (which ? V : A) + c * (int64_t)n * n;
+  const double *u = U + ck * kJb2 * kJb2;
+  for (int e = threadIdx.x; e < kJb2 * kJb2; e += 256) {
+    const int i = e / kJb2, j = e % kJb2;
+    Us[i][j] = u[e];
+    Ms[i][j] = mat[(int64_t)(i0 + i) * n + jb_index(I, J, j)];
+  }
+  __syncthreads();
+  const int ti = (threadIdx.x >> 4) * 4, tj = (threadIdx.x & 15) * 4;
+  double acc[4][4] = {};
+  for (int m = 0; m < kJb2; ++m) {
+    double x[4], y[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      x[v] = Ms[ti + v][m];
+      y[v] = Us[m][tj + v];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int w = 0; w < 4; ++w) acc[v][w] += x[v] * y[w];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) mat[(int64_t)(i0 + ti + v) * n + jb_index(I, J, tj + w)] = acc[v][w];
+}
+
+static bool jb_enabled(int n) {
+  const char *e = getenv("SB_JACOBI_BLOCK");
+  return n >= 128 && n % kJb2 == 0 && !(e && e[0] == '0');
+}
+
 // Off-diagonal and total sums of squares: kNormParts workgroups per matrix
 // write partial sums of rows [part n / kNormParts, ...), then one thread per
 // matrix adds the parts in order (a fixed summation order, so the sweep count
@@ -306,11 +490,17 @@ __global__ __launch_bounds__(256) void eig_classify_kernel(int n, const double *
   }
 }
 
+// (the blocked form's rotations: U [C][n / 64][64][64], n / 64 pairs of blocks)
+static size_t jb_u_count(int C, int n) {
+  return n % kJb2 == 0 ? (size_t)C * (size_t)(n / kJb2) * kJb2 * kJb2 : 0;
+}
+
 size_t reduce_ws_bytes(int C, int n) {
   const size_t nn = (size_t)n * n, np = (size_t)(n + (n & 1));
   return 2 * align_up(8 * (size_t)C * nn) + align_up(8 * (size_t)C * np) +
          align_up(8 * 2 * (size_t)C) + align_up(8 * (size_t)C * n) + align_up(4 * (size_t)C) +
-         align_up(4 * (size_t)C * n) + align_up(16 * (size_t)C * kNormParts) + 1024;
+         align_up(4 * (size_t)C * n) + align_up(16 * (size_t)C * kNormParts) +
+         align_up(8 * jb_u_count(C, n)) + 1024;
 }
 
 int run_eig_reduce(int C, int n, const double *H, const double *lo, const double *hi,
@@ -329,6 +519,7 @@ int run_eig_reduce(int C, int n, const double *H, const double *lo, const double
   int32_t *deff = ar.take<int32_t>(C);
   int32_t *rank_of = ar.take<int32_t>((size_t)C * n);
   double *nparts = ar.take<double>(2 * (size_t)C * kNormParts);
+  double *Ub = ar.take<double>(jb_u_count(C, n));
   if (!ar.ok()) {
     set_error("eigen reduction: workspace too small");
     return SB_E_NOMEM;
@@ -371,6 +562,19 @@ int run_eig_reduce(int C, int n, const double *H, const double *lo, const double
       break;
     }
     if (sweeps >= max_sweeps) break;
+    if (jb_enabled(n)) {
+      const int nb = n / kJb, bhalf = nb / 2;
+      const unsigned g_solve = (unsigned)(C * bhalf);
+      const unsigned g_rows = (unsigned)((int64_t)C * bhalf * (n / kJb2));
+      for (int r = 0; r < nb - 1; ++r) {
+        hipLaunchKernelGGL(jb_solve_kernel, dim3(g_solve), dim3(256), 0, st, C, n, r, A, Ub);
+        hipLaunchKernelGGL(jb_rows_kernel, dim3(g_rows), dim3(256), 0, st, C, n, r, A, Ub);
+        hipLaunchKernelGGL(jb_cols_kernel, dim3(2 * g_rows), dim3(256), 0, st, C, n, r, A, Vw,
+                           Ub);
+      }
+      SB_LAUNCH_CHECK();
+      continue;
+    }
     for (int r = 0; r < np - 1; ++r) {
       hipLaunchKernelGGL(jacobi_angles_kernel, dim3(g_pairs), dim3(256), 0, st, C, n, np, r, A,
                          cs);

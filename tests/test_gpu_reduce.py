@@ -76,10 +76,12 @@ def check(L, Hs, lo, hi, eps_i, eps_n):
             assert abs(lz[c] - ref["logz_marginal"]) <= bound, (c, bound)
 
 
-@pytest.mark.parametrize("n,C", [(1, 2), (2, 3), (7, 2), (33, 3), (64, 1), (200, 2)])
+@pytest.mark.parametrize("n,C", [(1, 2), (2, 3), (7, 2), (33, 3), (64, 1), (200, 2), (128, 2),
+                                 (256, 3)])
 def test_eig_reduce_constructed(L, n, C):
     """Batches of matrices with eigenvalues log-uniform over 1e-9..50 (all three classes);
-    odd n exercises the dummy index of the round-robin pairing."""
+    odd n exercises the dummy index of the round-robin pairing; n = 128 and 256 (multiples of
+    64) take the blocked form."""
     Hs = np.stack([spectrum_matrix(n, 100 * n + c) for c in range(C)])
     lo = -np.linspace(1.0, 4.0, n)
     hi = np.linspace(2.0, 6.0, n)
@@ -100,8 +102,11 @@ def test_eig_reduce_mode_hessians(L):
     assert out["d_eff"] == [48, 48, 48]
 
 
-def test_eig_reduce_d1024(L):
-    """The d = 1024 Gaussian's Hessian at its mode (its precision), one matrix."""
+@pytest.mark.parametrize("blocked", ["1", "0"])
+def test_eig_reduce_d1024(L, blocked, monkeypatch):
+    """The d = 1024 Gaussian's Hessian at its mode (its precision), one matrix, in the blocked
+    form and (SB_JACOBI_BLOCK=0) the scalar rounds."""
+    monkeypatch.setenv("SB_JACOBI_BLOCK", blocked)
     prob = synth.make_problem("c4a")
     check(L, prob.prec.copy(), prob.lo, prob.hi, 10.0, 1.5)
 
