@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(int C, int n, int np,
 
 // ------------------------------------------------------------ blocked
 //
-// Block form of the same method for n a multiple of 64 (Golub & Van Loan,
+// Block form of the same method for n a multiple of 64, 128 to 1024 (Golub & Van Loan,
 // block Jacobi): the indices fall into n / 32 blocks of 32, paired in the
 // round-robin order of the blocks, so a sweep is n / 32 - 1 rounds.  In a
 // round each pair (I, J) diagonalises (approximately) its 64 x 64 submatrix
@@ -365,9 +365,11 @@ __global__ __launch_bounds__(256) void jb_cols_kernel(int C, int n, int r, doubl
     for (int w = 0; w < 4; ++w) mat[(int64_t)(i0 + ti + v) * n + jb_index(I, J, tj + w)] = acc[v][w];
 }
 
+// (128 <= n <= 1024, the sizes measured against the sweep cap and the
+// eigenvalue bound; larger n keep the scalar rounds)
 static bool jb_enabled(int n) {
   const char *e = getenv("SB_JACOBI_BLOCK");
-  return n >= 128 && n % kJb2 == 0 && !(e && e[0] == '0');
+  return n >= 128 && n <= 1024 && n % kJb2 == 0 && !(e && e[0] == '0');
 }
 
 // Off-diagonal and total sums of squares: kNormParts workgroups per matrix
