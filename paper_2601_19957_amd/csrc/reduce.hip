@@ -188,16 +188,16 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(int C, int n, int np,
 
 // ------------------------------------------------------------ blocked
 //
-// Block form of the same method for n a multiple of 64, 128 to 1024 (Golub & Van Loan,
-// block Jacobi): the indices fall into n / 32 blocks of 32, paired in the
-// round-robin order of the blocks, so a sweep is n / 32 - 1 rounds.  In a
-// round each pair (I, J) diagonalises (approximately) its 64 x 64 submatrix
-// S = A[I u J, I u J] by kJbInner cyclic Jacobi sweeps of its own, giving
-// the orthogonal U with U^T S U nearly diagonal, and then A <- Q^T A Q,
-// V <- V Q with Q the block rotation of all the round's pairs: rows I u J of
-// A times U^T, then columns I u J of A and V times U, as 64 x 64 products.
-// Each A and V element moves three times per round instead of once per
-// scalar round, n / 32 - 1 rounds per sweep instead of n - 1.
+// Block form of the same method for n a multiple of 64, 128 to 1024 (Golub &
+// Van Loan, block Jacobi): the indices fall into n / 32 blocks of 32, paired
+// in the round-robin order of the blocks, so a sweep is n / 32 - 1 rounds.
+// In a round each pair (I, J) diagonalises (approximately) its 64 x 64
+// submatrix S = A[I u J, I u J] by kJbInner cyclic Jacobi sweeps of its own,
+// giving the orthogonal U with U^T S U nearly diagonal, and then
+// A <- Q^T A Q, V <- V Q with Q the block rotation of all the round's pairs:
+// each 64 x 64 block (a, b) of pairs of A becomes U_a^T A_ab U_b, and columns
+// I u J of V are multiplied by U.  A and V move once per round, n / 32 - 1
+// rounds per sweep instead of n - 1.
 constexpr int kJb = 32, kJb2 = 2 * kJb;
 constexpr int kJbInner = 1;
 
@@ -279,26 +279,28 @@ __global__ __launch_bounds__(256) void jb_solve_kernel(int C, int n, int r, cons
   for (int e = threadIdx.x; e < kJb2 * kJb2; e += 256) u[e] = W[e / kJb2][e % kJb2];
 }
 
-// Rows I u J of A times U^T, 64 columns per workgroup: out[i][j] =
-// sum_m U[m][i] A[g(m)][j0 + j], 4 x 4 outputs per thread.
-__global__ __launch_bounds__(256) void jb_rows_kernel(int C, int n, int r, double *A,
-                                                      const double *U) {
-  const int nb = n / kJb, half = nb / 2, nct = n / kJb2;
+// Block (a, b) of pairs of A: U_a^T A[R_a, R_b] U_b, one workgroup each
+// (R = I u J of the pair): T = U_a^T A_ab, then T U_b, each a sum over m in
+// order, 4 x 4 outputs per thread.  The blocks partition A, so A moves once.
+__global__ __launch_bounds__(256) void jb_a_kernel(int C, int n, int r, double *A,
+                                                   const double *U) {
+  const int nb = n / kJb, half = nb / 2;
   const int64_t b = blockIdx.x;
-  if (b >= (int64_t)C * half * nct) return;
-  const int j0 = (int)(b % nct) * kJb2;
-  const int64_t ck = b / nct;
-  const int64_t c = ck / half;
-  int I, J;
-  jacobi_pair(nb, r, (int)(ck % half), I, J);
-  __shared__ double Us[kJb2][kJb2 + 1];
-  __shared__ double Ms[kJb2][kJb2 + 1];
+  if (b >= (int64_t)C * half * half) return;
+  const int64_t c = b / ((int64_t)half * half);
+  const int ka = (int)((b / half) % half), kb = (int)(b % half);
+  int Ia, Ja, Ib, Jb;
+  jacobi_pair(nb, r, ka, Ia, Ja);
+  jacobi_pair(nb, r, kb, Ib, Jb);
+  __shared__ double Xs[kJb2][kJb2 + 1];
+  __shared__ double Ys[kJb2][kJb2 + 1];
   double *a = A + c * (int64_t)n * n;
-  const double *u = U + ck * kJb2 * kJb2;
+  const double *ua = U + (c * half + ka) * kJb2 * kJb2;
+  const double *ub = U + (c * half + kb) * kJb2 * kJb2;
   for (int e = threadIdx.x; e < kJb2 * kJb2; e += 256) {
     const int i = e / kJb2, j = e % kJb2;
-    Us[i][j] = u[e];
-    Ms[i][j] = a[(int64_t)jb_index(I, J, i) * n + j0 + j];
+    Xs[i][j] = ua[e];
+    Ys[i][j] = a[(int64_t)jb_index(Ia, Ja, i) * n + jb_index(Ib, Jb, j)];
   }
   __syncthreads();
   const int ti = (threadIdx.x >> 4) * 4, tj = (threadIdx.x & 15) * 4;
@@ -307,8 +309,31 @@ __global__ __launch_bounds__(256) void jb_rows_kernel(int C, int n, int r, doubl
     double x[4], y[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      x[v] = Us[m][ti + v];
-      y[v] = Ms[m][tj + v];
+      x[v] = Xs[m][ti + v];
+      y[v] = Ys[m][tj + v];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int w = 0; w < 4; ++w) acc[v][w] += x[v] * y[w];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) Ys[ti + v][tj + w] = acc[v][w];
+  for (int e = threadIdx.x; e < kJb2 * kJb2; e += 256) Xs[e / kJb2][e % kJb2] = ub[e];
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) acc[v][w] = 0.0;
+  for (int m = 0; m < kJb2; ++m) {
+    double x[4], y[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      x[v] = Ys[ti + v][m];
+      y[v] = Xs[m][tj + v];
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v)
@@ -318,26 +343,25 @@ __global__ __launch_bounds__(256) void jb_rows_kernel(int C, int n, int r, doubl
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
-    for (int w = 0; w < 4; ++w) a[(int64_t)jb_index(I, J, ti + v) * n + j0 + tj + w] = acc[v][w];
+    for (int w = 0; w < 4; ++w)
+      a[(int64_t)jb_index(Ia, Ja, ti + v) * n + jb_index(Ib, Jb, tj + w)] = acc[v][w];
 }
 
-// Columns I u J of A (which = 0) or V (which = 1) times U, 64 rows per
-// workgroup: out[i][j] = sum_m M[i0 + i][g(m)] U[m][j].
-__global__ __launch_bounds__(256) void jb_cols_kernel(int C, int n, int r, double *A, double *V,
+// Columns I u J of V times U, 64 rows per workgroup: out[i][j] =
+// sum_m V[i0 + i][g(m)] U[m][j].
+__global__ __launch_bounds__(256) void jb_cols_kernel(int C, int n, int r, double *V,
                                                       const double *U) {
   const int nb = n / kJb, half = nb / 2, nrt = n / kJb2;
   const int64_t b = blockIdx.x;
-  if (b >= (int64_t)C * half * nrt * 2) return;
-  const int which = (int)(b & 1);
-  const int64_t b2 = b >> 1;
-  const int i0 = (int)(b2 % nrt) * kJb2;
-  const int64_t ck = b2 / nrt;
+  if (b >= (int64_t)C * half * nrt) return;
+  const int i0 = (int)(b % nrt) * kJb2;
+  const int64_t ck = b / nrt;
   const int64_t c = ck / half;
   int I, J;
   jacobi_pair(nb, r, (int)(ck % half), I, J);
   __shared__ double Us[kJb2][kJb2 + 1];
   __shared__ double Ms[kJb2][kJb2 + 1];
-  double *mat = (which ? V : A) + c * (int64_t)n * n;
+  double *mat = V + c * (int64_t)n * n;
   const double *u = U + ck * kJb2 * kJb2;
   for (int e = threadIdx.x; e < kJb2 * kJb2; e += 256) {
     const int i = e / kJb2, j = e % kJb2;
@@ -567,12 +591,12 @@ int run_eig_reduce(int C, int n, const double *H, const double *lo, const double
     if (jb_enabled(n)) {
       const int nb = n / kJb, bhalf = nb / 2;
       const unsigned g_solve = (unsigned)(C * bhalf);
-      const unsigned g_rows = (unsigned)((int64_t)C * bhalf * (n / kJb2));
+      const unsigned g_a = (unsigned)((int64_t)C * bhalf * bhalf);
+      const unsigned g_v = (unsigned)((int64_t)C * bhalf * (n / kJb2));
       for (int r = 0; r < nb - 1; ++r) {
         hipLaunchKernelGGL(jb_solve_kernel, dim3(g_solve), dim3(256), 0, st, C, n, r, A, Ub);
-        hipLaunchKernelGGL(jb_rows_kernel, dim3(g_rows), dim3(256), 0, st, C, n, r, A, Ub);
-        hipLaunchKernelGGL(jb_cols_kernel, dim3(2 * g_rows), dim3(256), 0, st, C, n, r, A, Vw,
-                           Ub);
+        hipLaunchKernelGGL(jb_a_kernel, dim3(g_a), dim3(256), 0, st, C, n, r, A, Ub);
+        hipLaunchKernelGGL(jb_cols_kernel, dim3(g_v), dim3(256), 0, st, C, n, r, Vw, Ub);
       }
       SB_LAUNCH_CHECK();
       continue;
