@@ -279,9 +279,57 @@ __global__ __launch_bounds__(256) void jb_solve_kernel(int C, int n, int r, cons
   for (int e = threadIdx.x; e < kJb2 * kJb2; e += 256) u[e] = W[e / kJb2][e % kJb2];
 }
 
+// 64 x 64 x 64 FP64 products on the matrix cores: wave w of four owns the
+// 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 blocks of 16 x 16; item v of lane l
+// of a block holds row l / 16 + 4 v, column l % 16 (16x16x4 FP64 MFMA).
+typedef double jb_d4 __attribute__((ext_vector_type(4)));
+struct JbAcc {
+  jb_d4 c[2][2];
+};
+// D = P Q with P(i, m) = pa(i, m), Q(m, j) = qb(m, j) read from LDS.
+template <class PA, class QB>
+__device__ inline JbAcc jb_mma(PA pa, QB qb) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+  const int fr = lane & 15, fk = lane >> 4;
+  JbAcc o;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) o.c[bi][bj] = jb_d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < kJb2; k0 += 4) {
+    const int m = k0 + fk;
+    double av[2], bv[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      av[t] = pa(r0 + 16 * t + fr, m);
+      bv[t] = qb(m, c0 + 16 * t + fr);
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+        o.c[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv[bj], o.c[bi][bj], 0, 0, 0);
+  }
+  return o;
+}
+// Visits every output (row, column, value) of a JbAcc.
+template <class F>
+__device__ inline void jb_each(const JbAcc &o, F f) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        f(r0 + 16 * bi + (lane >> 4) + 4 * v, c0 + 16 * bj + (lane & 15), o.c[bi][bj][v]);
+}
+
 // Block (a, b) of pairs of A: U_a^T A[R_a, R_b] U_b, one workgroup each
-// (R = I u J of the pair): T = U_a^T A_ab, then T U_b, each a sum over m in
-// order, 4 x 4 outputs per thread.  The blocks partition A, so A moves once.
+// (R = I u J of the pair): T = U_a^T A_ab, then T U_b.  The blocks partition
+// A, so A moves once.
 __global__ __launch_bounds__(256) void jb_a_kernel(int C, int n, int r, double *A,
                                                    const double *U) {
   const int nb = n / kJb, half = nb / 2;
@@ -303,52 +351,20 @@ __global__ __launch_bounds__(256) void jb_a_kernel(int C, int n, int r, double *
     Ys[i][j] = a[(int64_t)jb_index(Ia, Ja, i) * n + jb_index(Ib, Jb, j)];
   }
   __syncthreads();
-  const int ti = (threadIdx.x >> 4) * 4, tj = (threadIdx.x & 15) * 4;
-  double acc[4][4] = {};
-  for (int m = 0; m < kJb2; ++m) {
-    double x[4], y[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      x[v] = Xs[m][ti + v];
-      y[v] = Ys[m][tj + v];
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int w = 0; w < 4; ++w) acc[v][w] += x[v] * y[w];
-  }
+  const JbAcc t = jb_mma([&](int i, int m) { return Xs[m][i]; },
+                         [&](int m, int j) { return Ys[m][j]; });
   __syncthreads();
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-#pragma unroll
-    for (int w = 0; w < 4; ++w) Ys[ti + v][tj + w] = acc[v][w];
+  jb_each(t, [&](int i, int j, double v) { Ys[i][j] = v; });
   for (int e = threadIdx.x; e < kJb2 * kJb2; e += 256) Xs[e / kJb2][e % kJb2] = ub[e];
   __syncthreads();
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-#pragma unroll
-    for (int w = 0; w < 4; ++w) acc[v][w] = 0.0;
-  for (int m = 0; m < kJb2; ++m) {
-    double x[4], y[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      x[v] = Ys[ti + v][m];
-      y[v] = Xs[m][tj + v];
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int w = 0; w < 4; ++w) acc[v][w] += x[v] * y[w];
-  }
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-#pragma unroll
-    for (int w = 0; w < 4; ++w)
-      a[(int64_t)jb_index(Ia, Ja, ti + v) * n + jb_index(Ib, Jb, tj + w)] = acc[v][w];
+  const JbAcc o = jb_mma([&](int i, int m) { return Ys[i][m]; },
+                         [&](int m, int j) { return Xs[m][j]; });
+  jb_each(o, [&](int i, int j, double v) {
+    a[(int64_t)jb_index(Ia, Ja, i) * n + jb_index(Ib, Jb, j)] = v;
+  });
 }
 
-// Columns I u J of V times U, 64 rows per workgroup: out[i][j] =
-// sum_m V[i0 + i][g(m)] U[m][j].
+// Columns I u J of V times U, 64 rows per workgroup: out = V[i0.., R] U.
 __global__ __launch_bounds__(256) void jb_cols_kernel(int C, int n, int r, double *V,
                                                       const double *U) {
   const int nb = n / kJb, half = nb / 2, nrt = n / kJb2;
@@ -369,24 +385,11 @@ __global__ __launch_bounds__(256) void jb_cols_kernel(int C, int n, int r, doubl
     Ms[i][j] = mat[(int64_t)(i0 + i) * n + jb_index(I, J, j)];
   }
   __syncthreads();
-  const int ti = (threadIdx.x >> 4) * 4, tj = (threadIdx.x & 15) * 4;
-  double acc[4][4] = {};
-  for (int m = 0; m < kJb2; ++m) {
-    double x[4], y[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      x[v] = Ms[ti + v][m];
-      y[v] = Us[m][tj + v];
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int w = 0; w < 4; ++w) acc[v][w] += x[v] * y[w];
-  }
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-#pragma unroll
-    for (int w = 0; w < 4; ++w) mat[(int64_t)(i0 + ti + v) * n + jb_index(I, J, tj + w)] = acc[v][w];
+  const JbAcc o = jb_mma([&](int i, int m) { return Ms[i][m]; },
+                         [&](int m, int j) { return Us[m][j]; });
+  jb_each(o, [&](int i, int j, double v) {
+    mat[(int64_t)(i0 + i) * n + jb_index(I, J, j)] = v;
+  });
 }
 
 // (128 <= n <= 1024, the sizes measured against the sweep cap and the
