@@ -133,12 +133,16 @@ def test_logl_grad_fp64_every_tile(L, tile, make, monkeypatch):
 
 
 @pytest.mark.parametrize("make", [lambda: small_mixture(96, 4, 21), lambda: t_problem(5, 22),
-                                  lambda: small_mixture(1, 1, 23), lambda: t_problem(128, 24)],
-                         ids=["mix_d96_K4", "t_d5", "gauss_d1", "t_d128"])
+                                  lambda: small_mixture(1, 1, 23), lambda: t_problem(128, 24),
+                                  lambda: small_mixture(40, 3, 26), lambda: small_mixture(64, 5, 27)],
+                         ids=["mix_d96_K4", "t_d5", "gauss_d1", "t_d128", "mix_d40_K3",
+                              "mix_d64_K5"])
 def test_logl_grad_fp64_fused_equals_two_launch(L, make, monkeypatch):
     """Small FP64 problems take the fused launch (contraction and row epilogue in one kernel,
-    d <= 128 and K * round_up(d, 32) <= 384: the first case sits at the second edge, the last
-    at the first); on a ragged last row
+    d <= 128 and K * round_up(d, 32) <= 384: the first case sits at the second edge, the
+    fourth at the first); 1 to 6 16-column output blocks per wave (t_d5 / gauss_d1 1, t_d128 2,
+    mix_d40_K3 3, mix_d64_K5 5, mix_d96_K4 6), element-wise P loads where d is not a multiple of
+    8 (t_d5, gauss_d1) and whole-run loads with lanes past d zeroed at d = 40; on a ragged last row
     tile its l equals the two-launch path's (SB_FUSED=0) to a few ulps of the O(d) sums, and l
     and the gradient equal the oracle's to 1e-11.  The two paths' gradients agree only as
     closely as their responsibilities: r_k = exp(a_k - lse) moves by r_k |dq_k| / 2, and q
