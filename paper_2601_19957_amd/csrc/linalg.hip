@@ -362,16 +362,35 @@ __global__ __launch_bounds__(SV_T) void chol_solve_kernel(int n, const double *L
     const int nb = min(64, n - i0);
     for (int r = w; r < nb; r += SV_W)  // diagonal block into LDS, row by row
       if (lane < nb) Tb[r][lane] = L[(size_t)(i0 + r) * n + i0 + lane];
-    // rows i0 + w + 16 q (q < 4) less sum_{k < i0} L[i][k] z_k; lanes split k
+    // rows i0 + w + 16 q (q < 4) less sum_{k < i0} L[i][k] z_k; lanes split k.
+    // Eight k values per lane per pass, their 32 loads issued before the
+    // first product (the sums keep their order: k ascending per lane); a row
+    // past the block reads row i0 and its sum is never used.
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int k = lane; k < i0; k += 64) {
+    const double *Lr[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = w + SV_W * q;
+      Lr[q] = L + (size_t)(i0 + (r < nb ? r : 0)) * n;
+    }
+    int k = lane;
+    for (; k + 64 * 7 < i0; k += 64 * 8) {
+      double lv[8][4];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lv[u][q] = Lr[q][k + 64 * u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double zk = xs[k + 64 * u];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += lv[u][q] * zk;
+      }
+    }
+    for (; k < i0; k += 64) {
       const double zk = xs[k];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = w + SV_W * q;
-        if (r < nb) acc[q] += L[(size_t)(i0 + r) * n + k] * zk;
-      }
+      for (int q = 0; q < 4; ++q) acc[q] += Lr[q][k] * zk;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -400,10 +419,20 @@ __global__ __launch_bounds__(SV_T) void chol_solve_kernel(int n, const double *L
     for (int r = w; r < nb; r += SV_W)
       if (lane < nb) Tb[r][lane] = L[(size_t)(i0 + r) * n + i0 + lane];
     // s_i = sum_{k >= iend} L[k][i] x_k for i in block; lanes index i, waves split k
+    // (sixteen rows per pass, their loads issued before the first product;
+    // k ascending per wave as before)
     double sacc = 0.0;
-    if (lane < nb)
-#pragma unroll 4
-      for (int k = iend + w; k < n; k += SV_W) sacc += L[(size_t)k * n + i0 + lane] * xs[k];
+    if (lane < nb) {
+      int k = iend + w;
+      for (; k + SV_W * 15 < n; k += SV_W * 16) {
+        double lv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) lv[u] = L[(size_t)(k + SV_W * u) * n + i0 + lane];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) sacc += lv[u] * xs[k + SV_W * u];
+      }
+      for (; k < n; k += SV_W) sacc += L[(size_t)k * n + i0 + lane] * xs[k];
+    }
     part[w][lane] = sacc;
     __syncthreads();
     if (w == 0) {
