@@ -70,6 +70,9 @@ __global__ __launch_bounds__(256) void fused_logl_grad_kernel(FusedArgs f) {
   double *sc = qs + R * K * nbk;
   double *MU = sc + R * K;  // mu_k, zero past d: [K][dp]
   const double *X = (const double *)f.a.X;
+  // beta_k of the mixture row epilogue's lane k = tid % 16 (index clamped,
+  // K >= 1), loaded here so that it arrives with the staging's values
+  const double beta_k = m.beta[(tid & 15) < K ? (tid & 15) : 0];
   // blocks b = wave + 4 s: column block t = b / K of component k = b % K
   const int fr = lane & 15, fg = lane >> 4;
   d4v acc[RB][NS];
@@ -249,7 +252,7 @@ __global__ __launch_bounds__(256) void fused_logl_grad_kernel(FusedArgs f) {
       const double *qp = qs + ((size_t)i * K + k) * nbk;
       double q = 0;
       for (int t = 0; t < nbk; ++t) q += qp[t];
-      a = m.beta[k] - 0.5 * q;
+      a = beta_k - 0.5 * q;
     }
     double mx = a;
 #pragma unroll
